@@ -1,0 +1,313 @@
+"""FP64 CPU oracle: plain definitions of everything the GPU path computes.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, ``__graft_entry__.smoke`` and the
+benchmark's CPU-baseline leg may import this package.  The product library in
+``paper_1601_04587_amd`` never imports or links it, and shares no code with it.
+
+Contents and the passages they follow:
+  * ``apply_D``, ``apply_hop``, ``clover_term``, ``solve``  (oracle.c):
+      Wilson-Dirac operator (Appendix A, eq. wdo), normalisation
+      2 kappa D = 1 - kappa D_hop (Section 6), Sheikholeslami-Wohlert term
+      (O(a) improvement, footnotes of Sections 4 and 6), Dirichlet restriction
+      D_Gamma (Section 2, eq. blkdec), S^(i) = D_Gamma_i^{-1} (eq. diric).
+  * ``series``: telescoping expansion S = S^(0) + [S^(1)-S^(0)] + ...
+      (Section 1, eq. Dseries).
+  * ``pp_trace``/``contract_pp_disconnected``: tr{gamma5 D_Gamma^{-1}(x,x)} and
+      the split W = W^(f) + W^(r1) (+ swap) + W^(r2) (Section 3, eqs. W0, rall0,
+      rall, with eq. bella identifying the r-kernels with [S - S^(0)](x,x)),
+      normalised by 1/L^3 (eq. sing).
+  * ``nucleon``: W_N1 - W_N2 (Section 5.2, eq. baryfact) summed over the sink
+      time slice (eq. baryN), with C = i gamma0 gamma2 and P_- = (1-gamma0)/2.
+
+Array conventions (complex128):
+  links U[site, mu, 3, 3]; spinors / propagator columns psi[rhs, site, 4, 3];
+  a point-source propagator has rhs = 3*beta + b, so S(y,x)[alpha a, beta b] =
+  psi[3*beta+b, y, alpha, a].
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force=False):
+    """Compile oracle.c into liboracle.so (gcc, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        subprocess.check_call(["gcc", "-O2", "-fcx-limited-range", "-fopenmp", "-fPIC", "-shared",
+                               "-std=c11", "-o", _LIB + ".tmp", _SRC, "-lm"])
+        os.replace(_LIB + ".tmp", _LIB)
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i4 = ctypes.POINTER(ctypes.c_int)
+        d = ctypes.c_double
+        i = ctypes.c_int
+        lib.oracle_gamma.argtypes = [i, P]
+        lib.oracle_field_strength.argtypes = [i4, P, i, i, P]
+        lib.oracle_clover_term.argtypes = [i4, P, d, P]
+        lib.oracle_apply_D.argtypes = [i4, P, P, d, i, i4, i4, i, P, P]
+        lib.oracle_apply_hop.argtypes = [i4, P, i, i4, i4, i, P, P]
+        lib.oracle_solve.argtypes = [i4, P, P, d, i, i4, i4, i, P, P, d, i, P, P]
+        lib.oracle_solve.restype = i
+        _lib = lib
+    return _lib
+
+
+def _i4(v):
+    return (ctypes.c_int * 4)(*[int(a) for a in v])
+
+
+def _c(a):
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def _domain(L, lo, hi):
+    lo = (0, 0, 0, 0) if lo is None else tuple(lo)
+    hi = tuple(L) if hi is None else tuple(hi)
+    return _i4(lo), _i4(hi)
+
+
+# ----------------------------------------------------------------- algebra
+def gamma(mu):
+    """gamma_mu, mu = 0..3, in the chiral basis used throughout."""
+    out = np.zeros((4, 4), dtype=np.complex128)
+    _load().oracle_gamma(mu, out.ctypes.data)
+    return out
+
+
+def gamma5():
+    return gamma(0) @ gamma(1) @ gamma(2) @ gamma(3)
+
+
+def charge_conjugation():
+    """C = i gamma0 gamma2 (Section 5.2)."""
+    return 1j * gamma(0) @ gamma(2)
+
+
+def P_minus():
+    return 0.5 * (np.eye(4) - gamma(0))
+
+
+# ---------------------------------------------------------------- operator
+def field_strength(U, L, mu, nu):
+    F = np.empty((int(np.prod(L)), 3, 3), dtype=np.complex128)
+    _load().oracle_field_strength(_i4(L), _c(U).ctypes.data, mu, nu, F.ctypes.data)
+    return F
+
+
+def clover_term(U, L, csw):
+    """Per-site 12x12 matrix c_sw (i/4) sum_{mu,nu} sigma_{mu nu} Fhat_{mu nu}, index spin*3+colour."""
+    C = np.empty((int(np.prod(L)), 12, 12), dtype=np.complex128)
+    _load().oracle_clover_term(_i4(L), _c(U).ctypes.data, float(csw), C.ctypes.data)
+    return C
+
+
+def apply_D(U, L, kappa, psi, C=None, antiperiodic=True, lo=None, hi=None):
+    """D_Gamma psi for psi[nrhs, V, 4, 3] (Gamma = [lo,hi), default the full lattice)."""
+    U = _c(U)
+    psi = _c(psi)
+    squeeze = psi.ndim == 3
+    if squeeze:
+        psi = psi[None]
+    out = np.empty_like(psi)
+    Cp = None if C is None else _c(C).ctypes.data
+    clo, chi = _domain(L, lo, hi)
+    _load().oracle_apply_D(_i4(L), U.ctypes.data, Cp, float(kappa), int(antiperiodic), clo, chi,
+                           psi.shape[0], psi.ctypes.data, out.ctypes.data)
+    return out[0] if squeeze else out
+
+
+def apply_hop(U, L, psi, antiperiodic=True, lo=None, hi=None):
+    """D_hop psi, the hopping term with 2 kappa D = 1 - kappa D_hop (Wilson)."""
+    U = _c(U)
+    psi = _c(psi)
+    squeeze = psi.ndim == 3
+    if squeeze:
+        psi = psi[None]
+    out = np.empty_like(psi)
+    clo, chi = _domain(L, lo, hi)
+    _load().oracle_apply_hop(_i4(L), U.ctypes.data, int(antiperiodic), clo, chi, psi.shape[0],
+                             psi.ctypes.data, out.ctypes.data)
+    return out[0] if squeeze else out
+
+
+def solve(U, L, kappa, b, C=None, antiperiodic=True, lo=None, hi=None, tol=1e-13, maxiter=20000):
+    """x = D_Gamma^{-1} b (zero outside Gamma) by BiCGstab; returns (x, iters, rel_residuals)."""
+    U = _c(U)
+    b = _c(b)
+    squeeze = b.ndim == 3
+    if squeeze:
+        b = b[None]
+    x = np.zeros_like(b)
+    n = b.shape[0]
+    iters = np.zeros(n, dtype=np.int32)
+    res = np.zeros(n, dtype=np.float64)
+    Cp = None if C is None else _c(C).ctypes.data
+    clo, chi = _domain(L, lo, hi)
+    _load().oracle_solve(_i4(L), U.ctypes.data, Cp, float(kappa), int(antiperiodic), clo, chi, n,
+                         b.ctypes.data, x.ctypes.data, float(tol), int(maxiter), iters.ctypes.data,
+                         res.ctypes.data)
+    if squeeze:
+        return x[0], iters, res
+    return x, iters, res
+
+
+def residual(U, L, kappa, b, x, C=None, antiperiodic=True, lo=None, hi=None):
+    """Per-rhs ||P_Gamma b - D_Gamma x|| / ||P_Gamma b|| (x restricted to Gamma first)."""
+    b = _c(b)
+    x = _c(x)
+    mask = domain_mask(L, lo, hi)
+    bm = b * mask[None, :, None, None]
+    xm = x * mask[None, :, None, None]
+    r = bm - apply_D(U, L, kappa, xm, C=C, antiperiodic=antiperiodic, lo=lo, hi=hi)
+    num = np.sqrt(np.sum(np.abs(r) ** 2, axis=(1, 2, 3)))
+    den = np.sqrt(np.sum(np.abs(bm) ** 2, axis=(1, 2, 3)))
+    return num / den
+
+
+def domain_mask(L, lo=None, hi=None):
+    lo = (0, 0, 0, 0) if lo is None else lo
+    hi = tuple(L) if hi is None else hi
+    t, x1, x2, x3 = np.meshgrid(*[np.arange(n) for n in L], indexing="ij")
+    m = np.ones(L, dtype=bool)
+    for c, a, b in zip((t, x1, x2, x3), lo, hi):
+        m &= (c >= a) & (c < b)
+    return m.reshape(-1)
+
+
+# ------------------------------------------------------------------ series
+def series(props):
+    """Terms of eq. Dseries from the nested-domain propagators S^(0..n-1).
+
+    Returns (terms, total): terms[0] = S^(0), terms[i] = S^(i) - S^(i-1),
+    total = S^(n-1) (each S^(i) already zero outside Gamma_i)."""
+    props = [np.asarray(p) for p in props]
+    terms = [props[0].copy()] + [props[i] - props[i - 1] for i in range(1, len(props))]
+    return np.stack(terms), props[-1].copy()
+
+
+def cumulative(terms):
+    """S^(i) = sum_{j<=i} terms[j]."""
+    return np.cumsum(np.asarray(terms), axis=0)
+
+
+# ----------------------------------------------------------- contractions
+def prop_matrix(sol, site):
+    """12x12 matrix S(y,x)[alpha a, beta b] at sink `site` from 12 point-source columns."""
+    sol = np.asarray(sol)
+    return sol[:, site, :, :].reshape(12, 12).T
+
+
+def pp_trace(sol, x_site):
+    """tr_{spin,colour}{gamma5 S(x,x)} (Section 3, eq. W0)."""
+    S = prop_matrix(sol, x_site)
+    G5 = np.kron(gamma5(), np.eye(3))
+    return np.trace(G5 @ S)
+
+
+def contract_pp_disconnected(terms_x, terms_y, x_site, y_site, L3):
+    """Disconnected pseudoscalar pieces per level (Section 3, eqs. deco1, W0, rall0, rall).
+
+    terms_x: series terms of the propagator from x (levels: nested domains
+    around x, the last one the full lattice); terms_y the same for y.  For
+    level i the domain propagators are S^(i) = sum_{j<=i} terms[j] and the full
+    propagator is the sum of all terms; by eq. bella the r-kernels equal
+    [S - S^(i)](x,x).  Returns out[level] = (f, r1, r2, full) each divided
+    by L^3 (eq. sing; for point sources the spatial sums collapse).
+    """
+    cx = cumulative(terms_x)
+    cy = cumulative(terms_y)
+    n = cx.shape[0]
+    tx = np.array([pp_trace(cx[i], x_site) for i in range(n)])
+    ty = np.array([pp_trace(cy[i], y_site) for i in range(n)])
+    out = np.zeros((n, 4), dtype=np.complex128)
+    for i in range(n):
+        dx = tx[-1] - tx[i]
+        dy = ty[-1] - ty[i]
+        out[i, 0] = tx[i] * ty[i]
+        out[i, 1] = dx * ty[i] + tx[i] * dy
+        out[i, 2] = dx * dy
+        out[i, 3] = tx[-1] * ty[-1]
+    return out / L3
+
+
+def _eps():
+    e = np.zeros((3, 3, 3))
+    for a, b, c, s in [(0, 1, 2, 1), (1, 2, 0, 1), (2, 0, 1, 1), (0, 2, 1, -1), (2, 1, 0, -1), (1, 0, 2, -1)]:
+        e[a, b, c] = s
+    return e
+
+
+def nucleon_W(Sarr):
+    """W_N1 - W_N2 (eq. baryfact) per sink site; Sarr as in ``nucleon_W_parts``."""
+    W1, W2 = nucleon_W_parts(Sarr)
+    return W1 - W2
+
+
+def nucleon_W_parts(Sarr):
+    """W_N1 and W_N2 (eq. baryfact) per sink site.
+
+    Sarr[y, alpha, a, beta, b] = S^{ab}_{alpha beta}(y, x) with S_u = S_d = S.
+      W_N1 = eps^{abc} eps^{feg} tr[S^{ag T} C g5 S^{bf} C g5] tr[S^{ce} P_-]
+      W_N2 = eps^{abc} eps^{feg} tr[S^{ag T} C g5 S^{be} P_- S^{cf} C g5]
+    (traces and transposes over spin only).
+    """
+    eps = _eps()
+    Cg5 = charge_conjugation() @ gamma5()
+    Pm = P_minus()
+    # tr[X^T M Y M] = X_{rs} M_{rk} Y_{kl} M_{ls}
+    T1 = np.einsum("yrasg,rk,ykblf,ls->yagbf", Sarr, Cg5, Sarr, Cg5, optimize=True)
+    T2 = np.einsum("yacbe,ba->yce", Sarr, Pm, optimize=True)
+    W1 = np.einsum("abc,feg,yagbf,yce->y", eps, eps, T1, T2, optimize=True)
+    W2 = _w2(eps, Sarr, Cg5, Pm)
+    return W1, W2
+
+
+def _w2(eps, Sarr, Cg5, Pm):
+    # X = S^{ag}, Y = S^{be}, Z = S^{cf}:  X_{rs} (Cg5)_{rk} Y_{kl} (P_-)_{lm} Z_{mn} (Cg5)_{ns}
+    XM = np.einsum("yrasg,rk->yaskg", Sarr, Cg5, optimize=True)      # (X^T Cg5)_{sk}
+    YP = np.einsum("ykble,lm->ykbme", Sarr, Pm, optimize=True)       # (Y P_-)_{km}
+    ZM = np.einsum("ymcnf,ns->ymcsf", Sarr, Cg5, optimize=True)      # (Z Cg5)_{ms}
+    XMY = np.einsum("yaskg,ykbme->yasmgbe", XM, YP, optimize=True)   # (X^T Cg5 Y P_-)_{sm}
+    tr = np.einsum("yasmgbe,ymcsf->yagbecf", XMY, ZM, optimize=True)
+    return np.einsum("abc,feg,yagbecf->y", eps, eps, tr, optimize=True)
+
+
+def nucleon(sol, L, t_range=None):
+    """C_N(y0) = sum_{y in slice y0} (W_N1 - W_N2)(y, x) for every y0 (eq. baryN).
+
+    sol: the 12 point-source columns [12, V, 4, 3] of one propagator."""
+    L = tuple(L)
+    V = int(np.prod(L))
+    V3 = V // L[0]
+    sol = np.asarray(sol)
+    # Sarr[y, alpha, a, beta, b] = sol[3 beta + b, y, alpha, a]
+    Sarr = sol.reshape(4, 3, V, 4, 3).transpose(2, 3, 4, 0, 1)
+    out = np.zeros(L[0], dtype=np.complex128)
+    ts = range(L[0]) if t_range is None else t_range
+    for t in ts:
+        out[t] = nucleon_W(np.ascontiguousarray(Sarr[t * V3:(t + 1) * V3])).sum()
+    return out
+
+
+def contract_nucleon(terms, L):
+    """C^(i)_N(y0) for each level's cumulative propagator, and the series differences.
+
+    Returns (levels, diffs): levels[i] = C_N[S^(i)], diffs[0] = levels[0],
+    diffs[i] = levels[i] - levels[i-1] (eq. seriesN)."""
+    cum = cumulative(terms)
+    levels = np.stack([nucleon(cum[i], L) for i in range(cum.shape[0])])
+    diffs = np.concatenate([levels[:1], np.diff(levels, axis=0)], axis=0)
+    return levels, diffs

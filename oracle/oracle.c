@@ -1,0 +1,401 @@
+/*
+ * FP64 CPU oracle for the domain-decomposed Wilson(-clover) propagator.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the tests, the smoke check and the benchmark's CPU
+ * baseline do.  It shares no source with the GPU path: its own gamma
+ * matrices, indexing, stencil and solver.
+ *
+ * What it computes (plain definitions, no blocking, no even-odd split):
+ *
+ *  - Wilson-Dirac operator (Appendix A, eq. wdo):  D = D_w + m0 with
+ *      D_w = 1/2 { gamma_mu (nabla*_mu + nabla_mu) - nabla*_mu nabla_mu },
+ *    which written out per site is
+ *      D psi(x) = (m0 + 4) psi(x)
+ *                 - 1/2 sum_mu [ (1 - gamma_mu) U_mu(x) psi(x+mu)
+ *                               + (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu) ].
+ *    m0 = 1/(2 kappa) - 4 so that 2 kappa D = 1 - kappa D_hop (Section 6).
+ *  - O(a) improvement (mentioned in the footnotes of Sections 4 and 6, not
+ *    defined by the paper): the Sheikholeslami-Wohlert term
+ *      c_sw (i/4) sum_{mu,nu} sigma_{mu nu} Fhat_{mu nu}(x),
+ *    sigma_{mu nu} = (i/2)[gamma_mu, gamma_nu], Fhat = (Q_{mu nu} - Q_{nu mu})/8,
+ *    Q_{mu nu}(x) the sum of the four plaquettes of the (mu,nu) plane at x.
+ *  - Dirichlet restriction to a hyper-cubic domain Gamma (Section 2, eq.
+ *    blkdec): D_Gamma = P_Gamma D P_Gamma, i.e. every hop that leaves Gamma is
+ *    dropped while the site-diagonal part (mass and clover, built from the
+ *    full gauge field) is kept.  S^(i) = D_Gamma_i^{-1} (eq. diric).
+ *  - Fermion boundary conditions: periodic in space, periodic or
+ *    antiperiodic in time (a hop across the time boundary picks up -1).
+ *  - BiCGstab (van der Vorst 1992) on the unpreconditioned D_Gamma, with the
+ *    true residual recomputed and the iteration restarted from it until
+ *    ||b - D_Gamma x|| <= tol ||b|| per right-hand side.
+ *
+ * Layouts: site = ((t*L1+x1)*L2+x2)*L3+x3; spinor [rhs][site][spin][colour];
+ * links [site][mu][3][3]; clover term [site][12][12] with index spin*3+colour.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex cplx;
+
+/* Chiral (Weyl) basis: gamma_0 = [[0,-1],[-1,0]], gamma_k = [[0,-i s_k],[i s_k,0]]. */
+static const cplx G[4][4][4] = {
+    {{0, 0, -1, 0}, {0, 0, 0, -1}, {-1, 0, 0, 0}, {0, -1, 0, 0}},
+    {{0, 0, 0, -I}, {0, 0, -I, 0}, {0, I, 0, 0}, {I, 0, 0, 0}},
+    {{0, 0, 0, -1}, {0, 0, 1, 0}, {0, 1, 0, 0}, {-1, 0, 0, 0}},
+    {{0, 0, -I, 0}, {0, 0, 0, I}, {I, 0, 0, 0}, {0, -I, 0, 0}},
+};
+
+void oracle_gamma(int mu, double *out) /* 4x4 complex, row-major */
+{
+    memcpy(out, G[mu], sizeof(G[mu]));
+}
+
+typedef struct {
+    int L[4];
+    long V;
+} lat_t;
+
+static void lat_init(lat_t *g, const int L[4])
+{
+    for (int m = 0; m < 4; ++m) g->L[m] = L[m];
+    g->V = (long)L[0] * L[1] * L[2] * L[3];
+}
+static inline void coords(const lat_t *g, long s, int x[4])
+{
+    x[3] = (int)(s % g->L[3]); s /= g->L[3];
+    x[2] = (int)(s % g->L[2]); s /= g->L[2];
+    x[1] = (int)(s % g->L[1]); s /= g->L[1];
+    x[0] = (int)s;
+}
+static inline long index_of(const lat_t *g, const int x[4])
+{
+    return ((long)(x[0] * g->L[1] + x[1]) * g->L[2] + x[2]) * g->L[3] + x[3];
+}
+static inline int inside(const int x[4], const int lo[4], const int hi[4])
+{
+    for (int m = 0; m < 4; ++m)
+        if (x[m] < lo[m] || x[m] >= hi[m]) return 0;
+    return 1;
+}
+
+static inline const cplx *link(const cplx *U, long s, int mu) { return U + (s * 4 + mu) * 9; }
+
+static void mm(const cplx *a, const cplx *b, cplx *c)
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            cplx t = 0;
+            for (int k = 0; k < 3; ++k) t += a[3 * i + k] * b[3 * k + j];
+            c[3 * i + j] = t;
+        }
+}
+static void dag(const cplx *a, cplx *c)
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) c[3 * i + j] = conj(a[3 * j + i]);
+}
+static void mm4(const cplx *a, const cplx *b, const cplx *c, const cplx *d, cplx *out)
+{
+    cplx t1[9], t2[9];
+    mm(a, b, t1);
+    mm(t1, c, t2);
+    mm(t2, d, out);
+}
+
+/* Q_{mu nu}(x): the four plaquettes of the (mu,nu) plane that start and end at x. */
+static void clover_leaves(const lat_t *g, const cplx *U, long s, int mu, int nu, cplx *Q)
+{
+    int x[4];
+    coords(g, s, x);
+    /* neighbour index x + a*mu + b*nu (periodic gauge field) */
+    long n[3][3];
+    for (int a = -1; a <= 1; ++a)
+        for (int b = -1; b <= 1; ++b) {
+            int t[4] = {x[0], x[1], x[2], x[3]};
+            t[mu] = (t[mu] + a + g->L[mu]) % g->L[mu];
+            t[nu] = (t[nu] + b + g->L[nu]) % g->L[nu];
+            n[a + 1][b + 1] = index_of(g, t);
+        }
+#define AT(a, b) n[(a) + 1][(b) + 1]
+    cplx d1[9], d2[9], P[9];
+    memset(Q, 0, 9 * sizeof(cplx));
+    /* leaf 1: U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag */
+    dag(link(U, AT(0, 1), mu), d1);
+    dag(link(U, s, nu), d2);
+    mm4(link(U, s, mu), link(U, AT(1, 0), nu), d1, d2, P);
+    for (int k = 0; k < 9; ++k) Q[k] += P[k];
+    /* leaf 2: U_nu(x) U_mu(x-mu+nu)^dag U_nu(x-mu)^dag U_mu(x-mu) */
+    dag(link(U, AT(-1, 1), mu), d1);
+    dag(link(U, AT(-1, 0), nu), d2);
+    mm4(link(U, s, nu), d1, d2, link(U, AT(-1, 0), mu), P);
+    for (int k = 0; k < 9; ++k) Q[k] += P[k];
+    /* leaf 3: U_mu(x-mu)^dag U_nu(x-mu-nu)^dag U_mu(x-mu-nu) U_nu(x-nu) */
+    dag(link(U, AT(-1, 0), mu), d1);
+    dag(link(U, AT(-1, -1), nu), d2);
+    mm4(d1, d2, link(U, AT(-1, -1), mu), link(U, AT(0, -1), nu), P);
+    for (int k = 0; k < 9; ++k) Q[k] += P[k];
+    /* leaf 4: U_nu(x-nu)^dag U_mu(x-nu) U_nu(x+mu-nu) U_mu(x)^dag */
+    dag(link(U, AT(0, -1), nu), d1);
+    dag(link(U, s, mu), d2);
+    mm4(d1, link(U, AT(0, -1), mu), link(U, AT(1, -1), nu), d2, P);
+    for (int k = 0; k < 9; ++k) Q[k] += P[k];
+#undef AT
+}
+
+/* Field strength Fhat_{mu nu}(x) = (Q_{mu nu} - Q_{nu mu}) / 8 with Q_{nu mu} = Q_{mu nu}^dag. */
+void oracle_field_strength(const int L[4], const double *Ud, int mu, int nu, double *Fout)
+{
+    lat_t g;
+    lat_init(&g, L);
+    const cplx *U = (const cplx *)Ud;
+    cplx *F = (cplx *)Fout;
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < g.V; ++s) {
+        cplx Q[9];
+        clover_leaves(&g, U, s, mu, nu, Q);
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) F[s * 9 + 3 * i + j] = (Q[3 * i + j] - conj(Q[3 * j + i])) / 8.0;
+    }
+}
+
+/* 12x12 clover term per site: c_sw (i/4) sum_{mu,nu} sigma_{mu nu} (x) Fhat_{mu nu}. */
+void oracle_clover_term(const int L[4], const double *Ud, double csw, double *Cout)
+{
+    lat_t g;
+    lat_init(&g, L);
+    const cplx *U = (const cplx *)Ud;
+    cplx *C = (cplx *)Cout;
+    /* sigma_{mu nu} = (i/2)(gamma_mu gamma_nu - gamma_nu gamma_mu) */
+    cplx sig[4][4][4][4];
+    for (int mu = 0; mu < 4; ++mu)
+        for (int nu = 0; nu < 4; ++nu)
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b) {
+                    cplx t = 0;
+                    for (int c = 0; c < 4; ++c) t += G[mu][a][c] * G[nu][c][b] - G[nu][a][c] * G[mu][c][b];
+                    sig[mu][nu][a][b] = 0.5 * I * t;
+                }
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < g.V; ++s) {
+        cplx *Cs = C + s * 144;
+        memset(Cs, 0, 144 * sizeof(cplx));
+        for (int mu = 0; mu < 4; ++mu)
+            for (int nu = 0; nu < 4; ++nu) {
+                if (mu == nu) continue;
+                cplx Q[9], F[9];
+                clover_leaves(&g, U, s, mu, nu, Q);
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) F[3 * i + j] = (Q[3 * i + j] - conj(Q[3 * j + i])) / 8.0;
+                for (int a = 0; a < 4; ++a)
+                    for (int b = 0; b < 4; ++b) {
+                        cplx w = csw * 0.25 * I * sig[mu][nu][a][b];
+                        if (w == 0) continue;
+                        for (int i = 0; i < 3; ++i)
+                            for (int j = 0; j < 3; ++j) Cs[(a * 3 + i) * 12 + b * 3 + j] += w * F[3 * i + j];
+                    }
+            }
+    }
+}
+
+/* The hopping term H psi(x) = sum_mu [(1-g_mu) U_mu(x) psi(x+mu) + (1+g_mu) U_mu(x-mu)^dag psi(x-mu)],
+ * restricted to the domain [lo,hi) (hops leaving it are dropped), with sign -1
+ * on hops across the time boundary when antiperiodic. Output zero outside the domain. */
+static void hop_site(const lat_t *g, const cplx *U, int antiperiodic, const int lo[4], const int hi[4],
+                     const cplx *in, long s, cplx *out /* [12] */)
+{
+    int x[4];
+    coords(g, s, x);
+    memset(out, 0, 12 * sizeof(cplx));
+    for (int mu = 0; mu < 4; ++mu) {
+        for (int dir = 0; dir < 2; ++dir) {
+            int y[4] = {x[0], x[1], x[2], x[3]};
+            int d = dir == 0 ? 1 : -1;
+            y[mu] = x[mu] + d;
+            double sign = 1.0;
+            if (y[mu] < 0 || y[mu] >= g->L[mu]) {
+                y[mu] = (y[mu] + g->L[mu]) % g->L[mu];
+                if (mu == 0 && antiperiodic) sign = -1.0;
+            }
+            if (!inside(y, lo, hi)) continue;
+            long sy = index_of(g, y);
+            const cplx *psi = in + sy * 12;
+            cplx Upsi[12]; /* colour rotation of each spin component */
+            if (dir == 0) {
+                const cplx *u = link(U, s, mu);
+                for (int a = 0; a < 4; ++a)
+                    for (int i = 0; i < 3; ++i)
+                        Upsi[a * 3 + i] = u[3 * i] * psi[a * 3] + u[3 * i + 1] * psi[a * 3 + 1] +
+                                          u[3 * i + 2] * psi[a * 3 + 2];
+            } else {
+                const cplx *u = link(U, sy, mu);
+                for (int a = 0; a < 4; ++a)
+                    for (int i = 0; i < 3; ++i)
+                        Upsi[a * 3 + i] = conj(u[i]) * psi[a * 3] + conj(u[3 + i]) * psi[a * 3 + 1] +
+                                          conj(u[6 + i]) * psi[a * 3 + 2];
+            }
+            /* spin projector (1 - d*gamma_mu) */
+            for (int a = 0; a < 4; ++a)
+                for (int i = 0; i < 3; ++i) {
+                    cplx t = Upsi[a * 3 + i];
+                    for (int b = 0; b < 4; ++b) t -= d * G[mu][a][b] * Upsi[b * 3 + i];
+                    out[a * 3 + i] += sign * t;
+                }
+        }
+    }
+}
+
+/* out = D_Gamma in for nrhs vectors of length V*12 (clover may be NULL). */
+void oracle_apply_D(const int L[4], const double *Ud, const double *Cd, double kappa, int antiperiodic,
+                    const int lo[4], const int hi[4], int nrhs, const double *ind, double *outd)
+{
+    lat_t g;
+    lat_init(&g, L);
+    const cplx *U = (const cplx *)Ud, *C = (const cplx *)Cd, *in = (const cplx *)ind;
+    cplx *out = (cplx *)outd;
+    double diag = 1.0 / (2.0 * kappa); /* m0 + 4 */
+    for (int r = 0; r < nrhs; ++r) {
+        const cplx *ir = in + (long)r * g.V * 12;
+        cplx *orr = out + (long)r * g.V * 12;
+#pragma omp parallel for schedule(static)
+        for (long s = 0; s < g.V; ++s) {
+            int x[4];
+            coords(&g, s, x);
+            cplx *o = orr + s * 12;
+            if (!inside(x, lo, hi)) {
+                memset(o, 0, 12 * sizeof(cplx));
+                continue;
+            }
+            cplx h[12];
+            hop_site(&g, U, antiperiodic, lo, hi, ir, s, h);
+            const cplx *p = ir + s * 12;
+            for (int k = 0; k < 12; ++k) {
+                cplx t = diag * p[k] - 0.5 * h[k];
+                if (C)
+                    for (int j = 0; j < 12; ++j) t += C[s * 144 + k * 12 + j] * p[j];
+                o[k] = t;
+            }
+        }
+    }
+}
+
+/* out = D_hop in (domain-restricted hopping term, no diagonal). */
+void oracle_apply_hop(const int L[4], const double *Ud, int antiperiodic, const int lo[4], const int hi[4],
+                      int nrhs, const double *ind, double *outd)
+{
+    lat_t g;
+    lat_init(&g, L);
+    const cplx *U = (const cplx *)Ud, *in = (const cplx *)ind;
+    cplx *out = (cplx *)outd;
+    for (int r = 0; r < nrhs; ++r) {
+        const cplx *ir = in + (long)r * g.V * 12;
+        cplx *orr = out + (long)r * g.V * 12;
+#pragma omp parallel for schedule(static)
+        for (long s = 0; s < g.V; ++s) {
+            int x[4];
+            coords(&g, s, x);
+            if (!inside(x, lo, hi)) {
+                memset(orr + s * 12, 0, 12 * sizeof(cplx));
+                continue;
+            }
+            hop_site(&g, U, antiperiodic, lo, hi, ir, s, orr + s * 12);
+        }
+    }
+}
+
+/* ------------------------------------------------------------- BiCGstab */
+static cplx dotc(long n, const cplx *a, const cplx *b) /* sum conj(a) b */
+{
+    double re = 0, im = 0;
+#pragma omp parallel for reduction(+ : re, im) schedule(static)
+    for (long i = 0; i < n; ++i) {
+        cplx t = conj(a[i]) * b[i];
+        re += creal(t);
+        im += cimag(t);
+    }
+    return re + I * im;
+}
+static double norm2(long n, const cplx *a) { return creal(dotc(n, a, a)); }
+
+/* Solve D_Gamma x = b for each rhs (x zero outside Gamma).  info[r] receives
+ * the iteration count and res[r] the final true relative residual.
+ * Returns 0 if every rhs reached tol. */
+int oracle_solve(const int L[4], const double *Ud, const double *Cd, double kappa, int antiperiodic,
+                 const int lo[4], const int hi[4], int nrhs, const double *bd, double *xd, double tol,
+                 int maxiter, int *iters, double *res)
+{
+    lat_t g;
+    lat_init(&g, L);
+    long n = g.V * 12;
+    int status = 0;
+    cplx *r = malloc(n * sizeof(cplx)), *rh = malloc(n * sizeof(cplx)), *p = malloc(n * sizeof(cplx));
+    cplx *v = malloc(n * sizeof(cplx)), *s = malloc(n * sizeof(cplx)), *t = malloc(n * sizeof(cplx));
+    cplx *bm = malloc(n * sizeof(cplx));
+    for (int k = 0; k < nrhs; ++k) {
+        const cplx *b = (const cplx *)bd + (long)k * n;
+        cplx *x = (cplx *)xd + (long)k * n;
+        /* restrict the source to the domain: D_Gamma acts on fields on Gamma */
+#pragma omp parallel for schedule(static)
+        for (long q = 0; q < g.V; ++q) {
+            int xc[4];
+            coords(&g, q, xc);
+            int in = inside(xc, lo, hi);
+            for (int c = 0; c < 12; ++c) {
+                bm[q * 12 + c] = in ? b[q * 12 + c] : 0;
+                x[q * 12 + c] = 0;
+            }
+        }
+        double bn = sqrt(norm2(n, bm));
+        int it = 0;
+        double rel = 0;
+        if (bn == 0) {
+            iters[k] = 0;
+            res[k] = 0;
+            continue;
+        }
+        for (int cycle = 0; cycle < 50; ++cycle) {
+            /* true residual */
+            oracle_apply_D(L, Ud, Cd, kappa, antiperiodic, lo, hi, 1, (const double *)x, (double *)r);
+#pragma omp parallel for schedule(static)
+            for (long i = 0; i < n; ++i) r[i] = bm[i] - r[i];
+            rel = sqrt(norm2(n, r)) / bn;
+            if (rel <= tol || it >= maxiter) break;
+            memcpy(rh, r, n * sizeof(cplx));
+            memset(p, 0, n * sizeof(cplx));
+            memset(v, 0, n * sizeof(cplx));
+            cplx rho = 1, alpha = 1, omega = 1;
+            while (it < maxiter) {
+                cplx rho_new = dotc(n, rh, r);
+                if (cabs(rho_new) == 0) break;
+                cplx beta = (rho_new / rho) * (alpha / omega);
+                rho = rho_new;
+#pragma omp parallel for schedule(static)
+                for (long i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+                oracle_apply_D(L, Ud, Cd, kappa, antiperiodic, lo, hi, 1, (const double *)p, (double *)v);
+                cplx rv = dotc(n, rh, v);
+                if (cabs(rv) == 0) break;
+                alpha = rho / rv;
+#pragma omp parallel for schedule(static)
+                for (long i = 0; i < n; ++i) s[i] = r[i] - alpha * v[i];
+                oracle_apply_D(L, Ud, Cd, kappa, antiperiodic, lo, hi, 1, (const double *)s, (double *)t);
+                double tt = norm2(n, t);
+                omega = tt > 0 ? dotc(n, t, s) / tt : 0;
+#pragma omp parallel for schedule(static)
+                for (long i = 0; i < n; ++i) {
+                    x[i] += alpha * p[i] + omega * s[i];
+                    r[i] = s[i] - omega * t[i];
+                }
+                ++it;
+                /* leave the recursion early and restart from the true residual */
+                if (sqrt(norm2(n, r)) <= 0.1 * tol * bn || omega == 0) break;
+            }
+        }
+        iters[k] = it;
+        res[k] = rel;
+        if (!(rel <= tol)) status = 1;
+    }
+    free(r); free(rh); free(p); free(v); free(s); free(t); free(bm);
+    return status;
+}
