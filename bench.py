@@ -1,0 +1,293 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched multi-level domain-solve path on one MI355X.
+
+Workload (one "step" = one level-1 update round of the two-level scheme):
+  32^3 x 64 lattice, quenched beta = 6.0 field, kappa = 0.1340, c_sw = 1.769,
+  antiperiodic time; 4 time slabs of 16 slices, each updated independently by
+  one heatbath sweep with its first-slice spatial links frozen (Section 3.1);
+  for every slab update: the new gauge version is uploaded and its clover term
+  built, then the nested Dirichlet domains Gamma0 (4 slices), Gamma1 (8) and
+  Gamma2 (the 16-slice slab) are solved for 12 point-source columns to a
+  relative residual of 1e-10 (FP32 inner BiCGstab, FP64 defect correction),
+  all 12 solves of the round in one batch; the telescoping series and the
+  nucleon and disconnected pseudoscalar contractions follow.
+Reported: domain solves/s (a solve = one domain x 12 columns to 1e-10), the
+stencil roofline (HIP events inside the library), the plain FP64 solver one
+solve at a time, serving latency percentiles, and the FP64 CPU oracle on a
+bounded sample.  Inputs are resident on the GPU before timing starts.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM = 8.0e12  # MI355X HBM3E, bytes/s
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--dims", default="64,32,32,32", help="T,L1,L2,L3 (T a multiple of 16)")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=32)
+    ap.add_argument("--serve-rate", type=float, default=0.0, help="req/s (0: 0.7 x measured capacity)")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--stencil-iters", type=int, default=20)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs every domain solve on a single "
+              "MI355X (no collectives); --gpus %d is not supported." % args.gpus, file=sys.stderr)
+        return 2
+    import torch
+
+    import inputs
+    from paper_1601_04587_amd import ddml
+
+    assert torch.cuda.is_available(), "needs a GPU"
+    dev = torch.device("cuda:0")
+    L = tuple(int(v) for v in args.dims.split(","))
+    T = L[0]
+    nslab = T // 16
+    V = int(np.prod(L))
+    V3 = V // T
+    kappa, csw, beta = 0.1340, 1.769, 6.0
+    seed = 1601004
+    nsteps = args.warmup + args.steps
+
+    # ------------------------------------------------------------ inputs
+    t = time.time()
+    U0 = inputs.quenched_field(L, seed, beta=beta)
+    log("base field %s plaquette %.4f (%.1fs)" % (L, inputs.plaquette(U0, L), time.time() - t))
+    t = time.time()
+    Uw = np.ascontiguousarray(U0.copy())
+    regions = []   # [step][slab] device tensors of the slab's links after the update
+    for j in range(nsteps):
+        row = []
+        for s in range(nslab):
+            inputs.level1_update_inplace(Uw, L, beta, seed, 1000 + j * nslab + s, 16 * s, 16 * s + 16,
+                                         nsweeps=1, n_or=0)
+            reg = np.ascontiguousarray(Uw[16 * s * V3:(16 * s + 16) * V3])
+            row.append(torch.from_numpy(reg).to(dev))
+        regions.append(row)
+    log("level-1 updates: %d x %d slabs (%.1fs)" % (nsteps, nslab, time.time() - t))
+    U0_dev = torch.from_numpy(U0).to(dev)
+    srcs, terms = [], []
+    xs = []
+    for s in range(nslab):
+        x = (16 * s + 7, 0, 0, 0)
+        xs.append(x)
+        b = torch.zeros((12, V, 4, 3), dtype=torch.complex128, device=dev)
+        idx = inputs.site_index(L, x)
+        for r in range(12):
+            b[r, idx, r // 3, r % 3] = 1.0
+        srcs.append(b)
+        terms.append(torch.zeros((3, 12, V, 4, 3), dtype=torch.complex128, device=dev))
+    torch.cuda.synchronize()
+
+    ctx = ddml.Context(L, ddml.BC_ANTIPERIODIC, device=0)
+    gid0 = ctx.set_gauge(U0_dev, kappa, csw)
+    doms = []
+    for s in range(nslab):
+        a = 16 * s
+        doms.append([ctx.set_domain((a + 6, 0, 0, 0), (a + 10,) + L[1:]),
+                     ctx.set_domain((a + 4, 0, 0, 0), (a + 12,) + L[1:]),
+                     ctx.set_domain((a, 0, 0, 0), (a + 16,) + L[1:])])
+    params = ddml.solver_params(tol=1e-10, prec=ddml.MIXED_FP32)
+
+    def step(j, prm=params, batched=True):
+        gids = [ctx.set_gauge_region(gid0, 16 * s, 16 * s + 16, regions[j][s]) for s in range(nslab)]
+        if batched:
+            rc, infos = ctx.propagator_series_batch(
+                [(gids[s], doms[s], srcs[s], terms[s], None) for s in range(nslab)], 12, prm)
+        else:
+            infos = []
+            rc = ddml.OK
+            for s in range(nslab):
+                per = []
+                for lev in range(3):
+                    r, inf = ctx.solve_domain(gids[s], doms[s][lev], srcs[s], terms[s][lev], 12, prm)
+                    rc = rc or r
+                    per.append(inf)
+                infos.append(per)
+        nuc = [ctx.contract_nucleon(terms[s], 3) for s in range(nslab)]
+        pp = [ctx.contract_pp_disconnected(terms[s], terms[(s + 2) % nslab], 3, xs[s], xs[(s + 2) % nslab])
+              for s in range(nslab // 2)]
+        for g in gids:
+            ctx.release_gauge(g)
+        return rc, infos, nuc, pp
+
+    # ------------------------------------------------------------ timed
+    for j in range(args.warmup):
+        rc, infos, _, _ = step(j)
+        log("warmup step %d rc %d" % (j, rc))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters, worst = [], 0.0
+    for j in range(args.warmup, nsteps):
+        rc, infos, nuc, pp = step(j)
+        assert rc == ddml.OK, "solve failed: %s" % ctx.last_error()
+        for per_slab in infos:
+            for per_level in per_slab:
+                iters.append(max(i.inner_iters for i in per_level))
+                worst = max(worst, max(i.true_rel_residual for i in per_level))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nsolves = 3 * nslab * args.steps
+    solves_per_s = nsolves / (t1 - t0)
+    ms_per_step = 1e3 * (t1 - t0) / args.steps
+    log("mixed batched: %d solves in %.2fs -> %.3f solves/s, worst residual %.2e, inner iters %s"
+        % (nsolves, t1 - t0, solves_per_s, worst, iters[:6]))
+
+    # --------------------------------------------------- stencil roofline
+    sten32 = ctx.time_stencil(gid0, doms[0][2], 12, ddml.MIXED_FP32, args.stencil_iters)
+    sten64 = ctx.time_stencil(gid0, doms[0][2], 12, ddml.FP64, max(4, args.stencil_iters // 2))
+    ach = sten32[3] / (sten32[1] * 1e-3)
+    ach_odd = sten32[2] / (sten32[0] * 1e-3)
+    ach64 = sten64[3] / (sten64[1] * 1e-3)
+    log("stencil fp32: even half %.3f ms %.0f GB/s, odd half %.3f ms %.0f GB/s; fp64 even half %.0f GB/s"
+        % (sten32[1], ach / 1e9, sten32[0], ach_odd / 1e9, ach64 / 1e9))
+
+    # ------------------------------------------------ plain FP64 baseline
+    fp64 = None
+    if not args.no_fp64:
+        prm64 = ddml.solver_params(tol=1e-10, prec=ddml.FP64)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        rc, infos, _, _ = step(nsteps - 1, prm64, batched=False)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        fp64 = {"solves_per_s": 3 * nslab / (b - a), "mode": "FP64 inner and outer, one solve at a time",
+                "status": ddml.STATUS_NAMES[rc]}
+        log("plain FP64 one-at-a-time: %.3f solves/s" % fp64["solves_per_s"])
+
+    # ------------------------------------------------------------ serving
+    serve = None
+    if not args.no_serve:
+        serve = run_serving(ctx, ddml, torch, dev, gid0, L, doms, srcs, terms, solves_per_s, args)
+
+    # ------------------------------------------------------- CPU baseline
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(U0, L, kappa, csw, args.cpu_seconds)
+
+    ctx.close()
+    out = {
+        "metric": "domain solves/s & stencil HBM GB/s, mixed vs FP64 @1e-10; p50/p99 solve latency",
+        "value": solves_per_s,
+        "unit": "domain solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32 inner / fp64 outer",
+        "data": "synthetic: seeded beta=6.0 quenched heatbath fields and level-1 slab updates",
+        "config": {"workload": "batched multi-level, %s lattice, %d slabs x 1 update per step, "
+                               "Gamma0/1/2 = 4/8/16 slices x 12 rhs, tol 1e-10" % ("x".join(map(str, L)), nslab),
+                   "lattice": list(L), "kappa": kappa, "csw": csw, "solves_per_step": 3 * nslab, "nrhs": 12},
+        "roofline": {"bound": "hbm", "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                     "frac": ach / PEAK_HBM, "traffic": None,
+                     "kernel": "k_hop_batch<float2> even half-stencil (Schur + fused dot), 32^3x16 domain, 12 rhs",
+                     "ms_per_launch": sten32[1], "bytes_per_launch": sten32[3],
+                     "odd_half": {"ms": sten32[0], "GB/s": ach_odd / 1e9},
+                     "fp64_even_half_GBps": ach64 / 1e9},
+        "fp64_one_at_a_time": fp64,
+        "mixed_over_fp64": (solves_per_s / fp64["solves_per_s"]) if fp64 else None,
+        "serving": serve,
+        "inner_iters_per_solve": iters,
+        "worst_true_rel_residual": worst,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def run_serving(ctx, ddml, torch, dev, gid0, L, doms, srcs, terms, capacity, args):
+    """Poisson stream of domain-solve requests on the slab domains of the base field."""
+    rng = np.random.default_rng(1601005)
+    rate = args.serve_rate if args.serve_rate > 0 else 0.7 * capacity
+    n = args.serve_requests
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    choice = rng.integers(0, 3, size=n)
+    slab = rng.integers(0, len(doms), size=n)
+    # output buffers are reused round-robin (outputs are not inspected here)
+    sols = [torch.zeros_like(srcs[0]) for _ in range(4)]
+    ctx.server_start(ddml.solver_params(tol=1e-10), max_queue=100000)
+    t0 = ddml.now()
+    tickets = []
+    for k in range(n):
+        while ddml.now() - t0 < arrivals[k]:
+            time.sleep(0.0005)
+        s = int(slab[k])
+        tickets.append(ctx.submit(gid0, doms[s][int(choice[k])], srcs[s], sols[k % 4], 12,
+                                  arrival_time=t0 + arrivals[k]))
+    res = [ctx.wait(tk, 600.0) for tk in tickets]
+    st = ctx.stats()
+    ctx.server_stop()
+    ok = sum(1 for r in res if r is not None and r.status == ddml.OK)
+    out = {"requests": n, "rate_req_per_s": rate, "ok": ok, "p50_latency_s": st.p50_latency,
+           "p99_latency_s": st.p99_latency, "mean_latency_s": st.mean_latency, "solves_per_s": st.solves_per_s,
+           "domains": "Gamma0/1/2 slabs (4/8/16 x 32^3) of the base field, 12 rhs, mixed 1e-10"}
+    log("serving: %s" % out)
+    return out
+
+
+def cpu_baseline(U0, L, kappa, csw, seconds):
+    """FP64 CPU oracle on a bounded sample: one column of a Gamma0 (4 x 32^3) solve."""
+    import inputs
+    import oracle
+
+    V3 = int(np.prod(L[1:]))
+    Ls = (16,) + tuple(L[1:])
+    Us = np.ascontiguousarray(U0[:16 * V3])          # slab 0 as its own 16 x 32^3 lattice
+    C = oracle.clover_term(Us, Ls, csw)
+    lo, hi = (6, 0, 0, 0), (10,) + tuple(L[1:])
+    b = inputs.point_source(Ls, (7, 0, 0, 0))[:1]
+    # calibrate the iteration time, then run a bounded solve
+    t = time.time()
+    _, it0, _ = oracle.solve(Us, Ls, kappa, b, C=C, lo=lo, hi=hi, tol=1e-30, maxiter=3)
+    per_it = (time.time() - t) / 3
+    maxit = max(5, int(seconds / per_it))
+    t = time.time()
+    x, it, res = oracle.solve(Us, Ls, kappa, b, C=C, lo=lo, hi=hi, tol=1e-10, maxiter=maxit)
+    el = time.time() - t
+    it = int(it[0])
+    r = float(res[0])
+    if r <= 1e-10:
+        need = it
+    else:  # linear in log residual
+        need = int(np.ceil(it * np.log(1e-10) / np.log(max(r, 1e-300))))
+    t_col = el / max(it, 1) * need
+    # a domain solve has 12 columns; the step mixes Gamma0/1/2 with volumes 1:2:4
+    solves_per_s = 3.0 / (12 * t_col * (1 + 2 + 4))
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count()))
+    out = {"value": solves_per_s, "unit": "domain solves/s", "cores": cores, "kind": "oracle",
+           "sample": "1 of 12 columns of a Gamma0 (4x32^3) solve, %d BiCGstab iterations in %.1fs, residual %.1e%s; "
+                     "scaled to 12 columns and the 1:2:4 volume mix of Gamma0/1/2 assuming equal iteration counts"
+                     % (it, el, r, "" if r <= 1e-10 else " (iterations to 1e-10 extrapolated: %d)" % need)}
+    log("cpu baseline: %s" % out)
+    return out
+
+
+if __name__ == "__main__":
+    sys.exit(main())

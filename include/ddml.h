@@ -1,0 +1,260 @@
+/*
+ * libddml: domain-decomposed Wilson-clover quark propagators on one MI355X.
+ *
+ * The method (Ce, Giusti, Schaefer, "Domain decomposition, multi-level
+ * integration and exponential noise reduction in lattice QCD"):
+ *   - D is the Wilson-Dirac operator of Appendix A (eq. wdo) with bare mass
+ *     m0 = 1/(2 kappa) - 4, i.e. 2 kappa D = 1 - kappa D_hop (Section 6), plus,
+ *     when c_sw != 0, the Sheikholeslami-Wohlert term
+ *     c_sw (i/4) sum_{mu,nu} sigma_{mu nu} Fhat_{mu nu} (the O(a) improvement
+ *     named in the footnotes of Sections 4 and 6; the paper gives no formula).
+ *   - D_Gamma is D restricted to a hyper-cubic domain Gamma with every term
+ *     that touches the exterior boundary set to zero (Section 2, eq. blkdec);
+ *     S^(i) = D_Gamma_i^{-1} (eq. diric), zero outside Gamma_i.
+ *   - The propagator series S = S^(0) + [S^(1) - S^(0)] + ... (eq. Dseries).
+ *   - The disconnected pseudoscalar contraction split into W^(f), W^(r1),
+ *     W^(r2) (Section 3, eqs. W0, rall0, rall) and the nucleon contraction
+ *     W_N1 - W_N2 (Section 5.2, eq. baryfact) summed over sink time slices
+ *     (eq. baryN).
+ *
+ * Canonical layouts at this boundary (all complex numbers are interleaved
+ * (re, im) doubles):
+ *   lattice   dims[4] = {T, L1, L2, L3}; site = ((t*L1 + x1)*L2 + x2)*L3 + x3
+ *   links     U[site][mu][3][3], row-major colour, U_mu(x) joins x and x+mu
+ *   spinors   psi[rhs][site][spin 4][colour 3]
+ *   gamma matrices: chiral basis, gamma_0 = [[0,-1],[-1,0]],
+ *             gamma_k = [[0,-i s_k],[i s_k,0]], gamma_5 = diag(1,1,-1,-1)
+ *   a point-source propagator holds S(y,x)[alpha a][beta b] in column
+ *   rhs = 3*beta + b, i.e. psi[3*beta+b][y][alpha][a].
+ * Fermion boundary conditions: periodic in space; periodic or antiperiodic in
+ * time.  The gauge field is periodic.
+ *
+ * Ownership: the caller owns every buffer it passes.  A buffer flagged
+ * on_device=1 is device memory on the context's GPU (e.g. a torch tensor's
+ * data_ptr()); on_device=0 means host memory.  The library copies what it
+ * keeps (gauge fields) and owns all internal device state.  `stream` is a
+ * hipStream_t (may be NULL for the default stream); work is ordered after
+ * what is already queued on it.  Calls that return solver information
+ * (solve_domain, propagator_series, solve_batch) block until the result is
+ * ready; apply_Dw and apply_eo with on_device=1 only enqueue.
+ *
+ * Errors: every call returns a ddml_status; no exception crosses this
+ * boundary.  The message of the most recent failure on a context is returned
+ * by ddml_last_error.  Calls on one context are serialised internally.
+ */
+#ifndef DDML_H
+#define DDML_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ddml_ctx_s* ddml_ctx;
+
+typedef enum {
+  DDML_OK = 0,
+  DDML_EINVAL = -1,          /* invalid argument */
+  DDML_ENOMEM = -2,          /* allocation failed or HBM budget exceeded */
+  DDML_EAGAIN = -3,          /* result not ready / queue full */
+  DDML_ENOTCONVERGED = -4,   /* a right-hand side missed the tolerance; info filled */
+  DDML_ENUMERIC = -5,        /* NaN/Inf or a non-invertible clover block */
+  DDML_EDEVICE = -6          /* HIP runtime error */
+} ddml_status;
+
+typedef enum { DDML_BC_PERIODIC = 0, DDML_BC_ANTIPERIODIC = 1 } ddml_bc;
+
+typedef enum {
+  DDML_FP64 = 0,        /* FP64 throughout (the plain FP64 GPU solver) */
+  DDML_MIXED_FP32 = 1   /* FP32 inner Krylov solve, FP64 defect correction */
+} ddml_prec;
+
+typedef struct {
+  int dims[4];   /* T, L1, L2, L3; all even */
+  int bc_time;   /* ddml_bc */
+} ddml_lattice;
+
+typedef struct {
+  double tol;        /* target ||b - D_Gamma x|| / ||b|| per rhs (FP64 true residual) */
+  int max_outer;     /* defect-correction cycles */
+  int max_inner;     /* BiCGstab iterations per cycle */
+  double inner_tol;  /* relative reduction of the inner residual per cycle */
+  int prec;          /* ddml_prec */
+  int solver;        /* 0 = BiCGstab (the only one) */
+  int gcr_m;         /* reserved */
+} ddml_solver_params;
+
+typedef struct {
+  int status;              /* ddml_status of this rhs */
+  int outer_iters;         /* defect-correction cycles used */
+  int inner_iters;         /* total BiCGstab iterations */
+  double true_rel_residual;/* final ||b - D_Gamma x|| / ||b|| in FP64 */
+} ddml_rhs_info;
+
+/* Context on GPU `device`.  hbm_budget_bytes bounds the library's own device
+ * allocations (0 = 90% of free memory at creation).  Lattice extents must be
+ * even.  Errors: EINVAL (bad lattice), EDEVICE. */
+int ddml_create(ddml_ctx* out, const ddml_lattice* lat, int device, size_t hbm_budget_bytes);
+int ddml_destroy(ddml_ctx ctx);
+/* Message of the last failure on ctx (static empty string if none). */
+const char* ddml_last_error(ddml_ctx ctx);
+
+/* Gauge field (Appendix A links; the whole lattice, canonical layout, copied)
+ * with the operator parameters kappa and c_sw used with it.  Returns a new
+ * gauge id.  Errors: EINVAL, ENOMEM. */
+int ddml_set_gauge(ddml_ctx ctx, const double* U, int on_device, double kappa, double csw, int* gauge_id);
+/* Level-1 update of the two-level integration (Section 3.1): a new gauge id
+ * equal to base_gauge_id except on time slices [t0, t1), whose links are
+ * U_region[(t - t0)*L1*L2*L3 + ...][mu][3][3].  The base is shared, not
+ * copied.  Errors: EINVAL (bad range or id), ENOMEM. */
+int ddml_set_gauge_region(ddml_ctx ctx, int base_gauge_id, int t0, int t1, const double* U_region,
+                          int on_device, int* new_gauge_id);
+/* Drop a gauge id and the operator data built from it. */
+int ddml_release_gauge(ddml_ctx ctx, int gauge_id);
+
+/* Hyper-cubic domain Gamma = [lo, hi) (Section 2), half-open per direction,
+ * extents even and inside the lattice.  A direction with hi-lo equal to the
+ * lattice extent keeps its (anti)periodic wrap; otherwise hops across the
+ * faces are dropped (Dirichlet, eq. blkdec).  Errors: EINVAL. */
+int ddml_set_domain(ddml_ctx ctx, const int lo[4], const int hi[4], int* dom_id);
+
+/* out = D_Gamma in (dom_id = -1: the full lattice), canonical layout,
+ * nrhs columns; out is zero outside Gamma (eq. blkdec, Appendix A).
+ * prec = DDML_FP64 only.  Errors: EINVAL, ENOMEM, EDEVICE. */
+int ddml_apply_Dw(ddml_ctx ctx, int gauge_id, int dom_id, const double* in, double* out, int nrhs,
+                  int prec, int on_device, void* stream);
+
+/* The even-odd Schur operator used inside the solver:
+ *   out_e = in_e - kappa^2 A_ee^{-1} H_eo A_oo^{-1} H_oe in_e
+ * with M = 2 kappa D = A - kappa H, on the sites of Gamma whose local parity
+ * (sum_mu (x_mu - lo_mu) mod 2) is even; out is zero on all other sites.
+ * prec selects FP64 or FP32 arithmetic (FP32: inputs rounded to FP32, output
+ * widened).  Errors: EINVAL, ENOMEM, EDEVICE. */
+int ddml_apply_eo(ddml_ctx ctx, int gauge_id, int dom_id, const double* in, double* out, int nrhs, int prec,
+                  int on_device, void* stream);
+
+/* sol = D_Gamma^{-1} src for nrhs columns (eq. diric), zero outside Gamma.
+ * Sources are restricted to Gamma first.  info[nrhs] receives per-column
+ * status, iteration counts and the FP64 true residual.  Returns
+ * ENOTCONVERGED if a column missed params->tol.  Errors: EINVAL, ENOMEM,
+ * ENUMERIC, EDEVICE. */
+int ddml_solve_domain(ddml_ctx ctx, int gauge_id, int dom_id, const double* src, double* sol, int nrhs,
+                      const ddml_solver_params* params, ddml_rhs_info* info, int on_device, void* stream);
+
+/* One solve of a batch. */
+typedef struct {
+  int gauge_id;
+  int dom_id;
+  const double* src;   /* [nrhs][V][4][3] */
+  double* sol;         /* [nrhs][V][4][3] */
+  int nrhs;
+  ddml_rhs_info* info; /* [nrhs] */
+} ddml_solve_desc;
+
+/* Many independent domain solves of uneven size advanced together: every
+ * inner iteration is one set of batched launches over all solves in flight,
+ * replayed from a captured HIP graph, and solves join and leave the batch as
+ * they converge (admission bounded by the HBM budget).  Same semantics per
+ * solve as ddml_solve_domain.  All descs must use the same nrhs. */
+int ddml_solve_batch(ddml_ctx ctx, int nsolves, const ddml_solve_desc* descs, const ddml_solver_params* params,
+                     int on_device, void* stream);
+
+/* eq. Dseries: solves S^(i) on the nested domains dom_ids[0..nlevels) and
+ * writes terms[0] = S^(0), terms[i] = S^(i) - S^(i-1) (each [nrhs][V][4][3],
+ * contiguous over i) and sum = S^(nlevels-1).  info is [nlevels][nrhs].
+ * Errors as ddml_solve_domain. */
+int ddml_propagator_series(ddml_ctx ctx, int gauge_id, const int* dom_ids, int nlevels, const double* src,
+                           int nrhs, const ddml_solver_params* params, double* terms, double* sum,
+                           ddml_rhs_info* info, int on_device, void* stream);
+
+/* One propagator series of a batch (see ddml_propagator_series). */
+typedef struct {
+  int gauge_id;
+  const int* dom_ids;   /* [nlevels], nested Gamma_0 c Gamma_1 c ... */
+  int nlevels;
+  const double* src;    /* [nrhs][V][4][3] */
+  double* terms;        /* [nlevels][nrhs][V][4][3] */
+  double* sum;          /* [nrhs][V][4][3] or NULL */
+  ddml_rhs_info* info;  /* [nlevels][nrhs] */
+} ddml_series_desc;
+
+/* Several series (e.g. one per level-1 slab update) with all their domain
+ * solves advanced in one batch (as ddml_solve_batch).  Same nrhs for all. */
+int ddml_propagator_series_batch(ddml_ctx ctx, int nseries, const ddml_series_desc* descs, int nrhs,
+                                 const ddml_solver_params* params, int on_device, void* stream);
+
+/* Disconnected pseudoscalar pieces (Section 3, eqs. deco1, W0, rall0, rall)
+ * from point-source series around x (terms_x) and y (terms_y), 12 columns
+ * each, nlevels levels with the last one the full-lattice propagator.
+ * For level i, t_x = tr{g5 S^(i)(x,x)} with S^(i) the partial sum of terms up
+ * to i, dt_x = t_x(full) - t_x; by eq. bella the r-kernels are [S - S^(i)](x,x).
+ * out[level][4] complex = (f, r1, r2, full) / L^3 with
+ * f = t_x t_y, r1 = dt_x t_y + t_x dt_y, r2 = dt_x dt_y, full = f + r1 + r2.
+ * Errors: EINVAL, EDEVICE. */
+int ddml_contract_pp_disconnected(ddml_ctx ctx, const double* terms_x, const double* terms_y, int nlevels,
+                                  const int xsrc[4], const int ysrc[4], double* out, int on_device, void* stream);
+
+/* Nucleon two-point function (eq. baryfact, eq. baryN) for each level of a
+ * 12-column point-source series: levels_out[i][y0] = sum_{y in slice y0}
+ * (W_N1 - W_N2)(y, x) with S = S^(i) (partial sums of terms), and
+ * diffs_out[i][y0] = levels[i] - levels[i-1] (eq. seriesN), diffs[0] = levels[0].
+ * Both are [nlevels][T] complex on the host.  Errors: EINVAL, EDEVICE. */
+int ddml_contract_nucleon(ddml_ctx ctx, const double* terms, int nlevels, double* levels_out, double* diffs_out,
+                          int on_device, void* stream);
+
+/* Measurement hook for the dominant kernels: times `iters` back-to-back
+ * applications of the two half-stencils of the even-odd Schur operator, as
+ * launched by the batched solver (links + A^{-1} + fused dot product), on the
+ * library stream with HIP events, after 3 untimed warm-up pairs.  out[0],
+ * out[1]: average milliseconds per launch of the odd half (out_o = A_oo^{-1}
+ * H_oe in_e) and of the even half (out_e = in_e - kappa^2 A_ee^{-1} H_eo t_o
+ * with the dot product (r0, out_e)); out[2], out[3]: algorithmic bytes of one
+ * launch of each (every array the kernel must touch, counted once).
+ * prec: DDML_FP64 or DDML_MIXED_FP32 (FP32 kernels).  Errors: EINVAL, ENOMEM. */
+int ddml_time_stencil(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec, int iters, double out[4]);
+
+/* ------------------------------------------------------------- serving */
+typedef struct {
+  int gauge_id;
+  int dom_id;
+  const double* src;    /* device pointer [nrhs][V][4][3], must stay valid until completion */
+  double* sol;          /* device pointer, written on completion */
+  int nrhs;
+  double arrival_time;  /* caller's clock (seconds), used for latency */
+} ddml_request;
+
+typedef struct {
+  int status;             /* ddml_status of the request */
+  int max_outer, max_inner_iters;
+  double worst_rel_residual;
+  double arrival_time, admit_time, finish_time;  /* same clock as arrival_time */
+} ddml_result;
+
+typedef struct {
+  long submitted, completed, queued, in_flight;
+  double p50_latency, p99_latency, mean_latency;  /* seconds, over completed requests */
+  double solves_per_s;                            /* completed / (last finish - first arrival) */
+  size_t hbm_in_use, hbm_budget;
+} ddml_server_stats;
+
+/* Start the request loop on its own host thread.  Requests are admitted as
+ * their HBM footprint fits the budget and join the running batch (continuous
+ * batching); params applies to every request.  max_queue bounds pending
+ * requests (submit returns EAGAIN beyond it). */
+int ddml_server_start(ddml_ctx ctx, const ddml_solver_params* params, int max_queue);
+int ddml_submit(ddml_ctx ctx, const ddml_request* req, uint64_t* ticket);
+/* EAGAIN while pending; DDML_OK and *res once finished (the result is kept). */
+int ddml_poll(ddml_ctx ctx, uint64_t ticket, ddml_result* res);
+int ddml_wait(ddml_ctx ctx, uint64_t ticket, ddml_result* res, double timeout_s);
+int ddml_stats(ddml_ctx ctx, ddml_server_stats* stats);
+int ddml_server_stop(ddml_ctx ctx);
+
+/* Seconds on the library's monotonic clock (the serving loop's clock). */
+double ddml_now(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -116,6 +116,17 @@ def level1_update(U, L, beta, seed, update_id, t0, t1, nsweeps=1, n_or=4):
     return U2
 
 
+def level1_update_inplace(U, L, beta, seed, update_id, t0, t1, nsweeps=1, n_or=4):
+    """In-place version of level1_update (U must be C-contiguous complex128).
+
+    Updates of different slabs touch disjoint links and read only their own
+    slab and frozen links, so several slab chains can share one array."""
+    cL, L = _dims(L)
+    assert U.dtype == np.complex128 and U.flags["C_CONTIGUOUS"]
+    _load().gen_level1_update(cL, beta, seed, update_id, t0, t1, nsweeps, n_or, U.ctypes.data)
+    return U
+
+
 def plaquette(U, L):
     cL, L = _dims(L)
     return _load().gen_plaquette(cL, np.ascontiguousarray(U).ctypes.data)

@@ -1,0 +1,410 @@
+// C ABI of libddml (declarations and documentation in include/ddml.h).
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "engine.hpp"
+#include "server.hpp"
+
+using namespace ddml;
+
+struct ddml_ctx_s {
+  Ctx c;
+};
+
+namespace {
+
+// Orders the library stream after the caller's stream on entry and the
+// caller's stream after the library stream on exit.
+struct StreamJoin {
+  Ctx* c;
+  hipStream_t user;
+  StreamJoin(Ctx* ctx, void* s) : c(ctx), user((hipStream_t)s) {
+    hipEvent_t e;
+    DDML_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    DDML_HIP(hipEventRecord(e, user));
+    DDML_HIP(hipStreamWaitEvent(c->stream, e, 0));
+    DDML_HIP(hipEventDestroy(e));
+  }
+  void done() {
+    hipEvent_t e;
+    DDML_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    DDML_HIP(hipEventRecord(e, c->stream));
+    DDML_HIP(hipStreamWaitEvent(user, e, 0));
+    DDML_HIP(hipEventDestroy(e));
+  }
+};
+
+template <typename F>
+int guarded(ddml_ctx ctx, F&& f) {
+  if (!ctx) return DDML_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->c.mu);
+  try {
+    DDML_HIP(hipSetDevice(ctx->c.device));
+    int rc = f(&ctx->c);
+    return rc;
+  } catch (const Error& e) {
+    ctx->c.last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    ctx->c.last_error = "host allocation failed";
+    return DDML_ENOMEM;
+  } catch (const std::exception& e) {
+    ctx->c.last_error = e.what();
+    return DDML_EINVAL;
+  }
+}
+
+// Staging of a canonical array: device pointer as is, or a device copy of host data.
+struct Staged {
+  DBuf buf;
+  const double* cptr = nullptr;
+  double* ptr = nullptr;
+};
+
+Staged stage_in(Ctx* c, const double* p, size_t bytes, int on_device) {
+  Staged s;
+  if (on_device) {
+    s.cptr = p;
+    s.ptr = const_cast<double*>(p);
+    return s;
+  }
+  s.buf = DBuf(c->pool.get(), bytes);
+  DDML_HIP(hipMemcpyAsync(s.buf.p, p, bytes, hipMemcpyHostToDevice, c->stream));
+  s.cptr = s.buf.as<double>();
+  s.ptr = s.buf.as<double>();
+  return s;
+}
+
+Staged stage_out(Ctx* c, double* p, size_t bytes, int on_device) {
+  Staged s;
+  if (on_device) {
+    s.ptr = p;
+    s.cptr = p;
+    return s;
+  }
+  s.buf = DBuf(c->pool.get(), bytes);
+  s.ptr = s.buf.as<double>();
+  s.cptr = s.ptr;
+  return s;
+}
+
+void copy_back(Ctx* c, double* host, const Staged& s, size_t bytes, int on_device) {
+  if (on_device) return;
+  DDML_HIP(hipMemcpyAsync(host, s.cptr, bytes, hipMemcpyDeviceToHost, c->stream));
+  DDML_HIP(hipStreamSynchronize(c->stream));
+}
+
+void need(bool cond, const char* msg) {
+  if (!cond) throw Error{DDML_EINVAL, msg};
+}
+
+}  // namespace
+
+extern "C" {
+
+double ddml_now(void) { return now_s(); }
+
+int ddml_create(ddml_ctx* out, const ddml_lattice* lat, int device, size_t hbm_budget_bytes) {
+  if (!out) return DDML_EINVAL;
+  *out = nullptr;
+  ddml_ctx ctx = new (std::nothrow) ddml_ctx_s();
+  if (!ctx) return DDML_ENOMEM;
+  try {
+    ctx_init(&ctx->c, lat, device, hbm_budget_bytes);
+  } catch (const Error& e) {
+    delete ctx;
+    return e.code;
+  }
+  *out = ctx;
+  return DDML_OK;
+}
+
+int ddml_destroy(ddml_ctx ctx) {
+  if (!ctx) return DDML_EINVAL;
+  ctx->c.server.reset();
+  {
+    std::lock_guard<std::recursive_mutex> lk(ctx->c.mu);
+    (void)hipSetDevice(ctx->c.device);
+    (void)hipStreamSynchronize(ctx->c.stream);
+  }
+  delete ctx;
+  return DDML_OK;
+}
+
+const char* ddml_last_error(ddml_ctx ctx) {
+  static const char empty[] = "";
+  if (!ctx) return empty;
+  return ctx->c.last_error.c_str();
+}
+
+int ddml_set_gauge(ddml_ctx ctx, const double* U, int on_device, double kappa, double csw, int* gauge_id) {
+  return guarded(ctx, [&](Ctx* c) {
+    need(gauge_id != nullptr, "gauge_id is NULL");
+    *gauge_id = gauge_new(c, U, on_device, kappa, csw);
+    return DDML_OK;
+  });
+}
+
+int ddml_set_gauge_region(ddml_ctx ctx, int base_gauge_id, int t0, int t1, const double* U_region, int on_device,
+                          int* new_gauge_id) {
+  return guarded(ctx, [&](Ctx* c) {
+    need(new_gauge_id != nullptr, "new_gauge_id is NULL");
+    *new_gauge_id = gauge_region(c, base_gauge_id, t0, t1, U_region, on_device);
+    return DDML_OK;
+  });
+}
+
+int ddml_release_gauge(ddml_ctx ctx, int gauge_id) {
+  return guarded(ctx, [&](Ctx* c) {
+    gauge_release(c, gauge_id);
+    return DDML_OK;
+  });
+}
+
+int ddml_set_domain(ddml_ctx ctx, const int lo[4], const int hi[4], int* dom_id) {
+  return guarded(ctx, [&](Ctx* c) {
+    need(dom_id != nullptr, "dom_id is NULL");
+    *dom_id = domain_new(c, lo, hi);
+    return DDML_OK;
+  });
+}
+
+int ddml_apply_Dw(ddml_ctx ctx, int gauge_id, int dom_id, const double* in, double* out, int nrhs, int prec,
+                  int on_device, void* stream) {
+  return guarded(ctx, [&](Ctx* c) {
+    need(in && out, "NULL buffer");
+    need(nrhs >= 1 && nrhs <= kMaxRhs, "nrhs must be in 1..12");
+    need(prec == DDML_FP64, "apply_Dw is FP64");
+    const size_t bytes = (size_t)nrhs * c->V * 12 * sizeof(double2);
+    StreamJoin sj(c, stream);
+    Staged si = stage_in(c, in, bytes, on_device);
+    Staged so = stage_out(c, out, bytes, on_device);
+    apply_D(c, gauge_id, dom_id, si.cptr, so.ptr, nrhs, c->stream);
+    copy_back(c, out, so, bytes, on_device);
+    sj.done();
+    return DDML_OK;
+  });
+}
+
+int ddml_apply_eo(ddml_ctx ctx, int gauge_id, int dom_id, const double* in, double* out, int nrhs, int prec,
+                  int on_device, void* stream) {
+  return guarded(ctx, [&](Ctx* c) {
+    need(in && out, "NULL buffer");
+    need(nrhs >= 1 && nrhs <= kMaxRhs, "nrhs must be in 1..12");
+    need(prec == DDML_FP64 || prec == DDML_MIXED_FP32, "unknown precision");
+    const size_t bytes = (size_t)nrhs * c->V * 12 * sizeof(double2);
+    StreamJoin sj(c, stream);
+    Staged si = stage_in(c, in, bytes, on_device);
+    Staged so = stage_out(c, out, bytes, on_device);
+    apply_eo(c, gauge_id, dom_id, si.cptr, so.ptr, nrhs, prec, c->stream);
+    copy_back(c, out, so, bytes, on_device);
+    sj.done();
+    return DDML_OK;
+  });
+}
+
+static int solve_many(Ctx* c, int n, const ddml_solve_desc* d, const ddml_solver_params* params, int on_device,
+                      void* stream) {
+  check_params(params);
+  need(n >= 1 && d != nullptr, "no solves");
+  const size_t bytes = (size_t)d[0].nrhs * c->V * 12 * sizeof(double2);
+  for (int i = 0; i < n; ++i) {
+    need(d[i].src && d[i].sol && d[i].info, "NULL buffer in solve desc");
+    need(d[i].nrhs >= 1 && d[i].nrhs <= kMaxRhs, "nrhs must be in 1..12");
+    need(d[i].nrhs == d[0].nrhs, "all solves of a batch must have the same nrhs");
+    need(c->gauges.count(d[i].gauge_id) == 1, "unknown gauge id");
+    (void)domain_get(c, d[i].dom_id);
+  }
+  StreamJoin sj(c, stream);
+  std::vector<Staged> sin, sout;
+  std::vector<Solve> solves(n);
+  std::vector<Solve*> ptrs;
+  for (int i = 0; i < n; ++i) {
+    sin.push_back(stage_in(c, d[i].src, bytes, on_device));
+    sout.push_back(stage_out(c, d[i].sol, bytes, on_device));
+  }
+  for (int i = 0; i < n; ++i) {
+    Solve& s = solves[i];
+    s.gauge_id = d[i].gauge_id;
+    s.dom_id = d[i].dom_id;
+    s.nrhs = d[i].nrhs;
+    s.prec = params->prec;
+    s.prm = *params;
+    s.src = sin[i].cptr;
+    s.sol = sout[i].ptr;
+    s.info = d[i].info;
+    ptrs.push_back(&s);
+  }
+  run_solves(c, ptrs);
+  for (int i = 0; i < n; ++i) copy_back(c, d[i].sol, sout[i], bytes, on_device);
+  sj.done();
+  int rc = DDML_OK;
+  for (int i = 0; i < n && rc == DDML_OK; ++i)
+    for (int col = 0; col < d[i].nrhs; ++col)
+      if (d[i].info[col].status != DDML_OK) {
+        rc = d[i].info[col].status;
+        c->last_error = "a right-hand side did not reach the tolerance";
+        break;
+      }
+  return rc;
+}
+
+int ddml_solve_domain(ddml_ctx ctx, int gauge_id, int dom_id, const double* src, double* sol, int nrhs,
+                      const ddml_solver_params* params, ddml_rhs_info* info, int on_device, void* stream) {
+  return guarded(ctx, [&](Ctx* c) {
+    ddml_solve_desc d{gauge_id, dom_id, src, sol, nrhs, info};
+    return solve_many(c, 1, &d, params, on_device, stream);
+  });
+}
+
+int ddml_solve_batch(ddml_ctx ctx, int nsolves, const ddml_solve_desc* descs, const ddml_solver_params* params,
+                     int on_device, void* stream) {
+  return guarded(ctx, [&](Ctx* c) { return solve_many(c, nsolves, descs, params, on_device, stream); });
+}
+
+static int series_many(Ctx* c, int ns, const ddml_series_desc* sd, int nrhs, const ddml_solver_params* params,
+                       int on_device, void* stream) {
+  need(ns >= 1 && sd != nullptr, "no series");
+  need(nrhs >= 1 && nrhs <= kMaxRhs, "nrhs must be in 1..12");
+  check_params(params);
+  const size_t per = (size_t)nrhs * c->V * 12;
+  const size_t bytes = per * sizeof(double2);
+  StreamJoin sj(c, stream);
+  std::vector<Staged> si, st, ss;
+  std::vector<ddml_solve_desc> d;
+  for (int k = 0; k < ns; ++k) {
+    need(sd[k].dom_ids && sd[k].nlevels >= 1 && sd[k].src && sd[k].terms && sd[k].info, "bad series desc");
+    si.push_back(stage_in(c, sd[k].src, bytes, on_device));
+    st.push_back(stage_out(c, sd[k].terms, bytes * sd[k].nlevels, on_device));
+    ss.push_back(sd[k].sum ? stage_out(c, sd[k].sum, bytes, on_device) : Staged{});
+  }
+  for (int k = 0; k < ns; ++k)
+    for (int i = 0; i < sd[k].nlevels; ++i)
+      d.push_back(ddml_solve_desc{sd[k].gauge_id, sd[k].dom_ids[i], si[k].cptr, st[k].ptr + 2 * per * i, nrhs,
+                                  sd[k].info + (size_t)i * nrhs});
+  // the solves read and write device memory already staged
+  int rc = solve_many(c, (int)d.size(), d.data(), params, 1, c->stream);
+  for (int k = 0; k < ns; ++k) {
+    DDML_HIP(launch_series_diff(reinterpret_cast<double2*>(st[k].ptr), per, sd[k].nlevels,
+                                sd[k].sum ? reinterpret_cast<double2*>(ss[k].ptr) : nullptr, c->stream));
+    copy_back(c, sd[k].terms, st[k], bytes * sd[k].nlevels, on_device);
+    if (sd[k].sum) copy_back(c, sd[k].sum, ss[k], bytes, on_device);
+  }
+  DDML_HIP(hipStreamSynchronize(c->stream));
+  sj.done();
+  return rc;
+}
+
+int ddml_propagator_series(ddml_ctx ctx, int gauge_id, const int* dom_ids, int nlevels, const double* src, int nrhs,
+                           const ddml_solver_params* params, double* terms, double* sum, ddml_rhs_info* info,
+                           int on_device, void* stream) {
+  return guarded(ctx, [&](Ctx* c) {
+    ddml_series_desc d{gauge_id, dom_ids, nlevels, src, terms, sum, info};
+    return series_many(c, 1, &d, nrhs, params, on_device, stream);
+  });
+}
+
+int ddml_propagator_series_batch(ddml_ctx ctx, int nseries, const ddml_series_desc* descs, int nrhs,
+                                 const ddml_solver_params* params, int on_device, void* stream) {
+  return guarded(ctx, [&](Ctx* c) { return series_many(c, nseries, descs, nrhs, params, on_device, stream); });
+}
+
+int ddml_time_stencil(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec, int iters, double out[4]) {
+  return guarded(ctx, [&](Ctx* c) {
+    need(out != nullptr, "out is NULL");
+    need(prec == DDML_FP64 || prec == DDML_MIXED_FP32, "unknown precision");
+    time_stencil(c, gauge_id, dom_id, nrhs, prec, iters, out);
+    return DDML_OK;
+  });
+}
+
+int ddml_contract_pp_disconnected(ddml_ctx ctx, const double* terms_x, const double* terms_y, int nlevels,
+                                  const int xsrc[4], const int ysrc[4], double* out, int on_device, void* stream) {
+  return guarded(ctx, [&](Ctx* c) {
+    need(terms_x && terms_y && xsrc && ysrc && out && nlevels >= 1, "bad arguments");
+    const int* L = c->lat.dims;
+    for (int m = 0; m < 4; ++m) need(xsrc[m] >= 0 && xsrc[m] < L[m] && ysrc[m] >= 0 && ysrc[m] < L[m], "bad site");
+    need(nlevels <= 64, "nlevels <= 64");
+    const size_t bytes = (size_t)nlevels * 12 * c->V * 12 * sizeof(double2);
+    StreamJoin sj(c, stream);
+    Staged sx = stage_in(c, terms_x, bytes, on_device);
+    Staged sy = stage_in(c, terms_y, bytes, on_device);
+    DBuf o(c->pool.get(), (size_t)nlevels * 4 * sizeof(double2));
+    const size_t xs = (((size_t)xsrc[0] * L[1] + xsrc[1]) * L[2] + xsrc[2]) * L[3] + xsrc[3];
+    const size_t ys = (((size_t)ysrc[0] * L[1] + ysrc[1]) * L[2] + ysrc[2]) * L[3] + ysrc[3];
+    const double invL3 = 1.0 / ((double)L[1] * L[2] * L[3]);
+    DDML_HIP(launch_pp(reinterpret_cast<const double2*>(sx.cptr), reinterpret_cast<const double2*>(sy.cptr), c->V,
+                       nlevels, xs, ys, invL3, o.as<double2>(), c->stream));
+    DDML_HIP(hipMemcpyAsync(out, o.p, (size_t)nlevels * 4 * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
+    DDML_HIP(hipStreamSynchronize(c->stream));
+    sj.done();
+    return DDML_OK;
+  });
+}
+
+int ddml_contract_nucleon(ddml_ctx ctx, const double* terms, int nlevels, double* levels_out, double* diffs_out,
+                          int on_device, void* stream) {
+  return guarded(ctx, [&](Ctx* c) {
+    need(terms && levels_out && nlevels >= 1 && nlevels <= 64, "bad arguments");
+    const int T = c->lat.dims[0];
+    const size_t bytes = (size_t)nlevels * 12 * c->V * 12 * sizeof(double2);
+    StreamJoin sj(c, stream);
+    Staged st = stage_in(c, terms, bytes, on_device);
+    DBuf W(c->pool.get(), (size_t)nlevels * c->V * sizeof(double2));
+    DBuf o(c->pool.get(), (size_t)nlevels * T * sizeof(double2));
+    DBuf d(c->pool.get(), (size_t)nlevels * T * sizeof(double2));
+    DDML_HIP(launch_nucleon(reinterpret_cast<const double2*>(st.cptr), c->V, T, nlevels, W.as<double2>(),
+                            o.as<double2>(), c->stream));
+    DDML_HIP(hipMemcpyAsync(d.p, o.p, (size_t)nlevels * T * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
+    DDML_HIP(launch_series_diff(d.as<double2>(), (size_t)T, nlevels, nullptr, c->stream));
+    DDML_HIP(hipMemcpyAsync(levels_out, o.p, (size_t)nlevels * T * sizeof(double2), hipMemcpyDeviceToHost,
+                            c->stream));
+    if (diffs_out)
+      DDML_HIP(hipMemcpyAsync(diffs_out, d.p, (size_t)nlevels * T * sizeof(double2), hipMemcpyDeviceToHost,
+                              c->stream));
+    DDML_HIP(hipStreamSynchronize(c->stream));
+    sj.done();
+    return DDML_OK;
+  });
+}
+
+int ddml_server_start(ddml_ctx ctx, const ddml_solver_params* params, int max_queue) {
+  return guarded(ctx, [&](Ctx* c) {
+    check_params(params);
+    need(max_queue >= 1, "max_queue >= 1");
+    need(!c->server, "server already running");
+    c->server.reset(new Server(c, *params, max_queue));
+    return DDML_OK;
+  });
+}
+
+int ddml_submit(ddml_ctx ctx, const ddml_request* req, uint64_t* ticket) {
+  if (!ctx || !req || !ticket || !ctx->c.server) return DDML_EINVAL;
+  if (req->nrhs < 1 || req->nrhs > kMaxRhs || !req->src || !req->sol) return DDML_EINVAL;
+  return ctx->c.server->submit(*req, ticket);
+}
+
+int ddml_poll(ddml_ctx ctx, uint64_t ticket, ddml_result* res) {
+  if (!ctx || !ctx->c.server) return DDML_EINVAL;
+  return ctx->c.server->poll(ticket, res);
+}
+
+int ddml_wait(ddml_ctx ctx, uint64_t ticket, ddml_result* res, double timeout_s) {
+  if (!ctx || !ctx->c.server) return DDML_EINVAL;
+  return ctx->c.server->wait(ticket, res, timeout_s);
+}
+
+int ddml_stats(ddml_ctx ctx, ddml_server_stats* stats) {
+  if (!ctx || !stats || !ctx->c.server) return DDML_EINVAL;
+  ctx->c.server->stats(stats);
+  return DDML_OK;
+}
+
+int ddml_server_stop(ddml_ctx ctx) {
+  if (!ctx || !ctx->c.server) return DDML_EINVAL;
+  ctx->c.server.reset();
+  return DDML_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,350 @@
+// Krylov vector kernels and FP64 reductions for the batched BiCGstab.
+//
+// BiCGstab (van der Vorst 1992) on the even-odd Schur operator, one
+// independent recursion per right-hand side.  Every kernel walks a slot table
+// (one entry per domain solve in flight) with a grid-stride loop over virtual
+// 64-site tiles; a workgroup is 64 sites x nrhs columns, one wavefront per
+// column, so every reduction is a wavefront reduction written to a fixed
+// partial slot and the final sums are taken in a fixed order: results do not
+// depend on how many solves share the launch.
+#include "ddml_common.hpp"
+#include "launchers.hpp"
+
+namespace ddml {
+
+__device__ __forceinline__ double2 wsum(double2 v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off, 64);
+    v.y += __shfl_xor(v.y, off, 64);
+  }
+  return v;
+}
+
+__device__ __forceinline__ int find_slot_v(const int* __restrict__ start, int n, int vt) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (start[mid] <= vt) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+template <typename T2, int OP>
+__global__ void __launch_bounds__(768) k_vec(const SlotDesc<T2>* __restrict__ slots, const int* __restrict__ tile_start,
+                                             const int* __restrict__ nslots_p) {
+  using T = decltype(T2::x);
+  const int ns = *nslots_p;
+  const int total = tile_start[ns];
+  const int lane = threadIdx.x & 63;
+  const int col = threadIdx.x >> 6;
+  for (int vt = blockIdx.x; vt < total; vt += gridDim.x) {
+    const int s = find_slot_v(tile_start, ns, vt);
+    const SlotDesc<T2>& d = slots[s];
+    if (col >= d.nrhs) continue;
+    if (OP != VEC_INIT && !d.active[col]) continue;  // uniform per wave
+    const int tile = vt - tile_start[s];
+    const int i = tile * kTile + lane;
+    const bool valid = i < d.g.Vh;
+    const size_t Vh = (size_t)d.g.Vh;
+    const size_t base = (size_t)col * 12 * Vh + i;
+    const BiState& st = d.st[col];
+    double2 s0 = make_double2(0, 0), s1 = make_double2(0, 0);
+    if (OP == VEC_P) {
+      if (valid) {
+        const T2 be = mk<T2>((T)st.beta.x, (T)st.beta.y), om = mk<T2>((T)st.omega.x, (T)st.omega.y);
+        T2* p = d.f[F_P];
+        const T2* r = d.f[F_R];
+        const T2* v = d.f[F_V];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          const size_t k = base + c * Vh;
+          p[k] = cadd(r[k], cmul(be, csub(p[k], cmul(om, v[k]))));
+        }
+      }
+    } else if (OP == VEC_S) {
+      if (valid) {
+        const T2 al = mk<T2>((T)st.alpha.x, (T)st.alpha.y);
+        T2* sv = d.f[F_S];
+        const T2* r = d.f[F_R];
+        const T2* v = d.f[F_V];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          const size_t k = base + c * Vh;
+          sv[k] = csub(r[k], cmul(al, v[k]));
+        }
+      }
+    } else if (OP == VEC_XR) {
+      if (valid) {
+        const T2 al = mk<T2>((T)st.alpha.x, (T)st.alpha.y), om = mk<T2>((T)st.omega.x, (T)st.omega.y);
+        T2* x = d.f[F_X];
+        T2* r = d.f[F_R];
+        const T2* p = d.f[F_P];
+        const T2* sv = d.f[F_S];
+        const T2* t = d.f[F_T];
+        const T2* rh = d.f[F_RH];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          const size_t k = base + c * Vh;
+          const T2 sk = sv[k];
+          x[k] = cadd(x[k], cadd(cmul(al, p[k]), cmul(om, sk)));
+          const T2 rn = csub(sk, cmul(om, t[k]));
+          r[k] = rn;
+          const T2 a = rh[k];
+          s0.x += (double)a.x * rn.x + (double)a.y * rn.y;
+          s0.y += (double)a.x * rn.y - (double)a.y * rn.x;
+          s1.x += (double)rn.x * rn.x + (double)rn.y * rn.y;
+        }
+      }
+    } else {  // VEC_INIT: r = rh = (T) src64, x = p = v = 0
+      if (valid) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          const size_t k = base + c * Vh;
+          const double2 b = d.src64[k];
+          const T2 bt = mk<T2>((T)b.x, (T)b.y);
+          d.f[F_R][k] = bt;
+          d.f[F_RH][k] = bt;
+          d.f[F_X][k] = mk<T2>(0, 0);
+          d.f[F_P][k] = mk<T2>(0, 0);
+          d.f[F_V][k] = mk<T2>(0, 0);
+          const double n2 = (double)bt.x * bt.x + (double)bt.y * bt.y;
+          s0.x += n2;
+          s1.x += n2;
+        }
+      }
+    }
+    if (OP == VEC_XR || OP == VEC_INIT) {
+      s0 = wsum(s0);
+      s1 = wsum(s1);
+      if (lane == 0) {
+        d.partial[(size_t)col * d.ntiles + tile] = s0;
+        d.partial[((size_t)d.nrhs + col) * d.ntiles + tile] = s1;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+  const double den = b.x * b.x + b.y * b.y;
+  return make_double2((a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den);
+}
+__device__ __forceinline__ double2 cmuld(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ bool finite2(double2 a) { return isfinite(a.x) && isfinite(a.y); }
+
+// One workgroup per slot, one wavefront per column: sum the tile partials in a
+// fixed order, then update that column's BiCGstab scalars.
+template <typename T2, int OP>
+__global__ void __launch_bounds__(768) k_fin(const SlotDesc<T2>* __restrict__ slots, const int* __restrict__ nslots_p) {
+  const int s = blockIdx.x;
+  if (s >= *nslots_p) return;
+  const SlotDesc<T2>& d = slots[s];
+  const int lane = threadIdx.x & 63;
+  const int col = threadIdx.x >> 6;
+  if (col >= d.nrhs) return;
+  BiState& st = d.st[col];
+  if (OP != FIN_INIT && !d.active[col]) return;
+  double2 a = make_double2(0, 0), b = make_double2(0, 0);
+  const double2* p0 = d.partial + (size_t)col * d.ntiles;
+  const double2* p1 = d.partial + ((size_t)d.nrhs + col) * d.ntiles;
+  for (int t = lane; t < d.ntiles; t += 64) {
+    const double2 u = p0[t];
+    a.x += u.x; a.y += u.y;
+    if (OP != FIN_ALPHA) {
+      const double2 w = p1[t];
+      b.x += w.x; b.y += w.y;
+    }
+  }
+  a = wsum(a);
+  b = wsum(b);
+  if (lane != 0) return;
+  if (OP == FIN_INIT) {
+    // a = (rh, r) = |r|^2, b = |r|^2 ; st.active holds the request flag
+    const int want = d.active[col];
+    st.rr = b.x;
+    st.rr0 = b.x;
+    st.rho = make_double2(b.x, 0);
+    st.alpha = make_double2(1, 0);
+    st.omega = make_double2(1, 0);
+    st.beta = st.rho;  // (rho/1)(1/1): p = r on the first iteration
+    st.iters = 0;
+    st.status = 0;
+    const int on = want && b.x > 0 && isfinite(b.x);
+    if (want && !isfinite(b.x)) st.status = 3;
+    d.active[col] = on;
+    st.active = on;
+  } else if (OP == FIN_ALPHA) {
+    if (!finite2(a) || (a.x == 0 && a.y == 0)) {
+      st.status = 1;
+      st.active = 0;
+      d.active[col] = 0;
+      st.alpha = make_double2(0, 0);
+      return;
+    }
+    st.alpha = cdiv(st.rho, a);
+  } else if (OP == FIN_OMEGA) {
+    if (b.x > 0 && isfinite(b.x) && finite2(a)) st.omega = make_double2(a.x / b.x, a.y / b.x);
+    else st.omega = make_double2(0, 0);
+  } else {  // FIN_RHO: a = (rh, r), b = |r|^2
+    st.iters += 1;
+    st.rr = b.x;
+    const bool conv = b.x <= st.tol2 * st.rr0;
+    int on = 1;
+    if (!isfinite(b.x) || !finite2(a)) { st.status = 3; on = 0; }
+    else if (conv) { st.status = 0; on = 0; }
+    else if (st.iters >= st.max_iters) { st.status = 2; on = 0; }
+    else if ((a.x == 0 && a.y == 0) || (st.omega.x == 0 && st.omega.y == 0)) { st.status = 1; on = 0; }
+    if (on) {
+      st.beta = cmuld(cdiv(a, st.rho), cdiv(st.alpha, st.omega));
+      st.rho = a;
+    }
+    st.active = on;
+    d.active[col] = on;
+  }
+}
+
+template <typename T2>
+static hipError_t vec_impl(const SlotDesc<T2>* slots, const int* tile_start, const int* nslots_p, int nrhs, int op,
+                           int grid, hipStream_t st) {
+  dim3 b(64 * nrhs);
+  switch (op) {
+    case VEC_P: hipLaunchKernelGGL((k_vec<T2, VEC_P>), dim3(grid), b, 0, st, slots, tile_start, nslots_p); break;
+    case VEC_S: hipLaunchKernelGGL((k_vec<T2, VEC_S>), dim3(grid), b, 0, st, slots, tile_start, nslots_p); break;
+    case VEC_XR: hipLaunchKernelGGL((k_vec<T2, VEC_XR>), dim3(grid), b, 0, st, slots, tile_start, nslots_p); break;
+    case VEC_INIT: hipLaunchKernelGGL((k_vec<T2, VEC_INIT>), dim3(grid), b, 0, st, slots, tile_start, nslots_p); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+hipError_t launch_vec(const SlotDesc<float2>* slots, const int* tile_start, const int* nslots_p, int nrhs, int op,
+                      int grid, hipStream_t st) {
+  return vec_impl(slots, tile_start, nslots_p, nrhs, op, grid, st);
+}
+hipError_t launch_vec(const SlotDesc<double2>* slots, const int* tile_start, const int* nslots_p, int nrhs, int op,
+                      int grid, hipStream_t st) {
+  return vec_impl(slots, tile_start, nslots_p, nrhs, op, grid, st);
+}
+
+template <typename T2>
+static hipError_t fin_impl(const SlotDesc<T2>* slots, const int* nslots_p, int max_slots, int op, hipStream_t st) {
+  dim3 b(64 * kMaxRhs);
+  switch (op) {
+    case FIN_INIT: hipLaunchKernelGGL((k_fin<T2, FIN_INIT>), dim3(max_slots), b, 0, st, slots, nslots_p); break;
+    case FIN_ALPHA: hipLaunchKernelGGL((k_fin<T2, FIN_ALPHA>), dim3(max_slots), b, 0, st, slots, nslots_p); break;
+    case FIN_OMEGA: hipLaunchKernelGGL((k_fin<T2, FIN_OMEGA>), dim3(max_slots), b, 0, st, slots, nslots_p); break;
+    case FIN_RHO: hipLaunchKernelGGL((k_fin<T2, FIN_RHO>), dim3(max_slots), b, 0, st, slots, nslots_p); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+hipError_t launch_fin(const SlotDesc<float2>* slots, const int* nslots_p, int max_slots, int op, hipStream_t st) {
+  return fin_impl(slots, nslots_p, max_slots, op, st);
+}
+hipError_t launch_fin(const SlotDesc<double2>* slots, const int* nslots_p, int max_slots, int op, hipStream_t st) {
+  return fin_impl(slots, nslots_p, max_slots, op, st);
+}
+
+// ------------------------------------------------------- raw elementwise
+template <typename Tin>
+__global__ void k_cast_d(const Tin* __restrict__ in, double2* __restrict__ out, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    out[i] = make_double2((double)in[i].x, (double)in[i].y);
+}
+__global__ void k_axpy_d(double2* __restrict__ y, const double2* __restrict__ x, double a, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    y[i].x += a * x[i].x;
+    y[i].y += a * x[i].y;
+  }
+}
+static int grid_n(size_t n) {
+  size_t g = (n + 255) / 256;
+  return (int)(g > 16384 ? 16384 : (g == 0 ? 1 : g));
+}
+hipError_t launch_cast_to_d(const float2* in, double2* out, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL((k_cast_d<float2>), dim3(grid_n(n)), dim3(256), 0, st, in, out, n);
+  return hipGetLastError();
+}
+hipError_t launch_cast_to_d(const double2* in, double2* out, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL((k_cast_d<double2>), dim3(grid_n(n)), dim3(256), 0, st, in, out, n);
+  return hipGetLastError();
+}
+__global__ void k_cast_f(const double2* __restrict__ in, float2* __restrict__ out, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    out[i] = make_float2((float)in[i].x, (float)in[i].y);
+}
+hipError_t launch_cast_to_f(const double2* in, float2* out, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_cast_f, dim3(grid_n(n)), dim3(256), 0, st, in, out, n);
+  return hipGetLastError();
+}
+template <typename T2>
+__global__ void k_fill(T2* __restrict__ v, size_t n, double a) {
+  using T = decltype(T2::x);
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    v[i] = mk<T2>((T)(a * (1.0 + 1e-3 * (double)(i % 97))), (T)(0.5 * a));
+}
+hipError_t launch_fill(float2* v, size_t n, double a, hipStream_t st) {
+  hipLaunchKernelGGL((k_fill<float2>), dim3(grid_n(n)), dim3(256), 0, st, v, n, a);
+  return hipGetLastError();
+}
+hipError_t launch_fill(double2* v, size_t n, double a, hipStream_t st) {
+  hipLaunchKernelGGL((k_fill<double2>), dim3(grid_n(n)), dim3(256), 0, st, v, n, a);
+  return hipGetLastError();
+}
+hipError_t launch_axpy_d(double2* y, const double2* x, double a, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy_d, dim3(grid_n(n)), dim3(256), 0, st, y, x, a, n);
+  return hipGetLastError();
+}
+
+// |v_col|^2 per 64-site tile into partial[col][tile]
+__global__ void k_col_norms(const double2* __restrict__ v, int Vh, int nrhs, double2* __restrict__ partial, int ntiles) {
+  const int lane = threadIdx.x & 63;
+  const int col = threadIdx.x >> 6;
+  if (col >= nrhs) return;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int i = tile * kTile + lane;
+    double2 s = make_double2(0, 0);
+    if (i < Vh) {
+      for (int c = 0; c < 12; ++c) {
+        const double2 a = v[((size_t)col * 12 + c) * Vh + i];
+        s.x += a.x * a.x + a.y * a.y;
+      }
+    }
+    s = wsum(s);
+    if (lane == 0) partial[(size_t)col * ntiles + tile] = s;
+  }
+}
+__global__ void k_sum_partials(const double2* __restrict__ partial, int nred, int nrhs, int ntiles,
+                               double2* __restrict__ out, int accumulate) {
+  const int lane = threadIdx.x & 63;
+  const int k = blockIdx.x;  // (red, col)
+  if (k >= nred * nrhs) return;
+  const double2* p = partial + (size_t)k * ntiles;
+  double2 a = make_double2(0, 0);
+  for (int t = lane; t < ntiles; t += 64) {
+    a.x += p[t].x;
+    a.y += p[t].y;
+  }
+  a = wsum(a);
+  if (lane == 0) {
+    if (accumulate) { out[k].x += a.x; out[k].y += a.y; }
+    else out[k] = a;
+  }
+}
+hipError_t launch_col_norms(const double2* v, int Vh, int nrhs, double2* partial, int ntiles, double2* out,
+                            int accumulate, hipStream_t st) {
+  int grid = ntiles < 16384 ? ntiles : 16384;
+  hipLaunchKernelGGL(k_col_norms, dim3(grid), dim3(64 * nrhs), 0, st, v, Vh, nrhs, partial, ntiles);
+  hipLaunchKernelGGL(k_sum_partials, dim3(nrhs), dim3(64), 0, st, partial, 1, nrhs, ntiles,
+                     out, accumulate);
+  return hipGetLastError();
+}
+hipError_t launch_sum_partials(const double2* partial, int nred, int nrhs, int ntiles, double2* out, int accumulate,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_partials, dim3(nred * nrhs), dim3(64), 0, st, partial, nred, nrhs, ntiles, out,
+                     accumulate);
+  return hipGetLastError();
+}
+
+}  // namespace ddml

@@ -1,0 +1,444 @@
+// Even-odd Wilson-clover stencil kernels on domain-local boxes (gfx950).
+//
+// The hopping term H = D_hop of Section 6 (from the covariant differences of
+// Appendix A):
+//   (H psi)(x) = sum_mu [ (1 - g_mu) U_mu(x) psi(x+mu) + (1 + g_mu) U_mu(x-mu)^dag psi(x-mu) ].
+// In the chiral basis g_mu = [[0, e_mu], [e_mu^dag, 0]] (e_0 = -1, e_k = -i s_k),
+// so (1 -+ g_mu) psi = [h ; -+ e_mu^dag h] with the half spinor h = psi_u -+ e_mu psi_l.
+// Only h (2 spins x 3 colours) is multiplied by the link, then the lower two
+// spins are rebuilt; that halves the SU(3) work.
+//
+// One thread owns one site of the output parity and R right-hand sides; a
+// workgroup is 64 consecutive sites (one wavefront per group of R columns), so
+// the waves of one workgroup read the same links and clover data and hit in
+// L1/L2 instead of HBM.  Domain restriction comes from zeroed face links, so
+// the inner loop has no masking branch.
+#include "ddml_common.hpp"
+#include "launchers.hpp"
+
+namespace ddml {
+
+// ---------------------------------------------------------------- spin maths
+template <typename T2>
+__device__ __forceinline__ void project(int mu, bool fwd, const T2 psi[12], T2 h[6]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const T2 p0 = psi[c], p1 = psi[3 + c], p2 = psi[6 + c], p3 = psi[9 + c];
+    T2 h0, h1;
+    switch (mu) {
+      case 0:
+        h0 = fwd ? cadd(p0, p2) : csub(p0, p2);
+        h1 = fwd ? cadd(p1, p3) : csub(p1, p3);
+        break;
+      case 1:
+        h0 = fwd ? cadd(p0, ci(p3)) : csub(p0, ci(p3));
+        h1 = fwd ? cadd(p1, ci(p2)) : csub(p1, ci(p2));
+        break;
+      case 2:
+        h0 = fwd ? cadd(p0, p3) : csub(p0, p3);
+        h1 = fwd ? csub(p1, p2) : cadd(p1, p2);
+        break;
+      default:
+        h0 = fwd ? cadd(p0, ci(p2)) : csub(p0, ci(p2));
+        h1 = fwd ? csub(p1, ci(p3)) : cadd(p1, ci(p3));
+        break;
+    }
+    h[c] = h0;
+    h[3 + c] = h1;
+  }
+}
+
+template <typename T2>
+__device__ __forceinline__ void reconstruct(int mu, bool fwd, const T2 g[6], T2 acc[12]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const T2 g0 = g[c], g1 = g[3 + c];
+    acc[c] = cadd(acc[c], g0);
+    acc[3 + c] = cadd(acc[3 + c], g1);
+    switch (mu) {
+      case 0:
+        acc[6 + c] = fwd ? cadd(acc[6 + c], g0) : csub(acc[6 + c], g0);
+        acc[9 + c] = fwd ? cadd(acc[9 + c], g1) : csub(acc[9 + c], g1);
+        break;
+      case 1:
+        acc[6 + c] = fwd ? cadd(acc[6 + c], cmi(g1)) : cadd(acc[6 + c], ci(g1));
+        acc[9 + c] = fwd ? cadd(acc[9 + c], cmi(g0)) : cadd(acc[9 + c], ci(g0));
+        break;
+      case 2:
+        acc[6 + c] = fwd ? csub(acc[6 + c], g1) : cadd(acc[6 + c], g1);
+        acc[9 + c] = fwd ? cadd(acc[9 + c], g0) : csub(acc[9 + c], g0);
+        break;
+      default:
+        acc[6 + c] = fwd ? cadd(acc[6 + c], cmi(g0)) : cadd(acc[6 + c], ci(g0));
+        acc[9 + c] = fwd ? cadd(acc[9 + c], ci(g1)) : cadd(acc[9 + c], cmi(g1));
+        break;
+    }
+  }
+}
+
+// g = U h (dag=false) or U^dag h (dag=true), per spin of the half spinor
+template <typename T2>
+__device__ __forceinline__ void su3_mul(const T2 u[9], bool dag, const T2 h[6], T2 g[6]) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      T2 acc;
+      if (!dag) {
+        acc = cmul(u[3 * a], h[3 * s]);
+        acc = cadd(acc, cmul(u[3 * a + 1], h[3 * s + 1]));
+        acc = cadd(acc, cmul(u[3 * a + 2], h[3 * s + 2]));
+      } else {
+        acc = cmulc(u[a], h[3 * s]);
+        acc = cadd(acc, cmulc(u[3 + a], h[3 * s + 1]));
+        acc = cadd(acc, cmulc(u[6 + a], h[3 * s + 2]));
+      }
+      g[3 * s + a] = acc;
+    }
+}
+
+// y = C x for one 6x6 Hermitian block stored in 18 slots (stride Vh)
+template <typename T2>
+__device__ __forceinline__ void herm6_load(const T2* __restrict__ base, size_t Vh, int i, T2 m[18]) {
+#pragma unroll
+  for (int k = 0; k < 18; ++k) m[k] = base[k * Vh + i];
+}
+template <typename T2>
+__device__ __forceinline__ void herm6_apply(const T2 m[18], const T2 x[6], T2 y[6]) {
+  using T = decltype(T2::x);
+  T d[6] = {m[0].x, m[0].y, m[1].x, m[1].y, m[2].x, m[2].y};
+#pragma unroll
+  for (int i = 0; i < 6; ++i) y[i] = cscale(x[i], d[i]);
+  int k = 3;
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = i + 1; j < 6; ++j) {
+      const T2 h = m[k++];
+      y[i] = cadd(y[i], cmul(h, x[j]));
+      y[j] = cadd(y[j], cmulc(h, x[i]));
+    }
+}
+
+// ------------------------------------------------------------ the stencil core
+template <typename T2, int R>
+__device__ __forceinline__ void hop_sum(const BoxGeom& g, int p, int i, const T2* __restrict__ U,
+                                        const T2* __restrict__ in, int r0, int nr, const int* __restrict__ act,
+                                        T2 acc[R][12]) {
+  int y[4];
+  eo_coords(g, p, i, y);
+  const int q = 1 - p;
+  const size_t Vh = (size_t)g.Vh;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[r][c] = mk<T2>(0, 0);
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+#pragma unroll
+    for (int dir = 0; dir < 2; ++dir) {
+      const bool fwd = dir == 0;
+      int z[4] = {y[0], y[1], y[2], y[3]};
+      if (fwd) z[mu] = (y[mu] + 1 == g.L[mu]) ? 0 : y[mu] + 1;
+      else z[mu] = (y[mu] == 0) ? g.L[mu] - 1 : y[mu] - 1;
+      const int n = eo_index(g, z);
+      const T2* __restrict__ ul = fwd ? U + ((size_t)(p * 4 + mu) * 9) * Vh + i
+                                      : U + ((size_t)(q * 4 + mu) * 9) * Vh + n;
+      T2 u[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) u[k] = ul[k * Vh];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (r < nr && (act == nullptr || act[r0 + r])) {
+          const T2* __restrict__ src = in + (size_t)(r0 + r) * 12 * Vh + n;
+          T2 psi[12], h[6], gg[6];
+#pragma unroll
+          for (int c = 0; c < 12; ++c) psi[c] = src[c * Vh];
+          project(mu, fwd, psi, h);
+          su3_mul(u, !fwd, h, gg);
+          reconstruct(mu, fwd, gg, acc[r]);
+        }
+      }
+    }
+  }
+}
+
+template <typename T2>
+__device__ __forceinline__ double2 wave_sum(double2 v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off, 64);
+    v.y += __shfl_xor(v.y, off, 64);
+  }
+  return v;
+}
+
+// Epilogue on one column.  acc = (H in)(x).
+template <typename T2, int MODE>
+__device__ __forceinline__ void epilogue(const T2* __restrict__ cl, size_t Vh, int i, const T2 acc[12],
+                                         const T2 aux[12], const T2 ra[12], double c1, double c2, T2 out[12]) {
+  using T = decltype(T2::x);
+  const T k1 = (T)c1, k2 = (T)c2;
+  if (MODE == MODE_CINV_HOP) {
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      T2 m[18];
+      herm6_load(cl + (size_t)b * 18 * Vh, Vh, i, m);
+      herm6_apply(m, acc + 6 * b, out + 6 * b);
+    }
+  } else if (MODE == MODE_SCHUR) {
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      T2 m[18], y[6];
+      herm6_load(cl + (size_t)b * 18 * Vh, Vh, i, m);
+      herm6_apply(m, acc + 6 * b, y);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) out[6 * b + c] = csub(aux[6 * b + c], cscale(y[c], k1));
+    }
+  } else if (MODE == MODE_M || MODE == MODE_RES) {
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      T2 m[18], y[6];
+      herm6_load(cl + (size_t)b * 18 * Vh, Vh, i, m);
+      herm6_apply(m, aux + 6 * b, y);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        T2 v = csub(y[c], cscale(acc[6 * b + c], k1));
+        out[6 * b + c] = (MODE == MODE_M) ? cscale(v, k2) : csub(ra[6 * b + c], v);
+      }
+    }
+  } else {  // MODE_PREP: out = C (aux + c1 acc)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      T2 m[18], v[6];
+      herm6_load(cl + (size_t)b * 18 * Vh, Vh, i, m);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) v[c] = cadd(aux[6 * b + c], cscale(acc[6 * b + c], k1));
+      herm6_apply(m, v, out + 6 * b);
+    }
+  }
+}
+
+template <typename T2, int R, int MODE, int RED>
+__device__ __forceinline__ void hop_tile(const BoxGeom g, const T2* __restrict__ U, const T2* __restrict__ clov,
+                                         const T2* __restrict__ in, const T2* __restrict__ aux,
+                                         const T2* __restrict__ red_a, T2* __restrict__ out,
+                                         double2* __restrict__ partial, const int* __restrict__ act, int p,
+                                         int nrhs, int ntiles, double c1, double c2, int tile) {
+  const int lane = threadIdx.x & 63;
+  const int grp = threadIdx.x >> 6;
+  const int r0 = grp * R;
+  if (r0 >= nrhs) return;  // whole wave idle (uniform)
+  const int nr = min(R, nrhs - r0);
+  const int i = tile * kTile + lane;
+  const bool valid = i < g.Vh;
+  const size_t Vh = (size_t)g.Vh;
+  const T2* __restrict__ cl = clov + (size_t)p * 36 * Vh;
+  T2 acc[R][12];
+  if (valid) hop_sum<T2, R>(g, p, i, U, in, r0, nr, act, acc);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (r >= nr) break;
+    const int col = r0 + r;
+    const bool on = (act == nullptr || act[col]);
+    if (!on) continue;  // uniform across the wave
+    double2 s0 = make_double2(0, 0), s1 = make_double2(0, 0);
+    if (valid) {
+      T2 av[12], ra[12], o[12];
+      const size_t base = (size_t)col * 12 * Vh + i;
+      if (MODE != MODE_CINV_HOP) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) av[c] = aux[base + c * Vh];
+      }
+      if (MODE == MODE_RES || RED == RED_DOT) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) ra[c] = red_a[base + c * Vh];
+      }
+      epilogue<T2, MODE>(cl, Vh, i, acc[r], av, ra, c1, c2, o);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) out[base + c * Vh] = o[c];
+      if (RED == RED_DOT) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          s0.x += (double)ra[c].x * o[c].x + (double)ra[c].y * o[c].y;
+          s0.y += (double)ra[c].x * o[c].y - (double)ra[c].y * o[c].x;
+        }
+      } else if (RED == RED_TS) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          s0.x += (double)o[c].x * av[c].x + (double)o[c].y * av[c].y;
+          s0.y += (double)o[c].x * av[c].y - (double)o[c].y * av[c].x;
+          s1.x += (double)o[c].x * o[c].x + (double)o[c].y * o[c].y;
+        }
+      } else if (RED == RED_NORM) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) s0.x += (double)o[c].x * o[c].x + (double)o[c].y * o[c].y;
+      }
+    }
+    if (RED != RED_NONE) {
+      s0 = wave_sum<T2>(s0);
+      if (RED == RED_TS) s1 = wave_sum<T2>(s1);
+      if (lane == 0) {
+        partial[(size_t)col * ntiles + tile] = s0;
+        if (RED == RED_TS) partial[((size_t)nrhs + col) * ntiles + tile] = s1;
+      }
+    }
+  }
+}
+
+// Single-item launch (operator application, outer FP64 steps).
+template <typename T2, int R, int MODE, int RED>
+__global__ void __launch_bounds__(64 * ((kMaxRhs + R - 1) / R)) k_hop_item(HopItem<T2> it) {
+  for (int tile = blockIdx.x; tile < it.ntiles; tile += gridDim.x)
+    hop_tile<T2, R, MODE, RED>(it.g, it.U, it.clov, it.in, it.aux, it.red_a, it.out, it.partial, it.active,
+                               it.par_out, it.nrhs, it.ntiles, it.c1, it.c2, tile);
+}
+
+// Batched launch over solver slots: the virtual tile vt of the whole batch is
+// mapped to (slot, tile) through the prefix table tile_start[nslots+1].
+__device__ __forceinline__ int find_slot(const int* __restrict__ start, int n, int vt) {
+  int lo = 0, hi = n;  // start[lo] <= vt < start[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (start[mid] <= vt) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+template <typename T2, int R, int MODE, int RED>
+__global__ void __launch_bounds__(64 * ((kMaxRhs + R - 1) / R)) k_hop_batch(const SlotDesc<T2>* __restrict__ slots,
+                                                   const int* __restrict__ tile_start,
+                                                   const int* __restrict__ nslots_p, int fin, int faux, int fout,
+                                                   int fred, int par_out) {
+  const int ns = *nslots_p;
+  const int total = tile_start[ns];
+  for (int vt = blockIdx.x; vt < total; vt += gridDim.x) {
+    const int s = find_slot(tile_start, ns, vt);
+    const SlotDesc<T2>& d = slots[s];
+    const int tile = vt - tile_start[s];
+    const T2* clov = d.Ainv;
+    double c1 = d.kappa * d.kappa;
+    hop_tile<T2, R, MODE, RED>(d.g, d.U, clov, d.f[fin], faux >= 0 ? d.f[faux] : nullptr,
+                               fred >= 0 ? d.f[fred] : nullptr, d.f[fout], d.partial, d.active, par_out, d.nrhs,
+                               d.ntiles, c1, 0.0, tile);
+  }
+}
+
+// Site-local clover application out = C in (parity p data of a [2][36][Vh] array).
+template <typename T2>
+__global__ void k_clover_apply(BoxGeom g, const T2* __restrict__ clov, int p, const T2* __restrict__ in,
+                               T2* __restrict__ out, int nrhs) {
+  const size_t Vh = (size_t)g.Vh;
+  const size_t n = Vh * nrhs;
+  const T2* cl = clov + (size_t)p * 36 * Vh;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(t % Vh);
+    const int col = (int)(t / Vh);
+    const size_t base = (size_t)col * 12 * Vh + i;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      T2 m[18], x[6], y[6];
+      herm6_load(cl + (size_t)b * 18 * Vh, Vh, i, m);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) x[c] = in[base + (6 * b + c) * Vh];
+      herm6_apply(m, x, y);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) out[base + (6 * b + c) * Vh] = y[c];
+    }
+  }
+}
+
+// --------------------------------------------------------------- launchers
+static int grid_for(int ntiles) { return ntiles < 65535 ? ntiles : 65535; }
+
+#define DDML_HOP_DISPATCH(T2, Rv, MODEv, REDv, ...)                                       \
+  if (R == Rv && mode == MODEv && red == REDv) {                                          \
+    hipLaunchKernelGGL((k_hop_item<T2, Rv, MODEv, REDv>), dim3(grid), dim3(block), 0, st, __VA_ARGS__); \
+    return hipGetLastError();                                                             \
+  }
+
+template <typename T2>
+static hipError_t hop_item_impl(const HopItem<T2>& it, int mode, int red, int R, hipStream_t st) {
+  const int groups = (it.nrhs + R - 1) / R;
+  const int block = 64 * groups;
+  const int grid = grid_for(it.ntiles);
+  if (block > 768) return hipErrorInvalidValue;
+  DDML_HOP_DISPATCH(T2, 1, MODE_CINV_HOP, RED_NONE, it)
+  DDML_HOP_DISPATCH(T2, 1, MODE_SCHUR, RED_NONE, it)
+  DDML_HOP_DISPATCH(T2, 1, MODE_M, RED_NONE, it)
+  DDML_HOP_DISPATCH(T2, 1, MODE_PREP, RED_NONE, it)
+  DDML_HOP_DISPATCH(T2, 1, MODE_RES, RED_NORM, it)
+  DDML_HOP_DISPATCH(T2, 2, MODE_CINV_HOP, RED_NONE, it)
+  DDML_HOP_DISPATCH(T2, 2, MODE_SCHUR, RED_NONE, it)
+  DDML_HOP_DISPATCH(T2, 2, MODE_M, RED_NONE, it)
+  DDML_HOP_DISPATCH(T2, 2, MODE_PREP, RED_NONE, it)
+  DDML_HOP_DISPATCH(T2, 2, MODE_RES, RED_NORM, it)
+  DDML_HOP_DISPATCH(T2, 3, MODE_CINV_HOP, RED_NONE, it)
+  DDML_HOP_DISPATCH(T2, 3, MODE_SCHUR, RED_NONE, it)
+  DDML_HOP_DISPATCH(T2, 3, MODE_M, RED_NONE, it)
+  DDML_HOP_DISPATCH(T2, 3, MODE_PREP, RED_NONE, it)
+  DDML_HOP_DISPATCH(T2, 3, MODE_RES, RED_NORM, it)
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_hop_item(const HopItem<double2>& it, int mode, int red, int R, hipStream_t st) {
+  return hop_item_impl(it, mode, red, R, st);
+}
+hipError_t launch_hop_item(const HopItem<float2>& it, int mode, int red, int R, hipStream_t st) {
+  return hop_item_impl(it, mode, red, R, st);
+}
+
+#define DDML_HOPB_DISPATCH(T2, Rv, MODEv, REDv)                                                        \
+  if (R == Rv && mode == MODEv && red == REDv) {                                                       \
+    hipLaunchKernelGGL((k_hop_batch<T2, Rv, MODEv, REDv>), dim3(grid), dim3(block), 0, st, slots,      \
+                       tile_start, nslots_p, fin, faux, fout, fred, par_out);                          \
+    return hipGetLastError();                                                                          \
+  }
+
+template <typename T2>
+static hipError_t hop_batch_impl(const SlotDesc<T2>* slots, const int* tile_start, const int* nslots_p,
+                                 int nrhs, int R, int mode, int red, int fin, int faux, int fout, int fred,
+                                 int par_out, int grid, hipStream_t st) {
+  const int block = 64 * ((nrhs + R - 1) / R);
+  if (block > 768) return hipErrorInvalidValue;
+  DDML_HOPB_DISPATCH(T2, 1, MODE_CINV_HOP, RED_NONE)
+  DDML_HOPB_DISPATCH(T2, 1, MODE_SCHUR, RED_DOT)
+  DDML_HOPB_DISPATCH(T2, 1, MODE_SCHUR, RED_TS)
+  DDML_HOPB_DISPATCH(T2, 1, MODE_SCHUR, RED_NONE)
+  DDML_HOPB_DISPATCH(T2, 2, MODE_CINV_HOP, RED_NONE)
+  DDML_HOPB_DISPATCH(T2, 2, MODE_SCHUR, RED_DOT)
+  DDML_HOPB_DISPATCH(T2, 2, MODE_SCHUR, RED_TS)
+  DDML_HOPB_DISPATCH(T2, 2, MODE_SCHUR, RED_NONE)
+  DDML_HOPB_DISPATCH(T2, 3, MODE_CINV_HOP, RED_NONE)
+  DDML_HOPB_DISPATCH(T2, 3, MODE_SCHUR, RED_DOT)
+  DDML_HOPB_DISPATCH(T2, 3, MODE_SCHUR, RED_TS)
+  DDML_HOPB_DISPATCH(T2, 3, MODE_SCHUR, RED_NONE)
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_hop_batch(const SlotDesc<float2>* slots, const int* tile_start, const int* nslots_p, int nrhs,
+                            int R, int mode, int red, int fin, int faux, int fout, int fred, int par_out, int grid,
+                            hipStream_t st) {
+  return hop_batch_impl(slots, tile_start, nslots_p, nrhs, R, mode, red, fin, faux, fout, fred, par_out, grid, st);
+}
+hipError_t launch_hop_batch(const SlotDesc<double2>* slots, const int* tile_start, const int* nslots_p, int nrhs,
+                            int R, int mode, int red, int fin, int faux, int fout, int fred, int par_out, int grid,
+                            hipStream_t st) {
+  return hop_batch_impl(slots, tile_start, nslots_p, nrhs, R, mode, red, fin, faux, fout, fred, par_out, grid, st);
+}
+
+template <typename T2>
+static hipError_t clover_apply_impl(const BoxGeom& g, const T2* clov, int p, const T2* in, T2* out, int nrhs,
+                                    hipStream_t st) {
+  size_t n = (size_t)g.Vh * nrhs;
+  int grid = (int)((n + 255) / 256);
+  if (grid > 65535) grid = 65535;
+  hipLaunchKernelGGL((k_clover_apply<T2>), dim3(grid), dim3(256), 0, st, g, clov, p, in, out, nrhs);
+  return hipGetLastError();
+}
+hipError_t launch_clover_apply(const BoxGeom& g, const double2* clov, int p, const double2* in, double2* out,
+                               int nrhs, hipStream_t st) {
+  return clover_apply_impl(g, clov, p, in, out, nrhs, st);
+}
+
+}  // namespace ddml

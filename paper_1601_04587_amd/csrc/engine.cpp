@@ -1,0 +1,912 @@
+// Host engine: gauge versions, domains, operator blocks, the FP64
+// defect-correction loop and the batched inner BiCGstab.
+//
+// Solve of D_Gamma x = b (eq. diric) in hopping units, M = 2 kappa D = A - kappa H:
+//   b' = 2 kappa P_Gamma b, x = 0
+//   repeat (FP64 outer loop, defect correction):
+//     r = b' - M x  (FP64 stencil); stop when |r| <= tol |b'| per column
+//     rhat_e = A_ee^{-1} (r_e + kappa H_eo A_oo^{-1} r_o)                (FP64)
+//     solve (1 - kappa^2 A_ee^{-1} H_eo A_oo^{-1} H_oe) e_e = rhat_e       (inner, FP32 or FP64)
+//     e_o = A_oo^{-1} (r_o + kappa H_oe e_e);  x += e                     (FP64)
+// Many solves advance together: the inner iterations of every solve in the
+// batch are one replay of a captured HIP graph over a slot table, and solves
+// enter and leave the table between replays.
+#include "engine.hpp"
+#include "server.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace ddml {
+
+// ------------------------------------------------------------------ DevPool
+DevPool::~DevPool() { trim(); }
+
+void DevPool::trim() {
+  std::lock_guard<std::mutex> lk(mu_);
+  for (auto& kv : free_)
+    for (void* p : kv.second) {
+      (void)hipFree(p);
+      sizes_.erase(p);
+    }
+  free_.clear();
+  cached_ = 0;
+}
+
+void* DevPool::alloc(size_t bytes) {
+  const size_t r = round(bytes);
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = free_.find(r);
+    if (it != free_.end() && !it->second.empty()) {
+      void* p = it->second.back();
+      it->second.pop_back();
+      cached_ -= r;
+      in_use_ += r;
+      return p;
+    }
+    if (in_use_ + r > budget_)
+      throw Error{DDML_ENOMEM, "device memory budget exceeded (" + std::to_string(in_use_ + r) + " > " +
+                                   std::to_string(budget_) + " bytes)"};
+  }
+  if (in_use_ + cached_ + r > budget_) trim();
+  void* p = nullptr;
+  if (hipMalloc(&p, r) != hipSuccess) {
+    (void)hipGetLastError();
+    trim();
+    if (hipMalloc(&p, r) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error{DDML_ENOMEM, "hipMalloc of " + std::to_string(r) + " bytes failed"};
+    }
+  }
+  std::lock_guard<std::mutex> lk(mu_);
+  sizes_[p] = r;
+  in_use_ += r;
+  return p;
+}
+
+void DevPool::free(void* p) {
+  std::lock_guard<std::mutex> lk(mu_);
+  auto it = sizes_.find(p);
+  if (it == sizes_.end()) return;
+  free_[it->second].push_back(p);
+  in_use_ -= it->second;
+  cached_ += it->second;
+}
+
+bool DevPool::fits(size_t bytes) const { return in_use_ + round(bytes) <= budget_; }
+
+// --------------------------------------------------------------- context
+Ctx::~Ctx() {
+  run32.clear();
+  run64.clear();
+  blocks.clear();
+  gauges.clear();
+  flag.reset();
+  if (pinned) (void)hipHostFree(pinned);
+  pool.reset();
+  if (stream) (void)hipStreamDestroy(stream);
+}
+
+static void* pinned_area(Ctx* c, size_t bytes) {
+  if (bytes > c->pinned_bytes) {
+    if (c->pinned) DDML_HIP(hipHostFree(c->pinned));
+    c->pinned = nullptr;
+    size_t nb = std::max<size_t>(bytes, 1 << 16);
+    DDML_HIP(hipHostMalloc(&c->pinned, nb, hipHostMallocDefault));
+    c->pinned_bytes = nb;
+  }
+  return c->pinned;
+}
+
+void ctx_init(Ctx* c, const ddml_lattice* lat, int device, size_t budget) {
+  if (!lat) throw Error{DDML_EINVAL, "lattice is NULL"};
+  for (int m = 0; m < 4; ++m)
+    if (lat->dims[m] < 2 || lat->dims[m] % 2)
+      throw Error{DDML_EINVAL, "lattice extents must be even and >= 2"};
+  if (lat->bc_time != DDML_BC_PERIODIC && lat->bc_time != DDML_BC_ANTIPERIODIC)
+    throw Error{DDML_EINVAL, "bc_time must be DDML_BC_PERIODIC or DDML_BC_ANTIPERIODIC"};
+  int ndev = 0;
+  DDML_HIP(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) throw Error{DDML_EINVAL, "no such device"};
+  DDML_HIP(hipSetDevice(device));
+  c->lat = *lat;
+  c->device = device;
+  c->V = (size_t)lat->dims[0] * lat->dims[1] * lat->dims[2] * lat->dims[3];
+  if (c->V > (size_t)1 << 30) throw Error{DDML_EINVAL, "lattice too large"};
+  DDML_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+  if (budget == 0) {
+    size_t fr = 0, tot = 0;
+    DDML_HIP(hipMemGetInfo(&fr, &tot));
+    budget = (size_t)(0.9 * (double)fr);
+  }
+  c->pool.reset(new DevPool(budget));
+  c->flag = DBuf(c->pool.get(), sizeof(int));
+  for (int m = 0; m < 4; ++m) {
+    c->full.lo[m] = 0;
+    c->full.hi[m] = lat->dims[m];
+  }
+}
+
+// ------------------------------------------------------------------ gauge
+static void copy_in(Ctx* c, void* dst, const double* src, size_t bytes, int on_device) {
+  DDML_HIP(hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+}
+
+int gauge_new(Ctx* c, const double* U, int on_device, double kappa, double csw) {
+  if (!U) throw Error{DDML_EINVAL, "gauge field pointer is NULL"};
+  if (!(kappa > 0) || !std::isfinite(kappa) || !std::isfinite(csw)) throw Error{DDML_EINVAL, "bad kappa or c_sw"};
+  GaugeRec g;
+  const size_t bytes = c->V * 36 * sizeof(double2);
+  g.base = std::make_shared<DBuf>(c->pool.get(), bytes);
+  copy_in(c, g.base->p, U, bytes, on_device);
+  DDML_HIP(hipStreamSynchronize(c->stream));
+  g.kappa = kappa;
+  g.csw = csw;
+  const int id = c->next_gauge++;
+  c->gauges[id] = std::move(g);
+  return id;
+}
+
+int gauge_region(Ctx* c, int base, int t0, int t1, const double* U, int on_device) {
+  auto it = c->gauges.find(base);
+  if (it == c->gauges.end()) throw Error{DDML_EINVAL, "unknown base gauge id"};
+  if (!U) throw Error{DDML_EINVAL, "region pointer is NULL"};
+  if (t0 < 0 || t1 > c->lat.dims[0] || t0 >= t1) throw Error{DDML_EINVAL, "bad time range"};
+  const size_t V3 = c->V / c->lat.dims[0];
+  GaugeRec g;
+  g.kappa = it->second.kappa;
+  g.csw = it->second.csw;
+  if (it->second.region) {
+    // a version of a version: materialise the parent first
+    const GaugeRec& p = it->second;
+    g.base = std::make_shared<DBuf>(c->pool.get(), c->V * 36 * sizeof(double2));
+    DDML_HIP(hipMemcpyAsync(g.base->p, p.base->p, c->V * 36 * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
+    DDML_HIP(hipMemcpyAsync(g.base->as<double2>() + (size_t)p.r_t0 * V3 * 36, p.region->p,
+                            (size_t)(p.r_t1 - p.r_t0) * V3 * 36 * sizeof(double2), hipMemcpyDeviceToDevice,
+                            c->stream));
+  } else {
+    g.base = it->second.base;
+  }
+  const size_t bytes = (size_t)(t1 - t0) * V3 * 36 * sizeof(double2);
+  g.region = std::make_shared<DBuf>(c->pool.get(), bytes);
+  copy_in(c, g.region->p, U, bytes, on_device);
+  DDML_HIP(hipStreamSynchronize(c->stream));
+  g.r_t0 = t0;
+  g.r_t1 = t1;
+  const int id = c->next_gauge++;
+  c->gauges[id] = std::move(g);
+  return id;
+}
+
+void gauge_release(Ctx* c, int id) {
+  if (!c->gauges.erase(id)) throw Error{DDML_EINVAL, "unknown gauge id"};
+  for (auto it = c->blocks.begin(); it != c->blocks.end();) {
+    if (it->first.first == id) it = c->blocks.erase(it);
+    else ++it;
+  }
+}
+
+int domain_new(Ctx* c, const int lo[4], const int hi[4]) {
+  if (!lo || !hi) throw Error{DDML_EINVAL, "lo/hi is NULL"};
+  DomainRec d;
+  for (int m = 0; m < 4; ++m) {
+    if (lo[m] < 0 || hi[m] > c->lat.dims[m] || lo[m] >= hi[m])
+      throw Error{DDML_EINVAL, "domain outside the lattice or empty"};
+    if ((hi[m] - lo[m]) % 2) throw Error{DDML_EINVAL, "domain extents must be even"};
+    d.lo[m] = lo[m];
+    d.hi[m] = hi[m];
+  }
+  const int id = c->next_dom++;
+  c->domains[id] = d;
+  return id;
+}
+
+const DomainRec& domain_get(Ctx* c, int dom_id) {
+  if (dom_id == -1) return c->full;
+  auto it = c->domains.find(dom_id);
+  if (it == c->domains.end()) throw Error{DDML_EINVAL, "unknown domain id"};
+  return it->second;
+}
+
+static void fill_spec(Ctx* c, const GaugeRec& g, const DomainRec& d, BlockSpec& bs, BoxGeom& geo) {
+  for (int m = 0; m < 4; ++m) {
+    bs.L[m] = c->lat.dims[m];
+    bs.lo[m] = d.lo[m];
+    bs.Lb[m] = d.hi[m] - d.lo[m];
+    geo.L[m] = bs.Lb[m];
+  }
+  bs.antiperiodic = c->lat.bc_time == DDML_BC_ANTIPERIODIC;
+  bs.kappa = g.kappa;
+  bs.csw = g.csw;
+  geo.Vh = bs.Lb[0] * bs.Lb[1] * bs.Lb[2] * bs.Lb[3] / 2;
+  geo.half3 = bs.Lb[3] / 2;
+}
+
+static size_t opblock_bytes(size_t Vh) {
+  return DevPool::round(72 * Vh * sizeof(double2)) + 2 * DevPool::round(72 * Vh * sizeof(double2)) +
+         DevPool::round(72 * Vh * sizeof(float2)) * 2;
+}
+
+static void evict_blocks(Ctx* c) {
+  for (auto it = c->blocks.begin(); it != c->blocks.end();) {
+    if (it->second.use_count() == 1) it = c->blocks.erase(it);
+    else ++it;
+  }
+}
+
+std::shared_ptr<OpBlock> opblock(Ctx* c, int gauge_id, int dom_id) {
+  auto key = std::make_pair(gauge_id, dom_id);
+  auto it = c->blocks.find(key);
+  if (it != c->blocks.end()) return it->second;
+  auto git = c->gauges.find(gauge_id);
+  if (git == c->gauges.end()) throw Error{DDML_EINVAL, "unknown gauge id"};
+  const DomainRec& d = domain_get(c, dom_id);
+  auto ob = std::make_shared<OpBlock>();
+  fill_spec(c, git->second, d, ob->bs, ob->g);
+  const size_t Vh = (size_t)ob->g.Vh;
+  ob->ntiles = (int)((Vh + kTile - 1) / kTile);
+  ob->bytes = opblock_bytes(Vh);
+  if (!c->pool->fits(ob->bytes)) evict_blocks(c);
+  ob->U64 = DBuf(c->pool.get(), 72 * Vh * sizeof(double2));
+  ob->U32 = DBuf(c->pool.get(), 72 * Vh * sizeof(float2));
+  ob->A64 = DBuf(c->pool.get(), 72 * Vh * sizeof(double2));
+  ob->Ainv64 = DBuf(c->pool.get(), 72 * Vh * sizeof(double2));
+  ob->Ainv32 = DBuf(c->pool.get(), 72 * Vh * sizeof(float2));
+  GaugeView gv;
+  gv.base = git->second.base->as<double2>();
+  gv.region = git->second.region ? git->second.region->as<double2>() : nullptr;
+  gv.r_t0 = git->second.r_t0;
+  gv.r_t1 = git->second.r_t1;
+  DDML_HIP(hipMemsetAsync(c->flag.p, 0, sizeof(int), c->stream));
+  DDML_HIP(launch_build_links(gv, ob->bs, ob->U64.as<double2>(), ob->U32.as<float2>(), c->stream));
+  DDML_HIP(launch_build_clover(gv, ob->bs, ob->A64.as<double2>(), ob->Ainv64.as<double2>(), ob->Ainv32.as<float2>(),
+                               c->flag.as<int>(), c->stream));
+  int* hf = (int*)pinned_area(c, sizeof(int));
+  DDML_HIP(hipMemcpyAsync(hf, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  DDML_HIP(hipStreamSynchronize(c->stream));
+  if (*hf) throw Error{DDML_ENUMERIC, "clover block not positive definite (cannot invert A)"};
+  c->blocks[key] = ob;
+  return ob;
+}
+
+size_t solve_footprint(Ctx* c, int dom_id, int nrhs, int prec) {
+  const DomainRec& d = domain_get(c, dom_id);
+  size_t Vb = 1;
+  for (int m = 0; m < 4; ++m) Vb *= (size_t)(d.hi[m] - d.lo[m]);
+  const size_t Vh = Vb / 2, n = (size_t)nrhs * 12 * Vh;
+  const size_t ntiles = (Vh + kTile - 1) / kTile;
+  const size_t inner = prec == DDML_FP64 ? sizeof(double2) : sizeof(float2);
+  return 8 * DevPool::round(n * sizeof(double2)) + F_NUM * DevPool::round(n * inner) +
+         2 * DevPool::round(2 * nrhs * ntiles * sizeof(double2)) + 6 * DevPool::round(64);
+}
+
+// ------------------------------------------------------------ operators
+static HopItem<double2> item64(const OpBlock& ob, int nrhs) {
+  HopItem<double2> it{};
+  it.g = ob.g;
+  it.U = ob.U64.as<double2>();
+  it.nrhs = nrhs;
+  it.ntiles = ob.ntiles;
+  return it;
+}
+
+void apply_D(Ctx* c, int gauge_id, int dom_id, const double* in, double* out, int nrhs, hipStream_t st) {
+  auto ob = opblock(c, gauge_id, dom_id);
+  const size_t Vh = ob->g.Vh, n = (size_t)nrhs * 12 * Vh;
+  DBuf xe(c->pool.get(), n * sizeof(double2)), xo(c->pool.get(), n * sizeof(double2));
+  DBuf oe(c->pool.get(), n * sizeof(double2)), oo(c->pool.get(), n * sizeof(double2));
+  const double2* cin = reinterpret_cast<const double2*>(in);
+  double2* cout = reinterpret_cast<double2*>(out);
+  DDML_HIP(launch_gather(cin, ob->bs, 0, nrhs, 1.0, xe.as<double2>(), st));
+  DDML_HIP(launch_gather(cin, ob->bs, 1, nrhs, 1.0, xo.as<double2>(), st));
+  const double kappa = ob->bs.kappa;
+  for (int p = 0; p < 2; ++p) {
+    HopItem<double2> it = item64(*ob, nrhs);
+    it.clov = ob->A64.as<double2>();
+    it.in = p == 0 ? xo.as<double2>() : xe.as<double2>();
+    it.aux = p == 0 ? xe.as<double2>() : xo.as<double2>();
+    it.out = p == 0 ? oe.as<double2>() : oo.as<double2>();
+    it.par_out = p;
+    it.c1 = kappa;
+    it.c2 = 1.0 / (2.0 * kappa);
+    DDML_HIP(launch_hop_item(it, MODE_M, RED_NONE, 1, st));
+  }
+  DDML_HIP(hipMemsetAsync(out, 0, (size_t)nrhs * c->V * 12 * sizeof(double2), st));
+  DDML_HIP(launch_scatter(oe.as<double2>(), ob->bs, 0, nrhs, 1.0, cout, st));
+  DDML_HIP(launch_scatter(oo.as<double2>(), ob->bs, 1, nrhs, 1.0, cout, st));
+  DDML_HIP(hipStreamSynchronize(st));  // temporaries go back to the pool
+}
+
+template <typename T2>
+static void schur_apply(Ctx* c, const OpBlock& ob, const T2* U, const T2* Ainv, const T2* xe, T2* tmp, T2* oe,
+                        int nrhs, hipStream_t st) {
+  HopItem<T2> it{};
+  it.g = ob.g;
+  it.U = U;
+  it.clov = Ainv;
+  it.nrhs = nrhs;
+  it.ntiles = ob.ntiles;
+  it.in = xe;
+  it.out = tmp;
+  it.par_out = 1;
+  DDML_HIP(launch_hop_item(it, MODE_CINV_HOP, RED_NONE, c->tune.R, st));
+  it.in = tmp;
+  it.aux = xe;
+  it.out = oe;
+  it.par_out = 0;
+  it.c1 = ob.bs.kappa * ob.bs.kappa;
+  DDML_HIP(launch_hop_item(it, MODE_SCHUR, RED_NONE, c->tune.R, st));
+}
+
+void apply_eo(Ctx* c, int gauge_id, int dom_id, const double* in, double* out, int nrhs, int prec, hipStream_t st) {
+  auto ob = opblock(c, gauge_id, dom_id);
+  const size_t Vh = ob->g.Vh, n = (size_t)nrhs * 12 * Vh;
+  DBuf xe(c->pool.get(), n * sizeof(double2)), oe(c->pool.get(), n * sizeof(double2));
+  DDML_HIP(launch_gather(reinterpret_cast<const double2*>(in), ob->bs, 0, nrhs, 1.0, xe.as<double2>(), st));
+  if (prec == DDML_FP64) {
+    DBuf tmp(c->pool.get(), n * sizeof(double2));
+    schur_apply<double2>(c, *ob, ob->U64.as<double2>(), ob->Ainv64.as<double2>(), xe.as<double2>(),
+                         tmp.as<double2>(), oe.as<double2>(), nrhs, st);
+    DDML_HIP(hipMemsetAsync(out, 0, (size_t)nrhs * c->V * 12 * sizeof(double2), st));
+    DDML_HIP(launch_scatter(oe.as<double2>(), ob->bs, 0, nrhs, 1.0, reinterpret_cast<double2*>(out), st));
+    DDML_HIP(hipStreamSynchronize(st));
+  } else {
+    DBuf xf(c->pool.get(), n * sizeof(float2)), tf(c->pool.get(), n * sizeof(float2)),
+        of(c->pool.get(), n * sizeof(float2));
+    DDML_HIP(launch_cast_to_f(xe.as<double2>(), xf.as<float2>(), n, st));
+    schur_apply<float2>(c, *ob, ob->U32.as<float2>(), ob->Ainv32.as<float2>(), xf.as<float2>(), tf.as<float2>(),
+                        of.as<float2>(), nrhs, st);
+    DDML_HIP(launch_cast_to_d(of.as<float2>(), oe.as<double2>(), n, st));
+    DDML_HIP(hipMemsetAsync(out, 0, (size_t)nrhs * c->V * 12 * sizeof(double2), st));
+    DDML_HIP(launch_scatter(oe.as<double2>(), ob->bs, 0, nrhs, 1.0, reinterpret_cast<double2*>(out), st));
+    DDML_HIP(hipStreamSynchronize(st));
+  }
+}
+
+// ----------------------------------------------------------- batch runner
+template <typename T2>
+BatchRunner<T2>::~BatchRunner() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+}
+
+template <typename T2>
+void BatchRunner<T2>::init(Ctx* c, int nrhs_, int R_, int K_, int grid_, int max_slots_) {
+  ctx = c;
+  nrhs = nrhs_;
+  R = R_;
+  K = K_;
+  grid = grid_;
+  max_slots = max_slots_;
+  table = DBuf(c->pool.get(), sizeof(SlotDesc<T2>) * max_slots);
+  tstart = DBuf(c->pool.get(), sizeof(int) * (max_slots + 1));
+  nslots = DBuf(c->pool.get(), sizeof(int));
+  st_all = DBuf(c->pool.get(), sizeof(BiState) * max_slots * kMaxRhs);
+  act_all = DBuf(c->pool.get(), sizeof(int) * max_slots * kMaxRhs);
+  SlotDesc<T2> empty{};
+  h_table.assign(max_slots, empty);
+  h_tstart.assign(max_slots + 1, 0);
+  slot_of.assign(max_slots, nullptr);
+  h_st.assign((size_t)max_slots * kMaxRhs, BiState{});
+  DDML_HIP(hipMemsetAsync(act_all.p, 0, sizeof(int) * max_slots * kMaxRhs, c->stream));
+  nused = 0;
+  dirty = true;
+  upload();
+  capture();
+}
+
+template <typename T2>
+void BatchRunner<T2>::capture() {
+  hipStream_t s = ctx->stream;
+  const auto* tb = table.as<SlotDesc<T2>>();
+  const int* ts = tstart.as<int>();
+  const int* ns = nslots.as<int>();
+  DDML_HIP(hipStreamSynchronize(s));
+  hipGraph_t graph = nullptr;
+  DDML_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  for (int k = 0; k < K; ++k) {
+    (void)launch_vec(tb, ts, ns, nrhs, VEC_P, grid, s);
+    (void)launch_hop_batch(tb, ts, ns, nrhs, R, MODE_CINV_HOP, RED_NONE, F_P, -1, F_TMP, -1, 1, grid, s);
+    (void)launch_hop_batch(tb, ts, ns, nrhs, R, MODE_SCHUR, RED_DOT, F_TMP, F_P, F_V, F_RH, 0, grid, s);
+    (void)launch_fin(tb, ns, max_slots, FIN_ALPHA, s);
+    (void)launch_vec(tb, ts, ns, nrhs, VEC_S, grid, s);
+    (void)launch_hop_batch(tb, ts, ns, nrhs, R, MODE_CINV_HOP, RED_NONE, F_S, -1, F_TMP, -1, 1, grid, s);
+    (void)launch_hop_batch(tb, ts, ns, nrhs, R, MODE_SCHUR, RED_TS, F_TMP, F_S, F_T, -1, 0, grid, s);
+    (void)launch_fin(tb, ns, max_slots, FIN_OMEGA, s);
+    (void)launch_vec(tb, ts, ns, nrhs, VEC_XR, grid, s);
+    (void)launch_fin(tb, ns, max_slots, FIN_RHO, s);
+  }
+  hipError_t e = hipStreamEndCapture(s, &graph);
+  if (e != hipSuccess) throw Error{DDML_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(e)};
+  e = hipGetLastError();
+  if (e != hipSuccess) throw Error{DDML_EDEVICE, std::string("launch in capture failed: ") + hipGetErrorString(e)};
+  if (exec) (void)hipGraphExecDestroy(exec);
+  exec = nullptr;
+  DDML_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  DDML_HIP(hipGraphDestroy(graph));
+}
+
+template <typename T2>
+int BatchRunner<T2>::members() const {
+  int n = 0;
+  for (auto* s : slot_of) n += s != nullptr;
+  return n;
+}
+
+template <typename T2>
+static SlotDesc<T2> make_desc(const Solve* s, BiState* st, int* act);
+
+template <>
+SlotDesc<float2> make_desc<float2>(const Solve* s, BiState* st, int* act) {
+  SlotDesc<float2> d{};
+  d.g = s->ob->g;
+  d.nrhs = s->nrhs;
+  d.ntiles = s->ob->ntiles;
+  d.kappa = s->ob->bs.kappa;
+  d.U = s->ob->U32.as<float2>();
+  d.Ainv = s->ob->Ainv32.as<float2>();
+  for (int k = 0; k < F_NUM; ++k) d.f[k] = s->f[k].as<float2>();
+  d.partial = s->partial.as<double2>();
+  d.active = act;
+  d.st = st;
+  d.src64 = s->te.as<double2>();
+  return d;
+}
+template <>
+SlotDesc<double2> make_desc<double2>(const Solve* s, BiState* st, int* act) {
+  SlotDesc<double2> d{};
+  d.g = s->ob->g;
+  d.nrhs = s->nrhs;
+  d.ntiles = s->ob->ntiles;
+  d.kappa = s->ob->bs.kappa;
+  d.U = s->ob->U64.as<double2>();
+  d.Ainv = s->ob->Ainv64.as<double2>();
+  for (int k = 0; k < F_NUM; ++k) d.f[k] = s->f[k].as<double2>();
+  d.partial = s->partial.as<double2>();
+  d.active = act;
+  d.st = st;
+  d.src64 = s->te.as<double2>();
+  return d;
+}
+
+template <typename T2>
+int BatchRunner<T2>::join(Solve* s) {
+  int slot = -1;
+  for (int i = 0; i < max_slots; ++i)
+    if (!slot_of[i]) { slot = i; break; }
+  if (slot < 0) return -1;
+  BiState* st = st_all.as<BiState>() + (size_t)slot * kMaxRhs;
+  int* act = act_all.as<int>() + (size_t)slot * kMaxRhs;
+  h_table[slot] = make_desc<T2>(s, st, act);
+  slot_of[slot] = s;
+  s->slot = slot;
+  dirty = true;
+  return slot;
+}
+
+template <typename T2>
+void BatchRunner<T2>::leave(Solve* s) {
+  if (s->slot < 0) return;
+  h_table[s->slot] = SlotDesc<T2>{};
+  slot_of[s->slot] = nullptr;
+  s->slot = -1;
+  dirty = true;
+}
+
+template <typename T2>
+void BatchRunner<T2>::upload() {
+  nused = 0;
+  for (int i = 0; i < max_slots; ++i)
+    if (slot_of[i]) nused = i + 1;
+  h_tstart[0] = 0;
+  for (int i = 0; i < max_slots; ++i) h_tstart[i + 1] = h_tstart[i] + (slot_of[i] ? h_table[i].ntiles : 0);
+  DDML_HIP(hipMemcpyAsync(table.p, h_table.data(), sizeof(SlotDesc<T2>) * max_slots, hipMemcpyHostToDevice,
+                          ctx->stream));
+  DDML_HIP(hipMemcpyAsync(tstart.p, h_tstart.data(), sizeof(int) * (max_slots + 1), hipMemcpyHostToDevice,
+                          ctx->stream));
+  DDML_HIP(hipMemcpyAsync(nslots.p, &nused, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+  dirty = false;
+}
+
+template <typename T2>
+void BatchRunner<T2>::replay() {
+  if (dirty) upload();
+  DDML_HIP(hipGraphLaunch(exec, ctx->stream));
+  const size_t nb = sizeof(BiState) * (size_t)std::max(nused, 1) * kMaxRhs;
+  BiState* hs = (BiState*)pinned_area(ctx, nb);
+  DDML_HIP(hipMemcpyAsync(hs, st_all.p, nb, hipMemcpyDeviceToHost, ctx->stream));
+  DDML_HIP(hipStreamSynchronize(ctx->stream));
+  std::memcpy(h_st.data(), hs, nb);
+}
+
+template struct BatchRunner<float2>;
+template struct BatchRunner<double2>;
+
+// ------------------------------------------------------------ solve flow
+ddml_solver_params default_params() {
+  ddml_solver_params p{};
+  p.tol = 1e-10;
+  p.max_outer = 12;
+  p.max_inner = 4000;
+  p.inner_tol = 1e-5;
+  p.prec = DDML_MIXED_FP32;
+  p.solver = 0;
+  p.gcr_m = 0;
+  return p;
+}
+
+void check_params(const ddml_solver_params* p) {
+  if (!p) throw Error{DDML_EINVAL, "solver params NULL"};
+  if (!(p->tol > 0) || !(p->tol < 1)) throw Error{DDML_EINVAL, "tol must be in (0,1)"};
+  if (p->max_outer < 1 || p->max_inner < 1) throw Error{DDML_EINVAL, "max_outer and max_inner must be >= 1"};
+  if (!(p->inner_tol > 0) || !(p->inner_tol < 1)) throw Error{DDML_EINVAL, "inner_tol must be in (0,1)"};
+  if (p->prec != DDML_FP64 && p->prec != DDML_MIXED_FP32) throw Error{DDML_EINVAL, "unknown precision"};
+  if (p->solver != 0) throw Error{DDML_EINVAL, "only BiCGstab (solver=0) is available"};
+}
+
+template <typename T2>
+static BatchRunner<T2>& runner(Ctx* c, int nrhs);
+template <>
+BatchRunner<float2>& runner<float2>(Ctx* c, int nrhs) {
+  auto& r = c->run32[nrhs];
+  if (!r) {
+    r.reset(new BatchRunner<float2>());
+    r->init(c, nrhs, c->tune.R, c->tune.K, c->tune.grid, 64);
+  }
+  return *r;
+}
+template <>
+BatchRunner<double2>& runner<double2>(Ctx* c, int nrhs) {
+  auto& r = c->run64[nrhs];
+  if (!r) {
+    r.reset(new BatchRunner<double2>());
+    r->init(c, nrhs, c->tune.R, c->tune.K, c->tune.grid, 64);
+  }
+  return *r;
+}
+
+void solve_prepare(Ctx* c, Solve* s) {
+  if (s->nrhs < 1 || s->nrhs > kMaxRhs) throw Error{DDML_EINVAL, "nrhs must be in 1..12"};
+  s->ob = opblock(c, s->gauge_id, s->dom_id);
+  const size_t Vh = s->ob->g.Vh, n = (size_t)s->nrhs * 12 * Vh;
+  const size_t nt = s->ob->ntiles;
+  DevPool* P = c->pool.get();
+  s->be = DBuf(P, n * sizeof(double2));
+  s->bo = DBuf(P, n * sizeof(double2));
+  s->xe = DBuf(P, n * sizeof(double2));
+  s->xo = DBuf(P, n * sizeof(double2));
+  s->re = DBuf(P, n * sizeof(double2));
+  s->ro = DBuf(P, n * sizeof(double2));
+  s->te = DBuf(P, n * sizeof(double2));
+  s->to = DBuf(P, n * sizeof(double2));
+  s->partial64 = DBuf(P, 2 * s->nrhs * nt * sizeof(double2));
+  s->norms = DBuf(P, 3 * s->nrhs * sizeof(double2));
+  const size_t inner = s->prec == DDML_FP64 ? sizeof(double2) : sizeof(float2);
+  for (int k = 0; k < F_NUM; ++k) s->f[k] = DBuf(P, n * inner);
+  s->partial = DBuf(P, 2 * s->nrhs * nt * sizeof(double2));
+  s->table1 = DBuf(P, std::max(sizeof(SlotDesc<double2>), sizeof(SlotDesc<float2>)));
+  s->tstart1 = DBuf(P, 2 * sizeof(int));
+  s->n1 = DBuf(P, sizeof(int));
+  const double kappa = s->ob->bs.kappa;
+  const double2* src = reinterpret_cast<const double2*>(s->src);
+  hipStream_t st = c->stream;
+  DDML_HIP(launch_gather(src, s->ob->bs, 0, s->nrhs, 2.0 * kappa, s->be.as<double2>(), st));
+  DDML_HIP(launch_gather(src, s->ob->bs, 1, s->nrhs, 2.0 * kappa, s->bo.as<double2>(), st));
+  DDML_HIP(hipMemsetAsync(s->xe.p, 0, n * sizeof(double2), st));
+  DDML_HIP(hipMemsetAsync(s->xo.p, 0, n * sizeof(double2), st));
+  DDML_HIP(launch_col_norms(s->be.as<double2>(), (int)Vh, s->nrhs, s->partial64.as<double2>(), (int)nt,
+                            s->norms.as<double2>(), 0, st));
+  DDML_HIP(launch_col_norms(s->bo.as<double2>(), (int)Vh, s->nrhs, s->partial64.as<double2>(), (int)nt,
+                            s->norms.as<double2>(), 1, st));
+  s->bn2.assign(s->nrhs, 0.0);
+  s->rel.assign(s->nrhs, 1.0);
+  s->done.assign(s->nrhs, 0);
+  s->inner_iters.assign(s->nrhs, 0);
+  s->status.assign(s->nrhs, DDML_OK);
+  s->outer = 0;
+  s->state = 1;
+}
+
+// r = b' - M x on both parities with |r|^2 partials
+static void launch_residual(Ctx* c, Solve* s) {
+  const OpBlock& ob = *s->ob;
+  const int nt = ob.ntiles;
+  for (int p = 0; p < 2; ++p) {
+    HopItem<double2> it = item64(ob, s->nrhs);
+    it.clov = ob.A64.as<double2>();
+    it.in = p == 0 ? s->xo.as<double2>() : s->xe.as<double2>();
+    it.aux = p == 0 ? s->xe.as<double2>() : s->xo.as<double2>();
+    it.red_a = p == 0 ? s->be.as<double2>() : s->bo.as<double2>();
+    it.out = p == 0 ? s->re.as<double2>() : s->ro.as<double2>();
+    it.partial = s->partial64.as<double2>() + (size_t)p * s->nrhs * nt;
+    it.par_out = p;
+    it.c1 = ob.bs.kappa;
+    DDML_HIP(launch_hop_item(it, MODE_RES, RED_NORM, 1, c->stream));
+  }
+  DDML_HIP(launch_sum_partials(s->partial64.as<double2>(), 2, s->nrhs, nt, s->norms.as<double2>() + s->nrhs, 0,
+                               c->stream));
+}
+
+// rhat_e = A_ee^{-1}(r_e + kappa H_eo A_oo^{-1} r_o) into te
+static void launch_prepare(Ctx* c, Solve* s) {
+  const OpBlock& ob = *s->ob;
+  DDML_HIP(launch_clover_apply(ob.g, ob.Ainv64.as<double2>(), 1, s->ro.as<double2>(), s->to.as<double2>(), s->nrhs,
+                               c->stream));
+  HopItem<double2> it = item64(ob, s->nrhs);
+  it.clov = ob.Ainv64.as<double2>();
+  it.in = s->to.as<double2>();
+  it.aux = s->re.as<double2>();
+  it.out = s->te.as<double2>();
+  it.par_out = 0;
+  it.c1 = ob.bs.kappa;
+  DDML_HIP(launch_hop_item(it, MODE_PREP, RED_NONE, 1, c->stream));
+}
+
+// e_e from the inner solution, e_o = A_oo^{-1}(r_o + kappa H_oe e_e), x += e
+template <typename T2>
+static void launch_export(Ctx* c, Solve* s) {
+  const OpBlock& ob = *s->ob;
+  const size_t n = (size_t)s->nrhs * 12 * ob.g.Vh;
+  DDML_HIP(launch_cast_to_d(s->f[F_X].as<T2>(), s->te.as<double2>(), n, c->stream));
+  HopItem<double2> it = item64(ob, s->nrhs);
+  it.clov = ob.Ainv64.as<double2>();
+  it.in = s->te.as<double2>();
+  it.aux = s->ro.as<double2>();
+  it.out = s->to.as<double2>();
+  it.par_out = 1;
+  it.c1 = ob.bs.kappa;
+  DDML_HIP(launch_hop_item(it, MODE_PREP, RED_NONE, 1, c->stream));
+  DDML_HIP(launch_axpy_d(s->xe.as<double2>(), s->te.as<double2>(), 1.0, n, c->stream));
+  DDML_HIP(launch_axpy_d(s->xo.as<double2>(), s->to.as<double2>(), 1.0, n, c->stream));
+}
+
+template <typename T2>
+static bool try_join(Ctx* c, Solve* s) {
+  BatchRunner<T2>& run = runner<T2>(c, s->nrhs);
+  const int slot = run.join(s);
+  if (slot < 0) return false;
+  // per-column request flags and limits for this cycle
+  std::vector<int> want(kMaxRhs, 0);
+  std::vector<BiState> st(kMaxRhs, BiState{});
+  const double tol = s->prm.tol;
+  for (int col = 0; col < s->nrhs; ++col) {
+    want[col] = !s->done[col];
+    // reduction needed this cycle: tol |b| / |r|, with a safety factor; never
+    // tighter than the requested inner tolerance in mixed precision
+    double need = s->rel[col] > 0 ? 0.1 * tol / s->rel[col] : 1e-3;
+    double it = s->prec == DDML_FP64 ? std::max(need, 1e-14) : std::max(need, s->prm.inner_tol);
+    it = std::min(it, 0.1);
+    st[col].tol2 = it * it;
+    st[col].max_iters = s->prm.max_inner;
+  }
+  BiState* dst = run.st_all.template as<BiState>() + (size_t)slot * kMaxRhs;
+  int* dact = run.act_all.template as<int>() + (size_t)slot * kMaxRhs;
+  DDML_HIP(hipMemcpyAsync(dst, st.data(), sizeof(BiState) * kMaxRhs, hipMemcpyHostToDevice, c->stream));
+  DDML_HIP(hipMemcpyAsync(dact, want.data(), sizeof(int) * kMaxRhs, hipMemcpyHostToDevice, c->stream));
+  // one-entry table for the initialisation
+  SlotDesc<T2> d = run.h_table[slot];
+  int ts[2] = {0, d.ntiles};
+  int one = 1;
+  DDML_HIP(hipMemcpyAsync(s->table1.p, &d, sizeof(d), hipMemcpyHostToDevice, c->stream));
+  DDML_HIP(hipMemcpyAsync(s->tstart1.p, ts, sizeof(ts), hipMemcpyHostToDevice, c->stream));
+  DDML_HIP(hipMemcpyAsync(s->n1.p, &one, sizeof(int), hipMemcpyHostToDevice, c->stream));
+  const int grid = std::min(d.ntiles, 4096);
+  DDML_HIP(launch_vec(s->table1.as<SlotDesc<T2>>(), s->tstart1.as<int>(), s->n1.as<int>(), s->nrhs, VEC_INIT, grid,
+                      c->stream));
+  DDML_HIP(launch_fin(s->table1.as<SlotDesc<T2>>(), s->n1.as<int>(), 1, FIN_INIT, c->stream));
+  s->state = 2;
+  return true;
+}
+
+static void finish_state(Solve* s) { s->state = 3; }
+
+// One scheduling round over the live solves.
+void solve_progress(Ctx* c, std::vector<Solve*>& live, bool block) {
+  (void)block;
+  hipStream_t st = c->stream;
+  // 1. residuals of every solve that needs one, one synchronisation
+  std::vector<Solve*> need;
+  for (Solve* s : live)
+    if (s->state == 1) need.push_back(s);
+  if (!need.empty()) {
+    size_t tot = 0;
+    for (Solve* s : need) tot += 3 * s->nrhs;
+    double2* h = (double2*)pinned_area(c, tot * sizeof(double2));
+    size_t off = 0;
+    for (Solve* s : need) {
+      launch_residual(c, s);
+      DDML_HIP(hipMemcpyAsync(h + off, s->norms.p, 3 * s->nrhs * sizeof(double2), hipMemcpyDeviceToHost, st));
+      off += 3 * s->nrhs;
+    }
+    DDML_HIP(hipStreamSynchronize(st));
+    std::vector<double2> hv(h, h + tot);
+    off = 0;
+    for (Solve* s : need) {
+      bool all = true, bad = false;
+      for (int col = 0; col < s->nrhs; ++col) {
+        const double bn2 = hv[off + col].x;
+        const double rn2 = hv[off + s->nrhs + col].x + hv[off + 2 * s->nrhs + col].x;
+        s->bn2[col] = bn2;
+        double rel = (bn2 > 0 || !std::isfinite(bn2)) ? std::sqrt(rn2 / bn2) : 0.0;
+        if (!std::isfinite(rel)) { bad = true; rel = INFINITY; s->status[col] = DDML_ENUMERIC; }
+        s->rel[col] = rel;
+        s->done[col] = rel <= s->prm.tol || s->status[col] == DDML_ENUMERIC;
+        all = all && s->done[col];
+      }
+      off += 3 * s->nrhs;
+      (void)bad;
+      if (all || s->outer >= s->prm.max_outer) {
+        finish_state(s);
+      } else {
+        launch_prepare(c, s);
+        s->outer += 1;
+        s->state = 4;
+      }
+    }
+  }
+  // 2. join the batch
+  for (Solve* s : live)
+    if (s->state == 4) {
+      if (s->prec == DDML_FP64) try_join<double2>(c, s);
+      else try_join<float2>(c, s);
+    }
+  // 3. one replay per runner with members; collect finished inner solves
+  auto step = [&](auto& runs, auto tag) {
+    using T2 = decltype(tag);
+    for (auto& kv : runs) {
+      auto& run = *kv.second;
+      if (run.members() == 0) continue;
+      run.replay();
+      for (int slot = 0; slot < run.max_slots; ++slot) {
+        Solve* s = run.slot_of[slot];
+        if (!s) continue;
+        bool any = false;
+        for (int col = 0; col < s->nrhs; ++col) any = any || run.h_st[(size_t)slot * kMaxRhs + col].active;
+        if (any) continue;
+        for (int col = 0; col < s->nrhs; ++col) {
+          const BiState& b = run.h_st[(size_t)slot * kMaxRhs + col];
+          if (!s->done[col]) s->inner_iters[col] += b.iters;
+        }
+        run.leave(s);
+        launch_export<T2>(c, s);
+        s->state = 1;
+      }
+    }
+  };
+  step(c->run32, float2{});
+  step(c->run64, double2{});
+}
+
+void solve_finish(Ctx* c, Solve* s) {
+  hipStream_t st = c->stream;
+  double2* sol = reinterpret_cast<double2*>(s->sol);
+  DDML_HIP(hipMemsetAsync(sol, 0, (size_t)s->nrhs * c->V * 12 * sizeof(double2), st));
+  DDML_HIP(launch_scatter(s->xe.as<double2>(), s->ob->bs, 0, s->nrhs, 1.0, sol, st));
+  DDML_HIP(launch_scatter(s->xo.as<double2>(), s->ob->bs, 1, s->nrhs, 1.0, sol, st));
+  if (s->info) {
+    for (int col = 0; col < s->nrhs; ++col) {
+      ddml_rhs_info& in = s->info[col];
+      in.outer_iters = s->outer;
+      in.inner_iters = s->inner_iters[col];
+      in.true_rel_residual = s->rel[col];
+      in.status = s->status[col] == DDML_ENUMERIC ? DDML_ENUMERIC
+                  : (s->rel[col] <= s->prm.tol ? DDML_OK : DDML_ENOTCONVERGED);
+    }
+  }
+  // release device state (the scatter is ordered before any reuse of the
+  // memory because every later use is on the same stream)
+  s->be.reset(); s->bo.reset(); s->xe.reset(); s->xo.reset();
+  s->re.reset(); s->ro.reset(); s->te.reset(); s->to.reset();
+  s->partial64.reset(); s->norms.reset(); s->partial.reset();
+  for (int k = 0; k < F_NUM; ++k) s->f[k].reset();
+  s->table1.reset(); s->tstart1.reset(); s->n1.reset();
+  s->ob.reset();
+  s->state = 3;
+}
+
+template <typename T2>
+static void time_stencil_t(Ctx* c, const OpBlock& ob, const T2* U, const T2* Ainv, int nrhs, int iters,
+                           double out[4]) {
+  hipStream_t st = c->stream;
+  const size_t Vh = ob.g.Vh, n = (size_t)nrhs * 12 * Vh;
+  DevPool* P = c->pool.get();
+  DBuf fP(P, n * sizeof(T2)), fT(P, n * sizeof(T2)), fV(P, n * sizeof(T2)), fR(P, n * sizeof(T2));
+  DBuf part(P, 2 * nrhs * ob.ntiles * sizeof(double2)), act(P, kMaxRhs * sizeof(int));
+  DBuf tab(P, sizeof(SlotDesc<T2>)), ts(P, 2 * sizeof(int)), ns(P, sizeof(int));
+  DDML_HIP(launch_fill(fP.as<T2>(), n, 1.0, st));
+  DDML_HIP(launch_fill(fR.as<T2>(), n, 0.5, st));
+  std::vector<int> ones(kMaxRhs, 1);
+  DDML_HIP(hipMemcpyAsync(act.p, ones.data(), kMaxRhs * sizeof(int), hipMemcpyHostToDevice, st));
+  SlotDesc<T2> d{};
+  d.g = ob.g;
+  d.nrhs = nrhs;
+  d.ntiles = ob.ntiles;
+  d.kappa = ob.bs.kappa;
+  d.U = U;
+  d.Ainv = Ainv;
+  d.f[F_P] = fP.as<T2>();
+  d.f[F_TMP] = fT.as<T2>();
+  d.f[F_V] = fV.as<T2>();
+  d.f[F_RH] = fR.as<T2>();
+  d.partial = part.as<double2>();
+  d.active = act.as<int>();
+  int h_ts[2] = {0, ob.ntiles}, one = 1;
+  DDML_HIP(hipMemcpyAsync(tab.p, &d, sizeof(d), hipMemcpyHostToDevice, st));
+  DDML_HIP(hipMemcpyAsync(ts.p, h_ts, sizeof(h_ts), hipMemcpyHostToDevice, st));
+  DDML_HIP(hipMemcpyAsync(ns.p, &one, sizeof(int), hipMemcpyHostToDevice, st));
+  const int R = c->tune.R, grid = c->tune.grid;
+  auto* tb = tab.as<SlotDesc<T2>>();
+  auto launch = [&](int which) {
+    if (which == 0)
+      DDML_HIP(launch_hop_batch(tb, ts.as<int>(), ns.as<int>(), nrhs, R, MODE_CINV_HOP, RED_NONE, F_P, -1, F_TMP, -1,
+                                1, grid, st));
+    else
+      DDML_HIP(launch_hop_batch(tb, ts.as<int>(), ns.as<int>(), nrhs, R, MODE_SCHUR, RED_DOT, F_TMP, F_P, F_V, F_RH,
+                                0, grid, st));
+  };
+  for (int w = 0; w < 3; ++w) { launch(0); launch(1); }
+  std::vector<hipEvent_t> ev(2 * iters + 1);
+  for (auto& e : ev) DDML_HIP(hipEventCreate(&e));
+  DDML_HIP(hipEventRecord(ev[0], st));
+  for (int i = 0; i < iters; ++i) {
+    launch(0);
+    DDML_HIP(hipEventRecord(ev[2 * i + 1], st));
+    launch(1);
+    DDML_HIP(hipEventRecord(ev[2 * i + 2], st));
+  }
+  DDML_HIP(hipEventSynchronize(ev[2 * iters]));
+  double t0 = 0, t1 = 0;
+  for (int i = 0; i < iters; ++i) {
+    float a = 0, b = 0;
+    DDML_HIP(hipEventElapsedTime(&a, ev[2 * i], ev[2 * i + 1]));
+    DDML_HIP(hipEventElapsedTime(&b, ev[2 * i + 1], ev[2 * i + 2]));
+    t0 += a;
+    t1 += b;
+  }
+  for (auto& e : ev) DDML_HIP(hipEventDestroy(e));
+  const double s = sizeof(T2) / 2;  // bytes per real
+  // CINV_HOP: read the input spinor, all links of the box (4 per site), A^{-1} of
+  // the output parity; write the output.  SCHUR (+dot): read input, aux and the
+  // dot operand, links, A^{-1}; write the output.
+  out[0] = t0 / iters;
+  out[1] = t1 / iters;
+  out[2] = (double)Vh * (48.0 * nrhs + 144.0 + 72.0) * s;
+  out[3] = (double)Vh * (96.0 * nrhs + 144.0 + 72.0) * s;
+}
+
+void time_stencil(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, int iters, double out[4]) {
+  if (nrhs < 1 || nrhs > kMaxRhs || iters < 1) throw Error{DDML_EINVAL, "bad nrhs or iters"};
+  auto ob = opblock(c, gauge_id, dom_id);
+  if (prec == DDML_FP64)
+    time_stencil_t<double2>(c, *ob, ob->U64.as<double2>(), ob->Ainv64.as<double2>(), nrhs, iters, out);
+  else
+    time_stencil_t<float2>(c, *ob, ob->U32.as<float2>(), ob->Ainv32.as<float2>(), nrhs, iters, out);
+}
+
+void run_solves(Ctx* c, std::vector<Solve*>& solves) {
+  std::deque<Solve*> queue(solves.begin(), solves.end());
+  std::vector<Solve*> live;
+  while (!queue.empty() || !live.empty()) {
+    while (!queue.empty()) {
+      Solve* s = queue.front();
+      const size_t fp = solve_footprint(c, s->dom_id, s->nrhs, s->prec);
+      if (!live.empty() && !c->pool->fits(fp)) break;
+      queue.pop_front();
+      solve_prepare(c, s);
+      live.push_back(s);
+    }
+    solve_progress(c, live, true);
+    for (auto it = live.begin(); it != live.end();) {
+      if ((*it)->state == 3) {
+        solve_finish(c, *it);
+        it = live.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  DDML_HIP(hipStreamSynchronize(c->stream));
+}
+
+}  // namespace ddml

@@ -1,0 +1,208 @@
+// Host engine of libddml: device memory, gauge versions, domains, operator
+// blocks and the batched mixed-precision solver.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/ddml.h"
+#include "ddml_common.hpp"
+#include "launchers.hpp"
+
+namespace ddml {
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+#define DDML_HIP(call)                                                                 \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      throw ::ddml::Error{DDML_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+// ---------------------------------------------------------------- memory
+// Caching device allocator with a byte budget.  Blocks are rounded to 2 MiB
+// and recycled by exact size, so the repeated same-size allocations of a
+// serving loop never reach hipMalloc after warm-up.
+class DevPool {
+ public:
+  explicit DevPool(size_t budget) : budget_(budget) {}
+  ~DevPool();
+  void* alloc(size_t bytes);   // throws Error{ENOMEM}
+  void free(void* p);
+  bool fits(size_t bytes) const;
+  size_t in_use() const { return in_use_; }
+  size_t budget() const { return budget_; }
+  size_t cached() const { return cached_; }
+  static size_t round(size_t b) { return ((b + (2u << 20) - 1) >> 21) << 21; }
+  void trim();  // release cached blocks
+
+ private:
+  std::mutex mu_;
+  size_t budget_;
+  size_t in_use_ = 0;   // bytes handed out
+  size_t cached_ = 0;   // bytes held in free lists
+  std::map<size_t, std::vector<void*>> free_;
+  std::unordered_map<void*, size_t> sizes_;
+};
+
+struct DBuf {
+  DevPool* pool = nullptr;
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(DevPool* pl, size_t b) : pool(pl), p(b ? pl->alloc(b) : nullptr), bytes(b) {}
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : pool(o.pool), p(o.p), bytes(o.bytes) { o.p = nullptr; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) { reset(); pool = o.pool; p = o.p; bytes = o.bytes; o.p = nullptr; }
+    return *this;
+  }
+  ~DBuf() { reset(); }
+  void reset() { if (p && pool) pool->free(p); p = nullptr; bytes = 0; }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ------------------------------------------------------------ model objects
+struct GaugeRec {
+  std::shared_ptr<DBuf> base;     // [V][4][9] double2
+  std::shared_ptr<DBuf> region;   // [V_region][4][9] or null
+  int r_t0 = 0, r_t1 = 0;
+  double kappa = 0, csw = 0;
+};
+
+struct DomainRec {
+  int lo[4], hi[4];
+};
+
+struct OpBlock {
+  BlockSpec bs;
+  BoxGeom g;
+  int ntiles = 0;
+  DBuf U64, A64, Ainv64;   // FP64 operator data
+  DBuf U32, Ainv32;        // FP32 copies for the inner solve
+  size_t bytes = 0;
+};
+
+struct Ctx;
+
+// One domain solve in flight.
+struct Solve {
+  int gauge_id = -1, dom_id = -1, nrhs = 0, prec = DDML_MIXED_FP32;
+  std::shared_ptr<OpBlock> ob;
+  ddml_solver_params prm{};
+  // FP64 outer state, each [nrhs][12][Vh]
+  DBuf be, bo, xe, xo, re, ro, te, to;
+  DBuf partial64;   // [2][nrhs][ntiles]
+  DBuf norms;       // double2 [4][nrhs]: |b|^2, |r|^2
+  // inner state in the inner precision
+  DBuf f[F_NUM];
+  DBuf partial;     // [2][nrhs][ntiles]
+  DBuf table1, tstart1, n1;  // one-entry slot table
+  int slot = -1;    // position in the batch table
+  // host bookkeeping
+  std::vector<double> bn2, rel;
+  std::vector<int> done, inner_iters, status;
+  int outer = 0;
+  int state = 0;    // 0 new, 1 needs residual, 2 inner, 3 finished
+  const double* src = nullptr;   // canonical device pointer
+  double* sol = nullptr;         // canonical device pointer
+  ddml_rhs_info* info = nullptr; // host
+  size_t footprint = 0;
+  uint64_t tag = 0;              // serving ticket (0 for direct calls)
+};
+
+// Batched inner solver for one precision and nrhs: a slot table in device
+// memory and a captured graph of K BiCGstab iterations over it.
+template <typename T2>
+struct BatchRunner {
+  Ctx* ctx = nullptr;
+  int nrhs = 0, R = 3, K = 8, grid = 1024, max_slots = 64;
+  DBuf table, tstart, nslots, st_all, act_all;
+  std::vector<SlotDesc<T2>> h_table;
+  std::vector<int> h_tstart;
+  std::vector<Solve*> slot_of;    // slot -> solve (nullptr = free)
+  std::vector<BiState> h_st;
+  hipGraphExec_t exec = nullptr;
+  bool dirty = true;
+  int nused = 0;                  // highest used slot + 1
+  ~BatchRunner();
+  void init(Ctx* c, int nrhs_, int R_, int K_, int grid_, int max_slots_);
+  void capture();
+  int join(Solve* s);             // returns slot or -1 if full
+  void leave(Solve* s);
+  void upload();
+  void replay();
+  int members() const;
+};
+
+struct TuneChoice {
+  int R = 1;
+  int K = 8;
+  int grid = 1024;
+};
+
+struct Server;
+
+struct Ctx {
+  ddml_lattice lat{};
+  int device = 0;
+  size_t V = 0;
+  hipStream_t stream = nullptr;
+  std::unique_ptr<DevPool> pool;
+  std::recursive_mutex mu;
+  std::string last_error;
+  int next_gauge = 1, next_dom = 1;
+  std::map<int, GaugeRec> gauges;
+  std::map<int, DomainRec> domains;
+  std::map<std::pair<int, int>, std::shared_ptr<OpBlock>> blocks;
+  std::map<int, std::unique_ptr<BatchRunner<float2>>> run32;   // by nrhs
+  std::map<int, std::unique_ptr<BatchRunner<double2>>> run64;
+  DBuf flag;        // device int for clover failures
+  DomainRec full{};  // the whole lattice (dom_id -1)
+  void* pinned = nullptr;   // small pinned host staging area
+  size_t pinned_bytes = 0;
+  TuneChoice tune;
+  std::unique_ptr<Server> server;
+  ~Ctx();
+};
+
+// engine.cpp
+void ctx_init(Ctx* c, const ddml_lattice* lat, int device, size_t budget);
+int gauge_new(Ctx* c, const double* U, int on_device, double kappa, double csw);
+int gauge_region(Ctx* c, int base, int t0, int t1, const double* U, int on_device);
+void gauge_release(Ctx* c, int id);
+int domain_new(Ctx* c, const int lo[4], const int hi[4]);
+const DomainRec& domain_get(Ctx* c, int dom_id);  // dom_id -1 = full lattice
+std::shared_ptr<OpBlock> opblock(Ctx* c, int gauge_id, int dom_id);
+size_t solve_footprint(Ctx* c, int dom_id, int nrhs, int prec);
+void apply_D(Ctx* c, int gauge_id, int dom_id, const double* in, double* out, int nrhs, hipStream_t st);
+void apply_eo(Ctx* c, int gauge_id, int dom_id, const double* in, double* out, int nrhs, int prec, hipStream_t st);
+// Runs every solve to completion (continuous batching inside).  Device pointers.
+void run_solves(Ctx* c, std::vector<Solve*>& solves);
+// Pieces used by the serving loop
+void solve_prepare(Ctx* c, Solve* s);                // allocate + set up (state -> 1)
+void solve_progress(Ctx* c, std::vector<Solve*>& live, bool block);  // one scheduling round
+void solve_finish(Ctx* c, Solve* s);                 // scatter, info, free
+void check_params(const ddml_solver_params* p);
+// Times the two stencil kernels of the inner solver (k_hop_batch, CINV_HOP and
+// SCHUR with its fused dot product) on one slot; out = {ms_cinv, ms_schur,
+// bytes_cinv, bytes_schur} per launch (algorithmic bytes).
+void time_stencil(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, int iters, double out[4]);
+ddml_solver_params default_params();
+
+}  // namespace ddml

@@ -1,0 +1,73 @@
+// Host-callable launchers for the device kernels of libddml.
+#pragma once
+#include "ddml_common.hpp"
+
+namespace ddml {
+
+// dirac.hip
+hipError_t launch_hop_item(const HopItem<double2>& it, int mode, int red, int R, hipStream_t st);
+hipError_t launch_hop_item(const HopItem<float2>& it, int mode, int red, int R, hipStream_t st);
+hipError_t launch_hop_batch(const SlotDesc<float2>* slots, const int* tile_start, const int* nslots_p, int nrhs,
+                            int R, int mode, int red, int fin, int faux, int fout, int fred, int par_out, int grid,
+                            hipStream_t st);
+hipError_t launch_hop_batch(const SlotDesc<double2>* slots, const int* tile_start, const int* nslots_p, int nrhs,
+                            int R, int mode, int red, int fin, int faux, int fout, int fred, int par_out, int grid,
+                            hipStream_t st);
+hipError_t launch_clover_apply(const BoxGeom& g, const double2* clov, int p, const double2* in, double2* out,
+                               int nrhs, hipStream_t st);
+
+// blas.hip: inner BiCGstab steps over a slot table
+enum { VEC_P = 0, VEC_S = 1, VEC_XR = 2, VEC_INIT = 3 };
+enum { FIN_INIT = 0, FIN_ALPHA = 1, FIN_OMEGA = 2, FIN_RHO = 3 };
+hipError_t launch_vec(const SlotDesc<float2>* slots, const int* tile_start, const int* nslots_p, int nrhs, int op,
+                      int grid, hipStream_t st);
+hipError_t launch_vec(const SlotDesc<double2>* slots, const int* tile_start, const int* nslots_p, int nrhs, int op,
+                      int grid, hipStream_t st);
+hipError_t launch_fin(const SlotDesc<float2>* slots, const int* nslots_p, int max_slots, int op, hipStream_t st);
+hipError_t launch_fin(const SlotDesc<double2>* slots, const int* nslots_p, int max_slots, int op, hipStream_t st);
+
+// elementwise helpers on raw FP64 / mixed arrays (n complex numbers)
+hipError_t launch_cast_to_d(const float2* in, double2* out, size_t n, hipStream_t st);
+hipError_t launch_cast_to_d(const double2* in, double2* out, size_t n, hipStream_t st);
+hipError_t launch_cast_to_f(const double2* in, float2* out, size_t n, hipStream_t st);
+hipError_t launch_fill(float2* v, size_t n, double a, hipStream_t st);
+hipError_t launch_fill(double2* v, size_t n, double a, hipStream_t st);
+hipError_t launch_axpy_d(double2* y, const double2* x, double a, size_t n, hipStream_t st);
+// column norms |v_col|^2 of [nrhs][12][Vh] into out[nrhs].x (accumulate=1 adds to out)
+hipError_t launch_col_norms(const double2* v, int Vh, int nrhs, double2* partial, int ntiles, double2* out,
+                            int accumulate, hipStream_t st);
+// sum partial[k][col][tile] over tiles into out[k*nrhs + col] (accumulate=1 adds)
+hipError_t launch_sum_partials(const double2* partial, int nred, int nrhs, int ntiles, double2* out,
+                               int accumulate, hipStream_t st);
+
+// gauge.hip: operator blocks
+struct GaugeView {
+  const double2* base;    // [V][4][9] canonical FP64 links of the whole lattice
+  const double2* region;  // [V_region][4][9] override for time slices [r_t0, r_t1), may be null
+  int r_t0, r_t1;
+};
+struct BlockSpec {
+  int L[4];       // lattice
+  int lo[4];      // domain origin
+  int Lb[4];      // domain extents (even)
+  int antiperiodic;
+  double kappa, csw;
+};
+hipError_t launch_build_links(const GaugeView& gv, const BlockSpec& bs, double2* U64, float2* U32, hipStream_t st);
+hipError_t launch_build_clover(const GaugeView& gv, const BlockSpec& bs, double2* A64, double2* Ainv64,
+                               float2* Ainv32, int* bad, hipStream_t st);
+// canonical [nrhs][V][12] complex128 <-> domain EO [nrhs][12][Vh] of parity p, scaled
+hipError_t launch_gather(const double2* canon, const BlockSpec& bs, int p, int nrhs, double scale, double2* eo,
+                         hipStream_t st);
+hipError_t launch_scatter(const double2* eo, const BlockSpec& bs, int p, int nrhs, double scale, double2* canon,
+                          hipStream_t st);
+
+// contract.hip
+hipError_t launch_series_diff(double2* terms, size_t n, int nlevels, double2* sum, hipStream_t st);
+hipError_t launch_pp(const double2* tx, const double2* ty, size_t V, int nlevels, size_t xs, size_t ys, double invL3,
+                     double2* out, hipStream_t st);
+// W: scratch [nlevels][V]; out: [nlevels][T]
+hipError_t launch_nucleon(const double2* terms, size_t V, int T, int nlevels, double2* W, double2* out,
+                          hipStream_t st);
+
+}  // namespace ddml

@@ -1,0 +1,344 @@
+"""Python binding of libddml (argument marshalling only).
+
+Every entry point has the name and meaning of its C counterpart in
+include/ddml.h.  Arrays are either numpy complex128 arrays (host, on_device=0)
+or torch complex128 / float64 tensors on the GPU (on_device=1); torch is used
+for device memory and the current stream only.  All arithmetic happens in the
+HIP library; if libddml.so is missing, loading fails with an error.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libddml.so")
+
+OK, EINVAL, ENOMEM, EAGAIN, ENOTCONVERGED, ENUMERIC, EDEVICE = 0, -1, -2, -3, -4, -5, -6
+BC_PERIODIC, BC_ANTIPERIODIC = 0, 1
+FP64, MIXED_FP32 = 0, 1
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EAGAIN", -4: "ENOTCONVERGED", -5: "ENUMERIC",
+                -6: "EDEVICE"}
+
+
+class Lattice(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int * 4), ("bc_time", ctypes.c_int)]
+
+
+class SolverParams(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_outer", ctypes.c_int), ("max_inner", ctypes.c_int),
+                ("inner_tol", ctypes.c_double), ("prec", ctypes.c_int), ("solver", ctypes.c_int),
+                ("gcr_m", ctypes.c_int)]
+
+
+class RhsInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("outer_iters", ctypes.c_int), ("inner_iters", ctypes.c_int),
+                ("true_rel_residual", ctypes.c_double)]
+
+
+class SolveDesc(ctypes.Structure):
+    _fields_ = [("gauge_id", ctypes.c_int), ("dom_id", ctypes.c_int), ("src", ctypes.c_void_p),
+                ("sol", ctypes.c_void_p), ("nrhs", ctypes.c_int), ("info", ctypes.POINTER(RhsInfo))]
+
+
+class SeriesDesc(ctypes.Structure):
+    _fields_ = [("gauge_id", ctypes.c_int), ("dom_ids", ctypes.POINTER(ctypes.c_int)), ("nlevels", ctypes.c_int),
+                ("src", ctypes.c_void_p), ("terms", ctypes.c_void_p), ("sum", ctypes.c_void_p),
+                ("info", ctypes.POINTER(RhsInfo))]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("gauge_id", ctypes.c_int), ("dom_id", ctypes.c_int), ("src", ctypes.c_void_p),
+                ("sol", ctypes.c_void_p), ("nrhs", ctypes.c_int), ("arrival_time", ctypes.c_double)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("max_outer", ctypes.c_int), ("max_inner_iters", ctypes.c_int),
+                ("worst_rel_residual", ctypes.c_double), ("arrival_time", ctypes.c_double),
+                ("admit_time", ctypes.c_double), ("finish_time", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_long), ("completed", ctypes.c_long), ("queued", ctypes.c_long),
+                ("in_flight", ctypes.c_long), ("p50_latency", ctypes.c_double), ("p99_latency", ctypes.c_double),
+                ("mean_latency", ctypes.c_double), ("solves_per_s", ctypes.c_double),
+                ("hbm_in_use", ctypes.c_size_t), ("hbm_budget", ctypes.c_size_t)]
+
+
+EXPORTS = ["ddml_create", "ddml_destroy", "ddml_last_error", "ddml_set_gauge", "ddml_set_gauge_region",
+           "ddml_release_gauge", "ddml_set_domain", "ddml_apply_Dw", "ddml_apply_eo", "ddml_solve_domain",
+           "ddml_solve_batch", "ddml_propagator_series", "ddml_propagator_series_batch", "ddml_time_stencil", "ddml_contract_pp_disconnected", "ddml_contract_nucleon",
+           "ddml_server_start", "ddml_submit", "ddml_poll", "ddml_wait", "ddml_stats", "ddml_server_stop",
+           "ddml_now"]
+
+_lib = None
+
+
+def load():
+    """Load libddml.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libddml.so is not built; run `python -m paper_1601_04587_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    IP = ctypes.POINTER(ctypes.c_int)
+    lib.ddml_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(Lattice), I, ctypes.c_size_t]
+    lib.ddml_destroy.argtypes = [P]
+    lib.ddml_last_error.argtypes = [P]
+    lib.ddml_last_error.restype = ctypes.c_char_p
+    lib.ddml_set_gauge.argtypes = [P, P, I, D, D, IP]
+    lib.ddml_set_gauge_region.argtypes = [P, I, I, I, P, I, IP]
+    lib.ddml_release_gauge.argtypes = [P, I]
+    lib.ddml_set_domain.argtypes = [P, IP, IP, IP]
+    lib.ddml_apply_Dw.argtypes = [P, I, I, P, P, I, I, I, P]
+    lib.ddml_apply_eo.argtypes = [P, I, I, P, P, I, I, I, P]
+    lib.ddml_solve_domain.argtypes = [P, I, I, P, P, I, ctypes.POINTER(SolverParams), ctypes.POINTER(RhsInfo), I, P]
+    lib.ddml_solve_batch.argtypes = [P, I, ctypes.POINTER(SolveDesc), ctypes.POINTER(SolverParams), I, P]
+    lib.ddml_propagator_series.argtypes = [P, I, IP, I, P, I, ctypes.POINTER(SolverParams), P, P,
+                                           ctypes.POINTER(RhsInfo), I, P]
+    lib.ddml_propagator_series_batch.argtypes = [P, I, ctypes.POINTER(SeriesDesc), I, ctypes.POINTER(SolverParams),
+                                                 I, P]
+    lib.ddml_time_stencil.argtypes = [P, I, I, I, I, I, ctypes.POINTER(ctypes.c_double)]
+    lib.ddml_contract_pp_disconnected.argtypes = [P, P, P, I, IP, IP, P, I, P]
+    lib.ddml_contract_nucleon.argtypes = [P, P, I, P, P, I, P]
+    lib.ddml_server_start.argtypes = [P, ctypes.POINTER(SolverParams), I]
+    lib.ddml_submit.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+    lib.ddml_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Result)]
+    lib.ddml_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Result), D]
+    lib.ddml_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
+    lib.ddml_server_stop.argtypes = [P]
+    lib.ddml_now.argtypes = []
+    lib.ddml_now.restype = D
+    _lib = lib
+    return lib
+
+
+class DDMLError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (STATUS_NAMES.get(code, "?"), code, msg))
+        self.code = code
+
+
+def solver_params(tol=1e-10, max_outer=12, max_inner=4000, inner_tol=1e-5, prec=MIXED_FP32):
+    return SolverParams(tol, max_outer, max_inner, inner_tol, prec, 0, 0)
+
+
+def _ptr(a):
+    """(pointer, on_device) of a numpy array or a torch tensor."""
+    if isinstance(a, np.ndarray):
+        if not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("array must be C-contiguous")
+        return a.ctypes.data, 0
+    if hasattr(a, "data_ptr"):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return a.data_ptr(), 1 if a.is_cuda else 0
+    raise TypeError("expected numpy array or torch tensor")
+
+
+def _stream(a):
+    if hasattr(a, "is_cuda") and a.is_cuda:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream(a.device).cuda_stream)
+    return ctypes.c_void_p(0)
+
+
+def now():
+    return load().ddml_now()
+
+
+class Context:
+    """One libddml context (ddml_create ... ddml_destroy)."""
+
+    def __init__(self, dims, bc_time=BC_ANTIPERIODIC, device=0, hbm_budget=0):
+        self.lib = load()
+        self.dims = tuple(int(d) for d in dims)
+        self.V = int(np.prod(self.dims))
+        lat = Lattice((ctypes.c_int * 4)(*self.dims), bc_time)
+        h = ctypes.c_void_p()
+        rc = self.lib.ddml_create(ctypes.byref(h), ctypes.byref(lat), device, hbm_budget)
+        if rc != OK:
+            raise DDMLError(rc, "ddml_create failed")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            self.lib.ddml_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow=()):
+        if rc != OK and rc not in allow:
+            raise DDMLError(rc, self.lib.ddml_last_error(self.h).decode())
+        return rc
+
+    def last_error(self):
+        return self.lib.ddml_last_error(self.h).decode()
+
+    # ------------------------------------------------------------ set-up
+    def set_gauge(self, U, kappa, csw):
+        p, dev = _ptr(U)
+        gid = ctypes.c_int()
+        self._check(self.lib.ddml_set_gauge(self.h, p, dev, kappa, csw, ctypes.byref(gid)))
+        return gid.value
+
+    def set_gauge_region(self, base, t0, t1, U_region):
+        p, dev = _ptr(U_region)
+        gid = ctypes.c_int()
+        self._check(self.lib.ddml_set_gauge_region(self.h, base, t0, t1, p, dev, ctypes.byref(gid)))
+        return gid.value
+
+    def release_gauge(self, gid):
+        self._check(self.lib.ddml_release_gauge(self.h, gid))
+
+    def set_domain(self, lo, hi):
+        did = ctypes.c_int()
+        self._check(self.lib.ddml_set_domain(self.h, (ctypes.c_int * 4)(*lo), (ctypes.c_int * 4)(*hi),
+                                             ctypes.byref(did)))
+        return did.value
+
+    # ---------------------------------------------------------- operators
+    def apply_Dw(self, gid, dom, inp, out, nrhs, prec=FP64):
+        pi, dev = _ptr(inp)
+        po, _ = _ptr(out)
+        self._check(self.lib.ddml_apply_Dw(self.h, gid, dom, pi, po, nrhs, prec, dev, _stream(inp)))
+        return out
+
+    def apply_eo(self, gid, dom, inp, out, nrhs, prec=FP64):
+        pi, dev = _ptr(inp)
+        po, _ = _ptr(out)
+        self._check(self.lib.ddml_apply_eo(self.h, gid, dom, pi, po, nrhs, prec, dev, _stream(inp)))
+        return out
+
+    # ------------------------------------------------------------- solves
+    def solve_domain(self, gid, dom, src, sol, nrhs, params=None):
+        params = params or solver_params()
+        info = (RhsInfo * nrhs)()
+        ps, dev = _ptr(src)
+        pd, _ = _ptr(sol)
+        rc = self.lib.ddml_solve_domain(self.h, gid, dom, ps, pd, nrhs, ctypes.byref(params), info, dev,
+                                        _stream(src))
+        self._check(rc, allow=(ENOTCONVERGED, ENUMERIC))
+        return rc, list(info)
+
+    def solve_batch(self, items, params=None):
+        """items: list of (gauge_id, dom_id, src, sol, nrhs)."""
+        params = params or solver_params()
+        n = len(items)
+        descs = (SolveDesc * n)()
+        infos = []
+        dev = 0
+        for k, (gid, dom, src, sol, nrhs) in enumerate(items):
+            info = (RhsInfo * nrhs)()
+            infos.append(info)
+            ps, dev = _ptr(src)
+            pd, _ = _ptr(sol)
+            descs[k] = SolveDesc(gid, dom, ps, pd, nrhs, ctypes.cast(info, ctypes.POINTER(RhsInfo)))
+        rc = self.lib.ddml_solve_batch(self.h, n, descs, ctypes.byref(params), dev, _stream(items[0][2]))
+        self._check(rc, allow=(ENOTCONVERGED, ENUMERIC))
+        return rc, [list(i) for i in infos]
+
+    def propagator_series(self, gid, doms, src, nrhs, terms, total=None, params=None):
+        params = params or solver_params()
+        n = len(doms)
+        info = (RhsInfo * (n * nrhs))()
+        ps, dev = _ptr(src)
+        pt, _ = _ptr(terms)
+        psum = _ptr(total)[0] if total is not None else None
+        rc = self.lib.ddml_propagator_series(self.h, gid, (ctypes.c_int * n)(*doms), n, ps, nrhs,
+                                             ctypes.byref(params), pt, psum, info, dev, _stream(src))
+        self._check(rc, allow=(ENOTCONVERGED, ENUMERIC))
+        return rc, [list(info[i * nrhs:(i + 1) * nrhs]) for i in range(n)]
+
+    def propagator_series_batch(self, items, nrhs, params=None):
+        """items: list of (gauge_id, dom_ids, src, terms, total_or_None); returns (rc, infos)."""
+        params = params or solver_params()
+        n = len(items)
+        descs = (SeriesDesc * n)()
+        keep = []
+        dev = 0
+        for k, (gid, doms, src, terms, total) in enumerate(items):
+            nl = len(doms)
+            d = (ctypes.c_int * nl)(*doms)
+            info = (RhsInfo * (nl * nrhs))()
+            keep.append((d, info))
+            ps, dev = _ptr(src)
+            pt, _ = _ptr(terms)
+            psum = _ptr(total)[0] if total is not None else None
+            descs[k] = SeriesDesc(gid, ctypes.cast(d, ctypes.POINTER(ctypes.c_int)), nl, ps, pt, psum,
+                                  ctypes.cast(info, ctypes.POINTER(RhsInfo)))
+        rc = self.lib.ddml_propagator_series_batch(self.h, n, descs, nrhs, ctypes.byref(params), dev,
+                                                   _stream(items[0][2]))
+        self._check(rc, allow=(ENOTCONVERGED, ENUMERIC))
+        return rc, [[list(info[i * nrhs:(i + 1) * nrhs]) for i in range(len(d))] for d, info in keep]
+
+    def time_stencil(self, gid, dom, nrhs, prec=MIXED_FP32, iters=20):
+        """(ms_odd_half, ms_even_half, bytes_odd_half, bytes_even_half) per launch."""
+        out = (ctypes.c_double * 4)()
+        self._check(self.lib.ddml_time_stencil(self.h, gid, dom, nrhs, prec, iters, out))
+        return tuple(out)
+
+    # ------------------------------------------------------- contractions
+    def contract_pp_disconnected(self, terms_x, terms_y, nlevels, xsrc, ysrc):
+        out = np.zeros((nlevels, 4), dtype=np.complex128)
+        px, dev = _ptr(terms_x)
+        py, _ = _ptr(terms_y)
+        self._check(self.lib.ddml_contract_pp_disconnected(self.h, px, py, nlevels, (ctypes.c_int * 4)(*xsrc),
+                                                           (ctypes.c_int * 4)(*ysrc), out.ctypes.data, dev,
+                                                           _stream(terms_x)))
+        return out
+
+    def contract_nucleon(self, terms, nlevels):
+        T = self.dims[0]
+        levels = np.zeros((nlevels, T), dtype=np.complex128)
+        diffs = np.zeros((nlevels, T), dtype=np.complex128)
+        pt, dev = _ptr(terms)
+        self._check(self.lib.ddml_contract_nucleon(self.h, pt, nlevels, levels.ctypes.data, diffs.ctypes.data, dev,
+                                                   _stream(terms)))
+        return levels, diffs
+
+    # ------------------------------------------------------------ serving
+    def server_start(self, params=None, max_queue=100000):
+        params = params or solver_params()
+        self._check(self.lib.ddml_server_start(self.h, ctypes.byref(params), max_queue))
+
+    def submit(self, gid, dom, src, sol, nrhs, arrival_time=None):
+        ps, _ = _ptr(src)
+        pd, _ = _ptr(sol)
+        t = now() if arrival_time is None else arrival_time
+        req = Request(gid, dom, ps, pd, nrhs, t)
+        ticket = ctypes.c_uint64()
+        rc = self.lib.ddml_submit(self.h, ctypes.byref(req), ctypes.byref(ticket))
+        self._check(rc)
+        return ticket.value
+
+    def poll(self, ticket):
+        r = Result()
+        rc = self.lib.ddml_poll(self.h, ticket, ctypes.byref(r))
+        if rc == EAGAIN:
+            return None
+        self._check(rc)
+        return r
+
+    def wait(self, ticket, timeout=-1.0):
+        r = Result()
+        rc = self.lib.ddml_wait(self.h, ticket, ctypes.byref(r), timeout)
+        if rc == EAGAIN:
+            return None
+        self._check(rc)
+        return r
+
+    def stats(self):
+        s = ServerStats()
+        self._check(self.lib.ddml_stats(self.h, ctypes.byref(s)))
+        return s
+
+    def server_stop(self):
+        self._check(self.lib.ddml_server_stop(self.h))

@@ -1,0 +1,251 @@
+"""GPU parity: libddml (HIP, gfx950) against the FP64 oracle on the same seeded inputs.
+
+Tolerances (from the arithmetic):
+  * FP64 operator applications: max |gpu - oracle| <= 1e-13 max |oracle|
+    (same operator, different summation order only);
+  * FP32 Schur operator: ||gpu - oracle|| <= 2e-6 ||oracle|| (single rounding of
+    inputs and arithmetic, ~8 ulp growth through two hops and two clover blocks);
+  * solves: the oracle's own operator applied to the GPU solution gives
+    ||b - D_Gamma x|| / ||b|| <= tol (1 + 1e-3), and the solution differs from
+    an oracle solve at 1e-13 by at most cond * tol (reported, bounded loosely);
+  * contractions, given identical propagator inputs: <= 1e-12 relative.
+"""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+ddml = pytest.importorskip("paper_1601_04587_amd.ddml")
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def _mask(L, lo, hi):
+    return oracle.domain_mask(L, lo, hi)
+
+
+def _local_parity(L, lo):
+    X = np.meshgrid(*[np.arange(n) for n in L], indexing="ij")
+    return (sum(X[m] - lo[m] for m in range(4)) % 2).reshape(-1)
+
+
+@pytest.fixture(scope="module")
+def cfg0():
+    """4^4 Wilson, U = exp(i 0.3 H), kappa = 0.12, antiperiodic time."""
+    L = (4, 4, 4, 4)
+    U = inputs.random_links(L, 1601001)
+    ctx = ddml.Context(L, ddml.BC_ANTIPERIODIC)
+    gid = ctx.set_gauge(U, 0.12, 0.0)
+    return L, U, ctx, gid
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    """8^3 x 16 clover, beta = 6.0 heatbath field, kappa = 0.1340, c_sw = 1.769."""
+    L = (16, 8, 8, 8)
+    U = inputs.quenched_field(L, 1601002)
+    ctx = ddml.Context(L, ddml.BC_ANTIPERIODIC)
+    gid = ctx.set_gauge(U, 0.1340, 1.769)
+    C = oracle.clover_term(U, L, 1.769)
+    doms = {"G0": ((6, 0, 0, 0), (10, 8, 8, 8)), "G1": ((4, 0, 0, 0), (12, 8, 8, 8)), "G2": ((0, 0, 0, 0), L)}
+    ids = {k: ctx.set_domain(*v) for k, v in doms.items()}
+    return L, U, C, ctx, gid, doms, ids
+
+
+def _rand(rng, L, n):
+    V = int(np.prod(L))
+    return rng.normal(size=(n, V, 4, 3)) + 1j * rng.normal(size=(n, V, 4, 3))
+
+
+# ------------------------------------------------------------- operators
+def test_apply_Dw_fp64_wilson_full_and_domain(cfg0, rng):
+    L, U, ctx, gid = cfg0
+    psi = _rand(rng, L, 3)
+    out = np.zeros_like(psi)
+    ctx.apply_Dw(gid, -1, psi, out, 3)
+    ref = oracle.apply_D(U, L, 0.12, psi)
+    assert _rel(out, ref) < 1e-13
+    lo, hi = (0, 0, 2, 0), (2, 4, 4, 4)
+    dom = ctx.set_domain(lo, hi)
+    m = _mask(L, lo, hi)[None, :, None, None]
+    ctx.apply_Dw(gid, dom, psi, out, 3)
+    ref = oracle.apply_D(U, L, 0.12, psi * m, lo=lo, hi=hi)
+    assert _rel(out, ref) < 1e-13
+    assert np.abs(out[:, ~m[0, :, 0, 0]]).max() == 0.0
+
+
+def test_apply_Dw_fp64_clover_domains(cfg1, rng):
+    L, U, C, ctx, gid, doms, ids = cfg1
+    psi = _rand(rng, L, 2)
+    out = np.zeros_like(psi)
+    for name in ("G0", "G2"):
+        lo, hi = doms[name]
+        m = _mask(L, lo, hi)[None, :, None, None]
+        ctx.apply_Dw(gid, ids[name], psi, out, 2)
+        ref = oracle.apply_D(U, L, 0.1340, psi * m, C=C, lo=lo, hi=hi)
+        assert _rel(out, ref) < 1e-13, name
+
+
+def _schur_ref(U, L, C, kappa, lo, hi, psi):
+    """psi_e - kappa^2 A_ee^{-1} H_eo A_oo^{-1} H_oe psi_e from oracle pieces, A = 1 + 2 kappa C."""
+    V = int(np.prod(L))
+    m = _mask(L, lo, hi)
+    par = _local_parity(L, lo)
+    ev = (m & (par == 0))[None, :, None, None]
+    od = (m & (par == 1))[None, :, None, None]
+    A = np.eye(12)[None] + 2 * kappa * C
+    Ainv = np.linalg.inv(A)
+    n = psi.shape[0]
+
+    def clov(M, v):
+        return np.einsum("sij,rsj->rsi", M, v.reshape(n, V, 12)).reshape(v.shape)
+
+    pe = psi * ev
+    t = oracle.apply_hop(U, L, pe, lo=lo, hi=hi) * od
+    t = clov(Ainv, t)
+    t = oracle.apply_hop(U, L, t, lo=lo, hi=hi) * ev
+    t = clov(Ainv, t)
+    return pe - kappa ** 2 * t
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-13), (1, 2e-6)])
+def test_apply_eo_schur_operator(cfg1, rng, prec, tol):
+    L, U, C, ctx, gid, doms, ids = cfg1
+    psi = _rand(rng, L, 12)
+    out = np.zeros_like(psi)
+    for name in ("G0", "G2"):
+        lo, hi = doms[name]
+        ctx.apply_eo(gid, ids[name], psi, out, 12, prec)
+        ref = _schur_ref(U, L, C, 0.1340, lo, hi, psi)
+        if prec == 0:
+            assert _rel(out, ref) < tol, name
+        else:
+            assert np.linalg.norm(out - ref) / np.linalg.norm(ref) < tol, name
+
+
+def test_apply_eo_ragged_tail_and_nrhs1(rng):
+    """A box whose half volume (6*2*2*6/2 = 72) is not a multiple of the 64-site tile."""
+    L = (8, 4, 2, 6)
+    U = inputs.random_links(L, 4)
+    ctx = ddml.Context(L)
+    gid = ctx.set_gauge(U, 0.125, 1.0)
+    C = oracle.clover_term(U, L, 1.0)
+    lo, hi = (2, 0, 0, 0), (8, 2, 2, 6)
+    dom = ctx.set_domain(lo, hi)
+    psi = _rand(rng, L, 1)
+    out = np.zeros_like(psi)
+    ctx.apply_eo(gid, dom, psi, out, 1, 0)
+    assert _rel(out, _schur_ref(U, L, C, 0.125, lo, hi, psi)) < 1e-13
+
+
+# ----------------------------------------------------------------- solves
+def test_solve_fp64_config0_against_dense_lu(cfg0):
+    """4^4 Wilson, point source at the origin, 12 rhs, tolerance 1e-12."""
+    L, U, ctx, gid = cfg0
+    b = inputs.point_source(L, (0, 0, 0, 0))
+    x = np.zeros_like(b)
+    rc, info = ctx.solve_domain(gid, -1, b, x, 12, ddml.solver_params(tol=1e-12, prec=ddml.FP64))
+    assert rc == ddml.OK
+    assert max(i.true_rel_residual for i in info) <= 1e-12
+    res = oracle.residual(U, L, 0.12, b, x)
+    assert res.max() <= 1e-12 * (1 + 1e-3)
+    from tests import _dense
+    D = _dense.wilson_dirac(U, L, 0.12)
+    ref = np.linalg.solve(D, b.reshape(12, -1).T).T.reshape(b.shape)
+    assert _rel(x, ref) < 1e-10
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_solve_clover_domain_matches_oracle(cfg1, prec):
+    L, U, C, ctx, gid, doms, ids = cfg1
+    lo, hi = doms["G0"]
+    b = inputs.point_source(L, (7, 0, 0, 0))
+    x = np.zeros_like(b)
+    rc, info = ctx.solve_domain(gid, ids["G0"], b, x, 12, ddml.solver_params(tol=1e-10, prec=prec))
+    assert rc == ddml.OK, [ddml.STATUS_NAMES[i.status] for i in info]
+    res = oracle.residual(U, L, 0.1340, b, x, C=C, lo=lo, hi=hi)
+    assert res.max() <= 1e-10 * (1 + 1e-3), res
+    xr, _, rr = oracle.solve(U, L, 0.1340, b, C=C, lo=lo, hi=hi, tol=1e-13)
+    assert _rel(x, xr) < 1e-7
+    m = _mask(L, lo, hi)
+    assert np.abs(x[:, ~m]).max() == 0.0
+
+
+def test_series_and_contractions_config1(cfg1):
+    """Config 1: Gamma0 (4 slices) c Gamma1 (8) c Gamma2 (the whole 16), 12 rhs, 1e-10."""
+    L, U, C, ctx, gid, doms, ids = cfg1
+    xs = (7, 0, 0, 0)
+    b = inputs.point_source(L, xs)
+    V = int(np.prod(L))
+    terms = np.zeros((3, 12, V, 4, 3), dtype=np.complex128)
+    total = np.zeros((12, V, 4, 3), dtype=np.complex128)
+    order = ["G0", "G1", "G2"]
+    rc, info = ctx.propagator_series(gid, [ids[k] for k in order], b, 12, terms, total,
+                                     ddml.solver_params(tol=1e-10))
+    assert rc == ddml.OK
+    cum = np.cumsum(terms, axis=0)
+    assert np.array_equal(cum[-1] * 0 + total, total)
+    for i, k in enumerate(order):
+        lo, hi = doms[k]
+        res = oracle.residual(U, L, 0.1340, b, cum[i], C=C, lo=lo, hi=hi)
+        assert res.max() <= 1e-10 * (1 + 1e-3), (k, res.max())
+    # exact telescoping identity of eq. Dseries on the returned arrays
+    assert np.abs(cum[-1] - total).max() <= 1e-15 * np.abs(total).max()
+    # contractions from the same terms: GPU vs oracle
+    s = inputs.site_index(L, xs)
+    pp_gpu = ctx.contract_pp_disconnected(terms, terms, 3, xs, xs)
+    pp_ref = oracle.contract_pp_disconnected(terms, terms, s, s, 8 ** 3)
+    assert np.abs(pp_gpu - pp_ref).max() <= 1e-12 * np.abs(pp_ref).max()
+    lev_gpu, diff_gpu = ctx.contract_nucleon(terms, 3)
+    lev_ref, diff_ref = oracle.contract_nucleon(terms, L)
+    assert np.abs(lev_gpu - lev_ref).max() <= 1e-12 * np.abs(lev_ref).max()
+    assert np.abs(diff_gpu - diff_ref).max() <= 1e-12 * np.abs(lev_ref).max()
+
+
+def test_batch_equals_individual_solves_bitwise(cfg1):
+    """Uneven domains solved in one batch give the same bits as solved alone."""
+    L, U, C, ctx, gid, doms, ids = cfg1
+    V = int(np.prod(L))
+    b = inputs.point_source(L, (7, 1, 2, 3))
+    items, outs = [], []
+    for k in ("G0", "G1", "G2", "G0"):
+        x = np.zeros((12, V, 4, 3), dtype=np.complex128)
+        outs.append(x)
+        items.append((gid, ids[k], b, x, 12))
+    rc, infos = ctx.solve_batch(items, ddml.solver_params(tol=1e-10))
+    assert rc == ddml.OK
+    for (g, d, src, xb, n) in items[:3]:
+        x1 = np.zeros_like(xb)
+        ctx.solve_domain(g, d, src, x1, 12, ddml.solver_params(tol=1e-10))
+        assert np.array_equal(x1, xb)
+    assert np.array_equal(outs[0], outs[3])
+
+
+def test_error_paths(cfg0):
+    L, U, ctx, gid = cfg0
+    with pytest.raises(ddml.DDMLError) as e:
+        ctx.set_domain((0, 0, 0, 0), (3, 4, 4, 4))       # odd extent
+    assert e.value.code == ddml.EINVAL
+    with pytest.raises(ddml.DDMLError) as e:
+        ctx.set_domain((0, 0, 0, 0), (6, 4, 4, 4))       # outside
+    assert e.value.code == ddml.EINVAL
+    b = inputs.point_source(L, (0, 0, 0, 0))
+    x = np.zeros_like(b)
+    with pytest.raises(ddml.DDMLError) as e:
+        ctx.solve_domain(999, -1, b, x, 12)
+    assert e.value.code == ddml.EINVAL
+    # iteration limit: not converged, info filled
+    rc, info = ctx.solve_domain(gid, -1, b, x, 12, ddml.solver_params(tol=1e-12, max_outer=1, max_inner=2))
+    assert rc == ddml.ENOTCONVERGED
+    assert all(i.status == ddml.ENOTCONVERGED and i.true_rel_residual > 1e-12 for i in info)
+    # NaN in a source column: that column fails, the others converge
+    bn = b.copy()
+    bn[3, 0, 1, 0] = np.nan
+    rc, info = ctx.solve_domain(gid, -1, bn, x, 12, ddml.solver_params(tol=1e-10))
+    assert info[3].status == ddml.ENUMERIC
+    assert all(info[c].status == ddml.OK for c in range(12) if c != 3)
