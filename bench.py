@@ -34,6 +34,26 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def counter_traffic(mode_key):
+    """HBM bytes per launch of a stencil kernel from the committed rocprofv3
+    counter summary, or None if the kernel source changed since it was taken."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "stencil_k_hop_batch_fp32_32x32x32x16_12rhs.md")
+    src = os.path.join(ROOT, "paper_1601_04587_amd", "csrc", "dirac.hip")
+    if not (os.path.exists(prof) and os.path.exists(src)):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    vals = {}
+    for line in open(prof):
+        if line.startswith("machine-readable: "):
+            k, v = line[len("machine-readable: "):].strip().split("=", 1)
+            vals[k] = v
+    if vals.get("dirac_hip_sha256") != sha:
+        return None
+    v = vals.get("traffic_bytes[%s]" % mode_key)
+    return float(v) if v else None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -47,11 +67,44 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=0.0, help="req/s (0: 0.7 x measured capacity)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--stencil-iters", type=int, default=20)
+    ap.add_argument("--stencil-only", action="store_true",
+                    help="only time the stencil kernels on the 32^3x16 slab domain (profiling runs); "
+                         "also runs one plain 1 GiB device copy as the reference for HBM counters")
     return ap.parse_args()
+
+
+def stencil_only(args):
+    """Stencil kernels alone on the Gamma2 slab domain, for rocprofv3 runs."""
+    import torch
+
+    import inputs
+    from paper_1601_04587_amd import ddml
+
+    L = tuple(int(v) for v in args.dims.split(","))
+    U = inputs.random_links(L, 1601004, 0.3)   # bandwidth does not depend on the link values
+    ctx = ddml.Context(L, ddml.BC_ANTIPERIODIC, device=0)
+    gid = ctx.set_gauge(U, 0.1340, 1.769)
+    dom = ctx.set_domain((0, 0, 0, 0), (16,) + L[1:])
+    s32 = ctx.time_stencil(gid, dom, 12, ddml.MIXED_FP32, args.stencil_iters)
+    log("stencil-only fp32: odd %.4f ms (%.3e B), even %.4f ms (%.3e B) -> even %.0f GB/s, odd %.0f GB/s"
+        % (s32[0], s32[2], s32[1], s32[3], s32[3] / s32[1] * 1e-6, s32[2] / s32[0] * 1e-6))
+    # plain copy of known size: the reference reading of the HBM byte counters
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0")   # 1 GiB
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    ctx.close()
+    print(json.dumps({"stencil_fp32": {"ms_odd": s32[0], "ms_even": s32[1], "bytes_odd": s32[2],
+                                       "bytes_even": s32[3]}, "copy_bytes_each_way": 1 << 30}), flush=True)
+    return 0
 
 
 def main():
     args = parse()
+    if args.stencil_only:
+        return stencil_only(args)
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs every domain solve on a single "
               "MI355X (no collectives); --gpus %d is not supported." % args.gpus, file=sys.stderr)
@@ -158,6 +211,7 @@ def main():
 
     # --------------------------------------------------- stencil roofline
     sten32 = ctx.time_stencil(gid0, doms[0][2], 12, ddml.MIXED_FP32, args.stencil_iters)
+    sten_R = 1
     sten64 = ctx.time_stencil(gid0, doms[0][2], 12, ddml.FP64, max(4, args.stencil_iters // 2))
     ach = sten32[3] / (sten32[1] * 1e-3)
     ach_odd = sten32[2] / (sten32[0] * 1e-3)
@@ -206,7 +260,7 @@ def main():
                                "Gamma0/1/2 = 4/8/16 slices x 12 rhs, tol 1e-10" % ("x".join(map(str, L)), nslab),
                    "lattice": list(L), "kappa": kappa, "csw": csw, "solves_per_step": 3 * nslab, "nrhs": 12},
         "roofline": {"bound": "hbm", "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                     "frac": ach / PEAK_HBM, "traffic": None,
+                     "frac": ach / PEAK_HBM, "traffic": counter_traffic("%d,1,1" % sten_R),
                      "kernel": "k_hop_batch<float2> even half-stencil (Schur + fused dot), 32^3x16 domain, 12 rhs",
                      "ms_per_launch": sten32[1], "bytes_per_launch": sten32[3],
                      "odd_half": {"ms": sten32[0], "GB/s": ach_odd / 1e9},
