@@ -212,8 +212,19 @@ int ddml_contract_nucleon(ddml_ctx ctx, const double* terms, int nlevels, double
  * H_oe in_e) and of the even half (out_e = in_e - kappa^2 A_ee^{-1} H_eo t_o
  * with the dot product (r0, out_e)); out[2], out[3]: algorithmic bytes of one
  * launch of each (every array the kernel must touch, counted once).
- * prec: DDML_FP64 or DDML_MIXED_FP32 (FP32 kernels).  Errors: EINVAL, ENOMEM. */
-int ddml_time_stencil(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec, int iters, double out[4]);
+ * prec: DDML_FP64 or DDML_MIXED_FP32 (FP32 kernels).  R (columns per thread,
+ * 1..3), order (0 linear, 1 XCD-banded tiles) and grid (workgroups) select the
+ * launch; values <= 0 (order < 0) take the context's current choice.
+ * Errors: EINVAL, ENOMEM. */
+int ddml_time_stencil(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec, int iters, int R, int order,
+                      int grid, double out[4]);
+
+/* Autotuner: times the stencil launch variants (R in 1..3, both tile orders,
+ * grid in {512, 1024, 2048}) on (gauge_id, dom_id, nrhs, prec) and makes the
+ * fastest the context's choice for every later solve (the captured solver
+ * graphs are rebuilt).  best[0..3] = R, order, grid, ms per odd+even pair.
+ * Errors: EINVAL, ENOMEM, EDEVICE. */
+int ddml_autotune(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec, double best[4]);
 
 /* ------------------------------------------------------------- serving */
 typedef struct {

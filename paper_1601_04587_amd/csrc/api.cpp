@@ -310,11 +310,21 @@ int ddml_propagator_series_batch(ddml_ctx ctx, int nseries, const ddml_series_de
   return guarded(ctx, [&](Ctx* c) { return series_many(c, nseries, descs, nrhs, params, on_device, stream); });
 }
 
-int ddml_time_stencil(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec, int iters, double out[4]) {
+int ddml_time_stencil(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec, int iters, int R, int order,
+                      int grid, double out[4]) {
   return guarded(ctx, [&](Ctx* c) {
     need(out != nullptr, "out is NULL");
     need(prec == DDML_FP64 || prec == DDML_MIXED_FP32, "unknown precision");
-    time_stencil(c, gauge_id, dom_id, nrhs, prec, iters, out);
+    time_stencil(c, gauge_id, dom_id, nrhs, prec, iters, R, order, grid, out);
+    return DDML_OK;
+  });
+}
+
+int ddml_autotune(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec, double best[4]) {
+  return guarded(ctx, [&](Ctx* c) {
+    need(best != nullptr, "best is NULL");
+    need(prec == DDML_FP64 || prec == DDML_MIXED_FP32, "unknown precision");
+    autotune(c, gauge_id, dom_id, nrhs, prec, best);
     return DDML_OK;
   });
 }

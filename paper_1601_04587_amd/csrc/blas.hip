@@ -46,72 +46,70 @@ __global__ void __launch_bounds__(768) k_vec(const SlotDesc<T2>* __restrict__ sl
     const int tile = vt - tile_start[s];
     const int i = tile * kTile + lane;
     const bool valid = i < d.g.Vh;
-    const size_t Vh = (size_t)d.g.Vh;
-    const size_t base = (size_t)col * 12 * Vh + i;
+    const size_t base = fidx(d.ntiles, col, 0, i);
     const BiState& st = d.st[col];
     double2 s0 = make_double2(0, 0), s1 = make_double2(0, 0);
     if (OP == VEC_P) {
       if (valid) {
         const T2 be = mk<T2>((T)st.beta.x, (T)st.beta.y), om = mk<T2>((T)st.omega.x, (T)st.omega.y);
-        T2* p = d.f[F_P];
-        const T2* r = d.f[F_R];
-        const T2* v = d.f[F_V];
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-          const size_t k = base + c * Vh;
-          p[k] = cadd(r[k], cmul(be, csub(p[k], cmul(om, v[k]))));
+        for (int k = 0; k < 6; ++k) {
+          const size_t o = base + 128 * k;
+          T2 p0, p1, r0, r1, v0, v1;
+          ld2(d.f[F_P] + o, p0, p1);
+          ld2(d.f[F_R] + o, r0, r1);
+          ld2(d.f[F_V] + o, v0, v1);
+          st2(d.f[F_P] + o, cadd(r0, cmul(be, csub(p0, cmul(om, v0)))), cadd(r1, cmul(be, csub(p1, cmul(om, v1)))));
         }
       }
     } else if (OP == VEC_S) {
-      if (valid) {
-        const T2 al = mk<T2>((T)st.alpha.x, (T)st.alpha.y);
-        T2* sv = d.f[F_S];
-        const T2* r = d.f[F_R];
-        const T2* v = d.f[F_V];
+      const T2 al = mk<T2>((T)st.alpha.x, (T)st.alpha.y);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-          const size_t k = base + c * Vh;
-          sv[k] = csub(r[k], cmul(al, v[k]));
+      for (int k = 0; k < 6; ++k) {
+        const size_t o = base + 128 * k;
+        T2 r0 = mk<T2>(0, 0), r1 = r0, v0 = r0, v1 = r0;
+        if (valid) {
+          ld2(d.f[F_R] + o, r0, r1);
+          ld2(d.f[F_V] + o, v0, v1);
         }
+        st2(d.f[F_S] + o, csub(r0, cmul(al, v0)), csub(r1, cmul(al, v1)));
       }
     } else if (OP == VEC_XR) {
       if (valid) {
         const T2 al = mk<T2>((T)st.alpha.x, (T)st.alpha.y), om = mk<T2>((T)st.omega.x, (T)st.omega.y);
-        T2* x = d.f[F_X];
-        T2* r = d.f[F_R];
-        const T2* p = d.f[F_P];
-        const T2* sv = d.f[F_S];
-        const T2* t = d.f[F_T];
-        const T2* rh = d.f[F_RH];
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-          const size_t k = base + c * Vh;
-          const T2 sk = sv[k];
-          x[k] = cadd(x[k], cadd(cmul(al, p[k]), cmul(om, sk)));
-          const T2 rn = csub(sk, cmul(om, t[k]));
-          r[k] = rn;
-          const T2 a = rh[k];
-          s0.x += (double)a.x * rn.x + (double)a.y * rn.y;
-          s0.y += (double)a.x * rn.y - (double)a.y * rn.x;
-          s1.x += (double)rn.x * rn.x + (double)rn.y * rn.y;
+        for (int k = 0; k < 6; ++k) {
+          const size_t o = base + 128 * k;
+          T2 x0, x1, p0, p1, s0v, s1v, t0, t1, h0, h1;
+          ld2(d.f[F_X] + o, x0, x1);
+          ld2(d.f[F_P] + o, p0, p1);
+          ld2(d.f[F_S] + o, s0v, s1v);
+          ld2(d.f[F_T] + o, t0, t1);
+          ld2(d.f[F_RH] + o, h0, h1);
+          st2(d.f[F_X] + o, cadd(x0, cadd(cmul(al, p0), cmul(om, s0v))), cadd(x1, cadd(cmul(al, p1), cmul(om, s1v))));
+          const T2 n0 = csub(s0v, cmul(om, t0)), n1 = csub(s1v, cmul(om, t1));
+          st2(d.f[F_R] + o, n0, n1);
+          s0.x += (double)h0.x * n0.x + (double)h0.y * n0.y + (double)h1.x * n1.x + (double)h1.y * n1.y;
+          s0.y += (double)h0.x * n0.y - (double)h0.y * n0.x + (double)h1.x * n1.y - (double)h1.y * n1.x;
+          s1.x += (double)n0.x * n0.x + (double)n0.y * n0.y + (double)n1.x * n1.x + (double)n1.y * n1.y;
         }
       }
-    } else {  // VEC_INIT: r = rh = (T) src64, x = p = v = 0
-      if (valid) {
+    } else {  // VEC_INIT: r = rh = (T) src64, x = p = v = 0 (padding sites: all zero)
+      const T2 z = mk<T2>(0, 0);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-          const size_t k = base + c * Vh;
-          const double2 b = d.src64[k];
-          const T2 bt = mk<T2>((T)b.x, (T)b.y);
-          d.f[F_R][k] = bt;
-          d.f[F_RH][k] = bt;
-          d.f[F_X][k] = mk<T2>(0, 0);
-          d.f[F_P][k] = mk<T2>(0, 0);
-          d.f[F_V][k] = mk<T2>(0, 0);
-          const double n2 = (double)bt.x * bt.x + (double)bt.y * bt.y;
-          s0.x += n2;
-          s1.x += n2;
-        }
+      for (int k = 0; k < 6; ++k) {
+        const size_t o = base + 128 * k;
+        double2 b0 = make_double2(0, 0), b1 = b0;
+        if (valid) ld2(d.src64 + o, b0, b1);
+        const T2 t0 = mk<T2>((T)b0.x, (T)b0.y), t1 = mk<T2>((T)b1.x, (T)b1.y);
+        st2(d.f[F_R] + o, t0, t1);
+        st2(d.f[F_RH] + o, t0, t1);
+        st2(d.f[F_X] + o, z, z);
+        st2(d.f[F_P] + o, z, z);
+        st2(d.f[F_V] + o, z, z);
+        const double n2 = (double)t0.x * t0.x + (double)t0.y * t0.y + (double)t1.x * t1.x + (double)t1.y * t1.y;
+        s0.x += n2;
+        s1.x += n2;
       }
     }
     if (OP == VEC_XR || OP == VEC_INIT) {
@@ -307,7 +305,7 @@ __global__ void k_col_norms(const double2* __restrict__ v, int Vh, int nrhs, dou
     double2 s = make_double2(0, 0);
     if (i < Vh) {
       for (int c = 0; c < 12; ++c) {
-        const double2 a = v[((size_t)col * 12 + c) * Vh + i];
+        const double2 a = v[fidx(ntiles, col, c, i)];
         s.x += a.x * a.x + a.y * a.y;
       }
     }

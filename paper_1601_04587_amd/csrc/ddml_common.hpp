@@ -9,12 +9,18 @@
 // Domain-local storage ("operator block").  A domain Gamma = [lo,hi) is stored
 // as its own box with even extents Lb[mu], sites split by local parity
 // (sum of local coordinates mod 2) and indexed by lex/2 inside each parity.
-// Every field is structure-of-arrays with the site index fastest:
-//   spinor field of one parity : T2 [nrhs][12][Vh]       (component = spin*3 + colour)
-//   links                      : T2 [2][4][9][Vh]        (U_mu(x) for x of each parity)
-//   clover A or A^{-1}         : T2 [2][36][Vh]          (two Hermitian 6x6 chiral blocks,
-//                                                        18 slots each: 3 packed diagonal pairs,
-//                                                        then the 15 upper elements row-major)
+// Every field is tile-blocked and pair-packed: sites come in tiles of 64 (one
+// wavefront); inside a tile, complex numbers are grouped in pairs and each
+// pair is a contiguous run of 64 sites x 2 values.  A lane then reads two
+// complex numbers with one 16-byte load (FP32) and a wavefront load is one
+// 1 KiB burst; the data of a tile sits in a few KiB instead of planes
+// megabytes apart (which alias in the L2 sets).
+//   spinor field of one parity : [nrhs][ntiles][6 pairs][64][2]  (component = spin*3 + colour)
+//   links                      : [2][ntiles][4 mu][5 pairs][64][2] (9 entries + 1 zero pad)
+//   clover A or A^{-1}         : [2][ntiles][18 pairs][64][2]   (two Hermitian 6x6 chiral blocks,
+//                                                              18 slots each: 3 packed diagonal
+//                                                              pairs, then the 15 upper elements)
+// ntiles = ceil(Vh/64); the padding sites of the last tile hold zeros.
 // Neighbours are taken with local periodic wrap-around.  Links that would leave
 // Gamma through a face that is not a full lattice extent are stored as zero, so
 // the Dirichlet restriction of eq. blkdec needs no branch in the stencil; the
@@ -55,7 +61,52 @@ struct BoxGeom {
   int L[4];     // box extents (all even)
   int Vh;       // sites per parity
   int half3;    // L[3]/2
+  int ntiles;   // ceil(Vh / 64)
 };
+
+// tile-blocked, pair-packed offsets (in complex numbers)
+constexpr int kSpinorSlots = 12;  // complex per site of a spinor
+constexpr int kLinkSlots = 40;    // complex per site of the 4 links (9 + 1 pad each)
+constexpr int kCloverSlots = 36;  // complex per site of the clover data
+__host__ __device__ __forceinline__ size_t fidx(int ntiles, int col, int c, int i) {
+  return ((size_t)(col * ntiles + (i >> 6)) * 6 + (c >> 1)) * 128 + (i & 63) * 2 + (c & 1);
+}
+__host__ __device__ __forceinline__ size_t lidx(int ntiles, int par, int mu, int k, int i) {
+  return ((size_t)(par * ntiles + (i >> 6)) * 20 + mu * 5 + (k >> 1)) * 128 + (i & 63) * 2 + (k & 1);
+}
+__host__ __device__ __forceinline__ size_t cidx(int ntiles, int par, int k, int i) {
+  return ((size_t)(par * ntiles + (i >> 6)) * 18 + (k >> 1)) * 128 + (i & 63) * 2 + (k & 1);
+}
+
+// Loads and stores of one pair through the global address space (so that the
+// compiler emits global_load/global_store rather than flat accesses).
+#define DDML_GLOBAL __attribute__((address_space(1)))
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void ld2(const float2* p, float2& a, float2& b) {
+  const f32x4 v = *(const DDML_GLOBAL f32x4*)p;
+  a = make_float2(v.x, v.y);
+  b = make_float2(v.z, v.w);
+}
+__device__ __forceinline__ void ld2(const double2* p, double2& a, double2& b) {
+  const DDML_GLOBAL f64x2* q = (const DDML_GLOBAL f64x2*)p;
+  const f64x2 u = q[0], v = q[1];
+  a = make_double2(u.x, u.y);
+  b = make_double2(v.x, v.y);
+}
+__device__ __forceinline__ int ldg(const int* p) { return *(const DDML_GLOBAL int*)p; }
+__device__ __forceinline__ void st2(float2* p, float2 a, float2 b) {
+  f32x4 v;
+  v.x = a.x; v.y = a.y; v.z = b.x; v.w = b.y;
+  *(DDML_GLOBAL f32x4*)p = v;
+}
+__device__ __forceinline__ void st2(double2* p, double2 a, double2 b) {
+  DDML_GLOBAL f64x2* q = (DDML_GLOBAL f64x2*)p;
+  f64x2 u, v;
+  u.x = a.x; u.y = a.y; v.x = b.x; v.y = b.y;
+  q[0] = u;
+  q[1] = v;
+}
 
 // local coordinates of EO index i of parity p
 __device__ __forceinline__ void eo_coords(const BoxGeom& g, int p, int i, int y[4]) {
@@ -75,9 +126,9 @@ __device__ __forceinline__ int eo_index(const BoxGeom& g, const int y[4]) {
 // application) with its own box, operator data and vectors.
 template <typename T2> struct HopItem {
   BoxGeom g;
-  const T2* U;        // links [2][4][9][Vh]
-  const T2* clov;     // clover data of the output parity [36][Vh] (A or A^{-1}), may be null
-  const T2* in;       // input field on the opposite parity [nrhs][12][Vh]
+  const T2* U;        // links [2][ntiles][4][9][64]
+  const T2* clov;     // clover data [2][ntiles][36][64] (A or A^{-1})
+  const T2* in;       // input field on the opposite parity [nrhs][ntiles][12][64]
   const T2* aux;      // field on the output parity, may be null
   const T2* red_a;    // first operand of a fused dot product, may be null
   T2* out;            // output field on the output parity
@@ -87,6 +138,7 @@ template <typename T2> struct HopItem {
   int nrhs;
   int ntiles;
   double c1, c2;
+  int tps;            // tiles per time slice (banded tile order), 0 = linear order
 };
 
 // Stencil epilogues (acc = H in on the output parity):
@@ -120,14 +172,23 @@ template <typename T2> struct SlotDesc {
   BoxGeom g;
   int nrhs;
   int ntiles;
+  int tps;              // tiles per time slice if a slice is a whole number of tiles, else 0
   double kappa;
-  const T2* U;          // links [2][4][9][Vh] in the inner precision
-  const T2* Ainv;       // A^{-1} [2][36][Vh] in the inner precision
-  T2* f[F_NUM];         // Krylov vectors [nrhs][12][Vh]
+  const T2* U;          // links in the inner precision
+  const T2* Ainv;       // A^{-1} in the inner precision
+  T2* f[F_NUM];         // Krylov vectors [nrhs][ntiles][12][64]
   double2* partial;     // [2][nrhs][ntiles]
   int* active;          // [nrhs]
   BiState* st;          // [nrhs]
-  const double2* src64; // FP64 even-parity right-hand side [nrhs][12][Vh]
+  const double2* src64; // FP64 even-parity right-hand side [nrhs][ntiles][12][64]
 };
+
+// Number of XCDs of the device and the tile order used by the stencil: with
+// TILE_ORDER_BANDED, workgroup b runs on XCD b % 8 and each XCD walks its own
+// band of every time slice, slice after slice, so the neighbours of a tile
+// (same slice, adjacent slices) are read through the same L2 shortly after
+// they were first fetched.
+constexpr int kXcd = 8;
+enum { TILE_ORDER_LINEAR = 0, TILE_ORDER_BANDED = 1 };
 
 }  // namespace ddml

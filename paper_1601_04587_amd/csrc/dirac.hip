@@ -9,10 +9,11 @@
 // spins are rebuilt; that halves the SU(3) work.
 //
 // One thread owns one site of the output parity and R right-hand sides; a
-// workgroup is 64 consecutive sites (one wavefront per group of R columns), so
-// the waves of one workgroup read the same links and clover data and hit in
-// L1/L2 instead of HBM.  Domain restriction comes from zeroed face links, so
-// the inner loop has no masking branch.
+// workgroup is one 64-site tile (one wavefront per group of R columns), so the
+// waves of one workgroup read the same links and clover data and hit in L1/L2
+// instead of HBM.  Domain restriction comes from zeroed face links, so the
+// inner loop has no masking branch.  Tiles are visited either linearly or in
+// XCD bands (see ddml_common.hpp) so that neighbour tiles share an L2.
 #include "ddml_common.hpp"
 #include "launchers.hpp"
 
@@ -97,11 +98,22 @@ __device__ __forceinline__ void su3_mul(const T2 u[9], bool dag, const T2 h[6], 
     }
 }
 
-// y = C x for one 6x6 Hermitian block stored in 18 slots (stride Vh)
+// 18 slots of one Hermitian 6x6 block (9 pairs, pair k at base + 128 k)
 template <typename T2>
-__device__ __forceinline__ void herm6_load(const T2* __restrict__ base, size_t Vh, int i, T2 m[18]) {
+__device__ __forceinline__ void herm6_load(const T2* __restrict__ base, T2 m[18]) {
 #pragma unroll
-  for (int k = 0; k < 18; ++k) m[k] = base[k * Vh + i];
+  for (int k = 0; k < 9; ++k) ld2(base + 128 * k, m[2 * k], m[2 * k + 1]);
+}
+// the 12 components of a spinor (6 pairs) starting at base
+template <typename T2>
+__device__ __forceinline__ void spinor_load(const T2* __restrict__ base, T2 v[12]) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) ld2(base + 128 * k, v[2 * k], v[2 * k + 1]);
+}
+template <typename T2>
+__device__ __forceinline__ void spinor_store(T2* __restrict__ base, const T2 v[12]) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) st2(base + 128 * k, v[2 * k], v[2 * k + 1]);
 }
 template <typename T2>
 __device__ __forceinline__ void herm6_apply(const T2 m[18], const T2 x[6], T2 y[6]) {
@@ -128,7 +140,7 @@ __device__ __forceinline__ void hop_sum(const BoxGeom& g, int p, int i, const T2
   int y[4];
   eo_coords(g, p, i, y);
   const int q = 1 - p;
-  const size_t Vh = (size_t)g.Vh;
+  const int nt = g.ntiles;
 #pragma unroll
   for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -142,18 +154,15 @@ __device__ __forceinline__ void hop_sum(const BoxGeom& g, int p, int i, const T2
       if (fwd) z[mu] = (y[mu] + 1 == g.L[mu]) ? 0 : y[mu] + 1;
       else z[mu] = (y[mu] == 0) ? g.L[mu] - 1 : y[mu] - 1;
       const int n = eo_index(g, z);
-      const T2* __restrict__ ul = fwd ? U + ((size_t)(p * 4 + mu) * 9) * Vh + i
-                                      : U + ((size_t)(q * 4 + mu) * 9) * Vh + n;
-      T2 u[9];
+      const T2* __restrict__ ul = fwd ? U + lidx(nt, p, mu, 0, i) : U + lidx(nt, q, mu, 0, n);
+      T2 u[10];
 #pragma unroll
-      for (int k = 0; k < 9; ++k) u[k] = ul[k * Vh];
+      for (int k = 0; k < 5; ++k) ld2(ul + 128 * k, u[2 * k], u[2 * k + 1]);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        if (r < nr && (act == nullptr || act[r0 + r])) {
-          const T2* __restrict__ src = in + (size_t)(r0 + r) * 12 * Vh + n;
+        if (r < nr && (act == nullptr || ldg(act + r0 + r))) {
           T2 psi[12], h[6], gg[6];
-#pragma unroll
-          for (int c = 0; c < 12; ++c) psi[c] = src[c * Vh];
+          spinor_load(in + fidx(nt, r0 + r, 0, n), psi);
           project(mu, fwd, psi, h);
           su3_mul(u, !fwd, h, gg);
           reconstruct(mu, fwd, gg, acc[r]);
@@ -163,7 +172,6 @@ __device__ __forceinline__ void hop_sum(const BoxGeom& g, int p, int i, const T2
   }
 }
 
-template <typename T2>
 __device__ __forceinline__ double2 wave_sum(double2 v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -173,45 +181,33 @@ __device__ __forceinline__ double2 wave_sum(double2 v) {
   return v;
 }
 
-// Epilogue on one column.  acc = (H in)(x).
+// Epilogue on one column.  acc = (H in)(x); cl points at slot 0 of this site.
 template <typename T2, int MODE>
-__device__ __forceinline__ void epilogue(const T2* __restrict__ cl, size_t Vh, int i, const T2 acc[12],
-                                         const T2 aux[12], const T2 ra[12], double c1, double c2, T2 out[12]) {
+__device__ __forceinline__ void epilogue(const T2* __restrict__ cl, const T2 acc[12], const T2 aux[12],
+                                         const T2 ra[12], double c1, double c2, T2 out[12]) {
   using T = decltype(T2::x);
   const T k1 = (T)c1, k2 = (T)c2;
-  if (MODE == MODE_CINV_HOP) {
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      T2 m[18];
-      herm6_load(cl + (size_t)b * 18 * Vh, Vh, i, m);
+  for (int b = 0; b < 2; ++b) {
+    T2 m[18];
+    herm6_load(cl + 128 * 9 * b, m);
+    if (MODE == MODE_CINV_HOP) {
       herm6_apply(m, acc + 6 * b, out + 6 * b);
-    }
-  } else if (MODE == MODE_SCHUR) {
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      T2 m[18], y[6];
-      herm6_load(cl + (size_t)b * 18 * Vh, Vh, i, m);
+    } else if (MODE == MODE_SCHUR) {
+      T2 y[6];
       herm6_apply(m, acc + 6 * b, y);
 #pragma unroll
       for (int c = 0; c < 6; ++c) out[6 * b + c] = csub(aux[6 * b + c], cscale(y[c], k1));
-    }
-  } else if (MODE == MODE_M || MODE == MODE_RES) {
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      T2 m[18], y[6];
-      herm6_load(cl + (size_t)b * 18 * Vh, Vh, i, m);
+    } else if (MODE == MODE_M || MODE == MODE_RES) {
+      T2 y[6];
       herm6_apply(m, aux + 6 * b, y);
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
         T2 v = csub(y[c], cscale(acc[6 * b + c], k1));
         out[6 * b + c] = (MODE == MODE_M) ? cscale(v, k2) : csub(ra[6 * b + c], v);
       }
-    }
-  } else {  // MODE_PREP: out = C (aux + c1 acc)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      T2 m[18], v[6];
-      herm6_load(cl + (size_t)b * 18 * Vh, Vh, i, m);
+    } else {  // MODE_PREP: out = C (aux + c1 acc)
+      T2 v[6];
 #pragma unroll
       for (int c = 0; c < 6; ++c) v[c] = cadd(aux[6 * b + c], cscale(acc[6 * b + c], k1));
       herm6_apply(m, v, out + 6 * b);
@@ -224,7 +220,7 @@ __device__ __forceinline__ void hop_tile(const BoxGeom g, const T2* __restrict__
                                          const T2* __restrict__ in, const T2* __restrict__ aux,
                                          const T2* __restrict__ red_a, T2* __restrict__ out,
                                          double2* __restrict__ partial, const int* __restrict__ act, int p,
-                                         int nrhs, int ntiles, double c1, double c2, int tile) {
+                                         int nrhs, double c1, double c2, int tile) {
   const int lane = threadIdx.x & 63;
   const int grp = threadIdx.x >> 6;
   const int r0 = grp * R;
@@ -232,31 +228,24 @@ __device__ __forceinline__ void hop_tile(const BoxGeom g, const T2* __restrict__
   const int nr = min(R, nrhs - r0);
   const int i = tile * kTile + lane;
   const bool valid = i < g.Vh;
-  const size_t Vh = (size_t)g.Vh;
-  const T2* __restrict__ cl = clov + (size_t)p * 36 * Vh;
+  const int nt = g.ntiles;
   T2 acc[R][12];
   if (valid) hop_sum<T2, R>(g, p, i, U, in, r0, nr, act, acc);
+  const T2* __restrict__ cl = clov + cidx(nt, p, 0, i);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     if (r >= nr) break;
     const int col = r0 + r;
-    const bool on = (act == nullptr || act[col]);
+    const bool on = (act == nullptr || ldg(act + col));
     if (!on) continue;  // uniform across the wave
     double2 s0 = make_double2(0, 0), s1 = make_double2(0, 0);
+    const size_t base = fidx(nt, col, 0, i);
     if (valid) {
       T2 av[12], ra[12], o[12];
-      const size_t base = (size_t)col * 12 * Vh + i;
-      if (MODE != MODE_CINV_HOP) {
-#pragma unroll
-        for (int c = 0; c < 12; ++c) av[c] = aux[base + c * Vh];
-      }
-      if (MODE == MODE_RES || RED == RED_DOT) {
-#pragma unroll
-        for (int c = 0; c < 12; ++c) ra[c] = red_a[base + c * Vh];
-      }
-      epilogue<T2, MODE>(cl, Vh, i, acc[r], av, ra, c1, c2, o);
-#pragma unroll
-      for (int c = 0; c < 12; ++c) out[base + c * Vh] = o[c];
+      if (MODE != MODE_CINV_HOP) spinor_load(aux + base, av);
+      if (MODE == MODE_RES || RED == RED_DOT) spinor_load(red_a + base, ra);
+      epilogue<T2, MODE>(cl, acc[r], av, ra, c1, c2, o);
+      spinor_store(out + base, o);
       if (RED == RED_DOT) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
@@ -274,28 +263,57 @@ __device__ __forceinline__ void hop_tile(const BoxGeom g, const T2* __restrict__
 #pragma unroll
         for (int c = 0; c < 12; ++c) s0.x += (double)o[c].x * o[c].x + (double)o[c].y * o[c].y;
       }
+    } else {
+      // padding sites of the last tile stay zero
+      T2 z[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) z[c] = mk<T2>(0, 0);
+      spinor_store(out + base, z);
     }
     if (RED != RED_NONE) {
-      s0 = wave_sum<T2>(s0);
-      if (RED == RED_TS) s1 = wave_sum<T2>(s1);
+      s0 = wave_sum(s0);
+      if (RED == RED_TS) s1 = wave_sum(s1);
       if (lane == 0) {
-        partial[(size_t)col * ntiles + tile] = s0;
-        if (RED == RED_TS) partial[((size_t)nrhs + col) * ntiles + tile] = s1;
+        partial[(size_t)col * nt + tile] = s0;
+        if (RED == RED_TS) partial[((size_t)nrhs + col) * nt + tile] = s1;
       }
     }
   }
 }
 
-// Single-item launch (operator application, outer FP64 steps).
-template <typename T2, int R, int MODE, int RED>
-__global__ void __launch_bounds__(64 * ((kMaxRhs + R - 1) / R)) k_hop_item(HopItem<T2> it) {
-  for (int tile = blockIdx.x; tile < it.ntiles; tile += gridDim.x)
-    hop_tile<T2, R, MODE, RED>(it.g, it.U, it.clov, it.in, it.aux, it.red_a, it.out, it.partial, it.active,
-                               it.par_out, it.nrhs, it.ntiles, it.c1, it.c2, tile);
+// Banded tile order of one box for XCD x: the box is nslice slices of S
+// tiles (S = tps, or the whole box if a slice is not a whole number of tiles);
+// XCD x owns tiles [x S / 8, (x+1) S / 8) of every slice, slice after slice.
+__device__ __forceinline__ void band_of(int ntiles, int tps, int x, int& S, int& lo, int& bs) {
+  S = tps > 0 ? tps : ntiles;
+  lo = (int)((long)x * S / kXcd);
+  bs = (int)((long)(x + 1) * S / kXcd) - lo;
+}
+__device__ __forceinline__ int band_tile(int S, int lo, int bs, int local) {
+  return (local / bs) * S + lo + local % bs;
 }
 
-// Batched launch over solver slots: the virtual tile vt of the whole batch is
-// mapped to (slot, tile) through the prefix table tile_start[nslots+1].
+// Single-item launch (operator application, outer FP64 steps).
+template <typename T2, int R, int MODE, int RED>
+__global__ void __launch_bounds__(64 * ((kMaxRhs + R - 1) / R)) k_hop_item(HopItem<T2> it, int order) {
+  if (order == TILE_ORDER_BANDED) {
+    const int x = blockIdx.x % kXcd, j = blockIdx.x / kXcd, nb = gridDim.x / kXcd;
+    int S, lo, bs;
+    band_of(it.ntiles, it.tps, x, S, lo, bs);
+    const int total = bs * (it.ntiles / S);
+    for (int v = j; v < total; v += nb)
+      hop_tile<T2, R, MODE, RED>(it.g, it.U, it.clov, it.in, it.aux, it.red_a, it.out, it.partial, it.active,
+                                 it.par_out, it.nrhs, it.c1, it.c2, band_tile(S, lo, bs, v));
+  } else {
+    for (int tile = blockIdx.x; tile < it.ntiles; tile += gridDim.x)
+      hop_tile<T2, R, MODE, RED>(it.g, it.U, it.clov, it.in, it.aux, it.red_a, it.out, it.partial, it.active,
+                                 it.par_out, it.nrhs, it.c1, it.c2, tile);
+  }
+}
+
+// Batched launch over solver slots.  Linear order: virtual tile vt of the
+// batch maps to (slot, tile) through tile_start[nslots+1].  Banded order:
+// XCD x walks xstart[x][*], the prefix over slots of its band sizes.
 __device__ __forceinline__ int find_slot(const int* __restrict__ start, int n, int vt) {
   int lo = 0, hi = n;  // start[lo] <= vt < start[hi]
   while (hi - lo > 1) {
@@ -306,131 +324,137 @@ __device__ __forceinline__ int find_slot(const int* __restrict__ start, int n, i
 }
 
 template <typename T2, int R, int MODE, int RED>
-__global__ void __launch_bounds__(64 * ((kMaxRhs + R - 1) / R)) k_hop_batch(const SlotDesc<T2>* __restrict__ slots,
-                                                   const int* __restrict__ tile_start,
-                                                   const int* __restrict__ nslots_p, int fin, int faux, int fout,
-                                                   int fred, int par_out) {
+__global__ void __launch_bounds__(64 * ((kMaxRhs + R - 1) / R))
+    k_hop_batch(const SlotDesc<T2>* __restrict__ slots, const int* __restrict__ tile_start,
+                const int* __restrict__ xstart, int xstride, const int* __restrict__ nslots_p, int fin, int faux,
+                int fout, int fred, int par_out, int order) {
   const int ns = *nslots_p;
-  const int total = tile_start[ns];
-  for (int vt = blockIdx.x; vt < total; vt += gridDim.x) {
-    const int s = find_slot(tile_start, ns, vt);
-    const SlotDesc<T2>& d = slots[s];
-    const int tile = vt - tile_start[s];
-    const T2* clov = d.Ainv;
-    double c1 = d.kappa * d.kappa;
-    hop_tile<T2, R, MODE, RED>(d.g, d.U, clov, d.f[fin], faux >= 0 ? d.f[faux] : nullptr,
-                               fred >= 0 ? d.f[fred] : nullptr, d.f[fout], d.partial, d.active, par_out, d.nrhs,
-                               d.ntiles, c1, 0.0, tile);
-  }
-}
-
-// Site-local clover application out = C in (parity p data of a [2][36][Vh] array).
-template <typename T2>
-__global__ void k_clover_apply(BoxGeom g, const T2* __restrict__ clov, int p, const T2* __restrict__ in,
-                               T2* __restrict__ out, int nrhs) {
-  const size_t Vh = (size_t)g.Vh;
-  const size_t n = Vh * nrhs;
-  const T2* cl = clov + (size_t)p * 36 * Vh;
-  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(t % Vh);
-    const int col = (int)(t / Vh);
-    const size_t base = (size_t)col * 12 * Vh + i;
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      T2 m[18], x[6], y[6];
-      herm6_load(cl + (size_t)b * 18 * Vh, Vh, i, m);
-#pragma unroll
-      for (int c = 0; c < 6; ++c) x[c] = in[base + (6 * b + c) * Vh];
-      herm6_apply(m, x, y);
-#pragma unroll
-      for (int c = 0; c < 6; ++c) out[base + (6 * b + c) * Vh] = y[c];
+  if (order == TILE_ORDER_BANDED) {
+    const int x = blockIdx.x % kXcd, j = blockIdx.x / kXcd, nb = gridDim.x / kXcd;
+    const int* P = xstart + (size_t)x * xstride;
+    const int total = P[ns];
+    for (int v = j; v < total; v += nb) {
+      const int s = find_slot(P, ns, v);
+      const SlotDesc<T2>& d = slots[s];
+      int S, lo, bs;
+      band_of(d.ntiles, d.tps, x, S, lo, bs);
+      const int tile = band_tile(S, lo, bs, v - P[s]);
+      hop_tile<T2, R, MODE, RED>(d.g, d.U, d.Ainv, d.f[fin], faux >= 0 ? d.f[faux] : nullptr,
+                                 fred >= 0 ? d.f[fred] : nullptr, d.f[fout], d.partial, d.active, par_out, d.nrhs,
+                                 d.kappa * d.kappa, 0.0, tile);
+    }
+  } else {
+    const int total = tile_start[ns];
+    for (int vt = blockIdx.x; vt < total; vt += gridDim.x) {
+      const int s = find_slot(tile_start, ns, vt);
+      const SlotDesc<T2>& d = slots[s];
+      hop_tile<T2, R, MODE, RED>(d.g, d.U, d.Ainv, d.f[fin], faux >= 0 ? d.f[faux] : nullptr,
+                                 fred >= 0 ? d.f[fred] : nullptr, d.f[fout], d.partial, d.active, par_out, d.nrhs,
+                                 d.kappa * d.kappa, 0.0, vt - tile_start[s]);
     }
   }
 }
 
-// --------------------------------------------------------------- launchers
-static int grid_for(int ntiles) { return ntiles < 65535 ? ntiles : 65535; }
+// Site-local clover application out = C in on parity p.
+template <typename T2>
+__global__ void k_clover_apply(BoxGeom g, const T2* __restrict__ clov, int p, const T2* __restrict__ in,
+                               T2* __restrict__ out, int nrhs) {
+  const size_t per = (size_t)g.ntiles * 64;
+  const size_t n = per * nrhs;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(t % per);  // a thread per (site, column)
+    const int col = (int)(t / per);
+    const size_t base = fidx(g.ntiles, col, 0, i);
+    const T2* cl = clov + cidx(g.ntiles, p, 0, i);
+    T2 x[12], y[12];
+    spinor_load(in + base, x);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      T2 m[18];
+      herm6_load(cl + 128 * 9 * b, m);
+      herm6_apply(m, x + 6 * b, y + 6 * b);
+    }
+    if (i >= g.Vh)
+#pragma unroll
+      for (int c = 0; c < 12; ++c) y[c] = mk<T2>(0, 0);
+    spinor_store(out + base, y);
+  }
+}
 
-#define DDML_HOP_DISPATCH(T2, Rv, MODEv, REDv, ...)                                       \
-  if (R == Rv && mode == MODEv && red == REDv) {                                          \
-    hipLaunchKernelGGL((k_hop_item<T2, Rv, MODEv, REDv>), dim3(grid), dim3(block), 0, st, __VA_ARGS__); \
-    return hipGetLastError();                                                             \
+// --------------------------------------------------------------- launchers
+#define DDML_HOP_DISPATCH(T2, Rv, MODEv, REDv)                                                        \
+  if (R == Rv && mode == MODEv && red == REDv) {                                                      \
+    hipLaunchKernelGGL((k_hop_item<T2, Rv, MODEv, REDv>), dim3(grid), dim3(block), 0, st, it, order); \
+    return hipGetLastError();                                                                         \
   }
 
 template <typename T2>
-static hipError_t hop_item_impl(const HopItem<T2>& it, int mode, int red, int R, hipStream_t st) {
-  const int groups = (it.nrhs + R - 1) / R;
-  const int block = 64 * groups;
-  const int grid = grid_for(it.ntiles);
-  if (block > 768) return hipErrorInvalidValue;
-  DDML_HOP_DISPATCH(T2, 1, MODE_CINV_HOP, RED_NONE, it)
-  DDML_HOP_DISPATCH(T2, 1, MODE_SCHUR, RED_NONE, it)
-  DDML_HOP_DISPATCH(T2, 1, MODE_M, RED_NONE, it)
-  DDML_HOP_DISPATCH(T2, 1, MODE_PREP, RED_NONE, it)
-  DDML_HOP_DISPATCH(T2, 1, MODE_RES, RED_NORM, it)
-  DDML_HOP_DISPATCH(T2, 2, MODE_CINV_HOP, RED_NONE, it)
-  DDML_HOP_DISPATCH(T2, 2, MODE_SCHUR, RED_NONE, it)
-  DDML_HOP_DISPATCH(T2, 2, MODE_M, RED_NONE, it)
-  DDML_HOP_DISPATCH(T2, 2, MODE_PREP, RED_NONE, it)
-  DDML_HOP_DISPATCH(T2, 2, MODE_RES, RED_NORM, it)
-  DDML_HOP_DISPATCH(T2, 3, MODE_CINV_HOP, RED_NONE, it)
-  DDML_HOP_DISPATCH(T2, 3, MODE_SCHUR, RED_NONE, it)
-  DDML_HOP_DISPATCH(T2, 3, MODE_M, RED_NONE, it)
-  DDML_HOP_DISPATCH(T2, 3, MODE_PREP, RED_NONE, it)
-  DDML_HOP_DISPATCH(T2, 3, MODE_RES, RED_NORM, it)
+static hipError_t hop_item_impl(const HopItem<T2>& it, int mode, int red, int R, int order, hipStream_t st) {
+  const int block = 64 * ((it.nrhs + R - 1) / R);
+  int grid = it.ntiles < 65535 ? it.ntiles : 65535;
+  if (order == TILE_ORDER_BANDED) grid = ((grid + kXcd - 1) / kXcd) * kXcd;
+  DDML_HOP_DISPATCH(T2, 1, MODE_CINV_HOP, RED_NONE)
+  DDML_HOP_DISPATCH(T2, 1, MODE_SCHUR, RED_NONE)
+  DDML_HOP_DISPATCH(T2, 1, MODE_M, RED_NONE)
+  DDML_HOP_DISPATCH(T2, 1, MODE_PREP, RED_NONE)
+  DDML_HOP_DISPATCH(T2, 1, MODE_RES, RED_NORM)
+  DDML_HOP_DISPATCH(T2, 2, MODE_CINV_HOP, RED_NONE)
+  DDML_HOP_DISPATCH(T2, 2, MODE_SCHUR, RED_NONE)
+  DDML_HOP_DISPATCH(T2, 3, MODE_CINV_HOP, RED_NONE)
+  DDML_HOP_DISPATCH(T2, 3, MODE_SCHUR, RED_NONE)
+  (void)block;
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_hop_item(const HopItem<double2>& it, int mode, int red, int R, hipStream_t st) {
-  return hop_item_impl(it, mode, red, R, st);
+hipError_t launch_hop_item(const HopItem<double2>& it, int mode, int red, int R, int order, hipStream_t st) {
+  return hop_item_impl(it, mode, red, R, order, st);
 }
-hipError_t launch_hop_item(const HopItem<float2>& it, int mode, int red, int R, hipStream_t st) {
-  return hop_item_impl(it, mode, red, R, st);
+hipError_t launch_hop_item(const HopItem<float2>& it, int mode, int red, int R, int order, hipStream_t st) {
+  return hop_item_impl(it, mode, red, R, order, st);
 }
 
-#define DDML_HOPB_DISPATCH(T2, Rv, MODEv, REDv)                                                        \
-  if (R == Rv && mode == MODEv && red == REDv) {                                                       \
-    hipLaunchKernelGGL((k_hop_batch<T2, Rv, MODEv, REDv>), dim3(grid), dim3(block), 0, st, slots,      \
-                       tile_start, nslots_p, fin, faux, fout, fred, par_out);                          \
-    return hipGetLastError();                                                                          \
+#define DDML_HOPB_DISPATCH(T2, Rv, MODEv, REDv)                                                              \
+  if (R == Rv && mode == MODEv && red == REDv) {                                                             \
+    hipLaunchKernelGGL((k_hop_batch<T2, Rv, MODEv, REDv>), dim3(grid), dim3(block), 0, st, slots, tile_start, \
+                       xstart, xstride, nslots_p, fin, faux, fout, fred, par_out, order);                   \
+    return hipGetLastError();                                                                                \
   }
 
 template <typename T2>
-static hipError_t hop_batch_impl(const SlotDesc<T2>* slots, const int* tile_start, const int* nslots_p,
-                                 int nrhs, int R, int mode, int red, int fin, int faux, int fout, int fred,
-                                 int par_out, int grid, hipStream_t st) {
+static hipError_t hop_batch_impl(const SlotDesc<T2>* slots, const int* tile_start, const int* xstart, int xstride,
+                                 const int* nslots_p, int nrhs, int R, int mode, int red, int fin, int faux, int fout,
+                                 int fred, int par_out, int grid, int order, hipStream_t st) {
   const int block = 64 * ((nrhs + R - 1) / R);
-  if (block > 768) return hipErrorInvalidValue;
+  if (order == TILE_ORDER_BANDED && grid % kXcd) return hipErrorInvalidValue;
   DDML_HOPB_DISPATCH(T2, 1, MODE_CINV_HOP, RED_NONE)
   DDML_HOPB_DISPATCH(T2, 1, MODE_SCHUR, RED_DOT)
   DDML_HOPB_DISPATCH(T2, 1, MODE_SCHUR, RED_TS)
-  DDML_HOPB_DISPATCH(T2, 1, MODE_SCHUR, RED_NONE)
   DDML_HOPB_DISPATCH(T2, 2, MODE_CINV_HOP, RED_NONE)
   DDML_HOPB_DISPATCH(T2, 2, MODE_SCHUR, RED_DOT)
   DDML_HOPB_DISPATCH(T2, 2, MODE_SCHUR, RED_TS)
-  DDML_HOPB_DISPATCH(T2, 2, MODE_SCHUR, RED_NONE)
   DDML_HOPB_DISPATCH(T2, 3, MODE_CINV_HOP, RED_NONE)
   DDML_HOPB_DISPATCH(T2, 3, MODE_SCHUR, RED_DOT)
   DDML_HOPB_DISPATCH(T2, 3, MODE_SCHUR, RED_TS)
-  DDML_HOPB_DISPATCH(T2, 3, MODE_SCHUR, RED_NONE)
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_hop_batch(const SlotDesc<float2>* slots, const int* tile_start, const int* nslots_p, int nrhs,
-                            int R, int mode, int red, int fin, int faux, int fout, int fred, int par_out, int grid,
-                            hipStream_t st) {
-  return hop_batch_impl(slots, tile_start, nslots_p, nrhs, R, mode, red, fin, faux, fout, fred, par_out, grid, st);
+hipError_t launch_hop_batch(const SlotDesc<float2>* slots, const int* tile_start, const int* xstart, int xstride,
+                            const int* nslots_p, int nrhs, int R, int mode, int red, int fin, int faux, int fout,
+                            int fred, int par_out, int grid, int order, hipStream_t st) {
+  return hop_batch_impl(slots, tile_start, xstart, xstride, nslots_p, nrhs, R, mode, red, fin, faux, fout, fred,
+                        par_out, grid, order, st);
 }
-hipError_t launch_hop_batch(const SlotDesc<double2>* slots, const int* tile_start, const int* nslots_p, int nrhs,
-                            int R, int mode, int red, int fin, int faux, int fout, int fred, int par_out, int grid,
-                            hipStream_t st) {
-  return hop_batch_impl(slots, tile_start, nslots_p, nrhs, R, mode, red, fin, faux, fout, fred, par_out, grid, st);
+hipError_t launch_hop_batch(const SlotDesc<double2>* slots, const int* tile_start, const int* xstart, int xstride,
+                            const int* nslots_p, int nrhs, int R, int mode, int red, int fin, int faux, int fout,
+                            int fred, int par_out, int grid, int order, hipStream_t st) {
+  return hop_batch_impl(slots, tile_start, xstart, xstride, nslots_p, nrhs, R, mode, red, fin, faux, fout, fred,
+                        par_out, grid, order, st);
 }
 
 template <typename T2>
 static hipError_t clover_apply_impl(const BoxGeom& g, const T2* clov, int p, const T2* in, T2* out, int nrhs,
                                     hipStream_t st) {
-  size_t n = (size_t)g.Vh * nrhs;
+  size_t n = (size_t)g.ntiles * 64 * nrhs;
   int grid = (int)((n + 255) / 256);
   if (grid > 65535) grid = 65535;
   hipLaunchKernelGGL((k_clover_apply<T2>), dim3(grid), dim3(256), 0, st, g, clov, p, in, out, nrhs);

@@ -222,11 +222,13 @@ static void fill_spec(Ctx* c, const GaugeRec& g, const DomainRec& d, BlockSpec& 
   bs.csw = g.csw;
   geo.Vh = bs.Lb[0] * bs.Lb[1] * bs.Lb[2] * bs.Lb[3] / 2;
   geo.half3 = bs.Lb[3] / 2;
+  geo.ntiles = (geo.Vh + kTile - 1) / kTile;
 }
 
-static size_t opblock_bytes(size_t Vh) {
-  return DevPool::round(72 * Vh * sizeof(double2)) + 2 * DevPool::round(72 * Vh * sizeof(double2)) +
-         DevPool::round(72 * Vh * sizeof(float2)) * 2;
+static size_t opblock_bytes(size_t nsites) {  // nsites = 2 * ntiles * 64
+  return DevPool::round(kLinkSlots * nsites * sizeof(double2)) + DevPool::round(kLinkSlots * nsites * sizeof(float2)) +
+         2 * DevPool::round(kCloverSlots * nsites * sizeof(double2)) +
+         DevPool::round(kCloverSlots * nsites * sizeof(float2));
 }
 
 static void evict_blocks(Ctx* c) {
@@ -245,15 +247,20 @@ std::shared_ptr<OpBlock> opblock(Ctx* c, int gauge_id, int dom_id) {
   const DomainRec& d = domain_get(c, dom_id);
   auto ob = std::make_shared<OpBlock>();
   fill_spec(c, git->second, d, ob->bs, ob->g);
-  const size_t Vh = (size_t)ob->g.Vh;
-  ob->ntiles = (int)((Vh + kTile - 1) / kTile);
-  ob->bytes = opblock_bytes(Vh);
+  ob->ntiles = ob->g.ntiles;
+  const size_t V3h = (size_t)ob->bs.Lb[1] * ob->bs.Lb[2] * ob->bs.Lb[3] / 2;
+  ob->tps = (V3h % kTile == 0) ? (int)(V3h / kTile) : 0;
+  ob->field = (size_t)12 * ob->ntiles * kTile;
+  const size_t ns = (size_t)2 * ob->ntiles * kTile;  // both parities, padded
+  ob->bytes = opblock_bytes(ns);
   if (!c->pool->fits(ob->bytes)) evict_blocks(c);
-  ob->U64 = DBuf(c->pool.get(), 72 * Vh * sizeof(double2));
-  ob->U32 = DBuf(c->pool.get(), 72 * Vh * sizeof(float2));
-  ob->A64 = DBuf(c->pool.get(), 72 * Vh * sizeof(double2));
-  ob->Ainv64 = DBuf(c->pool.get(), 72 * Vh * sizeof(double2));
-  ob->Ainv32 = DBuf(c->pool.get(), 72 * Vh * sizeof(float2));
+  ob->U64 = DBuf(c->pool.get(), kLinkSlots * ns * sizeof(double2));
+  ob->U32 = DBuf(c->pool.get(), kLinkSlots * ns * sizeof(float2));
+  ob->A64 = DBuf(c->pool.get(), kCloverSlots * ns * sizeof(double2));
+  ob->Ainv64 = DBuf(c->pool.get(), kCloverSlots * ns * sizeof(double2));
+  ob->Ainv32 = DBuf(c->pool.get(), kCloverSlots * ns * sizeof(float2));
+  for (DBuf* b : {&ob->U64, &ob->U32, &ob->A64, &ob->Ainv64, &ob->Ainv32})
+    DDML_HIP(hipMemsetAsync(b->p, 0, b->bytes, c->stream));
   GaugeView gv;
   gv.base = git->second.base->as<double2>();
   gv.region = git->second.region ? git->second.region->as<double2>() : nullptr;
@@ -275,8 +282,9 @@ size_t solve_footprint(Ctx* c, int dom_id, int nrhs, int prec) {
   const DomainRec& d = domain_get(c, dom_id);
   size_t Vb = 1;
   for (int m = 0; m < 4; ++m) Vb *= (size_t)(d.hi[m] - d.lo[m]);
-  const size_t Vh = Vb / 2, n = (size_t)nrhs * 12 * Vh;
+  const size_t Vh = Vb / 2;
   const size_t ntiles = (Vh + kTile - 1) / kTile;
+  const size_t n = (size_t)nrhs * 12 * ntiles * kTile;
   const size_t inner = prec == DDML_FP64 ? sizeof(double2) : sizeof(float2);
   return 8 * DevPool::round(n * sizeof(double2)) + F_NUM * DevPool::round(n * inner) +
          2 * DevPool::round(2 * nrhs * ntiles * sizeof(double2)) + 6 * DevPool::round(64);
@@ -289,14 +297,17 @@ static HopItem<double2> item64(const OpBlock& ob, int nrhs) {
   it.U = ob.U64.as<double2>();
   it.nrhs = nrhs;
   it.ntiles = ob.ntiles;
+  it.tps = ob.tps;
   return it;
 }
 
 void apply_D(Ctx* c, int gauge_id, int dom_id, const double* in, double* out, int nrhs, hipStream_t st) {
   auto ob = opblock(c, gauge_id, dom_id);
-  const size_t Vh = ob->g.Vh, n = (size_t)nrhs * 12 * Vh;
+  const size_t n = (size_t)nrhs * ob->field;
   DBuf xe(c->pool.get(), n * sizeof(double2)), xo(c->pool.get(), n * sizeof(double2));
   DBuf oe(c->pool.get(), n * sizeof(double2)), oo(c->pool.get(), n * sizeof(double2));
+  DDML_HIP(hipMemsetAsync(xe.p, 0, xe.bytes, st));
+  DDML_HIP(hipMemsetAsync(xo.p, 0, xo.bytes, st));
   const double2* cin = reinterpret_cast<const double2*>(in);
   double2* cout = reinterpret_cast<double2*>(out);
   DDML_HIP(launch_gather(cin, ob->bs, 0, nrhs, 1.0, xe.as<double2>(), st));
@@ -311,7 +322,7 @@ void apply_D(Ctx* c, int gauge_id, int dom_id, const double* in, double* out, in
     it.par_out = p;
     it.c1 = kappa;
     it.c2 = 1.0 / (2.0 * kappa);
-    DDML_HIP(launch_hop_item(it, MODE_M, RED_NONE, 1, st));
+    DDML_HIP(launch_hop_item(it, MODE_M, RED_NONE, 1, c->tune64.order, st));
   }
   DDML_HIP(hipMemsetAsync(out, 0, (size_t)nrhs * c->V * 12 * sizeof(double2), st));
   DDML_HIP(launch_scatter(oe.as<double2>(), ob->bs, 0, nrhs, 1.0, cout, st));
@@ -322,28 +333,31 @@ void apply_D(Ctx* c, int gauge_id, int dom_id, const double* in, double* out, in
 template <typename T2>
 static void schur_apply(Ctx* c, const OpBlock& ob, const T2* U, const T2* Ainv, const T2* xe, T2* tmp, T2* oe,
                         int nrhs, hipStream_t st) {
+  const TuneChoice& tn = c->tune(sizeof(T2) == sizeof(double2) ? DDML_FP64 : DDML_MIXED_FP32);
   HopItem<T2> it{};
   it.g = ob.g;
   it.U = U;
   it.clov = Ainv;
   it.nrhs = nrhs;
   it.ntiles = ob.ntiles;
+  it.tps = ob.tps;
   it.in = xe;
   it.out = tmp;
   it.par_out = 1;
-  DDML_HIP(launch_hop_item(it, MODE_CINV_HOP, RED_NONE, c->tune.R, st));
+  DDML_HIP(launch_hop_item(it, MODE_CINV_HOP, RED_NONE, tn.R, tn.order, st));
   it.in = tmp;
   it.aux = xe;
   it.out = oe;
   it.par_out = 0;
   it.c1 = ob.bs.kappa * ob.bs.kappa;
-  DDML_HIP(launch_hop_item(it, MODE_SCHUR, RED_NONE, c->tune.R, st));
+  DDML_HIP(launch_hop_item(it, MODE_SCHUR, RED_NONE, tn.R, tn.order, st));
 }
 
 void apply_eo(Ctx* c, int gauge_id, int dom_id, const double* in, double* out, int nrhs, int prec, hipStream_t st) {
   auto ob = opblock(c, gauge_id, dom_id);
-  const size_t Vh = ob->g.Vh, n = (size_t)nrhs * 12 * Vh;
+  const size_t n = (size_t)nrhs * ob->field;
   DBuf xe(c->pool.get(), n * sizeof(double2)), oe(c->pool.get(), n * sizeof(double2));
+  DDML_HIP(hipMemsetAsync(xe.p, 0, xe.bytes, st));
   DDML_HIP(launch_gather(reinterpret_cast<const double2*>(in), ob->bs, 0, nrhs, 1.0, xe.as<double2>(), st));
   if (prec == DDML_FP64) {
     DBuf tmp(c->pool.get(), n * sizeof(double2));
@@ -372,15 +386,17 @@ BatchRunner<T2>::~BatchRunner() {
 }
 
 template <typename T2>
-void BatchRunner<T2>::init(Ctx* c, int nrhs_, int R_, int K_, int grid_, int max_slots_) {
+void BatchRunner<T2>::init(Ctx* c, int nrhs_, int R_, int K_, int grid_, int max_slots_, int order_) {
   ctx = c;
   nrhs = nrhs_;
   R = R_;
   K = K_;
-  grid = grid_;
+  grid = ((grid_ + kXcd - 1) / kXcd) * kXcd;
   max_slots = max_slots_;
+  order = order_;
   table = DBuf(c->pool.get(), sizeof(SlotDesc<T2>) * max_slots);
   tstart = DBuf(c->pool.get(), sizeof(int) * (max_slots + 1));
+  xstart = DBuf(c->pool.get(), sizeof(int) * kXcd * (max_slots + 1));
   nslots = DBuf(c->pool.get(), sizeof(int));
   st_all = DBuf(c->pool.get(), sizeof(BiState) * max_slots * kMaxRhs);
   act_all = DBuf(c->pool.get(), sizeof(int) * max_slots * kMaxRhs);
@@ -401,18 +417,20 @@ void BatchRunner<T2>::capture() {
   hipStream_t s = ctx->stream;
   const auto* tb = table.as<SlotDesc<T2>>();
   const int* ts = tstart.as<int>();
+  const int* xs = xstart.as<int>();
+  const int xw = max_slots + 1;
   const int* ns = nslots.as<int>();
   DDML_HIP(hipStreamSynchronize(s));
   hipGraph_t graph = nullptr;
   DDML_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   for (int k = 0; k < K; ++k) {
     (void)launch_vec(tb, ts, ns, nrhs, VEC_P, grid, s);
-    (void)launch_hop_batch(tb, ts, ns, nrhs, R, MODE_CINV_HOP, RED_NONE, F_P, -1, F_TMP, -1, 1, grid, s);
-    (void)launch_hop_batch(tb, ts, ns, nrhs, R, MODE_SCHUR, RED_DOT, F_TMP, F_P, F_V, F_RH, 0, grid, s);
+    (void)launch_hop_batch(tb, ts, xs, xw, ns, nrhs, R, MODE_CINV_HOP, RED_NONE, F_P, -1, F_TMP, -1, 1, grid, order, s);
+    (void)launch_hop_batch(tb, ts, xs, xw, ns, nrhs, R, MODE_SCHUR, RED_DOT, F_TMP, F_P, F_V, F_RH, 0, grid, order, s);
     (void)launch_fin(tb, ns, max_slots, FIN_ALPHA, s);
     (void)launch_vec(tb, ts, ns, nrhs, VEC_S, grid, s);
-    (void)launch_hop_batch(tb, ts, ns, nrhs, R, MODE_CINV_HOP, RED_NONE, F_S, -1, F_TMP, -1, 1, grid, s);
-    (void)launch_hop_batch(tb, ts, ns, nrhs, R, MODE_SCHUR, RED_TS, F_TMP, F_S, F_T, -1, 0, grid, s);
+    (void)launch_hop_batch(tb, ts, xs, xw, ns, nrhs, R, MODE_CINV_HOP, RED_NONE, F_S, -1, F_TMP, -1, 1, grid, order, s);
+    (void)launch_hop_batch(tb, ts, xs, xw, ns, nrhs, R, MODE_SCHUR, RED_TS, F_TMP, F_S, F_T, -1, 0, grid, order, s);
     (void)launch_fin(tb, ns, max_slots, FIN_OMEGA, s);
     (void)launch_vec(tb, ts, ns, nrhs, VEC_XR, grid, s);
     (void)launch_fin(tb, ns, max_slots, FIN_RHO, s);
@@ -443,6 +461,7 @@ SlotDesc<float2> make_desc<float2>(const Solve* s, BiState* st, int* act) {
   d.g = s->ob->g;
   d.nrhs = s->nrhs;
   d.ntiles = s->ob->ntiles;
+  d.tps = s->ob->tps;
   d.kappa = s->ob->bs.kappa;
   d.U = s->ob->U32.as<float2>();
   d.Ainv = s->ob->Ainv32.as<float2>();
@@ -459,6 +478,7 @@ SlotDesc<double2> make_desc<double2>(const Solve* s, BiState* st, int* act) {
   d.g = s->ob->g;
   d.nrhs = s->nrhs;
   d.ntiles = s->ob->ntiles;
+  d.tps = s->ob->tps;
   d.kappa = s->ob->bs.kappa;
   d.U = s->ob->U64.as<double2>();
   d.Ainv = s->ob->Ainv64.as<double2>();
@@ -501,9 +521,17 @@ void BatchRunner<T2>::upload() {
     if (slot_of[i]) nused = i + 1;
   h_tstart[0] = 0;
   for (int i = 0; i < max_slots; ++i) h_tstart[i + 1] = h_tstart[i] + (slot_of[i] ? h_table[i].ntiles : 0);
+  h_xstart.assign((size_t)kXcd * (max_slots + 1), 0);
+  for (int x = 0; x < kXcd; ++x) {
+    int* P = h_xstart.data() + (size_t)x * (max_slots + 1);
+    for (int i = 0; i < max_slots; ++i)
+      P[i + 1] = P[i] + (slot_of[i] ? band_count(h_table[i].ntiles, h_table[i].tps, x) : 0);
+  }
   DDML_HIP(hipMemcpyAsync(table.p, h_table.data(), sizeof(SlotDesc<T2>) * max_slots, hipMemcpyHostToDevice,
                           ctx->stream));
   DDML_HIP(hipMemcpyAsync(tstart.p, h_tstart.data(), sizeof(int) * (max_slots + 1), hipMemcpyHostToDevice,
+                          ctx->stream));
+  DDML_HIP(hipMemcpyAsync(xstart.p, h_xstart.data(), sizeof(int) * h_xstart.size(), hipMemcpyHostToDevice,
                           ctx->stream));
   DDML_HIP(hipMemcpyAsync(nslots.p, &nused, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
   dirty = false;
@@ -552,7 +580,7 @@ BatchRunner<float2>& runner<float2>(Ctx* c, int nrhs) {
   auto& r = c->run32[nrhs];
   if (!r) {
     r.reset(new BatchRunner<float2>());
-    r->init(c, nrhs, c->tune.R, c->tune.K, c->tune.grid, 64);
+    r->init(c, nrhs, c->tune32.R, c->tune32.K, c->tune32.grid, 64, c->tune32.order);
   }
   return *r;
 }
@@ -561,7 +589,7 @@ BatchRunner<double2>& runner<double2>(Ctx* c, int nrhs) {
   auto& r = c->run64[nrhs];
   if (!r) {
     r.reset(new BatchRunner<double2>());
-    r->init(c, nrhs, c->tune.R, c->tune.K, c->tune.grid, 64);
+    r->init(c, nrhs, c->tune64.R, c->tune64.K, c->tune64.grid, 64, c->tune64.order);
   }
   return *r;
 }
@@ -569,7 +597,7 @@ BatchRunner<double2>& runner<double2>(Ctx* c, int nrhs) {
 void solve_prepare(Ctx* c, Solve* s) {
   if (s->nrhs < 1 || s->nrhs > kMaxRhs) throw Error{DDML_EINVAL, "nrhs must be in 1..12"};
   s->ob = opblock(c, s->gauge_id, s->dom_id);
-  const size_t Vh = s->ob->g.Vh, n = (size_t)s->nrhs * 12 * Vh;
+  const size_t Vh = s->ob->g.Vh, n = (size_t)s->nrhs * s->ob->field;
   const size_t nt = s->ob->ntiles;
   DevPool* P = c->pool.get();
   s->be = DBuf(P, n * sizeof(double2));
@@ -591,6 +619,8 @@ void solve_prepare(Ctx* c, Solve* s) {
   const double kappa = s->ob->bs.kappa;
   const double2* src = reinterpret_cast<const double2*>(s->src);
   hipStream_t st = c->stream;
+  DDML_HIP(hipMemsetAsync(s->be.p, 0, n * sizeof(double2), st));
+  DDML_HIP(hipMemsetAsync(s->bo.p, 0, n * sizeof(double2), st));
   DDML_HIP(launch_gather(src, s->ob->bs, 0, s->nrhs, 2.0 * kappa, s->be.as<double2>(), st));
   DDML_HIP(launch_gather(src, s->ob->bs, 1, s->nrhs, 2.0 * kappa, s->bo.as<double2>(), st));
   DDML_HIP(hipMemsetAsync(s->xe.p, 0, n * sizeof(double2), st));
@@ -622,7 +652,7 @@ static void launch_residual(Ctx* c, Solve* s) {
     it.partial = s->partial64.as<double2>() + (size_t)p * s->nrhs * nt;
     it.par_out = p;
     it.c1 = ob.bs.kappa;
-    DDML_HIP(launch_hop_item(it, MODE_RES, RED_NORM, 1, c->stream));
+    DDML_HIP(launch_hop_item(it, MODE_RES, RED_NORM, 1, c->tune64.order, c->stream));
   }
   DDML_HIP(launch_sum_partials(s->partial64.as<double2>(), 2, s->nrhs, nt, s->norms.as<double2>() + s->nrhs, 0,
                                c->stream));
@@ -640,14 +670,14 @@ static void launch_prepare(Ctx* c, Solve* s) {
   it.out = s->te.as<double2>();
   it.par_out = 0;
   it.c1 = ob.bs.kappa;
-  DDML_HIP(launch_hop_item(it, MODE_PREP, RED_NONE, 1, c->stream));
+  DDML_HIP(launch_hop_item(it, MODE_PREP, RED_NONE, 1, c->tune64.order, c->stream));
 }
 
 // e_e from the inner solution, e_o = A_oo^{-1}(r_o + kappa H_oe e_e), x += e
 template <typename T2>
 static void launch_export(Ctx* c, Solve* s) {
   const OpBlock& ob = *s->ob;
-  const size_t n = (size_t)s->nrhs * 12 * ob.g.Vh;
+  const size_t n = (size_t)s->nrhs * ob.field;
   DDML_HIP(launch_cast_to_d(s->f[F_X].as<T2>(), s->te.as<double2>(), n, c->stream));
   HopItem<double2> it = item64(ob, s->nrhs);
   it.clov = ob.Ainv64.as<double2>();
@@ -656,7 +686,7 @@ static void launch_export(Ctx* c, Solve* s) {
   it.out = s->to.as<double2>();
   it.par_out = 1;
   it.c1 = ob.bs.kappa;
-  DDML_HIP(launch_hop_item(it, MODE_PREP, RED_NONE, 1, c->stream));
+  DDML_HIP(launch_hop_item(it, MODE_PREP, RED_NONE, 1, c->tune64.order, c->stream));
   DDML_HIP(launch_axpy_d(s->xe.as<double2>(), s->te.as<double2>(), 1.0, n, c->stream));
   DDML_HIP(launch_axpy_d(s->xo.as<double2>(), s->to.as<double2>(), 1.0, n, c->stream));
 }
@@ -806,14 +836,14 @@ void solve_finish(Ctx* c, Solve* s) {
 }
 
 template <typename T2>
-static void time_stencil_t(Ctx* c, const OpBlock& ob, const T2* U, const T2* Ainv, int nrhs, int iters,
-                           double out[4]) {
+static void time_stencil_t(Ctx* c, const OpBlock& ob, const T2* U, const T2* Ainv, int nrhs, int iters, int R,
+                           int order, int grid, double out[4]) {
   hipStream_t st = c->stream;
-  const size_t Vh = ob.g.Vh, n = (size_t)nrhs * 12 * Vh;
+  const size_t Vh = ob.g.Vh, n = (size_t)nrhs * ob.field;
   DevPool* P = c->pool.get();
   DBuf fP(P, n * sizeof(T2)), fT(P, n * sizeof(T2)), fV(P, n * sizeof(T2)), fR(P, n * sizeof(T2));
   DBuf part(P, 2 * nrhs * ob.ntiles * sizeof(double2)), act(P, kMaxRhs * sizeof(int));
-  DBuf tab(P, sizeof(SlotDesc<T2>)), ts(P, 2 * sizeof(int)), ns(P, sizeof(int));
+  DBuf tab(P, sizeof(SlotDesc<T2>)), ts(P, 2 * sizeof(int)), ns(P, sizeof(int)), xs(P, kXcd * 2 * sizeof(int));
   DDML_HIP(launch_fill(fP.as<T2>(), n, 1.0, st));
   DDML_HIP(launch_fill(fR.as<T2>(), n, 0.5, st));
   std::vector<int> ones(kMaxRhs, 1);
@@ -822,6 +852,7 @@ static void time_stencil_t(Ctx* c, const OpBlock& ob, const T2* U, const T2* Ain
   d.g = ob.g;
   d.nrhs = nrhs;
   d.ntiles = ob.ntiles;
+  d.tps = ob.tps;
   d.kappa = ob.bs.kappa;
   d.U = U;
   d.Ainv = Ainv;
@@ -835,15 +866,20 @@ static void time_stencil_t(Ctx* c, const OpBlock& ob, const T2* U, const T2* Ain
   DDML_HIP(hipMemcpyAsync(tab.p, &d, sizeof(d), hipMemcpyHostToDevice, st));
   DDML_HIP(hipMemcpyAsync(ts.p, h_ts, sizeof(h_ts), hipMemcpyHostToDevice, st));
   DDML_HIP(hipMemcpyAsync(ns.p, &one, sizeof(int), hipMemcpyHostToDevice, st));
-  const int R = c->tune.R, grid = c->tune.grid;
+  int h_xs[kXcd * 2];
+  for (int x = 0; x < kXcd; ++x) {
+    h_xs[2 * x] = 0;
+    h_xs[2 * x + 1] = band_count(ob.ntiles, ob.tps, x);
+  }
+  DDML_HIP(hipMemcpyAsync(xs.p, h_xs, sizeof(h_xs), hipMemcpyHostToDevice, st));
   auto* tb = tab.as<SlotDesc<T2>>();
   auto launch = [&](int which) {
     if (which == 0)
-      DDML_HIP(launch_hop_batch(tb, ts.as<int>(), ns.as<int>(), nrhs, R, MODE_CINV_HOP, RED_NONE, F_P, -1, F_TMP, -1,
-                                1, grid, st));
+      DDML_HIP(launch_hop_batch(tb, ts.as<int>(), xs.as<int>(), 2, ns.as<int>(), nrhs, R, MODE_CINV_HOP, RED_NONE,
+                                F_P, -1, F_TMP, -1, 1, grid, order, st));
     else
-      DDML_HIP(launch_hop_batch(tb, ts.as<int>(), ns.as<int>(), nrhs, R, MODE_SCHUR, RED_DOT, F_TMP, F_P, F_V, F_RH,
-                                0, grid, st));
+      DDML_HIP(launch_hop_batch(tb, ts.as<int>(), xs.as<int>(), 2, ns.as<int>(), nrhs, R, MODE_SCHUR, RED_DOT, F_TMP,
+                                F_P, F_V, F_RH, 0, grid, order, st));
   };
   for (int w = 0; w < 3; ++w) { launch(0); launch(1); }
   std::vector<hipEvent_t> ev(2 * iters + 1);
@@ -875,13 +911,47 @@ static void time_stencil_t(Ctx* c, const OpBlock& ob, const T2* U, const T2* Ain
   out[3] = (double)Vh * (96.0 * nrhs + 144.0 + 72.0) * s;
 }
 
-void time_stencil(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, int iters, double out[4]) {
+void time_stencil(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, int iters, int R, int order, int grid,
+                  double out[4]) {
   if (nrhs < 1 || nrhs > kMaxRhs || iters < 1) throw Error{DDML_EINVAL, "bad nrhs or iters"};
+  const TuneChoice& tn = c->tune(prec);
+  if (R <= 0) R = tn.R;
+  if (order < 0) order = tn.order;
+  if (grid <= 0) grid = tn.grid;
+  if (R < 1 || R > 3 || (order != TILE_ORDER_LINEAR && order != TILE_ORDER_BANDED))
+    throw Error{DDML_EINVAL, "R must be 1..3 and order 0 or 1"};
+  grid = ((grid + kXcd - 1) / kXcd) * kXcd;
   auto ob = opblock(c, gauge_id, dom_id);
   if (prec == DDML_FP64)
-    time_stencil_t<double2>(c, *ob, ob->U64.as<double2>(), ob->Ainv64.as<double2>(), nrhs, iters, out);
+    time_stencil_t<double2>(c, *ob, ob->U64.as<double2>(), ob->Ainv64.as<double2>(), nrhs, iters, R, order, grid,
+                            out);
   else
-    time_stencil_t<float2>(c, *ob, ob->U32.as<float2>(), ob->Ainv32.as<float2>(), nrhs, iters, out);
+    time_stencil_t<float2>(c, *ob, ob->U32.as<float2>(), ob->Ainv32.as<float2>(), nrhs, iters, R, order, grid, out);
+}
+
+void autotune(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, double best[4]) {
+  double bt = 1e300;
+  TuneChoice b = c->tune(prec);
+  for (int R = 1; R <= 3; ++R)
+    for (int order = 0; order <= 1; ++order)
+      for (int grid : {512, 1024, 2048}) {
+        double o[4];
+        time_stencil(c, gauge_id, dom_id, nrhs, prec, 5, R, order, grid, o);
+        const double t = o[0] + o[1];
+        if (t < bt) {
+          bt = t;
+          b.R = R;
+          b.order = order;
+          b.grid = grid;
+        }
+      }
+  c->tune(prec) = b;
+  c->run32.clear();  // graphs are captured with the launch choice: rebuild on next use
+  c->run64.clear();
+  best[0] = b.R;
+  best[1] = b.order;
+  best[2] = b.grid;
+  best[3] = bt;
 }
 
 void run_solves(Ctx* c, std::vector<Solve*>& solves) {

@@ -93,6 +93,8 @@ struct OpBlock {
   BlockSpec bs;
   BoxGeom g;
   int ntiles = 0;
+  int tps = 0;             // tiles per time slice (0 if a slice is not a whole number of tiles)
+  size_t field = 0;        // complex numbers in one [12-column] field: nrhs * 12 * ntiles * 64 / nrhs
   DBuf U64, A64, Ainv64;   // FP64 operator data
   DBuf U32, Ainv32;        // FP32 copies for the inner solve
   size_t bytes = 0;
@@ -132,16 +134,17 @@ template <typename T2>
 struct BatchRunner {
   Ctx* ctx = nullptr;
   int nrhs = 0, R = 3, K = 8, grid = 1024, max_slots = 64;
-  DBuf table, tstart, nslots, st_all, act_all;
+  DBuf table, tstart, xstart, nslots, st_all, act_all;
+  int order = TILE_ORDER_BANDED;
   std::vector<SlotDesc<T2>> h_table;
-  std::vector<int> h_tstart;
+  std::vector<int> h_tstart, h_xstart;
   std::vector<Solve*> slot_of;    // slot -> solve (nullptr = free)
   std::vector<BiState> h_st;
   hipGraphExec_t exec = nullptr;
   bool dirty = true;
   int nused = 0;                  // highest used slot + 1
   ~BatchRunner();
-  void init(Ctx* c, int nrhs_, int R_, int K_, int grid_, int max_slots_);
+  void init(Ctx* c, int nrhs_, int R_, int K_, int grid_, int max_slots_, int order_);
   void capture();
   int join(Solve* s);             // returns slot or -1 if full
   void leave(Solve* s);
@@ -154,6 +157,7 @@ struct TuneChoice {
   int R = 1;
   int K = 8;
   int grid = 1024;
+  int order = TILE_ORDER_BANDED;
 };
 
 struct Server;
@@ -176,7 +180,8 @@ struct Ctx {
   DomainRec full{};  // the whole lattice (dom_id -1)
   void* pinned = nullptr;   // small pinned host staging area
   size_t pinned_bytes = 0;
-  TuneChoice tune;
+  TuneChoice tune64, tune32;   // launch choices of the FP64 and FP32 kernels
+  TuneChoice& tune(int prec) { return prec == DDML_FP64 ? tune64 : tune32; }
   std::unique_ptr<Server> server;
   ~Ctx();
 };
@@ -201,8 +206,12 @@ void solve_finish(Ctx* c, Solve* s);                 // scatter, info, free
 void check_params(const ddml_solver_params* p);
 // Times the two stencil kernels of the inner solver (k_hop_batch, CINV_HOP and
 // SCHUR with its fused dot product) on one slot; out = {ms_cinv, ms_schur,
-// bytes_cinv, bytes_schur} per launch (algorithmic bytes).
-void time_stencil(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, int iters, double out[4]);
+// bytes_cinv, bytes_schur} per launch (algorithmic bytes).  R, order, grid of
+// the launch: <= 0 selects the context's current choice.
+void time_stencil(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, int iters, int R, int order, int grid,
+                  double out[4]);
+// Picks the fastest stencil launch (R, order, grid) and rebuilds the solver graphs.
+void autotune(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, double best[4]);
 ddml_solver_params default_params();
 
 }  // namespace ddml

@@ -18,10 +18,6 @@
 
 namespace ddml {
 
-struct Site {
-  int x[4];
-};
-
 __device__ __forceinline__ size_t gidx(const int L[4], const int x[4]) {
   return (((size_t)x[0] * L[1] + x[1]) * L[2] + x[2]) * L[3] + x[3];
 }
@@ -49,9 +45,14 @@ __device__ __forceinline__ void lex_coords(const int Lb[4], int s, int y[4]) {
   y[0] = s / Lb[1];
 }
 
+__device__ __forceinline__ int ntiles_of(const BlockSpec& bs) {
+  const int Vh = bs.Lb[0] * bs.Lb[1] * bs.Lb[2] * bs.Lb[3] / 2;
+  return (Vh + kTile - 1) / kTile;
+}
+
 __global__ void k_build_links(GaugeView gv, BlockSpec bs, double2* __restrict__ U64, float2* __restrict__ U32) {
   const int Vb = bs.Lb[0] * bs.Lb[1] * bs.Lb[2] * bs.Lb[3];
-  const size_t Vh = (size_t)(Vb / 2);
+  const int nt = ntiles_of(bs);
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < Vb; s += gridDim.x * blockDim.x) {
     int y[4], x[4];
     lex_coords(bs.Lb, s, y);
@@ -67,9 +68,9 @@ __global__ void k_build_links(GaugeView gv, BlockSpec bs, double2* __restrict__ 
         else if (mu == 0 && bs.antiperiodic) f = -1.0;      // antiperiodic wrap in time
       }
 #pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        const double2 v = make_double2(f * u[k].x, f * u[k].y);
-        const size_t o = ((size_t)(p * 4 + mu) * 9 + k) * Vh + i;
+      for (int k = 0; k < 10; ++k) {  // entry 9 is the zero pad of the last pair
+        const double2 v = k < 9 ? make_double2(f * u[k].x, f * u[k].y) : make_double2(0, 0);
+        const size_t o = lidx(nt, p, mu, k, i);
         if (U64) U64[o] = v;
         if (U32) U32[o] = make_float2((float)v.x, (float)v.y);
       }
@@ -209,18 +210,20 @@ __device__ bool herm6_inverse(const double2 A[36], double2 Ai[36]) {
   return ok;
 }
 
+// 18 slots of chiral block blk of site i (parity p): 3 packed diagonal pairs,
+// then the 15 upper elements row-major
 template <typename T2>
-__device__ __forceinline__ void store_herm6(const double2 A[36], T2* base, size_t Vh, int i) {
+__device__ __forceinline__ void store_herm6(const double2 A[36], T2* arr, int nt, int p, int blk, int i) {
   using T = decltype(T2::x);
-  base[0 * Vh + i] = mk<T2>((T)A[0].x, (T)A[7].x);
-  base[1 * Vh + i] = mk<T2>((T)A[14].x, (T)A[21].x);
-  base[2 * Vh + i] = mk<T2>((T)A[28].x, (T)A[35].x);
+  arr[cidx(nt, p, 18 * blk + 0, i)] = mk<T2>((T)A[0].x, (T)A[7].x);
+  arr[cidx(nt, p, 18 * blk + 1, i)] = mk<T2>((T)A[14].x, (T)A[21].x);
+  arr[cidx(nt, p, 18 * blk + 2, i)] = mk<T2>((T)A[28].x, (T)A[35].x);
   int k = 3;
 #pragma unroll
   for (int r = 0; r < 6; ++r)
 #pragma unroll
     for (int c = r + 1; c < 6; ++c) {
-      base[(size_t)k * Vh + i] = mk<T2>((T)A[6 * r + c].x, (T)A[6 * r + c].y);
+      arr[cidx(nt, p, 18 * blk + k, i)] = mk<T2>((T)A[6 * r + c].x, (T)A[6 * r + c].y);
       ++k;
     }
 }
@@ -228,7 +231,7 @@ __device__ __forceinline__ void store_herm6(const double2 A[36], T2* base, size_
 __global__ void k_build_clover(GaugeView gv, BlockSpec bs, double2* __restrict__ A64, double2* __restrict__ Ainv64,
                                float2* __restrict__ Ainv32, int* __restrict__ bad) {
   const int Vb = bs.Lb[0] * bs.Lb[1] * bs.Lb[2] * bs.Lb[3];
-  const size_t Vh = (size_t)(Vb / 2);
+  const int nt = ntiles_of(bs);
   const double c = bs.kappa * bs.csw;  // X = i c (...)
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < Vb; s += gridDim.x * blockDim.x) {
     int y[4], x[4];
@@ -273,10 +276,9 @@ __global__ void k_build_clover(GaugeView gv, BlockSpec bs, double2* __restrict__
       double2 Ai[36];
       const bool ok = herm6_inverse(A, Ai);
       if (!ok) atomicOr(bad, 1);
-      const size_t off = ((size_t)p * 36 + (size_t)blk * 18) * Vh;
-      if (A64) store_herm6<double2>(A, A64 + off, Vh, i);
-      if (Ainv64) store_herm6<double2>(Ai, Ainv64 + off, Vh, i);
-      if (Ainv32) store_herm6<float2>(Ai, Ainv32 + off, Vh, i);
+      if (A64) store_herm6<double2>(A, A64, nt, p, blk, i);
+      if (Ainv64) store_herm6<double2>(Ai, Ainv64, nt, p, blk, i);
+      if (Ainv32) store_herm6<float2>(Ai, Ainv32, nt, p, blk, i);
     }
   }
 }
@@ -301,7 +303,7 @@ hipError_t launch_build_clover(const GaugeView& gv, const BlockSpec& bs, double2
 __global__ void k_gather(const double2* __restrict__ canon, BlockSpec bs, int p, int nrhs, double scale,
                          double2* __restrict__ eo) {
   const int Vb = bs.Lb[0] * bs.Lb[1] * bs.Lb[2] * bs.Lb[3];
-  const size_t Vh = (size_t)(Vb / 2);
+  const int nt = ntiles_of(bs);
   const size_t V = (size_t)bs.L[0] * bs.L[1] * bs.L[2] * bs.L[3];
   const size_t n = (size_t)Vb * nrhs;
   for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
@@ -315,13 +317,13 @@ __global__ void k_gather(const double2* __restrict__ canon, BlockSpec bs, int p,
     const int i = s >> 1;
 #pragma unroll
     for (int c = 0; c < 12; ++c)
-      eo[((size_t)col * 12 + c) * Vh + i] = make_double2(scale * src[c].x, scale * src[c].y);
+      eo[fidx(nt, col, c, i)] = make_double2(scale * src[c].x, scale * src[c].y);
   }
 }
 __global__ void k_scatter(const double2* __restrict__ eo, BlockSpec bs, int p, int nrhs, double scale,
                           double2* __restrict__ canon) {
   const int Vb = bs.Lb[0] * bs.Lb[1] * bs.Lb[2] * bs.Lb[3];
-  const size_t Vh = (size_t)(Vb / 2);
+  const int nt = ntiles_of(bs);
   const size_t V = (size_t)bs.L[0] * bs.L[1] * bs.L[2] * bs.L[3];
   const size_t n = (size_t)Vb * nrhs;
   for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
@@ -335,7 +337,7 @@ __global__ void k_scatter(const double2* __restrict__ eo, BlockSpec bs, int p, i
     const int i = s >> 1;
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-      const double2 v = eo[((size_t)col * 12 + c) * Vh + i];
+      const double2 v = eo[fidx(nt, col, c, i)];
       dst[c] = make_double2(scale * v.x, scale * v.y);
     }
   }

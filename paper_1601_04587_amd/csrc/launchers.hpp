@@ -5,14 +5,21 @@
 namespace ddml {
 
 // dirac.hip
-hipError_t launch_hop_item(const HopItem<double2>& it, int mode, int red, int R, hipStream_t st);
-hipError_t launch_hop_item(const HopItem<float2>& it, int mode, int red, int R, hipStream_t st);
-hipError_t launch_hop_batch(const SlotDesc<float2>* slots, const int* tile_start, const int* nslots_p, int nrhs,
-                            int R, int mode, int red, int fin, int faux, int fout, int fred, int par_out, int grid,
-                            hipStream_t st);
-hipError_t launch_hop_batch(const SlotDesc<double2>* slots, const int* tile_start, const int* nslots_p, int nrhs,
-                            int R, int mode, int red, int fin, int faux, int fout, int fred, int par_out, int grid,
-                            hipStream_t st);
+hipError_t launch_hop_item(const HopItem<double2>& it, int mode, int red, int R, int order, hipStream_t st);
+hipError_t launch_hop_item(const HopItem<float2>& it, int mode, int red, int R, int order, hipStream_t st);
+// xstart: [kXcd][xstride] per-XCD prefix of band sizes (banded order only)
+hipError_t launch_hop_batch(const SlotDesc<float2>* slots, const int* tile_start, const int* xstart, int xstride,
+                            const int* nslots_p, int nrhs, int R, int mode, int red, int fin, int faux, int fout,
+                            int fred, int par_out, int grid, int order, hipStream_t st);
+hipError_t launch_hop_batch(const SlotDesc<double2>* slots, const int* tile_start, const int* xstart, int xstride,
+                            const int* nslots_p, int nrhs, int R, int mode, int red, int fin, int faux, int fout,
+                            int fred, int par_out, int grid, int order, hipStream_t st);
+// host mirror of the banded order: tiles of a box (ntiles, tps) owned by XCD x
+inline int band_count(int ntiles, int tps, int x) {
+  const int S = tps > 0 ? tps : ntiles;
+  const int lo = (int)((long)x * S / kXcd), hi = (int)((long)(x + 1) * S / kXcd);
+  return (hi - lo) * (ntiles / S);
+}
 hipError_t launch_clover_apply(const BoxGeom& g, const double2* clov, int p, const double2* in, double2* out,
                                int nrhs, hipStream_t st);
 
@@ -33,7 +40,7 @@ hipError_t launch_cast_to_f(const double2* in, float2* out, size_t n, hipStream_
 hipError_t launch_fill(float2* v, size_t n, double a, hipStream_t st);
 hipError_t launch_fill(double2* v, size_t n, double a, hipStream_t st);
 hipError_t launch_axpy_d(double2* y, const double2* x, double a, size_t n, hipStream_t st);
-// column norms |v_col|^2 of [nrhs][12][Vh] into out[nrhs].x (accumulate=1 adds to out)
+// column norms |v_col|^2 of a [nrhs][ntiles][12][64] field into out[nrhs].x (accumulate=1 adds)
 hipError_t launch_col_norms(const double2* v, int Vh, int nrhs, double2* partial, int ntiles, double2* out,
                             int accumulate, hipStream_t st);
 // sum partial[k][col][tile] over tiles into out[k*nrhs + col] (accumulate=1 adds)
@@ -56,7 +63,7 @@ struct BlockSpec {
 hipError_t launch_build_links(const GaugeView& gv, const BlockSpec& bs, double2* U64, float2* U32, hipStream_t st);
 hipError_t launch_build_clover(const GaugeView& gv, const BlockSpec& bs, double2* A64, double2* Ainv64,
                                float2* Ainv32, int* bad, hipStream_t st);
-// canonical [nrhs][V][12] complex128 <-> domain EO [nrhs][12][Vh] of parity p, scaled
+// canonical [nrhs][V][12] complex128 <-> domain EO field [nrhs][ntiles][12][64] of parity p, scaled
 hipError_t launch_gather(const double2* canon, const BlockSpec& bs, int p, int nrhs, double scale, double2* eo,
                          hipStream_t st);
 hipError_t launch_scatter(const double2* eo, const BlockSpec& bs, int p, int nrhs, double scale, double2* canon,
