@@ -82,7 +82,9 @@ typedef struct {
   int max_inner;     /* BiCGstab iterations per cycle */
   double inner_tol;  /* relative reduction of the inner residual per cycle */
   int prec;          /* ddml_prec */
-  int solver;        /* 0 = BiCGstab (the only one) */
+  int solver;        /* 0 = BiCGstab restarted (r0 = r, p = v = 0) at every FP64 correction;
+                        1 = BiCGstab with reliable updates: the Krylov state is kept and only
+                        the residual is replaced by the FP64 one */
   int gcr_m;         /* reserved */
 } ddml_solver_params;
 

@@ -1,7 +1,11 @@
 // Krylov vector kernels and FP64 reductions for the batched BiCGstab.
 //
 // BiCGstab (van der Vorst 1992) on the even-odd Schur operator, one
-// independent recursion per right-hand side.  Every kernel walks a slot table
+// independent recursion per right-hand side.  Reliable updates: when the
+// FP64 defect-correction loop replaces the recursive residual r by the true
+// one, the Krylov state (r0, p, v, alpha, omega) is kept and only rho and beta
+// are rescaled to the new r (VEC_RELUP + FIN_RELUP); a column whose recursion
+// broke down starts afresh instead.  Every kernel walks a slot table
 // (one entry per domain solve in flight) with a grid-stride loop over virtual
 // 64-site tiles; a workgroup is 64 sites x nrhs columns, one wavefront per
 // column, so every reduction is a wavefront reduction written to a fixed
@@ -42,7 +46,7 @@ __global__ void __launch_bounds__(768) k_vec(const SlotDesc<T2>* __restrict__ sl
     const int s = find_slot_v(tile_start, ns, vt);
     const SlotDesc<T2>& d = slots[s];
     if (col >= d.nrhs) continue;
-    if (OP != VEC_INIT && !d.active[col]) continue;  // uniform per wave
+    if (OP != VEC_INIT && OP != VEC_RELUP && !d.active[col]) continue;  // uniform per wave
     const int tile = vt - tile_start[s];
     const int i = tile * kTile + lane;
     const bool valid = i < d.g.Vh;
@@ -94,6 +98,30 @@ __global__ void __launch_bounds__(768) k_vec(const SlotDesc<T2>* __restrict__ sl
           s1.x += (double)n0.x * n0.x + (double)n0.y * n0.y + (double)n1.x * n1.x + (double)n1.y * n1.y;
         }
       }
+    } else if (OP == VEC_RELUP) {
+      // r = (T) src64 and x = 0; a column that restarts also gets rh = r, p = v = 0
+      const bool fresh = st.status != 0;
+      const T2 z = mk<T2>(0, 0);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const size_t o = base + 128 * k;
+        double2 b0 = make_double2(0, 0), b1 = b0;
+        if (valid) ld2(d.src64 + o, b0, b1);
+        const T2 t0 = mk<T2>((T)b0.x, (T)b0.y), t1 = mk<T2>((T)b1.x, (T)b1.y);
+        st2(d.f[F_R] + o, t0, t1);
+        st2(d.f[F_X] + o, z, z);
+        T2 h0 = t0, h1 = t1;
+        if (fresh) {
+          st2(d.f[F_RH] + o, t0, t1);
+          st2(d.f[F_P] + o, z, z);
+          st2(d.f[F_V] + o, z, z);
+        } else if (valid) {
+          ld2(d.f[F_RH] + o, h0, h1);
+        }
+        s0.x += (double)h0.x * t0.x + (double)h0.y * t0.y + (double)h1.x * t1.x + (double)h1.y * t1.y;
+        s0.y += (double)h0.x * t0.y - (double)h0.y * t0.x + (double)h1.x * t1.y - (double)h1.y * t1.x;
+        s1.x += (double)t0.x * t0.x + (double)t0.y * t0.y + (double)t1.x * t1.x + (double)t1.y * t1.y;
+      }
     } else {  // VEC_INIT: r = rh = (T) src64, x = p = v = 0 (padding sites: all zero)
       const T2 z = mk<T2>(0, 0);
 #pragma unroll
@@ -112,7 +140,7 @@ __global__ void __launch_bounds__(768) k_vec(const SlotDesc<T2>* __restrict__ sl
         s1.x += n2;
       }
     }
-    if (OP == VEC_XR || OP == VEC_INIT) {
+    if (OP == VEC_XR || OP == VEC_INIT || OP == VEC_RELUP) {
       s0 = wsum(s0);
       s1 = wsum(s1);
       if (lane == 0) {
@@ -143,7 +171,7 @@ __global__ void __launch_bounds__(768) k_fin(const SlotDesc<T2>* __restrict__ sl
   const int col = threadIdx.x >> 6;
   if (col >= d.nrhs) return;
   BiState& st = d.st[col];
-  if (OP != FIN_INIT && !d.active[col]) return;
+  if (OP != FIN_INIT && OP != FIN_RELUP && !d.active[col]) return;
   double2 a = make_double2(0, 0), b = make_double2(0, 0);
   const double2* p0 = d.partial + (size_t)col * d.ntiles;
   const double2* p1 = d.partial + ((size_t)d.nrhs + col) * d.ntiles;
@@ -158,7 +186,22 @@ __global__ void __launch_bounds__(768) k_fin(const SlotDesc<T2>* __restrict__ sl
   a = wsum(a);
   b = wsum(b);
   if (lane != 0) return;
-  if (OP == FIN_INIT) {
+  if (OP == FIN_RELUP && st.status == 0) {
+    // a = (rh, r'), b = |r'|^2 for the replaced residual r'; keep the Krylov
+    // state and rescale: beta' = beta rho'/rho, rho' = (rh, r')
+    const int want = d.active[col];
+    if (finite2(a) && isfinite(b.x) && (st.rho.x != 0 || st.rho.y != 0)) {
+      st.beta = cmuld(st.beta, cdiv(a, st.rho));
+      st.rho = a;
+    }
+    st.rr = b.x;
+    st.rr0 = b.x;
+    st.iters = 0;
+    const int on = want && b.x > 0 && isfinite(b.x);
+    if (want && !isfinite(b.x)) st.status = 3;
+    d.active[col] = on;
+    st.active = on;
+  } else if (OP == FIN_INIT || OP == FIN_RELUP) {
     // a = (rh, r) = |r|^2, b = |r|^2 ; st.active holds the request flag
     const int want = d.active[col];
     st.rr = b.x;
@@ -212,6 +255,7 @@ static hipError_t vec_impl(const SlotDesc<T2>* slots, const int* tile_start, con
     case VEC_S: hipLaunchKernelGGL((k_vec<T2, VEC_S>), dim3(grid), b, 0, st, slots, tile_start, nslots_p); break;
     case VEC_XR: hipLaunchKernelGGL((k_vec<T2, VEC_XR>), dim3(grid), b, 0, st, slots, tile_start, nslots_p); break;
     case VEC_INIT: hipLaunchKernelGGL((k_vec<T2, VEC_INIT>), dim3(grid), b, 0, st, slots, tile_start, nslots_p); break;
+    case VEC_RELUP: hipLaunchKernelGGL((k_vec<T2, VEC_RELUP>), dim3(grid), b, 0, st, slots, tile_start, nslots_p); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -233,6 +277,7 @@ static hipError_t fin_impl(const SlotDesc<T2>* slots, const int* nslots_p, int m
     case FIN_ALPHA: hipLaunchKernelGGL((k_fin<T2, FIN_ALPHA>), dim3(max_slots), b, 0, st, slots, nslots_p); break;
     case FIN_OMEGA: hipLaunchKernelGGL((k_fin<T2, FIN_OMEGA>), dim3(max_slots), b, 0, st, slots, nslots_p); break;
     case FIN_RHO: hipLaunchKernelGGL((k_fin<T2, FIN_RHO>), dim3(max_slots), b, 0, st, slots, nslots_p); break;
+    case FIN_RELUP: hipLaunchKernelGGL((k_fin<T2, FIN_RELUP>), dim3(max_slots), b, 0, st, slots, nslots_p); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

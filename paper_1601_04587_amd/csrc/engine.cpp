@@ -570,7 +570,7 @@ void check_params(const ddml_solver_params* p) {
   if (p->max_outer < 1 || p->max_inner < 1) throw Error{DDML_EINVAL, "max_outer and max_inner must be >= 1"};
   if (!(p->inner_tol > 0) || !(p->inner_tol < 1)) throw Error{DDML_EINVAL, "inner_tol must be in (0,1)"};
   if (p->prec != DDML_FP64 && p->prec != DDML_MIXED_FP32) throw Error{DDML_EINVAL, "unknown precision"};
-  if (p->solver != 0) throw Error{DDML_EINVAL, "only BiCGstab (solver=0) is available"};
+  if (p->solver != 0 && p->solver != 1) throw Error{DDML_EINVAL, "solver must be 0 (restarted) or 1 (reliable updates)"};
 }
 
 template <typename T2>
@@ -635,6 +635,7 @@ void solve_prepare(Ctx* c, Solve* s) {
   s->inner_iters.assign(s->nrhs, 0);
   s->status.assign(s->nrhs, DDML_OK);
   s->outer = 0;
+  s->saved.clear();
   s->state = 1;
 }
 
@@ -697,8 +698,9 @@ static bool try_join(Ctx* c, Solve* s) {
   const int slot = run.join(s);
   if (slot < 0) return false;
   // per-column request flags and limits for this cycle
+  const bool relup = !s->saved.empty() && s->prm.solver == 1;
   std::vector<int> want(kMaxRhs, 0);
-  std::vector<BiState> st(kMaxRhs, BiState{});
+  std::vector<BiState> st = relup ? s->saved : std::vector<BiState>(kMaxRhs, BiState{});
   const double tol = s->prm.tol;
   for (int col = 0; col < s->nrhs; ++col) {
     want[col] = !s->done[col];
@@ -714,7 +716,7 @@ static bool try_join(Ctx* c, Solve* s) {
   int* dact = run.act_all.template as<int>() + (size_t)slot * kMaxRhs;
   DDML_HIP(hipMemcpyAsync(dst, st.data(), sizeof(BiState) * kMaxRhs, hipMemcpyHostToDevice, c->stream));
   DDML_HIP(hipMemcpyAsync(dact, want.data(), sizeof(int) * kMaxRhs, hipMemcpyHostToDevice, c->stream));
-  // one-entry table for the initialisation
+  // one-entry table for the (re)initialisation
   SlotDesc<T2> d = run.h_table[slot];
   int ts[2] = {0, d.ntiles};
   int one = 1;
@@ -722,9 +724,9 @@ static bool try_join(Ctx* c, Solve* s) {
   DDML_HIP(hipMemcpyAsync(s->tstart1.p, ts, sizeof(ts), hipMemcpyHostToDevice, c->stream));
   DDML_HIP(hipMemcpyAsync(s->n1.p, &one, sizeof(int), hipMemcpyHostToDevice, c->stream));
   const int grid = std::min(d.ntiles, 4096);
-  DDML_HIP(launch_vec(s->table1.as<SlotDesc<T2>>(), s->tstart1.as<int>(), s->n1.as<int>(), s->nrhs, VEC_INIT, grid,
-                      c->stream));
-  DDML_HIP(launch_fin(s->table1.as<SlotDesc<T2>>(), s->n1.as<int>(), 1, FIN_INIT, c->stream));
+  DDML_HIP(launch_vec(s->table1.as<SlotDesc<T2>>(), s->tstart1.as<int>(), s->n1.as<int>(), s->nrhs,
+                      relup ? VEC_RELUP : VEC_INIT, grid, c->stream));
+  DDML_HIP(launch_fin(s->table1.as<SlotDesc<T2>>(), s->n1.as<int>(), 1, relup ? FIN_RELUP : FIN_INIT, c->stream));
   s->state = 2;
   return true;
 }
@@ -798,6 +800,8 @@ void solve_progress(Ctx* c, std::vector<Solve*>& live, bool block) {
           const BiState& b = run.h_st[(size_t)slot * kMaxRhs + col];
           if (!s->done[col]) s->inner_iters[col] += b.iters;
         }
+        // keep the Krylov scalars for the reliable update of the next cycle
+        s->saved.assign(run.h_st.begin() + (size_t)slot * kMaxRhs, run.h_st.begin() + (size_t)(slot + 1) * kMaxRhs);
         run.leave(s);
         launch_export<T2>(c, s);
         s->state = 1;

@@ -24,8 +24,8 @@ hipError_t launch_clover_apply(const BoxGeom& g, const double2* clov, int p, con
                                int nrhs, hipStream_t st);
 
 // blas.hip: inner BiCGstab steps over a slot table
-enum { VEC_P = 0, VEC_S = 1, VEC_XR = 2, VEC_INIT = 3 };
-enum { FIN_INIT = 0, FIN_ALPHA = 1, FIN_OMEGA = 2, FIN_RHO = 3 };
+enum { VEC_P = 0, VEC_S = 1, VEC_XR = 2, VEC_INIT = 3, VEC_RELUP = 4 };
+enum { FIN_INIT = 0, FIN_ALPHA = 1, FIN_OMEGA = 2, FIN_RHO = 3, FIN_RELUP = 4 };
 hipError_t launch_vec(const SlotDesc<float2>* slots, const int* tile_start, const int* nslots_p, int nrhs, int op,
                       int grid, hipStream_t st);
 hipError_t launch_vec(const SlotDesc<double2>* slots, const int* tile_start, const int* nslots_p, int nrhs, int op,

@@ -122,8 +122,9 @@ class DDMLError(RuntimeError):
         self.code = code
 
 
-def solver_params(tol=1e-10, max_outer=12, max_inner=4000, inner_tol=1e-5, prec=MIXED_FP32):
-    return SolverParams(tol, max_outer, max_inner, inner_tol, prec, 0, 0)
+def solver_params(tol=1e-10, max_outer=12, max_inner=4000, inner_tol=1e-5, prec=MIXED_FP32, solver=0):
+    """solver 0: BiCGstab restarted at each FP64 correction; 1: reliable updates."""
+    return SolverParams(tol, max_outer, max_inner, inner_tol, prec, solver, 0)
 
 
 def _ptr(a):

@@ -1,0 +1,123 @@
+"""GPU: serving loop, batched series, autotuner and the stencil timing hook.
+
+The serving determinism test is the one the continuous-batching design is
+held to: a request gives bitwise the same solution alone and in a mix with
+other requests that overlap it on the device (per-solve reductions run in a
+fixed order and a solve's iterations do not depend on its neighbours in the
+batch).
+"""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+ddml = pytest.importorskip("paper_1601_04587_amd.ddml")
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def setup():
+    L = (16, 8, 8, 8)
+    U = inputs.quenched_field(L, 1601002)
+    ctx = ddml.Context(L, ddml.BC_ANTIPERIODIC)
+    gid = ctx.set_gauge(U, 0.1340, 1.769)
+    doms = {"G0": ((6, 0, 0, 0), (10, 8, 8, 8)), "G1": ((4, 0, 0, 0), (12, 8, 8, 8)), "G2": ((0, 0, 0, 0), L)}
+    ids = {k: ctx.set_domain(*v) for k, v in doms.items()}
+    yield L, U, ctx, gid, doms, ids
+    ctx.close()
+
+
+def test_serving_alone_equals_mixed_bitwise(setup):
+    L, U, ctx, gid, doms, ids = setup
+    dev = torch.device("cuda:0")
+    V = int(np.prod(L))
+    srcs = [torch.from_numpy(inputs.point_source(L, (7, k, 0, 1))).to(dev) for k in range(4)]
+    outs = [torch.zeros((12, V, 4, 3), dtype=torch.complex128, device=dev) for _ in range(4)]
+    torch.cuda.synchronize()
+    ctx.server_start(ddml.solver_params(tol=1e-10))
+    try:
+        t = ctx.submit(gid, ids["G1"], srcs[0], outs[0], 12)
+        r = ctx.wait(t, 120.0)
+        assert r is not None and r.status == ddml.OK
+        alone = outs[0].clone()
+        outs[0].zero_()
+        torch.cuda.synchronize()
+        # the same request in a mix: others arrive before and after it
+        tk = [ctx.submit(gid, ids["G2"], srcs[1], outs[1], 12),
+              ctx.submit(gid, ids["G1"], srcs[0], outs[0], 12),
+              ctx.submit(gid, ids["G0"], srcs[2], outs[2], 12),
+              ctx.submit(gid, ids["G2"], srcs[3], outs[3], 12)]
+        res = [ctx.wait(x, 120.0) for x in tk]
+        assert all(r is not None and r.status == ddml.OK for r in res)
+        st = ctx.stats()
+        assert st.completed == 5 and st.p99_latency >= st.p50_latency > 0
+    finally:
+        ctx.server_stop()
+    torch.cuda.synchronize()
+    assert torch.equal(alone, outs[0])
+    # and the mixed results are right: oracle residual on the full-lattice request
+    C = oracle.clover_term(U, L, 1.769)
+    b = srcs[3].cpu().numpy()
+    res = oracle.residual(U, L, 0.1340, b, outs[3].cpu().numpy(), C=C)
+    assert res.max() <= 1e-10 * (1 + 1e-3)
+
+
+def test_series_batch_matches_single_series(setup):
+    L, U, ctx, gid, doms, ids = setup
+    V = int(np.prod(L))
+    order = [ids["G0"], ids["G1"], ids["G2"]]
+    b1 = inputs.point_source(L, (7, 0, 0, 0))
+    b2 = inputs.point_source(L, (8, 1, 2, 3))
+    t1 = np.zeros((3, 12, V, 4, 3), dtype=np.complex128)
+    t2 = np.zeros_like(t1)
+    rc, infos = ctx.propagator_series_batch([(gid, order, b1, t1, None), (gid, order, b2, t2, None)], 12)
+    assert rc == ddml.OK
+    s1 = np.zeros_like(t1)
+    rc, _ = ctx.propagator_series(gid, order, b1, 12, s1)
+    assert rc == ddml.OK
+    assert np.array_equal(s1, t1)
+    C = oracle.clover_term(U, L, 1.769)
+    cum = np.cumsum(t2, axis=0)
+    for i, k in enumerate(["G0", "G1", "G2"]):
+        lo, hi = doms[k]
+        assert oracle.residual(U, L, 0.1340, b2, cum[i], C=C, lo=lo, hi=hi).max() <= 1e-10 * (1 + 1e-3)
+
+
+@pytest.mark.parametrize("solver", [0, 1])
+def test_mixed_solver_iterations_close_to_fp64(setup, solver):
+    """Mixed precision (restarted or with reliable updates) converges in about
+    as many BiCGstab iterations as the FP64 solver, to the FP64 residual."""
+    L, U, ctx, gid, doms, ids = setup
+    b = inputs.point_source(L, (7, 0, 0, 0))
+    x = np.zeros_like(b)
+    rc, info32 = ctx.solve_domain(gid, ids["G2"], b, x, 12, ddml.solver_params(tol=1e-10, solver=solver))
+    assert rc == ddml.OK
+    C = oracle.clover_term(U, L, 1.769)
+    assert oracle.residual(U, L, 0.1340, b, x, C=C).max() <= 1e-10 * (1 + 1e-3)
+    rc, info64 = ctx.solve_domain(gid, ids["G2"], b, x, 12, ddml.solver_params(tol=1e-10, prec=ddml.FP64))
+    assert rc == ddml.OK
+    it32 = max(i.inner_iters for i in info32)
+    it64 = max(i.inner_iters for i in info64)
+    assert it32 <= 1.25 * it64 + 5, (it32, it64)
+    assert max(i.outer_iters for i in info32) >= 2
+
+
+def test_autotune_and_stencil_timing(setup):
+    L, U, ctx, gid, doms, ids = setup
+    R, order, grid, ms = ctx.autotune(gid, ids["G2"], 12, ddml.MIXED_FP32)
+    assert 1 <= R <= 3 and order in (0, 1) and grid in (512, 1024, 2048) and ms > 0
+    ms_odd, ms_even, b_odd, b_even = ctx.time_stencil(gid, ids["G2"], 12, ddml.MIXED_FP32, 5)
+    Vh = int(np.prod(L)) // 2
+    assert b_odd == Vh * (48 * 12 + 216) * 4 and b_even == Vh * (96 * 12 + 216) * 4
+    assert ms_odd > 0 and ms_even > 0
+    # a solve after retuning still matches the oracle
+    lo, hi = doms["G0"]
+    b = inputs.point_source(L, (7, 0, 0, 0))
+    x = np.zeros_like(b)
+    rc, _ = ctx.solve_domain(gid, ids["G0"], b, x, 12)
+    assert rc == ddml.OK
+    C = oracle.clover_term(U, L, 1.769)
+    assert oracle.residual(U, L, 0.1340, b, x, C=C, lo=lo, hi=hi).max() <= 1e-10 * (1 + 1e-3)
