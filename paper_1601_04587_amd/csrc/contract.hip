@@ -80,109 +80,110 @@ __device__ __forceinline__ double2 cm(double2 a, double2 b) {
 }
 __device__ __forceinline__ double2 cadd2(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 
-// O = M C g5 with C g5 = diag(s_2, s_2): its only entries are (0,1) = (2,3) = -i and
-// (1,0) = (3,2) = +i, so column c of O is column c^1 of M times (+i for even c, -i for odd c).
-__device__ __forceinline__ void mul_cg5_right(const double2 M[16], double2 O[16]) {
-  for (int r = 0; r < 4; ++r) {
-    const double2 m1 = M[4 * r + 1], m0 = M[4 * r + 0], m3v = M[4 * r + 3], m2 = M[4 * r + 2];
-    O[4 * r + 0] = make_double2(-m1.y, m1.x);    // +i M_{r1}
-    O[4 * r + 1] = make_double2(m0.y, -m0.x);    // -i M_{r0}
-    O[4 * r + 2] = make_double2(-m3v.y, m3v.x);  // +i M_{r3}
-    O[4 * r + 3] = make_double2(m2.y, -m2.x);    // -i M_{r2}
-  }
-}
-// (M P_-)_{r c} = (M_{r c mod 2} + M_{r, c mod 2 + 2}) / 2 ... P_- = 1/2 [[I, I],[I, I]]
-__device__ __forceinline__ void mul_pm_right(const double2 M[16], double2 O[16]) {
-  for (int r = 0; r < 4; ++r)
-    for (int c = 0; c < 4; ++c) {
-      const int c0 = c & 1;
-      O[4 * r + c] = make_double2(0.5 * (M[4 * r + c0].x + M[4 * r + c0 + 2].x),
-                                  0.5 * (M[4 * r + c0].y + M[4 * r + c0 + 2].y));
-    }
-}
-
-// S^{ab} spin matrix at a sink, from LDS holding S[alpha][a][beta][b]
-__device__ __forceinline__ void spin_block(const double2* S, int a, int b, double2 M[16]) {
-  for (int al = 0; al < 4; ++al)
-    for (int be = 0; be < 4; ++be) M[4 * al + be] = S[((al * 3 + a) * 4 + be) * 3 + b];
-}
-
 __device__ const int kEps[6][4] = {{0, 1, 2, 1}, {1, 2, 0, 1}, {2, 0, 1, 1}, {0, 2, 1, -1}, {2, 1, 0, -1}, {1, 0, 2, -1}};
 
-// One workgroup of 64 threads per (sink site, level): 36 threads take one
-// (abc, feg) pair each.
-__global__ void k_nucleon_site(const double2* __restrict__ terms, size_t V, int level_count, int nlevels_total,
-                               double2* __restrict__ W) {
-  __shared__ double2 S[144];
-  __shared__ double2 part[64];
-  const size_t y = blockIdx.x;
-  const int level = blockIdx.y;
-  const int tid = threadIdx.x;
-  if (y >= V || level >= level_count) return;
-  (void)nlevels_total;
-  // S^(level)(y,x)[alpha a][beta b] = sum_{j<=level} terms[j][3 beta + b][y][alpha][a]
-  for (int e = tid; e < 144; e += blockDim.x) {
-    const int al = e / 36, a = (e / 12) % 3, be = (e / 3) % 4, b = e % 3;
-    const int col = 3 * be + b;
-    double2 v = make_double2(0, 0);
-    for (int j = 0; j <= level; ++j) {
-      const double2 t = terms[(((size_t)j * 12 + col) * V + y) * 12 + al * 3 + a];
-      v.x += t.x;
-      v.y += t.y;
+// Eight sink sites per workgroup of 64 threads, eight threads per site; thread
+// q of a site takes the (abc, feg) pairs q, q + 8, ... of the 36.  The levels
+// are walked in order and S^(i) = sum_{j<=i} terms[j] is accumulated in LDS,
+// so each term is read once, with loads contiguous over (site, component) for
+// each source column.  Sites where S^(i) vanishes (outside the outermost
+// domain of the series) skip the spin algebra, which is exact: every product
+// there is zero.
+//
+// The spin algebra uses the rank-2 form of P_-: (M P_-)_{kc} = y_{k, c mod 2}
+// with y_{kj} = (M_{kj} + M_{k, j+2}) / 2, so M P_- N = y z with
+// z_{jq} = N_{jq} + N_{j+2, q}; W_N2 then needs 40 complex products per pair.
+constexpr int kNucSites = 8;
+constexpr int kNucThreads = 8;
+
+__device__ __forceinline__ double2 sld(const double2* S, int al, int a, int be, int b) {
+  return S[((al * 3 + a) * 4 + be) * 3 + b];
+}
+// v * (+i) for even k, v * (-i) for odd k: the phase of column k of C g5 = diag(s_2, s_2)
+__device__ __forceinline__ double2 mul_ph(double2 v, int k) {
+  return (k & 1) ? make_double2(v.y, -v.x) : make_double2(-v.y, v.x);
+}
+
+__device__ double2 nucleon_pair(const double2* S, int pair) {
+  const int* e1 = kEps[pair / 6];
+  const int* e2 = kEps[pair % 6];
+  const int a = e1[0], b = e1[1], c = e1[2];
+  const int f = e2[0], e = e2[1], g = e2[2];
+  const double sgn = (double)(e1[3] * e2[3]);
+  // X = (S^{ag})^T C g5:  X_{rk} = ph(k) S^{ag}_{k^1, r}
+  double2 X[16];
+  for (int r = 0; r < 4; ++r)
+    for (int k = 0; k < 4; ++k) X[4 * r + k] = mul_ph(sld(S, k ^ 1, a, r, g), k);
+  // W_N1 = tr[X S^{bf} C g5] tr[S^{ce} P_-]
+  double2 t1 = make_double2(0, 0);
+  for (int r = 0; r < 4; ++r)
+    for (int k = 0; k < 4; ++k) t1 = cadd2(t1, cm(X[4 * r + k], mul_ph(sld(S, k, b, r ^ 1, f), r)));
+  double2 t2 = make_double2(0, 0);
+  for (int r = 0; r < 4; ++r) {
+    const double2 u = sld(S, r, c, r & 1, e), v = sld(S, r, c, (r & 1) + 2, e);
+    t2 = make_double2(t2.x + 0.5 * (u.x + v.x), t2.y + 0.5 * (u.y + v.y));
+  }
+  const double2 w1 = cm(t1, t2);
+  // W_N2 = tr[X S^{be} P_- S^{cf} C g5] = sum_{r,k,j} X_{rk} y_{kj} z_{jr}
+  double2 y[8], z[8];
+  for (int k = 0; k < 4; ++k)
+    for (int j = 0; j < 2; ++j) {
+      const double2 u = sld(S, k, b, j, e), v = sld(S, k, b, j + 2, e);
+      y[2 * k + j] = make_double2(0.5 * (u.x + v.x), 0.5 * (u.y + v.y));
     }
-    S[e] = v;
-  }
-  __syncthreads();
-  double2 acc = make_double2(0, 0);
-  if (tid < 36) {
-    const int* e1 = kEps[tid / 6];
-    const int* e2 = kEps[tid % 6];
-    const int a = e1[0], b = e1[1], c = e1[2];
-    const int f = e2[0], e = e2[1], g = e2[2];
-    const double sgn = (double)(e1[3] * e2[3]);
-    double2 Sag[16], Sbf[16], Sce[16], Sbe[16], Scf[16], X[16], Y[16], Z[16];
-    spin_block(S, a, g, Sag);
-    spin_block(S, b, f, Sbf);
-    spin_block(S, c, e, Sce);
-    spin_block(S, b, e, Sbe);
-    spin_block(S, c, f, Scf);
-    // X = S^{ag T} Cg5
-    double2 SagT[16];
-    for (int r = 0; r < 4; ++r)
-      for (int q = 0; q < 4; ++q) SagT[4 * r + q] = Sag[4 * q + r];
-    mul_cg5_right(SagT, X);
-    // W_N1 factor 1: tr[X S^{bf} Cg5]
-    mul_cg5_right(Sbf, Y);
-    double2 t1 = make_double2(0, 0);
-    for (int r = 0; r < 4; ++r)
-      for (int k = 0; k < 4; ++k) t1 = cadd2(t1, cm(X[4 * r + k], Y[4 * k + r]));
-    // tr[S^{ce} P_-]
-    double2 PceM[16];
-    mul_pm_right(Sce, PceM);
-    double2 t2 = make_double2(0, 0);
-    for (int r = 0; r < 4; ++r) t2 = cadd2(t2, PceM[5 * r]);
-    const double2 w1 = cm(t1, t2);
-    // W_N2: tr[X S^{be} P_- S^{cf} Cg5]
-    mul_pm_right(Sbe, Y);          // Y = S^{be} P_-
-    mul_cg5_right(Scf, Z);         // Z = S^{cf} Cg5
-    double2 YZ[16];
-    for (int r = 0; r < 4; ++r)
-      for (int q = 0; q < 4; ++q) {
-        double2 s = make_double2(0, 0);
-        for (int k = 0; k < 4; ++k) s = cadd2(s, cm(Y[4 * r + k], Z[4 * k + q]));
-        YZ[4 * r + q] = s;
+  for (int j = 0; j < 2; ++j)
+    for (int q = 0; q < 4; ++q) {
+      const double2 u = sld(S, j, c, q ^ 1, f), v = sld(S, j + 2, c, q ^ 1, f);
+      z[4 * j + q] = mul_ph(make_double2(u.x + v.x, u.y + v.y), q);
+    }
+  double2 w2 = make_double2(0, 0);
+  for (int r = 0; r < 4; ++r)
+    for (int j = 0; j < 2; ++j) {
+      double2 v = make_double2(0, 0);
+      for (int k = 0; k < 4; ++k) v = cadd2(v, cm(X[4 * r + k], y[2 * k + j]));
+      w2 = cadd2(w2, cm(v, z[4 * j + r]));
+    }
+  return make_double2(sgn * (w1.x - w2.x), sgn * (w1.y - w2.y));
+}
+
+__global__ void __launch_bounds__(64) k_nucleon_site(const double2* __restrict__ terms, size_t V, int nlevels,
+                                                     double2* __restrict__ W) {
+  __shared__ double2 S[kNucSites][144];
+  __shared__ double2 part[64];
+  __shared__ int nz[kNucSites];
+  const size_t y0 = (size_t)blockIdx.x * kNucSites;
+  const int nsite = (int)(V - y0 < (size_t)kNucSites ? V - y0 : kNucSites);
+  const int tid = threadIdx.x;
+  const int ls = tid / kNucThreads, q = tid % kNucThreads;
+  for (int e = tid; e < kNucSites * 144; e += 64) S[e / 144][e % 144] = make_double2(0, 0);
+  for (int level = 0; level < nlevels; ++level) {
+    if (tid < kNucSites) nz[tid] = 0;
+    __syncthreads();
+    // term `level`, column col = 3 beta + b holds S[alpha a][beta b] at component 3 alpha + a
+    for (int e = tid; e < 12 * kNucSites * 12; e += 64) {
+      const int col = e / (kNucSites * 12), r = e % (kNucSites * 12);
+      const int site = r / 12, comp = r % 12;
+      if (site < nsite) {
+        const double2 t = terms[(((size_t)level * 12 + col) * V + y0) * 12 + r];
+        const int al = comp / 3, aa = comp % 3, be = col / 3, bb = col % 3;
+        double2& d = S[site][((al * 3 + aa) * 4 + be) * 3 + bb];
+        d.x += t.x;
+        d.y += t.y;
+        if (d.x != 0 || d.y != 0) nz[site] = 1;
       }
-    double2 w2 = make_double2(0, 0);
-    for (int r = 0; r < 4; ++r)
-      for (int k = 0; k < 4; ++k) w2 = cadd2(w2, cm(X[4 * r + k], YZ[4 * k + r]));
-    acc = make_double2(sgn * (w1.x - w2.x), sgn * (w1.y - w2.y));
-  }
-  part[tid] = acc;
-  __syncthreads();
-  if (tid == 0) {
-    double2 s = make_double2(0, 0);
-    for (int k = 0; k < 36; ++k) s = cadd2(s, part[k]);   // fixed order
-    W[(size_t)level * V + y] = s;
+    }
+    __syncthreads();
+    double2 acc = make_double2(0, 0);
+    if (ls < nsite && nz[ls])
+      for (int p = q; p < 36; p += kNucThreads) acc = cadd2(acc, nucleon_pair(S[ls], p));
+    part[tid] = acc;
+    __syncthreads();
+    if (q == 0 && ls < nsite) {
+      double2 s = part[tid];                    // fixed order over the site's threads
+      for (int k = 1; k < kNucThreads; ++k) s = cadd2(s, part[tid + k]);
+      W[(size_t)level * V + y0 + ls] = s;
+    }
+    __syncthreads();
   }
 }
 
@@ -208,7 +209,8 @@ __global__ void k_slice_sum(const double2* __restrict__ W, size_t V, int T, doub
 
 hipError_t launch_nucleon(const double2* terms, size_t V, int T, int nlevels, double2* W, double2* out,
                           hipStream_t st) {
-  hipLaunchKernelGGL(k_nucleon_site, dim3((unsigned)V, nlevels), dim3(64), 0, st, terms, V, nlevels, nlevels, W);
+  const unsigned blocks = (unsigned)((V + kNucSites - 1) / kNucSites);
+  hipLaunchKernelGGL(k_nucleon_site, dim3(blocks), dim3(64), 0, st, terms, V, nlevels, W);
   hipLaunchKernelGGL(k_slice_sum, dim3(T, nlevels), dim3(256), 0, st, W, V, T, out);
   return hipGetLastError();
 }
