@@ -86,7 +86,7 @@ def stencil_only(args):
     gid = ctx.set_gauge(U, 0.1340, 1.769)
     dom = ctx.set_domain((0, 0, 0, 0), (16,) + L[1:])
     tune = ctx.autotune(gid, dom, 12, ddml.MIXED_FP32)
-    log("autotune fp32: R=%d order=%d grid=%d" % tune[:3])
+    log("autotune fp32: R=%d order=%d grid=%d splits=%d stage=%d" % tune[:5])
     s32 = ctx.time_stencil(gid, dom, 12, ddml.MIXED_FP32, args.stencil_iters)
     log("stencil-only fp32: odd %.4f ms (%.3e B), even %.4f ms (%.3e B) -> even %.0f GB/s, odd %.0f GB/s"
         % (s32[0], s32[2], s32[1], s32[3], s32[3] / s32[1] * 1e-6, s32[2] / s32[0] * 1e-6))
@@ -99,7 +99,8 @@ def stencil_only(args):
     torch.cuda.synchronize()
     ctx.close()
     print(json.dumps({"stencil_fp32": {"ms_odd": s32[0], "ms_even": s32[1], "bytes_odd": s32[2],
-                                       "bytes_even": s32[3], "R": tune[0], "tile_order": tune[1], "grid": tune[2]},
+                                       "bytes_even": s32[3], "R": tune[0], "tile_order": tune[1], "grid": tune[2],
+                                       "splits": tune[3], "stage": tune[4]},
                       "copy_bytes_each_way": 1 << 30}), flush=True)
     return 0
 
@@ -170,8 +171,8 @@ def main():
     # the project's autotuner picks the stencil launch (rhs per thread, tile order, grid)
     tune32 = ctx.autotune(gid0, doms[0][2], 12, ddml.MIXED_FP32)
     tune64 = ctx.autotune(gid0, doms[0][2], 12, ddml.FP64)
-    log("autotune fp32 R=%d order=%d grid=%d (%.3f ms/pair); fp64 R=%d order=%d grid=%d (%.3f ms/pair)"
-        % (tune32 + tune64))
+    log("autotune fp32 R=%d order=%d grid=%d splits=%d stage=%d (%.3f ms/pair); "
+        "fp64 R=%d order=%d grid=%d splits=%d stage=%d (%.3f ms/pair)" % (tune32 + tune64))
 
     def step(j, prm=params, batched=True):
         gids = [ctx.set_gauge_region(gid0, 16 * s, 16 * s + 16, regions[j][s]) for s in range(nslab)]
@@ -219,7 +220,6 @@ def main():
 
     # --------------------------------------------------- stencil roofline
     sten32 = ctx.time_stencil(gid0, doms[0][2], 12, ddml.MIXED_FP32, args.stencil_iters)
-    sten_R = tune32[0]
     sten64 = ctx.time_stencil(gid0, doms[0][2], 12, ddml.FP64, max(4, args.stencil_iters // 2))
     ach = sten32[3] / (sten32[1] * 1e-3)
     ach_odd = sten32[2] / (sten32[0] * 1e-3)
@@ -268,13 +268,14 @@ def main():
                                "Gamma0/1/2 = 4/8/16 slices x 12 rhs, tol 1e-10" % ("x".join(map(str, L)), nslab),
                    "lattice": list(L), "kappa": kappa, "csw": csw, "solves_per_step": 3 * nslab, "nrhs": 12},
         "roofline": {"bound": "hbm", "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                     "frac": ach / PEAK_HBM, "traffic": counter_traffic("%d,1,1" % sten_R),
+                     "frac": ach / PEAK_HBM, "traffic": counter_traffic("even,R=%d,order=%d,splits=%d,stage=%d" % (tune32[0], tune32[1], tune32[3],
+                                                                                      tune32[4])),
                      "kernel": "k_hop_batch<float2> even half-stencil (Schur + fused dot), 32^3x16 domain, 12 rhs",
                      "ms_per_launch": sten32[1], "bytes_per_launch": sten32[3],
                      "odd_half": {"ms": sten32[0], "GB/s": ach_odd / 1e9},
                      "fp64_even_half_GBps": ach64 / 1e9},
-        "autotune": {"fp32": dict(zip(("R", "tile_order", "grid", "ms_pair"), tune32)),
-                     "fp64": dict(zip(("R", "tile_order", "grid", "ms_pair"), tune64))},
+        "autotune": {"fp32": dict(zip(("R", "tile_order", "grid", "splits", "stage", "ms_pair"), tune32)),
+                     "fp64": dict(zip(("R", "tile_order", "grid", "splits", "stage", "ms_pair"), tune64))},
         "fp64_one_at_a_time": fp64,
         "mixed_over_fp64": (solves_per_s / fp64["solves_per_s"]) if fp64 else None,
         "serving": serve,

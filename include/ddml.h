@@ -215,18 +215,27 @@ int ddml_contract_nucleon(ddml_ctx ctx, const double* terms, int nlevels, double
  * with the dot product (r0, out_e)); out[2], out[3]: algorithmic bytes of one
  * launch of each (every array the kernel must touch, counted once).
  * prec: DDML_FP64 or DDML_MIXED_FP32 (FP32 kernels).  R (columns per thread,
- * 1..3), order (0 linear, 1 XCD-banded tiles) and grid (workgroups) select the
- * launch; values <= 0 (order < 0) take the context's current choice.
+ * 1..3), order, grid (workgroups), splits and stage select the launch; values
+ * <= 0 (order, stage: < 0) take the context's current choice.  Tile orders: 0 linear;
+ * 1 each of the 8 XCDs owns a band of every time slice and walks the slices in
+ * turn; 2 and 3: each XCD owns an x1 range of the domain, split by x2 into 2
+ * (order 2) or 4 (order 3) sub-bands, each walked slice by slice.  splits: the
+ * ceil(nrhs / R) wavefronts that cover the columns of a 64-site tile are spread
+ * over this many workgroups (1 = one workgroup per tile; clamped to the number
+ * of wavefronts).  stage: 1 = each workgroup first copies the links and
+ * clover data of its tile to LDS, so they are read once per tile instead of
+ * once per wavefront; 0 = every wavefront reads them itself.
  * Errors: EINVAL, ENOMEM. */
 int ddml_time_stencil(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec, int iters, int R, int order,
-                      int grid, double out[4]);
+                      int grid, int splits, int stage, double out[4]);
 
-/* Autotuner: times the stencil launch variants (R in 1..3, both tile orders,
- * grid in {512, 1024, 2048}) on (gauge_id, dom_id, nrhs, prec) and makes the
- * fastest the context's choice for every later solve (the captured solver
- * graphs are rebuilt).  best[0..3] = R, order, grid, ms per odd+even pair.
+/* Autotuner: times the stencil launch variants (stage 0/1, R in 1..3, splits
+ * in 1..3, tile orders 0..3, grid in {512, 1024, 2048}) on (gauge_id, dom_id,
+ * nrhs, prec) and makes the fastest the context's choice for every later solve
+ * (the captured solver graphs are rebuilt).  best[0..5] = R, order, grid,
+ * splits, stage, ms per odd+even pair.
  * Errors: EINVAL, ENOMEM, EDEVICE. */
-int ddml_autotune(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec, double best[4]);
+int ddml_autotune(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec, double best[6]);
 
 /* ------------------------------------------------------------- serving */
 typedef struct {

@@ -311,16 +311,22 @@ int ddml_propagator_series_batch(ddml_ctx ctx, int nseries, const ddml_series_de
 }
 
 int ddml_time_stencil(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec, int iters, int R, int order,
-                      int grid, double out[4]) {
+                      int grid, int splits, int stage, double out[4]) {
   return guarded(ctx, [&](Ctx* c) {
     need(out != nullptr, "out is NULL");
     need(prec == DDML_FP64 || prec == DDML_MIXED_FP32, "unknown precision");
-    time_stencil(c, gauge_id, dom_id, nrhs, prec, iters, R, order, grid, out);
+    TuneChoice w;
+    w.R = R;
+    w.order = order;
+    w.grid = grid;
+    w.splits = splits;
+    w.stage = stage;
+    time_stencil(c, gauge_id, dom_id, nrhs, prec, iters, w, out);
     return DDML_OK;
   });
 }
 
-int ddml_autotune(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec, double best[4]) {
+int ddml_autotune(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec, double best[6]) {
   return guarded(ctx, [&](Ctx* c) {
     need(best != nullptr, "best is NULL");
     need(prec == DDML_FP64 || prec == DDML_MIXED_FP32, "unknown precision");

@@ -95,6 +95,31 @@ __device__ __forceinline__ void ld2(const double2* p, double2& a, double2& b) {
   b = make_double2(v.x, v.y);
 }
 __device__ __forceinline__ int ldg(const int* p) { return *(const DDML_GLOBAL int*)p; }
+// Streaming variants (non-temporal hint): data read or written once per
+// kernel, so that it does not push the reused neighbour spinors out of L2.
+__device__ __forceinline__ void ld2nt(const float2* p, float2& a, float2& b) {
+  const f32x4 v = __builtin_nontemporal_load((const DDML_GLOBAL f32x4*)p);
+  a = make_float2(v.x, v.y);
+  b = make_float2(v.z, v.w);
+}
+__device__ __forceinline__ void ld2nt(const double2* p, double2& a, double2& b) {
+  const DDML_GLOBAL f64x2* q = (const DDML_GLOBAL f64x2*)p;
+  const f64x2 u = __builtin_nontemporal_load(q), v = __builtin_nontemporal_load(q + 1);
+  a = make_double2(u.x, u.y);
+  b = make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void st2nt(float2* p, float2 a, float2 b) {
+  f32x4 v;
+  v.x = a.x; v.y = a.y; v.z = b.x; v.w = b.y;
+  __builtin_nontemporal_store(v, (DDML_GLOBAL f32x4*)p);
+}
+__device__ __forceinline__ void st2nt(double2* p, double2 a, double2 b) {
+  DDML_GLOBAL f64x2* q = (DDML_GLOBAL f64x2*)p;
+  f64x2 u, v;
+  u.x = a.x; u.y = a.y; v.x = b.x; v.y = b.y;
+  __builtin_nontemporal_store(u, q);
+  __builtin_nontemporal_store(v, q + 1);
+}
 __device__ __forceinline__ void st2(float2* p, float2 a, float2 b) {
   f32x4 v;
   v.x = a.x; v.y = a.y; v.z = b.x; v.w = b.y;
@@ -121,6 +146,20 @@ __device__ __forceinline__ int eo_index(const BoxGeom& g, const int y[4]) {
   return (((y[0] * g.L[1] + y[1]) * g.L[2] + y[2]) * g.L[3] + y[3]) >> 1;
 }
 
+// Number of XCDs of the device and the tile orders of the stencil.  With
+// every order but TILE_ORDER_LINEAR, workgroup b runs on XCD b % 8 and each XCD
+// walks its own part of the box:
+//   TILE_ORDER_BANDED  the XCD owns a band of every time slice and walks the
+//                      slices in order;
+//   TILE_ORDER_SUB2/4  the XCD owns an x1 range of the box, split by the x2
+//                      position of the tiles into 2 or 4 sub-bands, and walks
+//                      each sub-band slice by slice (walk table of the box).
+// Either way the neighbours of a tile (same slice, adjacent slices) are read
+// through the same L2 shortly after they were first fetched; the sub-bands
+// shorten the distance to the next time slice so it stays in the L2.
+constexpr int kXcd = 8;
+enum { TILE_ORDER_LINEAR = 0, TILE_ORDER_BANDED = 1, TILE_ORDER_SUB2 = 2, TILE_ORDER_SUB4 = 3, TILE_ORDER_NUM = 4 };
+
 // ---------------------------------------------------------- kernel argument
 // Work item of the batched launches: one domain solve (or one operator
 // application) with its own box, operator data and vectors.
@@ -139,6 +178,8 @@ template <typename T2> struct HopItem {
   int ntiles;
   double c1, c2;
   int tps;            // tiles per time slice (banded tile order), 0 = linear order
+  const int* walk;    // tile walk of the sub-banded orders (all tiles, XCD-major), may be null
+  int xoff[kXcd + 1]; // XCD x walks walk[xoff[x] .. xoff[x+1])
 };
 
 // Stencil epilogues (acc = H in on the output parity):
@@ -181,14 +222,8 @@ template <typename T2> struct SlotDesc {
   int* active;          // [nrhs]
   BiState* st;          // [nrhs]
   const double2* src64; // FP64 even-parity right-hand side [nrhs][ntiles][12][64]
+  const int* walk;      // tile walk of the sub-banded orders, as in HopItem
+  int xoff[kXcd + 1];
 };
-
-// Number of XCDs of the device and the tile order used by the stencil: with
-// TILE_ORDER_BANDED, workgroup b runs on XCD b % 8 and each XCD walks its own
-// band of every time slice, slice after slice, so the neighbours of a tile
-// (same slice, adjacent slices) are read through the same L2 shortly after
-// they were first fetched.
-constexpr int kXcd = 8;
-enum { TILE_ORDER_LINEAR = 0, TILE_ORDER_BANDED = 1 };
 
 }  // namespace ddml

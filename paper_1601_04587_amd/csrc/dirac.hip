@@ -98,11 +98,42 @@ __device__ __forceinline__ void su3_mul(const T2 u[9], bool dag, const T2 h[6], 
     }
 }
 
+// Loads of one pair from the LDS staging area of a tile (same pair stride as
+// the global layout: pair k of lane l at base + 128 k, base = area + 2 l).
+__device__ __forceinline__ void lds2(const float2* p, float2& a, float2& b) {
+  const f32x4 v = *(const __attribute__((address_space(3))) f32x4*)p;
+  a = make_float2(v.x, v.y);
+  b = make_float2(v.z, v.w);
+}
+__device__ __forceinline__ void lds2(const double2* p, double2& a, double2& b) {
+  const __attribute__((address_space(3))) f64x2* q = (const __attribute__((address_space(3))) f64x2*)p;
+  const f64x2 u = q[0], v = q[1];
+  a = make_double2(u.x, u.y);
+  b = make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void sts2(float2* p, float2 a, float2 b) {
+  f32x4 v;
+  v.x = a.x; v.y = a.y; v.z = b.x; v.w = b.y;
+  *(__attribute__((address_space(3))) f32x4*)p = v;
+}
+__device__ __forceinline__ void sts2(double2* p, double2 a, double2 b) {
+  __attribute__((address_space(3))) f64x2* q = (__attribute__((address_space(3))) f64x2*)p;
+  f64x2 u, v;
+  u.x = a.x; u.y = a.y; v.x = b.x; v.y = b.y;
+  q[0] = u;
+  q[1] = v;
+}
+
 // 18 slots of one Hermitian 6x6 block (9 pairs, pair k at base + 128 k)
 template <typename T2>
 __device__ __forceinline__ void herm6_load(const T2* __restrict__ base, T2 m[18]) {
 #pragma unroll
-  for (int k = 0; k < 9; ++k) ld2(base + 128 * k, m[2 * k], m[2 * k + 1]);
+  for (int k = 0; k < 9; ++k) ld2nt(base + 128 * k, m[2 * k], m[2 * k + 1]);
+}
+template <typename T2>
+__device__ __forceinline__ void herm6_load_lds(const T2* base, T2 m[18]) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) lds2(base + 128 * k, m[2 * k], m[2 * k + 1]);
 }
 // the 12 components of a spinor (6 pairs) starting at base
 template <typename T2>
@@ -114,6 +145,17 @@ template <typename T2>
 __device__ __forceinline__ void spinor_store(T2* __restrict__ base, const T2 v[12]) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) st2(base + 128 * k, v[2 * k], v[2 * k + 1]);
+}
+// streaming spinor access: fields read or written once per stencil launch
+template <typename T2>
+__device__ __forceinline__ void spinor_load_nt(const T2* __restrict__ base, T2 v[12]) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) ld2nt(base + 128 * k, v[2 * k], v[2 * k + 1]);
+}
+template <typename T2>
+__device__ __forceinline__ void spinor_store_nt(T2* __restrict__ base, const T2 v[12]) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) st2nt(base + 128 * k, v[2 * k], v[2 * k + 1]);
 }
 template <typename T2>
 __device__ __forceinline__ void herm6_apply(const T2 m[18], const T2 x[6], T2 y[6]) {
@@ -133,8 +175,48 @@ __device__ __forceinline__ void herm6_apply(const T2 m[18], const T2 x[6], T2 y[
 }
 
 // ------------------------------------------------------------ the stencil core
-template <typename T2, int R>
-__device__ __forceinline__ void hop_sum(const BoxGeom& g, int p, int i, const T2* __restrict__ U,
+// LDS staging of the operator data of one tile (ST = true): the links of the
+// 8 hops of every site ([hop = 2 mu + backward][5 pairs]) and the 18 clover
+// pairs, as [58 pairs][64 lanes][2] complex (the pair stride of the global
+// layout).  The workgroup reads them from HBM/L2 once instead of once per
+// wavefront (12 wavefronts share a tile at R = 1).
+constexpr int kStageLinkPairs = 8 * 5;
+constexpr int kStagePairs = kStageLinkPairs + 18;
+
+template <typename T2>
+__device__ __forceinline__ void stage_tile(const BoxGeom& g, const T2* __restrict__ U, const T2* __restrict__ clov,
+                                           int p, int tile, T2* sm) {
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6, W = blockDim.x >> 6;
+  const int i = tile * kTile + lane;
+  const bool valid = i < g.Vh;
+  const int nt = g.ntiles;
+  const int q = 1 - p;
+  int y[4] = {0, 0, 0, 0};
+  if (valid) eo_coords(g, p, i, y);
+  for (int j = w; j < kStagePairs; j += W) {
+    T2 a = mk<T2>(0, 0), b = mk<T2>(0, 0);
+    if (j < kStageLinkPairs) {
+      const int h = j / 5, k = j - 5 * h, mu = h >> 1;
+      if (valid) {
+        if ((h & 1) == 0) {
+          ld2nt(U + lidx(nt, p, mu, 2 * k, i), a, b);
+        } else {
+          int z[4] = {y[0], y[1], y[2], y[3]};
+          z[mu] = (y[mu] == 0) ? g.L[mu] - 1 : y[mu] - 1;
+          ld2nt(U + lidx(nt, q, mu, 2 * k, eo_index(g, z)), a, b);
+        }
+      }
+    } else {
+      ld2nt(clov + cidx(nt, p, 2 * (j - kStageLinkPairs), i), a, b);  // padding sites hold zeros
+    }
+    sts2(sm + j * 128 + lane * 2, a, b);
+  }
+  __syncthreads();
+}
+
+template <typename T2, int R, bool ST>
+__device__ __forceinline__ void hop_sum(const BoxGeom& g, int p, int i, const T2* __restrict__ U, const T2* sm,
                                         const T2* __restrict__ in, int r0, int nr, const int* __restrict__ act,
                                         T2 acc[R][12]) {
   int y[4];
@@ -154,10 +236,16 @@ __device__ __forceinline__ void hop_sum(const BoxGeom& g, int p, int i, const T2
       if (fwd) z[mu] = (y[mu] + 1 == g.L[mu]) ? 0 : y[mu] + 1;
       else z[mu] = (y[mu] == 0) ? g.L[mu] - 1 : y[mu] - 1;
       const int n = eo_index(g, z);
-      const T2* __restrict__ ul = fwd ? U + lidx(nt, p, mu, 0, i) : U + lidx(nt, q, mu, 0, n);
       T2 u[10];
+      if (ST) {
+        const T2* ul = sm + (2 * mu + dir) * 5 * 128 + (i & 63) * 2;
 #pragma unroll
-      for (int k = 0; k < 5; ++k) ld2(ul + 128 * k, u[2 * k], u[2 * k + 1]);
+        for (int k = 0; k < 5; ++k) lds2(ul + 128 * k, u[2 * k], u[2 * k + 1]);
+      } else {
+        const T2* __restrict__ ul = fwd ? U + lidx(nt, p, mu, 0, i) : U + lidx(nt, q, mu, 0, n);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) ld2nt(ul + 128 * k, u[2 * k], u[2 * k + 1]);
+      }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (r < nr && (act == nullptr || ldg(act + r0 + r))) {
@@ -182,15 +270,16 @@ __device__ __forceinline__ double2 wave_sum(double2 v) {
 }
 
 // Epilogue on one column.  acc = (H in)(x); cl points at slot 0 of this site.
-template <typename T2, int MODE>
-__device__ __forceinline__ void epilogue(const T2* __restrict__ cl, const T2 acc[12], const T2 aux[12],
+template <typename T2, int MODE, bool ST>
+__device__ __forceinline__ void epilogue(const T2* cl, const T2 acc[12], const T2 aux[12],
                                          const T2 ra[12], double c1, double c2, T2 out[12]) {
   using T = decltype(T2::x);
   const T k1 = (T)c1, k2 = (T)c2;
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
     T2 m[18];
-    herm6_load(cl + 128 * 9 * b, m);
+    if (ST) herm6_load_lds(cl + 128 * 9 * b, m);
+    else herm6_load(cl + 128 * 9 * b, m);
     if (MODE == MODE_CINV_HOP) {
       herm6_apply(m, acc + 6 * b, out + 6 * b);
     } else if (MODE == MODE_SCHUR) {
@@ -215,14 +304,17 @@ __device__ __forceinline__ void epilogue(const T2* __restrict__ cl, const T2 acc
   }
 }
 
-template <typename T2, int R, int MODE, int RED>
+// One tile on the output parity p.  ST: the tile's links and clover data are
+// staged in LDS at sm (stage_tile) and taken from there.
+template <typename T2, int R, int MODE, int RED, bool ST = false>
 __device__ __forceinline__ void hop_tile(const BoxGeom g, const T2* __restrict__ U, const T2* __restrict__ clov,
                                          const T2* __restrict__ in, const T2* __restrict__ aux,
                                          const T2* __restrict__ red_a, T2* __restrict__ out,
                                          double2* __restrict__ partial, const int* __restrict__ act, int p,
-                                         int nrhs, double c1, double c2, int tile) {
+                                         int nrhs, double c1, double c2, int tile, int wave0 = 0,
+                                         const T2* sm = nullptr) {
   const int lane = threadIdx.x & 63;
-  const int grp = threadIdx.x >> 6;
+  const int grp = wave0 + (threadIdx.x >> 6);
   const int r0 = grp * R;
   if (r0 >= nrhs) return;  // whole wave idle (uniform)
   const int nr = min(R, nrhs - r0);
@@ -230,8 +322,8 @@ __device__ __forceinline__ void hop_tile(const BoxGeom g, const T2* __restrict__
   const bool valid = i < g.Vh;
   const int nt = g.ntiles;
   T2 acc[R][12];
-  if (valid) hop_sum<T2, R>(g, p, i, U, in, r0, nr, act, acc);
-  const T2* __restrict__ cl = clov + cidx(nt, p, 0, i);
+  if (valid) hop_sum<T2, R, ST>(g, p, i, U, sm, in, r0, nr, act, acc);
+  const T2* cl = ST ? sm + kStageLinkPairs * 128 + lane * 2 : clov + cidx(nt, p, 0, i);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     if (r >= nr) break;
@@ -242,10 +334,10 @@ __device__ __forceinline__ void hop_tile(const BoxGeom g, const T2* __restrict__
     const size_t base = fidx(nt, col, 0, i);
     if (valid) {
       T2 av[12], ra[12], o[12];
-      if (MODE != MODE_CINV_HOP) spinor_load(aux + base, av);
-      if (MODE == MODE_RES || RED == RED_DOT) spinor_load(red_a + base, ra);
-      epilogue<T2, MODE>(cl, acc[r], av, ra, c1, c2, o);
-      spinor_store(out + base, o);
+      if (MODE != MODE_CINV_HOP) spinor_load_nt(aux + base, av);
+      if (MODE == MODE_RES || RED == RED_DOT) spinor_load_nt(red_a + base, ra);
+      epilogue<T2, MODE, ST>(cl, acc[r], av, ra, c1, c2, o);
+      spinor_store_nt(out + base, o);
       if (RED == RED_DOT) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
@@ -296,14 +388,20 @@ __device__ __forceinline__ int band_tile(int S, int lo, int bs, int local) {
 // Single-item launch (operator application, outer FP64 steps).
 template <typename T2, int R, int MODE, int RED>
 __global__ void __launch_bounds__(64 * ((kMaxRhs + R - 1) / R)) k_hop_item(HopItem<T2> it, int order) {
-  if (order == TILE_ORDER_BANDED) {
+  if (order != TILE_ORDER_LINEAR) {
     const int x = blockIdx.x % kXcd, j = blockIdx.x / kXcd, nb = gridDim.x / kXcd;
-    int S, lo, bs;
-    band_of(it.ntiles, it.tps, x, S, lo, bs);
-    const int total = bs * (it.ntiles / S);
-    for (int v = j; v < total; v += nb)
+    int S = 0, lo = 0, bs = 1, total;
+    if (order == TILE_ORDER_BANDED) {
+      band_of(it.ntiles, it.tps, x, S, lo, bs);
+      total = bs * (it.ntiles / S);
+    } else {
+      total = it.xoff[x + 1] - it.xoff[x];
+    }
+    for (int v = j; v < total; v += nb) {
+      const int tile = order == TILE_ORDER_BANDED ? band_tile(S, lo, bs, v) : ldg(it.walk + it.xoff[x] + v);
       hop_tile<T2, R, MODE, RED>(it.g, it.U, it.clov, it.in, it.aux, it.red_a, it.out, it.partial, it.active,
-                                 it.par_out, it.nrhs, it.c1, it.c2, band_tile(S, lo, bs, v));
+                                 it.par_out, it.nrhs, it.c1, it.c2, tile);
+    }
   } else {
     for (int tile = blockIdx.x; tile < it.ntiles; tile += gridDim.x)
       hop_tile<T2, R, MODE, RED>(it.g, it.U, it.clov, it.in, it.aux, it.red_a, it.out, it.partial, it.active,
@@ -312,8 +410,8 @@ __global__ void __launch_bounds__(64 * ((kMaxRhs + R - 1) / R)) k_hop_item(HopIt
 }
 
 // Batched launch over solver slots.  Linear order: virtual tile vt of the
-// batch maps to (slot, tile) through tile_start[nslots+1].  Banded order:
-// XCD x walks xstart[x][*], the prefix over slots of its band sizes.
+// batch maps to (slot, tile) through tile_start[nslots+1].  Other orders:
+// XCD x walks xstart[x][*], the prefix over slots of its share of the tiles.
 __device__ __forceinline__ int find_slot(const int* __restrict__ start, int n, int vt) {
   int lo = 0, hi = n;  // start[lo] <= vt < start[hi]
   while (hi - lo > 1) {
@@ -323,35 +421,43 @@ __device__ __forceinline__ int find_slot(const int* __restrict__ start, int n, i
   return lo;
 }
 
-template <typename T2, int R, int MODE, int RED>
+// The columns of a tile are split into ng groups of W = blockDim.x / 64
+// waves (W * R columns each); virtual item v is (tile v / ng, group v % ng),
+// so the groups of one tile run back to back on the same XCD.  ST: the
+// workgroup stages each tile's links and clover data in LDS first (the trip
+// count of the tile loop is uniform over the workgroup, so every wavefront
+// reaches both barriers).
+template <typename T2, int R, int MODE, int RED, bool ST>
 __global__ void __launch_bounds__(64 * ((kMaxRhs + R - 1) / R))
     k_hop_batch(const SlotDesc<T2>* __restrict__ slots, const int* __restrict__ tile_start,
                 const int* __restrict__ xstart, int xstride, const int* __restrict__ nslots_p, int fin, int faux,
-                int fout, int fred, int par_out, int order) {
+                int fout, int fred, int par_out, int order, int ng) {
+  __shared__ T2 sm[ST ? kStagePairs * 128 : 1];
   const int ns = *nslots_p;
-  if (order == TILE_ORDER_BANDED) {
-    const int x = blockIdx.x % kXcd, j = blockIdx.x / kXcd, nb = gridDim.x / kXcd;
-    const int* P = xstart + (size_t)x * xstride;
-    const int total = P[ns];
-    for (int v = j; v < total; v += nb) {
-      const int s = find_slot(P, ns, v);
-      const SlotDesc<T2>& d = slots[s];
+  const int W = blockDim.x >> 6;
+  const bool banded = order != TILE_ORDER_LINEAR;
+  const int x = blockIdx.x % kXcd;
+  const int* P = banded ? xstart + (size_t)x * xstride : tile_start;
+  const int first = banded ? blockIdx.x / kXcd : blockIdx.x;
+  const int step = banded ? gridDim.x / kXcd : gridDim.x;
+  const int total = P[ns] * ng;
+  for (int v = first; v < total; v += step) {
+    const int tv = v / ng, grp = v - tv * ng;
+    const int s = find_slot(P, ns, tv);
+    const SlotDesc<T2>& d = slots[s];
+    int tile = tv - P[s];
+    if (order == TILE_ORDER_BANDED) {
       int S, lo, bs;
       band_of(d.ntiles, d.tps, x, S, lo, bs);
-      const int tile = band_tile(S, lo, bs, v - P[s]);
-      hop_tile<T2, R, MODE, RED>(d.g, d.U, d.Ainv, d.f[fin], faux >= 0 ? d.f[faux] : nullptr,
-                                 fred >= 0 ? d.f[fred] : nullptr, d.f[fout], d.partial, d.active, par_out, d.nrhs,
-                                 d.kappa * d.kappa, 0.0, tile);
+      tile = band_tile(S, lo, bs, tile);
+    } else if (order != TILE_ORDER_LINEAR) {
+      tile = ldg(d.walk + d.xoff[x] + tile);
     }
-  } else {
-    const int total = tile_start[ns];
-    for (int vt = blockIdx.x; vt < total; vt += gridDim.x) {
-      const int s = find_slot(tile_start, ns, vt);
-      const SlotDesc<T2>& d = slots[s];
-      hop_tile<T2, R, MODE, RED>(d.g, d.U, d.Ainv, d.f[fin], faux >= 0 ? d.f[faux] : nullptr,
-                                 fred >= 0 ? d.f[fred] : nullptr, d.f[fout], d.partial, d.active, par_out, d.nrhs,
-                                 d.kappa * d.kappa, 0.0, vt - tile_start[s]);
-    }
+    if (ST) stage_tile<T2>(d.g, d.U, d.Ainv, par_out, tile, sm);
+    hop_tile<T2, R, MODE, RED, ST>(d.g, d.U, d.Ainv, d.f[fin], faux >= 0 ? d.f[faux] : nullptr,
+                                   fred >= 0 ? d.f[fred] : nullptr, d.f[fout], d.partial, d.active, par_out, d.nrhs,
+                                   d.kappa * d.kappa, 0.0, tile, grp * W, sm);
+    if (ST) __syncthreads();
   }
 }
 
@@ -392,7 +498,9 @@ template <typename T2>
 static hipError_t hop_item_impl(const HopItem<T2>& it, int mode, int red, int R, int order, hipStream_t st) {
   const int block = 64 * ((it.nrhs + R - 1) / R);
   int grid = it.ntiles < 65535 ? it.ntiles : 65535;
-  if (order == TILE_ORDER_BANDED) grid = ((grid + kXcd - 1) / kXcd) * kXcd;
+  if (order < 0 || order >= TILE_ORDER_NUM || (order >= TILE_ORDER_SUB2 && it.walk == nullptr))
+    return hipErrorInvalidValue;
+  if (order != TILE_ORDER_LINEAR) grid = ((grid + kXcd - 1) / kXcd) * kXcd;
   DDML_HOP_DISPATCH(T2, 1, MODE_CINV_HOP, RED_NONE)
   DDML_HOP_DISPATCH(T2, 1, MODE_SCHUR, RED_NONE)
   DDML_HOP_DISPATCH(T2, 1, MODE_M, RED_NONE)
@@ -413,19 +521,27 @@ hipError_t launch_hop_item(const HopItem<float2>& it, int mode, int red, int R, 
   return hop_item_impl(it, mode, red, R, order, st);
 }
 
-#define DDML_HOPB_DISPATCH(T2, Rv, MODEv, REDv)                                                              \
-  if (R == Rv && mode == MODEv && red == REDv) {                                                             \
-    hipLaunchKernelGGL((k_hop_batch<T2, Rv, MODEv, REDv>), dim3(grid), dim3(block), 0, st, slots, tile_start, \
-                       xstart, xstride, nslots_p, fin, faux, fout, fred, par_out, order);                   \
-    return hipGetLastError();                                                                                \
+#define DDML_HOPB_DISPATCH1(T2, Rv, MODEv, REDv, STv)                                                    \
+  if (R == Rv && mode == MODEv && red == REDv && (stage != 0) == STv) {                                  \
+    hipLaunchKernelGGL((k_hop_batch<T2, Rv, MODEv, REDv, STv>), dim3(grid), dim3(block), 0, st, slots,   \
+                       tile_start, xstart, xstride, nslots_p, fin, faux, fout, fred, par_out, order, ng); \
+    return hipGetLastError();                                                                            \
   }
+#define DDML_HOPB_DISPATCH(T2, Rv, MODEv, REDv)     \
+  DDML_HOPB_DISPATCH1(T2, Rv, MODEv, REDv, false) \
+  DDML_HOPB_DISPATCH1(T2, Rv, MODEv, REDv, true)
 
 template <typename T2>
 static hipError_t hop_batch_impl(const SlotDesc<T2>* slots, const int* tile_start, const int* xstart, int xstride,
                                  const int* nslots_p, int nrhs, int R, int mode, int red, int fin, int faux, int fout,
-                                 int fred, int par_out, int grid, int order, hipStream_t st) {
-  const int block = 64 * ((nrhs + R - 1) / R);
-  if (order == TILE_ORDER_BANDED && grid % kXcd) return hipErrorInvalidValue;
+                                 int fred, int par_out, int grid, int order, int splits, int stage,
+                                 hipStream_t st) {
+  // nw waves cover the columns of a tile; they are split into ng blocks of W waves
+  const int nw = (nrhs + R - 1) / R;
+  if (splits < 1 || splits > nw) return hipErrorInvalidValue;
+  const int W = (nw + splits - 1) / splits, ng = (nw + W - 1) / W;
+  const int block = 64 * W;
+  if (order < 0 || order >= TILE_ORDER_NUM || (order != TILE_ORDER_LINEAR && grid % kXcd)) return hipErrorInvalidValue;
   DDML_HOPB_DISPATCH(T2, 1, MODE_CINV_HOP, RED_NONE)
   DDML_HOPB_DISPATCH(T2, 1, MODE_SCHUR, RED_DOT)
   DDML_HOPB_DISPATCH(T2, 1, MODE_SCHUR, RED_TS)
@@ -440,15 +556,15 @@ static hipError_t hop_batch_impl(const SlotDesc<T2>* slots, const int* tile_star
 
 hipError_t launch_hop_batch(const SlotDesc<float2>* slots, const int* tile_start, const int* xstart, int xstride,
                             const int* nslots_p, int nrhs, int R, int mode, int red, int fin, int faux, int fout,
-                            int fred, int par_out, int grid, int order, hipStream_t st) {
+                            int fred, int par_out, int grid, int order, int splits, int stage, hipStream_t st) {
   return hop_batch_impl(slots, tile_start, xstart, xstride, nslots_p, nrhs, R, mode, red, fin, faux, fout, fred,
-                        par_out, grid, order, st);
+                        par_out, grid, order, splits, stage, st);
 }
 hipError_t launch_hop_batch(const SlotDesc<double2>* slots, const int* tile_start, const int* xstart, int xstride,
                             const int* nslots_p, int nrhs, int R, int mode, int red, int fin, int faux, int fout,
-                            int fred, int par_out, int grid, int order, hipStream_t st) {
+                            int fred, int par_out, int grid, int order, int splits, int stage, hipStream_t st) {
   return hop_batch_impl(slots, tile_start, xstart, xstride, nslots_p, nrhs, R, mode, red, fin, faux, fout, fred,
-                        par_out, grid, order, st);
+                        par_out, grid, order, splits, stage, st);
 }
 
 template <typename T2>

@@ -228,7 +228,7 @@ static void fill_spec(Ctx* c, const GaugeRec& g, const DomainRec& d, BlockSpec& 
 static size_t opblock_bytes(size_t nsites) {  // nsites = 2 * ntiles * 64
   return DevPool::round(kLinkSlots * nsites * sizeof(double2)) + DevPool::round(kLinkSlots * nsites * sizeof(float2)) +
          2 * DevPool::round(kCloverSlots * nsites * sizeof(double2)) +
-         DevPool::round(kCloverSlots * nsites * sizeof(float2));
+         DevPool::round(kCloverSlots * nsites * sizeof(float2)) + 2 * DevPool::round(sizeof(int) * nsites / 128);
 }
 
 static void evict_blocks(Ctx* c) {
@@ -236,6 +236,65 @@ static void evict_blocks(Ctx* c) {
     if (it->second.use_count() == 1) it = c->blocks.erase(it);
     else ++it;
   }
+}
+
+// Tile walk of the sub-banded orders: XCD x takes the x1 range
+// [x L1 / 8, (x+1) L1 / 8) of the box, splits its tiles by their x2 position
+// inside the (t, x1) plane into nsub sub-bands and walks each sub-band slice by
+// slice (t outermost, then x1, then the tiles of the plane).  A box whose
+// (x2, x3) planes are not a whole number of tiles, or with L1 < 8, gets the
+// banded walk instead.  The walk is checked to be a permutation of the tiles.
+static void build_walk(const BoxGeom& g, int tps, int nsub, std::vector<int>& walk, int xoff[kXcd + 1]) {
+  walk.clear();
+  const int nt = g.ntiles;
+  const long plane = (long)g.L[2] * g.L[3] / 2;
+  if (tps > 0 && plane % kTile == 0 && g.L[1] >= kXcd) {
+    const int tpp = (int)(plane / kTile);
+    const int nslice = nt / tps;
+    for (int x = 0; x < kXcd; ++x) {
+      xoff[x] = (int)walk.size();
+      const int a = x * g.L[1] / kXcd, b = (x + 1) * g.L[1] / kXcd;
+      for (int sb = 0; sb < nsub; ++sb) {
+        const int glo = sb * tpp / nsub, ghi = (sb + 1) * tpp / nsub;
+        for (int t = 0; t < nslice; ++t)
+          for (int x1 = a; x1 < b; ++x1)
+            for (int gg = glo; gg < ghi; ++gg) walk.push_back(t * tps + x1 * tpp + gg);
+      }
+    }
+  } else {
+    const int S = tps > 0 ? tps : nt;
+    for (int x = 0; x < kXcd; ++x) {
+      xoff[x] = (int)walk.size();
+      const int lo = (int)((long)x * S / kXcd), bs = (int)((long)(x + 1) * S / kXcd) - lo;
+      for (int v = 0; v < bs * (nt / S); ++v) walk.push_back((v / bs) * S + lo + v % bs);
+    }
+  }
+  xoff[kXcd] = (int)walk.size();
+  std::vector<char> seen(nt, 0);
+  bool ok = (int)walk.size() == nt;
+  for (int t : walk) {
+    if (t < 0 || t >= nt || seen[t]) { ok = false; break; }
+    seen[t] = 1;
+  }
+  if (!ok) throw Error{DDML_EDEVICE, "internal: tile walk is not a permutation"};
+}
+
+// Attaches the walk of `order` (if it uses one) to a kernel argument.
+template <typename D>
+static void attach_walk(D& d, const OpBlock& ob, int order) {
+  if (order >= TILE_ORDER_SUB2) {
+    const int w = order - TILE_ORDER_SUB2;
+    d.walk = ob.walk[w].as<int>();
+    for (int x = 0; x <= kXcd; ++x) d.xoff[x] = ob.xoff[w][x];
+  } else {
+    d.walk = nullptr;
+  }
+}
+
+// Tiles XCD x walks in one box under `order` (not used by TILE_ORDER_LINEAR).
+template <typename D>
+static int xcd_share(const D& d, int order, int x) {
+  return order == TILE_ORDER_BANDED ? band_count(d.ntiles, d.tps, x) : d.xoff[x + 1] - d.xoff[x];
 }
 
 std::shared_ptr<OpBlock> opblock(Ctx* c, int gauge_id, int dom_id) {
@@ -261,6 +320,13 @@ std::shared_ptr<OpBlock> opblock(Ctx* c, int gauge_id, int dom_id) {
   ob->Ainv32 = DBuf(c->pool.get(), kCloverSlots * ns * sizeof(float2));
   for (DBuf* b : {&ob->U64, &ob->U32, &ob->A64, &ob->Ainv64, &ob->Ainv32})
     DDML_HIP(hipMemsetAsync(b->p, 0, b->bytes, c->stream));
+  std::vector<int> walks[2];
+  for (int w = 0; w < 2; ++w) {
+    build_walk(ob->g, ob->tps, w == 0 ? 2 : 4, walks[w], ob->xoff[w]);
+    ob->walk[w] = DBuf(c->pool.get(), sizeof(int) * walks[w].size());
+    DDML_HIP(hipMemcpyAsync(ob->walk[w].p, walks[w].data(), sizeof(int) * walks[w].size(), hipMemcpyHostToDevice,
+                            c->stream));
+  }
   GaugeView gv;
   gv.base = git->second.base->as<double2>();
   gv.region = git->second.region ? git->second.region->as<double2>() : nullptr;
@@ -291,13 +357,14 @@ size_t solve_footprint(Ctx* c, int dom_id, int nrhs, int prec) {
 }
 
 // ------------------------------------------------------------ operators
-static HopItem<double2> item64(const OpBlock& ob, int nrhs) {
+static HopItem<double2> item64(const OpBlock& ob, int nrhs, int order) {
   HopItem<double2> it{};
   it.g = ob.g;
   it.U = ob.U64.as<double2>();
   it.nrhs = nrhs;
   it.ntiles = ob.ntiles;
   it.tps = ob.tps;
+  attach_walk(it, ob, order);
   return it;
 }
 
@@ -314,7 +381,7 @@ void apply_D(Ctx* c, int gauge_id, int dom_id, const double* in, double* out, in
   DDML_HIP(launch_gather(cin, ob->bs, 1, nrhs, 1.0, xo.as<double2>(), st));
   const double kappa = ob->bs.kappa;
   for (int p = 0; p < 2; ++p) {
-    HopItem<double2> it = item64(*ob, nrhs);
+    HopItem<double2> it = item64(*ob, nrhs, c->tune64.order);
     it.clov = ob->A64.as<double2>();
     it.in = p == 0 ? xo.as<double2>() : xe.as<double2>();
     it.aux = p == 0 ? xe.as<double2>() : xo.as<double2>();
@@ -341,6 +408,7 @@ static void schur_apply(Ctx* c, const OpBlock& ob, const T2* U, const T2* Ainv, 
   it.nrhs = nrhs;
   it.ntiles = ob.ntiles;
   it.tps = ob.tps;
+  attach_walk(it, ob, tn.order);
   it.in = xe;
   it.out = tmp;
   it.par_out = 1;
@@ -386,14 +454,16 @@ BatchRunner<T2>::~BatchRunner() {
 }
 
 template <typename T2>
-void BatchRunner<T2>::init(Ctx* c, int nrhs_, int R_, int K_, int grid_, int max_slots_, int order_) {
+void BatchRunner<T2>::init(Ctx* c, int nrhs_, const TuneChoice& tn, int max_slots_) {
   ctx = c;
   nrhs = nrhs_;
-  R = R_;
-  K = K_;
-  grid = ((grid_ + kXcd - 1) / kXcd) * kXcd;
+  R = tn.R;
+  K = tn.K;
+  grid = ((tn.grid + kXcd - 1) / kXcd) * kXcd;
   max_slots = max_slots_;
-  order = order_;
+  order = tn.order;
+  splits = std::min(tn.splits, (nrhs + R - 1) / R);
+  stage = tn.stage;
   table = DBuf(c->pool.get(), sizeof(SlotDesc<T2>) * max_slots);
   tstart = DBuf(c->pool.get(), sizeof(int) * (max_slots + 1));
   xstart = DBuf(c->pool.get(), sizeof(int) * kXcd * (max_slots + 1));
@@ -423,20 +493,32 @@ void BatchRunner<T2>::capture() {
   DDML_HIP(hipStreamSynchronize(s));
   hipGraph_t graph = nullptr;
   DDML_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  // a launcher that rejects its arguments returns an error without touching
+  // the stream: keep the first one and fail after the capture is closed
+  hipError_t first = hipSuccess;
+  auto chk = [&](hipError_t r) { if (first == hipSuccess && r != hipSuccess) first = r; };
   for (int k = 0; k < K; ++k) {
-    (void)launch_vec(tb, ts, ns, nrhs, VEC_P, grid, s);
-    (void)launch_hop_batch(tb, ts, xs, xw, ns, nrhs, R, MODE_CINV_HOP, RED_NONE, F_P, -1, F_TMP, -1, 1, grid, order, s);
-    (void)launch_hop_batch(tb, ts, xs, xw, ns, nrhs, R, MODE_SCHUR, RED_DOT, F_TMP, F_P, F_V, F_RH, 0, grid, order, s);
-    (void)launch_fin(tb, ns, max_slots, FIN_ALPHA, s);
-    (void)launch_vec(tb, ts, ns, nrhs, VEC_S, grid, s);
-    (void)launch_hop_batch(tb, ts, xs, xw, ns, nrhs, R, MODE_CINV_HOP, RED_NONE, F_S, -1, F_TMP, -1, 1, grid, order, s);
-    (void)launch_hop_batch(tb, ts, xs, xw, ns, nrhs, R, MODE_SCHUR, RED_TS, F_TMP, F_S, F_T, -1, 0, grid, order, s);
-    (void)launch_fin(tb, ns, max_slots, FIN_OMEGA, s);
-    (void)launch_vec(tb, ts, ns, nrhs, VEC_XR, grid, s);
-    (void)launch_fin(tb, ns, max_slots, FIN_RHO, s);
+    chk(launch_vec(tb, ts, ns, nrhs, VEC_P, grid, s));
+    chk(launch_hop_batch(tb, ts, xs, xw, ns, nrhs, R, MODE_CINV_HOP, RED_NONE, F_P, -1, F_TMP, -1, 1, grid, order,
+                         splits, stage, s));
+    chk(launch_hop_batch(tb, ts, xs, xw, ns, nrhs, R, MODE_SCHUR, RED_DOT, F_TMP, F_P, F_V, F_RH, 0, grid, order,
+                         splits, stage, s));
+    chk(launch_fin(tb, ns, max_slots, FIN_ALPHA, s));
+    chk(launch_vec(tb, ts, ns, nrhs, VEC_S, grid, s));
+    chk(launch_hop_batch(tb, ts, xs, xw, ns, nrhs, R, MODE_CINV_HOP, RED_NONE, F_S, -1, F_TMP, -1, 1, grid, order,
+                         splits, stage, s));
+    chk(launch_hop_batch(tb, ts, xs, xw, ns, nrhs, R, MODE_SCHUR, RED_TS, F_TMP, F_S, F_T, -1, 0, grid, order,
+                         splits, stage, s));
+    chk(launch_fin(tb, ns, max_slots, FIN_OMEGA, s));
+    chk(launch_vec(tb, ts, ns, nrhs, VEC_XR, grid, s));
+    chk(launch_fin(tb, ns, max_slots, FIN_RHO, s));
   }
   hipError_t e = hipStreamEndCapture(s, &graph);
   if (e != hipSuccess) throw Error{DDML_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(e)};
+  if (first != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    throw Error{DDML_EDEVICE, std::string("launch in capture rejected: ") + hipGetErrorString(first)};
+  }
   e = hipGetLastError();
   if (e != hipSuccess) throw Error{DDML_EDEVICE, std::string("launch in capture failed: ") + hipGetErrorString(e)};
   if (exec) (void)hipGraphExecDestroy(exec);
@@ -453,10 +535,10 @@ int BatchRunner<T2>::members() const {
 }
 
 template <typename T2>
-static SlotDesc<T2> make_desc(const Solve* s, BiState* st, int* act);
+static SlotDesc<T2> make_desc(const Solve* s, BiState* st, int* act, int order);
 
 template <>
-SlotDesc<float2> make_desc<float2>(const Solve* s, BiState* st, int* act) {
+SlotDesc<float2> make_desc<float2>(const Solve* s, BiState* st, int* act, int order) {
   SlotDesc<float2> d{};
   d.g = s->ob->g;
   d.nrhs = s->nrhs;
@@ -470,10 +552,11 @@ SlotDesc<float2> make_desc<float2>(const Solve* s, BiState* st, int* act) {
   d.active = act;
   d.st = st;
   d.src64 = s->te.as<double2>();
+  attach_walk(d, *s->ob, order);
   return d;
 }
 template <>
-SlotDesc<double2> make_desc<double2>(const Solve* s, BiState* st, int* act) {
+SlotDesc<double2> make_desc<double2>(const Solve* s, BiState* st, int* act, int order) {
   SlotDesc<double2> d{};
   d.g = s->ob->g;
   d.nrhs = s->nrhs;
@@ -487,6 +570,7 @@ SlotDesc<double2> make_desc<double2>(const Solve* s, BiState* st, int* act) {
   d.active = act;
   d.st = st;
   d.src64 = s->te.as<double2>();
+  attach_walk(d, *s->ob, order);
   return d;
 }
 
@@ -498,7 +582,7 @@ int BatchRunner<T2>::join(Solve* s) {
   if (slot < 0) return -1;
   BiState* st = st_all.as<BiState>() + (size_t)slot * kMaxRhs;
   int* act = act_all.as<int>() + (size_t)slot * kMaxRhs;
-  h_table[slot] = make_desc<T2>(s, st, act);
+  h_table[slot] = make_desc<T2>(s, st, act, order);
   slot_of[slot] = s;
   s->slot = slot;
   dirty = true;
@@ -525,7 +609,7 @@ void BatchRunner<T2>::upload() {
   for (int x = 0; x < kXcd; ++x) {
     int* P = h_xstart.data() + (size_t)x * (max_slots + 1);
     for (int i = 0; i < max_slots; ++i)
-      P[i + 1] = P[i] + (slot_of[i] ? band_count(h_table[i].ntiles, h_table[i].tps, x) : 0);
+      P[i + 1] = P[i] + (slot_of[i] && order != TILE_ORDER_LINEAR ? xcd_share(h_table[i], order, x) : 0);
   }
   DDML_HIP(hipMemcpyAsync(table.p, h_table.data(), sizeof(SlotDesc<T2>) * max_slots, hipMemcpyHostToDevice,
                           ctx->stream));
@@ -580,7 +664,7 @@ BatchRunner<float2>& runner<float2>(Ctx* c, int nrhs) {
   auto& r = c->run32[nrhs];
   if (!r) {
     r.reset(new BatchRunner<float2>());
-    r->init(c, nrhs, c->tune32.R, c->tune32.K, c->tune32.grid, 64, c->tune32.order);
+    r->init(c, nrhs, c->tune32, 64);
   }
   return *r;
 }
@@ -589,7 +673,7 @@ BatchRunner<double2>& runner<double2>(Ctx* c, int nrhs) {
   auto& r = c->run64[nrhs];
   if (!r) {
     r.reset(new BatchRunner<double2>());
-    r->init(c, nrhs, c->tune64.R, c->tune64.K, c->tune64.grid, 64, c->tune64.order);
+    r->init(c, nrhs, c->tune64, 64);
   }
   return *r;
 }
@@ -644,7 +728,7 @@ static void launch_residual(Ctx* c, Solve* s) {
   const OpBlock& ob = *s->ob;
   const int nt = ob.ntiles;
   for (int p = 0; p < 2; ++p) {
-    HopItem<double2> it = item64(ob, s->nrhs);
+    HopItem<double2> it = item64(ob, s->nrhs, c->tune64.order);
     it.clov = ob.A64.as<double2>();
     it.in = p == 0 ? s->xo.as<double2>() : s->xe.as<double2>();
     it.aux = p == 0 ? s->xe.as<double2>() : s->xo.as<double2>();
@@ -664,7 +748,7 @@ static void launch_prepare(Ctx* c, Solve* s) {
   const OpBlock& ob = *s->ob;
   DDML_HIP(launch_clover_apply(ob.g, ob.Ainv64.as<double2>(), 1, s->ro.as<double2>(), s->to.as<double2>(), s->nrhs,
                                c->stream));
-  HopItem<double2> it = item64(ob, s->nrhs);
+  HopItem<double2> it = item64(ob, s->nrhs, c->tune64.order);
   it.clov = ob.Ainv64.as<double2>();
   it.in = s->to.as<double2>();
   it.aux = s->re.as<double2>();
@@ -680,7 +764,7 @@ static void launch_export(Ctx* c, Solve* s) {
   const OpBlock& ob = *s->ob;
   const size_t n = (size_t)s->nrhs * ob.field;
   DDML_HIP(launch_cast_to_d(s->f[F_X].as<T2>(), s->te.as<double2>(), n, c->stream));
-  HopItem<double2> it = item64(ob, s->nrhs);
+  HopItem<double2> it = item64(ob, s->nrhs, c->tune64.order);
   it.clov = ob.Ainv64.as<double2>();
   it.in = s->te.as<double2>();
   it.aux = s->ro.as<double2>();
@@ -841,7 +925,7 @@ void solve_finish(Ctx* c, Solve* s) {
 
 template <typename T2>
 static void time_stencil_t(Ctx* c, const OpBlock& ob, const T2* U, const T2* Ainv, int nrhs, int iters, int R,
-                           int order, int grid, double out[4]) {
+                           int order, int grid, int splits, int stage, double out[4]) {
   hipStream_t st = c->stream;
   const size_t Vh = ob.g.Vh, n = (size_t)nrhs * ob.field;
   DevPool* P = c->pool.get();
@@ -866,6 +950,7 @@ static void time_stencil_t(Ctx* c, const OpBlock& ob, const T2* U, const T2* Ain
   d.f[F_RH] = fR.as<T2>();
   d.partial = part.as<double2>();
   d.active = act.as<int>();
+  attach_walk(d, ob, order);
   int h_ts[2] = {0, ob.ntiles}, one = 1;
   DDML_HIP(hipMemcpyAsync(tab.p, &d, sizeof(d), hipMemcpyHostToDevice, st));
   DDML_HIP(hipMemcpyAsync(ts.p, h_ts, sizeof(h_ts), hipMemcpyHostToDevice, st));
@@ -873,17 +958,17 @@ static void time_stencil_t(Ctx* c, const OpBlock& ob, const T2* U, const T2* Ain
   int h_xs[kXcd * 2];
   for (int x = 0; x < kXcd; ++x) {
     h_xs[2 * x] = 0;
-    h_xs[2 * x + 1] = band_count(ob.ntiles, ob.tps, x);
+    h_xs[2 * x + 1] = order == TILE_ORDER_LINEAR ? 0 : xcd_share(d, order, x);
   }
   DDML_HIP(hipMemcpyAsync(xs.p, h_xs, sizeof(h_xs), hipMemcpyHostToDevice, st));
   auto* tb = tab.as<SlotDesc<T2>>();
   auto launch = [&](int which) {
     if (which == 0)
       DDML_HIP(launch_hop_batch(tb, ts.as<int>(), xs.as<int>(), 2, ns.as<int>(), nrhs, R, MODE_CINV_HOP, RED_NONE,
-                                F_P, -1, F_TMP, -1, 1, grid, order, st));
+                                F_P, -1, F_TMP, -1, 1, grid, order, splits, stage, st));
     else
       DDML_HIP(launch_hop_batch(tb, ts.as<int>(), xs.as<int>(), 2, ns.as<int>(), nrhs, R, MODE_SCHUR, RED_DOT, F_TMP,
-                                F_P, F_V, F_RH, 0, grid, order, st));
+                                F_P, F_V, F_RH, 0, grid, order, splits, stage, st));
   };
   for (int w = 0; w < 3; ++w) { launch(0); launch(1); }
   std::vector<hipEvent_t> ev(2 * iters + 1);
@@ -915,39 +1000,51 @@ static void time_stencil_t(Ctx* c, const OpBlock& ob, const T2* U, const T2* Ain
   out[3] = (double)Vh * (96.0 * nrhs + 144.0 + 72.0) * s;
 }
 
-void time_stencil(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, int iters, int R, int order, int grid,
+void time_stencil(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, int iters, const TuneChoice& want,
                   double out[4]) {
   if (nrhs < 1 || nrhs > kMaxRhs || iters < 1) throw Error{DDML_EINVAL, "bad nrhs or iters"};
   const TuneChoice& tn = c->tune(prec);
-  if (R <= 0) R = tn.R;
-  if (order < 0) order = tn.order;
-  if (grid <= 0) grid = tn.grid;
-  if (R < 1 || R > 3 || (order != TILE_ORDER_LINEAR && order != TILE_ORDER_BANDED))
-    throw Error{DDML_EINVAL, "R must be 1..3 and order 0 or 1"};
+  const int R = want.R > 0 ? want.R : tn.R;
+  const int order = want.order >= 0 ? want.order : tn.order;
+  int grid = want.grid > 0 ? want.grid : tn.grid;
+  int splits = want.splits > 0 ? want.splits : tn.splits;
+  const int stage = want.stage >= 0 ? want.stage : tn.stage;
+  if (R < 1 || R > 3 || order >= TILE_ORDER_NUM || stage > 1)
+    throw Error{DDML_EINVAL, "R must be 1..3, order 0..3 and stage 0 or 1"};
+  splits = std::min(splits, (nrhs + R - 1) / R);
   grid = ((grid + kXcd - 1) / kXcd) * kXcd;
   auto ob = opblock(c, gauge_id, dom_id);
   if (prec == DDML_FP64)
     time_stencil_t<double2>(c, *ob, ob->U64.as<double2>(), ob->Ainv64.as<double2>(), nrhs, iters, R, order, grid,
-                            out);
+                            splits, stage, out);
   else
-    time_stencil_t<float2>(c, *ob, ob->U32.as<float2>(), ob->Ainv32.as<float2>(), nrhs, iters, R, order, grid, out);
+    time_stencil_t<float2>(c, *ob, ob->U32.as<float2>(), ob->Ainv32.as<float2>(), nrhs, iters, R, order, grid,
+                           splits, stage, out);
 }
 
-void autotune(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, double best[4]) {
+void autotune(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, double best[6]) {
   double bt = 1e300;
   TuneChoice b = c->tune(prec);
-  for (int R = 1; R <= 3; ++R)
-    for (int order = 0; order <= 1; ++order)
-      for (int grid : {512, 1024, 2048}) {
-        double o[4];
-        time_stencil(c, gauge_id, dom_id, nrhs, prec, 5, R, order, grid, o);
-        const double t = o[0] + o[1];
-        if (t < bt) {
-          bt = t;
-          b.R = R;
-          b.order = order;
-          b.grid = grid;
-        }
+  for (int stage = 0; stage <= 1; ++stage)
+    for (int R = 1; R <= 3; ++R)
+      for (int splits = 1; splits <= 3; ++splits) {
+        if (splits > (nrhs + R - 1) / R) continue;
+        for (int order = 0; order < TILE_ORDER_NUM; ++order)
+          for (int grid : {512, 1024, 2048}) {
+            TuneChoice w = b;
+            w.R = R;
+            w.order = order;
+            w.grid = grid;
+            w.splits = splits;
+            w.stage = stage;
+            double o[4];
+            time_stencil(c, gauge_id, dom_id, nrhs, prec, 4, w, o);
+            const double t = o[0] + o[1];
+            if (t < bt) {
+              bt = t;
+              b = w;
+            }
+          }
       }
   c->tune(prec) = b;
   c->run32.clear();  // graphs are captured with the launch choice: rebuild on next use
@@ -955,7 +1052,9 @@ void autotune(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, double best[
   best[0] = b.R;
   best[1] = b.order;
   best[2] = b.grid;
-  best[3] = bt;
+  best[3] = b.splits;
+  best[4] = b.stage;
+  best[5] = bt;
 }
 
 void run_solves(Ctx* c, std::vector<Solve*>& solves) {

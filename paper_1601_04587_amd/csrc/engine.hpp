@@ -97,6 +97,8 @@ struct OpBlock {
   size_t field = 0;        // complex numbers in one [12-column] field: nrhs * 12 * ntiles * 64 / nrhs
   DBuf U64, A64, Ainv64;   // FP64 operator data
   DBuf U32, Ainv32;        // FP32 copies for the inner solve
+  DBuf walk[2];            // tile walks of TILE_ORDER_SUB2 / TILE_ORDER_SUB4
+  int xoff[2][kXcd + 1] = {};
   size_t bytes = 0;
 };
 
@@ -129,12 +131,23 @@ struct Solve {
   uint64_t tag = 0;              // serving ticket (0 for direct calls)
 };
 
+// Launch choice of the batched stencil: columns per thread R, captured
+// iterations K, workgroups, tile order and column splits (workgroups per tile).
+struct TuneChoice {
+  int R = 1;
+  int K = 8;
+  int grid = 1024;
+  int order = TILE_ORDER_BANDED;
+  int splits = 1;
+  int stage = 0;
+};
+
 // Batched inner solver for one precision and nrhs: a slot table in device
 // memory and a captured graph of K BiCGstab iterations over it.
 template <typename T2>
 struct BatchRunner {
   Ctx* ctx = nullptr;
-  int nrhs = 0, R = 3, K = 8, grid = 1024, max_slots = 64;
+  int nrhs = 0, R = 3, K = 8, grid = 1024, max_slots = 64, splits = 1, stage = 0;
   DBuf table, tstart, xstart, nslots, st_all, act_all;
   int order = TILE_ORDER_BANDED;
   std::vector<SlotDesc<T2>> h_table;
@@ -145,7 +158,7 @@ struct BatchRunner {
   bool dirty = true;
   int nused = 0;                  // highest used slot + 1
   ~BatchRunner();
-  void init(Ctx* c, int nrhs_, int R_, int K_, int grid_, int max_slots_, int order_);
+  void init(Ctx* c, int nrhs_, const TuneChoice& tn, int max_slots_);
   void capture();
   int join(Solve* s);             // returns slot or -1 if full
   void leave(Solve* s);
@@ -154,12 +167,6 @@ struct BatchRunner {
   int members() const;
 };
 
-struct TuneChoice {
-  int R = 1;
-  int K = 8;
-  int grid = 1024;
-  int order = TILE_ORDER_BANDED;
-};
 
 struct Server;
 
@@ -207,12 +214,13 @@ void solve_finish(Ctx* c, Solve* s);                 // scatter, info, free
 void check_params(const ddml_solver_params* p);
 // Times the two stencil kernels of the inner solver (k_hop_batch, CINV_HOP and
 // SCHUR with its fused dot product) on one slot; out = {ms_cinv, ms_schur,
-// bytes_cinv, bytes_schur} per launch (algorithmic bytes).  R, order, grid of
-// the launch: <= 0 selects the context's current choice.
-void time_stencil(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, int iters, int R, int order, int grid,
+// bytes_cinv, bytes_schur} per launch (algorithmic bytes).  Fields of `want`
+// that are <= 0 (order, stage: < 0) take the context's current choice.
+void time_stencil(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, int iters, const TuneChoice& want,
                   double out[4]);
-// Picks the fastest stencil launch (R, order, grid) and rebuilds the solver graphs.
-void autotune(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, double best[4]);
+// Picks the fastest stencil launch (R, order, grid, splits, stage) and rebuilds
+// the solver graphs.
+void autotune(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, double best[6]);
 ddml_solver_params default_params();
 
 }  // namespace ddml

@@ -7,13 +7,16 @@ namespace ddml {
 // dirac.hip
 hipError_t launch_hop_item(const HopItem<double2>& it, int mode, int red, int R, int order, hipStream_t st);
 hipError_t launch_hop_item(const HopItem<float2>& it, int mode, int red, int R, int order, hipStream_t st);
-// xstart: [kXcd][xstride] per-XCD prefix of band sizes (banded order only)
+// xstart: [kXcd][xstride] per-XCD prefix of tile counts (all orders but linear);
+// splits: the waves covering the columns of a tile are spread over this many
+// workgroups (1 = one workgroup per tile); stage: 1 = stage each tile's links
+// and clover data in LDS once per workgroup
 hipError_t launch_hop_batch(const SlotDesc<float2>* slots, const int* tile_start, const int* xstart, int xstride,
                             const int* nslots_p, int nrhs, int R, int mode, int red, int fin, int faux, int fout,
-                            int fred, int par_out, int grid, int order, hipStream_t st);
+                            int fred, int par_out, int grid, int order, int splits, int stage, hipStream_t st);
 hipError_t launch_hop_batch(const SlotDesc<double2>* slots, const int* tile_start, const int* xstart, int xstride,
                             const int* nslots_p, int nrhs, int R, int mode, int red, int fin, int faux, int fout,
-                            int fred, int par_out, int grid, int order, hipStream_t st);
+                            int fred, int par_out, int grid, int order, int splits, int stage, hipStream_t st);
 // host mirror of the banded order: tiles of a box (ntiles, tps) owned by XCD x
 inline int band_count(int ntiles, int tps, int x) {
   const int S = tps > 0 ? tps : ntiles;

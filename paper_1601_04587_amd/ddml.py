@@ -100,7 +100,7 @@ def load():
                                            ctypes.POINTER(RhsInfo), I, P]
     lib.ddml_propagator_series_batch.argtypes = [P, I, ctypes.POINTER(SeriesDesc), I, ctypes.POINTER(SolverParams),
                                                  I, P]
-    lib.ddml_time_stencil.argtypes = [P, I, I, I, I, I, I, I, I, ctypes.POINTER(ctypes.c_double)]
+    lib.ddml_time_stencil.argtypes = [P, I, I, I, I, I, I, I, I, I, I, ctypes.POINTER(ctypes.c_double)]
     lib.ddml_autotune.argtypes = [P, I, I, I, I, ctypes.POINTER(ctypes.c_double)]
     lib.ddml_contract_pp_disconnected.argtypes = [P, P, P, I, IP, IP, P, I, P]
     lib.ddml_contract_nucleon.argtypes = [P, P, I, P, P, I, P]
@@ -281,17 +281,18 @@ class Context:
         self._check(rc, allow=(ENOTCONVERGED, ENUMERIC))
         return rc, [[list(info[i * nrhs:(i + 1) * nrhs]) for i in range(len(d))] for d, info in keep]
 
-    def time_stencil(self, gid, dom, nrhs, prec=MIXED_FP32, iters=20, R=0, order=-1, grid=0):
+    def time_stencil(self, gid, dom, nrhs, prec=MIXED_FP32, iters=20, R=0, order=-1, grid=0, splits=0, stage=-1):
         """(ms_odd_half, ms_even_half, bytes_odd_half, bytes_even_half) per launch."""
         out = (ctypes.c_double * 4)()
-        self._check(self.lib.ddml_time_stencil(self.h, gid, dom, nrhs, prec, iters, R, order, grid, out))
+        self._check(self.lib.ddml_time_stencil(self.h, gid, dom, nrhs, prec, iters, R, order, grid, splits, stage,
+                                               out))
         return tuple(out)
 
     def autotune(self, gid, dom, nrhs, prec=MIXED_FP32):
-        """Pick the fastest stencil launch; returns (R, order, grid, ms per odd+even pair)."""
-        out = (ctypes.c_double * 4)()
+        """Pick the fastest stencil launch; returns (R, order, grid, splits, stage, ms per odd+even pair)."""
+        out = (ctypes.c_double * 6)()
         self._check(self.lib.ddml_autotune(self.h, gid, dom, nrhs, prec, out))
-        return int(out[0]), int(out[1]), int(out[2]), out[3]
+        return int(out[0]), int(out[1]), int(out[2]), int(out[3]), int(out[4]), out[5]
 
     # ------------------------------------------------------- contractions
     def contract_pp_disconnected(self, terms_x, terms_y, nlevels, xsrc, ysrc):

@@ -107,8 +107,9 @@ def test_mixed_solver_iterations_close_to_fp64(setup, solver):
 
 def test_autotune_and_stencil_timing(setup):
     L, U, ctx, gid, doms, ids = setup
-    R, order, grid, ms = ctx.autotune(gid, ids["G2"], 12, ddml.MIXED_FP32)
-    assert 1 <= R <= 3 and order in (0, 1) and grid in (512, 1024, 2048) and ms > 0
+    R, order, grid, splits, stage, ms = ctx.autotune(gid, ids["G2"], 12, ddml.MIXED_FP32)
+    assert 1 <= R <= 3 and order in (0, 1, 2, 3) and grid in (512, 1024, 2048) and 1 <= splits <= 3 and ms > 0
+    assert stage in (0, 1)
     ms_odd, ms_even, b_odd, b_even = ctx.time_stencil(gid, ids["G2"], 12, ddml.MIXED_FP32, 5)
     Vh = int(np.prod(L)) // 2
     assert b_odd == Vh * (48 * 12 + 216) * 4 and b_even == Vh * (96 * 12 + 216) * 4
