@@ -68,7 +68,12 @@ typedef enum { DDML_BC_PERIODIC = 0, DDML_BC_ANTIPERIODIC = 1 } ddml_bc;
 
 typedef enum {
   DDML_FP64 = 0,        /* FP64 throughout (the plain FP64 GPU solver) */
-  DDML_MIXED_FP32 = 1   /* FP32 inner Krylov solve, FP64 defect correction */
+  DDML_MIXED_FP32 = 1,  /* FP32 inner Krylov solve, FP64 defect correction */
+  DDML_MIXED_FP16 = 2   /* inner Krylov vectors, links and A^{-1} stored as 16-bit
+                           fixed point (one FP32 scale per site and column for
+                           spinors, per site for A^{-1}), FP32 arithmetic and FP32
+                           solution vector, FP64 defect correction.  Inner solves
+                           stop at no less than 1e-3 relative reduction. */
 } ddml_prec;
 
 typedef struct {

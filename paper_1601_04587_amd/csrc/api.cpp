@@ -192,7 +192,7 @@ int ddml_apply_eo(ddml_ctx ctx, int gauge_id, int dom_id, const double* in, doub
   return guarded(ctx, [&](Ctx* c) {
     need(in && out, "NULL buffer");
     need(nrhs >= 1 && nrhs <= kMaxRhs, "nrhs must be in 1..12");
-    need(prec == DDML_FP64 || prec == DDML_MIXED_FP32, "unknown precision");
+    need(prec == DDML_FP64 || prec == DDML_MIXED_FP32 || prec == DDML_MIXED_FP16, "unknown precision");
     const size_t bytes = (size_t)nrhs * c->V * 12 * sizeof(double2);
     StreamJoin sj(c, stream);
     Staged si = stage_in(c, in, bytes, on_device);
@@ -314,7 +314,7 @@ int ddml_time_stencil(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec
                       int grid, int splits, int stage, double out[4]) {
   return guarded(ctx, [&](Ctx* c) {
     need(out != nullptr, "out is NULL");
-    need(prec == DDML_FP64 || prec == DDML_MIXED_FP32, "unknown precision");
+    need(prec == DDML_FP64 || prec == DDML_MIXED_FP32 || prec == DDML_MIXED_FP16, "unknown precision");
     TuneChoice w;
     w.R = R;
     w.order = order;
@@ -329,7 +329,7 @@ int ddml_time_stencil(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec
 int ddml_autotune(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec, double best[6]) {
   return guarded(ctx, [&](Ctx* c) {
     need(best != nullptr, "best is NULL");
-    need(prec == DDML_FP64 || prec == DDML_MIXED_FP32, "unknown precision");
+    need(prec == DDML_FP64 || prec == DDML_MIXED_FP32 || prec == DDML_MIXED_FP16, "unknown precision");
     autotune(c, gauge_id, dom_id, nrhs, prec, best);
     return DDML_OK;
   });

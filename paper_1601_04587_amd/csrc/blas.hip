@@ -151,6 +151,132 @@ __global__ void __launch_bounds__(768) k_vec(const SlotDesc<T2>* __restrict__ sl
   }
 }
 
+// The same steps on 16-bit fields (DDML_MIXED_FP16): every vector but the
+// solution is stored as 16-bit fixed point with one scale per (site, column);
+// the solution accumulates in FP32 (x32).  Each output is quantised before the
+// fused reductions use it.
+__device__ __forceinline__ float2 cm32(float2 a, float2 b) { return cmul(a, b); }
+
+template <int OP>
+__global__ void __launch_bounds__(768) k_vec16(const SlotDesc<h16c>* __restrict__ slots,
+                                               const int* __restrict__ tile_start, const int* __restrict__ nslots_p) {
+  const int ns = *nslots_p;
+  const int total = tile_start[ns];
+  const int lane = threadIdx.x & 63;
+  const int col = threadIdx.x >> 6;
+  for (int vt = blockIdx.x; vt < total; vt += gridDim.x) {
+    const int s = find_slot_v(tile_start, ns, vt);
+    const SlotDesc<h16c>& d = slots[s];
+    if (col >= d.nrhs) continue;
+    if (OP != VEC_INIT && OP != VEC_RELUP && !d.active[col]) continue;  // uniform per wave
+    const int tile = vt - tile_start[s];
+    const int nt = d.ntiles;
+    const int i = tile * kTile + lane;
+    const bool valid = i < d.g.Vh;
+    const size_t base = fidx(nt, col, 0, i);
+    const size_t sx = (size_t)col * nt * kTile + i;
+    const BiState& st = d.st[col];
+    auto ld = [&](int f, float2 v[12]) { spinor_load_q(d.f[f] + base, d.nrm[f][sx], v, true); };
+    auto stq = [&](int f, const float2 v[12], float2 dq[12]) {
+      spinor_store_q(d.f[f] + base, d.nrm[f] + sx, v, dq, true);
+    };
+    double2 s0 = make_double2(0, 0), s1 = make_double2(0, 0);
+    float2 z[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) z[c] = make_float2(0, 0);
+    if (OP == VEC_P) {
+      if (valid) {
+        const float2 be = make_float2((float)st.beta.x, (float)st.beta.y);
+        const float2 om = make_float2((float)st.omega.x, (float)st.omega.y);
+        float2 p[12], r[12], v[12], o[12], dq[12];
+        ld(F_P, p);
+        ld(F_R, r);
+        ld(F_V, v);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) o[c] = cadd(r[c], cm32(be, csub(p[c], cm32(om, v[c]))));
+        stq(F_P, o, dq);
+      }
+    } else if (OP == VEC_S) {
+      const float2 al = make_float2((float)st.alpha.x, (float)st.alpha.y);
+      float2 r[12], v[12], o[12], dq[12];
+      if (valid) {
+        ld(F_R, r);
+        ld(F_V, v);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) o[c] = csub(r[c], cm32(al, v[c]));
+      } else {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) o[c] = z[c];
+      }
+      stq(F_S, o, dq);
+    } else if (OP == VEC_XR) {
+      if (valid) {
+        const float2 al = make_float2((float)st.alpha.x, (float)st.alpha.y);
+        const float2 om = make_float2((float)st.omega.x, (float)st.omega.y);
+        float2 p[12], sv[12], t[12], h[12], o[12], dq[12];
+        ld(F_P, p);
+        ld(F_S, sv);
+        ld(F_T, t);
+        ld(F_RH, h);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          float2 x0, x1;
+          ld2(d.x32 + base + 128 * k, x0, x1);
+          x0 = cadd(x0, cadd(cm32(al, p[2 * k]), cm32(om, sv[2 * k])));
+          x1 = cadd(x1, cadd(cm32(al, p[2 * k + 1]), cm32(om, sv[2 * k + 1])));
+          st2(d.x32 + base + 128 * k, x0, x1);
+        }
+#pragma unroll
+        for (int c = 0; c < 12; ++c) o[c] = csub(sv[c], cm32(om, t[c]));
+        stq(F_R, o, dq);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          s0.x += (double)h[c].x * dq[c].x + (double)h[c].y * dq[c].y;
+          s0.y += (double)h[c].x * dq[c].y - (double)h[c].y * dq[c].x;
+          s1.x += (double)dq[c].x * dq[c].x + (double)dq[c].y * dq[c].y;
+        }
+      }
+    } else {  // VEC_INIT / VEC_RELUP: r = (16-bit) src64, x = 0; a fresh column also gets rh = r, p = v = 0
+      float2 b[12], dq[12], h[12];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        double2 b0 = make_double2(0, 0), b1 = b0;
+        if (valid) ld2(d.src64 + base + 128 * k, b0, b1);
+        b[2 * k] = make_float2((float)b0.x, (float)b0.y);
+        b[2 * k + 1] = make_float2((float)b1.x, (float)b1.y);
+        st2(d.x32 + base + 128 * k, z[2 * k], z[2 * k + 1]);
+      }
+      stq(F_R, b, dq);
+      const bool fresh = OP == VEC_INIT || st.status != 0;
+      if (fresh) {
+        float2 dz[12];
+        stq(F_RH, b, h);
+        stq(F_P, z, dz);
+        stq(F_V, z, dz);
+      } else if (valid) {
+        ld(F_RH, h);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) h[c] = z[c];
+      }
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        s0.x += (double)h[c].x * dq[c].x + (double)h[c].y * dq[c].y;
+        s0.y += (double)h[c].x * dq[c].y - (double)h[c].y * dq[c].x;
+        s1.x += (double)dq[c].x * dq[c].x + (double)dq[c].y * dq[c].y;
+      }
+    }
+    if (OP == VEC_XR || OP == VEC_INIT || OP == VEC_RELUP) {
+      s0 = wsum(s0);
+      s1 = wsum(s1);
+      if (lane == 0) {
+        d.partial[(size_t)col * d.ntiles + tile] = s0;
+        d.partial[((size_t)d.nrhs + col) * d.ntiles + tile] = s1;
+      }
+    }
+  }
+}
+
 __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
   const double den = b.x * b.x + b.y * b.y;
   return make_double2((a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den);
@@ -268,6 +394,19 @@ hipError_t launch_vec(const SlotDesc<double2>* slots, const int* tile_start, con
                       int grid, hipStream_t st) {
   return vec_impl(slots, tile_start, nslots_p, nrhs, op, grid, st);
 }
+hipError_t launch_vec(const SlotDesc<h16c>* slots, const int* tile_start, const int* nslots_p, int nrhs, int op,
+                      int grid, hipStream_t st) {
+  dim3 b(64 * nrhs);
+  switch (op) {
+    case VEC_P: hipLaunchKernelGGL(k_vec16<VEC_P>, dim3(grid), b, 0, st, slots, tile_start, nslots_p); break;
+    case VEC_S: hipLaunchKernelGGL(k_vec16<VEC_S>, dim3(grid), b, 0, st, slots, tile_start, nslots_p); break;
+    case VEC_XR: hipLaunchKernelGGL(k_vec16<VEC_XR>, dim3(grid), b, 0, st, slots, tile_start, nslots_p); break;
+    case VEC_INIT: hipLaunchKernelGGL(k_vec16<VEC_INIT>, dim3(grid), b, 0, st, slots, tile_start, nslots_p); break;
+    case VEC_RELUP: hipLaunchKernelGGL(k_vec16<VEC_RELUP>, dim3(grid), b, 0, st, slots, tile_start, nslots_p); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 
 template <typename T2>
 static hipError_t fin_impl(const SlotDesc<T2>* slots, const int* nslots_p, int max_slots, int op, hipStream_t st) {
@@ -286,6 +425,9 @@ hipError_t launch_fin(const SlotDesc<float2>* slots, const int* nslots_p, int ma
   return fin_impl(slots, nslots_p, max_slots, op, st);
 }
 hipError_t launch_fin(const SlotDesc<double2>* slots, const int* nslots_p, int max_slots, int op, hipStream_t st) {
+  return fin_impl(slots, nslots_p, max_slots, op, st);
+}
+hipError_t launch_fin(const SlotDesc<h16c>* slots, const int* nslots_p, int max_slots, int op, hipStream_t st) {
   return fin_impl(slots, nslots_p, max_slots, op, st);
 }
 
@@ -335,6 +477,61 @@ hipError_t launch_fill(double2* v, size_t n, double a, hipStream_t st) {
   hipLaunchKernelGGL((k_fill<double2>), dim3(grid_n(n)), dim3(256), 0, st, v, n, a);
   return hipGetLastError();
 }
+// 16-bit field with values {q, q/2} (q varying per element) and every scale a
+__global__ void k_fill16(h16c* __restrict__ v, size_t n, float* __restrict__ nrm, size_t nn, float a) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const short q = (short)(16384 + 100 * (int)(i % 97));
+    v[i] = h16c{q, (short)(q / 2)};
+  }
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nn; i += (size_t)gridDim.x * blockDim.x)
+    nrm[i] = a;
+}
+hipError_t launch_fill16(h16c* v, size_t n, float* nrm, size_t nn, double a, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill16, dim3(grid_n(n)), dim3(256), 0, st, v, n, nrm, nn, (float)a);
+  return hipGetLastError();
+}
+// FP64 field <-> 16-bit field, one thread per (site, column) of [nrhs][ntiles * 64]
+__global__ void k_quant16(const double2* __restrict__ in, h16c* __restrict__ out, float* __restrict__ nrm, int nrhs,
+                          int ntiles) {
+  const size_t per = (size_t)ntiles * kTile;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < per * nrhs; t += (size_t)gridDim.x * blockDim.x) {
+    const int col = (int)(t / per), i = (int)(t % per);
+    const size_t base = fidx(ntiles, col, 0, i);
+    float2 v[12], dq[12];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      double2 a, b;
+      ld2(in + base + 128 * k, a, b);
+      v[2 * k] = make_float2((float)a.x, (float)a.y);
+      v[2 * k + 1] = make_float2((float)b.x, (float)b.y);
+    }
+    spinor_store_q(out + base, nrm + t, v, dq, false);
+  }
+}
+__global__ void k_dequant16(const h16c* __restrict__ in, const float* __restrict__ nrm, double2* __restrict__ out,
+                            int nrhs, int ntiles) {
+  const size_t per = (size_t)ntiles * kTile;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < per * nrhs; t += (size_t)gridDim.x * blockDim.x) {
+    const int col = (int)(t / per), i = (int)(t % per);
+    const size_t base = fidx(ntiles, col, 0, i);
+    float2 v[12];
+    spinor_load_q(in + base, nrm[t], v, false);
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      st2(out + base + 128 * k, make_double2(v[2 * k].x, v[2 * k].y), make_double2(v[2 * k + 1].x, v[2 * k + 1].y));
+  }
+}
+hipError_t launch_quant16(const double2* in, h16c* out, float* nrm, int nrhs, int ntiles, hipStream_t st) {
+  hipLaunchKernelGGL(k_quant16, dim3(grid_n((size_t)nrhs * ntiles * kTile)), dim3(256), 0, st, in, out, nrm, nrhs,
+                     ntiles);
+  return hipGetLastError();
+}
+hipError_t launch_dequant16(const h16c* in, const float* nrm, double2* out, int nrhs, int ntiles, hipStream_t st) {
+  hipLaunchKernelGGL(k_dequant16, dim3(grid_n((size_t)nrhs * ntiles * kTile)), dim3(256), 0, st, in, nrm, out, nrhs,
+                     ntiles);
+  return hipGetLastError();
+}
+
 hipError_t launch_axpy_d(double2* y, const double2* x, double a, size_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_axpy_d, dim3(grid_n(n)), dim3(256), 0, st, y, x, a, n);
   return hipGetLastError();

@@ -34,6 +34,20 @@ namespace ddml {
 constexpr int kTile = 64;          // sites per tile (one wavefront)
 constexpr int kMaxRhs = 12;
 
+// ------------------------------------------------------- 16-bit storage
+// Inner-solver fields of DDML_MIXED_FP16 store a complex number as two int16
+// (fixed point): value = q * scale / 32767.  Spinors carry one FP32 scale per
+// (site, column), the largest |real component| of its 24 reals; the clover data
+// one scale per site; links none (scale 1: every entry of an SU(3) matrix has
+// |Re|, |Im| <= 1).  Arithmetic is FP32.
+struct h16c {
+  short x, y;
+};
+constexpr float kQ = 32767.0f;
+// compute type of an element type
+template <typename E> struct CompOf { using type = E; };
+template <> struct CompOf<h16c> { using type = float2; };
+
 // ------------------------------------------------------------------ complex
 template <typename T> struct Cpx;
 template <> struct Cpx<float> { using T2 = float2; };
@@ -133,6 +147,62 @@ __device__ __forceinline__ void st2(double2* p, double2 a, double2 b) {
   q[1] = v;
 }
 
+// 16-bit pairs: two complex numbers as 4 x int16 (8 bytes per lane).  ld2q
+// returns the raw integers as floats; the caller applies the scale.
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void ld2q(const h16c* p, float2& a, float2& b) {
+  const s16x4 v = *(const DDML_GLOBAL s16x4*)p;
+  a = make_float2((float)v.x, (float)v.y);
+  b = make_float2((float)v.z, (float)v.w);
+}
+__device__ __forceinline__ void ld2q_nt(const h16c* p, float2& a, float2& b) {
+  const s16x4 v = __builtin_nontemporal_load((const DDML_GLOBAL s16x4*)p);
+  a = make_float2((float)v.x, (float)v.y);
+  b = make_float2((float)v.z, (float)v.w);
+}
+__device__ __forceinline__ short q16(float v) { return (short)__float2int_rn(fminf(fmaxf(v, -kQ), kQ)); }
+// a, b already multiplied by kQ / scale
+__device__ __forceinline__ void st2q(h16c* p, float2 a, float2 b, bool nt) {
+  s16x4 v;
+  v.x = q16(a.x); v.y = q16(a.y); v.z = q16(b.x); v.w = q16(b.y);
+  if (nt) __builtin_nontemporal_store(v, (DDML_GLOBAL s16x4*)p);
+  else *(DDML_GLOBAL s16x4*)p = v;
+}
+// One site-column (12 complex, pair k at base + 128 k) in 16-bit storage.
+__device__ __forceinline__ void spinor_load_q(const h16c* base, float nrm, float2 v[12], bool nt) {
+  const float sc = nrm / kQ;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    float2 a, b;
+    if (nt) ld2q_nt(base + 128 * k, a, b);
+    else ld2q(base + 128 * k, a, b);
+    v[2 * k] = make_float2(a.x * sc, a.y * sc);
+    v[2 * k + 1] = make_float2(b.x * sc, b.y * sc);
+  }
+}
+// Stores v with scale max|v| (NaN if any component is not finite) and returns
+// in dq the values a later spinor_load_q reads back.
+__device__ __forceinline__ void spinor_store_q(h16c* base, float* nrm, const float2 v[12], float2 dq[12], bool nt) {
+  float m = 0.f, s = 0.f;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    m = fmaxf(m, fmaxf(fabsf(v[c].x), fabsf(v[c].y)));
+    s += fabsf(v[c].x) + fabsf(v[c].y);
+  }
+  if (!isfinite(s)) m = __builtin_nanf("");
+  const float inv = (m > 0.f && isfinite(m)) ? kQ / m : 0.f;
+  const float sc = m / kQ;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const float2 a = make_float2(v[2 * k].x * inv, v[2 * k].y * inv);
+    const float2 b = make_float2(v[2 * k + 1].x * inv, v[2 * k + 1].y * inv);
+    st2q(base + 128 * k, a, b, nt);
+    dq[2 * k] = make_float2((float)q16(a.x) * sc, (float)q16(a.y) * sc);
+    dq[2 * k + 1] = make_float2((float)q16(b.x) * sc, (float)q16(b.y) * sc);
+  }
+  *nrm = m;
+}
+
 // local coordinates of EO index i of parity p
 __device__ __forceinline__ void eo_coords(const BoxGeom& g, int p, int i, int y[4]) {
   int j = i % g.half3;
@@ -224,6 +294,11 @@ template <typename T2> struct SlotDesc {
   const double2* src64; // FP64 even-parity right-hand side [nrhs][ntiles][12][64]
   const int* walk;      // tile walk of the sub-banded orders, as in HopItem
   int xoff[kXcd + 1];
+  // 16-bit storage only (T2 = h16c): scales of f[k] ([nrhs][ntiles * 64]),
+  // of the clover data ([2][ntiles * 64]), and the FP32 solution vector
+  float* nrm[F_NUM];
+  const float* Ainv_nrm;
+  float2* x32;
 };
 
 }  // namespace ddml

@@ -14,6 +14,8 @@
 // instead of HBM.  Domain restriction comes from zeroed face links, so the
 // inner loop has no masking branch.  Tiles are visited either linearly or in
 // XCD bands (see ddml_common.hpp) so that neighbour tiles share an L2.
+#include <type_traits>
+
 #include "ddml_common.hpp"
 #include "launchers.hpp"
 
@@ -183,9 +185,13 @@ __device__ __forceinline__ void herm6_apply(const T2 m[18], const T2 x[6], T2 y[
 constexpr int kStageLinkPairs = 8 * 5;
 constexpr int kStagePairs = kStageLinkPairs + 18;
 
-template <typename T2>
-__device__ __forceinline__ void stage_tile(const BoxGeom& g, const T2* __restrict__ U, const T2* __restrict__ clov,
-                                           int p, int tile, T2* sm) {
+template <typename E>
+constexpr bool kIs16 = std::is_same<E, h16c>::value;
+
+// E: element type of the fields (float2, double2 or 16-bit h16c); C: compute type.
+template <typename E, typename C = typename CompOf<E>::type>
+__device__ __forceinline__ void stage_tile(const BoxGeom& g, const E* __restrict__ U, const E* __restrict__ clov,
+                                           const float* __restrict__ clov_n, int p, int tile, C* sm) {
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6, W = blockDim.x >> 6;
   const int i = tile * kTile + lane;
@@ -195,30 +201,42 @@ __device__ __forceinline__ void stage_tile(const BoxGeom& g, const T2* __restric
   int y[4] = {0, 0, 0, 0};
   if (valid) eo_coords(g, p, i, y);
   for (int j = w; j < kStagePairs; j += W) {
-    T2 a = mk<T2>(0, 0), b = mk<T2>(0, 0);
+    C a = mk<C>(0, 0), b = mk<C>(0, 0);
+    const E* src = nullptr;
+    float sc = 1.0f / kQ;
     if (j < kStageLinkPairs) {
       const int h = j / 5, k = j - 5 * h, mu = h >> 1;
       if (valid) {
         if ((h & 1) == 0) {
-          ld2nt(U + lidx(nt, p, mu, 2 * k, i), a, b);
+          src = U + lidx(nt, p, mu, 2 * k, i);
         } else {
           int z[4] = {y[0], y[1], y[2], y[3]};
           z[mu] = (y[mu] == 0) ? g.L[mu] - 1 : y[mu] - 1;
-          ld2nt(U + lidx(nt, q, mu, 2 * k, eo_index(g, z)), a, b);
+          src = U + lidx(nt, q, mu, 2 * k, eo_index(g, z));
         }
       }
     } else {
-      ld2nt(clov + cidx(nt, p, 2 * (j - kStageLinkPairs), i), a, b);  // padding sites hold zeros
+      src = clov + cidx(nt, p, 2 * (j - kStageLinkPairs), i);  // padding sites hold zeros
+      if constexpr (kIs16<E>) sc = clov_n[(size_t)p * nt * kTile + i] / kQ;
+    }
+    if (src) {
+      if constexpr (kIs16<E>) {
+        ld2q_nt(src, a, b);
+        a = make_float2(a.x * sc, a.y * sc);
+        b = make_float2(b.x * sc, b.y * sc);
+      } else {
+        ld2nt(src, a, b);
+      }
     }
     sts2(sm + j * 128 + lane * 2, a, b);
   }
   __syncthreads();
 }
 
-template <typename T2, int R, bool ST>
-__device__ __forceinline__ void hop_sum(const BoxGeom& g, int p, int i, const T2* __restrict__ U, const T2* sm,
-                                        const T2* __restrict__ in, int r0, int nr, const int* __restrict__ act,
-                                        T2 acc[R][12]) {
+template <typename E, int R, bool ST, typename C = typename CompOf<E>::type>
+__device__ __forceinline__ void hop_sum(const BoxGeom& g, int p, int i, const E* __restrict__ U, const C* sm,
+                                        const E* __restrict__ in, const float* __restrict__ in_n, int r0, int nr,
+                                        const int* __restrict__ act, C acc[R][12]) {
   int y[4];
   eo_coords(g, p, i, y);
   const int q = 1 - p;
@@ -226,7 +244,7 @@ __device__ __forceinline__ void hop_sum(const BoxGeom& g, int p, int i, const T2
 #pragma unroll
   for (int r = 0; r < R; ++r)
 #pragma unroll
-    for (int c = 0; c < 12; ++c) acc[r][c] = mk<T2>(0, 0);
+    for (int c = 0; c < 12; ++c) acc[r][c] = mk<C>(0, 0);
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
 #pragma unroll
@@ -236,21 +254,25 @@ __device__ __forceinline__ void hop_sum(const BoxGeom& g, int p, int i, const T2
       if (fwd) z[mu] = (y[mu] + 1 == g.L[mu]) ? 0 : y[mu] + 1;
       else z[mu] = (y[mu] == 0) ? g.L[mu] - 1 : y[mu] - 1;
       const int n = eo_index(g, z);
-      T2 u[10];
-      if (ST) {
-        const T2* ul = sm + (2 * mu + dir) * 5 * 128 + (i & 63) * 2;
+      C u[10];
+      if constexpr (ST) {
+        const C* ul = sm + (2 * mu + dir) * 5 * 128 + (i & 63) * 2;
 #pragma unroll
         for (int k = 0; k < 5; ++k) lds2(ul + 128 * k, u[2 * k], u[2 * k + 1]);
       } else {
-        const T2* __restrict__ ul = fwd ? U + lidx(nt, p, mu, 0, i) : U + lidx(nt, q, mu, 0, n);
+        static_assert(!kIs16<E>, "16-bit fields are read through the LDS staging only");
+        const E* __restrict__ ul = fwd ? U + lidx(nt, p, mu, 0, i) : U + lidx(nt, q, mu, 0, n);
 #pragma unroll
         for (int k = 0; k < 5; ++k) ld2nt(ul + 128 * k, u[2 * k], u[2 * k + 1]);
       }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (r < nr && (act == nullptr || ldg(act + r0 + r))) {
-          T2 psi[12], h[6], gg[6];
-          spinor_load(in + fidx(nt, r0 + r, 0, n), psi);
+          C psi[12], h[6], gg[6];
+          if constexpr (kIs16<E>)
+            spinor_load_q(in + fidx(nt, r0 + r, 0, n), in_n[(size_t)(r0 + r) * nt * kTile + n], psi, false);
+          else
+            spinor_load(in + fidx(nt, r0 + r, 0, n), psi);
           project(mu, fwd, psi, h);
           su3_mul(u, !fwd, h, gg);
           reconstruct(mu, fwd, gg, acc[r]);
@@ -304,15 +326,30 @@ __device__ __forceinline__ void epilogue(const T2* cl, const T2 acc[12], const T
   }
 }
 
+// Field arguments of one tile launch: element pointers and, for 16-bit
+// fields, their per-(site, column) scales.
+template <typename E> struct TileArgs {
+  const E* U;
+  const E* clov;
+  const float* clov_n;
+  const E* in;
+  const float* in_n;
+  const E* aux;
+  const float* aux_n;
+  const E* red_a;
+  const float* red_n;
+  E* out;
+  float* out_n;
+};
+
 // One tile on the output parity p.  ST: the tile's links and clover data are
-// staged in LDS at sm (stage_tile) and taken from there.
-template <typename T2, int R, int MODE, int RED, bool ST = false>
-__device__ __forceinline__ void hop_tile(const BoxGeom g, const T2* __restrict__ U, const T2* __restrict__ clov,
-                                         const T2* __restrict__ in, const T2* __restrict__ aux,
-                                         const T2* __restrict__ red_a, T2* __restrict__ out,
-                                         double2* __restrict__ partial, const int* __restrict__ act, int p,
-                                         int nrhs, double c1, double c2, int tile, int wave0 = 0,
-                                         const T2* sm = nullptr) {
+// staged in LDS at sm (stage_tile) and taken from there.  16-bit outputs are
+// quantised before the fused reductions, so the dot products are those of the
+// stored vectors.
+template <typename E, int R, int MODE, int RED, bool ST = false, typename C = typename CompOf<E>::type>
+__device__ __forceinline__ void hop_tile(const BoxGeom g, const TileArgs<E>& a, double2* __restrict__ partial,
+                                         const int* __restrict__ act, int p, int nrhs, double c1, double c2, int tile,
+                                         int wave0 = 0, const C* sm = nullptr) {
   const int lane = threadIdx.x & 63;
   const int grp = wave0 + (threadIdx.x >> 6);
   const int r0 = grp * R;
@@ -321,9 +358,11 @@ __device__ __forceinline__ void hop_tile(const BoxGeom g, const T2* __restrict__
   const int i = tile * kTile + lane;
   const bool valid = i < g.Vh;
   const int nt = g.ntiles;
-  T2 acc[R][12];
-  if (valid) hop_sum<T2, R, ST>(g, p, i, U, sm, in, r0, nr, act, acc);
-  const T2* cl = ST ? sm + kStageLinkPairs * 128 + lane * 2 : clov + cidx(nt, p, 0, i);
+  C acc[R][12];
+  if (valid) hop_sum<E, R, ST>(g, p, i, a.U, sm, a.in, a.in_n, r0, nr, act, acc);
+  const C* cl;
+  if constexpr (ST) cl = sm + kStageLinkPairs * 128 + lane * 2;
+  else cl = a.clov + cidx(nt, p, 0, i);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     if (r >= nr) break;
@@ -332,12 +371,21 @@ __device__ __forceinline__ void hop_tile(const BoxGeom g, const T2* __restrict__
     if (!on) continue;  // uniform across the wave
     double2 s0 = make_double2(0, 0), s1 = make_double2(0, 0);
     const size_t base = fidx(nt, col, 0, i);
+    const size_t ns = (size_t)col * nt * kTile + i;  // scale index of 16-bit fields
     if (valid) {
-      T2 av[12], ra[12], o[12];
-      if (MODE != MODE_CINV_HOP) spinor_load_nt(aux + base, av);
-      if (MODE == MODE_RES || RED == RED_DOT) spinor_load_nt(red_a + base, ra);
-      epilogue<T2, MODE, ST>(cl, acc[r], av, ra, c1, c2, o);
-      spinor_store_nt(out + base, o);
+      C av[12], ra[12], o[12];
+      if constexpr (kIs16<E>) {
+        if (MODE != MODE_CINV_HOP) spinor_load_q(a.aux + base, a.aux_n[ns], av, true);
+        if (MODE == MODE_RES || RED == RED_DOT) spinor_load_q(a.red_a + base, a.red_n[ns], ra, true);
+        C w[12];
+        epilogue<C, MODE, ST>(cl, acc[r], av, ra, c1, c2, w);
+        spinor_store_q(a.out + base, a.out_n + ns, w, o, true);
+      } else {
+        if (MODE != MODE_CINV_HOP) spinor_load_nt(a.aux + base, av);
+        if (MODE == MODE_RES || RED == RED_DOT) spinor_load_nt(a.red_a + base, ra);
+        epilogue<C, MODE, ST>(cl, acc[r], av, ra, c1, c2, o);
+        spinor_store_nt(a.out + base, o);
+      }
       if (RED == RED_DOT) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
@@ -357,10 +405,11 @@ __device__ __forceinline__ void hop_tile(const BoxGeom g, const T2* __restrict__
       }
     } else {
       // padding sites of the last tile stay zero
-      T2 z[12];
+      C z[12], zq[12];
 #pragma unroll
-      for (int c = 0; c < 12; ++c) z[c] = mk<T2>(0, 0);
-      spinor_store(out + base, z);
+      for (int c = 0; c < 12; ++c) z[c] = mk<C>(0, 0);
+      if constexpr (kIs16<E>) spinor_store_q(a.out + base, a.out_n + ns, z, zq, false);
+      else spinor_store(a.out + base, z);
     }
     if (RED != RED_NONE) {
       s0 = wave_sum(s0);
@@ -388,6 +437,7 @@ __device__ __forceinline__ int band_tile(int S, int lo, int bs, int local) {
 // Single-item launch (operator application, outer FP64 steps).
 template <typename T2, int R, int MODE, int RED>
 __global__ void __launch_bounds__(64 * ((kMaxRhs + R - 1) / R)) k_hop_item(HopItem<T2> it, int order) {
+  const TileArgs<T2> ta{it.U, it.clov, nullptr, it.in, nullptr, it.aux, nullptr, it.red_a, nullptr, it.out, nullptr};
   if (order != TILE_ORDER_LINEAR) {
     const int x = blockIdx.x % kXcd, j = blockIdx.x / kXcd, nb = gridDim.x / kXcd;
     int S = 0, lo = 0, bs = 1, total;
@@ -399,13 +449,11 @@ __global__ void __launch_bounds__(64 * ((kMaxRhs + R - 1) / R)) k_hop_item(HopIt
     }
     for (int v = j; v < total; v += nb) {
       const int tile = order == TILE_ORDER_BANDED ? band_tile(S, lo, bs, v) : ldg(it.walk + it.xoff[x] + v);
-      hop_tile<T2, R, MODE, RED>(it.g, it.U, it.clov, it.in, it.aux, it.red_a, it.out, it.partial, it.active,
-                                 it.par_out, it.nrhs, it.c1, it.c2, tile);
+      hop_tile<T2, R, MODE, RED>(it.g, ta, it.partial, it.active, it.par_out, it.nrhs, it.c1, it.c2, tile);
     }
   } else {
     for (int tile = blockIdx.x; tile < it.ntiles; tile += gridDim.x)
-      hop_tile<T2, R, MODE, RED>(it.g, it.U, it.clov, it.in, it.aux, it.red_a, it.out, it.partial, it.active,
-                                 it.par_out, it.nrhs, it.c1, it.c2, tile);
+      hop_tile<T2, R, MODE, RED>(it.g, ta, it.partial, it.active, it.par_out, it.nrhs, it.c1, it.c2, tile);
   }
 }
 
@@ -432,7 +480,8 @@ __global__ void __launch_bounds__(64 * ((kMaxRhs + R - 1) / R))
     k_hop_batch(const SlotDesc<T2>* __restrict__ slots, const int* __restrict__ tile_start,
                 const int* __restrict__ xstart, int xstride, const int* __restrict__ nslots_p, int fin, int faux,
                 int fout, int fred, int par_out, int order, int ng) {
-  __shared__ T2 sm[ST ? kStagePairs * 128 : 1];
+  using C = typename CompOf<T2>::type;
+  __shared__ C sm[ST ? kStagePairs * 128 : 1];
   const int ns = *nslots_p;
   const int W = blockDim.x >> 6;
   const bool banded = order != TILE_ORDER_LINEAR;
@@ -453,11 +502,16 @@ __global__ void __launch_bounds__(64 * ((kMaxRhs + R - 1) / R))
     } else if (order != TILE_ORDER_LINEAR) {
       tile = ldg(d.walk + d.xoff[x] + tile);
     }
-    if (ST) stage_tile<T2>(d.g, d.U, d.Ainv, par_out, tile, sm);
-    hop_tile<T2, R, MODE, RED, ST>(d.g, d.U, d.Ainv, d.f[fin], faux >= 0 ? d.f[faux] : nullptr,
-                                   fred >= 0 ? d.f[fred] : nullptr, d.f[fout], d.partial, d.active, par_out, d.nrhs,
-                                   d.kappa * d.kappa, 0.0, tile, grp * W, sm);
-    if (ST) __syncthreads();
+    const bool h16 = kIs16<T2>;
+    const TileArgs<T2> ta{d.U, d.Ainv, h16 ? d.Ainv_nrm : nullptr,
+                          d.f[fin], h16 ? d.nrm[fin] : nullptr,
+                          faux >= 0 ? d.f[faux] : nullptr, h16 && faux >= 0 ? d.nrm[faux] : nullptr,
+                          fred >= 0 ? d.f[fred] : nullptr, h16 && fred >= 0 ? d.nrm[fred] : nullptr,
+                          d.f[fout], h16 ? d.nrm[fout] : nullptr};
+    if constexpr (ST) stage_tile<T2>(d.g, d.U, d.Ainv, ta.clov_n, par_out, tile, sm);
+    hop_tile<T2, R, MODE, RED, ST>(d.g, ta, d.partial, d.active, par_out, d.nrhs, d.kappa * d.kappa, 0.0, tile,
+                                   grp * W, sm);
+    if constexpr (ST) __syncthreads();
   }
 }
 
@@ -522,14 +576,21 @@ hipError_t launch_hop_item(const HopItem<float2>& it, int mode, int red, int R, 
 }
 
 #define DDML_HOPB_DISPATCH1(T2, Rv, MODEv, REDv, STv)                                                    \
-  if (R == Rv && mode == MODEv && red == REDv && (stage != 0) == STv) {                                  \
+  if (R == Rv && mode == MODEv && red == REDv) {                                                         \
     hipLaunchKernelGGL((k_hop_batch<T2, Rv, MODEv, REDv, STv>), dim3(grid), dim3(block), 0, st, slots,   \
                        tile_start, xstart, xstride, nslots_p, fin, faux, fout, fred, par_out, order, ng); \
     return hipGetLastError();                                                                            \
   }
-#define DDML_HOPB_DISPATCH(T2, Rv, MODEv, REDv)     \
-  DDML_HOPB_DISPATCH1(T2, Rv, MODEv, REDv, false) \
-  DDML_HOPB_DISPATCH1(T2, Rv, MODEv, REDv, true)
+#define DDML_HOPB_DISPATCH_ST(T2, STv)                           \
+  DDML_HOPB_DISPATCH1(T2, 1, MODE_CINV_HOP, RED_NONE, STv)       \
+  DDML_HOPB_DISPATCH1(T2, 1, MODE_SCHUR, RED_DOT, STv)           \
+  DDML_HOPB_DISPATCH1(T2, 1, MODE_SCHUR, RED_TS, STv)            \
+  DDML_HOPB_DISPATCH1(T2, 2, MODE_CINV_HOP, RED_NONE, STv)       \
+  DDML_HOPB_DISPATCH1(T2, 2, MODE_SCHUR, RED_DOT, STv)           \
+  DDML_HOPB_DISPATCH1(T2, 2, MODE_SCHUR, RED_TS, STv)            \
+  DDML_HOPB_DISPATCH1(T2, 3, MODE_CINV_HOP, RED_NONE, STv)       \
+  DDML_HOPB_DISPATCH1(T2, 3, MODE_SCHUR, RED_DOT, STv)           \
+  DDML_HOPB_DISPATCH1(T2, 3, MODE_SCHUR, RED_TS, STv)
 
 template <typename T2>
 static hipError_t hop_batch_impl(const SlotDesc<T2>* slots, const int* tile_start, const int* xstart, int xstride,
@@ -542,16 +603,14 @@ static hipError_t hop_batch_impl(const SlotDesc<T2>* slots, const int* tile_star
   const int W = (nw + splits - 1) / splits, ng = (nw + W - 1) / W;
   const int block = 64 * W;
   if (order < 0 || order >= TILE_ORDER_NUM || (order != TILE_ORDER_LINEAR && grid % kXcd)) return hipErrorInvalidValue;
-  DDML_HOPB_DISPATCH(T2, 1, MODE_CINV_HOP, RED_NONE)
-  DDML_HOPB_DISPATCH(T2, 1, MODE_SCHUR, RED_DOT)
-  DDML_HOPB_DISPATCH(T2, 1, MODE_SCHUR, RED_TS)
-  DDML_HOPB_DISPATCH(T2, 2, MODE_CINV_HOP, RED_NONE)
-  DDML_HOPB_DISPATCH(T2, 2, MODE_SCHUR, RED_DOT)
-  DDML_HOPB_DISPATCH(T2, 2, MODE_SCHUR, RED_TS)
-  DDML_HOPB_DISPATCH(T2, 3, MODE_CINV_HOP, RED_NONE)
-  DDML_HOPB_DISPATCH(T2, 3, MODE_SCHUR, RED_DOT)
-  DDML_HOPB_DISPATCH(T2, 3, MODE_SCHUR, RED_TS)
-  return hipErrorInvalidValue;
+  if (stage) {
+    DDML_HOPB_DISPATCH_ST(T2, true)
+  } else {
+    if constexpr (!kIs16<T2>) {
+      DDML_HOPB_DISPATCH_ST(T2, false)
+    }
+  }
+  return hipErrorInvalidValue;  // unknown variant; 16-bit fields need stage = 1
 }
 
 hipError_t launch_hop_batch(const SlotDesc<float2>* slots, const int* tile_start, const int* xstart, int xstride,
@@ -561,6 +620,12 @@ hipError_t launch_hop_batch(const SlotDesc<float2>* slots, const int* tile_start
                         par_out, grid, order, splits, stage, st);
 }
 hipError_t launch_hop_batch(const SlotDesc<double2>* slots, const int* tile_start, const int* xstart, int xstride,
+                            const int* nslots_p, int nrhs, int R, int mode, int red, int fin, int faux, int fout,
+                            int fred, int par_out, int grid, int order, int splits, int stage, hipStream_t st) {
+  return hop_batch_impl(slots, tile_start, xstart, xstride, nslots_p, nrhs, R, mode, red, fin, faux, fout, fred,
+                        par_out, grid, order, splits, stage, st);
+}
+hipError_t launch_hop_batch(const SlotDesc<h16c>* slots, const int* tile_start, const int* xstart, int xstride,
                             const int* nslots_p, int nrhs, int R, int mode, int red, int fin, int faux, int fout,
                             int fred, int par_out, int grid, int order, int splits, int stage, hipStream_t st) {
   return hop_batch_impl(slots, tile_start, xstart, xstride, nslots_p, nrhs, R, mode, red, fin, faux, fout, fred,

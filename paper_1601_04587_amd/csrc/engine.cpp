@@ -12,6 +12,8 @@
 // batch are one replay of a captured HIP graph over a slot table, and solves
 // enter and leave the table between replays.
 #include "engine.hpp"
+
+#include <type_traits>
 #include "server.hpp"
 
 #include <algorithm>
@@ -81,6 +83,7 @@ bool DevPool::fits(size_t bytes) const { return in_use_ + round(bytes) <= budget
 Ctx::~Ctx() {
   run32.clear();
   run64.clear();
+  run16.clear();
   blocks.clear();
   gauges.clear();
   flag.reset();
@@ -123,6 +126,7 @@ void ctx_init(Ctx* c, const ddml_lattice* lat, int device, size_t budget) {
   }
   c->pool.reset(new DevPool(budget));
   c->flag = DBuf(c->pool.get(), sizeof(int));
+  c->tune16.stage = 1;  // 16-bit fields are always read through the LDS staging
   for (int m = 0; m < 4; ++m) {
     c->full.lo[m] = 0;
     c->full.hi[m] = lat->dims[m];
@@ -344,6 +348,25 @@ std::shared_ptr<OpBlock> opblock(Ctx* c, int gauge_id, int dom_id) {
   return ob;
 }
 
+// 16-bit links and A^{-1} of an operator block, built on first use.
+static void ensure16(Ctx* c, OpBlock& ob) {
+  if (ob.U16.p) return;
+  const size_t ns = (size_t)2 * ob.ntiles * kTile;
+  ob.U16 = DBuf(c->pool.get(), kLinkSlots * ns * sizeof(h16c));
+  ob.Ainv16 = DBuf(c->pool.get(), kCloverSlots * ns * sizeof(h16c));
+  ob.Ainv16n = DBuf(c->pool.get(), ns * sizeof(float));
+  DDML_HIP(launch_quant_links(ob.U64.as<double2>(), ob.U16.as<h16c>(), kLinkSlots * ns, c->stream));
+  DDML_HIP(launch_quant_clover(ob.Ainv64.as<double2>(), ob.Ainv16.as<h16c>(), ob.Ainv16n.as<float>(), ob.ntiles,
+                               c->stream));
+  ob.bytes += ob.U16.bytes + ob.Ainv16.bytes + ob.Ainv16n.bytes;
+}
+
+// bytes of one inner field of a solve: 16-bit values + scales, or complex FP32/FP64
+static size_t inner_field_bytes(int prec, size_t n, int nrhs, size_t ntiles) {
+  if (prec == DDML_MIXED_FP16) return n * sizeof(h16c) + (size_t)nrhs * ntiles * kTile * sizeof(float);
+  return n * (prec == DDML_FP64 ? sizeof(double2) : sizeof(float2));
+}
+
 size_t solve_footprint(Ctx* c, int dom_id, int nrhs, int prec) {
   const DomainRec& d = domain_get(c, dom_id);
   size_t Vb = 1;
@@ -351,8 +374,9 @@ size_t solve_footprint(Ctx* c, int dom_id, int nrhs, int prec) {
   const size_t Vh = Vb / 2;
   const size_t ntiles = (Vh + kTile - 1) / kTile;
   const size_t n = (size_t)nrhs * 12 * ntiles * kTile;
-  const size_t inner = prec == DDML_FP64 ? sizeof(double2) : sizeof(float2);
-  return 8 * DevPool::round(n * sizeof(double2)) + F_NUM * DevPool::round(n * inner) +
+  const size_t fx = prec == DDML_MIXED_FP16 ? n * sizeof(float2) : inner_field_bytes(prec, n, nrhs, ntiles);
+  return 8 * DevPool::round(n * sizeof(double2)) + (F_NUM - 1) * DevPool::round(inner_field_bytes(prec, n, nrhs, ntiles)) +
+         DevPool::round(fx) +
          2 * DevPool::round(2 * nrhs * ntiles * sizeof(double2)) + 6 * DevPool::round(64);
 }
 
@@ -421,6 +445,61 @@ static void schur_apply(Ctx* c, const OpBlock& ob, const T2* U, const T2* Ainv, 
   DDML_HIP(launch_hop_item(it, MODE_SCHUR, RED_NONE, tn.R, tn.order, st));
 }
 
+// The Schur operator in 16-bit storage (input quantised, both half-stencils
+// through the batched kernels on a one-slot table, output read back to FP64).
+static void schur_apply16(Ctx* c, OpBlock& ob, const double2* xe, double2* oe, int nrhs, hipStream_t st) {
+  ensure16(c, ob);
+  const TuneChoice& tn = c->tune16;
+  const size_t n = (size_t)nrhs * ob.field, nt = ob.ntiles;
+  const size_t fb = inner_field_bytes(DDML_MIXED_FP16, n, nrhs, nt);
+  DevPool* P = c->pool.get();
+  DBuf fx(P, fb), ft(P, fb), fo(P, fb);
+  DBuf part(P, 2 * nrhs * nt * sizeof(double2)), act(P, kMaxRhs * sizeof(int));
+  DBuf tab(P, sizeof(SlotDesc<h16c>)), ts(P, 2 * sizeof(int)), ns(P, sizeof(int)), xs(P, kXcd * 2 * sizeof(int));
+  auto scales = [&](DBuf& b) { return reinterpret_cast<float*>(b.as<h16c>() + n); };
+  DDML_HIP(launch_quant16(xe, fx.as<h16c>(), scales(fx), nrhs, (int)nt, st));
+  std::vector<int> ones(kMaxRhs, 1);
+  DDML_HIP(hipMemcpyAsync(act.p, ones.data(), kMaxRhs * sizeof(int), hipMemcpyHostToDevice, st));
+  SlotDesc<h16c> d{};
+  d.g = ob.g;
+  d.nrhs = nrhs;
+  d.ntiles = ob.ntiles;
+  d.tps = ob.tps;
+  d.kappa = ob.bs.kappa;
+  d.U = ob.U16.as<h16c>();
+  d.Ainv = ob.Ainv16.as<h16c>();
+  d.Ainv_nrm = ob.Ainv16n.as<float>();
+  d.f[F_P] = fx.as<h16c>();
+  d.nrm[F_P] = scales(fx);
+  d.f[F_RH] = fx.as<h16c>();
+  d.nrm[F_RH] = scales(fx);
+  d.f[F_TMP] = ft.as<h16c>();
+  d.nrm[F_TMP] = scales(ft);
+  d.f[F_V] = fo.as<h16c>();
+  d.nrm[F_V] = scales(fo);
+  d.partial = part.as<double2>();
+  d.active = act.as<int>();
+  attach_walk(d, ob, tn.order);
+  int h_ts[2] = {0, ob.ntiles}, one = 1, h_xs[kXcd * 2];
+  for (int x = 0; x < kXcd; ++x) {
+    h_xs[2 * x] = 0;
+    h_xs[2 * x + 1] = tn.order == TILE_ORDER_LINEAR ? 0 : xcd_share(d, tn.order, x);
+  }
+  DDML_HIP(hipMemcpyAsync(tab.p, &d, sizeof(d), hipMemcpyHostToDevice, st));
+  DDML_HIP(hipMemcpyAsync(ts.p, h_ts, sizeof(h_ts), hipMemcpyHostToDevice, st));
+  DDML_HIP(hipMemcpyAsync(ns.p, &one, sizeof(int), hipMemcpyHostToDevice, st));
+  DDML_HIP(hipMemcpyAsync(xs.p, h_xs, sizeof(h_xs), hipMemcpyHostToDevice, st));
+  const int grid = ((tn.grid + kXcd - 1) / kXcd) * kXcd;
+  const int splits = std::min(tn.splits, (nrhs + tn.R - 1) / tn.R);
+  auto* tb = tab.as<SlotDesc<h16c>>();
+  DDML_HIP(launch_hop_batch(tb, ts.as<int>(), xs.as<int>(), 2, ns.as<int>(), nrhs, tn.R, MODE_CINV_HOP, RED_NONE, F_P,
+                            -1, F_TMP, -1, 1, grid, tn.order, splits, 1, st));
+  DDML_HIP(launch_hop_batch(tb, ts.as<int>(), xs.as<int>(), 2, ns.as<int>(), nrhs, tn.R, MODE_SCHUR, RED_DOT, F_TMP,
+                            F_P, F_V, F_RH, 0, grid, tn.order, splits, 1, st));
+  DDML_HIP(launch_dequant16(fo.as<h16c>(), scales(fo), oe, nrhs, (int)nt, st));
+  DDML_HIP(hipStreamSynchronize(st));  // temporaries go back to the pool
+}
+
 void apply_eo(Ctx* c, int gauge_id, int dom_id, const double* in, double* out, int nrhs, int prec, hipStream_t st) {
   auto ob = opblock(c, gauge_id, dom_id);
   const size_t n = (size_t)nrhs * ob->field;
@@ -431,6 +510,11 @@ void apply_eo(Ctx* c, int gauge_id, int dom_id, const double* in, double* out, i
     DBuf tmp(c->pool.get(), n * sizeof(double2));
     schur_apply<double2>(c, *ob, ob->U64.as<double2>(), ob->Ainv64.as<double2>(), xe.as<double2>(),
                          tmp.as<double2>(), oe.as<double2>(), nrhs, st);
+    DDML_HIP(hipMemsetAsync(out, 0, (size_t)nrhs * c->V * 12 * sizeof(double2), st));
+    DDML_HIP(launch_scatter(oe.as<double2>(), ob->bs, 0, nrhs, 1.0, reinterpret_cast<double2*>(out), st));
+    DDML_HIP(hipStreamSynchronize(st));
+  } else if (prec == DDML_MIXED_FP16) {
+    schur_apply16(c, *ob, xe.as<double2>(), oe.as<double2>(), nrhs, st);
     DDML_HIP(hipMemsetAsync(out, 0, (size_t)nrhs * c->V * 12 * sizeof(double2), st));
     DDML_HIP(launch_scatter(oe.as<double2>(), ob->bs, 0, nrhs, 1.0, reinterpret_cast<double2*>(out), st));
     DDML_HIP(hipStreamSynchronize(st));
@@ -574,6 +658,33 @@ SlotDesc<double2> make_desc<double2>(const Solve* s, BiState* st, int* act, int 
   return d;
 }
 
+template <>
+SlotDesc<h16c> make_desc<h16c>(const Solve* s, BiState* st, int* act, int order) {
+  SlotDesc<h16c> d{};
+  const OpBlock& ob = *s->ob;
+  const size_t n = (size_t)s->nrhs * ob.field;
+  d.g = ob.g;
+  d.nrhs = s->nrhs;
+  d.ntiles = ob.ntiles;
+  d.tps = ob.tps;
+  d.kappa = ob.bs.kappa;
+  d.U = ob.U16.as<h16c>();
+  d.Ainv = ob.Ainv16.as<h16c>();
+  d.Ainv_nrm = ob.Ainv16n.as<float>();
+  for (int k = 0; k < F_NUM; ++k) {
+    if (k == F_X) continue;
+    d.f[k] = s->f[k].as<h16c>();
+    d.nrm[k] = reinterpret_cast<float*>(d.f[k] + n);
+  }
+  d.x32 = s->f[F_X].as<float2>();
+  d.partial = s->partial.as<double2>();
+  d.active = act;
+  d.st = st;
+  d.src64 = s->te.as<double2>();
+  attach_walk(d, ob, order);
+  return d;
+}
+
 template <typename T2>
 int BatchRunner<T2>::join(Solve* s) {
   int slot = -1;
@@ -634,6 +745,7 @@ void BatchRunner<T2>::replay() {
 
 template struct BatchRunner<float2>;
 template struct BatchRunner<double2>;
+template struct BatchRunner<h16c>;
 
 // ------------------------------------------------------------ solve flow
 ddml_solver_params default_params() {
@@ -653,7 +765,8 @@ void check_params(const ddml_solver_params* p) {
   if (!(p->tol > 0) || !(p->tol < 1)) throw Error{DDML_EINVAL, "tol must be in (0,1)"};
   if (p->max_outer < 1 || p->max_inner < 1) throw Error{DDML_EINVAL, "max_outer and max_inner must be >= 1"};
   if (!(p->inner_tol > 0) || !(p->inner_tol < 1)) throw Error{DDML_EINVAL, "inner_tol must be in (0,1)"};
-  if (p->prec != DDML_FP64 && p->prec != DDML_MIXED_FP32) throw Error{DDML_EINVAL, "unknown precision"};
+  if (p->prec != DDML_FP64 && p->prec != DDML_MIXED_FP32 && p->prec != DDML_MIXED_FP16)
+    throw Error{DDML_EINVAL, "unknown precision"};
   if (p->solver != 0 && p->solver != 1) throw Error{DDML_EINVAL, "solver must be 0 (restarted) or 1 (reliable updates)"};
 }
 
@@ -677,6 +790,15 @@ BatchRunner<double2>& runner<double2>(Ctx* c, int nrhs) {
   }
   return *r;
 }
+template <>
+BatchRunner<h16c>& runner<h16c>(Ctx* c, int nrhs) {
+  auto& r = c->run16[nrhs];
+  if (!r) {
+    r.reset(new BatchRunner<h16c>());
+    r->init(c, nrhs, c->tune16, 64);
+  }
+  return *r;
+}
 
 void solve_prepare(Ctx* c, Solve* s) {
   if (s->nrhs < 1 || s->nrhs > kMaxRhs) throw Error{DDML_EINVAL, "nrhs must be in 1..12"};
@@ -694,10 +816,12 @@ void solve_prepare(Ctx* c, Solve* s) {
   s->to = DBuf(P, n * sizeof(double2));
   s->partial64 = DBuf(P, 2 * s->nrhs * nt * sizeof(double2));
   s->norms = DBuf(P, 3 * s->nrhs * sizeof(double2));
-  const size_t inner = s->prec == DDML_FP64 ? sizeof(double2) : sizeof(float2);
-  for (int k = 0; k < F_NUM; ++k) s->f[k] = DBuf(P, n * inner);
+  for (int k = 0; k < F_NUM; ++k)
+    s->f[k] = DBuf(P, (k == F_X && s->prec == DDML_MIXED_FP16) ? n * sizeof(float2)
+                                                             : inner_field_bytes(s->prec, n, s->nrhs, nt));
+  if (s->prec == DDML_MIXED_FP16) ensure16(c, *s->ob);
   s->partial = DBuf(P, 2 * s->nrhs * nt * sizeof(double2));
-  s->table1 = DBuf(P, std::max(sizeof(SlotDesc<double2>), sizeof(SlotDesc<float2>)));
+  s->table1 = DBuf(P, std::max({sizeof(SlotDesc<double2>), sizeof(SlotDesc<float2>), sizeof(SlotDesc<h16c>)}));
   s->tstart1 = DBuf(P, 2 * sizeof(int));
   s->n1 = DBuf(P, sizeof(int));
   const double kappa = s->ob->bs.kappa;
@@ -763,7 +887,8 @@ template <typename T2>
 static void launch_export(Ctx* c, Solve* s) {
   const OpBlock& ob = *s->ob;
   const size_t n = (size_t)s->nrhs * ob.field;
-  DDML_HIP(launch_cast_to_d(s->f[F_X].as<T2>(), s->te.as<double2>(), n, c->stream));
+  using XT = typename std::conditional<std::is_same<T2, h16c>::value, float2, T2>::type;  // 16-bit: FP32 x
+  DDML_HIP(launch_cast_to_d(s->f[F_X].as<XT>(), s->te.as<double2>(), n, c->stream));
   HopItem<double2> it = item64(ob, s->nrhs, c->tune64.order);
   it.clov = ob.Ainv64.as<double2>();
   it.in = s->te.as<double2>();
@@ -775,6 +900,10 @@ static void launch_export(Ctx* c, Solve* s) {
   DDML_HIP(launch_axpy_d(s->xe.as<double2>(), s->te.as<double2>(), 1.0, n, c->stream));
   DDML_HIP(launch_axpy_d(s->xo.as<double2>(), s->to.as<double2>(), 1.0, n, c->stream));
 }
+
+// Smallest relative reduction asked of a 16-bit inner solve: below it the
+// recursive residual drifts away from the true one by the storage rounding.
+constexpr double kInnerFloor16 = 1e-3;
 
 template <typename T2>
 static bool try_join(Ctx* c, Solve* s) {
@@ -792,6 +921,7 @@ static bool try_join(Ctx* c, Solve* s) {
     // tighter than the requested inner tolerance in mixed precision
     double need = s->rel[col] > 0 ? 0.1 * tol / s->rel[col] : 1e-3;
     double it = s->prec == DDML_FP64 ? std::max(need, 1e-14) : std::max(need, s->prm.inner_tol);
+    if (s->prec == DDML_MIXED_FP16) it = std::max(it, kInnerFloor16);
     it = std::min(it, 0.1);
     st[col].tol2 = it * it;
     st[col].max_iters = s->prm.max_inner;
@@ -865,6 +995,7 @@ void solve_progress(Ctx* c, std::vector<Solve*>& live, bool block) {
   for (Solve* s : live)
     if (s->state == 4) {
       if (s->prec == DDML_FP64) try_join<double2>(c, s);
+      else if (s->prec == DDML_MIXED_FP16) try_join<h16c>(c, s);
       else try_join<float2>(c, s);
     }
   // 3. one replay per runner with members; collect finished inner solves
@@ -894,6 +1025,7 @@ void solve_progress(Ctx* c, std::vector<Solve*>& live, bool block) {
   };
   step(c->run32, float2{});
   step(c->run64, double2{});
+  step(c->run16, h16c{});
 }
 
 void solve_finish(Ctx* c, Solve* s) {
@@ -928,12 +1060,21 @@ static void time_stencil_t(Ctx* c, const OpBlock& ob, const T2* U, const T2* Ain
                            int order, int grid, int splits, int stage, double out[4]) {
   hipStream_t st = c->stream;
   const size_t Vh = ob.g.Vh, n = (size_t)nrhs * ob.field;
+  constexpr bool h16 = std::is_same<T2, h16c>::value;
+  const int prec = h16 ? DDML_MIXED_FP16 : (sizeof(T2) == sizeof(double2) ? DDML_FP64 : DDML_MIXED_FP32);
+  const size_t fb = inner_field_bytes(prec, n, nrhs, ob.ntiles), nn = (size_t)nrhs * ob.ntiles * kTile;
   DevPool* P = c->pool.get();
-  DBuf fP(P, n * sizeof(T2)), fT(P, n * sizeof(T2)), fV(P, n * sizeof(T2)), fR(P, n * sizeof(T2));
+  DBuf fP(P, fb), fT(P, fb), fV(P, fb), fR(P, fb);
   DBuf part(P, 2 * nrhs * ob.ntiles * sizeof(double2)), act(P, kMaxRhs * sizeof(int));
   DBuf tab(P, sizeof(SlotDesc<T2>)), ts(P, 2 * sizeof(int)), ns(P, sizeof(int)), xs(P, kXcd * 2 * sizeof(int));
-  DDML_HIP(launch_fill(fP.as<T2>(), n, 1.0, st));
-  DDML_HIP(launch_fill(fR.as<T2>(), n, 0.5, st));
+  auto scales = [&](DBuf& b) { return reinterpret_cast<float*>(b.as<h16c>() + n); };
+  if constexpr (h16) {
+    DDML_HIP(launch_fill16(fP.as<h16c>(), n, scales(fP), nn, 1.0, st));
+    DDML_HIP(launch_fill16(fR.as<h16c>(), n, scales(fR), nn, 0.5, st));
+  } else {
+    DDML_HIP(launch_fill(fP.as<T2>(), n, 1.0, st));
+    DDML_HIP(launch_fill(fR.as<T2>(), n, 0.5, st));
+  }
   std::vector<int> ones(kMaxRhs, 1);
   DDML_HIP(hipMemcpyAsync(act.p, ones.data(), kMaxRhs * sizeof(int), hipMemcpyHostToDevice, st));
   SlotDesc<T2> d{};
@@ -948,6 +1089,13 @@ static void time_stencil_t(Ctx* c, const OpBlock& ob, const T2* U, const T2* Ain
   d.f[F_TMP] = fT.as<T2>();
   d.f[F_V] = fV.as<T2>();
   d.f[F_RH] = fR.as<T2>();
+  if constexpr (h16) {
+    d.nrm[F_P] = scales(fP);
+    d.nrm[F_TMP] = scales(fT);
+    d.nrm[F_V] = scales(fV);
+    d.nrm[F_RH] = scales(fR);
+    d.Ainv_nrm = ob.Ainv16n.as<float>();
+  }
   d.partial = part.as<double2>();
   d.active = act.as<int>();
   attach_walk(d, ob, order);
@@ -990,14 +1138,17 @@ static void time_stencil_t(Ctx* c, const OpBlock& ob, const T2* U, const T2* Ain
     t1 += b;
   }
   for (auto& e : ev) DDML_HIP(hipEventDestroy(e));
-  const double s = sizeof(T2) / 2;  // bytes per real
+  const double s = h16 ? 2.0 : sizeof(T2) / 2;  // bytes per real
   // CINV_HOP: read the input spinor, all links of the box (4 per site), A^{-1} of
   // the output parity; write the output.  SCHUR (+dot): read input, aux and the
   // dot operand, links, A^{-1}; write the output.
   out[0] = t0 / iters;
   out[1] = t1 / iters;
-  out[2] = (double)Vh * (48.0 * nrhs + 144.0 + 72.0) * s;
-  out[3] = (double)Vh * (96.0 * nrhs + 144.0 + 72.0) * s;
+  // 16-bit: plus one 4-byte scale per site and column of every spinor touched
+  // and per site of A^{-1}
+  const double sc = h16 ? 4.0 : 0.0;
+  out[2] = (double)Vh * ((48.0 * nrhs + 144.0 + 72.0) * s + sc * (2 * nrhs + 1));
+  out[3] = (double)Vh * ((96.0 * nrhs + 144.0 + 72.0) * s + sc * (4 * nrhs + 1));
 }
 
 void time_stencil(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, int iters, const TuneChoice& want,
@@ -1014,18 +1165,24 @@ void time_stencil(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, int iter
   splits = std::min(splits, (nrhs + R - 1) / R);
   grid = ((grid + kXcd - 1) / kXcd) * kXcd;
   auto ob = opblock(c, gauge_id, dom_id);
-  if (prec == DDML_FP64)
+  if (prec == DDML_FP64) {
     time_stencil_t<double2>(c, *ob, ob->U64.as<double2>(), ob->Ainv64.as<double2>(), nrhs, iters, R, order, grid,
                             splits, stage, out);
-  else
+  } else if (prec == DDML_MIXED_FP16) {
+    if (stage != 1) throw Error{DDML_EINVAL, "16-bit fields need stage 1"};
+    ensure16(c, *ob);
+    time_stencil_t<h16c>(c, *ob, ob->U16.as<h16c>(), ob->Ainv16.as<h16c>(), nrhs, iters, R, order, grid, splits,
+                         stage, out);
+  } else {
     time_stencil_t<float2>(c, *ob, ob->U32.as<float2>(), ob->Ainv32.as<float2>(), nrhs, iters, R, order, grid,
                            splits, stage, out);
+  }
 }
 
 void autotune(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, double best[6]) {
   double bt = 1e300;
   TuneChoice b = c->tune(prec);
-  for (int stage = 0; stage <= 1; ++stage)
+  for (int stage = prec == DDML_MIXED_FP16 ? 1 : 0; stage <= 1; ++stage)
     for (int R = 1; R <= 3; ++R)
       for (int splits = 1; splits <= 3; ++splits) {
         if (splits > (nrhs + R - 1) / R) continue;
@@ -1049,6 +1206,7 @@ void autotune(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, double best[
   c->tune(prec) = b;
   c->run32.clear();  // graphs are captured with the launch choice: rebuild on next use
   c->run64.clear();
+  c->run16.clear();
   best[0] = b.R;
   best[1] = b.order;
   best[2] = b.grid;

@@ -97,6 +97,7 @@ struct OpBlock {
   size_t field = 0;        // complex numbers in one [12-column] field: nrhs * 12 * ntiles * 64 / nrhs
   DBuf U64, A64, Ainv64;   // FP64 operator data
   DBuf U32, Ainv32;        // FP32 copies for the inner solve
+  DBuf U16, Ainv16, Ainv16n;  // 16-bit copies (built on first use by a DDML_MIXED_FP16 solve)
   DBuf walk[2];            // tile walks of TILE_ORDER_SUB2 / TILE_ORDER_SUB4
   int xoff[2][kXcd + 1] = {};
   size_t bytes = 0;
@@ -113,7 +114,7 @@ struct Solve {
   DBuf be, bo, xe, xo, re, ro, te, to;
   DBuf partial64;   // [2][nrhs][ntiles]
   DBuf norms;       // double2 [4][nrhs]: |b|^2, |r|^2
-  // inner state in the inner precision
+  // inner state in the inner precision (16-bit: values then scales; F_X in FP32)
   DBuf f[F_NUM];
   DBuf partial;     // [2][nrhs][ntiles]
   DBuf table1, tstart1, n1;  // one-entry slot table
@@ -184,12 +185,15 @@ struct Ctx {
   std::map<std::pair<int, int>, std::shared_ptr<OpBlock>> blocks;
   std::map<int, std::unique_ptr<BatchRunner<float2>>> run32;   // by nrhs
   std::map<int, std::unique_ptr<BatchRunner<double2>>> run64;
+  std::map<int, std::unique_ptr<BatchRunner<h16c>>> run16;
   DBuf flag;        // device int for clover failures
   DomainRec full{};  // the whole lattice (dom_id -1)
   void* pinned = nullptr;   // small pinned host staging area
   size_t pinned_bytes = 0;
-  TuneChoice tune64, tune32;   // launch choices of the FP64 and FP32 kernels
-  TuneChoice& tune(int prec) { return prec == DDML_FP64 ? tune64 : tune32; }
+  TuneChoice tune64, tune32, tune16;   // launch choices of the FP64, FP32 and 16-bit kernels
+  TuneChoice& tune(int prec) {
+    return prec == DDML_FP64 ? tune64 : (prec == DDML_MIXED_FP16 ? tune16 : tune32);
+  }
   std::unique_ptr<Server> server;
   ~Ctx();
 };

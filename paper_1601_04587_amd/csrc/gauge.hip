@@ -342,6 +342,45 @@ __global__ void k_scatter(const double2* __restrict__ eo, BlockSpec bs, int p, i
     }
   }
 }
+// 16-bit copies for the FP16-storage inner solver: links with scale 1 (their
+// entries are bounded by 1 in magnitude), A^{-1} with one scale per site.
+__global__ void k_quant_links(const double2* __restrict__ U64, h16c* __restrict__ U16, size_t n) {
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+    const double2 u = U64[k];
+    U16[k] = h16c{q16((float)u.x * kQ), q16((float)u.y * kQ)};
+  }
+}
+__global__ void k_quant_clover(const double2* __restrict__ A, h16c* __restrict__ A16, float* __restrict__ nrm,
+                               int nt) {
+  const size_t nsite = (size_t)2 * nt * kTile;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < nsite; t += (size_t)gridDim.x * blockDim.x) {
+    const int p = (int)(t / ((size_t)nt * kTile)), i = (int)(t % ((size_t)nt * kTile));
+    double m = 0;
+    for (int k = 0; k < kCloverSlots; ++k) {
+      const double2 a = A[cidx(nt, p, k, i)];
+      m = fmax(m, fmax(fabs(a.x), fabs(a.y)));
+    }
+    const float mf = (float)m;
+    const float inv = mf > 0.f ? kQ / mf : 0.f;
+    for (int k = 0; k < kCloverSlots; ++k) {
+      const double2 a = A[cidx(nt, p, k, i)];
+      A16[cidx(nt, p, k, i)] = h16c{q16((float)a.x * inv), q16((float)a.y * inv)};
+    }
+    nrm[t] = mf;
+  }
+}
+hipError_t launch_quant_links(const double2* U64, h16c* U16, size_t n, hipStream_t st) {
+  size_t g = (n + 255) / 256;
+  hipLaunchKernelGGL(k_quant_links, dim3((int)(g > 16384 ? 16384 : (g ? g : 1))), dim3(256), 0, st, U64, U16, n);
+  return hipGetLastError();
+}
+hipError_t launch_quant_clover(const double2* Ainv64, h16c* Ainv16, float* nrm, int ntiles, hipStream_t st) {
+  size_t g = ((size_t)2 * ntiles * kTile + 255) / 256;
+  hipLaunchKernelGGL(k_quant_clover, dim3((int)(g > 16384 ? 16384 : (g ? g : 1))), dim3(256), 0, st, Ainv64, Ainv16,
+                     nrm, ntiles);
+  return hipGetLastError();
+}
+
 static int grid_of(size_t n) {
   size_t g = (n + 255) / 256;
   return (int)(g > 16384 ? 16384 : (g == 0 ? 1 : g));

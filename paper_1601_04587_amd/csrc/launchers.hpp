@@ -17,6 +17,9 @@ hipError_t launch_hop_batch(const SlotDesc<float2>* slots, const int* tile_start
 hipError_t launch_hop_batch(const SlotDesc<double2>* slots, const int* tile_start, const int* xstart, int xstride,
                             const int* nslots_p, int nrhs, int R, int mode, int red, int fin, int faux, int fout,
                             int fred, int par_out, int grid, int order, int splits, int stage, hipStream_t st);
+hipError_t launch_hop_batch(const SlotDesc<h16c>* slots, const int* tile_start, const int* xstart, int xstride,
+                            const int* nslots_p, int nrhs, int R, int mode, int red, int fin, int faux, int fout,
+                            int fred, int par_out, int grid, int order, int splits, int stage, hipStream_t st);
 // host mirror of the banded order: tiles of a box (ntiles, tps) owned by XCD x
 inline int band_count(int ntiles, int tps, int x) {
   const int S = tps > 0 ? tps : ntiles;
@@ -35,6 +38,9 @@ hipError_t launch_vec(const SlotDesc<double2>* slots, const int* tile_start, con
                       int grid, hipStream_t st);
 hipError_t launch_fin(const SlotDesc<float2>* slots, const int* nslots_p, int max_slots, int op, hipStream_t st);
 hipError_t launch_fin(const SlotDesc<double2>* slots, const int* nslots_p, int max_slots, int op, hipStream_t st);
+hipError_t launch_vec(const SlotDesc<h16c>* slots, const int* tile_start, const int* nslots_p, int nrhs, int op,
+                      int grid, hipStream_t st);
+hipError_t launch_fin(const SlotDesc<h16c>* slots, const int* nslots_p, int max_slots, int op, hipStream_t st);
 
 // elementwise helpers on raw FP64 / mixed arrays (n complex numbers)
 hipError_t launch_cast_to_d(const float2* in, double2* out, size_t n, hipStream_t st);
@@ -43,6 +49,10 @@ hipError_t launch_cast_to_f(const double2* in, float2* out, size_t n, hipStream_
 hipError_t launch_fill(float2* v, size_t n, double a, hipStream_t st);
 hipError_t launch_fill(double2* v, size_t n, double a, hipStream_t st);
 hipError_t launch_axpy_d(double2* y, const double2* x, double a, size_t n, hipStream_t st);
+// 16-bit fields: values [nrhs][ntiles][12][64] with scales [nrhs][ntiles * 64]
+hipError_t launch_fill16(h16c* v, size_t n, float* nrm, size_t nn, double a, hipStream_t st);
+hipError_t launch_quant16(const double2* in, h16c* out, float* nrm, int nrhs, int ntiles, hipStream_t st);
+hipError_t launch_dequant16(const h16c* in, const float* nrm, double2* out, int nrhs, int ntiles, hipStream_t st);
 // column norms |v_col|^2 of a [nrhs][ntiles][12][64] field into out[nrhs].x (accumulate=1 adds)
 hipError_t launch_col_norms(const double2* v, int Vh, int nrhs, double2* partial, int ntiles, double2* out,
                             int accumulate, hipStream_t st);
@@ -66,6 +76,9 @@ struct BlockSpec {
 hipError_t launch_build_links(const GaugeView& gv, const BlockSpec& bs, double2* U64, float2* U32, hipStream_t st);
 hipError_t launch_build_clover(const GaugeView& gv, const BlockSpec& bs, double2* A64, double2* Ainv64,
                                float2* Ainv32, int* bad, hipStream_t st);
+// 16-bit copies of an operator block's links and A^{-1} (n = 2 * ntiles * 64 sites)
+hipError_t launch_quant_links(const double2* U64, h16c* U16, size_t n, hipStream_t st);
+hipError_t launch_quant_clover(const double2* Ainv64, h16c* Ainv16, float* nrm, int ntiles, hipStream_t st);
 // canonical [nrhs][V][12] complex128 <-> domain EO field [nrhs][ntiles][12][64] of parity p, scaled
 hipError_t launch_gather(const double2* canon, const BlockSpec& bs, int p, int nrhs, double scale, double2* eo,
                          hipStream_t st);

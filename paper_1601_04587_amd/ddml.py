@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libddml.so")
 
 OK, EINVAL, ENOMEM, EAGAIN, ENOTCONVERGED, ENUMERIC, EDEVICE = 0, -1, -2, -3, -4, -5, -6
 BC_PERIODIC, BC_ANTIPERIODIC = 0, 1
-FP64, MIXED_FP32 = 0, 1
+FP64, MIXED_FP32, MIXED_FP16 = 0, 1, 2
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EAGAIN", -4: "ENOTCONVERGED", -5: "ENUMERIC",
                 -6: "EDEVICE"}
 

@@ -122,3 +122,23 @@ def test_autotune_and_stencil_timing(setup):
     assert rc == ddml.OK
     C = oracle.clover_term(U, L, 1.769)
     assert oracle.residual(U, L, 0.1340, b, x, C=C, lo=lo, hi=hi).max() <= 1e-10 * (1 + 1e-3)
+
+
+def test_fp16_storage_solve_and_iterations(setup):
+    """16-bit storage of the inner solver: FP64 defect correction still reaches
+    1e-10, at a bounded cost in BiCGstab iterations over FP32 storage."""
+    L, U, ctx, gid, doms, ids = setup
+    b = inputs.point_source(L, (7, 0, 0, 0))
+    C = oracle.clover_term(U, L, 1.769)
+    x16 = np.zeros_like(b)
+    rc, info16 = ctx.solve_domain(gid, ids["G2"], b, x16, 12, ddml.solver_params(tol=1e-10, prec=ddml.MIXED_FP16))
+    assert rc == ddml.OK
+    assert oracle.residual(U, L, 0.1340, b, x16, C=C).max() <= 1e-10 * (1 + 1e-3)
+    x32 = np.zeros_like(b)
+    rc, info32 = ctx.solve_domain(gid, ids["G2"], b, x32, 12, ddml.solver_params(tol=1e-10))
+    assert rc == ddml.OK
+    it16 = max(i.inner_iters for i in info16)
+    it32 = max(i.inner_iters for i in info32)
+    assert it16 <= 2 * it32 + 10, (it16, it32)
+    # 16-bit runs take more FP64 corrections (each inner solve stops at 1e-3)
+    assert max(i.outer_iters for i in info16) >= max(i.outer_iters for i in info32)
