@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--dims", default="64,32,32,32", help="T,L1,L2,L3 (T a multiple of 16)")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-fp16", action="store_true", help="skip the 16-bit storage leg")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=32)
@@ -218,6 +219,36 @@ def main():
     log("mixed batched: %d solves in %.2fs -> %.3f solves/s, worst residual %.2e, inner iters %s"
         % (nsolves, t1 - t0, solves_per_s, worst, iters[:6]))
 
+    # ------------------------------------ 16-bit storage of the inner solve
+    fp16 = None
+    if not args.no_fp16:
+        tune16 = ctx.autotune(gid0, doms[0][2], 12, ddml.MIXED_FP16)
+        prm16 = ddml.solver_params(tol=1e-10, prec=ddml.MIXED_FP16)
+        rc, _, _, _ = step(0, prm16)   # warm-up (graph capture)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        it16, outer16, worst16 = [], [], 0.0
+        for j in range(args.warmup, nsteps):
+            rc, infos, _, _ = step(j, prm16)
+            assert rc == ddml.OK, "16-bit solve failed: %s" % ctx.last_error()
+            for per_slab in infos:
+                for per_level in per_slab:
+                    it16.append(max(i.inner_iters for i in per_level))
+                    outer16.append(max(i.outer_iters for i in per_level))
+                    worst16 = max(worst16, max(i.true_rel_residual for i in per_level))
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        s16 = ctx.time_stencil(gid0, doms[0][2], 12, ddml.MIXED_FP16, args.stencil_iters)
+        fp16 = {"solves_per_s": nsolves / (b - a), "ms_per_step": 1e3 * (b - a) / args.steps,
+                "inner_iters_per_solve": it16, "outer_iters_per_solve": outer16,
+                "worst_true_rel_residual": worst16,
+                "autotune": dict(zip(("R", "tile_order", "grid", "splits", "stage", "ms_pair"), tune16)),
+                "stencil_even_half": {"ms": s16[1], "bytes": s16[3], "GB/s": s16[3] / s16[1] * 1e-6},
+                "stencil_odd_half": {"ms": s16[0], "bytes": s16[2], "GB/s": s16[2] / s16[0] * 1e-6}}
+        log("16-bit storage: %.3f solves/s, worst residual %.2e, inner iters %s, outer %s; stencil even %.3f ms "
+            "%.0f GB/s (algorithmic, 16-bit)" % (fp16["solves_per_s"], worst16, it16[:6], outer16[:6], s16[1],
+                                                 s16[3] / s16[1] * 1e-6))
+
     # --------------------------------------------------- stencil roofline
     sten32 = ctx.time_stencil(gid0, doms[0][2], 12, ddml.MIXED_FP32, args.stencil_iters)
     sten64 = ctx.time_stencil(gid0, doms[0][2], 12, ddml.FP64, max(4, args.stencil_iters // 2))
@@ -277,6 +308,7 @@ def main():
         "autotune": {"fp32": dict(zip(("R", "tile_order", "grid", "splits", "stage", "ms_pair"), tune32)),
                      "fp64": dict(zip(("R", "tile_order", "grid", "splits", "stage", "ms_pair"), tune64))},
         "fp64_one_at_a_time": fp64,
+        "fp16_storage": fp16,
         "mixed_over_fp64": (solves_per_s / fp64["solves_per_s"]) if fp64 else None,
         "serving": serve,
         "inner_iters_per_solve": iters,

@@ -233,10 +233,12 @@ __device__ __forceinline__ void stage_tile(const BoxGeom& g, const E* __restrict
   __syncthreads();
 }
 
+// on: bit r set if column r0 + r is active (read once per tile by the caller,
+// so the direction loop has no load-dependent branch and its loads can overlap)
 template <typename E, int R, bool ST, typename C = typename CompOf<E>::type>
 __device__ __forceinline__ void hop_sum(const BoxGeom& g, int p, int i, const E* __restrict__ U, const C* sm,
                                         const E* __restrict__ in, const float* __restrict__ in_n, int r0, int nr,
-                                        const int* __restrict__ act, C acc[R][12]) {
+                                        unsigned on, C acc[R][12]) {
   int y[4];
   eo_coords(g, p, i, y);
   const int q = 1 - p;
@@ -267,7 +269,7 @@ __device__ __forceinline__ void hop_sum(const BoxGeom& g, int p, int i, const E*
       }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        if (r < nr && (act == nullptr || ldg(act + r0 + r))) {
+        if (r < nr && ((on >> r) & 1u)) {
           C psi[12], h[6], gg[6];
           if constexpr (kIs16<E>)
             spinor_load_q(in + fidx(nt, r0 + r, 0, n), in_n[(size_t)(r0 + r) * nt * kTile + n], psi, false);
@@ -358,8 +360,13 @@ __device__ __forceinline__ void hop_tile(const BoxGeom g, const TileArgs<E>& a, 
   const int i = tile * kTile + lane;
   const bool valid = i < g.Vh;
   const int nt = g.ntiles;
+  unsigned on = 0;  // active columns of this wavefront
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (r < nr && (act == nullptr || ldg(act + r0 + r))) on |= 1u << r;
+  if (on == 0) return;  // uniform across the wave
   C acc[R][12];
-  if (valid) hop_sum<E, R, ST>(g, p, i, a.U, sm, a.in, a.in_n, r0, nr, act, acc);
+  if (valid) hop_sum<E, R, ST>(g, p, i, a.U, sm, a.in, a.in_n, r0, nr, on, acc);
   const C* cl;
   if constexpr (ST) cl = sm + kStageLinkPairs * 128 + lane * 2;
   else cl = a.clov + cidx(nt, p, 0, i);
@@ -367,8 +374,7 @@ __device__ __forceinline__ void hop_tile(const BoxGeom g, const TileArgs<E>& a, 
   for (int r = 0; r < R; ++r) {
     if (r >= nr) break;
     const int col = r0 + r;
-    const bool on = (act == nullptr || ldg(act + col));
-    if (!on) continue;  // uniform across the wave
+    if (!((on >> r) & 1u)) continue;  // uniform across the wave
     double2 s0 = make_double2(0, 0), s1 = make_double2(0, 0);
     const size_t base = fidx(nt, col, 0, i);
     const size_t ns = (size_t)col * nt * kTile + i;  // scale index of 16-bit fields
