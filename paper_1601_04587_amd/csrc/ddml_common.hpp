@@ -66,6 +66,23 @@ template <typename T2> __device__ __forceinline__ T2 cmulc(T2 a, T2 b) {
   return mk<T2>(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
 template <typename T2> __device__ __forceinline__ T2 cscale(T2 a, decltype(T2::x) s) { return mk<T2>(a.x * s, a.y * s); }
+// acc + a b and acc + conj(a) b as four fused multiply-adds
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <typename T2> __device__ __forceinline__ T2 cmac(T2 acc, T2 a, T2 b) {
+  acc.x = fmadd(a.x, b.x, acc.x);
+  acc.x = fmadd(-a.y, b.y, acc.x);
+  acc.y = fmadd(a.x, b.y, acc.y);
+  acc.y = fmadd(a.y, b.x, acc.y);
+  return acc;
+}
+template <typename T2> __device__ __forceinline__ T2 cmacc(T2 acc, T2 a, T2 b) {
+  acc.x = fmadd(a.x, b.x, acc.x);
+  acc.x = fmadd(a.y, b.y, acc.x);
+  acc.y = fmadd(a.x, b.y, acc.y);
+  acc.y = fmadd(-a.y, b.x, acc.y);
+  return acc;
+}
 // i*a and -i*a
 template <typename T2> __device__ __forceinline__ T2 ci(T2 a) { return mk<T2>(-a.y, a.x); }
 template <typename T2> __device__ __forceinline__ T2 cmi(T2 a) { return mk<T2>(a.y, -a.x); }

@@ -79,22 +79,19 @@ __device__ __forceinline__ void reconstruct(int mu, bool fwd, const T2 g[6], T2 
   }
 }
 
-// g = U h (dag=false) or U^dag h (dag=true), per spin of the half spinor
+// g = U h (dag=false) or U^dag h (dag=true), per spin of the half spinor;
+// every complex multiply-add is four fused multiply-adds
 template <typename T2>
 __device__ __forceinline__ void su3_mul(const T2 u[9], bool dag, const T2 h[6], T2 g[6]) {
 #pragma unroll
   for (int s = 0; s < 2; ++s)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      T2 acc;
-      if (!dag) {
-        acc = cmul(u[3 * a], h[3 * s]);
-        acc = cadd(acc, cmul(u[3 * a + 1], h[3 * s + 1]));
-        acc = cadd(acc, cmul(u[3 * a + 2], h[3 * s + 2]));
-      } else {
-        acc = cmulc(u[a], h[3 * s]);
-        acc = cadd(acc, cmulc(u[3 + a], h[3 * s + 1]));
-        acc = cadd(acc, cmulc(u[6 + a], h[3 * s + 2]));
+      T2 acc = mk<T2>(0, 0);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        if (!dag) acc = cmac(acc, u[3 * a + b], h[3 * s + b]);
+        else acc = cmacc(acc, u[3 * b + a], h[3 * s + b]);
       }
       g[3 * s + a] = acc;
     }
@@ -171,8 +168,8 @@ __device__ __forceinline__ void herm6_apply(const T2 m[18], const T2 x[6], T2 y[
 #pragma unroll
     for (int j = i + 1; j < 6; ++j) {
       const T2 h = m[k++];
-      y[i] = cadd(y[i], cmul(h, x[j]));
-      y[j] = cadd(y[j], cmulc(h, x[i]));
+      y[i] = cmac(y[i], h, x[j]);
+      y[j] = cmacc(y[j], h, x[i]);
     }
 }
 
