@@ -84,13 +84,17 @@ typedef struct {
 typedef struct {
   double tol;        /* target ||b - D_Gamma x|| / ||b|| per rhs (FP64 true residual) */
   int max_outer;     /* defect-correction cycles */
-  int max_inner;     /* BiCGstab iterations per cycle */
+  int max_inner;     /* inner Krylov iterations per cycle */
   double inner_tol;  /* relative reduction of the inner residual per cycle */
   int prec;          /* ddml_prec */
-  int solver;        /* 0 = BiCGstab restarted (r0 = r, p = v = 0) at every FP64 correction;
+  int solver;        /* 0 = BiCGstab (van der Vorst 1992) restarted (r0 = r, p = v = 0) at every
+                        FP64 correction;
                         1 = BiCGstab with reliable updates: the Krylov state is kept and only
-                        the residual is replaced by the FP64 one */
-  int gcr_m;         /* reserved */
+                        the residual is replaced by the FP64 one;
+                        2 = GCR(m) (Eisenstat, Elman, Schultz 1983), restarted every gcr_m
+                        steps: minimal residual over the cycle's directions, orthogonalised
+                        by classical Gram-Schmidt; FP32 or FP64 inner vectors only */
+  int gcr_m;         /* GCR restart length, 1..8 (0 = 8); ignored by BiCGstab */
 } ddml_solver_params;
 
 typedef struct {
@@ -137,8 +141,9 @@ int ddml_apply_Dw(ddml_ctx ctx, int gauge_id, int dom_id, const double* in, doub
  *   out_e = in_e - kappa^2 A_ee^{-1} H_eo A_oo^{-1} H_oe in_e
  * with M = 2 kappa D = A - kappa H, on the sites of Gamma whose local parity
  * (sum_mu (x_mu - lo_mu) mod 2) is even; out is zero on all other sites.
- * prec selects FP64 or FP32 arithmetic (FP32: inputs rounded to FP32, output
- * widened).  Errors: EINVAL, ENOMEM, EDEVICE. */
+ * prec selects FP64, FP32 or 16-bit storage (inputs rounded to the inner
+ * format, output widened; DDML_MIXED_FP16 also stores the intermediate odd
+ * field and reads 16-bit links and A^{-1}).  Errors: EINVAL, ENOMEM, EDEVICE. */
 int ddml_apply_eo(ddml_ctx ctx, int gauge_id, int dom_id, const double* in, double* out, int nrhs, int prec,
                   int on_device, void* stream);
 
@@ -219,7 +224,8 @@ int ddml_contract_nucleon(ddml_ctx ctx, const double* terms, int nlevels, double
  * H_oe in_e) and of the even half (out_e = in_e - kappa^2 A_ee^{-1} H_eo t_o
  * with the dot product (r0, out_e)); out[2], out[3]: algorithmic bytes of one
  * launch of each (every array the kernel must touch, counted once).
- * prec: DDML_FP64 or DDML_MIXED_FP32 (FP32 kernels).  R (columns per thread,
+ * prec: DDML_FP64, DDML_MIXED_FP32 or DDML_MIXED_FP16 (16-bit storage, stage 1
+ * only; bytes then count 2 per real plus the scales).  R (columns per thread,
  * 1..3), order, grid (workgroups), splits and stage select the launch; values
  * <= 0 (order, stage: < 0) take the context's current choice.  Tile orders: 0 linear;
  * 1 each of the 8 XCDs owns a band of every time slice and walks the slices in

@@ -372,6 +372,239 @@ __global__ void __launch_bounds__(768) k_fin(const SlotDesc<T2>* __restrict__ sl
   }
 }
 
+// ------------------------------------------------------------------ GCR(m)
+// Generalised conjugate residual on the Schur operator (Eisenstat, Elman and
+// Schultz 1983), restarted every m steps, one recursion per column.  Step k
+// of a cycle, with p_k the current residual (written by the previous step):
+//   q_k = M p_k (stencil);  beta_j = (q_j, q_k) / |q_j|^2 for j < k (classical
+//   Gram-Schmidt, one pass for all j);  q_k -= sum beta_j q_j, p_k -= sum
+//   beta_j p_j;  alpha = (q_k, r) / |q_k|^2;  x += alpha p_k;  r -= alpha q_k;
+//   p_{k+1 mod m} = r.
+// The residual norm decreases monotonically.  Reductions as in BiCGstab:
+// per-tile FP64 partials, fixed-order finalisation.
+template <typename T2, int OP>
+__global__ void __launch_bounds__(768) k_gcr(const SlotDesc<T2>* __restrict__ slots, const int* __restrict__ tile_start,
+                                             const int* __restrict__ nslots_p, int k, int m) {
+  using T = decltype(T2::x);
+  const int ns = *nslots_p;
+  const int total = tile_start[ns];
+  const int lane = threadIdx.x & 63;
+  const int col = threadIdx.x >> 6;
+  for (int vt = blockIdx.x; vt < total; vt += gridDim.x) {
+    const int s = find_slot_v(tile_start, ns, vt);
+    const SlotDesc<T2>& d = slots[s];
+    if (col >= d.nrhs) continue;
+    if (OP != GCR_INIT && !d.active[col]) continue;  // uniform per wave
+    const int tile = vt - tile_start[s];
+    const int nt = d.ntiles;
+    const int i = tile * kTile + lane;
+    const bool valid = i < d.g.Vh;
+    const size_t base = fidx(nt, col, 0, i);
+    const double2* gc = d.gcoef + (size_t)col * 2 * kGcrMax;
+    double2 red[kGcrMax];
+#pragma unroll
+    for (int j = 0; j < kGcrMax; ++j) red[j] = make_double2(0, 0);
+    if (OP == GCR_INIT) {  // r = (T) src64, x = 0, p_0 = r; red[0] = |r|^2
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const size_t o = base + 128 * q;
+        double2 b0 = make_double2(0, 0), b1 = b0;
+        if (valid) ld2(d.src64 + o, b0, b1);
+        const T2 t0 = mk<T2>((T)b0.x, (T)b0.y), t1 = mk<T2>((T)b1.x, (T)b1.y), z = mk<T2>(0, 0);
+        st2(d.f[F_R] + o, t0, t1);
+        st2(d.f[F_GP0] + o, t0, t1);
+        st2(d.f[F_X] + o, z, z);
+        red[0].x += (double)t0.x * t0.x + (double)t0.y * t0.y + (double)t1.x * t1.x + (double)t1.y * t1.y;
+      }
+    } else if (OP == GCR_DOTS) {  // red[j] = (q_j, q_k), j < k
+      if (valid) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          const size_t o = base + 128 * q;
+          T2 a0, a1;
+          ld2(d.f[F_GQ0 + k] + o, a0, a1);
+#pragma unroll
+          for (int j = 0; j < kGcrMax; ++j) {
+            if (j >= k) break;
+            T2 b0, b1;
+            ld2(d.f[F_GQ0 + j] + o, b0, b1);
+            red[j].x += (double)b0.x * a0.x + (double)b0.y * a0.y + (double)b1.x * a1.x + (double)b1.y * a1.y;
+            red[j].y += (double)b0.x * a0.y - (double)b0.y * a0.x + (double)b1.x * a1.y - (double)b1.y * a1.x;
+          }
+        }
+      }
+    } else if (OP == GCR_UPDATE) {  // orthogonalise q_k, p_k; red[0] = (q_k, r), red[1] = |q_k|^2
+      if (valid) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          const size_t o = base + 128 * q;
+          T2 qa, qb, pa, pb, ra, rb;
+          ld2(d.f[F_GQ0 + k] + o, qa, qb);
+          ld2(d.f[F_GP0 + k] + o, pa, pb);
+#pragma unroll
+          for (int j = 0; j < kGcrMax; ++j) {
+            if (j >= k) break;
+            const T2 be = mk<T2>((T)gc[j].x, (T)gc[j].y);
+            T2 u0, u1;
+            ld2(d.f[F_GQ0 + j] + o, u0, u1);
+            qa = csub(qa, cmul(be, u0));
+            qb = csub(qb, cmul(be, u1));
+            ld2(d.f[F_GP0 + j] + o, u0, u1);
+            pa = csub(pa, cmul(be, u0));
+            pb = csub(pb, cmul(be, u1));
+          }
+          if (k > 0) {
+            st2(d.f[F_GQ0 + k] + o, qa, qb);
+            st2(d.f[F_GP0 + k] + o, pa, pb);
+          }
+          ld2(d.f[F_R] + o, ra, rb);
+          red[0].x += (double)qa.x * ra.x + (double)qa.y * ra.y + (double)qb.x * rb.x + (double)qb.y * rb.y;
+          red[0].y += (double)qa.x * ra.y - (double)qa.y * ra.x + (double)qb.x * rb.y - (double)qb.y * rb.x;
+          red[1].x += (double)qa.x * qa.x + (double)qa.y * qa.y + (double)qb.x * qb.x + (double)qb.y * qb.y;
+        }
+      }
+    } else {  // GCR_XR: x += alpha p_k, r -= alpha q_k, p_{k+1 mod m} = r; red[0] = |r|^2
+      if (valid) {
+        const BiState& st = d.st[col];
+        const T2 al = mk<T2>((T)st.alpha.x, (T)st.alpha.y);
+        const int nx = (k + 1 == m) ? 0 : k + 1;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          const size_t o = base + 128 * q;
+          T2 x0, x1, p0, p1, q0, q1, r0, r1;
+          ld2(d.f[F_X] + o, x0, x1);
+          ld2(d.f[F_GP0 + k] + o, p0, p1);
+          ld2(d.f[F_GQ0 + k] + o, q0, q1);
+          ld2(d.f[F_R] + o, r0, r1);
+          st2(d.f[F_X] + o, cadd(x0, cmul(al, p0)), cadd(x1, cmul(al, p1)));
+          r0 = csub(r0, cmul(al, q0));
+          r1 = csub(r1, cmul(al, q1));
+          st2(d.f[F_R] + o, r0, r1);
+          st2(d.f[F_GP0 + nx] + o, r0, r1);
+          red[0].x += (double)r0.x * r0.x + (double)r0.y * r0.y + (double)r1.x * r1.x + (double)r1.y * r1.y;
+        }
+      }
+    }
+    const int nred = OP == GCR_DOTS ? k : (OP == GCR_UPDATE ? 2 : 1);
+#pragma unroll
+    for (int j = 0; j < kGcrMax; ++j) {
+      if (j >= nred) break;
+      const double2 v = wsum(red[j]);
+      if (lane == 0) d.partial[((size_t)j * d.nrhs + col) * d.ntiles + tile] = v;
+    }
+  }
+}
+
+// One workgroup per slot, one wavefront per column (fixed-order sums).
+template <typename T2, int OP>
+__global__ void __launch_bounds__(768) k_gcr_fin(const SlotDesc<T2>* __restrict__ slots, const int* __restrict__ nslots_p,
+                                                 int k) {
+  const int s = blockIdx.x;
+  if (s >= *nslots_p) return;
+  const SlotDesc<T2>& d = slots[s];
+  const int lane = threadIdx.x & 63;
+  const int col = threadIdx.x >> 6;
+  if (col >= d.nrhs) return;
+  BiState& st = d.st[col];
+  if (OP != GFIN_INIT && !d.active[col]) return;
+  const int nred = OP == GFIN_BETA ? k : (OP == GFIN_ALPHA ? 2 : 1);
+  double2 sum[kGcrMax];
+#pragma unroll
+  for (int j = 0; j < kGcrMax; ++j) {
+    sum[j] = make_double2(0, 0);
+    if (j >= nred) continue;
+    const double2* p = d.partial + ((size_t)j * d.nrhs + col) * d.ntiles;
+    for (int t = lane; t < d.ntiles; t += 64) {
+      sum[j].x += p[t].x;
+      sum[j].y += p[t].y;
+    }
+    sum[j] = wsum(sum[j]);
+  }
+  if (lane != 0) return;
+  double2* gc = d.gcoef + (size_t)col * 2 * kGcrMax;
+  if (OP == GFIN_INIT) {  // st.active holds the request flag
+    const int want = d.active[col];
+    st.rr = sum[0].x;
+    st.rr0 = sum[0].x;
+    st.iters = 0;
+    st.status = 0;
+    const int on = want && sum[0].x > 0 && isfinite(sum[0].x);
+    if (want && !isfinite(sum[0].x)) st.status = 3;
+    d.active[col] = on;
+    st.active = on;
+  } else if (OP == GFIN_BETA) {
+    for (int j = 0; j < k; ++j) {
+      const double qq = gc[kGcrMax + j].x;
+      gc[j] = qq > 0 ? make_double2(sum[j].x / qq, sum[j].y / qq) : make_double2(0, 0);
+    }
+  } else if (OP == GFIN_ALPHA) {  // sum[0] = (q_k, r), sum[1] = |q_k|^2
+    const double qq = sum[1].x;
+    gc[kGcrMax + k] = make_double2(qq, 0);
+    if (!(qq > 0) || !isfinite(qq) || !finite2(sum[0])) {
+      st.status = isfinite(qq) ? 1 : 3;
+      st.active = 0;
+      d.active[col] = 0;
+      st.alpha = make_double2(0, 0);
+      return;
+    }
+    st.alpha = make_double2(sum[0].x / qq, sum[0].y / qq);
+  } else {  // GFIN_CHECK: sum[0] = |r|^2
+    st.iters += 1;
+    st.rr = sum[0].x;
+    int on = 1;
+    if (!isfinite(sum[0].x)) { st.status = 3; on = 0; }
+    else if (sum[0].x <= st.tol2 * st.rr0) { st.status = 0; on = 0; }
+    else if (st.iters >= st.max_iters) { st.status = 2; on = 0; }
+    st.active = on;
+    d.active[col] = on;
+  }
+}
+
+template <typename T2>
+static hipError_t gcr_impl(const SlotDesc<T2>* slots, const int* tile_start, const int* nslots_p, int nrhs, int op,
+                           int k, int m, int grid, hipStream_t st) {
+  if (k < 0 || k >= m || m < 1 || m > kGcrMax) return hipErrorInvalidValue;
+  dim3 b(64 * nrhs);
+  switch (op) {
+    case GCR_INIT: hipLaunchKernelGGL((k_gcr<T2, GCR_INIT>), dim3(grid), b, 0, st, slots, tile_start, nslots_p, k, m); break;
+    case GCR_DOTS: hipLaunchKernelGGL((k_gcr<T2, GCR_DOTS>), dim3(grid), b, 0, st, slots, tile_start, nslots_p, k, m); break;
+    case GCR_UPDATE: hipLaunchKernelGGL((k_gcr<T2, GCR_UPDATE>), dim3(grid), b, 0, st, slots, tile_start, nslots_p, k, m); break;
+    case GCR_XR: hipLaunchKernelGGL((k_gcr<T2, GCR_XR>), dim3(grid), b, 0, st, slots, tile_start, nslots_p, k, m); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+template <typename T2>
+static hipError_t gcr_fin_impl(const SlotDesc<T2>* slots, const int* nslots_p, int max_slots, int op, int k,
+                               hipStream_t st) {
+  if (k < 0 || k >= kGcrMax) return hipErrorInvalidValue;
+  dim3 b(64 * kMaxRhs);
+  switch (op) {
+    case GFIN_INIT: hipLaunchKernelGGL((k_gcr_fin<T2, GFIN_INIT>), dim3(max_slots), b, 0, st, slots, nslots_p, k); break;
+    case GFIN_BETA: hipLaunchKernelGGL((k_gcr_fin<T2, GFIN_BETA>), dim3(max_slots), b, 0, st, slots, nslots_p, k); break;
+    case GFIN_ALPHA: hipLaunchKernelGGL((k_gcr_fin<T2, GFIN_ALPHA>), dim3(max_slots), b, 0, st, slots, nslots_p, k); break;
+    case GFIN_CHECK: hipLaunchKernelGGL((k_gcr_fin<T2, GFIN_CHECK>), dim3(max_slots), b, 0, st, slots, nslots_p, k); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+hipError_t launch_gcr(const SlotDesc<float2>* slots, const int* tile_start, const int* nslots_p, int nrhs, int op,
+                      int k, int m, int grid, hipStream_t st) {
+  return gcr_impl(slots, tile_start, nslots_p, nrhs, op, k, m, grid, st);
+}
+hipError_t launch_gcr(const SlotDesc<double2>* slots, const int* tile_start, const int* nslots_p, int nrhs, int op,
+                      int k, int m, int grid, hipStream_t st) {
+  return gcr_impl(slots, tile_start, nslots_p, nrhs, op, k, m, grid, st);
+}
+hipError_t launch_gcr_fin(const SlotDesc<float2>* slots, const int* nslots_p, int max_slots, int op, int k,
+                          hipStream_t st) {
+  return gcr_fin_impl(slots, nslots_p, max_slots, op, k, st);
+}
+hipError_t launch_gcr_fin(const SlotDesc<double2>* slots, const int* nslots_p, int max_slots, int op, int k,
+                          hipStream_t st) {
+  return gcr_fin_impl(slots, nslots_p, max_slots, op, k, st);
+}
+
 template <typename T2>
 static hipError_t vec_impl(const SlotDesc<T2>* slots, const int* tile_start, const int* nslots_p, int nrhs, int op,
                            int grid, hipStream_t st) {

@@ -282,6 +282,10 @@ enum { RED_NONE = 0, RED_DOT = 1, RED_TS = 2, RED_NORM = 3 };
 
 // Krylov vector slots of one inner solve (even parity unless noted)
 enum { F_R = 0, F_RH = 1, F_P = 2, F_V = 3, F_S = 4, F_T = 5, F_X = 6, F_TMP = 7 /* odd */, F_NUM = 8 };
+// GCR(m) (solver 2) keeps m search directions p_j and their images q_j = M p_j
+// in the field slots after the BiCGstab ones (F_R, F_X and F_TMP are shared).
+constexpr int kGcrMax = 8;
+constexpr int F_GP0 = F_NUM, F_GQ0 = F_NUM + kGcrMax, F_ALL = F_NUM + 2 * kGcrMax;
 
 // Per right-hand-side BiCGstab scalars (device resident).
 struct BiState {
@@ -304,16 +308,17 @@ template <typename T2> struct SlotDesc {
   double kappa;
   const T2* U;          // links in the inner precision
   const T2* Ainv;       // A^{-1} in the inner precision
-  T2* f[F_NUM];         // Krylov vectors [nrhs][ntiles][12][64]
-  double2* partial;     // [2][nrhs][ntiles]
+  T2* f[F_ALL];         // Krylov vectors [nrhs][ntiles][12][64] (GCR slots null for BiCGstab)
+  double2* partial;     // [2][nrhs][ntiles] (GCR: [max(2, m)][nrhs][ntiles])
   int* active;          // [nrhs]
   BiState* st;          // [nrhs]
   const double2* src64; // FP64 even-parity right-hand side [nrhs][ntiles][12][64]
+  double2* gcoef;       // GCR: [nrhs][2 * kGcrMax]: beta_j, then |q_j|^2 (x)
   const int* walk;      // tile walk of the sub-banded orders, as in HopItem
   int xoff[kXcd + 1];
   // 16-bit storage only (T2 = h16c): scales of f[k] ([nrhs][ntiles * 64]),
   // of the clover data ([2][ntiles * 64]), and the FP32 solution vector
-  float* nrm[F_NUM];
+  float* nrm[F_ALL];
   const float* Ainv_nrm;
   float2* x32;
 };

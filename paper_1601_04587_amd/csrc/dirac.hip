@@ -584,16 +584,17 @@ hipError_t launch_hop_item(const HopItem<float2>& it, int mode, int red, int R, 
                        tile_start, xstart, xstride, nslots_p, fin, faux, fout, fred, par_out, order, ng); \
     return hipGetLastError();                                                                            \
   }
-#define DDML_HOPB_DISPATCH_ST(T2, STv)                           \
-  DDML_HOPB_DISPATCH1(T2, 1, MODE_CINV_HOP, RED_NONE, STv)       \
-  DDML_HOPB_DISPATCH1(T2, 1, MODE_SCHUR, RED_DOT, STv)           \
-  DDML_HOPB_DISPATCH1(T2, 1, MODE_SCHUR, RED_TS, STv)            \
-  DDML_HOPB_DISPATCH1(T2, 2, MODE_CINV_HOP, RED_NONE, STv)       \
-  DDML_HOPB_DISPATCH1(T2, 2, MODE_SCHUR, RED_DOT, STv)           \
-  DDML_HOPB_DISPATCH1(T2, 2, MODE_SCHUR, RED_TS, STv)            \
-  DDML_HOPB_DISPATCH1(T2, 3, MODE_CINV_HOP, RED_NONE, STv)       \
-  DDML_HOPB_DISPATCH1(T2, 3, MODE_SCHUR, RED_DOT, STv)           \
-  DDML_HOPB_DISPATCH1(T2, 3, MODE_SCHUR, RED_TS, STv)
+#define DDML_HOPB_DISPATCH_R(T2, Rv, STv)                        \
+  DDML_HOPB_DISPATCH1(T2, Rv, MODE_CINV_HOP, RED_NONE, STv)      \
+  DDML_HOPB_DISPATCH1(T2, Rv, MODE_SCHUR, RED_DOT, STv)          \
+  DDML_HOPB_DISPATCH1(T2, Rv, MODE_SCHUR, RED_TS, STv)           \
+  if constexpr (!kIs16<T2>) {                                    \
+    DDML_HOPB_DISPATCH1(T2, Rv, MODE_SCHUR, RED_NONE, STv)       \
+  }
+#define DDML_HOPB_DISPATCH_ST(T2, STv) \
+  DDML_HOPB_DISPATCH_R(T2, 1, STv)     \
+  DDML_HOPB_DISPATCH_R(T2, 2, STv)     \
+  DDML_HOPB_DISPATCH_R(T2, 3, STv)
 
 template <typename T2>
 static hipError_t hop_batch_impl(const SlotDesc<T2>* slots, const int* tile_start, const int* xstart, int xstride,

@@ -367,17 +367,25 @@ static size_t inner_field_bytes(int prec, size_t n, int nrhs, size_t ntiles) {
   return n * (prec == DDML_FP64 ? sizeof(double2) : sizeof(float2));
 }
 
-size_t solve_footprint(Ctx* c, int dom_id, int nrhs, int prec) {
+int gcr_len(const ddml_solver_params& prm) {
+  if (prm.solver != 2) return 0;
+  return prm.gcr_m > 0 ? prm.gcr_m : kGcrMax;
+}
+
+size_t solve_footprint(Ctx* c, int dom_id, int nrhs, const ddml_solver_params& prm) {
+  const int prec = prm.prec, m = gcr_len(prm);
   const DomainRec& d = domain_get(c, dom_id);
   size_t Vb = 1;
-  for (int m = 0; m < 4; ++m) Vb *= (size_t)(d.hi[m] - d.lo[m]);
+  for (int k = 0; k < 4; ++k) Vb *= (size_t)(d.hi[k] - d.lo[k]);
   const size_t Vh = Vb / 2;
   const size_t ntiles = (Vh + kTile - 1) / kTile;
   const size_t n = (size_t)nrhs * 12 * ntiles * kTile;
   const size_t fx = prec == DDML_MIXED_FP16 ? n * sizeof(float2) : inner_field_bytes(prec, n, nrhs, ntiles);
-  return 8 * DevPool::round(n * sizeof(double2)) + (F_NUM - 1) * DevPool::round(inner_field_bytes(prec, n, nrhs, ntiles)) +
-         DevPool::round(fx) +
-         2 * DevPool::round(2 * nrhs * ntiles * sizeof(double2)) + 6 * DevPool::round(64);
+  const size_t nfield = m > 0 ? 2 + 2 * (size_t)m : F_NUM - 1;  // besides F_X
+  const size_t npart = m > 0 ? std::max(2, m) : 2;
+  return 8 * DevPool::round(n * sizeof(double2)) + nfield * DevPool::round(inner_field_bytes(prec, n, nrhs, ntiles)) +
+         DevPool::round(fx) + DevPool::round(npart * nrhs * ntiles * sizeof(double2)) +
+         DevPool::round(2 * nrhs * ntiles * sizeof(double2)) + 6 * DevPool::round(64);
 }
 
 // ------------------------------------------------------------ operators
@@ -538,9 +546,10 @@ BatchRunner<T2>::~BatchRunner() {
 }
 
 template <typename T2>
-void BatchRunner<T2>::init(Ctx* c, int nrhs_, const TuneChoice& tn, int max_slots_) {
+void BatchRunner<T2>::init(Ctx* c, int nrhs_, const TuneChoice& tn, int max_slots_, int gcr_m_) {
   ctx = c;
   nrhs = nrhs_;
+  gcr_m = gcr_m_;
   R = tn.R;
   K = tn.K;
   grid = ((tn.grid + kXcd - 1) / kXcd) * kXcd;
@@ -554,6 +563,7 @@ void BatchRunner<T2>::init(Ctx* c, int nrhs_, const TuneChoice& tn, int max_slot
   nslots = DBuf(c->pool.get(), sizeof(int));
   st_all = DBuf(c->pool.get(), sizeof(BiState) * max_slots * kMaxRhs);
   act_all = DBuf(c->pool.get(), sizeof(int) * max_slots * kMaxRhs);
+  if (gcr_m > 0) gc_all = DBuf(c->pool.get(), sizeof(double2) * max_slots * kMaxRhs * 2 * kGcrMax);
   SlotDesc<T2> empty{};
   h_table.assign(max_slots, empty);
   h_tstart.assign(max_slots + 1, 0);
@@ -581,7 +591,25 @@ void BatchRunner<T2>::capture() {
   // the stream: keep the first one and fail after the capture is closed
   hipError_t first = hipSuccess;
   auto chk = [&](hipError_t r) { if (first == hipSuccess && r != hipSuccess) first = r; };
-  for (int k = 0; k < K; ++k) {
+  if constexpr (!std::is_same<T2, h16c>::value) {
+    // one GCR(m) cycle: step k applies M to p_k, orthogonalises against the
+    // cycle's earlier directions and updates x, r and the next direction
+    for (int k = 0; k < gcr_m; ++k) {
+      chk(launch_hop_batch(tb, ts, xs, xw, ns, nrhs, R, MODE_CINV_HOP, RED_NONE, F_GP0 + k, -1, F_TMP, -1, 1, grid,
+                           order, splits, stage, s));
+      chk(launch_hop_batch(tb, ts, xs, xw, ns, nrhs, R, MODE_SCHUR, RED_NONE, F_TMP, F_GP0 + k, F_GQ0 + k, -1, 0,
+                           grid, order, splits, stage, s));
+      if (k > 0) {
+        chk(launch_gcr(tb, ts, ns, nrhs, GCR_DOTS, k, gcr_m, grid, s));
+        chk(launch_gcr_fin(tb, ns, max_slots, GFIN_BETA, k, s));
+      }
+      chk(launch_gcr(tb, ts, ns, nrhs, GCR_UPDATE, k, gcr_m, grid, s));
+      chk(launch_gcr_fin(tb, ns, max_slots, GFIN_ALPHA, k, s));
+      chk(launch_gcr(tb, ts, ns, nrhs, GCR_XR, k, gcr_m, grid, s));
+      chk(launch_gcr_fin(tb, ns, max_slots, GFIN_CHECK, k, s));
+    }
+  }
+  for (int k = 0; k < (gcr_m > 0 ? 0 : K); ++k) {
     chk(launch_vec(tb, ts, ns, nrhs, VEC_P, grid, s));
     chk(launch_hop_batch(tb, ts, xs, xw, ns, nrhs, R, MODE_CINV_HOP, RED_NONE, F_P, -1, F_TMP, -1, 1, grid, order,
                          splits, stage, s));
@@ -631,7 +659,7 @@ SlotDesc<float2> make_desc<float2>(const Solve* s, BiState* st, int* act, int or
   d.kappa = s->ob->bs.kappa;
   d.U = s->ob->U32.as<float2>();
   d.Ainv = s->ob->Ainv32.as<float2>();
-  for (int k = 0; k < F_NUM; ++k) d.f[k] = s->f[k].as<float2>();
+  for (int k = 0; k < F_ALL; ++k) d.f[k] = s->f[k].as<float2>();
   d.partial = s->partial.as<double2>();
   d.active = act;
   d.st = st;
@@ -649,7 +677,7 @@ SlotDesc<double2> make_desc<double2>(const Solve* s, BiState* st, int* act, int 
   d.kappa = s->ob->bs.kappa;
   d.U = s->ob->U64.as<double2>();
   d.Ainv = s->ob->Ainv64.as<double2>();
-  for (int k = 0; k < F_NUM; ++k) d.f[k] = s->f[k].as<double2>();
+  for (int k = 0; k < F_ALL; ++k) d.f[k] = s->f[k].as<double2>();
   d.partial = s->partial.as<double2>();
   d.active = act;
   d.st = st;
@@ -694,6 +722,7 @@ int BatchRunner<T2>::join(Solve* s) {
   BiState* st = st_all.as<BiState>() + (size_t)slot * kMaxRhs;
   int* act = act_all.as<int>() + (size_t)slot * kMaxRhs;
   h_table[slot] = make_desc<T2>(s, st, act, order);
+  if (gcr_m > 0) h_table[slot].gcoef = gc_all.template as<double2>() + (size_t)slot * kMaxRhs * 2 * kGcrMax;
   slot_of[slot] = s;
   s->slot = slot;
   dirty = true;
@@ -767,35 +796,39 @@ void check_params(const ddml_solver_params* p) {
   if (!(p->inner_tol > 0) || !(p->inner_tol < 1)) throw Error{DDML_EINVAL, "inner_tol must be in (0,1)"};
   if (p->prec != DDML_FP64 && p->prec != DDML_MIXED_FP32 && p->prec != DDML_MIXED_FP16)
     throw Error{DDML_EINVAL, "unknown precision"};
-  if (p->solver != 0 && p->solver != 1) throw Error{DDML_EINVAL, "solver must be 0 (restarted) or 1 (reliable updates)"};
+  if (p->solver < 0 || p->solver > 2)
+    throw Error{DDML_EINVAL, "solver must be 0 (BiCGstab restarted), 1 (reliable updates) or 2 (GCR(m))"};
+  if (p->solver == 2 && (p->gcr_m < 0 || p->gcr_m > kGcrMax)) throw Error{DDML_EINVAL, "gcr_m must be in 0..8"};
+  if (p->solver == 2 && p->prec == DDML_MIXED_FP16)
+    throw Error{DDML_EINVAL, "GCR(m) runs with FP32 or FP64 inner vectors"};
 }
 
 template <typename T2>
-static BatchRunner<T2>& runner(Ctx* c, int nrhs);
+static BatchRunner<T2>& runner(Ctx* c, int nrhs, int m);  // m: GCR restart length, 0 = BiCGstab
 template <>
-BatchRunner<float2>& runner<float2>(Ctx* c, int nrhs) {
-  auto& r = c->run32[nrhs];
+BatchRunner<float2>& runner<float2>(Ctx* c, int nrhs, int m) {
+  auto& r = c->run32[nrhs + 64 * m];
   if (!r) {
     r.reset(new BatchRunner<float2>());
-    r->init(c, nrhs, c->tune32, 64);
+    r->init(c, nrhs, c->tune32, 64, m);
   }
   return *r;
 }
 template <>
-BatchRunner<double2>& runner<double2>(Ctx* c, int nrhs) {
-  auto& r = c->run64[nrhs];
+BatchRunner<double2>& runner<double2>(Ctx* c, int nrhs, int m) {
+  auto& r = c->run64[nrhs + 64 * m];
   if (!r) {
     r.reset(new BatchRunner<double2>());
-    r->init(c, nrhs, c->tune64, 64);
+    r->init(c, nrhs, c->tune64, 64, m);
   }
   return *r;
 }
 template <>
-BatchRunner<h16c>& runner<h16c>(Ctx* c, int nrhs) {
-  auto& r = c->run16[nrhs];
+BatchRunner<h16c>& runner<h16c>(Ctx* c, int nrhs, int m) {
+  auto& r = c->run16[nrhs + 64 * m];
   if (!r) {
     r.reset(new BatchRunner<h16c>());
-    r->init(c, nrhs, c->tune16, 64);
+    r->init(c, nrhs, c->tune16, 64, m);
   }
   return *r;
 }
@@ -816,11 +849,16 @@ void solve_prepare(Ctx* c, Solve* s) {
   s->to = DBuf(P, n * sizeof(double2));
   s->partial64 = DBuf(P, 2 * s->nrhs * nt * sizeof(double2));
   s->norms = DBuf(P, 3 * s->nrhs * sizeof(double2));
-  for (int k = 0; k < F_NUM; ++k)
-    s->f[k] = DBuf(P, (k == F_X && s->prec == DDML_MIXED_FP16) ? n * sizeof(float2)
-                                                             : inner_field_bytes(s->prec, n, s->nrhs, nt));
+  const int m = gcr_len(s->prm);
+  const size_t fb = inner_field_bytes(s->prec, n, s->nrhs, nt);
+  for (int k = 0; k < F_ALL; ++k) {
+    const bool used = m > 0 ? (k == F_R || k == F_X || k == F_TMP || (k >= F_GP0 && k < F_GP0 + m) ||
+                               (k >= F_GQ0 && k < F_GQ0 + m))
+                            : k < F_NUM;
+    if (used) s->f[k] = DBuf(P, (k == F_X && s->prec == DDML_MIXED_FP16) ? n * sizeof(float2) : fb);
+  }
   if (s->prec == DDML_MIXED_FP16) ensure16(c, *s->ob);
-  s->partial = DBuf(P, 2 * s->nrhs * nt * sizeof(double2));
+  s->partial = DBuf(P, (size_t)std::max(2, m) * s->nrhs * nt * sizeof(double2));
   s->table1 = DBuf(P, std::max({sizeof(SlotDesc<double2>), sizeof(SlotDesc<float2>), sizeof(SlotDesc<h16c>)}));
   s->tstart1 = DBuf(P, 2 * sizeof(int));
   s->n1 = DBuf(P, sizeof(int));
@@ -907,7 +945,8 @@ constexpr double kInnerFloor16 = 1e-3;
 
 template <typename T2>
 static bool try_join(Ctx* c, Solve* s) {
-  BatchRunner<T2>& run = runner<T2>(c, s->nrhs);
+  const int m = gcr_len(s->prm);
+  BatchRunner<T2>& run = runner<T2>(c, s->nrhs, m);
   const int slot = run.join(s);
   if (slot < 0) return false;
   // per-column request flags and limits for this cycle
@@ -938,9 +977,17 @@ static bool try_join(Ctx* c, Solve* s) {
   DDML_HIP(hipMemcpyAsync(s->tstart1.p, ts, sizeof(ts), hipMemcpyHostToDevice, c->stream));
   DDML_HIP(hipMemcpyAsync(s->n1.p, &one, sizeof(int), hipMemcpyHostToDevice, c->stream));
   const int grid = std::min(d.ntiles, 4096);
-  DDML_HIP(launch_vec(s->table1.as<SlotDesc<T2>>(), s->tstart1.as<int>(), s->n1.as<int>(), s->nrhs,
-                      relup ? VEC_RELUP : VEC_INIT, grid, c->stream));
-  DDML_HIP(launch_fin(s->table1.as<SlotDesc<T2>>(), s->n1.as<int>(), 1, relup ? FIN_RELUP : FIN_INIT, c->stream));
+  if (m > 0) {
+    if constexpr (!std::is_same<T2, h16c>::value) {
+      DDML_HIP(launch_gcr(s->table1.as<SlotDesc<T2>>(), s->tstart1.as<int>(), s->n1.as<int>(), s->nrhs, GCR_INIT, 0,
+                          m, grid, c->stream));
+      DDML_HIP(launch_gcr_fin(s->table1.as<SlotDesc<T2>>(), s->n1.as<int>(), 1, GFIN_INIT, 0, c->stream));
+    }
+  } else {
+    DDML_HIP(launch_vec(s->table1.as<SlotDesc<T2>>(), s->tstart1.as<int>(), s->n1.as<int>(), s->nrhs,
+                        relup ? VEC_RELUP : VEC_INIT, grid, c->stream));
+    DDML_HIP(launch_fin(s->table1.as<SlotDesc<T2>>(), s->n1.as<int>(), 1, relup ? FIN_RELUP : FIN_INIT, c->stream));
+  }
   s->state = 2;
   return true;
 }
@@ -1049,7 +1096,7 @@ void solve_finish(Ctx* c, Solve* s) {
   s->be.reset(); s->bo.reset(); s->xe.reset(); s->xo.reset();
   s->re.reset(); s->ro.reset(); s->te.reset(); s->to.reset();
   s->partial64.reset(); s->norms.reset(); s->partial.reset();
-  for (int k = 0; k < F_NUM; ++k) s->f[k].reset();
+  for (int k = 0; k < F_ALL; ++k) s->f[k].reset();
   s->table1.reset(); s->tstart1.reset(); s->n1.reset();
   s->ob.reset();
   s->state = 3;
@@ -1221,7 +1268,7 @@ void run_solves(Ctx* c, std::vector<Solve*>& solves) {
   while (!queue.empty() || !live.empty()) {
     while (!queue.empty()) {
       Solve* s = queue.front();
-      const size_t fp = solve_footprint(c, s->dom_id, s->nrhs, s->prec);
+      const size_t fp = solve_footprint(c, s->dom_id, s->nrhs, s->prm);
       if (!live.empty() && !c->pool->fits(fp)) break;
       queue.pop_front();
       solve_prepare(c, s);

@@ -114,8 +114,9 @@ struct Solve {
   DBuf be, bo, xe, xo, re, ro, te, to;
   DBuf partial64;   // [2][nrhs][ntiles]
   DBuf norms;       // double2 [4][nrhs]: |b|^2, |r|^2
-  // inner state in the inner precision (16-bit: values then scales; F_X in FP32)
-  DBuf f[F_NUM];
+  // inner state in the inner precision (16-bit: values then scales; F_X in FP32);
+  // BiCGstab uses slots [0, F_NUM), GCR(m) F_R, F_X, F_TMP and the 2m GCR slots
+  DBuf f[F_ALL];
   DBuf partial;     // [2][nrhs][ntiles]
   DBuf table1, tstart1, n1;  // one-entry slot table
   int slot = -1;    // position in the batch table
@@ -143,13 +144,15 @@ struct TuneChoice {
   int stage = 0;
 };
 
-// Batched inner solver for one precision and nrhs: a slot table in device
-// memory and a captured graph of K BiCGstab iterations over it.
+// Batched inner solver for one precision, nrhs and Krylov method: a slot table
+// in device memory and a captured graph of K BiCGstab iterations (or of one
+// GCR(m) cycle) over it.
 template <typename T2>
 struct BatchRunner {
   Ctx* ctx = nullptr;
   int nrhs = 0, R = 3, K = 8, grid = 1024, max_slots = 64, splits = 1, stage = 0;
-  DBuf table, tstart, xstart, nslots, st_all, act_all;
+  int gcr_m = 0;                  // 0: BiCGstab; m > 0: GCR(m)
+  DBuf table, tstart, xstart, nslots, st_all, act_all, gc_all;
   int order = TILE_ORDER_BANDED;
   std::vector<SlotDesc<T2>> h_table;
   std::vector<int> h_tstart, h_xstart;
@@ -159,7 +162,7 @@ struct BatchRunner {
   bool dirty = true;
   int nused = 0;                  // highest used slot + 1
   ~BatchRunner();
-  void init(Ctx* c, int nrhs_, const TuneChoice& tn, int max_slots_);
+  void init(Ctx* c, int nrhs_, const TuneChoice& tn, int max_slots_, int gcr_m_);
   void capture();
   int join(Solve* s);             // returns slot or -1 if full
   void leave(Solve* s);
@@ -206,7 +209,9 @@ void gauge_release(Ctx* c, int id);
 int domain_new(Ctx* c, const int lo[4], const int hi[4]);
 const DomainRec& domain_get(Ctx* c, int dom_id);  // dom_id -1 = full lattice
 std::shared_ptr<OpBlock> opblock(Ctx* c, int gauge_id, int dom_id);
-size_t solve_footprint(Ctx* c, int dom_id, int nrhs, int prec);
+size_t solve_footprint(Ctx* c, int dom_id, int nrhs, const ddml_solver_params& prm);
+// GCR restart length of a parameter set (0 for BiCGstab)
+int gcr_len(const ddml_solver_params& prm);
 void apply_D(Ctx* c, int gauge_id, int dom_id, const double* in, double* out, int nrhs, hipStream_t st);
 void apply_eo(Ctx* c, int gauge_id, int dom_id, const double* in, double* out, int nrhs, int prec, hipStream_t st);
 // Runs every solve to completion (continuous batching inside).  Device pointers.

@@ -40,6 +40,17 @@ hipError_t launch_fin(const SlotDesc<float2>* slots, const int* nslots_p, int ma
 hipError_t launch_fin(const SlotDesc<double2>* slots, const int* nslots_p, int max_slots, int op, hipStream_t st);
 hipError_t launch_vec(const SlotDesc<h16c>* slots, const int* tile_start, const int* nslots_p, int nrhs, int op,
                       int grid, hipStream_t st);
+// GCR(m) steps (k = step inside the cycle)
+enum { GCR_INIT = 0, GCR_DOTS = 1, GCR_UPDATE = 2, GCR_XR = 3 };
+enum { GFIN_INIT = 0, GFIN_BETA = 1, GFIN_ALPHA = 2, GFIN_CHECK = 3 };
+hipError_t launch_gcr(const SlotDesc<float2>* slots, const int* tile_start, const int* nslots_p, int nrhs, int op,
+                      int k, int m, int grid, hipStream_t st);
+hipError_t launch_gcr(const SlotDesc<double2>* slots, const int* tile_start, const int* nslots_p, int nrhs, int op,
+                      int k, int m, int grid, hipStream_t st);
+hipError_t launch_gcr_fin(const SlotDesc<float2>* slots, const int* nslots_p, int max_slots, int op, int k,
+                          hipStream_t st);
+hipError_t launch_gcr_fin(const SlotDesc<double2>* slots, const int* nslots_p, int max_slots, int op, int k,
+                          hipStream_t st);
 hipError_t launch_fin(const SlotDesc<h16c>* slots, const int* nslots_p, int max_slots, int op, hipStream_t st);
 
 // elementwise helpers on raw FP64 / mixed arrays (n complex numbers)

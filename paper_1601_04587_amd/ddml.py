@@ -122,9 +122,10 @@ class DDMLError(RuntimeError):
         self.code = code
 
 
-def solver_params(tol=1e-10, max_outer=12, max_inner=4000, inner_tol=1e-5, prec=MIXED_FP32, solver=0):
-    """solver 0: BiCGstab restarted at each FP64 correction; 1: reliable updates."""
-    return SolverParams(tol, max_outer, max_inner, inner_tol, prec, solver, 0)
+def solver_params(tol=1e-10, max_outer=12, max_inner=4000, inner_tol=1e-5, prec=MIXED_FP32, solver=0, gcr_m=0):
+    """solver 0: BiCGstab restarted at each FP64 correction; 1: BiCGstab with
+    reliable updates; 2: GCR(gcr_m) (gcr_m 0 = 8)."""
+    return SolverParams(tol, max_outer, max_inner, inner_tol, prec, solver, gcr_m)
 
 
 def _ptr(a):

@@ -255,3 +255,45 @@ def test_error_paths(cfg0):
     rc, info = ctx.solve_domain(gid, -1, bn, x, 12, ddml.solver_params(tol=1e-10))
     assert info[3].status == ddml.ENUMERIC
     assert all(info[c].status == ddml.OK for c in range(12) if c != 3)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_gcr_solver_matches_oracle(cfg1, prec):
+    """GCR(m) inner solver (solver 2): the FP64-corrected solution meets the
+    oracle's residual, for a restart length that forces several cycles."""
+    L, U, C, ctx, gid, doms, ids = cfg1
+    lo, hi = doms["G1"]
+    b = inputs.point_source(L, (7, 1, 0, 2))
+    x = np.zeros_like(b)
+    rc, info = ctx.solve_domain(gid, ids["G1"], b, x, 12,
+                                ddml.solver_params(tol=1e-10, prec=prec, solver=2, gcr_m=6))
+    assert rc == ddml.OK, [ddml.STATUS_NAMES[i.status] for i in info]
+    assert oracle.residual(U, L, 0.1340, b, x, C=C, lo=lo, hi=hi).max() <= 1e-10 * (1 + 1e-3)
+    assert min(i.inner_iters for i in info) > 6   # more than one cycle
+    m = _mask(L, lo, hi)
+    assert np.abs(x[:, ~m]).max() == 0.0
+
+
+def test_gcr_batch_equals_individual_bitwise(cfg1):
+    L, U, C, ctx, gid, doms, ids = cfg1
+    V = int(np.prod(L))
+    b = inputs.point_source(L, (7, 1, 2, 3))
+    prm = ddml.solver_params(tol=1e-10, solver=2, gcr_m=8)
+    items = [(gid, ids[k], b, np.zeros((12, V, 4, 3), dtype=np.complex128), 12) for k in ("G0", "G1")]
+    rc, _ = ctx.solve_batch(items, prm)
+    assert rc == ddml.OK
+    for (g, d, src, xb, n) in items:
+        x1 = np.zeros_like(xb)
+        ctx.solve_domain(g, d, src, x1, 12, prm)
+        assert np.array_equal(x1, xb)
+
+
+def test_solver_parameter_errors(cfg1):
+    L, U, C, ctx, gid, doms, ids = cfg1
+    b = inputs.point_source(L, (7, 0, 0, 0))
+    x = np.zeros_like(b)
+    for bad in (ddml.solver_params(solver=3), ddml.solver_params(solver=2, gcr_m=9),
+                ddml.solver_params(solver=2, prec=ddml.MIXED_FP16)):
+        with pytest.raises(ddml.DDMLError) as e:
+            ctx.solve_domain(gid, ids["G0"], b, x, 12, bad)
+        assert e.value.code == ddml.EINVAL
