@@ -116,6 +116,14 @@ const char* ddml_last_error(ddml_ctx ctx);
  * with the operator parameters kappa and c_sw used with it.  Returns a new
  * gauge id.  Errors: EINVAL, ENOMEM. */
 int ddml_set_gauge(ddml_ctx ctx, const double* U, int on_device, double kappa, double csw, int* gauge_id);
+/* The same for a field on its own host lattice `lat` (extents even, any size):
+ * one context can then serve domains of fields of several sizes.  Sources and
+ * solutions of solves with this gauge id are [nrhs][V_lat][4][3]; domain ids
+ * are interpreted on this lattice (dom_id -1 = the whole of it).  The
+ * contraction entry points work on the context's lattice.  Errors: EINVAL,
+ * ENOMEM. */
+int ddml_set_gauge_lattice(ddml_ctx ctx, const ddml_lattice* lat, const double* U, int on_device, double kappa,
+                           double csw, int* gauge_id);
 /* Level-1 update of the two-level integration (Section 3.1): a new gauge id
  * equal to base_gauge_id except on time slices [t0, t1), whose links are
  * U_region[(t - t0)*L1*L2*L3 + ...][mu][3][3].  The base is shared, not
@@ -126,9 +134,10 @@ int ddml_set_gauge_region(ddml_ctx ctx, int base_gauge_id, int t0, int t1, const
 int ddml_release_gauge(ddml_ctx ctx, int gauge_id);
 
 /* Hyper-cubic domain Gamma = [lo, hi) (Section 2), half-open per direction,
- * extents even and inside the lattice.  A direction with hi-lo equal to the
- * lattice extent keeps its (anti)periodic wrap; otherwise hops across the
- * faces are dropped (Dirichlet, eq. blkdec).  Errors: EINVAL. */
+ * extents even; it must lie inside the lattice of every gauge field it is
+ * used with (checked at use).  A direction with hi-lo equal to the lattice
+ * extent keeps its (anti)periodic wrap; otherwise hops across the faces are
+ * dropped (Dirichlet, eq. blkdec).  Errors: EINVAL. */
 int ddml_set_domain(ddml_ctx ctx, const int lo[4], const int hi[4], int* dom_id);
 
 /* out = D_Gamma in (dom_id = -1: the full lattice), canonical layout,

@@ -146,6 +146,15 @@ int ddml_set_gauge(ddml_ctx ctx, const double* U, int on_device, double kappa, d
   });
 }
 
+int ddml_set_gauge_lattice(ddml_ctx ctx, const ddml_lattice* lat, const double* U, int on_device, double kappa,
+                           double csw, int* gauge_id) {
+  return guarded(ctx, [&](Ctx* c) {
+    need(gauge_id != nullptr, "gauge_id is NULL");
+    *gauge_id = gauge_new_lattice(c, lat, U, on_device, kappa, csw);
+    return DDML_OK;
+  });
+}
+
 int ddml_set_gauge_region(ddml_ctx ctx, int base_gauge_id, int t0, int t1, const double* U_region, int on_device,
                           int* new_gauge_id) {
   return guarded(ctx, [&](Ctx* c) {
@@ -176,7 +185,7 @@ int ddml_apply_Dw(ddml_ctx ctx, int gauge_id, int dom_id, const double* in, doub
     need(in && out, "NULL buffer");
     need(nrhs >= 1 && nrhs <= kMaxRhs, "nrhs must be in 1..12");
     need(prec == DDML_FP64, "apply_Dw is FP64");
-    const size_t bytes = (size_t)nrhs * c->V * 12 * sizeof(double2);
+    const size_t bytes = (size_t)nrhs * gauge_get(c, gauge_id).V * 12 * sizeof(double2);
     StreamJoin sj(c, stream);
     Staged si = stage_in(c, in, bytes, on_device);
     Staged so = stage_out(c, out, bytes, on_device);
@@ -193,7 +202,7 @@ int ddml_apply_eo(ddml_ctx ctx, int gauge_id, int dom_id, const double* in, doub
     need(in && out, "NULL buffer");
     need(nrhs >= 1 && nrhs <= kMaxRhs, "nrhs must be in 1..12");
     need(prec == DDML_FP64 || prec == DDML_MIXED_FP32 || prec == DDML_MIXED_FP16, "unknown precision");
-    const size_t bytes = (size_t)nrhs * c->V * 12 * sizeof(double2);
+    const size_t bytes = (size_t)nrhs * gauge_get(c, gauge_id).V * 12 * sizeof(double2);
     StreamJoin sj(c, stream);
     Staged si = stage_in(c, in, bytes, on_device);
     Staged so = stage_out(c, out, bytes, on_device);
@@ -208,21 +217,21 @@ static int solve_many(Ctx* c, int n, const ddml_solve_desc* d, const ddml_solver
                       void* stream) {
   check_params(params);
   need(n >= 1 && d != nullptr, "no solves");
-  const size_t bytes = (size_t)d[0].nrhs * c->V * 12 * sizeof(double2);
+  std::vector<size_t> bytes(n);  // canonical arrays on each solve's host lattice
   for (int i = 0; i < n; ++i) {
     need(d[i].src && d[i].sol && d[i].info, "NULL buffer in solve desc");
     need(d[i].nrhs >= 1 && d[i].nrhs <= kMaxRhs, "nrhs must be in 1..12");
     need(d[i].nrhs == d[0].nrhs, "all solves of a batch must have the same nrhs");
-    need(c->gauges.count(d[i].gauge_id) == 1, "unknown gauge id");
-    (void)domain_get(c, d[i].dom_id);
+    bytes[i] = (size_t)d[i].nrhs * gauge_get(c, d[i].gauge_id).V * 12 * sizeof(double2);
+    if (d[i].dom_id != -1) (void)domain_get(c, d[i].dom_id);
   }
   StreamJoin sj(c, stream);
   std::vector<Staged> sin, sout;
   std::vector<Solve> solves(n);
   std::vector<Solve*> ptrs;
   for (int i = 0; i < n; ++i) {
-    sin.push_back(stage_in(c, d[i].src, bytes, on_device));
-    sout.push_back(stage_out(c, d[i].sol, bytes, on_device));
+    sin.push_back(stage_in(c, d[i].src, bytes[i], on_device));
+    sout.push_back(stage_out(c, d[i].sol, bytes[i], on_device));
   }
   for (int i = 0; i < n; ++i) {
     Solve& s = solves[i];
@@ -237,7 +246,7 @@ static int solve_many(Ctx* c, int n, const ddml_solve_desc* d, const ddml_solver
     ptrs.push_back(&s);
   }
   run_solves(c, ptrs);
-  for (int i = 0; i < n; ++i) copy_back(c, d[i].sol, sout[i], bytes, on_device);
+  for (int i = 0; i < n; ++i) copy_back(c, d[i].sol, sout[i], bytes[i], on_device);
   sj.done();
   int rc = DDML_OK;
   for (int i = 0; i < n && rc == DDML_OK; ++i)
@@ -268,25 +277,27 @@ static int series_many(Ctx* c, int ns, const ddml_series_desc* sd, int nrhs, con
   need(ns >= 1 && sd != nullptr, "no series");
   need(nrhs >= 1 && nrhs <= kMaxRhs, "nrhs must be in 1..12");
   check_params(params);
-  const size_t per = (size_t)nrhs * c->V * 12;
-  const size_t bytes = per * sizeof(double2);
   StreamJoin sj(c, stream);
   std::vector<Staged> si, st, ss;
+  std::vector<size_t> per(ns);  // complex numbers of one level on the series' host lattice
   std::vector<ddml_solve_desc> d;
   for (int k = 0; k < ns; ++k) {
     need(sd[k].dom_ids && sd[k].nlevels >= 1 && sd[k].src && sd[k].terms && sd[k].info, "bad series desc");
+    per[k] = (size_t)nrhs * gauge_get(c, sd[k].gauge_id).V * 12;
+    const size_t bytes = per[k] * sizeof(double2);
     si.push_back(stage_in(c, sd[k].src, bytes, on_device));
     st.push_back(stage_out(c, sd[k].terms, bytes * sd[k].nlevels, on_device));
     ss.push_back(sd[k].sum ? stage_out(c, sd[k].sum, bytes, on_device) : Staged{});
   }
   for (int k = 0; k < ns; ++k)
     for (int i = 0; i < sd[k].nlevels; ++i)
-      d.push_back(ddml_solve_desc{sd[k].gauge_id, sd[k].dom_ids[i], si[k].cptr, st[k].ptr + 2 * per * i, nrhs,
+      d.push_back(ddml_solve_desc{sd[k].gauge_id, sd[k].dom_ids[i], si[k].cptr, st[k].ptr + 2 * per[k] * i, nrhs,
                                   sd[k].info + (size_t)i * nrhs});
   // the solves read and write device memory already staged
   int rc = solve_many(c, (int)d.size(), d.data(), params, 1, c->stream);
   for (int k = 0; k < ns; ++k) {
-    DDML_HIP(launch_series_diff(reinterpret_cast<double2*>(st[k].ptr), per, sd[k].nlevels,
+    const size_t bytes = per[k] * sizeof(double2);
+    DDML_HIP(launch_series_diff(reinterpret_cast<double2*>(st[k].ptr), per[k], sd[k].nlevels,
                                 sd[k].sum ? reinterpret_cast<double2*>(ss[k].ptr) : nullptr, c->stream));
     copy_back(c, sd[k].terms, st[k], bytes * sd[k].nlevels, on_device);
     if (sd[k].sum) copy_back(c, sd[k].sum, ss[k], bytes, on_device);

@@ -138,11 +138,24 @@ static void copy_in(Ctx* c, void* dst, const double* src, size_t bytes, int on_d
   DDML_HIP(hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
 }
 
-int gauge_new(Ctx* c, const double* U, int on_device, double kappa, double csw) {
+static void check_lattice(const ddml_lattice* lat) {
+  if (!lat) throw Error{DDML_EINVAL, "lattice is NULL"};
+  for (int m = 0; m < 4; ++m)
+    if (lat->dims[m] < 2 || lat->dims[m] % 2) throw Error{DDML_EINVAL, "lattice extents must be even and >= 2"};
+  if (lat->bc_time != DDML_BC_PERIODIC && lat->bc_time != DDML_BC_ANTIPERIODIC)
+    throw Error{DDML_EINVAL, "bc_time must be DDML_BC_PERIODIC or DDML_BC_ANTIPERIODIC"};
+  const size_t V = (size_t)lat->dims[0] * lat->dims[1] * lat->dims[2] * lat->dims[3];
+  if (V > (size_t)1 << 30) throw Error{DDML_EINVAL, "lattice too large"};
+}
+
+int gauge_new_lattice(Ctx* c, const ddml_lattice* lat, const double* U, int on_device, double kappa, double csw) {
+  check_lattice(lat);
   if (!U) throw Error{DDML_EINVAL, "gauge field pointer is NULL"};
   if (!(kappa > 0) || !std::isfinite(kappa) || !std::isfinite(csw)) throw Error{DDML_EINVAL, "bad kappa or c_sw"};
   GaugeRec g;
-  const size_t bytes = c->V * 36 * sizeof(double2);
+  g.lat = *lat;
+  g.V = (size_t)lat->dims[0] * lat->dims[1] * lat->dims[2] * lat->dims[3];
+  const size_t bytes = g.V * 36 * sizeof(double2);
   g.base = std::make_shared<DBuf>(c->pool.get(), bytes);
   copy_in(c, g.base->p, U, bytes, on_device);
   DDML_HIP(hipStreamSynchronize(c->stream));
@@ -153,20 +166,34 @@ int gauge_new(Ctx* c, const double* U, int on_device, double kappa, double csw) 
   return id;
 }
 
+int gauge_new(Ctx* c, const double* U, int on_device, double kappa, double csw) {
+  return gauge_new_lattice(c, &c->lat, U, on_device, kappa, csw);
+}
+
+const GaugeRec& gauge_get(Ctx* c, int gauge_id) {
+  auto it = c->gauges.find(gauge_id);
+  if (it == c->gauges.end()) throw Error{DDML_EINVAL, "unknown gauge id"};
+  return it->second;
+}
+
 int gauge_region(Ctx* c, int base, int t0, int t1, const double* U, int on_device) {
   auto it = c->gauges.find(base);
   if (it == c->gauges.end()) throw Error{DDML_EINVAL, "unknown base gauge id"};
   if (!U) throw Error{DDML_EINVAL, "region pointer is NULL"};
-  if (t0 < 0 || t1 > c->lat.dims[0] || t0 >= t1) throw Error{DDML_EINVAL, "bad time range"};
-  const size_t V3 = c->V / c->lat.dims[0];
+  const ddml_lattice& lat = it->second.lat;
+  const size_t V = it->second.V;
+  if (t0 < 0 || t1 > lat.dims[0] || t0 >= t1) throw Error{DDML_EINVAL, "bad time range"};
+  const size_t V3 = V / lat.dims[0];
   GaugeRec g;
   g.kappa = it->second.kappa;
   g.csw = it->second.csw;
+  g.lat = lat;
+  g.V = V;
   if (it->second.region) {
     // a version of a version: materialise the parent first
     const GaugeRec& p = it->second;
-    g.base = std::make_shared<DBuf>(c->pool.get(), c->V * 36 * sizeof(double2));
-    DDML_HIP(hipMemcpyAsync(g.base->p, p.base->p, c->V * 36 * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
+    g.base = std::make_shared<DBuf>(c->pool.get(), V * 36 * sizeof(double2));
+    DDML_HIP(hipMemcpyAsync(g.base->p, p.base->p, V * 36 * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
     DDML_HIP(hipMemcpyAsync(g.base->as<double2>() + (size_t)p.r_t0 * V3 * 36, p.region->p,
                             (size_t)(p.r_t1 - p.r_t0) * V3 * 36 * sizeof(double2), hipMemcpyDeviceToDevice,
                             c->stream));
@@ -196,8 +223,8 @@ int domain_new(Ctx* c, const int lo[4], const int hi[4]) {
   if (!lo || !hi) throw Error{DDML_EINVAL, "lo/hi is NULL"};
   DomainRec d;
   for (int m = 0; m < 4; ++m) {
-    if (lo[m] < 0 || hi[m] > c->lat.dims[m] || lo[m] >= hi[m])
-      throw Error{DDML_EINVAL, "domain outside the lattice or empty"};
+    // checked against the host lattice of each gauge field it is used with
+    if (lo[m] < 0 || lo[m] >= hi[m]) throw Error{DDML_EINVAL, "domain outside the lattice or empty"};
     if ((hi[m] - lo[m]) % 2) throw Error{DDML_EINVAL, "domain extents must be even"};
     d.lo[m] = lo[m];
     d.hi[m] = hi[m];
@@ -214,14 +241,31 @@ const DomainRec& domain_get(Ctx* c, int dom_id) {
   return it->second;
 }
 
+// The domain on the gauge field's host lattice (dom_id -1: that whole lattice).
+static DomainRec domain_on(Ctx* c, const GaugeRec& g, int dom_id) {
+  DomainRec d;
+  if (dom_id == -1) {
+    for (int m = 0; m < 4; ++m) {
+      d.lo[m] = 0;
+      d.hi[m] = g.lat.dims[m];
+    }
+    return d;
+  }
+  d = domain_get(c, dom_id);
+  for (int m = 0; m < 4; ++m)
+    if (d.hi[m] > g.lat.dims[m]) throw Error{DDML_EINVAL, "domain outside the gauge field's lattice"};
+  return d;
+}
+
 static void fill_spec(Ctx* c, const GaugeRec& g, const DomainRec& d, BlockSpec& bs, BoxGeom& geo) {
+  (void)c;
   for (int m = 0; m < 4; ++m) {
-    bs.L[m] = c->lat.dims[m];
+    bs.L[m] = g.lat.dims[m];
     bs.lo[m] = d.lo[m];
     bs.Lb[m] = d.hi[m] - d.lo[m];
     geo.L[m] = bs.Lb[m];
   }
-  bs.antiperiodic = c->lat.bc_time == DDML_BC_ANTIPERIODIC;
+  bs.antiperiodic = g.lat.bc_time == DDML_BC_ANTIPERIODIC;
   bs.kappa = g.kappa;
   bs.csw = g.csw;
   geo.Vh = bs.Lb[0] * bs.Lb[1] * bs.Lb[2] * bs.Lb[3] / 2;
@@ -307,7 +351,7 @@ std::shared_ptr<OpBlock> opblock(Ctx* c, int gauge_id, int dom_id) {
   if (it != c->blocks.end()) return it->second;
   auto git = c->gauges.find(gauge_id);
   if (git == c->gauges.end()) throw Error{DDML_EINVAL, "unknown gauge id"};
-  const DomainRec& d = domain_get(c, dom_id);
+  const DomainRec d = domain_on(c, git->second, dom_id);
   auto ob = std::make_shared<OpBlock>();
   fill_spec(c, git->second, d, ob->bs, ob->g);
   ob->ntiles = ob->g.ntiles;
@@ -372,9 +416,9 @@ int gcr_len(const ddml_solver_params& prm) {
   return prm.gcr_m > 0 ? prm.gcr_m : kGcrMax;
 }
 
-size_t solve_footprint(Ctx* c, int dom_id, int nrhs, const ddml_solver_params& prm) {
+size_t solve_footprint(Ctx* c, int gauge_id, int dom_id, int nrhs, const ddml_solver_params& prm) {
   const int prec = prm.prec, m = gcr_len(prm);
-  const DomainRec& d = domain_get(c, dom_id);
+  const DomainRec d = domain_on(c, gauge_get(c, gauge_id), dom_id);
   size_t Vb = 1;
   for (int k = 0; k < 4; ++k) Vb *= (size_t)(d.hi[k] - d.lo[k]);
   const size_t Vh = Vb / 2;
@@ -423,7 +467,7 @@ void apply_D(Ctx* c, int gauge_id, int dom_id, const double* in, double* out, in
     it.c2 = 1.0 / (2.0 * kappa);
     DDML_HIP(launch_hop_item(it, MODE_M, RED_NONE, 1, c->tune64.order, st));
   }
-  DDML_HIP(hipMemsetAsync(out, 0, (size_t)nrhs * c->V * 12 * sizeof(double2), st));
+  DDML_HIP(hipMemsetAsync(out, 0, (size_t)nrhs * gauge_get(c, gauge_id).V * 12 * sizeof(double2), st));
   DDML_HIP(launch_scatter(oe.as<double2>(), ob->bs, 0, nrhs, 1.0, cout, st));
   DDML_HIP(launch_scatter(oo.as<double2>(), ob->bs, 1, nrhs, 1.0, cout, st));
   DDML_HIP(hipStreamSynchronize(st));  // temporaries go back to the pool
@@ -518,12 +562,12 @@ void apply_eo(Ctx* c, int gauge_id, int dom_id, const double* in, double* out, i
     DBuf tmp(c->pool.get(), n * sizeof(double2));
     schur_apply<double2>(c, *ob, ob->U64.as<double2>(), ob->Ainv64.as<double2>(), xe.as<double2>(),
                          tmp.as<double2>(), oe.as<double2>(), nrhs, st);
-    DDML_HIP(hipMemsetAsync(out, 0, (size_t)nrhs * c->V * 12 * sizeof(double2), st));
+    DDML_HIP(hipMemsetAsync(out, 0, (size_t)nrhs * gauge_get(c, gauge_id).V * 12 * sizeof(double2), st));
     DDML_HIP(launch_scatter(oe.as<double2>(), ob->bs, 0, nrhs, 1.0, reinterpret_cast<double2*>(out), st));
     DDML_HIP(hipStreamSynchronize(st));
   } else if (prec == DDML_MIXED_FP16) {
     schur_apply16(c, *ob, xe.as<double2>(), oe.as<double2>(), nrhs, st);
-    DDML_HIP(hipMemsetAsync(out, 0, (size_t)nrhs * c->V * 12 * sizeof(double2), st));
+    DDML_HIP(hipMemsetAsync(out, 0, (size_t)nrhs * gauge_get(c, gauge_id).V * 12 * sizeof(double2), st));
     DDML_HIP(launch_scatter(oe.as<double2>(), ob->bs, 0, nrhs, 1.0, reinterpret_cast<double2*>(out), st));
     DDML_HIP(hipStreamSynchronize(st));
   } else {
@@ -533,7 +577,7 @@ void apply_eo(Ctx* c, int gauge_id, int dom_id, const double* in, double* out, i
     schur_apply<float2>(c, *ob, ob->U32.as<float2>(), ob->Ainv32.as<float2>(), xf.as<float2>(), tf.as<float2>(),
                         of.as<float2>(), nrhs, st);
     DDML_HIP(launch_cast_to_d(of.as<float2>(), oe.as<double2>(), n, st));
-    DDML_HIP(hipMemsetAsync(out, 0, (size_t)nrhs * c->V * 12 * sizeof(double2), st));
+    DDML_HIP(hipMemsetAsync(out, 0, (size_t)nrhs * gauge_get(c, gauge_id).V * 12 * sizeof(double2), st));
     DDML_HIP(launch_scatter(oe.as<double2>(), ob->bs, 0, nrhs, 1.0, reinterpret_cast<double2*>(out), st));
     DDML_HIP(hipStreamSynchronize(st));
   }
@@ -1078,7 +1122,7 @@ void solve_progress(Ctx* c, std::vector<Solve*>& live, bool block) {
 void solve_finish(Ctx* c, Solve* s) {
   hipStream_t st = c->stream;
   double2* sol = reinterpret_cast<double2*>(s->sol);
-  DDML_HIP(hipMemsetAsync(sol, 0, (size_t)s->nrhs * c->V * 12 * sizeof(double2), st));
+  DDML_HIP(hipMemsetAsync(sol, 0, (size_t)s->nrhs * gauge_get(c, s->gauge_id).V * 12 * sizeof(double2), st));
   DDML_HIP(launch_scatter(s->xe.as<double2>(), s->ob->bs, 0, s->nrhs, 1.0, sol, st));
   DDML_HIP(launch_scatter(s->xo.as<double2>(), s->ob->bs, 1, s->nrhs, 1.0, sol, st));
   if (s->info) {
@@ -1268,7 +1312,7 @@ void run_solves(Ctx* c, std::vector<Solve*>& solves) {
   while (!queue.empty() || !live.empty()) {
     while (!queue.empty()) {
       Solve* s = queue.front();
-      const size_t fp = solve_footprint(c, s->dom_id, s->nrhs, s->prm);
+      const size_t fp = solve_footprint(c, s->gauge_id, s->dom_id, s->nrhs, s->prm);
       if (!live.empty() && !c->pool->fits(fp)) break;
       queue.pop_front();
       solve_prepare(c, s);

@@ -83,6 +83,8 @@ struct GaugeRec {
   std::shared_ptr<DBuf> region;   // [V_region][4][9] or null
   int r_t0 = 0, r_t1 = 0;
   double kappa = 0, csw = 0;
+  ddml_lattice lat{};             // the host lattice of this field (the context's by default)
+  size_t V = 0;
 };
 
 struct DomainRec {
@@ -204,12 +206,14 @@ struct Ctx {
 // engine.cpp
 void ctx_init(Ctx* c, const ddml_lattice* lat, int device, size_t budget);
 int gauge_new(Ctx* c, const double* U, int on_device, double kappa, double csw);
+int gauge_new_lattice(Ctx* c, const ddml_lattice* lat, const double* U, int on_device, double kappa, double csw);
+const GaugeRec& gauge_get(Ctx* c, int gauge_id);
 int gauge_region(Ctx* c, int base, int t0, int t1, const double* U, int on_device);
 void gauge_release(Ctx* c, int id);
 int domain_new(Ctx* c, const int lo[4], const int hi[4]);
 const DomainRec& domain_get(Ctx* c, int dom_id);  // dom_id -1 = full lattice
 std::shared_ptr<OpBlock> opblock(Ctx* c, int gauge_id, int dom_id);
-size_t solve_footprint(Ctx* c, int dom_id, int nrhs, const ddml_solver_params& prm);
+size_t solve_footprint(Ctx* c, int gauge_id, int dom_id, int nrhs, const ddml_solver_params& prm);
 // GCR restart length of a parameter set (0 for BiCGstab)
 int gcr_len(const ddml_solver_params& prm);
 void apply_D(Ctx* c, int gauge_id, int dom_id, const double* in, double* out, int nrhs, hipStream_t st);

@@ -134,7 +134,7 @@ void Server::loop() {
         s->info = q->info;
         size_t fp = 0;
         try {
-          fp = solve_footprint(ctx, s->dom_id, s->nrhs, s->prm);
+          fp = solve_footprint(ctx, s->gauge_id, s->dom_id, s->nrhs, s->prm);
         } catch (const Error& e) {
           q->res.status = e.code;
           waiting.pop_front();

@@ -65,7 +65,8 @@ class ServerStats(ctypes.Structure):
                 ("hbm_in_use", ctypes.c_size_t), ("hbm_budget", ctypes.c_size_t)]
 
 
-EXPORTS = ["ddml_create", "ddml_destroy", "ddml_last_error", "ddml_set_gauge", "ddml_set_gauge_region",
+EXPORTS = ["ddml_create", "ddml_destroy", "ddml_last_error", "ddml_set_gauge", "ddml_set_gauge_lattice",
+           "ddml_set_gauge_region",
            "ddml_release_gauge", "ddml_set_domain", "ddml_apply_Dw", "ddml_apply_eo", "ddml_solve_domain",
            "ddml_solve_batch", "ddml_propagator_series", "ddml_propagator_series_batch", "ddml_time_stencil", "ddml_autotune", "ddml_contract_pp_disconnected", "ddml_contract_nucleon",
            "ddml_server_start", "ddml_submit", "ddml_poll", "ddml_wait", "ddml_stats", "ddml_server_stop",
@@ -89,6 +90,7 @@ def load():
     lib.ddml_last_error.argtypes = [P]
     lib.ddml_last_error.restype = ctypes.c_char_p
     lib.ddml_set_gauge.argtypes = [P, P, I, D, D, IP]
+    lib.ddml_set_gauge_lattice.argtypes = [P, ctypes.POINTER(Lattice), P, I, D, D, IP]
     lib.ddml_set_gauge_region.argtypes = [P, I, I, I, P, I, IP]
     lib.ddml_release_gauge.argtypes = [P, I]
     lib.ddml_set_domain.argtypes = [P, IP, IP, IP]
@@ -190,6 +192,14 @@ class Context:
         p, dev = _ptr(U)
         gid = ctypes.c_int()
         self._check(self.lib.ddml_set_gauge(self.h, p, dev, kappa, csw, ctypes.byref(gid)))
+        return gid.value
+
+    def set_gauge_lattice(self, dims, U, kappa, csw, bc_time=BC_ANTIPERIODIC):
+        """A gauge field on its own host lattice `dims` (T, L1, L2, L3)."""
+        p, dev = _ptr(U)
+        gid = ctypes.c_int()
+        lat = Lattice((ctypes.c_int * 4)(*[int(v) for v in dims]), bc_time)
+        self._check(self.lib.ddml_set_gauge_lattice(self.h, ctypes.byref(lat), p, dev, kappa, csw, ctypes.byref(gid)))
         return gid.value
 
     def set_gauge_region(self, base, t0, t1, U_region):

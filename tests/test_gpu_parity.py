@@ -238,10 +238,15 @@ def test_error_paths(cfg0):
         ctx.set_domain((0, 0, 0, 0), (3, 4, 4, 4))       # odd extent
     assert e.value.code == ddml.EINVAL
     with pytest.raises(ddml.DDMLError) as e:
-        ctx.set_domain((0, 0, 0, 0), (6, 4, 4, 4))       # outside
+        ctx.set_domain((2, 0, 0, 0), (2, 4, 4, 4))       # empty
     assert e.value.code == ddml.EINVAL
     b = inputs.point_source(L, (0, 0, 0, 0))
     x = np.zeros_like(b)
+    # a domain is checked against the lattice of the field it is used with
+    outside = ctx.set_domain((0, 0, 0, 0), (6, 4, 4, 4))
+    with pytest.raises(ddml.DDMLError) as e:
+        ctx.solve_domain(gid, outside, b, x, 12)
+    assert e.value.code == ddml.EINVAL
     with pytest.raises(ddml.DDMLError) as e:
         ctx.solve_domain(999, -1, b, x, 12)
     assert e.value.code == ddml.EINVAL
