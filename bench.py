@@ -64,8 +64,8 @@ def parse():
     ap.add_argument("--no-fp16", action="store_true", help="skip the 16-bit storage leg")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=32)
-    ap.add_argument("--serve-rate", type=float, default=0.0, help="req/s (0: 0.7 x measured capacity)")
+    ap.add_argument("--serve-requests", type=int, default=64, help="requests per serving stream")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="configured Poisson rate, req/s")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--stencil-iters", type=int, default=20)
     ap.add_argument("--sweep-iters", type=int, default=2, help="timed pairs per launch variant (--stencil-only)")
@@ -298,7 +298,7 @@ def main():
     # ------------------------------------------------------------ serving
     serve = None
     if not args.no_serve:
-        serve = run_serving(ctx, ddml, torch, dev, gid0, L, doms, srcs, terms, solves_per_s, args)
+        serve = run_serving(ctx, ddml, torch, dev, gid0, L, args)
 
     # ------------------------------------------------------- CPU baseline
     cpu = None
@@ -342,32 +342,76 @@ def main():
     return 0
 
 
-def run_serving(ctx, ddml, torch, dev, gid0, L, doms, srcs, terms, capacity, args):
-    """Poisson stream of domain-solve requests on the slab domains of the base field."""
-    rng = np.random.default_rng(1601005)
-    rate = args.serve_rate if args.serve_rate > 0 else 0.7 * capacity
-    n = args.serve_requests
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n))
-    choice = rng.integers(0, 3, size=n)
-    slab = rng.integers(0, len(doms), size=n)
-    # output buffers are reused round-robin (outputs are not inspected here)
-    sols = [torch.zeros_like(srcs[0]) for _ in range(4)]
-    ctx.server_start(ddml.solver_params(tol=1e-10), max_queue=100000)
-    t0 = ddml.now()
-    tickets = []
-    for k in range(n):
-        while ddml.now() - t0 < arrivals[k]:
-            time.sleep(0.0005)
-        s = int(slab[k])
-        tickets.append(ctx.submit(gid0, doms[s][int(choice[k])], srcs[s], sols[k % 4], 12,
-                                  arrival_time=t0 + arrivals[k]))
-    res = [ctx.wait(tk, 600.0) for tk in tickets]
-    st = ctx.stats()
-    ctx.server_stop()
-    ok = sum(1 for r in res if r is not None and r.status == ddml.OK)
-    out = {"requests": n, "rate_req_per_s": rate, "ok": ok, "p50_latency_s": st.p50_latency,
-           "p99_latency_s": st.p99_latency, "mean_latency_s": st.mean_latency, "solves_per_s": st.solves_per_s,
-           "domains": "Gamma0/1/2 slabs (4/8/16 x 32^3) of the base field, 12 rhs, mixed 1e-10"}
+SERVE_MIX = [((16, 8, 8, 8), (4, 12), 1601051), ((16, 16, 16, 16), (4, 12), 1601052),
+             ((48, 24, 24, 24), (16, 32), 1601053), (None, (24, 40), None)]   # None: the base 32^3x64 field
+
+
+def run_serving(ctx, ddml, torch, dev, gid0, L, args):
+    """Serving workload: Poisson streams of domain-solve requests whose domain is
+    drawn uniformly from the 8^4, 16^3x8, 24^3x16 and 32^3x16 Dirichlet time slabs
+    of 8^3x16, 16^3x16, 24^3x48 and 32^3x64 fields (12 rhs, point source at the
+    slab centre, mixed precision to 1e-10), at the configured rate and at 0.7x
+    the measured capacity."""
+    import inputs
+
+    kinds = []
+    for Lh, (t0, t1), seed in SERVE_MIX:
+        if Lh is None:
+            Lh, gid = L, gid0
+        else:
+            U = inputs.quenched_field(Lh, seed)
+            gid = ctx.set_gauge_lattice(Lh, torch.from_numpy(U).to(dev), 0.1340, 1.769)
+        dom = ctx.set_domain((t0, 0, 0, 0), (t1,) + tuple(Lh[1:]))
+        src = ((t0 + t1) // 2, Lh[1] // 2, Lh[2] // 2, Lh[3] // 2)
+        b = torch.from_numpy(inputs.point_source(Lh, src)).to(dev)
+        sols = [torch.zeros_like(b) for _ in range(4)]   # reused round-robin (outputs not inspected here)
+        kinds.append({"gid": gid, "dom": dom, "src": b, "sols": sols,
+                      "name": "%d^3x%d" % (Lh[1], t1 - t0)})
+    params = ddml.solver_params(tol=1e-10)
+    # capacity: the mix (4 of each) as one batch; FP64 one at a time: one of each
+    items = [(k["gid"], k["dom"], k["src"], k["sols"][j], 12) for j in range(4) for k in kinds]
+    ctx.solve_batch(items[:4], params)   # warm-up
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    rc, _ = ctx.solve_batch(items, params)
+    torch.cuda.synchronize()
+    capacity = len(items) / (time.perf_counter() - a)
+    a = time.perf_counter()
+    for k in kinds:
+        ctx.solve_domain(k["gid"], k["dom"], k["src"], k["sols"][0], 12, ddml.solver_params(tol=1e-10, prec=ddml.FP64))
+    torch.cuda.synchronize()
+    fp64 = len(kinds) / (time.perf_counter() - a)
+
+    def stream(rate, n, seed):
+        rng = np.random.default_rng(seed)
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n))
+        pick = rng.integers(0, len(kinds), size=n)
+        ctx.server_start(params, max_queue=100000)
+        t0 = ddml.now()
+        tickets = []
+        for j in range(n):
+            while ddml.now() - t0 < arrivals[j]:
+                time.sleep(0.0005)
+            k = kinds[int(pick[j])]
+            tickets.append(ctx.submit(k["gid"], k["dom"], k["src"], k["sols"][j % 4], 12,
+                                      arrival_time=t0 + arrivals[j]))
+        res = [ctx.wait(tk, 600.0) for tk in tickets]
+        st = ctx.stats()
+        ctx.server_stop()
+        ok = sum(1 for r in res if r is not None and r.status == ddml.OK)
+        failed = {}
+        for r in res:
+            if r is None or r.status != ddml.OK:
+                name = "timeout" if r is None else ddml.STATUS_NAMES.get(r.status, str(r.status))
+                failed[name] = failed.get(name, 0) + 1
+        return {"requests": n, "rate_req_per_s": rate, "ok": ok, "failed": failed, "p50_latency_s": st.p50_latency,
+                "p99_latency_s": st.p99_latency, "mean_latency_s": st.mean_latency,
+                "solves_per_s": st.solves_per_s}
+
+    out = {"domains": "uniform over %s slabs (12 rhs, mixed 1e-10)" % ", ".join(k["name"] for k in kinds),
+           "capacity_solves_per_s": capacity, "fp64_one_at_a_time_solves_per_s": fp64,
+           "configured": stream(args.serve_rate, args.serve_requests, 1601005),
+           "sub_saturation_0.7x": stream(0.7 * capacity, args.serve_requests, 1601006)}
     log("serving: %s" % out)
     return out
 

@@ -79,6 +79,16 @@ void DevPool::free(void* p) {
 
 bool DevPool::fits(size_t bytes) const { return in_use_ + round(bytes) <= budget_; }
 
+bool DevPool::fits_device(size_t bytes) const {
+  if (!fits(bytes)) return false;
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    (void)hipGetLastError();
+    return true;
+  }
+  return fr + cached_ >= round(bytes) + ((size_t)256 << 20);  // margin for rounding of many buffers
+}
+
 // --------------------------------------------------------------- context
 Ctx::~Ctx() {
   run32.clear();
@@ -1137,13 +1147,17 @@ void solve_finish(Ctx* c, Solve* s) {
   }
   // release device state (the scatter is ordered before any reuse of the
   // memory because every later use is on the same stream)
+  solve_release(s);
+  s->state = 3;
+}
+
+void solve_release(Solve* s) {
   s->be.reset(); s->bo.reset(); s->xe.reset(); s->xo.reset();
   s->re.reset(); s->ro.reset(); s->te.reset(); s->to.reset();
   s->partial64.reset(); s->norms.reset(); s->partial.reset();
   for (int k = 0; k < F_ALL; ++k) s->f[k].reset();
   s->table1.reset(); s->tstart1.reset(); s->n1.reset();
   s->ob.reset();
-  s->state = 3;
 }
 
 template <typename T2>
@@ -1313,9 +1327,15 @@ void run_solves(Ctx* c, std::vector<Solve*>& solves) {
     while (!queue.empty()) {
       Solve* s = queue.front();
       const size_t fp = solve_footprint(c, s->gauge_id, s->dom_id, s->nrhs, s->prm);
-      if (!live.empty() && !c->pool->fits(fp)) break;
+      if (!live.empty() && !c->pool->fits_device(fp)) break;
+      try {
+        solve_prepare(c, s);
+      } catch (const Error& e) {
+        solve_release(s);
+        if (e.code == DDML_ENOMEM && !live.empty()) break;  // retry once solves in flight have finished
+        throw;
+      }
       queue.pop_front();
-      solve_prepare(c, s);
       live.push_back(s);
     }
     solve_progress(c, live, true);

@@ -44,6 +44,9 @@ class DevPool {
   void* alloc(size_t bytes);   // throws Error{ENOMEM}
   void free(void* p);
   bool fits(size_t bytes) const;
+  // fits() and the device's free memory (plus this pool's cache) covers it:
+  // memory taken by other allocators (e.g. the caller's tensors) counts too
+  bool fits_device(size_t bytes) const;
   size_t in_use() const { return in_use_; }
   size_t budget() const { return budget_; }
   size_t cached() const { return cached_; }
@@ -224,6 +227,7 @@ void run_solves(Ctx* c, std::vector<Solve*>& solves);
 void solve_prepare(Ctx* c, Solve* s);                // allocate + set up (state -> 1)
 void solve_progress(Ctx* c, std::vector<Solve*>& live, bool block);  // one scheduling round
 void solve_finish(Ctx* c, Solve* s);                 // scatter, info, free
+void solve_release(Solve* s);                        // free device state (after a failed prepare)
 void check_params(const ddml_solver_params* p);
 // Times the two stencil kernels of the inner solver (k_hop_batch, CINV_HOP and
 // SCHUR with its fused dot product) on one slot; out = {ms_cinv, ms_schur,

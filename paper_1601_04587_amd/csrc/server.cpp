@@ -141,7 +141,7 @@ void Server::loop() {
           finished.push_back(q);
           continue;
         }
-        if (!live.empty() && !ctx->pool->fits(fp)) break;
+        if (!live.empty() && !ctx->pool->fits_device(fp)) break;
         waiting.pop_front();
         try {
           solve_prepare(ctx, s);
@@ -149,6 +149,12 @@ void Server::loop() {
           live.push_back(s);
           owner[s] = q;
         } catch (const Error& e) {
+          solve_release(s);
+          if (e.code == DDML_ENOMEM && !live.empty()) {
+            // memory frees up as the solves in flight finish: wait for them
+            waiting.push_front(q);
+            break;
+          }
           q->res.status = e.code;
           finished.push_back(q);
         }
