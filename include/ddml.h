@@ -257,6 +257,12 @@ int ddml_time_stencil(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec
  * Errors: EINVAL, ENOMEM, EDEVICE. */
 int ddml_autotune(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec, double best[6]);
 
+/* Sets the stencil launch of precision prec by hand (same meaning as the
+ * arguments of ddml_time_stencil; grid >= 8; 16-bit storage needs stage 1).
+ * Every launch choice computes the same bits.
+ * Errors: EINVAL. */
+int ddml_set_launch(ddml_ctx ctx, int prec, int R, int order, int grid, int splits, int stage);
+
 /* ------------------------------------------------------------- serving */
 typedef struct {
   int gauge_id;

@@ -337,6 +337,20 @@ int ddml_time_stencil(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec
   });
 }
 
+int ddml_set_launch(ddml_ctx ctx, int prec, int R, int order, int grid, int splits, int stage) {
+  return guarded(ctx, [&](Ctx* c) {
+    need(prec == DDML_FP64 || prec == DDML_MIXED_FP32 || prec == DDML_MIXED_FP16, "unknown precision");
+    TuneChoice w;
+    w.R = R;
+    w.order = order;
+    w.grid = grid;
+    w.splits = splits;
+    w.stage = stage;
+    set_launch(c, prec, w);
+    return DDML_OK;
+  });
+}
+
 int ddml_autotune(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec, double best[6]) {
   return guarded(ctx, [&](Ctx* c) {
     need(best != nullptr, "best is NULL");

@@ -1284,6 +1284,20 @@ void time_stencil(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, int iter
   }
 }
 
+void set_launch(Ctx* c, int prec, const TuneChoice& want) {
+  const bool h16 = prec == DDML_MIXED_FP16;
+  if (want.R < 1 || want.R > 3 || want.order < 0 || want.order >= TILE_ORDER_NUM || want.grid < kXcd ||
+      want.splits < 1 || want.splits > 12 || want.stage < 0 || want.stage > 1 || (h16 && want.stage != 1))
+    throw Error{DDML_EINVAL, "invalid launch choice"};
+  TuneChoice& t = c->tune(prec);
+  const int K = t.K;
+  t = want;
+  t.K = K;
+  c->run32.clear();  // graphs are captured with the launch choice: rebuild on next use
+  c->run64.clear();
+  c->run16.clear();
+}
+
 void autotune(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, double best[6]) {
   double bt = 1e300;
   TuneChoice b = c->tune(prec);

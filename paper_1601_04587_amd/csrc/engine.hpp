@@ -238,6 +238,8 @@ void time_stencil(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, int iter
 // Picks the fastest stencil launch (R, order, grid, splits, stage) and rebuilds
 // the solver graphs.
 void autotune(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, double best[6]);
+// Makes `want` the launch choice of precision prec (the solver graphs are rebuilt).
+void set_launch(Ctx* c, int prec, const TuneChoice& want);
 ddml_solver_params default_params();
 
 }  // namespace ddml

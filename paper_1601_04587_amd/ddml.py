@@ -68,7 +68,7 @@ class ServerStats(ctypes.Structure):
 EXPORTS = ["ddml_create", "ddml_destroy", "ddml_last_error", "ddml_set_gauge", "ddml_set_gauge_lattice",
            "ddml_set_gauge_region",
            "ddml_release_gauge", "ddml_set_domain", "ddml_apply_Dw", "ddml_apply_eo", "ddml_solve_domain",
-           "ddml_solve_batch", "ddml_propagator_series", "ddml_propagator_series_batch", "ddml_time_stencil", "ddml_autotune", "ddml_contract_pp_disconnected", "ddml_contract_nucleon",
+           "ddml_solve_batch", "ddml_propagator_series", "ddml_propagator_series_batch", "ddml_time_stencil", "ddml_autotune", "ddml_set_launch", "ddml_contract_pp_disconnected", "ddml_contract_nucleon",
            "ddml_server_start", "ddml_submit", "ddml_poll", "ddml_wait", "ddml_stats", "ddml_server_stop",
            "ddml_now"]
 
@@ -104,6 +104,7 @@ def load():
                                                  I, P]
     lib.ddml_time_stencil.argtypes = [P, I, I, I, I, I, I, I, I, I, I, ctypes.POINTER(ctypes.c_double)]
     lib.ddml_autotune.argtypes = [P, I, I, I, I, ctypes.POINTER(ctypes.c_double)]
+    lib.ddml_set_launch.argtypes = [P, I, I, I, I, I, I]
     lib.ddml_contract_pp_disconnected.argtypes = [P, P, P, I, IP, IP, P, I, P]
     lib.ddml_contract_nucleon.argtypes = [P, P, I, P, P, I, P]
     lib.ddml_server_start.argtypes = [P, ctypes.POINTER(SolverParams), I]
@@ -304,6 +305,10 @@ class Context:
         out = (ctypes.c_double * 6)()
         self._check(self.lib.ddml_autotune(self.h, gid, dom, nrhs, prec, out))
         return int(out[0]), int(out[1]), int(out[2]), int(out[3]), int(out[4]), out[5]
+
+    def set_launch(self, prec, R, order, grid, splits, stage):
+        """Set the stencil launch of a precision by hand (see time_stencil)."""
+        self._check(self.lib.ddml_set_launch(self.h, prec, R, order, grid, splits, stage))
 
     # ------------------------------------------------------- contractions
     def contract_pp_disconnected(self, terms_x, terms_y, nlevels, xsrc, ysrc):

@@ -146,3 +146,40 @@ def test_fp16_storage_solve_and_iterations(setup):
     assert it16 <= 2 * it32 + 10, (it16, it32)
     # 16-bit runs take more FP64 corrections (each inner solve stops at 1e-3)
     assert max(i.outer_iters for i in info16) >= max(i.outer_iters for i in info32)
+
+
+def test_every_launch_variant_computes_the_same_bits():
+    """The stencil launch (columns per thread, tile order, grid, column splits,
+    LDS staging) changes only the schedule: every site and column is computed
+    and reduced the same way, so solves agree bit for bit.  A 16^4 box gives
+    planar tile walks (sub-banded orders)."""
+    L = (16, 16, 16, 16)
+    U = inputs.random_links(L, 1601077, 0.3)
+    ctx = ddml.Context(L, ddml.BC_ANTIPERIODIC)
+    try:
+        gid = ctx.set_gauge(U, 0.1200, 1.0)
+        dom = ctx.set_domain((4, 0, 0, 0), (10, 16, 16, 16))
+        b = inputs.point_source(L, (6, 3, 5, 7))
+        variants = {
+            ddml.MIXED_FP32: [(1, 1, 1024, 1, 0), (1, 3, 512, 1, 1), (1, 2, 1024, 2, 1), (2, 0, 512, 2, 0),
+                              (3, 1, 2048, 1, 1), (1, 0, 1024, 3, 0)],
+            ddml.FP64: [(1, 1, 1024, 1, 0), (1, 3, 1024, 1, 1), (3, 2, 512, 2, 1)],
+            ddml.MIXED_FP16: [(1, 1, 1024, 1, 1), (1, 3, 512, 2, 1), (2, 2, 1024, 1, 1)],
+        }
+        for prec, vs in variants.items():
+            ref = None
+            for v in vs:
+                ctx.set_launch(prec, *v)
+                x = np.zeros_like(b)
+                rc, info = ctx.solve_domain(gid, dom, b, x, 12, ddml.solver_params(tol=1e-10, prec=prec))
+                assert rc == ddml.OK, (prec, v)
+                if ref is None:
+                    ref = x
+                else:
+                    assert np.array_equal(x, ref), (prec, v)
+        with pytest.raises(ddml.DDMLError):
+            ctx.set_launch(ddml.MIXED_FP16, 1, 1, 1024, 1, 0)      # 16-bit needs the LDS staging
+        with pytest.raises(ddml.DDMLError):
+            ctx.set_launch(ddml.MIXED_FP32, 1, 1, 1024, 1, 2)      # no such stage
+    finally:
+        ctx.close()
