@@ -18,6 +18,23 @@ Contents and the passages they follow:
       normalised by 1/L^3 (eq. sing).
   * ``nucleon``: W_N1 - W_N2 (Section 5.2, eq. baryfact) summed over the sink
       time slice (eq. baryN), with C = i gamma0 gamma2 and P_- = (1-gamma0)/2.
+  * ``apply_boundary``: D_{dGamma}, the block of D that couples the sites
+      outside a domain to the sites inside it (Section 2, eq. blkdec; Appendix
+      A, eq. Scmpt2).  Its entries are those of D itself, so a backward time
+      hop into the domain carries -P_+ U_0(x-0)^dag and a forward one -P_-
+      U_0(x), with the 1/2 of eq. wdo and the minus sign that the block formula
+      eq. fact3 leaves out.
+  * ``factorized_propagator``: S^(f) = -D_{Gamma*}^{-1} D_{dGamma*}
+      D_{Gammabar}^{-1} (Section 5.2, eq. approxlong), the bottom-left block of
+      eq. Scmpt2 with the exact Schur-complement inverse replaced by the
+      propagator of the larger domain Gammabar.
+  * ``pion_connected``/``contract_pion``: C_Pc(y0) = -(1/L^3) sum tr{S S^dag}
+      (eqs. pipi, W0pc) and its expansion in the overlap thickness Delta
+      (eqs. decpi, seriespi, with the rest W^(r) = W - W^(f) of eq. W0pc2).
+
+Time boundary conditions: ``antiperiodic`` is True (antiperiodic), False
+(periodic) or ``OPEN`` (hops across the time boundary dropped, the set-up
+Sections 2 and 5.2 assume).
 
 Array conventions (complex128):
   links U[site, mu, 3, 3]; spinors / propagator columns psi[rhs, site, 4, 3];
@@ -29,6 +46,8 @@ import os
 import subprocess
 
 import numpy as np
+
+OPEN = 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
@@ -311,3 +330,66 @@ def contract_nucleon(terms, L):
     levels = np.stack([nucleon(cum[i], L) for i in range(cum.shape[0])])
     diffs = np.concatenate([levels[:1], np.diff(levels, axis=0)], axis=0)
     return levels, diffs
+
+
+# ------------------------------------------------- two-domain factorization
+def apply_boundary(U, L, psi, lo, hi, antiperiodic=True):
+    """D_{dGamma} psi for Gamma = [lo,hi): rows in Gamma, columns outside it.
+
+    By definition the block P_Gamma D (1 - P_Gamma) of the full operator
+    (eq. blkdec; the bottom-left block of eq. Scmpt2 when Gamma is the second
+    block).  Only hops cross a domain boundary, so kappa and the clover term
+    do not enter: D is applied with an arbitrary kappa to psi with its
+    components inside Gamma cleared, and the diagonal part then vanishes on the
+    rows that are kept."""
+    psi = _c(psi)
+    m = domain_mask(L, lo, hi)
+    outside = psi * (~m)[..., :, None, None]
+    return apply_D(U, L, 0.125, outside, antiperiodic=antiperiodic) * m[..., :, None, None]
+
+
+def factorized_propagator(U, L, kappa, b, bar, star, C=None, antiperiodic=True, tol=1e-13):
+    """S^(f) b = -D_{Gamma*}^{-1} D_{dGamma*} D_{Gammabar}^{-1} b (Section 5.2, eq. approxlong).
+
+    bar = (lo, hi) of Gammabar (it holds the source), star = (lo, hi) of
+    Gamma*.  Returns (S^(f) b, D_{Gammabar}^{-1} b); the first is zero outside
+    Gamma*, the second outside Gammabar."""
+    psi, _, _ = solve(U, L, kappa, b, C=C, antiperiodic=antiperiodic, lo=bar[0], hi=bar[1], tol=tol)
+    bstar = -apply_boundary(U, L, psi, star[0], star[1], antiperiodic)
+    sf, _, _ = solve(U, L, kappa, bstar, C=C, antiperiodic=antiperiodic, lo=star[0], hi=star[1], tol=tol)
+    return sf, psi
+
+
+def pion_W(sol):
+    """W_Pc(y, x) = tr{S(y,x) S(y,x)^dag} at every sink y (eq. W0pc), from 12 point-source columns."""
+    sol = np.asarray(sol)
+    V = sol.shape[1]
+    # S[y][alpha a, beta b] = sol[3 beta + b, y, alpha, a]
+    S = sol.reshape(12, V, 12).transpose(1, 2, 0)
+    SS = np.matmul(S, np.conj(S).transpose(0, 2, 1))
+    return np.trace(SS, axis1=1, axis2=2).real
+
+
+def pion_connected(sol, L):
+    """C_Pc(y0) = -(1/L^3) sum_{y in slice y0} W_Pc(y, x) for every y0 (eq. pipi).
+
+    With a point source the sum over the source's spatial position reduces to
+    that one point, as for the disconnected pieces."""
+    L = tuple(L)
+    V3 = int(np.prod(L[1:]))
+    W = pion_W(sol)
+    return -W.reshape(L[0], V3).sum(axis=1) / V3
+
+
+def contract_pion(levels, L, full=None):
+    """The connected pion correlator of each factorized level, the series of
+    eq. seriespi and its rest (eqs. decpi, W0pc2).
+
+    levels: [n, 12, V, 4, 3] factorized propagators S^(f) for a growing overlap
+    Delta; full: the propagator S on the whole lattice, or None.  Returns
+    (C, diffs, rest): C[i] = C^(i)_Pc, diffs[0] = C[0], diffs[i] = C[i] - C[i-1],
+    rest = C_Pc[S] - C[n-1] (None without ``full``)."""
+    C = np.stack([pion_connected(levels[i], L) for i in range(len(levels))])
+    diffs = np.concatenate([C[:1], np.diff(C, axis=0)], axis=0)
+    rest = None if full is None else pion_connected(full, L) - C[-1]
+    return C, diffs, rest

@@ -24,8 +24,11 @@
  *    blkdec): D_Gamma = P_Gamma D P_Gamma, i.e. every hop that leaves Gamma is
  *    dropped while the site-diagonal part (mass and clover, built from the
  *    full gauge field) is kept.  S^(i) = D_Gamma_i^{-1} (eq. diric).
- *  - Fermion boundary conditions: periodic in space, periodic or
- *    antiperiodic in time (a hop across the time boundary picks up -1).
+ *  - Fermion boundary conditions: periodic in space; in time (argument tbc)
+ *    0 periodic, 1 antiperiodic (a hop across the time boundary picks up -1)
+ *    or 2 open (hops across the time boundary are dropped, the site-diagonal
+ *    part is kept: the fermion field vanishes beyond the first and last time
+ *    slices, the set-up the paper assumes in Sections 2 and 5.2).
  *  - BiCGstab (van der Vorst 1992) on the unpreconditioned D_Gamma, with the
  *    true residual recomputed and the iteration restarted from it until
  *    ||b - D_Gamma x|| <= tol ||b|| per right-hand side.
@@ -202,8 +205,9 @@ void oracle_clover_term(const int L[4], const double *Ud, double csw, double *Co
 
 /* The hopping term H psi(x) = sum_mu [(1-g_mu) U_mu(x) psi(x+mu) + (1+g_mu) U_mu(x-mu)^dag psi(x-mu)],
  * restricted to the domain [lo,hi) (hops leaving it are dropped), with sign -1
- * on hops across the time boundary when antiperiodic. Output zero outside the domain. */
-static void hop_site(const lat_t *g, const cplx *U, int antiperiodic, const int lo[4], const int hi[4],
+ * on hops across the time boundary when antiperiodic (tbc 1) and no such hops
+ * when open (tbc 2). Output zero outside the domain. */
+static void hop_site(const lat_t *g, const cplx *U, int tbc, const int lo[4], const int hi[4],
                      const cplx *in, long s, cplx *out /* [12] */)
 {
     int x[4];
@@ -217,7 +221,8 @@ static void hop_site(const lat_t *g, const cplx *U, int antiperiodic, const int 
             double sign = 1.0;
             if (y[mu] < 0 || y[mu] >= g->L[mu]) {
                 y[mu] = (y[mu] + g->L[mu]) % g->L[mu];
-                if (mu == 0 && antiperiodic) sign = -1.0;
+                if (mu == 0 && tbc == 2) continue; /* open: no hop across the time boundary */
+                if (mu == 0 && tbc == 1) sign = -1.0;
             }
             if (!inside(y, lo, hi)) continue;
             long sy = index_of(g, y);
@@ -248,7 +253,7 @@ static void hop_site(const lat_t *g, const cplx *U, int antiperiodic, const int 
 }
 
 /* out = D_Gamma in for nrhs vectors of length V*12 (clover may be NULL). */
-void oracle_apply_D(const int L[4], const double *Ud, const double *Cd, double kappa, int antiperiodic,
+void oracle_apply_D(const int L[4], const double *Ud, const double *Cd, double kappa, int tbc,
                     const int lo[4], const int hi[4], int nrhs, const double *ind, double *outd)
 {
     lat_t g;
@@ -269,7 +274,7 @@ void oracle_apply_D(const int L[4], const double *Ud, const double *Cd, double k
                 continue;
             }
             cplx h[12];
-            hop_site(&g, U, antiperiodic, lo, hi, ir, s, h);
+            hop_site(&g, U, tbc, lo, hi, ir, s, h);
             const cplx *p = ir + s * 12;
             for (int k = 0; k < 12; ++k) {
                 cplx t = diag * p[k] - 0.5 * h[k];
@@ -282,7 +287,7 @@ void oracle_apply_D(const int L[4], const double *Ud, const double *Cd, double k
 }
 
 /* out = D_hop in (domain-restricted hopping term, no diagonal). */
-void oracle_apply_hop(const int L[4], const double *Ud, int antiperiodic, const int lo[4], const int hi[4],
+void oracle_apply_hop(const int L[4], const double *Ud, int tbc, const int lo[4], const int hi[4],
                       int nrhs, const double *ind, double *outd)
 {
     lat_t g;
@@ -300,7 +305,7 @@ void oracle_apply_hop(const int L[4], const double *Ud, int antiperiodic, const 
                 memset(orr + s * 12, 0, 12 * sizeof(cplx));
                 continue;
             }
-            hop_site(&g, U, antiperiodic, lo, hi, ir, s, orr + s * 12);
+            hop_site(&g, U, tbc, lo, hi, ir, s, orr + s * 12);
         }
     }
 }
@@ -322,7 +327,7 @@ static double norm2(long n, const cplx *a) { return creal(dotc(n, a, a)); }
 /* Solve D_Gamma x = b for each rhs (x zero outside Gamma).  info[r] receives
  * the iteration count and res[r] the final true relative residual.
  * Returns 0 if every rhs reached tol. */
-int oracle_solve(const int L[4], const double *Ud, const double *Cd, double kappa, int antiperiodic,
+int oracle_solve(const int L[4], const double *Ud, const double *Cd, double kappa, int tbc,
                  const int lo[4], const int hi[4], int nrhs, const double *bd, double *xd, double tol,
                  int maxiter, int *iters, double *res)
 {
@@ -357,7 +362,7 @@ int oracle_solve(const int L[4], const double *Ud, const double *Cd, double kapp
         }
         for (int cycle = 0; cycle < 50; ++cycle) {
             /* true residual */
-            oracle_apply_D(L, Ud, Cd, kappa, antiperiodic, lo, hi, 1, (const double *)x, (double *)r);
+            oracle_apply_D(L, Ud, Cd, kappa, tbc, lo, hi, 1, (const double *)x, (double *)r);
 #pragma omp parallel for schedule(static)
             for (long i = 0; i < n; ++i) r[i] = bm[i] - r[i];
             rel = sqrt(norm2(n, r)) / bn;
@@ -373,13 +378,13 @@ int oracle_solve(const int L[4], const double *Ud, const double *Cd, double kapp
                 rho = rho_new;
 #pragma omp parallel for schedule(static)
                 for (long i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
-                oracle_apply_D(L, Ud, Cd, kappa, antiperiodic, lo, hi, 1, (const double *)p, (double *)v);
+                oracle_apply_D(L, Ud, Cd, kappa, tbc, lo, hi, 1, (const double *)p, (double *)v);
                 cplx rv = dotc(n, rh, v);
                 if (cabs(rv) == 0) break;
                 alpha = rho / rv;
 #pragma omp parallel for schedule(static)
                 for (long i = 0; i < n; ++i) s[i] = r[i] - alpha * v[i];
-                oracle_apply_D(L, Ud, Cd, kappa, antiperiodic, lo, hi, 1, (const double *)s, (double *)t);
+                oracle_apply_D(L, Ud, Cd, kappa, tbc, lo, hi, 1, (const double *)s, (double *)t);
                 double tt = norm2(n, t);
                 omega = tt > 0 ? dotc(n, t, s) / tt : 0;
 #pragma omp parallel for schedule(static)
