@@ -15,6 +15,10 @@ Reported: domain solves/s (a solve = one domain x 12 columns to 1e-10), the
 stencil roofline (HIP events inside the library), the plain FP64 solver one
 solve at a time, serving latency percentiles, and the FP64 CPU oracle on a
 bounded sample.  Inputs are resident on the GPU before timing starts.
+A second workload (Section 5.2): the two-domain factorized propagator and
+connected pion series on the same field with open time boundaries, x0cut = 24,
+Delta = 8, 12, 16, source on t = 4 (eqs. approxlong, W0pc, seriespi), plus the
+whole-lattice solve for the rest; reported beside the headline figure.
 """
 import argparse
 import json
@@ -64,6 +68,9 @@ def parse():
     ap.add_argument("--no-fp16", action="store_true", help="skip the 16-bit storage leg")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-factorized", action="store_true", help="skip the factorized pion leg")
+    ap.add_argument("--factorized-only", action="store_true",
+                    help="only the factorized pion leg (profiling runs)")
     ap.add_argument("--serve-requests", type=int, default=64, help="requests per serving stream")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="configured Poisson rate, req/s")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -158,6 +165,12 @@ def main():
     t = time.time()
     U0 = inputs.quenched_field(L, seed, beta=beta)
     log("base field %s plaquette %.4f (%.1fs)" % (L, inputs.plaquette(U0, L), time.time() - t))
+    if args.factorized_only:
+        ctx = ddml.Context(L, ddml.BC_ANTIPERIODIC, device=0)
+        out = run_factorized(ctx, ddml, torch, dev, torch.from_numpy(U0).to(dev), L, kappa, csw, args)
+        ctx.close()
+        print(json.dumps({"factorized_pion": out}), flush=True)
+        return 0
     t = time.time()
     Uw = np.ascontiguousarray(U0.copy())
     regions = []   # [step][slab] device tensors of the slab's links after the update
@@ -295,6 +308,11 @@ def main():
                 "status": ddml.STATUS_NAMES[rc]}
         log("plain FP64 one-at-a-time: %.3f solves/s" % fp64["solves_per_s"])
 
+    # ------------------------------------------------- factorized pion series
+    fact = None
+    if not args.no_factorized:
+        fact = run_factorized(ctx, ddml, torch, dev, U0_dev, L, kappa, csw, args)
+
     # ------------------------------------------------------------ serving
     serve = None
     if not args.no_serve:
@@ -334,6 +352,7 @@ def main():
         "fp16_storage": fp16,
         "mixed_over_fp64": (solves_per_s / fp64["solves_per_s"]) if fp64 else None,
         "serving": serve,
+        "factorized_pion": fact,
         "inner_iters_per_solve": iters,
         "worst_true_rel_residual": worst,
         "cpu_baseline": cpu,
@@ -413,6 +432,59 @@ def run_serving(ctx, ddml, torch, dev, gid0, L, args):
            "configured": stream(args.serve_rate, args.serve_requests, 1601005),
            "sub_saturation_0.7x": stream(0.7 * capacity, args.serve_requests, 1601006)}
     log("serving: %s" % out)
+    return out
+
+
+def run_factorized(ctx, ddml, torch, dev, U0_dev, L, kappa, csw, args):
+    """Section 5.2 workload: S^(f) = -D_{Gamma*}^{-1} D_{dGamma*} D_{Gammabar_i}^{-1}
+    with Gammabar_i = [0, x0cut + Delta_i), Gamma* = [x0cut, T), open time
+    boundaries, then C^(i)_Pc, the series differences and the rest against the
+    whole-lattice propagator.  Timed: the 2 x 3 domain solves (one batch per
+    stage), the boundary blocks, the whole-lattice solve and the contraction."""
+    T = L[0]
+    xcut = 24 if T >= 48 else T // 2
+    deltas = [d for d in (8, 12, 16) if xcut + d <= T] or [T - xcut]
+    xsrc = (4 if xcut > 4 else 0, 0, 0, 0)
+    V = int(np.prod(L))
+    gid = ctx.set_gauge_lattice(L, U0_dev, kappa, csw, bc_time=ddml.BC_OPEN)
+    bars = [ctx.set_domain((0, 0, 0, 0), (xcut + d,) + tuple(L[1:])) for d in deltas]
+    star = ctx.set_domain((xcut, 0, 0, 0), tuple(L))
+    b = torch.zeros((12, V, 4, 3), dtype=torch.complex128, device=dev)
+    idx = ((xsrc[0] * L[1] + xsrc[1]) * L[2] + xsrc[2]) * L[3] + xsrc[3]
+    for r in range(12):
+        b[r, idx, r // 3, r % 3] = 1.0
+    levels = torch.zeros((len(deltas), 12, V, 4, 3), dtype=torch.complex128, device=dev)
+    full = torch.zeros((12, V, 4, 3), dtype=torch.complex128, device=dev)
+    prm = ddml.solver_params(tol=1e-10)
+
+    def once():
+        t0 = time.perf_counter()
+        rc, infos = ctx.factorized_series(gid, bars, star, b, 12, levels, None, prm)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rc2, info_full = ctx.solve_domain(gid, -1, b, full, 12, prm)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        C, diffs, rest = ctx.contract_pion(levels, len(deltas), full)
+        t3 = time.perf_counter()
+        return rc or rc2, infos, info_full, (C, diffs, rest), (t1 - t0, t2 - t1, t3 - t2)
+
+    once()    # warm-up
+    rc, infos, info_full, (C, diffs, rest), (ts, tf, tc) = once()
+    assert rc == ddml.OK, "factorized series failed: %s" % ctx.last_error()
+    ctx.release_gauge(gid)
+    worst = max(x.true_rel_residual for per in infos for stage in per for x in stage)
+    ys = [y for y in (xcut, xcut + 8, xcut + 16, xcut + 24, T - 1) if y < T]
+    out = {"lattice": list(L), "bc_time": "open", "x0cut": xcut, "deltas": deltas, "source": list(xsrc),
+           "nrhs": 12, "tol": 1e-10, "prec": "fp32 inner / fp64 outer",
+           "s_series": ts, "solves_per_s": 2 * len(deltas) / ts, "s_whole_lattice_solve": tf,
+           "s_contraction": tc,
+           "inner_iters": [[max(x.inner_iters for x in stage) for stage in per] for per in infos],
+           "whole_lattice_inner_iters": max(x.inner_iters for x in info_full),
+           "worst_true_rel_residual": worst,
+           "C_levels": {str(y): [float(C[i, y]) for i in range(len(deltas))] for y in ys},
+           "C_rest": {str(y): float(rest[y]) for y in ys}}
+    log("factorized pion: %s" % out)
     return out
 
 

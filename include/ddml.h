@@ -16,6 +16,10 @@
  *     W^(r2) (Section 3, eqs. W0, rall0, rall) and the nucleon contraction
  *     W_N1 - W_N2 (Section 5.2, eq. baryfact) summed over sink time slices
  *     (eq. baryN).
+ *   - The two-domain factorized propagator S^(f) = -D_{Gamma*}^{-1}
+ *     D_{dGamma*} D_{Gammabar}^{-1} (Section 5.2, eq. approxlong) and the
+ *     connected pion correlator built from it (eqs. pipi, W0pc, decpi,
+ *     seriespi).
  *
  * Canonical layouts at this boundary (all complex numbers are interleaved
  * (re, im) doubles):
@@ -26,8 +30,9 @@
  *             gamma_k = [[0,-i s_k],[i s_k,0]], gamma_5 = diag(1,1,-1,-1)
  *   a point-source propagator holds S(y,x)[alpha a][beta b] in column
  *   rhs = 3*beta + b, i.e. psi[3*beta+b][y][alpha][a].
- * Fermion boundary conditions: periodic in space; periodic or antiperiodic in
- * time.  The gauge field is periodic.
+ * Fermion boundary conditions: periodic in space; periodic, antiperiodic or
+ * open in time.  The gauge field is periodic (the clover term of every site is
+ * built from all four leaves, also next to an open time boundary).
  *
  * Ownership: the caller owns every buffer it passes.  A buffer flagged
  * on_device=1 is device memory on the context's GPU (e.g. a torch tensor's
@@ -64,7 +69,13 @@ typedef enum {
   DDML_EDEVICE = -6          /* HIP runtime error */
 } ddml_status;
 
-typedef enum { DDML_BC_PERIODIC = 0, DDML_BC_ANTIPERIODIC = 1 } ddml_bc;
+typedef enum {
+  DDML_BC_PERIODIC = 0,
+  DDML_BC_ANTIPERIODIC = 1,  /* a hop across the time boundary picks up -1 */
+  DDML_BC_OPEN = 2           /* no hops across the time boundary: the quark field
+                                vanishes before t = 0 and after t = T-1, the set-up
+                                Sections 2 and 5.2 assume */
+} ddml_bc;
 
 typedef enum {
   DDML_FP64 = 0,        /* FP64 throughout (the plain FP64 GPU solver) */
@@ -224,6 +235,52 @@ int ddml_contract_pp_disconnected(ddml_ctx ctx, const double* terms_x, const dou
  * Both are [nlevels][T] complex on the host.  Errors: EINVAL, EDEVICE. */
 int ddml_contract_nucleon(ddml_ctx ctx, const double* terms, int nlevels, double* levels_out, double* diffs_out,
                           int on_device, void* stream);
+
+/* Boundary block of D (Section 2, eq. blkdec; the off-diagonal block of eq.
+ * Scmpt2): out = scale * D_{dGamma} in, where D_{dGamma} holds the entries of
+ * D that couple a site y outside the domain Gamma to a site x inside it,
+ *   forward  y = x + mu:  -1/2 (1 - gamma_mu) U_mu(x)       in(y)
+ *   backward y = x - mu:  -1/2 (1 + gamma_mu) U_mu(x - mu)^dag in(y)
+ * with the time-boundary phase of the gauge field's lattice (open: no hop).
+ * For a time slab these are -P_- U_0 and -P_+ U_0^dag (eq. fact3 up to the
+ * sign and 1/2 of eq. wdo).  out is zero outside Gamma; in is read only
+ * outside Gamma.  in/out: [nrhs][V][4][3] complex128 on the gauge field's
+ * lattice, nrhs 1..12, not overlapping.  FP64.  Errors: EINVAL (ids, sizes),
+ * EDEVICE. */
+int ddml_apply_boundary(ddml_ctx ctx, int gauge_id, int dom_id, const double* in, double* out, int nrhs,
+                        double scale, int on_device, void* stream);
+
+/* Two-domain factorized propagators (Section 5.2, eq. approxlong) for a
+ * sequence of growing overlaps Delta (eq. seriespi):
+ *   psi_i = D_{Gammabar_i}^{-1} src,
+ *   S^(f)_i src = -D_{Gamma*}^{-1} D_{dGamma*} psi_i,     i = 0 .. nlevels-1,
+ * Gammabar_i = bar_ids[i] holds the source, Gamma* = star_id the sinks; with
+ * time slabs Gammabar_i = [0, x0cut + Delta_i) and Gamma* = [x0cut, T) the
+ * overlap thickness is Delta_i.  When Gammabar is the whole lattice S^(f)(y,x)
+ * is the exact propagator for x outside Gamma* and y in Gamma* (eq. Scmpt2).
+ * All Gammabar solves run as one batch, then all Gamma* solves as another
+ * (as ddml_solve_batch, same params).
+ *   src        [nrhs][V][4][3]
+ *   levels_out [nlevels][nrhs][V][4][3]: S^(f)_i src, zero outside Gamma*
+ *   bar_out    [nlevels][nrhs][V][4][3] or NULL: psi_i, zero outside Gammabar_i
+ *   info       [nlevels][2][nrhs]: the Gammabar solve, then the Gamma* solve
+ * Errors: EINVAL, ENOMEM, ENOTCONVERGED (info filled), EDEVICE. */
+int ddml_factorized_series(ddml_ctx ctx, int gauge_id, const int* bar_ids, int nlevels, int star_id,
+                           const double* src, int nrhs, const ddml_solver_params* params, double* levels_out,
+                           double* bar_out, ddml_rhs_info* info, int on_device, void* stream);
+
+/* Connected pseudoscalar correlator (eqs. pipi, W0pc):
+ *   C(y0) = -(1/L^3) sum_{y in slice y0} tr{S(y,x) S(y,x)^dag}
+ * for 12-column point-source propagators (the sum over the source position
+ * reduces to the one source point), on the context's lattice.
+ *   levels     [nlevels][12][V][4][3]: e.g. S^(f) for growing Delta
+ *   full       [12][V][4][3] or NULL: the propagator on the whole lattice
+ *   levels_out [nlevels][T] (host, real): C^(i)
+ *   diffs_out  [nlevels][T] (host) or NULL: C^(0), C^(i) - C^(i-1) (eq. seriespi)
+ *   rest_out   [T] (host) or NULL: C[full] - C^(nlevels-1) (eq. W0pc2); needs full
+ * Sums run in a fixed order.  Errors: EINVAL, EDEVICE. */
+int ddml_contract_pion(ddml_ctx ctx, const double* levels, int nlevels, const double* full, double* levels_out,
+                       double* diffs_out, double* rest_out, int on_device, void* stream);
 
 /* Measurement hook for the dominant kernels: times `iters` back-to-back
  * applications of the two half-stencils of the even-odd Schur operator, as

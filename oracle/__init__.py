@@ -78,6 +78,7 @@ def _load():
         lib.oracle_clover_term.argtypes = [i4, P, d, P]
         lib.oracle_apply_D.argtypes = [i4, P, P, d, i, i4, i4, i, P, P]
         lib.oracle_apply_hop.argtypes = [i4, P, i, i4, i4, i, P, P]
+        lib.oracle_apply_D_sites.argtypes = [i4, P, d, d, i, i4, i4, i, ctypes.c_long, P, P, P]
         lib.oracle_solve.argtypes = [i4, P, P, d, i, i4, i4, i, P, P, d, i, P, P]
         lib.oracle_solve.restype = i
         _lib = lib
@@ -146,6 +147,23 @@ def apply_D(U, L, kappa, psi, C=None, antiperiodic=True, lo=None, hi=None):
     _load().oracle_apply_D(_i4(L), U.ctypes.data, Cp, float(kappa), int(antiperiodic), clo, chi,
                            psi.shape[0], psi.ctypes.data, out.ctypes.data)
     return out[0] if squeeze else out
+
+
+def apply_D_sites(U, L, kappa, psi, sites, csw=0.0, antiperiodic=True, lo=None, hi=None):
+    """(D_Gamma psi)(x) at the listed sites only: [nrhs, len(sites), 4, 3].
+
+    The clover term (csw != 0) is built at those sites only, so a check on a
+    large lattice needs no [V, 12, 12] array."""
+    U = _c(U)
+    psi = _c(psi)
+    if psi.ndim == 3:
+        psi = psi[None]
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    out = np.empty((psi.shape[0], len(sites), 4, 3), dtype=np.complex128)
+    clo, chi = _domain(L, lo, hi)
+    _load().oracle_apply_D_sites(_i4(L), U.ctypes.data, float(csw), float(kappa), int(antiperiodic), clo, chi,
+                                 psi.shape[0], len(sites), sites.ctypes.data, psi.ctypes.data, out.ctypes.data)
+    return out
 
 
 def apply_hop(U, L, psi, antiperiodic=True, lo=None, hi=None):
@@ -346,6 +364,16 @@ def apply_boundary(U, L, psi, lo, hi, antiperiodic=True):
     m = domain_mask(L, lo, hi)
     outside = psi * (~m)[..., :, None, None]
     return apply_D(U, L, 0.125, outside, antiperiodic=antiperiodic) * m[..., :, None, None]
+
+
+def apply_boundary_sites(U, L, psi, sites, lo, hi, antiperiodic=True):
+    """(D_{dGamma} psi)(x) at listed sites x: on a row of Gamma the full operator
+    is D_Gamma plus the couplings from outside, so the boundary block is the
+    difference of the two there (zero for sites outside Gamma)."""
+    full = apply_D_sites(U, L, 0.125, psi, sites, antiperiodic=antiperiodic)
+    dom = apply_D_sites(U, L, 0.125, psi, sites, antiperiodic=antiperiodic, lo=lo, hi=hi)
+    m = domain_mask(L, lo, hi)[np.asarray(sites)]
+    return (full - dom) * m[None, :, None, None]
 
 
 def factorized_propagator(U, L, kappa, b, bar, star, C=None, antiperiodic=True, tol=1e-13):

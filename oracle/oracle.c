@@ -164,15 +164,9 @@ void oracle_field_strength(const int L[4], const double *Ud, int mu, int nu, dou
     }
 }
 
-/* 12x12 clover term per site: c_sw (i/4) sum_{mu,nu} sigma_{mu nu} (x) Fhat_{mu nu}. */
-void oracle_clover_term(const int L[4], const double *Ud, double csw, double *Cout)
+/* sigma_{mu nu} = (i/2)(gamma_mu gamma_nu - gamma_nu gamma_mu) */
+static void sigma_table(cplx sig[4][4][4][4])
 {
-    lat_t g;
-    lat_init(&g, L);
-    const cplx *U = (const cplx *)Ud;
-    cplx *C = (cplx *)Cout;
-    /* sigma_{mu nu} = (i/2)(gamma_mu gamma_nu - gamma_nu gamma_mu) */
-    cplx sig[4][4][4][4];
     for (int mu = 0; mu < 4; ++mu)
         for (int nu = 0; nu < 4; ++nu)
             for (int a = 0; a < 4; ++a)
@@ -181,26 +175,40 @@ void oracle_clover_term(const int L[4], const double *Ud, double csw, double *Co
                     for (int c = 0; c < 4; ++c) t += G[mu][a][c] * G[nu][c][b] - G[nu][a][c] * G[mu][c][b];
                     sig[mu][nu][a][b] = 0.5 * I * t;
                 }
+}
+
+/* 12x12 clover term of site s: c_sw (i/4) sum_{mu,nu} sigma_{mu nu} (x) Fhat_{mu nu}. */
+static void clover_site(const lat_t *g, const cplx *U, double csw, cplx sig[4][4][4][4], long s, cplx *Cs)
+{
+    memset(Cs, 0, 144 * sizeof(cplx));
+    for (int mu = 0; mu < 4; ++mu)
+        for (int nu = 0; nu < 4; ++nu) {
+            if (mu == nu) continue;
+            cplx Q[9], F[9];
+            clover_leaves(g, U, s, mu, nu, Q);
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) F[3 * i + j] = (Q[3 * i + j] - conj(Q[3 * j + i])) / 8.0;
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b) {
+                    cplx w = csw * 0.25 * I * sig[mu][nu][a][b];
+                    if (w == 0) continue;
+                    for (int i = 0; i < 3; ++i)
+                        for (int j = 0; j < 3; ++j) Cs[(a * 3 + i) * 12 + b * 3 + j] += w * F[3 * i + j];
+                }
+        }
+}
+
+/* The clover term of every site, [V][12][12]. */
+void oracle_clover_term(const int L[4], const double *Ud, double csw, double *Cout)
+{
+    lat_t g;
+    lat_init(&g, L);
+    const cplx *U = (const cplx *)Ud;
+    cplx *C = (cplx *)Cout;
+    cplx sig[4][4][4][4];
+    sigma_table(sig);
 #pragma omp parallel for schedule(static)
-    for (long s = 0; s < g.V; ++s) {
-        cplx *Cs = C + s * 144;
-        memset(Cs, 0, 144 * sizeof(cplx));
-        for (int mu = 0; mu < 4; ++mu)
-            for (int nu = 0; nu < 4; ++nu) {
-                if (mu == nu) continue;
-                cplx Q[9], F[9];
-                clover_leaves(&g, U, s, mu, nu, Q);
-                for (int i = 0; i < 3; ++i)
-                    for (int j = 0; j < 3; ++j) F[3 * i + j] = (Q[3 * i + j] - conj(Q[3 * j + i])) / 8.0;
-                for (int a = 0; a < 4; ++a)
-                    for (int b = 0; b < 4; ++b) {
-                        cplx w = csw * 0.25 * I * sig[mu][nu][a][b];
-                        if (w == 0) continue;
-                        for (int i = 0; i < 3; ++i)
-                            for (int j = 0; j < 3; ++j) Cs[(a * 3 + i) * 12 + b * 3 + j] += w * F[3 * i + j];
-                    }
-            }
-    }
+    for (long s = 0; s < g.V; ++s) clover_site(&g, U, csw, sig, s, C + s * 144);
 }
 
 /* The hopping term H psi(x) = sum_mu [(1-g_mu) U_mu(x) psi(x+mu) + (1+g_mu) U_mu(x-mu)^dag psi(x-mu)],
@@ -281,6 +289,48 @@ void oracle_apply_D(const int L[4], const double *Ud, const double *Cd, double k
                 if (C)
                     for (int j = 0; j < 12; ++j) t += C[s * 144 + k * 12 + j] * p[j];
                 o[k] = t;
+            }
+        }
+    }
+}
+
+/* (D_Gamma in)(x) at the listed sites only, for checks of large fields one
+ * site at a time: out[r][k][12] = (D_Gamma in_r)(sites[k]).  The clover term
+ * (csw != 0) of each listed site is built there, as oracle_clover_term builds
+ * it; the rest is oracle_apply_D's arithmetic for that site. */
+void oracle_apply_D_sites(const int L[4], const double *Ud, double csw, double kappa, int tbc,
+                          const int lo[4], const int hi[4], int nrhs, long nsites, const long *sites,
+                          const double *ind, double *outd)
+{
+    lat_t g;
+    lat_init(&g, L);
+    const cplx *U = (const cplx *)Ud, *in = (const cplx *)ind;
+    cplx *out = (cplx *)outd;
+    double diag = 1.0 / (2.0 * kappa);
+    cplx sig[4][4][4][4];
+    sigma_table(sig);
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < nsites; ++k) {
+        long s = sites[k];
+        int x[4];
+        coords(&g, s, x);
+        cplx Cs[144];
+        if (csw != 0) clover_site(&g, U, csw, sig, s, Cs);
+        for (int r = 0; r < nrhs; ++r) {
+            const cplx *ir = in + (long)r * g.V * 12;
+            cplx *o = out + ((long)r * nsites + k) * 12;
+            if (!inside(x, lo, hi)) {
+                memset(o, 0, 12 * sizeof(cplx));
+                continue;
+            }
+            cplx h[12];
+            hop_site(&g, U, tbc, lo, hi, ir, s, h);
+            const cplx *p = ir + s * 12;
+            for (int a = 0; a < 12; ++a) {
+                cplx t = diag * p[a] - 0.5 * h[a];
+                if (csw != 0)
+                    for (int j = 0; j < 12; ++j) t += Cs[a * 12 + j] * p[j];
+                o[a] = t;
             }
         }
     }

@@ -321,6 +321,103 @@ int ddml_propagator_series_batch(ddml_ctx ctx, int nseries, const ddml_series_de
   return guarded(ctx, [&](Ctx* c) { return series_many(c, nseries, descs, nrhs, params, on_device, stream); });
 }
 
+int ddml_apply_boundary(ddml_ctx ctx, int gauge_id, int dom_id, const double* in, double* out, int nrhs,
+                        double scale, int on_device, void* stream) {
+  return guarded(ctx, [&](Ctx* c) {
+    need(in && out, "NULL buffer");
+    need(nrhs >= 1 && nrhs <= kMaxRhs, "nrhs must be in 1..12");
+    const size_t bytes = (size_t)nrhs * gauge_get(c, gauge_id).V * 12 * sizeof(double2);
+    const char* a = reinterpret_cast<const char*>(in);
+    const char* b = reinterpret_cast<const char*>(out);
+    need(a + bytes <= b || b + bytes <= a, "in and out overlap");
+    StreamJoin sj(c, stream);
+    Staged si = stage_in(c, in, bytes, on_device);
+    Staged so = stage_out(c, out, bytes, on_device);
+    apply_boundary(c, gauge_id, dom_id, si.cptr, so.ptr, nrhs, scale, c->stream);
+    copy_back(c, out, so, bytes, on_device);
+    sj.done();
+    return DDML_OK;
+  });
+}
+
+// Two batches: every Gammabar_i solve, then the boundary blocks, then every Gamma* solve.
+int ddml_factorized_series(ddml_ctx ctx, int gauge_id, const int* bar_ids, int nlevels, int star_id,
+                           const double* src, int nrhs, const ddml_solver_params* params, double* levels_out,
+                           double* bar_out, ddml_rhs_info* info, int on_device, void* stream) {
+  return guarded(ctx, [&](Ctx* c) {
+    need(bar_ids && src && levels_out && info, "NULL argument");
+    need(nlevels >= 1 && nlevels <= 64, "nlevels must be in 1..64");
+    need(nrhs >= 1 && nrhs <= kMaxRhs, "nrhs must be in 1..12");
+    check_params(params);
+    (void)domain_get(c, star_id);
+    for (int i = 0; i < nlevels; ++i) (void)domain_get(c, bar_ids[i]);
+    const size_t per = (size_t)nrhs * gauge_get(c, gauge_id).V * 12;  // complex numbers of one field
+    const size_t bytes = per * sizeof(double2);
+    StreamJoin sj(c, stream);
+    Staged si = stage_in(c, src, bytes, on_device);
+    Staged sl = stage_out(c, levels_out, bytes * nlevels, on_device);
+    Staged sb;
+    if (bar_out) sb = stage_out(c, bar_out, bytes * nlevels, on_device);
+    else sb.buf = DBuf(c->pool.get(), bytes * nlevels), sb.ptr = sb.buf.as<double>();
+    DBuf bstar(c->pool.get(), bytes * nlevels);
+    std::vector<ddml_solve_desc> d;
+    for (int i = 0; i < nlevels; ++i)
+      d.push_back(ddml_solve_desc{gauge_id, bar_ids[i], si.cptr, sb.ptr + 2 * per * i, nrhs,
+                                  info + (size_t)(2 * i) * nrhs});
+    const int rc1 = solve_many(c, nlevels, d.data(), params, 1, c->stream);
+    for (int i = 0; i < nlevels; ++i)
+      apply_boundary(c, gauge_id, star_id, sb.ptr + 2 * per * i, bstar.as<double>() + 2 * per * i, nrhs, -1.0,
+                     c->stream);
+    d.clear();
+    for (int i = 0; i < nlevels; ++i)
+      d.push_back(ddml_solve_desc{gauge_id, star_id, bstar.as<double>() + 2 * per * i, sl.ptr + 2 * per * i, nrhs,
+                                  info + (size_t)(2 * i + 1) * nrhs});
+    const int rc2 = solve_many(c, nlevels, d.data(), params, 1, c->stream);
+    copy_back(c, levels_out, sl, bytes * nlevels, on_device);
+    if (bar_out) copy_back(c, bar_out, sb, bytes * nlevels, on_device);
+    DDML_HIP(hipStreamSynchronize(c->stream));
+    sj.done();
+    return rc1 != DDML_OK ? rc1 : rc2;
+  });
+}
+
+int ddml_contract_pion(ddml_ctx ctx, const double* levels, int nlevels, const double* full, double* levels_out,
+                       double* diffs_out, double* rest_out, int on_device, void* stream) {
+  return guarded(ctx, [&](Ctx* c) {
+    need(levels && levels_out && nlevels >= 1 && nlevels <= 64, "bad arguments");
+    need(full || !rest_out, "rest_out needs the full propagator");
+    const int T = c->lat.dims[0];
+    const size_t one = (size_t)12 * c->V * 12 * sizeof(double2);
+    const int np = nlevels + (full ? 1 : 0);
+    StreamJoin sj(c, stream);
+    Staged sl = stage_in(c, levels, one * nlevels, on_device);
+    Staged sf;
+    if (full) sf = stage_in(c, full, one, on_device);
+    DBuf W(c->pool.get(), (size_t)np * c->V * sizeof(double2));
+    DBuf sums(c->pool.get(), (size_t)np * T * sizeof(double2));
+    DBuf o(c->pool.get(), (size_t)(2 * nlevels + 1) * T * sizeof(double));
+    DDML_HIP(launch_pion(reinterpret_cast<const double2*>(sl.cptr), c->V, T, nlevels, W.as<double2>(),
+                         sums.as<double2>(), c->stream));
+    if (full)
+      DDML_HIP(launch_pion(reinterpret_cast<const double2*>(sf.cptr), c->V, T, 1,
+                           W.as<double2>() + (size_t)nlevels * c->V, sums.as<double2>() + (size_t)nlevels * T,
+                           c->stream));
+    const double invL3 = 1.0 / ((double)c->lat.dims[1] * c->lat.dims[2] * c->lat.dims[3]);
+    DDML_HIP(launch_pion_fin(sums.as<double2>(), nlevels, T, full ? 1 : 0, invL3, o.as<double>(), c->stream));
+    const size_t rowb = (size_t)T * sizeof(double);
+    DDML_HIP(hipMemcpyAsync(levels_out, o.p, nlevels * rowb, hipMemcpyDeviceToHost, c->stream));
+    if (diffs_out)
+      DDML_HIP(hipMemcpyAsync(diffs_out, o.as<double>() + (size_t)nlevels * T, nlevels * rowb,
+                              hipMemcpyDeviceToHost, c->stream));
+    if (rest_out)
+      DDML_HIP(hipMemcpyAsync(rest_out, o.as<double>() + (size_t)2 * nlevels * T, rowb, hipMemcpyDeviceToHost,
+                              c->stream));
+    DDML_HIP(hipStreamSynchronize(c->stream));
+    sj.done();
+    return DDML_OK;
+  });
+}
+
 int ddml_time_stencil(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec, int iters, int R, int order,
                       int grid, int splits, int stage, double out[4]) {
   return guarded(ctx, [&](Ctx* c) {

@@ -9,6 +9,10 @@
 //      W_N2 = eps^{abc} eps^{feg} tr[S^{ag T} C g5 S^{be} P_- S^{cf} C g5]
 //    per sink site, then summed over each sink time slice (eq. baryN) in a
 //    fixed order.
+//  * Connected pseudoscalar (eqs. pipi, W0pc): W(y) = tr{S(y,x) S(y,x)^dag},
+//    the sum of |S|^2 over the 144 entries at the sink, summed per time slice
+//    and scaled by -1/L^3; series differences (eq. seriespi) and the rest
+//    against the full propagator (eq. W0pc2).
 // In the chiral basis C = diag(s_2, -s_2), so C g5 = diag(s_2, s_2), and
 // P_- = [[1,1],[1,1]]/2 in 2x2 spin blocks; both are applied in closed form below.
 #include "ddml_common.hpp"
@@ -205,6 +209,55 @@ __global__ void k_slice_sum(const double2* __restrict__ W, size_t V, int T, doub
     __syncthreads();
   }
   if (threadIdx.x == 0) out[(size_t)level * T + t] = part[0];
+}
+
+// ---------------------------------------------------- connected pseudoscalar
+// W[prop][site] = sum over the 12 columns and 12 components of |S|^2 (column
+// by column, components in order).  Real, kept as double2 (im = 0) for the slice sum.
+__global__ void k_pion_site(const double2* __restrict__ props, size_t V, double2* __restrict__ W) {
+  const int prop = blockIdx.y;
+  for (size_t y = blockIdx.x * (size_t)blockDim.x + threadIdx.x; y < V; y += (size_t)gridDim.x * blockDim.x) {
+    double w = 0;
+    for (int col = 0; col < 12; ++col) {
+      const double2* v = props + (((size_t)prop * 12 + col) * V + y) * 12;
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        const double2 e = v[c];
+        w += e.x * e.x + e.y * e.y;
+      }
+    }
+    W[(size_t)prop * V + y] = make_double2(w, 0.0);
+  }
+}
+
+// out rows: [0, n) levels C^(i) = -sums[i]/L^3; [n, 2n) differences; 2n: rest.
+__global__ void k_pion_fin(const double2* __restrict__ sums, int nlevels, int T, int has_full, double invL3,
+                           double* __restrict__ out) {
+  for (int t = threadIdx.x; t < T; t += blockDim.x) {
+    double prev = 0;
+    for (int i = 0; i < nlevels; ++i) {
+      const double c = -sums[(size_t)i * T + t].x * invL3;
+      out[(size_t)i * T + t] = c;
+      out[(size_t)(nlevels + i) * T + t] = i == 0 ? c : c - prev;
+      prev = c;
+    }
+    out[(size_t)2 * nlevels * T + t] = has_full ? -sums[(size_t)nlevels * T + t].x * invL3 - prev : 0.0;
+  }
+}
+
+hipError_t launch_pion(const double2* props, size_t V, int T, int nprops, double2* W, double2* sums,
+                       hipStream_t st) {
+  size_t g = (V + 255) / 256;
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_pion_site, dim3((unsigned)g, nprops), dim3(256), 0, st, props, V, W);
+  hipLaunchKernelGGL(k_slice_sum, dim3(T, nprops), dim3(256), 0, st, W, V, T, sums);
+  return hipGetLastError();
+}
+
+hipError_t launch_pion_fin(const double2* sums, int nlevels, int T, int has_full, double invL3, double* out,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_pion_fin, dim3(1), dim3(256), 0, st, sums, nlevels, T, has_full, invL3, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_nucleon(const double2* terms, size_t V, int T, int nlevels, double2* W, double2* out,

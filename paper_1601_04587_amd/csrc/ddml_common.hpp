@@ -24,7 +24,8 @@
 // Neighbours are taken with local periodic wrap-around.  Links that would leave
 // Gamma through a face that is not a full lattice extent are stored as zero, so
 // the Dirichlet restriction of eq. blkdec needs no branch in the stencil; the
-// antiperiodic time phase is folded into the time links of the wrap.
+// antiperiodic time phase is folded into the time links of the wrap, and with
+// open time boundaries those links are zero as well.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

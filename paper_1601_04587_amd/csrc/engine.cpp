@@ -118,8 +118,8 @@ void ctx_init(Ctx* c, const ddml_lattice* lat, int device, size_t budget) {
   for (int m = 0; m < 4; ++m)
     if (lat->dims[m] < 2 || lat->dims[m] % 2)
       throw Error{DDML_EINVAL, "lattice extents must be even and >= 2"};
-  if (lat->bc_time != DDML_BC_PERIODIC && lat->bc_time != DDML_BC_ANTIPERIODIC)
-    throw Error{DDML_EINVAL, "bc_time must be DDML_BC_PERIODIC or DDML_BC_ANTIPERIODIC"};
+  if (lat->bc_time != DDML_BC_PERIODIC && lat->bc_time != DDML_BC_ANTIPERIODIC && lat->bc_time != DDML_BC_OPEN)
+    throw Error{DDML_EINVAL, "bc_time must be DDML_BC_PERIODIC, DDML_BC_ANTIPERIODIC or DDML_BC_OPEN"};
   int ndev = 0;
   DDML_HIP(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) throw Error{DDML_EINVAL, "no such device"};
@@ -152,8 +152,8 @@ static void check_lattice(const ddml_lattice* lat) {
   if (!lat) throw Error{DDML_EINVAL, "lattice is NULL"};
   for (int m = 0; m < 4; ++m)
     if (lat->dims[m] < 2 || lat->dims[m] % 2) throw Error{DDML_EINVAL, "lattice extents must be even and >= 2"};
-  if (lat->bc_time != DDML_BC_PERIODIC && lat->bc_time != DDML_BC_ANTIPERIODIC)
-    throw Error{DDML_EINVAL, "bc_time must be DDML_BC_PERIODIC or DDML_BC_ANTIPERIODIC"};
+  if (lat->bc_time != DDML_BC_PERIODIC && lat->bc_time != DDML_BC_ANTIPERIODIC && lat->bc_time != DDML_BC_OPEN)
+    throw Error{DDML_EINVAL, "bc_time must be DDML_BC_PERIODIC, DDML_BC_ANTIPERIODIC or DDML_BC_OPEN"};
   const size_t V = (size_t)lat->dims[0] * lat->dims[1] * lat->dims[2] * lat->dims[3];
   if (V > (size_t)1 << 30) throw Error{DDML_EINVAL, "lattice too large"};
 }
@@ -275,7 +275,7 @@ static void fill_spec(Ctx* c, const GaugeRec& g, const DomainRec& d, BlockSpec& 
     bs.Lb[m] = d.hi[m] - d.lo[m];
     geo.L[m] = bs.Lb[m];
   }
-  bs.antiperiodic = g.lat.bc_time == DDML_BC_ANTIPERIODIC;
+  bs.tbc = g.lat.bc_time;
   bs.kappa = g.kappa;
   bs.csw = g.csw;
   geo.Vh = bs.Lb[0] * bs.Lb[1] * bs.Lb[2] * bs.Lb[3] / 2;
@@ -481,6 +481,24 @@ void apply_D(Ctx* c, int gauge_id, int dom_id, const double* in, double* out, in
   DDML_HIP(launch_scatter(oe.as<double2>(), ob->bs, 0, nrhs, 1.0, cout, st));
   DDML_HIP(launch_scatter(oo.as<double2>(), ob->bs, 1, nrhs, 1.0, cout, st));
   DDML_HIP(hipStreamSynchronize(st));  // temporaries go back to the pool
+}
+
+// Couplings of D from outside a domain into it; no operator block is needed:
+// the kernel reads the canonical links of the gauge field directly.
+void apply_boundary(Ctx* c, int gauge_id, int dom_id, const double* in, double* out, int nrhs, double scale,
+                    hipStream_t st) {
+  const GaugeRec& g = gauge_get(c, gauge_id);
+  const DomainRec d = domain_on(c, g, dom_id);
+  BlockSpec bs{};
+  BoxGeom geo{};
+  fill_spec(c, g, d, bs, geo);
+  GaugeView gv;
+  gv.base = g.base->as<double2>();
+  gv.region = g.region ? g.region->as<double2>() : nullptr;
+  gv.r_t0 = g.r_t0;
+  gv.r_t1 = g.r_t1;
+  DDML_HIP(launch_boundary(gv, bs, reinterpret_cast<const double2*>(in), reinterpret_cast<double2*>(out), nrhs, scale,
+                           st));
 }
 
 template <typename T2>

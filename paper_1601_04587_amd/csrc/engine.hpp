@@ -221,6 +221,9 @@ size_t solve_footprint(Ctx* c, int gauge_id, int dom_id, int nrhs, const ddml_so
 int gcr_len(const ddml_solver_params& prm);
 void apply_D(Ctx* c, int gauge_id, int dom_id, const double* in, double* out, int nrhs, hipStream_t st);
 void apply_eo(Ctx* c, int gauge_id, int dom_id, const double* in, double* out, int nrhs, int prec, hipStream_t st);
+// out = scale * D_{dGamma} in (canonical FP64 fields on the gauge field's lattice)
+void apply_boundary(Ctx* c, int gauge_id, int dom_id, const double* in, double* out, int nrhs, double scale,
+                    hipStream_t st);
 // Runs every solve to completion (continuous batching inside).  Device pointers.
 void run_solves(Ctx* c, std::vector<Solve*>& solves);
 // Pieces used by the serving loop

@@ -65,7 +65,8 @@ __global__ void k_build_links(GaugeView gv, BlockSpec bs, double2* __restrict__ 
       double f = 1.0;
       if (y[mu] == bs.Lb[mu] - 1) {
         if (bs.Lb[mu] != bs.L[mu]) f = 0.0;                  // Dirichlet face of the domain
-        else if (mu == 0 && bs.antiperiodic) f = -1.0;      // antiperiodic wrap in time
+        else if (mu == 0 && bs.tbc == 1) f = -1.0;          // antiperiodic wrap in time
+        else if (mu == 0 && bs.tbc == 2) f = 0.0;           // open: no hop across the time boundary
       }
 #pragma unroll
       for (int k = 0; k < 10; ++k) {  // entry 9 is the zero pad of the last pair
@@ -342,6 +343,102 @@ __global__ void k_scatter(const double2* __restrict__ eo, BlockSpec bs, int p, i
     }
   }
 }
+// ------------------------------------------------- boundary block D_{dGamma}
+// The entries of D that join a site x of the domain Gamma to a neighbour y
+// outside it (eq. blkdec; the off-diagonal block of eq. Scmpt2):
+//   y = x + mu:  -1/2 (1 - gamma_mu) U_mu(x) psi(y)
+//   y = x - mu:  -1/2 (1 + gamma_mu) U_mu(y)^dag psi(y)
+// with the time-boundary phase (antiperiodic -1, open: no such hop).  One
+// thread per (column, site) of the canonical field; sites outside Gamma and
+// inner sites write zero.  Each row of a chiral-basis gamma matrix has a
+// single entry: (gamma_mu psi)_a = ph * psi_{col}.
+__constant__ int kGamCol[4][4] = {{2, 3, 0, 1}, {3, 2, 1, 0}, {3, 2, 1, 0}, {2, 3, 0, 1}};
+__constant__ double kGamRe[4][4] = {{-1, -1, -1, -1}, {0, 0, 0, 0}, {-1, 1, 1, -1}, {0, 0, 0, 0}};
+__constant__ double kGamIm[4][4] = {{0, 0, 0, 0}, {-1, -1, 1, 1}, {0, 0, 0, 0}, {-1, 1, 1, -1}};
+
+__device__ __forceinline__ bool in_box(const BlockSpec& bs, const int x[4]) {
+  bool in = true;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) in = in && x[m] >= bs.lo[m] && x[m] < bs.lo[m] + bs.Lb[m];
+  return in;
+}
+
+__global__ void k_boundary(GaugeView gv, BlockSpec bs, const double2* __restrict__ in, double2* __restrict__ out,
+                           int nrhs, double scale) {
+  const size_t V = (size_t)bs.L[0] * bs.L[1] * bs.L[2] * bs.L[3];
+  const size_t n = V * nrhs;
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+    const size_t site = k % V, col = k / V;
+    int x[4];
+    size_t r = site;
+    x[3] = (int)(r % bs.L[3]); r /= bs.L[3];
+    x[2] = (int)(r % bs.L[2]); r /= bs.L[2];
+    x[1] = (int)(r % bs.L[1]);
+    x[0] = (int)(r / bs.L[1]);
+    double2 acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = make_double2(0, 0);
+    if (in_box(bs, x)) {
+      for (int mu = 0; mu < 4; ++mu)
+        for (int d = 1; d >= -1; d -= 2) {
+          int y[4] = {x[0], x[1], x[2], x[3]};
+          y[mu] += d;
+          double ph = -0.5 * scale;
+          if (y[mu] < 0 || y[mu] >= bs.L[mu]) {
+            y[mu] = (y[mu] + bs.L[mu]) % bs.L[mu];
+            if (mu == 0 && bs.tbc == 2) continue;
+            if (mu == 0 && bs.tbc == 1) ph = -ph;
+          }
+          if (in_box(bs, y)) continue;
+          double2 u[9];
+          load_link(gv, bs.L, d > 0 ? x : y, mu, u);
+          const double2* psi = in + (col * V + gidx(bs.L, y)) * 12;
+          double2 chi[12];  // U psi or U^dag psi, per spin component
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+              double2 t = make_double2(0, 0);
+#pragma unroll
+              for (int j = 0; j < 3; ++j) {
+                const double2 v = psi[3 * a + j];
+                const double2 w = d > 0 ? dmul(u[3 * i + j], v) : dmulc(u[3 * j + i], v);
+                t.x += w.x;
+                t.y += w.y;
+              }
+              chi[3 * a + i] = t;
+            }
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            const int b = kGamCol[mu][a];
+            const double gr = kGamRe[mu][a], gi = kGamIm[mu][a];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+              const double2 v = chi[3 * b + i];
+              // (1 - d gamma_mu) chi
+              const double2 t = make_double2(chi[3 * a + i].x - d * (gr * v.x - gi * v.y),
+                                             chi[3 * a + i].y - d * (gr * v.y + gi * v.x));
+              acc[3 * a + i].x += ph * t.x;
+              acc[3 * a + i].y += ph * t.y;
+            }
+          }
+        }
+    }
+    double2* o = out + (col * V + site) * 12;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) o[c] = acc[c];
+  }
+}
+
+hipError_t launch_boundary(const GaugeView& gv, const BlockSpec& bs, const double2* in, double2* out, int nrhs,
+                           double scale, hipStream_t st) {
+  const size_t n = (size_t)bs.L[0] * bs.L[1] * bs.L[2] * bs.L[3] * nrhs;
+  size_t grid = (n + 255) / 256;
+  if (grid > 32768) grid = 32768;
+  hipLaunchKernelGGL(k_boundary, dim3((unsigned)grid), dim3(256), 0, st, gv, bs, in, out, nrhs, scale);
+  return hipGetLastError();
+}
+
 // 16-bit copies for the FP16-storage inner solver: links with scale 1 (their
 // entries are bounded by 1 in magnitude), A^{-1} with one scale per site.
 __global__ void k_quant_links(const double2* __restrict__ U64, h16c* __restrict__ U16, size_t n) {

@@ -81,7 +81,7 @@ struct BlockSpec {
   int L[4];       // lattice
   int lo[4];      // domain origin
   int Lb[4];      // domain extents (even)
-  int antiperiodic;
+  int tbc;        // time boundary of the lattice: 0 periodic, 1 antiperiodic, 2 open
   double kappa, csw;
 };
 hipError_t launch_build_links(const GaugeView& gv, const BlockSpec& bs, double2* U64, float2* U32, hipStream_t st);
@@ -95,11 +95,20 @@ hipError_t launch_gather(const double2* canon, const BlockSpec& bs, int p, int n
                          hipStream_t st);
 hipError_t launch_scatter(const double2* eo, const BlockSpec& bs, int p, int nrhs, double scale, double2* canon,
                           hipStream_t st);
+// out = scale * D_{dGamma} in on canonical [nrhs][V][12] fields, Gamma = [bs.lo, bs.lo + bs.Lb)
+hipError_t launch_boundary(const GaugeView& gv, const BlockSpec& bs, const double2* in, double2* out, int nrhs,
+                           double scale, hipStream_t st);
 
 // contract.hip
 hipError_t launch_series_diff(double2* terms, size_t n, int nlevels, double2* sum, hipStream_t st);
 hipError_t launch_pp(const double2* tx, const double2* ty, size_t V, int nlevels, size_t xs, size_t ys, double invL3,
                      double2* out, hipStream_t st);
+// connected pion: W scratch [nprops][V]; sums [nprops][T] of tr{S S^dag} per time slice
+hipError_t launch_pion(const double2* props, size_t V, int T, int nprops, double2* W, double2* sums, hipStream_t st);
+// C^(i) = -sums[i] / L^3, the series differences and (has_full: sums[nlevels] is the full
+// propagator's) the rest; out: [2 * nlevels + 1][T] = levels, diffs, rest
+hipError_t launch_pion_fin(const double2* sums, int nlevels, int T, int has_full, double invL3, double* out,
+                           hipStream_t st);
 // W: scratch [nlevels][V]; out: [nlevels][T]
 hipError_t launch_nucleon(const double2* terms, size_t V, int T, int nlevels, double2* W, double2* out,
                           hipStream_t st);

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libddml.so")
 
 OK, EINVAL, ENOMEM, EAGAIN, ENOTCONVERGED, ENUMERIC, EDEVICE = 0, -1, -2, -3, -4, -5, -6
-BC_PERIODIC, BC_ANTIPERIODIC = 0, 1
+BC_PERIODIC, BC_ANTIPERIODIC, BC_OPEN = 0, 1, 2
 FP64, MIXED_FP32, MIXED_FP16 = 0, 1, 2
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EAGAIN", -4: "ENOTCONVERGED", -5: "ENUMERIC",
                 -6: "EDEVICE"}
@@ -69,7 +69,7 @@ EXPORTS = ["ddml_create", "ddml_destroy", "ddml_last_error", "ddml_set_gauge", "
            "ddml_set_gauge_region",
            "ddml_release_gauge", "ddml_set_domain", "ddml_apply_Dw", "ddml_apply_eo", "ddml_solve_domain",
            "ddml_solve_batch", "ddml_propagator_series", "ddml_propagator_series_batch", "ddml_time_stencil", "ddml_autotune", "ddml_set_launch", "ddml_contract_pp_disconnected", "ddml_contract_nucleon",
-           "ddml_server_start", "ddml_submit", "ddml_poll", "ddml_wait", "ddml_stats", "ddml_server_stop",
+           "ddml_apply_boundary", "ddml_factorized_series", "ddml_contract_pion", "ddml_server_start", "ddml_submit", "ddml_poll", "ddml_wait", "ddml_stats", "ddml_server_stop",
            "ddml_now"]
 
 _lib = None
@@ -107,6 +107,10 @@ def load():
     lib.ddml_set_launch.argtypes = [P, I, I, I, I, I, I]
     lib.ddml_contract_pp_disconnected.argtypes = [P, P, P, I, IP, IP, P, I, P]
     lib.ddml_contract_nucleon.argtypes = [P, P, I, P, P, I, P]
+    lib.ddml_apply_boundary.argtypes = [P, I, I, P, P, I, D, I, P]
+    lib.ddml_factorized_series.argtypes = [P, I, IP, I, I, P, I, ctypes.POINTER(SolverParams), P, P,
+                                           ctypes.POINTER(RhsInfo), I, P]
+    lib.ddml_contract_pion.argtypes = [P, P, I, P, P, P, P, I, P]
     lib.ddml_server_start.argtypes = [P, ctypes.POINTER(SolverParams), I]
     lib.ddml_submit.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
     lib.ddml_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Result)]
@@ -231,6 +235,13 @@ class Context:
         self._check(self.lib.ddml_apply_eo(self.h, gid, dom, pi, po, nrhs, prec, dev, _stream(inp)))
         return out
 
+    def apply_boundary(self, gid, dom, inp, out, nrhs, scale=1.0):
+        """out = scale * D_{dGamma} inp (couplings of D from outside the domain into it)."""
+        pi, dev = _ptr(inp)
+        po, _ = _ptr(out)
+        self._check(self.lib.ddml_apply_boundary(self.h, gid, dom, pi, po, nrhs, float(scale), dev, _stream(inp)))
+        return out
+
     # ------------------------------------------------------------- solves
     def solve_domain(self, gid, dom, src, sol, nrhs, params=None):
         params = params or solver_params()
@@ -293,6 +304,22 @@ class Context:
         self._check(rc, allow=(ENOTCONVERGED, ENUMERIC))
         return rc, [[list(info[i * nrhs:(i + 1) * nrhs]) for i in range(len(d))] for d, info in keep]
 
+    def factorized_series(self, gid, bar_doms, star_dom, src, nrhs, levels, bar=None, params=None):
+        """S^(f)_i src = -D_{Gamma*}^{-1} D_{dGamma*} D_{Gammabar_i}^{-1} src for each Gammabar_i.
+
+        Returns (rc, infos) with infos[i] = (Gammabar_i solve infos, Gamma* solve infos)."""
+        params = params or solver_params()
+        n = len(bar_doms)
+        info = (RhsInfo * (2 * n * nrhs))()
+        ps, dev = _ptr(src)
+        pl, _ = _ptr(levels)
+        pb = _ptr(bar)[0] if bar is not None else None
+        rc = self.lib.ddml_factorized_series(self.h, gid, (ctypes.c_int * n)(*bar_doms), n, star_dom, ps, nrhs,
+                                             ctypes.byref(params), pl, pb, info, dev, _stream(src))
+        self._check(rc, allow=(ENOTCONVERGED, ENUMERIC))
+        return rc, [(list(info[(2 * i) * nrhs:(2 * i + 1) * nrhs]), list(info[(2 * i + 1) * nrhs:(2 * i + 2) * nrhs]))
+                    for i in range(n)]
+
     def time_stencil(self, gid, dom, nrhs, prec=MIXED_FP32, iters=20, R=0, order=-1, grid=0, splits=0, stage=-1):
         """(ms_odd_half, ms_even_half, bytes_odd_half, bytes_even_half) per launch."""
         out = (ctypes.c_double * 4)()
@@ -328,6 +355,20 @@ class Context:
         self._check(self.lib.ddml_contract_nucleon(self.h, pt, nlevels, levels.ctypes.data, diffs.ctypes.data, dev,
                                                    _stream(terms)))
         return levels, diffs
+
+    def contract_pion(self, levels, nlevels, full=None):
+        """Connected pion correlator per level, its series differences and (with the full
+        propagator) the rest; returns (levels [n, T], diffs [n, T], rest [T] or None)."""
+        T = self.dims[0]
+        lv = np.zeros((nlevels, T))
+        df = np.zeros((nlevels, T))
+        rest = np.zeros(T) if full is not None else None
+        pl, dev = _ptr(levels)
+        pf = _ptr(full)[0] if full is not None else None
+        self._check(self.lib.ddml_contract_pion(self.h, pl, nlevels, pf, lv.ctypes.data, df.ctypes.data,
+                                                rest.ctypes.data if rest is not None else None, dev,
+                                                _stream(levels)))
+        return lv, df, rest
 
     # ------------------------------------------------------------ serving
     def server_start(self, params=None, max_queue=100000):

@@ -186,3 +186,22 @@ def test_pion_contraction_equals_gamma5_wick_form():
     lv = np.stack([0.5 * sol, 0.9 * sol, sol])
     Cs, diffs, rest = oracle.contract_pion(lv, L, full=1.1 * sol)
     assert np.allclose(diffs.sum(axis=0), Cs[-1]) and np.allclose(Cs[-1] + rest, 1.21 * Cs[-1])
+
+
+@pytest.mark.parametrize("bc", [True, oracle.OPEN])
+def test_site_by_site_operator_and_boundary_agree_with_whole_field(rng, bc):
+    """The site-by-site forms used on large lattices give the whole-field values."""
+    L = (8, 4, 2, 4)
+    kappa = 0.13
+    U = inputs.random_links(L, 1601206, 0.4)
+    V = int(np.prod(L))
+    C = oracle.clover_term(U, L, 1.3)
+    psi = rng.normal(size=(3, V, 4, 3)) + 1j * rng.normal(size=(3, V, 4, 3))
+    sites = rng.choice(V, size=40, replace=False)
+    lo, hi = (2, 0, 0, 2), (6, 4, 2, 4)
+    full = oracle.apply_D(U, L, kappa, psi, C=C, antiperiodic=bc, lo=lo, hi=hi)
+    assert np.array_equal(oracle.apply_D_sites(U, L, kappa, psi, sites, csw=1.3, antiperiodic=bc, lo=lo, hi=hi),
+                          full[:, sites])
+    bd = oracle.apply_boundary(U, L, psi, lo, hi, antiperiodic=bc)
+    got = oracle.apply_boundary_sites(U, L, psi, sites, lo, hi, antiperiodic=bc)
+    assert np.abs(got - bd[:, sites]).max() < 1e-13 * np.abs(bd).max()
