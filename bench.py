@@ -167,7 +167,11 @@ def main():
     log("base field %s plaquette %.4f (%.1fs)" % (L, inputs.plaquette(U0, L), time.time() - t))
     if args.factorized_only:
         ctx = ddml.Context(L, ddml.BC_ANTIPERIODIC, device=0)
-        out = run_factorized(ctx, ddml, torch, dev, torch.from_numpy(U0).to(dev), L, kappa, csw, args)
+        U0_dev = torch.from_numpy(U0).to(dev)
+        g = ctx.set_gauge(U0_dev, kappa, csw)
+        tune = ctx.autotune(g, ctx.set_domain((0, 0, 0, 0), (16,) + L[1:]), 12, ddml.MIXED_FP32)
+        log("autotune fp32 R=%d order=%d grid=%d splits=%d stage=%d (%.3f ms/pair)" % tune)
+        out = run_factorized(ctx, ddml, torch, dev, U0_dev, L, kappa, csw, args)
         ctx.close()
         print(json.dumps({"factorized_pion": out}), flush=True)
         return 0
@@ -309,6 +313,12 @@ def main():
         log("plain FP64 one-at-a-time: %.3f solves/s" % fp64["solves_per_s"])
 
     # ------------------------------------------------- factorized pion series
+    # the series buffers of the multi-level workload are not needed any more
+    terms.clear()
+    srcs.clear()
+    regions.clear()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     fact = None
     if not args.no_factorized:
         fact = run_factorized(ctx, ddml, torch, dev, U0_dev, L, kappa, csw, args)

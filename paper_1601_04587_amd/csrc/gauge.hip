@@ -45,7 +45,7 @@ __device__ __forceinline__ void lex_coords(const int Lb[4], int s, int y[4]) {
   y[0] = s / Lb[1];
 }
 
-__device__ __forceinline__ int ntiles_of(const BlockSpec& bs) {
+__host__ __device__ __forceinline__ int ntiles_of(const BlockSpec& bs) {
   const int Vh = bs.Lb[0] * bs.Lb[1] * bs.Lb[2] * bs.Lb[3] / 2;
   return (Vh + kTile - 1) / kTile;
 }
@@ -103,45 +103,69 @@ __device__ __forceinline__ void m3(const double2 a[9], bool da, const double2 b[
     }
 }
 
-__device__ __forceinline__ void shift(const int L[4], const int x[4], int mu, int dmu, int nu, int dnu, int y[4]) {
-  for (int m = 0; m < 4; ++m) y[m] = x[m];
-  y[mu] = (y[mu] + dmu + L[mu]) % L[mu];
-  y[nu] = (y[nu] + dnu + L[nu]) % L[nu];
+// y = x + dmu mu + dnu nu (periodic gauge field), without indexing x by mu
+__device__ __forceinline__ void nbr(const int L[4], const int x[4], int mu, int dmu, int nu, int dnu, int y[4]) {
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int v = x[m] + (m == mu ? dmu : 0) + (m == nu ? dnu : 0);
+    y[m] = v < 0 ? v + L[m] : (v >= L[m] ? v - L[m] : v);
+  }
 }
 
-// Fhat_{mu nu}(x) = (Q - Q^dag)/8 with Q the sum of the four counter-clockwise leaves at x
-__device__ void field_strength(const GaugeView& gv, const int L[4], const int x[4], int mu, int nu, double2 F[9]) {
-  double2 Q[9], a[9], b[9], c[9], d[9], t1[9], t2[9], t3[9];
+// acc <- acc U_dir(x + dmu mu + dnu nu)  (or its adjoint)
+__device__ __forceinline__ void leaf_step(const GaugeView& gv, const int L[4], const int x[4], int mu, int dmu,
+                                          int nu, int dnu, int dir, bool dag, double2 acc[9]) {
   int y[4];
+  nbr(L, x, mu, dmu, nu, dnu, y);
+  double2 u[9], t[9];
+  load_link(gv, L, y, dir, u);
+  m3(acc, false, u, dag, t);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = t[k];
+}
+
+// Fhat_{mu nu}(x) = (Q - Q^dag)/8 with Q the sum of the four counter-clockwise
+// leaves at x, each built link by link:
+//   U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
+//   U_nu(x) U_mu(x-mu+nu)^dag U_nu(x-mu)^dag U_mu(x-mu)
+//   U_mu(x-mu)^dag U_nu(x-mu-nu)^dag U_mu(x-mu-nu) U_nu(x-nu)
+//   U_nu(x-nu)^dag U_mu(x-nu) U_nu(x+mu-nu) U_mu(x)^dag
+__device__ __forceinline__ void field_strength(const GaugeView& gv, const int L[4], const int x[4], int mu, int nu,
+                                               double2 F[9]) {
+  double2 Q[9], acc[9];
+#pragma unroll
   for (int k = 0; k < 9; ++k) Q[k] = make_double2(0, 0);
-  // x -> x+mu -> x+mu+nu -> x+nu -> x
-  load_link(gv, L, x, mu, a);
-  shift(L, x, mu, 1, nu, 0, y); load_link(gv, L, y, nu, b);
-  shift(L, x, mu, 0, nu, 1, y); load_link(gv, L, y, mu, c);
-  load_link(gv, L, x, nu, d);
-  m3(a, false, b, false, t1); m3(t1, false, c, true, t2); m3(t2, false, d, true, t3);
-  for (int k = 0; k < 9; ++k) { Q[k].x += t3[k].x; Q[k].y += t3[k].y; }
-  // x -> x+nu -> x+nu-mu -> x-mu -> x
-  load_link(gv, L, x, nu, a);
-  shift(L, x, mu, -1, nu, 1, y); load_link(gv, L, y, mu, b);
-  shift(L, x, mu, -1, nu, 0, y); load_link(gv, L, y, nu, c);
-  load_link(gv, L, y, mu, d);
-  m3(a, false, b, true, t1); m3(t1, false, c, true, t2); m3(t2, false, d, false, t3);
-  for (int k = 0; k < 9; ++k) { Q[k].x += t3[k].x; Q[k].y += t3[k].y; }
-  // x -> x-mu -> x-mu-nu -> x-nu -> x
-  shift(L, x, mu, -1, nu, 0, y); load_link(gv, L, y, mu, a);
-  shift(L, x, mu, -1, nu, -1, y); load_link(gv, L, y, nu, b);
-  load_link(gv, L, y, mu, c);
-  shift(L, x, mu, 0, nu, -1, y); load_link(gv, L, y, nu, d);
-  m3(a, true, b, true, t1); m3(t1, false, c, false, t2); m3(t2, false, d, false, t3);
-  for (int k = 0; k < 9; ++k) { Q[k].x += t3[k].x; Q[k].y += t3[k].y; }
-  // x -> x-nu -> x-nu+mu -> x+mu -> x
-  shift(L, x, mu, 0, nu, -1, y); load_link(gv, L, y, nu, a);
-  load_link(gv, L, y, mu, b);
-  shift(L, x, mu, 1, nu, -1, y); load_link(gv, L, y, nu, c);
-  load_link(gv, L, x, mu, d);
-  m3(a, true, b, false, t1); m3(t1, false, c, false, t2); m3(t2, false, d, true, t3);
-  for (int k = 0; k < 9; ++k) { Q[k].x += t3[k].x; Q[k].y += t3[k].y; }
+#pragma unroll 1
+  for (int leaf = 0; leaf < 4; ++leaf) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[k] = make_double2(k % 4 == 0 ? 1.0 : 0.0, 0.0);
+    if (leaf == 0) {
+      leaf_step(gv, L, x, mu, 0, nu, 0, mu, false, acc);
+      leaf_step(gv, L, x, mu, 1, nu, 0, nu, false, acc);
+      leaf_step(gv, L, x, mu, 0, nu, 1, mu, true, acc);
+      leaf_step(gv, L, x, mu, 0, nu, 0, nu, true, acc);
+    } else if (leaf == 1) {
+      leaf_step(gv, L, x, mu, 0, nu, 0, nu, false, acc);
+      leaf_step(gv, L, x, mu, -1, nu, 1, mu, true, acc);
+      leaf_step(gv, L, x, mu, -1, nu, 0, nu, true, acc);
+      leaf_step(gv, L, x, mu, -1, nu, 0, mu, false, acc);
+    } else if (leaf == 2) {
+      leaf_step(gv, L, x, mu, -1, nu, 0, mu, true, acc);
+      leaf_step(gv, L, x, mu, -1, nu, -1, nu, true, acc);
+      leaf_step(gv, L, x, mu, -1, nu, -1, mu, false, acc);
+      leaf_step(gv, L, x, mu, 0, nu, -1, nu, false, acc);
+    } else {
+      leaf_step(gv, L, x, mu, 0, nu, -1, nu, true, acc);
+      leaf_step(gv, L, x, mu, 0, nu, -1, mu, false, acc);
+      leaf_step(gv, L, x, mu, 1, nu, -1, nu, false, acc);
+      leaf_step(gv, L, x, mu, 0, nu, 0, mu, true, acc);
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      Q[k].x += acc[k].x;
+      Q[k].y += acc[k].y;
+    }
+  }
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -149,138 +173,190 @@ __device__ void field_strength(const GaugeView& gv, const int L[4], const int x[
       F[3 * i + j] = make_double2((Q[3 * i + j].x - Q[3 * j + i].x) * 0.125, (Q[3 * i + j].y + Q[3 * j + i].y) * 0.125);
 }
 
-// In-register inverse of a Hermitian positive definite 6x6 matrix (Cholesky).
-// Returns false if a pivot is not positive.
-__device__ bool herm6_inverse(const double2 A[36], double2 Ai[36]) {
-  double2 Lm[36];
-  double dinv[6];
-  bool ok = true;
-#pragma unroll
-  for (int k = 0; k < 36; ++k) Lm[k] = make_double2(0, 0);
-#pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    double dj = A[6 * j + j].x;
-#pragma unroll
-    for (int k = 0; k < j; ++k) dj -= Lm[6 * j + k].x * Lm[6 * j + k].x + Lm[6 * j + k].y * Lm[6 * j + k].y;
-    if (!(dj > 0)) { ok = false; dj = 1.0; }
-    const double ljj = sqrt(dj);
-    Lm[6 * j + j] = make_double2(ljj, 0);
-    dinv[j] = 1.0 / ljj;
-#pragma unroll
-    for (int i = j + 1; i < 6; ++i) {
-      double2 s = A[6 * i + j];
-#pragma unroll
-      for (int k = 0; k < j; ++k) {
-        const double2 t = dmulc(Lm[6 * j + k], Lm[6 * i + k]);  // L_ik conj(L_jk)
-        s.x -= t.x; s.y -= t.y;
-      }
-      Lm[6 * i + j] = make_double2(s.x * dinv[j], s.y * dinv[j]);
-    }
-  }
-  // W = L^{-1} (lower triangular)
-  double2 W[36];
-#pragma unroll
-  for (int k = 0; k < 36; ++k) W[k] = make_double2(0, 0);
-#pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    W[6 * j + j] = make_double2(dinv[j], 0);
-#pragma unroll
-    for (int i = j + 1; i < 6; ++i) {
-      double2 s = make_double2(0, 0);
-#pragma unroll
-      for (int k = j; k < i; ++k) {
-        const double2 t = dmul(Lm[6 * i + k], W[6 * k + j]);
-        s.x += t.x; s.y += t.y;
-      }
-      W[6 * i + j] = make_double2(-s.x * dinv[i], -s.y * dinv[i]);
-    }
-  }
-  // A^{-1} = W^dag W
-#pragma unroll
-  for (int i = 0; i < 6; ++i)
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      double2 s = make_double2(0, 0);
-#pragma unroll
-      for (int k = (i > j ? i : j); k < 6; ++k) {
-        const double2 t = dmulc(W[6 * k + i], W[6 * k + j]);
-        s.x += t.x; s.y += t.y;
-      }
-      Ai[6 * i + j] = s;
-    }
-  return ok;
-}
+// A Hermitian 6x6 block is kept packed: the real diagonal d[6] and the 15
+// upper elements u[] row-major (row r holds columns r+1..5).
+__device__ __forceinline__ constexpr int up_idx(int r, int c) { return r * (11 - r) / 2 + (c - r - 1); }
+// strictly lower (i > j) packed row-major
+__device__ __forceinline__ constexpr int lo_idx(int i, int j) { return i * (i - 1) / 2 + j; }
 
-// 18 slots of chiral block blk of site i (parity p): 3 packed diagonal pairs,
-// then the 15 upper elements row-major
-template <typename T2>
-__device__ __forceinline__ void store_herm6(const double2 A[36], T2* arr, int nt, int p, int blk, int i) {
-  using T = decltype(T2::x);
-  arr[cidx(nt, p, 18 * blk + 0, i)] = mk<T2>((T)A[0].x, (T)A[7].x);
-  arr[cidx(nt, p, 18 * blk + 1, i)] = mk<T2>((T)A[14].x, (T)A[21].x);
-  arr[cidx(nt, p, 18 * blk + 2, i)] = mk<T2>((T)A[28].x, (T)A[35].x);
-  int k = 3;
-#pragma unroll
-  for (int r = 0; r < 6; ++r)
-#pragma unroll
-    for (int c = r + 1; c < 6; ++c) {
-      arr[cidx(nt, p, 18 * blk + k, i)] = mk<T2>((T)A[6 * r + c].x, (T)A[6 * r + c].y);
-      ++k;
-    }
-}
-
-__global__ void k_build_clover(GaugeView gv, BlockSpec bs, double2* __restrict__ A64, double2* __restrict__ Ainv64,
-                               float2* __restrict__ Ainv32, int* __restrict__ bad) {
+// Clover term of every site of the box, as the two chiral 6x6 blocks of
+//   A = 1 + sum_l s_l (x) X_l^{+-},  X_l^{+-} = i kappa c_sw (+-Fhat_{0l} - B_l),
+// accumulated plane by plane so that only one Fhat and the packed block are
+// live: the (0,l) planes enter X_l with +-1, (2,3) enters X_1 with -1, (1,3)
+// X_2 with +1 (B_2 = Fhat_31 = -Fhat_13) and (1,2) X_3 with -1.  s_3 puts X_3
+// on the diagonal spin blocks with + and -, s_1 and s_2 put X_1 - i X_2 on
+// the upper off-diagonal spin block.
+__global__ void __launch_bounds__(128) k_build_clover(GaugeView gv, BlockSpec bs, double2* __restrict__ A64) {
   const int Vb = bs.Lb[0] * bs.Lb[1] * bs.Lb[2] * bs.Lb[3];
   const int nt = ntiles_of(bs);
-  const double c = bs.kappa * bs.csw;  // X = i c (...)
+  const double c = bs.kappa * bs.csw;
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < Vb; s += gridDim.x * blockDim.x) {
     int y[4], x[4];
     lex_coords(bs.Lb, s, y);
     for (int m = 0; m < 4; ++m) x[m] = bs.lo[m] + y[m];
     const int p = (y[0] + y[1] + y[2] + y[3]) & 1;
     const int i = s >> 1;
-    double2 F0[3][9], B[3][9];
-    if (c != 0.0) {
-      field_strength(gv, bs.L, x, 0, 1, F0[0]);
-      field_strength(gv, bs.L, x, 0, 2, F0[1]);
-      field_strength(gv, bs.L, x, 0, 3, F0[2]);
-      double2 F13[9];
-      field_strength(gv, bs.L, x, 2, 3, B[0]);   // B_1 = F_23
-      field_strength(gv, bs.L, x, 1, 3, F13);    // B_2 = F_31 = -F_13
-      for (int k = 0; k < 9; ++k) B[1][k] = make_double2(-F13[k].x, -F13[k].y);
-      field_strength(gv, bs.L, x, 1, 2, B[2]);   // B_3 = F_12
-    } else {
-      for (int l = 0; l < 3; ++l)
-        for (int k = 0; k < 9; ++k) F0[l][k] = B[l][k] = make_double2(0, 0);
-    }
+#pragma unroll 1
     for (int blk = 0; blk < 2; ++blk) {
       const double sg = blk == 0 ? 1.0 : -1.0;
-      // X_l = i c (sg F_0l - B_l), Hermitian 3x3
-      double2 X[3][9];
-      for (int l = 0; l < 3; ++l)
-        for (int k = 0; k < 9; ++k) {
-          const double re = sg * F0[l][k].x - B[l][k].x, im = sg * F0[l][k].y - B[l][k].y;
-          X[l][k] = make_double2(-c * im, c * re);
+      double dg[6];
+      double2 up[15];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) dg[k] = 1.0;
+#pragma unroll
+      for (int k = 0; k < 15; ++k) up[k] = make_double2(0, 0);
+      if (c != 0.0) {
+#pragma unroll 1
+        for (int pl = 0; pl < 6; ++pl) {
+          const int mu = pl < 3 ? 0 : (pl == 5 ? 1 : (pl == 3 ? 2 : 1));
+          const int nu = pl < 3 ? pl + 1 : (pl == 5 ? 2 : 3);
+          const int l = pl < 3 ? pl : pl - 3;                       // X_{l+1}
+          const double f = pl < 3 ? sg : (pl == 4 ? 1.0 : -1.0);
+          double2 F[9];
+          field_strength(gv, bs.L, x, mu, nu, F);
+          // contribution i c f Fhat to X_{l+1}
+          double2 Z[9];
+#pragma unroll
+          for (int k = 0; k < 9; ++k) Z[k] = make_double2(-c * f * F[k].y, c * f * F[k].x);
+          if (l == 2) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              dg[a] += Z[4 * a].x;
+              dg[3 + a] -= Z[4 * a].x;
+#pragma unroll
+              for (int b2 = a + 1; b2 < 3; ++b2) {
+                const double2 z = Z[3 * a + b2];
+                up[up_idx(a, b2)].x += z.x;
+                up[up_idx(a, b2)].y += z.y;
+                up[up_idx(3 + a, 3 + b2)].x -= z.x;
+                up[up_idx(3 + a, 3 + b2)].y -= z.y;
+              }
+            }
+          } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+              for (int b2 = 0; b2 < 3; ++b2) {
+                const double2 z = Z[3 * a + b2];
+                double2& u = up[up_idx(a, 3 + b2)];
+                if (l == 0) {            // + X_1
+                  u.x += z.x;
+                  u.y += z.y;
+                } else {                 // - i X_2
+                  u.x += z.y;
+                  u.y -= z.x;
+                }
+              }
+          }
         }
-      // block = 1 + s1 X1 + s2 X2 + s3 X3 on (spin, colour)
-      double2 A[36];
-      for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) {
-          const double id = (a == b) ? 1.0 : 0.0;
-          const double2 x1 = X[0][3 * a + b], x2 = X[1][3 * a + b], x3 = X[2][3 * a + b];
-          A[6 * a + b] = make_double2(id + x3.x, x3.y);                       // (0,0): 1 + X3
-          A[6 * (3 + a) + 3 + b] = make_double2(id - x3.x, -x3.y);            // (1,1): 1 - X3
-          A[6 * a + 3 + b] = make_double2(x1.x + x2.y, x1.y - x2.x);          // (0,1): X1 - i X2
-          A[6 * (3 + a) + b] = make_double2(x1.x - x2.y, x1.y + x2.x);        // (1,0): X1 + i X2
-        }
-      double2 Ai[36];
-      const bool ok = herm6_inverse(A, Ai);
-      if (!ok) atomicOr(bad, 1);
-      if (A64) store_herm6<double2>(A, A64, nt, p, blk, i);
-      if (Ainv64) store_herm6<double2>(Ai, Ainv64, nt, p, blk, i);
-      if (Ainv32) store_herm6<float2>(Ai, Ainv32, nt, p, blk, i);
+      }
+      A64[cidx(nt, p, 18 * blk + 0, i)] = make_double2(dg[0], dg[1]);
+      A64[cidx(nt, p, 18 * blk + 1, i)] = make_double2(dg[2], dg[3]);
+      A64[cidx(nt, p, 18 * blk + 2, i)] = make_double2(dg[4], dg[5]);
+#pragma unroll
+      for (int k = 0; k < 15; ++k) A64[cidx(nt, p, 18 * blk + 3 + k, i)] = up[k];
     }
+  }
+}
+
+// Inverse of each packed block by Cholesky A = L L^dag in FP64:
+//   L_jj = sqrt(A_jj - sum_{k<j} |L_jk|^2),  L_ij = (A_ij - sum_{k<j} L_ik conj(L_jk)) / L_jj,
+//   W = L^{-1} (lower),  A^{-1} = W^dag W.
+// One thread per (parity, block, site); a non-positive pivot sets *bad.
+__global__ void __launch_bounds__(128) k_invert_clover(const double2* __restrict__ A64, int nt, int Vh,
+                                                       double2* __restrict__ Ainv64, float2* __restrict__ Ainv32,
+                                                       int* __restrict__ bad) {
+  const size_t n = (size_t)4 * Vh;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(t % Vh);
+    const int pb = (int)(t / Vh);
+    const int p = pb >> 1, blk = pb & 1;
+    double ad[6];
+    double2 au[15];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double2 v = A64[cidx(nt, p, 18 * blk + k, i)];
+      ad[2 * k] = v.x;
+      ad[2 * k + 1] = v.y;
+    }
+#pragma unroll
+    for (int k = 0; k < 15; ++k) au[k] = A64[cidx(nt, p, 18 * blk + 3 + k, i)];
+    double ld[6], dinv[6];
+    double2 lo[15];
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      double dj = ad[j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) dj -= lo[lo_idx(j, k)].x * lo[lo_idx(j, k)].x + lo[lo_idx(j, k)].y * lo[lo_idx(j, k)].y;
+      if (!(dj > 0)) {
+        ok = false;
+        dj = 1.0;
+      }
+      ld[j] = sqrt(dj);
+      dinv[j] = 1.0 / ld[j];
+#pragma unroll
+      for (int r = j + 1; r < 6; ++r) {
+        // A_rj = conj(A_jr) for r > j
+        double2 s2 = make_double2(au[up_idx(j, r)].x, -au[up_idx(j, r)].y);
+#pragma unroll
+        for (int k = 0; k < j; ++k) {
+          const double2 q = dmulc(lo[lo_idx(j, k)], lo[lo_idx(r, k)]);  // L_rk conj(L_jk)
+          s2.x -= q.x;
+          s2.y -= q.y;
+        }
+        lo[lo_idx(r, j)] = make_double2(s2.x * dinv[j], s2.y * dinv[j]);
+      }
+    }
+    if (!ok) atomicOr(bad, 1);
+    // W = L^{-1}: diagonal dinv, strictly lower wo
+    double2 wo[15];
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+#pragma unroll
+      for (int r = j + 1; r < 6; ++r) {
+        double2 s2 = dmul(lo[lo_idx(r, j)], make_double2(dinv[j], 0.0));
+#pragma unroll
+        for (int k = j + 1; k < r; ++k) {
+          const double2 q = dmul(lo[lo_idx(r, k)], wo[lo_idx(k, j)]);
+          s2.x += q.x;
+          s2.y += q.y;
+        }
+        wo[lo_idx(r, j)] = make_double2(-s2.x * dinv[r], -s2.y * dinv[r]);
+      }
+    // (A^{-1})_rc = sum_{k >= max(r,c)} conj(W_kr) W_kc; diagonal real
+    auto w = [&](int k, int j) { return k == j ? make_double2(dinv[j], 0.0) : wo[lo_idx(k, j)]; };
+    double idg[6];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      double acc = 0;
+#pragma unroll
+      for (int k = r; k < 6; ++k) {
+        const double2 v = w(k, r);
+        acc += v.x * v.x + v.y * v.y;
+      }
+      idg[r] = acc;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double2 v = make_double2(idg[2 * k], idg[2 * k + 1]);
+      if (Ainv64) Ainv64[cidx(nt, p, 18 * blk + k, i)] = v;
+      if (Ainv32) Ainv32[cidx(nt, p, 18 * blk + k, i)] = make_float2((float)v.x, (float)v.y);
+    }
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int cc = r + 1; cc < 6; ++cc) {
+        double2 acc = make_double2(0, 0);
+#pragma unroll
+        for (int k = cc; k < 6; ++k) {
+          const double2 q = dmulc(w(k, r), w(k, cc));
+          acc.x += q.x;
+          acc.y += q.y;
+        }
+        if (Ainv64) Ainv64[cidx(nt, p, 18 * blk + 3 + up_idx(r, cc), i)] = acc;
+        if (Ainv32) Ainv32[cidx(nt, p, 18 * blk + 3 + up_idx(r, cc), i)] = make_float2((float)acc.x, (float)acc.y);
+      }
   }
 }
 
@@ -296,7 +372,11 @@ hipError_t launch_build_clover(const GaugeView& gv, const BlockSpec& bs, double2
   const int Vb = bs.Lb[0] * bs.Lb[1] * bs.Lb[2] * bs.Lb[3];
   int grid = (Vb + 127) / 128;
   if (grid > 16384) grid = 16384;
-  hipLaunchKernelGGL(k_build_clover, dim3(grid), dim3(128), 0, st, gv, bs, A64, Ainv64, Ainv32, bad);
+  hipLaunchKernelGGL(k_build_clover, dim3(grid), dim3(128), 0, st, gv, bs, A64);
+  const int Vh = Vb / 2;
+  int grid2 = (4 * Vh + 127) / 128;
+  if (grid2 > 16384) grid2 = 16384;
+  hipLaunchKernelGGL(k_invert_clover, dim3(grid2), dim3(128), 0, st, A64, ntiles_of(bs), Vh, Ainv64, Ainv32, bad);
   return hipGetLastError();
 }
 
@@ -351,10 +431,16 @@ __global__ void k_scatter(const double2* __restrict__ eo, BlockSpec bs, int p, i
 // with the time-boundary phase (antiperiodic -1, open: no such hop).  One
 // thread per (column, site) of the canonical field; sites outside Gamma and
 // inner sites write zero.  Each row of a chiral-basis gamma matrix has a
-// single entry: (gamma_mu psi)_a = ph * psi_{col}.
-__constant__ int kGamCol[4][4] = {{2, 3, 0, 1}, {3, 2, 1, 0}, {3, 2, 1, 0}, {2, 3, 0, 1}};
-__constant__ double kGamRe[4][4] = {{-1, -1, -1, -1}, {0, 0, 0, 0}, {-1, 1, 1, -1}, {0, 0, 0, 0}};
-__constant__ double kGamIm[4][4] = {{0, 0, 0, 0}, {-1, -1, 1, 1}, {0, 0, 0, 0}, {-1, 1, 1, -1}};
+// single entry: (gamma_mu psi)_a = ph_mu(a) psi_{col_mu(a)}, with
+//   col: a ^ 2 for mu = 0, 3 and 3 - a for mu = 1, 2;
+//   ph:  -1 (mu 0); -i, -i, +i, +i (mu 1); -1, +1, +1, -1 (mu 2); -i, +i, +i, -i (mu 3).
+__device__ __forceinline__ constexpr int gam_col(int mu, int a) { return (mu == 0 || mu == 3) ? (a ^ 2) : 3 - a; }
+__device__ __forceinline__ constexpr double gam_re(int mu, int a) {
+  return mu == 0 ? -1.0 : (mu == 2 ? ((a == 0 || a == 3) ? -1.0 : 1.0) : 0.0);
+}
+__device__ __forceinline__ constexpr double gam_im(int mu, int a) {
+  return mu == 1 ? (a < 2 ? -1.0 : 1.0) : (mu == 3 ? ((a == 0 || a == 3) ? -1.0 : 1.0) : 0.0);
+}
 
 __device__ __forceinline__ bool in_box(const BlockSpec& bs, const int x[4]) {
   bool in = true;
@@ -363,7 +449,7 @@ __device__ __forceinline__ bool in_box(const BlockSpec& bs, const int x[4]) {
   return in;
 }
 
-__global__ void k_boundary(GaugeView gv, BlockSpec bs, const double2* __restrict__ in, double2* __restrict__ out,
+__global__ void __launch_bounds__(256) k_boundary(GaugeView gv, BlockSpec bs, const double2* __restrict__ in, double2* __restrict__ out,
                            int nrhs, double scale) {
   const size_t V = (size_t)bs.L[0] * bs.L[1] * bs.L[2] * bs.L[3];
   const size_t n = V * nrhs;
@@ -379,7 +465,9 @@ __global__ void k_boundary(GaugeView gv, BlockSpec bs, const double2* __restrict
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = make_double2(0, 0);
     if (in_box(bs, x)) {
+#pragma unroll
       for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
         for (int d = 1; d >= -1; d -= 2) {
           int y[4] = {x[0], x[1], x[2], x[3]};
           y[mu] += d;
@@ -410,8 +498,8 @@ __global__ void k_boundary(GaugeView gv, BlockSpec bs, const double2* __restrict
             }
 #pragma unroll
           for (int a = 0; a < 4; ++a) {
-            const int b = kGamCol[mu][a];
-            const double gr = kGamRe[mu][a], gi = kGamIm[mu][a];
+            const int b = gam_col(mu, a);
+            const double gr = gam_re(mu, a), gi = gam_im(mu, a);
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
               const double2 v = chi[3 * b + i];
