@@ -70,6 +70,10 @@ template <typename T2> __device__ __forceinline__ T2 cscale(T2 a, decltype(T2::x
 // acc + a b and acc + conj(a) b as four fused multiply-adds
 __device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// acc + s a for a real s, as two fused multiply-adds
+template <typename T2> __device__ __forceinline__ T2 cmas(T2 acc, T2 a, decltype(T2::x) s) {
+  return mk<T2>(fmadd(a.x, s, acc.x), fmadd(a.y, s, acc.y));
+}
 template <typename T2> __device__ __forceinline__ T2 cmac(T2 acc, T2 a, T2 b) {
   acc.x = fmadd(a.x, b.x, acc.x);
   acc.x = fmadd(-a.y, b.y, acc.x);
@@ -187,6 +191,12 @@ __device__ __forceinline__ void st2q(h16c* p, float2 a, float2 b, bool nt) {
   else *(DDML_GLOBAL s16x4*)p = v;
 }
 // One site-column (12 complex, pair k at base + 128 k) in 16-bit storage.
+// a product that is rounded on its own (never fused into a following add), so
+// that a dequantised value is the same number wherever it is used
+__device__ __forceinline__ float mul_rounded(float a, float b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
 __device__ __forceinline__ void spinor_load_q(const h16c* base, float nrm, float2 v[12], bool nt) {
   const float sc = nrm / kQ;
 #pragma unroll
@@ -194,8 +204,8 @@ __device__ __forceinline__ void spinor_load_q(const h16c* base, float nrm, float
     float2 a, b;
     if (nt) ld2q_nt(base + 128 * k, a, b);
     else ld2q(base + 128 * k, a, b);
-    v[2 * k] = make_float2(a.x * sc, a.y * sc);
-    v[2 * k + 1] = make_float2(b.x * sc, b.y * sc);
+    v[2 * k] = make_float2(mul_rounded(a.x, sc), mul_rounded(a.y, sc));
+    v[2 * k + 1] = make_float2(mul_rounded(b.x, sc), mul_rounded(b.y, sc));
   }
 }
 // Stores v with scale max|v| (NaN if any component is not finite) and returns

@@ -16,6 +16,12 @@
 // XCD bands (see ddml_common.hpp) so that neighbour tiles share an L2.
 #include <type_traits>
 
+// No implicit contraction of a multiply and an add into one FMA in this file:
+// every FMA of the stencil is written out (cmac, cmas, fmadd), so each site is
+// computed by the same operations whatever launch variant or tile order the
+// compiler sees around it, and all variants agree bit for bit by construction.
+#pragma clang fp contract(off)
+
 #include "ddml_common.hpp"
 #include "launchers.hpp"
 
@@ -307,19 +313,19 @@ __device__ __forceinline__ void epilogue(const T2* cl, const T2 acc[12], const T
       T2 y[6];
       herm6_apply(m, acc + 6 * b, y);
 #pragma unroll
-      for (int c = 0; c < 6; ++c) out[6 * b + c] = csub(aux[6 * b + c], cscale(y[c], k1));
+      for (int c = 0; c < 6; ++c) out[6 * b + c] = cmas(aux[6 * b + c], y[c], -k1);
     } else if (MODE == MODE_M || MODE == MODE_RES) {
       T2 y[6];
       herm6_apply(m, aux + 6 * b, y);
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
-        T2 v = csub(y[c], cscale(acc[6 * b + c], k1));
+        T2 v = cmas(y[c], acc[6 * b + c], -k1);
         out[6 * b + c] = (MODE == MODE_M) ? cscale(v, k2) : csub(ra[6 * b + c], v);
       }
     } else {  // MODE_PREP: out = C (aux + c1 acc)
       T2 v[6];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) v[c] = cadd(aux[6 * b + c], cscale(acc[6 * b + c], k1));
+      for (int c = 0; c < 6; ++c) v[c] = cmas(aux[6 * b + c], acc[6 * b + c], k1);
       herm6_apply(m, v, out + 6 * b);
     }
   }
@@ -392,19 +398,24 @@ __device__ __forceinline__ void hop_tile(const BoxGeom g, const TileArgs<E>& a, 
       if (RED == RED_DOT) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-          s0.x += (double)ra[c].x * o[c].x + (double)ra[c].y * o[c].y;
-          s0.y += (double)ra[c].x * o[c].y - (double)ra[c].y * o[c].x;
+          const double rx = ra[c].x, ry = ra[c].y, ox = o[c].x, oy = o[c].y;
+          s0.x = fmadd(rx, ox, fmadd(ry, oy, s0.x));
+          s0.y = fmadd(rx, oy, fmadd(-ry, ox, s0.y));
         }
       } else if (RED == RED_TS) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-          s0.x += (double)o[c].x * av[c].x + (double)o[c].y * av[c].y;
-          s0.y += (double)o[c].x * av[c].y - (double)o[c].y * av[c].x;
-          s1.x += (double)o[c].x * o[c].x + (double)o[c].y * o[c].y;
+          const double ox = o[c].x, oy = o[c].y, ax = av[c].x, ay = av[c].y;
+          s0.x = fmadd(ox, ax, fmadd(oy, ay, s0.x));
+          s0.y = fmadd(ox, ay, fmadd(-oy, ax, s0.y));
+          s1.x = fmadd(ox, ox, fmadd(oy, oy, s1.x));
         }
       } else if (RED == RED_NORM) {
 #pragma unroll
-        for (int c = 0; c < 12; ++c) s0.x += (double)o[c].x * o[c].x + (double)o[c].y * o[c].y;
+        for (int c = 0; c < 12; ++c) {
+          const double ox = o[c].x, oy = o[c].y;
+          s0.x = fmadd(ox, ox, fmadd(oy, oy, s0.x));
+        }
       }
     } else {
       // padding sites of the last tile stay zero

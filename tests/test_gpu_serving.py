@@ -152,7 +152,8 @@ def test_every_launch_variant_computes_the_same_bits():
     """The stencil launch (columns per thread, tile order, grid, column splits,
     LDS staging) changes only the schedule: every site and column is computed
     and reduced the same way, so solves agree bit for bit.  A 16^4 box gives
-    planar tile walks (sub-banded orders)."""
+    planar tile walks (sub-banded orders); a 6^4 box has time slices that are
+    not whole tiles (banded fallback walks, a padded last tile)."""
     L = (16, 16, 16, 16)
     U = inputs.random_links(L, 1601077, 0.3)
     ctx = ddml.Context(L, ddml.BC_ANTIPERIODIC)
@@ -160,6 +161,9 @@ def test_every_launch_variant_computes_the_same_bits():
         gid = ctx.set_gauge(U, 0.1200, 1.0)
         dom = ctx.set_domain((4, 0, 0, 0), (10, 16, 16, 16))
         b = inputs.point_source(L, (6, 3, 5, 7))
+        # a box whose time slice (6^3 sites) is not a whole number of 64-site tiles
+        dom2 = ctx.set_domain((2, 2, 2, 2), (8, 8, 8, 8))
+        b2 = inputs.point_source(L, (4, 4, 4, 4))
         variants = {
             ddml.MIXED_FP32: [(1, 1, 1024, 1, 0), (1, 3, 512, 1, 1), (1, 2, 1024, 2, 1), (2, 0, 512, 2, 0),
                               (3, 1, 2048, 1, 1), (1, 0, 1024, 3, 0)],
@@ -170,13 +174,16 @@ def test_every_launch_variant_computes_the_same_bits():
             ref = None
             for v in vs:
                 ctx.set_launch(prec, *v)
-                x = np.zeros_like(b)
-                rc, info = ctx.solve_domain(gid, dom, b, x, 12, ddml.solver_params(tol=1e-10, prec=prec))
-                assert rc == ddml.OK, (prec, v)
+                xs = []
+                for d, src in ((dom, b), (dom2, b2)):
+                    x = np.zeros_like(src)
+                    rc, info = ctx.solve_domain(gid, d, src, x, 12, ddml.solver_params(tol=1e-10, prec=prec))
+                    assert rc == ddml.OK, (prec, v)
+                    xs.append(x)
                 if ref is None:
-                    ref = x
+                    ref = xs
                 else:
-                    assert np.array_equal(x, ref), (prec, v)
+                    assert all(np.array_equal(x, r) for x, r in zip(xs, ref)), (prec, v)
         with pytest.raises(ddml.DDMLError):
             ctx.set_launch(ddml.MIXED_FP16, 1, 1, 1024, 1, 0)      # 16-bit needs the LDS staging
         with pytest.raises(ddml.DDMLError):
