@@ -32,6 +32,16 @@ Contents and the passages they follow:
       (eqs. pipi, W0pc) and its expansion in the overlap thickness Delta
       (eqs. decpi, seriespi, with the rest W^(r) = W - W^(f) of eq. W0pc2).
 
+  * ``hop_power``/``hpe_trace``: the stochastic estimator of the
+      disconnected trace sum_x tr{gamma5 D_Gamma^{-1}(x,x)} per time slice
+      with the hopping parameter expansion (Section 6, eq. HPEtr and the
+      estimator that follows it):
+      (1/n) sum_i sum_x eta_i^dag(x) [(kappa D_hop)^p D_Gamma^{-1} gamma5 eta_i](x),
+      with kappa D_hop = 1 - 2 kappa D (so that the clover term, when present,
+      sits in the site-diagonal part of D_hop).  The identity holds for p <= 8
+      with the Wilson operator and p <= 2 with the clover term (the trace of
+      gamma5 (1 - A)^2 does not vanish).
+
 Time boundary conditions: ``antiperiodic`` is True (antiperiodic), False
 (periodic) or ``OPEN`` (hops across the time boundary dropped, the set-up
 Sections 2 and 5.2 assume).
@@ -421,3 +431,33 @@ def contract_pion(levels, L, full=None):
     diffs = np.concatenate([C[:1], np.diff(C, axis=0)], axis=0)
     rest = None if full is None else pion_connected(full, L) - C[-1]
     return C, diffs, rest
+
+
+# ------------------------------------------- stochastic traces with the HPE
+def hop_power(U, L, kappa, psi, p, C=None, antiperiodic=True, lo=None, hi=None):
+    """(kappa D_hop)^p psi with kappa D_hop = 1 - 2 kappa D_Gamma (Section 6)."""
+    psi = _c(psi)
+    for _ in range(p):
+        psi = psi - 2.0 * kappa * apply_D(U, L, kappa, psi, C=C, antiperiodic=antiperiodic, lo=lo, hi=hi)
+    return psi
+
+
+def apply_gamma5(psi):
+    """gamma5 on the spin index of psi[..., 4, 3]."""
+    return np.einsum("ab,...bc->...ac", gamma5(), _c(psi))
+
+
+def hpe_trace(U, L, kappa, eta, p, C=None, antiperiodic=True, lo=None, hi=None, tol=1e-13):
+    """Per time slice t: (1/n) sum_i sum_{x in slice t} eta_i^dag(x) [(kappa D_hop)^p D_Gamma^{-1} gamma5 eta_i](x)
+    (Section 6, eq. HPEtr and the stochastic estimator after it).
+
+    eta: [n, V, 4, 3] sources (Gaussian noise; unit vectors give the exact
+    trace).  Only the part of each source on Gamma enters the solve; the
+    contraction runs over the whole slice.  Returns a complex array [T]."""
+    L = tuple(L)
+    eta = _c(eta)
+    V3 = int(np.prod(L[1:]))
+    x, _, _ = solve(U, L, kappa, apply_gamma5(eta), C=C, antiperiodic=antiperiodic, lo=lo, hi=hi, tol=tol)
+    phi = hop_power(U, L, kappa, x, p, C=C, antiperiodic=antiperiodic, lo=lo, hi=hi)
+    w = np.einsum("nsac,nsac->s", np.conj(eta), phi)
+    return w.reshape(L[0], V3).sum(axis=1) / eta.shape[0]
