@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-factorized", action="store_true", help="skip the factorized pion leg")
+    ap.add_argument("--no-hpe", action="store_true", help="skip the stochastic trace leg")
+    ap.add_argument("--hpe-sources", type=int, default=24, help="Gaussian sources per domain (stochastic traces)")
     ap.add_argument("--factorized-only", action="store_true",
                     help="only the factorized pion leg (profiling runs)")
     ap.add_argument("--serve-requests", type=int, default=64, help="requests per serving stream")
@@ -322,6 +324,9 @@ def main():
     fact = None
     if not args.no_factorized:
         fact = run_factorized(ctx, ddml, torch, dev, U0_dev, L, kappa, csw, args)
+    hpe = None
+    if not args.no_hpe:
+        hpe = run_hpe(ctx, ddml, torch, dev, gid0, L, args)
 
     # ------------------------------------------------------------ serving
     serve = None
@@ -363,6 +368,7 @@ def main():
         "mixed_over_fp64": (solves_per_s / fp64["solves_per_s"]) if fp64 else None,
         "serving": serve,
         "factorized_pion": fact,
+        "stochastic_traces": hpe,
         "inner_iters_per_solve": iters,
         "worst_true_rel_residual": worst,
         "cpu_baseline": cpu,
@@ -496,6 +502,43 @@ def run_factorized(ctx, ddml, torch, dev, U0_dev, L, kappa, csw, args):
            "C_rest": {str(y): float(rest[y]) for y in ys}}
     log("factorized pion: %s" % out)
     return out
+
+
+def run_hpe(ctx, ddml, torch, dev, gid, L, args):
+    """Section 6 workload: the disconnected traces on the two halves
+    Gamma_A = [0, T/2), Gamma_B = [T/2, T) of the base field (clover, so the
+    hopping parameter expansion goes to p = 2), from Gaussian sources over the
+    volume drawn on the device with a seeded generator; 12 sources per solve.
+    Timed: the solves, the 2 x p FP64 operator applications and the
+    contractions of both domains."""
+    T = L[0]
+    V = int(np.prod(L))
+    n = args.hpe_sources
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(1601601)
+    eta = torch.complex(torch.randn((n, V, 4, 3), generator=gen, device=dev, dtype=torch.float64),
+                        torch.randn((n, V, 4, 3), generator=gen, device=dev, dtype=torch.float64)) / np.sqrt(2.0)
+    doms = [ctx.set_domain((0, 0, 0, 0), (T // 2,) + tuple(L[1:])), ctx.set_domain((T // 2, 0, 0, 0), tuple(L))]
+    prm = ddml.solver_params(tol=1e-10)
+    ctx.hpe_trace(gid, doms[0], eta[:12].contiguous(), 12, 2, prm)   # warm-up
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    outs, iters = [], []
+    for d in doms:
+        rc, out, info = ctx.hpe_trace(gid, d, eta, n, 2, prm)
+        assert rc == ddml.OK, "stochastic trace failed: %s" % ctx.last_error()
+        outs.append(out)
+        iters.append(max(x.inner_iters for x in info))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - a
+    ys = [1, T // 4, T // 2 - 2, T // 2 + 1, 3 * T // 4, T - 2]
+    res = {"lattice": list(L), "domains": "t in [0, %d) and [%d, %d)" % (T // 2, T // 2, T), "sources": n, "p": 2,
+           "nrhs_per_solve": 12, "tol": 1e-10, "s": el, "sources_per_s": 2 * n / el,
+           "domain_solves_per_s": 2 * ((n + 11) // 12) / el, "max_inner_iters": iters,
+           "trace_p0": {str(y): [outs[y >= T // 2][0][y].real, outs[y >= T // 2][0][y].imag] for y in ys},
+           "trace_hpe": {str(y): [outs[y >= T // 2][1][y].real, outs[y >= T // 2][1][y].imag] for y in ys}}
+    log("stochastic traces: %s" % res)
+    return res
 
 
 def cpu_baseline(U0, L, kappa, csw, seconds):

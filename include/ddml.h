@@ -16,6 +16,8 @@
  *     W^(r2) (Section 3, eqs. W0, rall0, rall) and the nucleon contraction
  *     W_N1 - W_N2 (Section 5.2, eq. baryfact) summed over sink time slices
  *     (eq. baryN).
+ *   - Stochastic disconnected traces with the hopping parameter expansion
+ *     (Section 6, eq. HPEtr).
  *   - The two-domain factorized propagator S^(f) = -D_{Gamma*}^{-1}
  *     D_{dGamma*} D_{Gammabar}^{-1} (Section 5.2, eq. approxlong) and the
  *     connected pion correlator built from it (eqs. pipi, W0pc, decpi,
@@ -281,6 +283,27 @@ int ddml_factorized_series(ddml_ctx ctx, int gauge_id, const int* bar_ids, int n
  * Sums run in a fixed order.  Errors: EINVAL, EDEVICE. */
 int ddml_contract_pion(ddml_ctx ctx, const double* levels, int nlevels, const double* full, double* levels_out,
                        double* diffs_out, double* rest_out, int on_device, void* stream);
+
+/* Stochastic estimate of the disconnected trace with the hopping parameter
+ * expansion (Section 6, eq. HPEtr and the estimator that follows it), per
+ * time slice t of the gauge field's lattice:
+ *   out[0][t] = (1/nsrc) sum_i sum_{x in slice t} eta_i^dag(x) [D_Gamma^{-1} gamma5 eta_i](x)
+ *   out[1][t] = (1/nsrc) sum_i sum_{x in slice t} eta_i^dag(x) [(kappa D_hop)^p D_Gamma^{-1} gamma5 eta_i](x)
+ * with kappa D_hop = 1 - 2 kappa D_Gamma (the clover term sits in its site
+ * diagonal).  Both estimate sum_x tr{gamma5 D_Gamma^{-1}(x,x)}; the second has
+ * the smaller variance.  p: 0..8 without the clover term, 0..2 with it (the
+ * range in which the expansion's lower orders have zero trace); else EINVAL.
+ *   eta      [nsrc][V][4][3] sources (e.g. Gaussian noise; unit vectors give
+ *            the exact trace); only their part on Gamma enters the solves
+ *   out      [2][T] complex, host
+ *   psi_out  [nsrc][V][4][3] or NULL: D_Gamma^{-1} gamma5 eta
+ *   phi_out  [nsrc][V][4][3] or NULL: (kappa D_hop)^p D_Gamma^{-1} gamma5 eta
+ *   info     [nsrc]: the solve of each source (12 sources per solve, the
+ *            solves batched as ddml_solve_batch)
+ * Errors: EINVAL, ENOMEM, ENOTCONVERGED (out still written), EDEVICE. */
+int ddml_hpe_trace(ddml_ctx ctx, int gauge_id, int dom_id, const double* eta, int nsrc, int p,
+                   const ddml_solver_params* params, double* out, double* psi_out, double* phi_out,
+                   ddml_rhs_info* info, int on_device, void* stream);
 
 /* Measurement hook for the dominant kernels: times `iters` back-to-back
  * applications of the two half-stencils of the even-odd Schur operator, as

@@ -1,4 +1,5 @@
 // C ABI of libddml (declarations and documentation in include/ddml.h).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -415,6 +416,83 @@ int ddml_contract_pion(ddml_ctx ctx, const double* levels, int nlevels, const do
     DDML_HIP(hipStreamSynchronize(c->stream));
     sj.done();
     return DDML_OK;
+  });
+}
+
+// Stochastic traces with the hopping parameter expansion: solves of gamma5 eta
+// (12 sources per solve, batched), p FP64 applications of 1 - 2 kappa D_Gamma,
+// and the per-slice contractions with eta before and after them.
+int ddml_hpe_trace(ddml_ctx ctx, int gauge_id, int dom_id, const double* eta, int nsrc, int p,
+                   const ddml_solver_params* params, double* out, double* psi_out, double* phi_out,
+                   ddml_rhs_info* info, int on_device, void* stream) {
+  return guarded(ctx, [&](Ctx* c) {
+    need(eta && out && info, "NULL argument");
+    need(nsrc >= 1, "nsrc must be >= 1");
+    check_params(params);
+    const GaugeRec& g = gauge_get(c, gauge_id);
+    const int pmax = g.csw != 0.0 ? 2 : 8;
+    need(p >= 0 && p <= pmax, "p must be in 0..8 without and 0..2 with the clover term");
+    if (dom_id != -1) (void)domain_get(c, dom_id);
+    const size_t V = g.V;
+    const int T = g.lat.dims[0];
+    const double kappa = g.kappa;
+    const size_t per = V * 12;  // complex numbers of one source
+    const size_t bytes = (size_t)nsrc * per * sizeof(double2);
+    StreamJoin sj(c, stream);
+    Staged se = stage_in(c, eta, bytes, on_device);
+    DBuf g5(c->pool.get(), bytes);
+    Staged sp, sf;
+    if (psi_out) sp = stage_out(c, psi_out, bytes, on_device);
+    else sp.buf = DBuf(c->pool.get(), bytes), sp.ptr = sp.buf.as<double>();
+    if (phi_out) sf = stage_out(c, phi_out, bytes, on_device);
+    else sf.buf = DBuf(c->pool.get(), bytes), sf.ptr = sf.buf.as<double>();
+    DDML_HIP(launch_gamma5(reinterpret_cast<const double2*>(se.cptr), g5.as<double2>(), (size_t)nsrc * V, c->stream));
+    // solves of 12 sources at a time: the full groups as one batch, the rest as another
+    const int nfull = nsrc / kMaxRhs, rest = nsrc - nfull * kMaxRhs;
+    int rc = DDML_OK;
+    for (int part = 0; part < 2; ++part) {
+      std::vector<ddml_solve_desc> d;
+      const int cols = part == 0 ? kMaxRhs : rest;
+      const int ng = part == 0 ? nfull : (rest > 0 ? 1 : 0);
+      for (int k = 0; k < ng; ++k) {
+        const size_t first = (size_t)(part == 0 ? k * kMaxRhs : nfull * kMaxRhs);
+        d.push_back(ddml_solve_desc{gauge_id, dom_id, g5.as<double>() + 2 * per * first,
+                                    sp.ptr + 2 * per * first, cols, info + first});
+      }
+      if (!d.empty()) {
+        const int r = solve_many(c, (int)d.size(), d.data(), params, 1, c->stream);
+        if (rc == DDML_OK) rc = r;
+      }
+    }
+    DBuf W(c->pool.get(), V * sizeof(double2)), sums(c->pool.get(), 2 * (size_t)T * sizeof(double2));
+    DDML_HIP(launch_noise_trace(reinterpret_cast<const double2*>(se.cptr), reinterpret_cast<const double2*>(sp.ptr),
+                                nsrc, V, T, W.as<double2>(), sums.as<double2>(), c->stream));
+    // phi = (1 - 2 kappa D_Gamma)^p psi, 12 sources at a time
+    DDML_HIP(hipMemcpyAsync(sf.ptr, sp.ptr, bytes, hipMemcpyDeviceToDevice, c->stream));
+    if (p > 0) {
+      DBuf tmp(c->pool.get(), (size_t)kMaxRhs * per * sizeof(double2));
+      for (int step = 0; step < p; ++step)
+        for (int first = 0; first < nsrc; first += kMaxRhs) {
+          const int cols = std::min(kMaxRhs, nsrc - first);
+          double* ph = sf.ptr + 2 * per * first;
+          apply_D(c, gauge_id, dom_id, ph, tmp.as<double>(), cols, c->stream);
+          DDML_HIP(launch_axpy_d(reinterpret_cast<double2*>(ph), tmp.as<double2>(), -2.0 * kappa, (size_t)cols * per,
+                                 c->stream));
+        }
+    }
+    DDML_HIP(launch_noise_trace(reinterpret_cast<const double2*>(se.cptr), reinterpret_cast<const double2*>(sf.ptr),
+                                nsrc, V, T, W.as<double2>(), sums.as<double2>() + T, c->stream));
+    std::vector<double2> h(2 * (size_t)T);
+    DDML_HIP(hipMemcpyAsync(h.data(), sums.p, h.size() * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
+    if (psi_out) copy_back(c, psi_out, sp, bytes, on_device);
+    if (phi_out) copy_back(c, phi_out, sf, bytes, on_device);
+    DDML_HIP(hipStreamSynchronize(c->stream));
+    for (size_t k = 0; k < h.size(); ++k) {
+      out[2 * k] = h[k].x / nsrc;
+      out[2 * k + 1] = h[k].y / nsrc;
+    }
+    sj.done();
+    return rc;
   });
 }
 

@@ -13,6 +13,9 @@
 //    the sum of |S|^2 over the 144 entries at the sink, summed per time slice
 //    and scaled by -1/L^3; series differences (eq. seriespi) and the rest
 //    against the full propagator (eq. W0pc2).
+//  * Stochastic traces (Section 6, eq. HPEtr and the estimator after it):
+//    gamma5 on the sources, and sum_i sum_c conj(eta_i(x)_c) phi_i(x)_c per
+//    site (sources, then components, in order) before the slice sums.
 // In the chiral basis C = diag(s_2, -s_2), so C g5 = diag(s_2, s_2), and
 // P_- = [[1,1],[1,1]]/2 in 2x2 spin blocks; both are applied in closed form below.
 #include "ddml_common.hpp"
@@ -257,6 +260,50 @@ hipError_t launch_pion(const double2* props, size_t V, int T, int nprops, double
 hipError_t launch_pion_fin(const double2* sums, int nlevels, int T, int has_full, double invL3, double* out,
                            hipStream_t st) {
   hipLaunchKernelGGL(k_pion_fin, dim3(1), dim3(256), 0, st, sums, nlevels, T, has_full, invL3, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- stochastic traces
+// out = gamma5 in for n sites of canonical spinors (gamma5 = diag(1, 1, -1, -1))
+__global__ void k_gamma5(const double2* __restrict__ in, double2* __restrict__ out, size_t n) {
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n * 12; k += (size_t)gridDim.x * blockDim.x) {
+    const double2 v = in[k];
+    const int comp = (int)(k % 12);
+    out[k] = comp < 6 ? v : make_double2(-v.x, -v.y);
+  }
+}
+
+__global__ void k_noise_dot(const double2* __restrict__ eta, const double2* __restrict__ phi, int nsrc, size_t V,
+                            double2* __restrict__ W) {
+  for (size_t y = blockIdx.x * (size_t)blockDim.x + threadIdx.x; y < V; y += (size_t)gridDim.x * blockDim.x) {
+    double2 w = make_double2(0, 0);
+    for (int i = 0; i < nsrc; ++i) {
+      const double2* e = eta + ((size_t)i * V + y) * 12;
+      const double2* f = phi + ((size_t)i * V + y) * 12;
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        const double2 a = e[c], b = f[c];
+        w.x += a.x * b.x + a.y * b.y;
+        w.y += a.x * b.y - a.y * b.x;
+      }
+    }
+    W[y] = w;
+  }
+}
+
+hipError_t launch_gamma5(const double2* in, double2* out, size_t nsites, hipStream_t st) {
+  size_t g = (nsites * 12 + 255) / 256;
+  if (g > 16384) g = 16384;
+  hipLaunchKernelGGL(k_gamma5, dim3((unsigned)g), dim3(256), 0, st, in, out, nsites);
+  return hipGetLastError();
+}
+
+hipError_t launch_noise_trace(const double2* eta, const double2* phi, int nsrc, size_t V, int T, double2* W,
+                              double2* sums, hipStream_t st) {
+  size_t g = (V + 255) / 256;
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_noise_dot, dim3((unsigned)g), dim3(256), 0, st, eta, phi, nsrc, V, W);
+  hipLaunchKernelGGL(k_slice_sum, dim3(T, 1), dim3(256), 0, st, W, V, T, sums);
   return hipGetLastError();
 }
 

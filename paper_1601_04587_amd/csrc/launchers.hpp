@@ -109,6 +109,11 @@ hipError_t launch_pion(const double2* props, size_t V, int T, int nprops, double
 // propagator's) the rest; out: [2 * nlevels + 1][T] = levels, diffs, rest
 hipError_t launch_pion_fin(const double2* sums, int nlevels, int T, int has_full, double invL3, double* out,
                            hipStream_t st);
+// gamma5 on nsites canonical spinors; noise trace: W scratch [V], sums [T] of
+// sum_i eta_i^dag(x) phi_i(x) over the sites of each time slice
+hipError_t launch_gamma5(const double2* in, double2* out, size_t nsites, hipStream_t st);
+hipError_t launch_noise_trace(const double2* eta, const double2* phi, int nsrc, size_t V, int T, double2* W,
+                              double2* sums, hipStream_t st);
 // W: scratch [nlevels][V]; out: [nlevels][T]
 hipError_t launch_nucleon(const double2* terms, size_t V, int T, int nlevels, double2* W, double2* out,
                           hipStream_t st);

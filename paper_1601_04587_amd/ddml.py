@@ -69,7 +69,8 @@ EXPORTS = ["ddml_create", "ddml_destroy", "ddml_last_error", "ddml_set_gauge", "
            "ddml_set_gauge_region",
            "ddml_release_gauge", "ddml_set_domain", "ddml_apply_Dw", "ddml_apply_eo", "ddml_solve_domain",
            "ddml_solve_batch", "ddml_propagator_series", "ddml_propagator_series_batch", "ddml_time_stencil", "ddml_autotune", "ddml_set_launch", "ddml_contract_pp_disconnected", "ddml_contract_nucleon",
-           "ddml_apply_boundary", "ddml_factorized_series", "ddml_contract_pion", "ddml_server_start", "ddml_submit", "ddml_poll", "ddml_wait", "ddml_stats", "ddml_server_stop",
+           "ddml_apply_boundary", "ddml_factorized_series", "ddml_contract_pion", "ddml_hpe_trace",
+           "ddml_server_start", "ddml_submit", "ddml_poll", "ddml_wait", "ddml_stats", "ddml_server_stop",
            "ddml_now"]
 
 _lib = None
@@ -111,6 +112,8 @@ def load():
     lib.ddml_factorized_series.argtypes = [P, I, IP, I, I, P, I, ctypes.POINTER(SolverParams), P, P,
                                            ctypes.POINTER(RhsInfo), I, P]
     lib.ddml_contract_pion.argtypes = [P, P, I, P, P, P, P, I, P]
+    lib.ddml_hpe_trace.argtypes = [P, I, I, P, I, I, ctypes.POINTER(SolverParams), P, P, P,
+                                   ctypes.POINTER(RhsInfo), I, P]
     lib.ddml_server_start.argtypes = [P, ctypes.POINTER(SolverParams), I]
     lib.ddml_submit.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
     lib.ddml_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Result)]
@@ -166,6 +169,7 @@ class Context:
         self.lib = load()
         self.dims = tuple(int(d) for d in dims)
         self.V = int(np.prod(self.dims))
+        self.gauge_dims = {}   # host lattice of fields set with set_gauge_lattice
         lat = Lattice((ctypes.c_int * 4)(*self.dims), bc_time)
         h = ctypes.c_void_p()
         rc = self.lib.ddml_create(ctypes.byref(h), ctypes.byref(lat), device, hbm_budget)
@@ -205,12 +209,15 @@ class Context:
         gid = ctypes.c_int()
         lat = Lattice((ctypes.c_int * 4)(*[int(v) for v in dims]), bc_time)
         self._check(self.lib.ddml_set_gauge_lattice(self.h, ctypes.byref(lat), p, dev, kappa, csw, ctypes.byref(gid)))
+        self.gauge_dims[gid.value] = tuple(int(v) for v in dims)
         return gid.value
 
     def set_gauge_region(self, base, t0, t1, U_region):
         p, dev = _ptr(U_region)
         gid = ctypes.c_int()
         self._check(self.lib.ddml_set_gauge_region(self.h, base, t0, t1, p, dev, ctypes.byref(gid)))
+        if base in self.gauge_dims:
+            self.gauge_dims[gid.value] = self.gauge_dims[base]
         return gid.value
 
     def release_gauge(self, gid):
@@ -319,6 +326,21 @@ class Context:
         self._check(rc, allow=(ENOTCONVERGED, ENUMERIC))
         return rc, [(list(info[(2 * i) * nrhs:(2 * i + 1) * nrhs]), list(info[(2 * i + 1) * nrhs:(2 * i + 2) * nrhs]))
                     for i in range(n)]
+
+    def hpe_trace(self, gid, dom, eta, nsrc, p, params=None, psi_out=None, phi_out=None):
+        """Stochastic trace estimates per time slice without and with the hopping
+        parameter expansion; returns (rc, out [2, T] complex, infos)."""
+        params = params or solver_params()
+        T = self.gauge_dims.get(gid, self.dims)[0]
+        out = np.zeros((2, T), dtype=np.complex128)
+        info = (RhsInfo * nsrc)()
+        pe, dev = _ptr(eta)
+        pp = _ptr(psi_out)[0] if psi_out is not None else None
+        pf = _ptr(phi_out)[0] if phi_out is not None else None
+        rc = self.lib.ddml_hpe_trace(self.h, gid, dom, pe, nsrc, p, ctypes.byref(params), out.ctypes.data, pp, pf,
+                                     info, dev, _stream(eta))
+        self._check(rc, allow=(ENOTCONVERGED, ENUMERIC))
+        return rc, out, list(info)
 
     def time_stencil(self, gid, dom, nrhs, prec=MIXED_FP32, iters=20, R=0, order=-1, grid=0, splits=0, stage=-1):
         """(ms_odd_half, ms_even_half, bytes_odd_half, bytes_even_half) per launch."""
