@@ -42,6 +42,14 @@ Contents and the passages they follow:
       with the Wilson operator and p <= 2 with the clover term (the trace of
       gamma5 (1 - A)^2 does not vanish).
 
+  * ``inverse_iteration``/``gram_slices``/``projected_pion``: the
+      projector-cut factorization (Section 5.2, eqs. approxlong2, fullfactpi,
+      Bpions): basis vectors from inverse iterations of D on a domain, each
+      iterate orthonormalised (Q of the QR factorisation with positive real
+      diagonal R), per-slice Gram matrices of chi = D_Gammabar^{-1} gamma5 phi
+      and eta = D_Gamma*^{-1} D_dGamma* phi, and C(y0, x0) =
+      -(1/L^3) Re Tr(Gt(y0) G(x0)).
+
 Time boundary conditions: ``antiperiodic`` is True (antiperiodic), False
 (periodic) or ``OPEN`` (hops across the time boundary dropped, the set-up
 Sections 2 and 5.2 assume).
@@ -461,3 +469,49 @@ def hpe_trace(U, L, kappa, eta, p, C=None, antiperiodic=True, lo=None, hi=None, 
     phi = hop_power(U, L, kappa, x, p, C=C, antiperiodic=antiperiodic, lo=lo, hi=hi)
     w = np.einsum("nsac,nsac->s", np.conj(eta), phi)
     return w.reshape(L[0], V3).sum(axis=1) / eta.shape[0]
+
+
+# ------------------------------------------------ projector-cut factorization
+def orthonormal_q(X):
+    """Q of X = Q R with R upper triangular and real positive diagonal (columns
+    of X are the fields: X[n, V, 4, 3]); numpy's QR, phases fixed."""
+    n = X.shape[0]
+    M = _c(X).reshape(n, -1).T
+    Q, R = np.linalg.qr(M)
+    d = np.diag(R)
+    Q = Q * (np.abs(d) / d)[None, :]
+    return Q.T.reshape(X.shape)
+
+
+def inverse_iteration(U, L, kappa, start, niter, C=None, antiperiodic=True, lo=None, hi=None, tol=1e-13):
+    """v <- orth(D_Gamma^{-1} v), niter times, from start[n, V, 4, 3]
+    (Section 5.2: basis vectors by inverse iteration on a domain)."""
+    v = _c(start)
+    for _ in range(niter):
+        x, _, _ = solve(U, L, kappa, v, C=C, antiperiodic=antiperiodic, lo=lo, hi=hi, tol=tol)
+        v = orthonormal_q(x)
+    return v
+
+
+def gram_slices(X, L):
+    """G[t]_ij = sum_{x in slice t} X_i(x)^dag X_j(x) for fields X[n, V, 4, 3]."""
+    L = tuple(L)
+    X = _c(X)
+    n = X.shape[0]
+    Y = X.reshape(n, L[0], -1)
+    return np.einsum("itk,jtk->tij", np.conj(Y), Y)
+
+
+def projected_pion(U, L, kappa, phi, bar, star, C=None, antiperiodic=True, tol=1e-13):
+    """-(1/L^3) Re Tr(Gt(y0) G(x0)) [T, T] with G from chi = D_Gammabar^{-1} gamma5 phi
+    and Gt from eta = D_Gamma*^{-1} D_dGamma* phi (eqs. approxlong2, fullfactpi, Bpions).
+    Returns (C, G, Gt)."""
+    L = tuple(L)
+    chi, _, _ = solve(U, L, kappa, apply_gamma5(phi), C=C, antiperiodic=antiperiodic, lo=bar[0], hi=bar[1], tol=tol)
+    eta, _, _ = solve(U, L, kappa, apply_boundary(U, L, phi, star[0], star[1], antiperiodic), C=C,
+                      antiperiodic=antiperiodic, lo=star[0], hi=star[1], tol=tol)
+    G = gram_slices(chi, L)
+    Gt = gram_slices(eta, L)
+    V3 = int(np.prod(L[1:]))
+    Cm = -np.einsum("yij,xji->yx", Gt, G).real / V3
+    return Cm, G, Gt
