@@ -70,6 +70,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-factorized", action="store_true", help="skip the factorized pion leg")
     ap.add_argument("--no-hpe", action="store_true", help="skip the stochastic trace leg")
+    ap.add_argument("--no-projected", action="store_true", help="skip the projector-cut pion leg")
+    ap.add_argument("--proj-vectors", type=int, default=24, help="basis vectors of the projector-cut leg")
+    ap.add_argument("--proj-iters", type=int, default=4, help="inverse iterations of the projector-cut leg")
     ap.add_argument("--hpe-sources", type=int, default=24, help="Gaussian sources per domain (stochastic traces)")
     ap.add_argument("--factorized-only", action="store_true",
                     help="only the factorized pion leg (profiling runs)")
@@ -327,6 +330,9 @@ def main():
     hpe = None
     if not args.no_hpe:
         hpe = run_hpe(ctx, ddml, torch, dev, gid0, L, args)
+    proj = None
+    if not args.no_projected:
+        proj = run_projected(ctx, ddml, torch, dev, U0_dev, L, kappa, csw, args)
 
     # ------------------------------------------------------------ serving
     serve = None
@@ -369,6 +375,7 @@ def main():
         "serving": serve,
         "factorized_pion": fact,
         "stochastic_traces": hpe,
+        "projected_pion": proj,
         "inner_iters_per_solve": iters,
         "worst_true_rel_residual": worst,
         "cpu_baseline": cpu,
@@ -538,6 +545,53 @@ def run_hpe(ctx, ddml, torch, dev, gid, L, args):
            "trace_p0": {str(y): [outs[y >= T // 2][0][y].real, outs[y >= T // 2][0][y].imag] for y in ys},
            "trace_hpe": {str(y): [outs[y >= T // 2][1][y].real, outs[y >= T // 2][1][y].imag] for y in ys}}
     log("stochastic traces: %s" % res)
+    return res
+
+
+def run_projected(ctx, ddml, torch, dev, U0_dev, L, kappa, csw, args):
+    """Section 5.2 projector-cut workload on the base field with open time
+    boundaries: n basis vectors from inverse iterations on
+    Omega* = [x0cut - 8, x0cut + 8) (Gaussian start from a seeded device
+    generator), then chi = D_Gammabar^{-1} gamma5 phi, eta = D_Gamma*^{-1} D_d phi,
+    the per-slice Gram matrices (rocBLAS ZGEMM, batched over slices) and
+    C(y0, x0) = -(1/L^3) Tr(Gt(y0) G(x0)); x0cut = 24, Gammabar = [0, 32),
+    Gamma* = [24, 64)."""
+    T = L[0]
+    xcut = 24 if T >= 48 else T // 2
+    d = 8 if T >= 48 else max(2, T // 8)
+    V = int(np.prod(L))
+    n = args.proj_vectors
+    gid = ctx.set_gauge_lattice(L, U0_dev, kappa, csw, bc_time=ddml.BC_OPEN)
+    om = ctx.set_domain((xcut - d, 0, 0, 0), (xcut + d,) + tuple(L[1:]))
+    bar = ctx.set_domain((0, 0, 0, 0), (xcut + d,) + tuple(L[1:]))
+    star = ctx.set_domain((xcut, 0, 0, 0), tuple(L))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(1601901)
+    start = torch.complex(torch.randn((n, V, 4, 3), generator=gen, device=dev, dtype=torch.float64),
+                          torch.randn((n, V, 4, 3), generator=gen, device=dev, dtype=torch.float64))
+    phi = torch.zeros_like(start)
+    prm = ddml.solver_params(tol=1e-10)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    rc, info = ctx.inverse_iteration(gid, om, start, n, args.proj_iters, phi, prm)
+    assert rc == ddml.OK, "inverse iteration failed: %s" % ctx.last_error()
+    torch.cuda.synchronize()
+    b = time.perf_counter()
+    rc, Cm, _, info2 = ctx.projected_pion(gid, bar, star, phi, n, prm)
+    assert rc == ddml.OK, "projected pion failed: %s" % ctx.last_error()
+    torch.cuda.synchronize()
+    c = time.perf_counter()
+    ctx.release_gauge(gid)
+    x0 = 4 if xcut > 4 else 0
+    ys = [y for y in (xcut, xcut + 8, xcut + 16, xcut + 24, T - 1) if y < T]
+    res = {"lattice": list(L), "bc_time": "open", "vectors": n, "inverse_iterations": args.proj_iters,
+           "omega": [xcut - d, xcut + d], "gammabar": [0, xcut + d], "gamma_star": [xcut, T],
+           "s_inverse_iteration": b - a, "s_projected_pion": c - b,
+           "vector_solves_per_s": (args.proj_iters * n + 2 * n) / (c - a),
+           "max_inner_iters": {"inverse_iteration_last": max(x.inner_iters for x in info),
+                               "projected": max(x.inner_iters for x in info2)},
+           "C_y0_x0=%d" % x0: {str(y): float(Cm[y, x0]) for y in ys}}
+    log("projected pion: %s" % res)
     return res
 
 

@@ -21,7 +21,8 @@
  *   - The two-domain factorized propagator S^(f) = -D_{Gamma*}^{-1}
  *     D_{dGamma*} D_{Gammabar}^{-1} (Section 5.2, eq. approxlong) and the
  *     connected pion correlator built from it (eqs. pipi, W0pc, decpi,
- *     seriespi).
+ *     seriespi), and its projector-cut form with inverse-iteration basis
+ *     vectors (eqs. approxlong2, fullfactpi, Bpions).
  *
  * Canonical layouts at this boundary (all complex numbers are interleaved
  * (re, im) doubles):
@@ -304,6 +305,42 @@ int ddml_contract_pion(ddml_ctx ctx, const double* levels, int nlevels, const do
 int ddml_hpe_trace(ddml_ctx ctx, int gauge_id, int dom_id, const double* eta, int nsrc, int p,
                    const ddml_solver_params* params, double* out, double* psi_out, double* phi_out,
                    ddml_rhs_info* info, int on_device, void* stream);
+
+/* Basis vectors of the projector-cut factorization (Section 5.2, after eq.
+ * approxlong2): nvec vectors on the domain Omega (dom_id) from niter inverse
+ * iterations of D_Omega, each followed by orthonormalisation:
+ *   v <- Q,  D_Omega^{-1} v = Q R  (Q^dag Q = 1, R upper triangular with
+ *                                   positive real diagonal: Cholesky QR, twice)
+ * starting from `start`.  The orthonormalisation runs over the time slices of
+ * Omega (a time slab in the paper's use).  The solves take 12 vectors at a
+ * time, batched.
+ *   start, out [nvec][V][4][3] (not overlapping); out holds the last Q
+ *   info [nvec]: the solves of the last iteration
+ * nvec 1..1024, niter >= 1.  Errors: EINVAL, ENOMEM, ENOTCONVERGED,
+ * ENUMERIC (dependent vectors), EDEVICE. */
+int ddml_inverse_iteration(ddml_ctx ctx, int gauge_id, int dom_id, const double* start, int nvec, int niter,
+                           const ddml_solver_params* params, double* out, ddml_rhs_info* info, int on_device,
+                           void* stream);
+
+/* Connected pion with the projector-cut propagator (Section 5.2, eqs.
+ * approxlong2, fullfactpi, Bpions): for orthonormal phi_1..phi_n,
+ *   chi_j = D_Gammabar^{-1} gamma5 phi_j,   eta_j = D_Gamma*^{-1} D_dGamma* phi_j,
+ *   G(x0)_ij  = sum_{x in slice x0} chi_i(x)^dag chi_j(x)     (= B_ij summed over the slice),
+ *   Gt(y0)_ij = sum_{y in slice y0} eta_i(y)^dag eta_j(y)    (= Btilde_ij; by gamma5-hermiticity
+ *               phi_i^dag gamma5 D_d D^{-1} gamma5 is eta_i^dag),
+ *   out[y0][x0] = -(1/L^3) Re Tr(Gt(y0) G(x0))   (sums over both x and y of eq. pipi)
+ * for y0 in the time range of Gamma* and x0 in that of Gammabar, zero
+ * elsewhere.  With phi spanning the sites D_dGamma* reads, the projector is
+ * exact there and out equals the factorized correlator summed over all
+ * sources.  The Gram matrices are library GEMMs (rocBLAS).
+ *   phi        [nvec][V][4][3]
+ *   out        [T][T] real, host
+ *   gram_bar, gram_star  [T][nvec][nvec] complex column-major, host, or NULL
+ *   info       [2][nvec]: the Gammabar solves, then the Gamma* solves
+ * Errors: EINVAL, ENOMEM, ENOTCONVERGED, EDEVICE. */
+int ddml_projected_pion(ddml_ctx ctx, int gauge_id, int bar_id, int star_id, const double* phi, int nvec,
+                        const ddml_solver_params* params, double* out, double* gram_bar, double* gram_star,
+                        ddml_rhs_info* info, int on_device, void* stream);
 
 /* Measurement hook for the dominant kernels: times `iters` back-to-back
  * applications of the two half-stencils of the even-odd Schur operator, as

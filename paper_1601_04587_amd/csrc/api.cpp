@@ -260,6 +260,28 @@ static int solve_many(Ctx* c, int n, const ddml_solve_desc* d, const ddml_solver
   return rc;
 }
 
+// ncols canonical device fields solved 12 at a time: the full groups as one
+// batch, the remainder as another; info [ncols].  Returns the first failure.
+static int solve_columns(Ctx* c, int gauge_id, int dom_id, const double* src, double* sol, int ncols, size_t per,
+                         const ddml_solver_params* params, ddml_rhs_info* info) {
+  const int nfull = ncols / kMaxRhs, rest = ncols - nfull * kMaxRhs;
+  int rc = DDML_OK;
+  for (int part = 0; part < 2; ++part) {
+    std::vector<ddml_solve_desc> d;
+    const int cols = part == 0 ? kMaxRhs : rest;
+    const int ng = part == 0 ? nfull : (rest > 0 ? 1 : 0);
+    for (int k = 0; k < ng; ++k) {
+      const size_t first = (size_t)(part == 0 ? k * kMaxRhs : nfull * kMaxRhs);
+      d.push_back(ddml_solve_desc{gauge_id, dom_id, src + 2 * per * first, sol + 2 * per * first, cols, info + first});
+    }
+    if (!d.empty()) {
+      const int r = solve_many(c, (int)d.size(), d.data(), params, 1, c->stream);
+      if (rc == DDML_OK) rc = r;
+    }
+  }
+  return rc;
+}
+
 int ddml_solve_domain(ddml_ctx ctx, int gauge_id, int dom_id, const double* src, double* sol, int nrhs,
                       const ddml_solver_params* params, ddml_rhs_info* info, int on_device, void* stream) {
   return guarded(ctx, [&](Ctx* c) {
@@ -447,23 +469,7 @@ int ddml_hpe_trace(ddml_ctx ctx, int gauge_id, int dom_id, const double* eta, in
     if (phi_out) sf = stage_out(c, phi_out, bytes, on_device);
     else sf.buf = DBuf(c->pool.get(), bytes), sf.ptr = sf.buf.as<double>();
     DDML_HIP(launch_gamma5(reinterpret_cast<const double2*>(se.cptr), g5.as<double2>(), (size_t)nsrc * V, c->stream));
-    // solves of 12 sources at a time: the full groups as one batch, the rest as another
-    const int nfull = nsrc / kMaxRhs, rest = nsrc - nfull * kMaxRhs;
-    int rc = DDML_OK;
-    for (int part = 0; part < 2; ++part) {
-      std::vector<ddml_solve_desc> d;
-      const int cols = part == 0 ? kMaxRhs : rest;
-      const int ng = part == 0 ? nfull : (rest > 0 ? 1 : 0);
-      for (int k = 0; k < ng; ++k) {
-        const size_t first = (size_t)(part == 0 ? k * kMaxRhs : nfull * kMaxRhs);
-        d.push_back(ddml_solve_desc{gauge_id, dom_id, g5.as<double>() + 2 * per * first,
-                                    sp.ptr + 2 * per * first, cols, info + first});
-      }
-      if (!d.empty()) {
-        const int r = solve_many(c, (int)d.size(), d.data(), params, 1, c->stream);
-        if (rc == DDML_OK) rc = r;
-      }
-    }
+    const int rc = solve_columns(c, gauge_id, dom_id, g5.as<double>(), sp.ptr, nsrc, per, params, info);
     DBuf W(c->pool.get(), V * sizeof(double2)), sums(c->pool.get(), 2 * (size_t)T * sizeof(double2));
     DDML_HIP(launch_noise_trace(reinterpret_cast<const double2*>(se.cptr), reinterpret_cast<const double2*>(sp.ptr),
                                 nsrc, V, T, W.as<double2>(), sums.as<double2>(), c->stream));
@@ -491,6 +497,102 @@ int ddml_hpe_trace(ddml_ctx ctx, int gauge_id, int dom_id, const double* eta, in
       out[2 * k] = h[k].x / nsrc;
       out[2 * k + 1] = h[k].y / nsrc;
     }
+    sj.done();
+    return rc;
+  });
+}
+
+// Time slices [t0, t1) of a domain on the gauge field's lattice.
+static void slab_of(Ctx* c, const GaugeRec& g, int dom_id, int& t0, int& t1) {
+  if (dom_id == -1) {
+    t0 = 0;
+    t1 = g.lat.dims[0];
+    return;
+  }
+  const DomainRec& d = domain_get(c, dom_id);
+  need(d.hi[0] <= g.lat.dims[0], "domain outside the gauge field's lattice");
+  t0 = d.lo[0];
+  t1 = d.hi[0];
+}
+
+// Subspace (inverse) iteration: v <- orth(D_Gamma^{-1} v), niter times.
+int ddml_inverse_iteration(ddml_ctx ctx, int gauge_id, int dom_id, const double* start, int nvec, int niter,
+                           const ddml_solver_params* params, double* out, ddml_rhs_info* info, int on_device,
+                           void* stream) {
+  return guarded(ctx, [&](Ctx* c) {
+    need(start && out && info, "NULL argument");
+    need(nvec >= 1 && nvec <= 1024, "nvec must be in 1..1024");
+    need(niter >= 1, "niter must be >= 1");
+    check_params(params);
+    const GaugeRec& g = gauge_get(c, gauge_id);
+    int t0, t1;
+    slab_of(c, g, dom_id, t0, t1);
+    const size_t V = g.V, per = V * 12, V3 = V / g.lat.dims[0];
+    const size_t bytes = (size_t)nvec * per * sizeof(double2);
+    StreamJoin sj(c, stream);
+    Staged si = stage_in(c, start, bytes, on_device);
+    Staged so = stage_out(c, out, bytes, on_device);
+    DBuf tmp(c->pool.get(), bytes);
+    // ping-pong so that the last iterate lands in `out`
+    double* bufs[2] = {so.ptr, tmp.as<double>()};
+    const double* src = si.cptr;
+    int rc = DDML_OK;
+    for (int it = 0; it < niter; ++it) {
+      double* dst = bufs[(niter - 1 - it) % 2];
+      const int r = solve_columns(c, gauge_id, dom_id, src, dst, nvec, per, params, info);
+      if (rc == DDML_OK) rc = r;
+      orthonormalize(c, reinterpret_cast<double2*>(dst), nvec, V, (size_t)t0 * 12 * V3, (size_t)(t1 - t0) * 12 * V3);
+      src = dst;
+    }
+    copy_back(c, out, so, bytes, on_device);
+    DDML_HIP(hipStreamSynchronize(c->stream));
+    sj.done();
+    return rc;
+  });
+}
+
+// Projector-cut connected pion: chi_j = D_Gammabar^{-1} gamma5 phi_j and
+// eta_j = D_Gamma*^{-1} D_dGamma* phi_j, per-slice Gram matrices of both, and
+// C(y0, x0) = -(1/L^3) Re Tr(Gt(y0) G(x0)).
+int ddml_projected_pion(ddml_ctx ctx, int gauge_id, int bar_id, int star_id, const double* phi, int nvec,
+                        const ddml_solver_params* params, double* out, double* gram_bar, double* gram_star,
+                        ddml_rhs_info* info, int on_device, void* stream) {
+  return guarded(ctx, [&](Ctx* c) {
+    need(phi && out && info, "NULL argument");
+    need(nvec >= 1 && nvec <= 1024, "nvec must be in 1..1024");
+    check_params(params);
+    const GaugeRec& g = gauge_get(c, gauge_id);
+    int b0, b1, s0, s1;
+    slab_of(c, g, bar_id, b0, b1);
+    slab_of(c, g, star_id, s0, s1);
+    const int T = g.lat.dims[0];
+    const size_t V = g.V, per = V * 12;
+    const size_t bytes = (size_t)nvec * per * sizeof(double2);
+    const size_t gbytes = (size_t)T * nvec * nvec * sizeof(double2);
+    StreamJoin sj(c, stream);
+    Staged sp = stage_in(c, phi, bytes, on_device);
+    DBuf src(c->pool.get(), bytes), sol(c->pool.get(), bytes);
+    DBuf G(c->pool.get(), gbytes), Gt(c->pool.get(), gbytes), o(c->pool.get(), (size_t)T * T * sizeof(double));
+    DDML_HIP(launch_gamma5(reinterpret_cast<const double2*>(sp.cptr), src.as<double2>(), (size_t)nvec * V, c->stream));
+    int rc = solve_columns(c, gauge_id, bar_id, src.as<double>(), sol.as<double>(), nvec, per, params, info);
+    gram_slices(c, sol.as<double2>(), nvec, V, T, b0, b1, G.as<double2>());
+    for (int first = 0; first < nvec; first += kMaxRhs) {
+      const int cols = std::min(kMaxRhs, nvec - first);
+      apply_boundary(c, gauge_id, star_id, sp.cptr + 2 * per * first, src.as<double>() + 2 * per * first, cols, 1.0,
+                     c->stream);
+    }
+    const int r = solve_columns(c, gauge_id, star_id, src.as<double>(), sol.as<double>(), nvec, per, params,
+                                info + nvec);
+    if (rc == DDML_OK) rc = r;
+    gram_slices(c, sol.as<double2>(), nvec, V, T, s0, s1, Gt.as<double2>());
+    const double invL3 = 1.0 / ((double)g.lat.dims[1] * g.lat.dims[2] * g.lat.dims[3]);
+    DDML_HIP(hipMemsetAsync(o.p, 0, o.bytes, c->stream));
+    DDML_HIP(launch_trace_pairs(Gt.as<double2>(), G.as<double2>(), nvec, T, s0, s1, b0, b1, -invL3, o.as<double>(),
+                                c->stream));
+    DDML_HIP(hipMemcpyAsync(out, o.p, o.bytes, hipMemcpyDeviceToHost, c->stream));
+    if (gram_bar) DDML_HIP(hipMemcpyAsync(gram_bar, G.p, gbytes, hipMemcpyDeviceToHost, c->stream));
+    if (gram_star) DDML_HIP(hipMemcpyAsync(gram_star, Gt.p, gbytes, hipMemcpyDeviceToHost, c->stream));
+    DDML_HIP(hipStreamSynchronize(c->stream));
     sj.done();
     return rc;
   });

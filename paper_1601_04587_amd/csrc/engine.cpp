@@ -91,6 +91,7 @@ bool DevPool::fits_device(size_t bytes) const {
 
 // --------------------------------------------------------------- context
 Ctx::~Ctx() {
+  blas_release(this);
   run32.clear();
   run64.clear();
   run16.clear();

@@ -203,6 +203,7 @@ struct Ctx {
     return prec == DDML_FP64 ? tune64 : (prec == DDML_MIXED_FP16 ? tune16 : tune32);
   }
   std::unique_ptr<Server> server;
+  void* blas = nullptr;   // rocBLAS handle (linalg_blas.cpp), created on first use
   ~Ctx();
 };
 
@@ -224,6 +225,12 @@ void apply_eo(Ctx* c, int gauge_id, int dom_id, const double* in, double* out, i
 // out = scale * D_{dGamma} in (canonical FP64 fields on the gauge field's lattice)
 void apply_boundary(Ctx* c, int gauge_id, int dom_id, const double* in, double* out, int nrhs, double scale,
                     hipStream_t st);
+// linalg_blas.cpp (rocBLAS): per-slice Gram matrices G[t] = X_t^dag X_t for t in
+// [t0, t1) (zero elsewhere), X = n canonical fields; orthonormalisation of the
+// columns of X on rows [row0, row0 + nrows) by Cholesky QR (twice)
+void gram_slices(Ctx* c, const double2* X, int n, size_t V, int T, int t0, int t1, double2* G);
+void orthonormalize(Ctx* c, double2* X, int n, size_t V, size_t row0, size_t nrows);
+void blas_release(Ctx* c);
 // Runs every solve to completion (continuous batching inside).  Device pointers.
 void run_solves(Ctx* c, std::vector<Solve*>& solves);
 // Pieces used by the serving loop

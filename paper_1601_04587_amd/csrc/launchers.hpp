@@ -114,6 +114,11 @@ hipError_t launch_pion_fin(const double2* sums, int nlevels, int T, int has_full
 hipError_t launch_gamma5(const double2* in, double2* out, size_t nsites, hipStream_t st);
 hipError_t launch_noise_trace(const double2* eta, const double2* phi, int nsrc, size_t V, int T, double2* W,
                               double2* sums, hipStream_t st);
+// linalg.hip: G (column-major n x n) -> upper Cholesky factor R, G = R^dag R
+hipError_t launch_cholesky_upper(double2* G, int n, int* bad, hipStream_t st);
+// out[y * T + x] = scale * Re Tr(Gt[y] G[x]) for y in [ya, yb), x in [xa, xb)
+hipError_t launch_trace_pairs(const double2* Gt, const double2* G, int n, int T, int ya, int yb, int xa, int xb,
+                              double scale, double* out, hipStream_t st);
 // W: scratch [nlevels][V]; out: [nlevels][T]
 hipError_t launch_nucleon(const double2* terms, size_t V, int T, int nlevels, double2* W, double2* out,
                           hipStream_t st);

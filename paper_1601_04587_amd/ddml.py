@@ -70,6 +70,7 @@ EXPORTS = ["ddml_create", "ddml_destroy", "ddml_last_error", "ddml_set_gauge", "
            "ddml_release_gauge", "ddml_set_domain", "ddml_apply_Dw", "ddml_apply_eo", "ddml_solve_domain",
            "ddml_solve_batch", "ddml_propagator_series", "ddml_propagator_series_batch", "ddml_time_stencil", "ddml_autotune", "ddml_set_launch", "ddml_contract_pp_disconnected", "ddml_contract_nucleon",
            "ddml_apply_boundary", "ddml_factorized_series", "ddml_contract_pion", "ddml_hpe_trace",
+           "ddml_inverse_iteration", "ddml_projected_pion",
            "ddml_server_start", "ddml_submit", "ddml_poll", "ddml_wait", "ddml_stats", "ddml_server_stop",
            "ddml_now"]
 
@@ -112,6 +113,10 @@ def load():
     lib.ddml_factorized_series.argtypes = [P, I, IP, I, I, P, I, ctypes.POINTER(SolverParams), P, P,
                                            ctypes.POINTER(RhsInfo), I, P]
     lib.ddml_contract_pion.argtypes = [P, P, I, P, P, P, P, I, P]
+    lib.ddml_inverse_iteration.argtypes = [P, I, I, P, I, I, ctypes.POINTER(SolverParams), P,
+                                           ctypes.POINTER(RhsInfo), I, P]
+    lib.ddml_projected_pion.argtypes = [P, I, I, I, P, I, ctypes.POINTER(SolverParams), P, P, P,
+                                        ctypes.POINTER(RhsInfo), I, P]
     lib.ddml_hpe_trace.argtypes = [P, I, I, P, I, I, ctypes.POINTER(SolverParams), P, P, P,
                                    ctypes.POINTER(RhsInfo), I, P]
     lib.ddml_server_start.argtypes = [P, ctypes.POINTER(SolverParams), I]
@@ -341,6 +346,36 @@ class Context:
                                      info, dev, _stream(eta))
         self._check(rc, allow=(ENOTCONVERGED, ENUMERIC))
         return rc, out, list(info)
+
+    def inverse_iteration(self, gid, dom, start, nvec, niter, out, params=None):
+        """nvec orthonormal vectors on the domain from niter inverse iterations; returns (rc, infos)."""
+        params = params or solver_params()
+        info = (RhsInfo * nvec)()
+        ps, dev = _ptr(start)
+        po, _ = _ptr(out)
+        rc = self.lib.ddml_inverse_iteration(self.h, gid, dom, ps, nvec, niter, ctypes.byref(params), po, info, dev,
+                                             _stream(start))
+        self._check(rc, allow=(ENOTCONVERGED, ENUMERIC))
+        return rc, list(info)
+
+    def projected_pion(self, gid, bar, star, phi, nvec, params=None, grams=False):
+        """Projector-cut connected pion C(y0, x0) [T, T]; with grams=True also the
+        per-slice Gram matrices (G, Gt) as [T, nvec, nvec] arrays (row-major i, j)."""
+        params = params or solver_params()
+        T = self.gauge_dims.get(gid, self.dims)[0]
+        out = np.zeros((T, T))
+        info = (RhsInfo * (2 * nvec))()
+        gb = np.zeros((T, nvec, nvec), dtype=np.complex128) if grams else None
+        gs = np.zeros((T, nvec, nvec), dtype=np.complex128) if grams else None
+        pp, dev = _ptr(phi)
+        rc = self.lib.ddml_projected_pion(self.h, gid, bar, star, pp, nvec, ctypes.byref(params), out.ctypes.data,
+                                          gb.ctypes.data if grams else None, gs.ctypes.data if grams else None,
+                                          info, dev, _stream(phi))
+        self._check(rc, allow=(ENOTCONVERGED, ENUMERIC))
+        if grams:   # stored column-major: transpose to [t][i][j]
+            gb = np.ascontiguousarray(gb.transpose(0, 2, 1))
+            gs = np.ascontiguousarray(gs.transpose(0, 2, 1))
+        return rc, out, (gb, gs), list(info)
 
     def time_stencil(self, gid, dom, nrhs, prec=MIXED_FP32, iters=20, R=0, order=-1, grid=0, splits=0, stage=-1):
         """(ms_odd_half, ms_even_half, bytes_odd_half, bytes_even_half) per launch."""

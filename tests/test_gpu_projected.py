@@ -1,0 +1,178 @@
+"""GPU: projector-cut factorization (Section 5.2, eqs. approxlong2,
+fullfactpi, Bpions) and its inverse-iteration basis.
+
+* Inverse iteration: the orthonormal Q (unique: positive real diagonal R)
+  against the oracle's from the same start after 1 and 3 iterations; Q^dag Q = 1.
+* Projected pion and its per-slice Gram matrices against the oracle's on the
+  same basis vectors: a complete projector on a 8x2^3 lattice (equal to the
+  factorized correlator summed over all sources, pinned in the oracle tests)
+  and the GPU's own inverse-iteration basis on the 16x8^3 field.
+* At 32^3x64 with open time boundaries: orthonormality of the basis, Gram
+  matrices Hermitian and positive semi-definite, zero outside their domains,
+  and the correlator equal to the trace of the returned Gram matrices.
+Tolerances: the solves stop at relative residual 1e-10; with condition
+numbers below 1e3 the fields, and with them Q, G and C, are good to 1e-7
+relative.
+"""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+ddml = pytest.importorskip("paper_1601_04587_amd.ddml")
+torch = pytest.importorskip("torch")
+
+TOL = 1e-10
+REL = 1e-7
+
+
+def _unit_vectors(L, slices):
+    V = int(np.prod(L))
+    V3 = V // L[0]
+    sites = [t * V3 + k for t in slices for k in range(V3)]
+    phi = np.zeros((12 * len(sites), V, 4, 3), complex)
+    for m, s in enumerate(sites):
+        for c in range(12):
+            phi[12 * m + c, s, c // 3, c % 3] = 1.0
+    return phi
+
+
+@pytest.mark.parametrize("bc", [ddml.BC_OPEN, ddml.BC_ANTIPERIODIC])
+def test_complete_projector_matches_the_oracle(bc):
+    L = (8, 2, 2, 2)
+    kappa = 0.13
+    U = inputs.random_links(L, 1601701, 0.4)
+    C = oracle.clover_term(U, L, 1.2)
+    xcut, delta = 4, 2
+    bar = ((0, 0, 0, 0), (xcut + delta, 2, 2, 2))
+    star = ((xcut, 0, 0, 0), L)
+    ap = oracle.OPEN if bc == ddml.BC_OPEN else True
+    phi = _unit_vectors(L, [xcut - 1] if bc == ddml.BC_OPEN else [0, xcut - 1])
+    n = phi.shape[0]
+    ctx = ddml.Context(L, bc)
+    try:
+        gid = ctx.set_gauge(U, kappa, 1.2)
+        rc, Cg, (G, Gt), info = ctx.projected_pion(gid, ctx.set_domain(*bar), ctx.set_domain(*star), phi, n,
+                                                   ddml.solver_params(tol=TOL), grams=True)
+        assert rc == ddml.OK, ctx.last_error()
+    finally:
+        ctx.close()
+    ref, Gr, Gtr = oracle.projected_pion(U, L, kappa, phi, bar, star, C=C, antiperiodic=ap)
+    assert np.abs(Cg - ref).max() <= REL * np.abs(ref).max()
+    assert np.abs(G - Gr).max() <= REL * np.abs(Gr).max()
+    assert np.abs(Gt - Gtr).max() <= REL * np.abs(Gtr).max()
+
+
+@pytest.fixture(scope="module")
+def cfg2():
+    L = (16, 8, 8, 8)
+    U = inputs.quenched_field(L, 1601002)
+    C = oracle.clover_term(U, L, 1.769)
+    ctx = ddml.Context(L, ddml.BC_ANTIPERIODIC)
+    gid = ctx.set_gauge(U, 0.1340, 1.769)
+    yield L, U, C, ctx, gid
+    ctx.close()
+
+
+@pytest.fixture(scope="module")
+def basis(cfg2):
+    L, U, C, ctx, gid = cfg2
+    V = int(np.prod(L))
+    n = 14
+    start = inputs.gaussian(1601801, 0, (n, V, 4, 3)) + 1j * inputs.gaussian(1601801, 1, (n, V, 4, 3))
+    om = ((4, 0, 0, 0), (12, 8, 8, 8))
+    dom = ctx.set_domain(*om)
+    out = {}
+    for niter in (1, 3):
+        q = np.zeros_like(start)
+        rc, info = ctx.inverse_iteration(gid, dom, start, n, niter, q, ddml.solver_params(tol=TOL))
+        assert rc == ddml.OK, ctx.last_error()
+        out[niter] = q
+    return start, om, out
+
+
+def test_inverse_iteration_matches_the_oracle(cfg2, basis):
+    L, U, C, ctx, gid = cfg2
+    start, om, out = basis
+    n = start.shape[0]
+    for niter, q in out.items():
+        M = q.reshape(n, -1)
+        assert np.abs(np.conj(M) @ M.T - np.eye(n)).max() < 1e-12
+        assert not q[:, ~oracle.domain_mask(L, *om)].any()
+        ref = oracle.inverse_iteration(U, L, 0.1340, start, niter, C=C, lo=om[0], hi=om[1])
+        err = max(np.linalg.norm(q[i] - ref[i]) for i in range(n))
+        assert err <= REL, (niter, err)
+        print("inverse iteration", niter, "max |q - q_oracle|", err)
+
+
+def test_projected_pion_on_the_inverse_iteration_basis(cfg2, basis):
+    L, U, C, ctx, gid = cfg2
+    start, om, out = basis
+    phi = out[3]
+    n = phi.shape[0]
+    bar = ((0, 0, 0, 0), (12, 8, 8, 8))
+    star = ((8, 0, 0, 0), L)
+    rc, Cg, (G, Gt), info = ctx.projected_pion(gid, ctx.set_domain(*bar), ctx.set_domain(*star), phi, n,
+                                               ddml.solver_params(tol=TOL), grams=True)
+    assert rc == ddml.OK and len(info) == 2 * n
+    ref, Gr, Gtr = oracle.projected_pion(U, L, 0.1340, phi, bar, star, C=C)
+    assert np.abs(Cg - ref).max() <= REL * np.abs(ref).max()
+    assert np.abs(G - Gr).max() <= REL * np.abs(Gr).max()
+    assert np.abs(Gt - Gtr).max() <= REL * np.abs(Gtr).max()
+    assert np.all(Cg[8:, :12] < 0) and not Cg[:8].any() and not Cg[:, 12:].any()
+
+
+def test_projected_error_paths(cfg2):
+    L, U, C, ctx, gid = cfg2
+    V = int(np.prod(L))
+    x = np.zeros((2, V, 4, 3), complex)
+    x[0, 0, 0, 0] = 1.0                      # the second vector is zero: no basis
+    q = np.zeros_like(x)
+    rc, _ = ctx.inverse_iteration(gid, -1, x, 2, 1, q)
+    assert rc == ddml.ENUMERIC
+    with pytest.raises(ddml.DDMLError):
+        ctx.inverse_iteration(gid, -1, x, 2, 0, q)
+    with pytest.raises(ddml.DDMLError):
+        ctx.projected_pion(gid, 9999, -1, x, 2)
+
+
+@pytest.mark.slow
+def test_bench_size_projected_properties():
+    """32^3x64, open time boundaries: 12 vectors, 2 inverse iterations on
+    Omega* = [16, 32), then Gammabar = [0, 32), Gamma* = [24, 64)."""
+    L = (64, 32, 32, 32)
+    V = int(np.prod(L))
+    U = inputs.quenched_field(L, 1601004)
+    dev = torch.device("cuda:0")
+    n = 12
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(1601802)
+    start = torch.complex(torch.randn((n, V, 4, 3), generator=gen, device=dev, dtype=torch.float64),
+                          torch.randn((n, V, 4, 3), generator=gen, device=dev, dtype=torch.float64))
+    ctx = ddml.Context(L, ddml.BC_OPEN)
+    try:
+        gid = ctx.set_gauge(torch.from_numpy(U).to(dev), 0.1340, 1.769)
+        q = torch.zeros_like(start)
+        rc, _ = ctx.inverse_iteration(gid, ctx.set_domain((16, 0, 0, 0), (32,) + L[1:]), start, n, 2, q,
+                                      ddml.solver_params(tol=TOL))
+        assert rc == ddml.OK
+        M = q.reshape(n, -1)
+        gram = (torch.conj(M) @ M.T).cpu().numpy()
+        assert np.abs(gram - np.eye(n)).max() < 1e-12
+        rc, Cg, (G, Gt), _ = ctx.projected_pion(gid, ctx.set_domain((0, 0, 0, 0), (32,) + L[1:]),
+                                                ctx.set_domain((24, 0, 0, 0), L), q, n,
+                                                ddml.solver_params(tol=TOL), grams=True)
+        assert rc == ddml.OK
+    finally:
+        ctx.close()
+    V3 = V // L[0]
+    ref = -np.einsum("yij,xji->yx", Gt, G).real / V3
+    assert np.abs(Cg - ref).max() <= 1e-12 * np.abs(ref).max()
+    for Gm, (a, b) in ((G, (0, 32)), (Gt, (24, 64))):
+        assert not np.delete(Gm, np.arange(a, b), axis=0).any()
+        assert np.abs(Gm - np.conj(Gm.transpose(0, 2, 1))).max() <= 1e-12 * np.abs(Gm).max()
+        assert min(np.linalg.eigvalsh(g).min() for g in Gm[a:b]) > -1e-10 * np.abs(Gm).max()
+    print("32^3x64 projected pion C(y0, x0=4) at y0 = 32, 40, 48:", Cg[[32, 40, 48], 4])
