@@ -50,6 +50,12 @@ Contents and the passages they follow:
       and eta = D_Gamma*^{-1} D_dGamma* phi, and C(y0, x0) =
       -(1/L^3) Re Tr(Gt(y0) G(x0)).
 
+  * ``level1_update``: quenched updates of a time slab with the spatial links
+      of its first slice fixed (the level-1 updates of Section 3.1): Wilson
+      plaquette action, Cabibbo-Marinari heatbath (Kennedy-Pendleton SU(2)
+      sampler) plus SU(2) over-relaxation, Philox4x32-10 random numbers keyed
+      by link and sweep (oracle.c states the exact mapping).
+
 Time boundary conditions: ``antiperiodic`` is True (antiperiodic), False
 (periodic) or ``OPEN`` (hops across the time boundary dropped, the set-up
 Sections 2 and 5.2 assume).
@@ -97,6 +103,12 @@ def _load():
         lib.oracle_apply_D.argtypes = [i4, P, P, d, i, i4, i4, i, P, P]
         lib.oracle_apply_hop.argtypes = [i4, P, i, i4, i4, i, P, P]
         lib.oracle_apply_D_sites.argtypes = [i4, P, d, d, i, i4, i4, i, ctypes.c_long, P, P, P]
+        u32 = ctypes.c_uint32
+        lib.oracle_philox.argtypes = [P, P, P]
+        lib.oracle_kp_sample.argtypes = [d, ctypes.c_uint64, ctypes.c_long, P]
+        lib.oracle_level1_update.argtypes = [i4, d, ctypes.c_uint64, u32, i, i, i, i, P]
+        lib.oracle_plaquette.argtypes = [i4, P]
+        lib.oracle_plaquette.restype = d
         lib.oracle_solve.argtypes = [i4, P, P, d, i, i4, i4, i, P, P, d, i, P, P]
         lib.oracle_solve.restype = i
         _lib = lib
@@ -515,3 +527,34 @@ def projected_pion(U, L, kappa, phi, bar, star, C=None, antiperiodic=True, tol=1
     V3 = int(np.prod(L[1:]))
     Cm = -np.einsum("yij,xji->yx", Gt, G).real / V3
     return Cm, G, Gt
+
+
+# ------------------------------------------------------- level-1 updates
+def philox(ctr, key):
+    """Philox4x32-10 of a 4-word counter and 2-word key."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    _load().oracle_philox(c.ctypes.data, k.ctypes.data, out.ctypes.data)
+    return out
+
+
+def kp_sample(alpha, seed, n):
+    """n draws of the Kennedy-Pendleton sampler (density ~ sqrt(1-x^2) exp(alpha x))."""
+    out = np.empty(int(n))
+    _load().oracle_kp_sample(float(alpha), int(seed), int(n), out.ctypes.data)
+    return out
+
+
+def level1_update(U, L, beta, seed, update_id, t0, t1, nsweeps=1, n_or=0):
+    """A copy of U after nsweeps level-1 sweeps of the slab [t0, t1) (random
+    stream 3 + update_id)."""
+    out = _c(U).copy()
+    _load().oracle_level1_update(_i4(L), float(beta), int(seed), int(3 + update_id), int(t0), int(t1),
+                                 int(nsweeps), int(n_or), out.ctypes.data)
+    return out
+
+
+def plaquette(U, L):
+    """Average of Re tr U_P / 3 over all plaquettes."""
+    return _load().oracle_plaquette(_i4(L), _c(U).ctypes.data)

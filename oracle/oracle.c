@@ -454,3 +454,240 @@ int oracle_solve(const int L[4], const double *Ud, const double *Cd, double kapp
     free(r); free(rh); free(p); free(v); free(s); free(t); free(bm);
     return status;
 }
+
+/* ---------------------------------------------------- level-1 gauge updates
+ * Quenched updates of the links of a time slab [t0,t1) with the spatial links
+ * of slice t0 kept fixed (the level-1 updates of the two-level integration,
+ * Section 3.1): Wilson plaquette action S = beta sum_P (1 - Re tr U_P / 3);
+ * each link is updated by Cabibbo-Marinari heatbath over the SU(2) subgroups
+ * (0,1), (0,2), (1,2) with the Kennedy-Pendleton sampler, then n_or SU(2)
+ * over-relaxation passes, then projected back onto SU(3).  Links of one
+ * direction and one site parity do not enter each other's staples, so a
+ * sweep is: for mu, for parity, every such link (in any order).
+ * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), key
+ * (seed low word, seed high word ^ stream * 0x85EBCA6B), counter (site,
+ * mu | sweep << 2, 0x5EED, n) with n counting the blocks of four 32-bit words
+ * of that link; a uniform in (0,1] is (w + 1) / 2^32. */
+#include <stdint.h>
+
+static const double kPi = 3.14159265358979323846;
+
+void oracle_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x[4] = {ctr[0], ctr[1], ctr[2], ctr[3]}, k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * x[0], p1 = (uint64_t)0xCD9E8D57u * x[2];
+        const uint32_t y0 = (uint32_t)(p1 >> 32) ^ x[1] ^ k0, y1 = (uint32_t)p1;
+        const uint32_t y2 = (uint32_t)(p0 >> 32) ^ x[3] ^ k1, y3 = (uint32_t)p0;
+        x[0] = y0; x[1] = y1; x[2] = y2; x[3] = y3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    memcpy(out, x, sizeof x);
+}
+
+typedef struct { uint32_t key[2], ctr[4], w[4]; int left; } draws_t;
+
+static void draws_init(draws_t *d, uint64_t seed, uint32_t stream, uint32_t c0, uint32_t c1)
+{
+    d->key[0] = (uint32_t)seed;
+    d->key[1] = (uint32_t)(seed >> 32) ^ (stream * 0x85EBCA6Bu);
+    d->ctr[0] = c0; d->ctr[1] = c1; d->ctr[2] = 0x5EEDu; d->ctr[3] = 0;
+    d->left = 0;
+}
+static double draw(draws_t *d) /* uniform in (0,1] */
+{
+    if (d->left == 0) {
+        oracle_philox(d->ctr, d->key, d->w);
+        d->ctr[3] += 1;
+        d->left = 4;
+    }
+    const uint32_t w = d->w[4 - d->left];
+    d->left -= 1;
+    return ((double)w + 1.0) / 4294967296.0;
+}
+
+static void mat3(const cplx *a, int da, const cplx *b, int db, cplx *c) /* c = a b with optional adjoints */
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            cplx s = 0;
+            for (int k = 0; k < 3; ++k)
+                s += (da ? conj(a[3 * k + i]) : a[3 * i + k]) * (db ? conj(b[3 * j + k]) : b[3 * k + j]);
+            c[3 * i + j] = s;
+        }
+}
+
+/* A = sum_{nu != mu} of the upper and lower staples of U_mu(x), so that the
+ * part of the action that depends on U_mu(x) is -(beta/3) Re tr(U_mu(x) A). */
+static void staple_sum(const lat_t *g, const cplx *U, long s, int mu, cplx *A)
+{
+    int x[4];
+    coords(g, s, x);
+    memset(A, 0, 9 * sizeof(cplx));
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == mu) continue;
+        int y[4];
+        cplx t[9], w[9];
+        /* U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag */
+        memcpy(y, x, sizeof y); y[mu] = (y[mu] + 1) % g->L[mu];
+        const cplx *a = link(U, index_of(g, y), nu);
+        memcpy(y, x, sizeof y); y[nu] = (y[nu] + 1) % g->L[nu];
+        mat3(a, 0, link(U, index_of(g, y), mu), 1, t);
+        mat3(t, 0, link(U, s, nu), 1, w);
+        for (int k = 0; k < 9; ++k) A[k] += w[k];
+        /* U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu) */
+        memcpy(y, x, sizeof y); y[nu] = (y[nu] - 1 + g->L[nu]) % g->L[nu];
+        const long xmn = index_of(g, y);
+        y[mu] = (y[mu] + 1) % g->L[mu];
+        mat3(link(U, index_of(g, y), nu), 1, link(U, xmn, mu), 1, t);
+        mat3(t, 0, link(U, xmn, nu), 0, w);
+        for (int k = 0; k < 9; ++k) A[k] += w[k];
+    }
+}
+
+/* quaternion q = (q0, q1, q2, q3) <-> q0 + i (q1 s1 + q2 s2 + q3 s3) */
+static void quat_of_block(const cplx *W, int i, int j, double q[4])
+{
+    q[0] = 0.5 * (creal(W[3 * i + i]) + creal(W[3 * j + j]));
+    q[1] = 0.5 * (cimag(W[3 * i + j]) + cimag(W[3 * j + i]));
+    q[2] = 0.5 * (creal(W[3 * i + j]) - creal(W[3 * j + i]));
+    q[3] = 0.5 * (cimag(W[3 * i + i]) - cimag(W[3 * j + j]));
+}
+static void quat_times(const double a[4], const double b[4], double c[4])
+{
+    c[0] = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+    c[1] = a[0] * b[1] + b[0] * a[1] - (a[2] * b[3] - a[3] * b[2]);
+    c[2] = a[0] * b[2] + b[0] * a[2] - (a[3] * b[1] - a[1] * b[3]);
+    c[3] = a[0] * b[3] + b[0] * a[3] - (a[1] * b[2] - a[2] * b[1]);
+}
+/* rows i, j of U <- the 2x2 matrix of quaternion r times those rows */
+static void rows_times_quat(const double r[4], int i, int j, cplx *U)
+{
+    const cplx m00 = r[0] + I * r[3], m01 = r[2] + I * r[1], m10 = -r[2] + I * r[1], m11 = r[0] - I * r[3];
+    for (int c = 0; c < 3; ++c) {
+        const cplx ui = U[3 * i + c], uj = U[3 * j + c];
+        U[3 * i + c] = m00 * ui + m01 * uj;
+        U[3 * j + c] = m10 * ui + m11 * uj;
+    }
+}
+
+/* Kennedy-Pendleton: x0 in [-1,1] with density ~ sqrt(1 - x0^2) exp(alpha x0). */
+static double kp_x0(double alpha, draws_t *d)
+{
+    for (int tries = 0; tries <= 10000; ++tries) {
+        const double r1 = draw(d), r2 = draw(d), r3 = draw(d), r4 = draw(d);
+        const double c = cos(2.0 * kPi * r2);
+        const double lam2 = -(log(r1) + c * c * log(r3)) / (2.0 * alpha);
+        if (r4 * r4 <= 1.0 - lam2) return 1.0 - 2.0 * lam2;
+    }
+    return 1.0;
+}
+
+void oracle_kp_sample(double alpha, uint64_t seed, long n, double *out)
+{
+    for (long k = 0; k < n; ++k) {
+        draws_t d;
+        draws_init(&d, seed, 1u, (uint32_t)k, 0u);
+        out[k] = kp_x0(alpha, &d);
+    }
+}
+
+/* Gram-Schmidt on rows 0 and 1, row 2 = conj(row0 x row1). */
+static void to_su3(cplx *u)
+{
+    double n = 0;
+    for (int j = 0; j < 3; ++j) n += creal(u[j] * conj(u[j]));
+    n = 1.0 / sqrt(n);
+    for (int j = 0; j < 3; ++j) u[j] *= n;
+    cplx p = 0;
+    for (int j = 0; j < 3; ++j) p += conj(u[j]) * u[3 + j];
+    for (int j = 0; j < 3; ++j) u[3 + j] -= p * u[j];
+    n = 0;
+    for (int j = 0; j < 3; ++j) n += creal(u[3 + j] * conj(u[3 + j]));
+    n = 1.0 / sqrt(n);
+    for (int j = 0; j < 3; ++j) u[3 + j] *= n;
+    u[6] = conj(u[1] * u[5] - u[2] * u[4]);
+    u[7] = conj(u[2] * u[3] - u[0] * u[5]);
+    u[8] = conj(u[0] * u[4] - u[1] * u[3]);
+}
+
+static void update_one_link(cplx *Ul, const cplx *A, double beta, int n_or, draws_t *d)
+{
+    static const int sub[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    for (int pass = 0; pass < 1 + n_or; ++pass)
+        for (int k = 0; k < 3; ++k) {
+            cplx W[9];
+            mat3(Ul, 0, A, 0, W);
+            double q[4];
+            quat_of_block(W, sub[k][0], sub[k][1], q);
+            const double norm = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+            if (norm < 1e-14) continue;
+            const double vdag[4] = {q[0] / norm, -q[1] / norm, -q[2] / norm, -q[3] / norm};
+            double R[4];
+            if (pass == 0) {
+                /* SU(2) weight exp((beta/3) Re tr_2(R W)) = exp(alpha x0), alpha = 2 beta |q| / 3 */
+                const double x0 = kp_x0(2.0 * beta * norm / 3.0, d);
+                const double rad = sqrt(fmax(0.0, 1.0 - x0 * x0));
+                const double ct = 2.0 * draw(d) - 1.0, ph = 2.0 * kPi * draw(d);
+                const double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+                const double X[4] = {x0, rad * st * cos(ph), rad * st * sin(ph), rad * ct};
+                quat_times(X, vdag, R);
+            } else {
+                quat_times(vdag, vdag, R); /* over-relaxation: Re tr(R W) unchanged */
+            }
+            rows_times_quat(R, sub[k][0], sub[k][1], Ul);
+        }
+    to_su3(Ul);
+}
+
+void oracle_level1_update(const int L[4], double beta, uint64_t seed, uint32_t stream, int t0, int t1,
+                          int nsweeps, int n_or, double *Ud)
+{
+    lat_t g;
+    lat_init(&g, L);
+    cplx *U = (cplx *)Ud;
+    const long V3 = (long)L[1] * L[2] * L[3];
+    for (int sweep = 0; sweep < nsweeps; ++sweep)
+        for (int mu = 0; mu < 4; ++mu)
+            for (int par = 0; par < 2; ++par) {
+#pragma omp parallel for schedule(static)
+                for (long s = (long)t0 * V3; s < (long)t1 * V3; ++s) {
+                    int x[4];
+                    coords(&g, s, x);
+                    if (((x[0] + x[1] + x[2] + x[3]) & 1) != par) continue;
+                    if (mu != 0 && x[0] == t0) continue; /* frozen spatial links of the first slice */
+                    cplx A[9];
+                    staple_sum(&g, U, s, mu, A);
+                    draws_t d;
+                    draws_init(&d, seed, stream, (uint32_t)s, (uint32_t)(mu | (sweep << 2)));
+                    update_one_link((cplx *)link(U, s, mu), A, beta, n_or, &d);
+                }
+            }
+}
+
+/* Average plaquette (1/3) Re tr U_P over all sites and the six planes. */
+double oracle_plaquette(const int L[4], const double *Ud)
+{
+    lat_t g;
+    lat_init(&g, L);
+    const cplx *U = (const cplx *)Ud;
+    double sum = 0;
+#pragma omp parallel for reduction(+ : sum) schedule(static)
+    for (long s = 0; s < g.V; ++s) {
+        int x[4];
+        coords(&g, s, x);
+        for (int mu = 0; mu < 4; ++mu)
+            for (int nu = mu + 1; nu < 4; ++nu) {
+                int y[4];
+                cplx t[9], w[9];
+                memcpy(y, x, sizeof y); y[mu] = (y[mu] + 1) % g.L[mu];
+                mat3(link(U, s, mu), 0, link(U, index_of(&g, y), nu), 0, t);
+                memcpy(y, x, sizeof y); y[nu] = (y[nu] + 1) % g.L[nu];
+                mat3(t, 0, link(U, index_of(&g, y), mu), 1, w);
+                mat3(w, 0, link(U, s, nu), 1, t);
+                sum += creal(t[0] + t[4] + t[8]) / 3.0;
+            }
+    }
+    return sum / (6.0 * g.V);
+}
