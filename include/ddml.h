@@ -141,9 +141,36 @@ int ddml_set_gauge_lattice(ddml_ctx ctx, const ddml_lattice* lat, const double* 
 /* Level-1 update of the two-level integration (Section 3.1): a new gauge id
  * equal to base_gauge_id except on time slices [t0, t1), whose links are
  * U_region[(t - t0)*L1*L2*L3 + ...][mu][3][3].  The base is shared, not
- * copied.  Errors: EINVAL (bad range or id), ENOMEM. */
+ * copied (a base that is itself such a version with slices outside [t0, t1)
+ * is copied once into a whole field).  Errors: EINVAL (bad range or id),
+ * ENOMEM. */
 int ddml_set_gauge_region(ddml_ctx ctx, int base_gauge_id, int t0, int t1, const double* U_region,
                           int on_device, int* new_gauge_id);
+/* Level-1 updates generated on the device (Section 3.1): a new gauge id equal
+ * to base_gauge_id except on the slab [t0, t1), whose links are the base's
+ * after nsweeps quenched sweeps with the Wilson plaquette action at coupling
+ * beta, the spatial links of slice t0 held fixed (they are the frozen
+ * boundary shared by neighbouring level-0 regions).  One sweep visits, for
+ * mu = 0..3 and parity (x0+x1+x2+x3) mod 2 = 0, 1, every link of that class
+ * in the slab once: a Cabibbo-Marinari heatbath over the SU(2) subgroups
+ * (0,1), (0,2), (1,2) with the Kennedy-Pendleton sampler, then n_or
+ * over-relaxation passes over the same subgroups, then projection onto SU(3)
+ * (Gram-Schmidt of rows 0 and 1, row 2 their conjugate cross product).  Links
+ * outside the slab enter the staples unchanged; the time direction of the
+ * gauge field is periodic.  Random numbers: Philox4x32-10 with key
+ * (seed mod 2^32, (seed >> 32) ^ (stream * 0x85EBCA6B mod 2^32)) and counter
+ * (lexicographic site, mu | sweep << 2, 0x5EED, n) for the n-th block of four
+ * words of that link, each word w giving the uniform (w + 1) / 2^32; a link's
+ * draws are taken in the order the update consumes them (the sampler four
+ * per try, at most 10001 tries, then two for the direction).  Deterministic
+ * for given arguments.  Lattice extents must be even.  Errors: EINVAL (bad
+ * range, id or parameters), ENOMEM, EDEVICE. */
+int ddml_level1_update(ddml_ctx ctx, int base_gauge_id, int t0, int t1, double beta, uint64_t seed,
+                       uint32_t stream, int nsweeps, int n_or, int* new_gauge_id);
+/* Copy of the links of gauge id (the whole field of its lattice, region
+ * included) into U [V][4][3][3] complex (host or device memory, caller
+ * owned).  Synchronous.  Errors: EINVAL, EDEVICE. */
+int ddml_get_gauge(ddml_ctx ctx, int gauge_id, double* U, int on_device);
 /* Drop a gauge id and the operator data built from it. */
 int ddml_release_gauge(ddml_ctx ctx, int gauge_id);
 

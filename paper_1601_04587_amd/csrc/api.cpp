@@ -165,6 +165,23 @@ int ddml_set_gauge_region(ddml_ctx ctx, int base_gauge_id, int t0, int t1, const
   });
 }
 
+int ddml_level1_update(ddml_ctx ctx, int base_gauge_id, int t0, int t1, double beta, uint64_t seed,
+                       uint32_t stream, int nsweeps, int n_or, int* new_gauge_id) {
+  return guarded(ctx, [&](Ctx* c) {
+    need(new_gauge_id != nullptr, "new_gauge_id is NULL");
+    *new_gauge_id = gauge_level1(c, base_gauge_id, t0, t1, beta, seed, stream, nsweeps, n_or);
+    return DDML_OK;
+  });
+}
+
+int ddml_get_gauge(ddml_ctx ctx, int gauge_id, double* U, int on_device) {
+  return guarded(ctx, [&](Ctx* c) {
+    need(U != nullptr, "U is NULL");
+    gauge_copy_out(c, gauge_id, U, on_device);
+    return DDML_OK;
+  });
+}
+
 int ddml_release_gauge(ddml_ctx ctx, int gauge_id) {
   return guarded(ctx, [&](Ctx* c) {
     gauge_release(c, gauge_id);

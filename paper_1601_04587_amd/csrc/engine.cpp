@@ -187,39 +187,84 @@ const GaugeRec& gauge_get(Ctx* c, int gauge_id) {
   return it->second;
 }
 
-int gauge_region(Ctx* c, int base, int t0, int t1, const double* U, int on_device) {
+// A new version of gauge field `base` that owns the slices [t0, t1), region
+// allocated and left for the caller to fill.  It shares the parent's base
+// buffer; a parent that is a version itself is materialised into a new base
+// first, unless its own slices lie inside [t0, t1) (then the new region
+// replaces them and `*overlay` is set to the parent, whose region holds the
+// parent's values of those slices).
+static GaugeRec version_of(Ctx* c, int base, int t0, int t1, const GaugeRec** overlay) {
   auto it = c->gauges.find(base);
   if (it == c->gauges.end()) throw Error{DDML_EINVAL, "unknown base gauge id"};
-  if (!U) throw Error{DDML_EINVAL, "region pointer is NULL"};
   const ddml_lattice& lat = it->second.lat;
   const size_t V = it->second.V;
   if (t0 < 0 || t1 > lat.dims[0] || t0 >= t1) throw Error{DDML_EINVAL, "bad time range"};
   const size_t V3 = V / lat.dims[0];
+  const GaugeRec& p = it->second;
   GaugeRec g;
-  g.kappa = it->second.kappa;
-  g.csw = it->second.csw;
+  g.kappa = p.kappa;
+  g.csw = p.csw;
   g.lat = lat;
   g.V = V;
-  if (it->second.region) {
-    // a version of a version: materialise the parent first
-    const GaugeRec& p = it->second;
+  *overlay = nullptr;
+  if (p.region && !(p.r_t0 >= t0 && p.r_t1 <= t1)) {
     g.base = std::make_shared<DBuf>(c->pool.get(), V * 36 * sizeof(double2));
     DDML_HIP(hipMemcpyAsync(g.base->p, p.base->p, V * 36 * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
     DDML_HIP(hipMemcpyAsync(g.base->as<double2>() + (size_t)p.r_t0 * V3 * 36, p.region->p,
                             (size_t)(p.r_t1 - p.r_t0) * V3 * 36 * sizeof(double2), hipMemcpyDeviceToDevice,
                             c->stream));
   } else {
-    g.base = it->second.base;
+    g.base = p.base;
+    if (p.region) *overlay = &p;
   }
-  const size_t bytes = (size_t)(t1 - t0) * V3 * 36 * sizeof(double2);
-  g.region = std::make_shared<DBuf>(c->pool.get(), bytes);
-  copy_in(c, g.region->p, U, bytes, on_device);
-  DDML_HIP(hipStreamSynchronize(c->stream));
+  g.region = std::make_shared<DBuf>(c->pool.get(), (size_t)(t1 - t0) * V3 * 36 * sizeof(double2));
   g.r_t0 = t0;
   g.r_t1 = t1;
+  return g;
+}
+
+int gauge_region(Ctx* c, int base, int t0, int t1, const double* U, int on_device) {
+  if (!U) throw Error{DDML_EINVAL, "region pointer is NULL"};
+  const GaugeRec* overlay;
+  GaugeRec g = version_of(c, base, t0, t1, &overlay);
+  copy_in(c, g.region->p, U, g.region->bytes, on_device);
+  DDML_HIP(hipStreamSynchronize(c->stream));
   const int id = c->next_gauge++;
   c->gauges[id] = std::move(g);
   return id;
+}
+
+int gauge_level1(Ctx* c, int base, int t0, int t1, double beta, uint64_t seed, uint32_t stream, int nsweeps,
+                 int n_or) {
+  if (!(beta > 0) || nsweeps < 0 || n_or < 0) throw Error{DDML_EINVAL, "need beta > 0, nsweeps >= 0, n_or >= 0"};
+  const GaugeRec* overlay;
+  GaugeRec g = version_of(c, base, t0, t1, &overlay);
+  const size_t V3 = g.V / g.lat.dims[0], link = 36 * sizeof(double2);
+  // the region starts from the parent's links on [t0, t1)
+  DDML_HIP(hipMemcpyAsync(g.region->p, g.base->as<double2>() + (size_t)t0 * V3 * 36, g.region->bytes,
+                          hipMemcpyDeviceToDevice, c->stream));
+  if (overlay)
+    DDML_HIP(hipMemcpyAsync((char*)g.region->p + (size_t)(overlay->r_t0 - t0) * V3 * link, overlay->region->p,
+                            (size_t)(overlay->r_t1 - overlay->r_t0) * V3 * link, hipMemcpyDeviceToDevice, c->stream));
+  const GaugeView gv{g.base->as<double2>(), g.region->as<double2>(), t0, t1};
+  BlockSpec bs{};
+  for (int m = 0; m < 4; ++m) bs.L[m] = g.lat.dims[m];
+  DDML_HIP(launch_level1_sweeps(gv, g.region->as<double2>(), bs, beta, seed, stream, nsweeps, n_or, c->stream));
+  DDML_HIP(hipStreamSynchronize(c->stream));
+  const int id = c->next_gauge++;
+  c->gauges[id] = std::move(g);
+  return id;
+}
+
+void gauge_copy_out(Ctx* c, int id, double* U, int on_device) {
+  const GaugeRec& g = gauge_get(c, id);
+  const size_t V3 = g.V / g.lat.dims[0], link = 36 * sizeof(double2);
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  DDML_HIP(hipMemcpyAsync(U, g.base->p, g.V * link, kind, c->stream));
+  if (g.region)
+    DDML_HIP(hipMemcpyAsync((char*)U + (size_t)g.r_t0 * V3 * link, g.region->p,
+                            (size_t)(g.r_t1 - g.r_t0) * V3 * link, kind, c->stream));
+  DDML_HIP(hipStreamSynchronize(c->stream));
 }
 
 void gauge_release(Ctx* c, int id) {

@@ -213,6 +213,10 @@ int gauge_new(Ctx* c, const double* U, int on_device, double kappa, double csw);
 int gauge_new_lattice(Ctx* c, const ddml_lattice* lat, const double* U, int on_device, double kappa, double csw);
 const GaugeRec& gauge_get(Ctx* c, int gauge_id);
 int gauge_region(Ctx* c, int base, int t0, int t1, const double* U, int on_device);
+// new version whose slices [t0, t1) are the parent's after nsweeps level-1 sweeps
+int gauge_level1(Ctx* c, int base, int t0, int t1, double beta, uint64_t seed, uint32_t stream, int nsweeps,
+                 int n_or);
+void gauge_copy_out(Ctx* c, int id, double* U, int on_device);
 void gauge_release(Ctx* c, int id);
 int domain_new(Ctx* c, const int lo[4], const int hi[4]);
 const DomainRec& domain_get(Ctx* c, int dom_id);  // dom_id -1 = full lattice

@@ -527,6 +527,212 @@ hipError_t launch_boundary(const GaugeView& gv, const BlockSpec& bs, const doubl
   return hipGetLastError();
 }
 
+// ----------------------------------------------------------- level-1 updates
+// Quenched updates of the links of the slab [t0, t1) of a gauge version with
+// the spatial links of slice t0 fixed (the level-1 updates of the two-level
+// integration): Wilson plaquette action; per link a Cabibbo-Marinari
+// heatbath over the SU(2) subgroups (0,1), (0,2), (1,2) with the
+// Kennedy-Pendleton sampler, n_or SU(2) over-relaxation passes, projection
+// onto SU(3).  One launch updates one (direction, parity) class, whose links
+// do not enter each other's staples.  Random numbers: Philox4x32-10 (Salmon
+// et al., SC'11), key (seed low word, seed high word ^ stream * 0x85EBCA6B),
+// counter (site, mu | sweep << 2, 0x5EED, n), uniform (w + 1) / 2^32.
+__device__ __forceinline__ void philox4x32_10(uint32_t x[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t hi0 = __umulhi(0xD2511F53u, x[0]), lo0 = 0xD2511F53u * x[0];
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, x[2]), lo1 = 0xCD9E8D57u * x[2];
+    const uint32_t y0 = hi1 ^ x[1] ^ k0, y2 = hi0 ^ x[3] ^ k1;
+    x[0] = y0;
+    x[1] = lo1;
+    x[2] = y2;
+    x[3] = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+struct LinkDraws {
+  uint32_t k0, k1, c0, c1, n;
+  uint32_t w0, w1, w2, w3;
+  int left;
+  __device__ double next() {
+    if (left == 0) {
+      uint32_t x[4] = {c0, c1, 0x5EEDu, n};
+      philox4x32_10(x, k0, k1);
+      w0 = x[0];
+      w1 = x[1];
+      w2 = x[2];
+      w3 = x[3];
+      ++n;
+      left = 4;
+    }
+    const uint32_t w = left == 4 ? w0 : (left == 3 ? w1 : (left == 2 ? w2 : w3));
+    --left;
+    return ((double)w + 1.0) * (1.0 / 4294967296.0);
+  }
+};
+
+// A = sum over nu != mu of U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag + U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)
+__device__ void wilson_staples(const GaugeView& gv, const int L[4], const int x[4], int mu, double2 A[9]) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) A[k] = make_double2(0, 0);
+  for (int nu = 0; nu < 4; ++nu) {
+    if (nu == mu) continue;
+    double2 a[9], b[9], t[9], w[9];
+    int y[4];
+    nbr(L, x, mu, 1, nu, 0, y);
+    load_link(gv, L, y, nu, a);
+    nbr(L, x, mu, 0, nu, 1, y);
+    load_link(gv, L, y, mu, b);
+    m3(a, false, b, true, t);
+    load_link(gv, L, x, nu, a);
+    m3(t, false, a, true, w);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) A[k] = make_double2(A[k].x + w[k].x, A[k].y + w[k].y);
+    nbr(L, x, mu, 1, nu, -1, y);
+    load_link(gv, L, y, nu, a);
+    nbr(L, x, mu, 0, nu, -1, y);
+    load_link(gv, L, y, mu, b);
+    m3(a, true, b, true, t);
+    load_link(gv, L, y, nu, a);
+    m3(t, false, a, false, w);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) A[k] = make_double2(A[k].x + w[k].x, A[k].y + w[k].y);
+  }
+}
+
+__device__ __forceinline__ void quat_times(const double a[4], const double b[4], double c[4]) {
+  c[0] = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+  c[1] = a[0] * b[1] + b[0] * a[1] - (a[2] * b[3] - a[3] * b[2]);
+  c[2] = a[0] * b[2] + b[0] * a[2] - (a[3] * b[1] - a[1] * b[3]);
+  c[3] = a[0] * b[3] + b[0] * a[3] - (a[1] * b[2] - a[2] * b[1]);
+}
+
+// Kennedy-Pendleton: x0 with density ~ sqrt(1 - x0^2) exp(alpha x0)
+__device__ double kp_sample(double alpha, LinkDraws& d) {
+  const double twopi = 2.0 * 3.14159265358979323846;
+  for (int tries = 0; tries <= 10000; ++tries) {
+    const double r1 = d.next(), r2 = d.next(), r3 = d.next(), r4 = d.next();
+    const double c = cos(twopi * r2);
+    const double lam2 = -(log(r1) + c * c * log(r3)) / (2.0 * alpha);
+    if (r4 * r4 <= 1.0 - lam2) return 1.0 - 2.0 * lam2;
+  }
+  return 1.0;
+}
+
+__device__ void level1_link(double2 U[9], const double2 A[9], double beta, int n_or, LinkDraws& d) {
+  const double twopi = 2.0 * 3.14159265358979323846;
+  for (int pass = 0; pass <= n_or; ++pass)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int i = k == 2 ? 1 : 0, j = k == 0 ? 1 : 2;
+      double2 W[9];
+      m3(U, false, A, false, W);
+      const double q[4] = {0.5 * (W[3 * i + i].x + W[3 * j + j].x), 0.5 * (W[3 * i + j].y + W[3 * j + i].y),
+                           0.5 * (W[3 * i + j].x - W[3 * j + i].x), 0.5 * (W[3 * i + i].y - W[3 * j + j].y)};
+      const double norm = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+      if (norm < 1e-14) continue;
+      const double vd[4] = {q[0] / norm, -q[1] / norm, -q[2] / norm, -q[3] / norm};
+      double R[4];
+      if (pass == 0) {
+        const double x0 = kp_sample(2.0 * beta * norm / 3.0, d);
+        const double rad = sqrt(fmax(0.0, 1.0 - x0 * x0));
+        const double ct = 2.0 * d.next() - 1.0, ph = twopi * d.next();
+        const double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+        const double X[4] = {x0, rad * st * cos(ph), rad * st * sin(ph), rad * ct};
+        quat_times(X, vd, R);
+      } else {
+        quat_times(vd, vd, R);  // over-relaxation keeps Re tr(R W)
+      }
+      // rows i, j of U <- [[r0 + i r3, r2 + i r1], [-r2 + i r1, r0 - i r3]] (rows i, j)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double2 ui = U[3 * i + c], uj = U[3 * j + c];
+        U[3 * i + c] = make_double2(R[0] * ui.x - R[3] * ui.y + R[2] * uj.x - R[1] * uj.y,
+                                    R[0] * ui.y + R[3] * ui.x + R[2] * uj.y + R[1] * uj.x);
+        U[3 * j + c] = make_double2(-R[2] * ui.x - R[1] * ui.y + R[0] * uj.x + R[3] * uj.y,
+                                    -R[2] * ui.y + R[1] * ui.x + R[0] * uj.y - R[3] * uj.x);
+      }
+    }
+  // back onto SU(3): Gram-Schmidt on rows 0 and 1, row 2 = conj(row 0 x row 1)
+  double n = 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) n += U[c].x * U[c].x + U[c].y * U[c].y;
+  n = 1.0 / sqrt(n);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) U[c] = make_double2(U[c].x * n, U[c].y * n);
+  double2 p = make_double2(0, 0);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double2 t = dmulc(U[c], U[3 + c]);
+    p.x += t.x;
+    p.y += t.y;
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double2 t = dmul(p, U[c]);
+    U[3 + c] = make_double2(U[3 + c].x - t.x, U[3 + c].y - t.y);
+  }
+  n = 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) n += U[3 + c].x * U[3 + c].x + U[3 + c].y * U[3 + c].y;
+  n = 1.0 / sqrt(n);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) U[3 + c] = make_double2(U[3 + c].x * n, U[3 + c].y * n);
+  auto cross = [&](int a, int b, int e, int f) {  // conj(U[a] U[b] - U[e] U[f])
+    const double2 t1 = dmul(U[a], U[b]), t2 = dmul(U[e], U[f]);
+    return make_double2(t1.x - t2.x, -(t1.y - t2.y));
+  };
+  U[6] = cross(1, 5, 2, 4);
+  U[7] = cross(2, 3, 0, 5);
+  U[8] = cross(0, 4, 1, 3);
+}
+
+__global__ void __launch_bounds__(128) k_level1_class(GaugeView gv, double2* __restrict__ region, BlockSpec bs,
+                                                       int mu, int par, double beta, uint32_t k0, uint32_t k1,
+                                                       int sweep, int n_or) {
+  const int t0 = gv.r_t0, t1 = gv.r_t1;
+  const size_t V3 = (size_t)bs.L[1] * bs.L[2] * bs.L[3];
+  const size_t n = (size_t)(t1 - t0) * V3;
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+    const size_t s = (size_t)t0 * V3 + k;
+    int x[4];
+    size_t r = s;
+    x[3] = (int)(r % bs.L[3]); r /= bs.L[3];
+    x[2] = (int)(r % bs.L[2]); r /= bs.L[2];
+    x[1] = (int)(r % bs.L[1]);
+    x[0] = (int)(r / bs.L[1]);
+    if (((x[0] + x[1] + x[2] + x[3]) & 1) != par) continue;
+    if (mu != 0 && x[0] == t0) continue;  // frozen spatial links of the first slice
+    double2 A[9], U[9];
+    wilson_staples(gv, bs.L, x, mu, A);
+    load_link(gv, bs.L, x, mu, U);
+    LinkDraws d{k0, k1, (uint32_t)s, (uint32_t)(mu | (sweep << 2)), 0u, 0u, 0u, 0u, 0u, 0};
+    level1_link(U, A, beta, n_or, d);
+    double2* dst = region + (k * 4 + mu) * 9;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) dst[c] = U[c];
+  }
+}
+
+hipError_t launch_level1_sweeps(const GaugeView& gv, double2* region, const BlockSpec& bs, double beta,
+                                uint64_t seed, uint32_t stream, int nsweeps, int n_or, hipStream_t st) {
+  const size_t n = (size_t)(gv.r_t1 - gv.r_t0) * bs.L[1] * bs.L[2] * bs.L[3];
+  size_t grid = (n + 127) / 128;
+  if (grid > 16384) grid = 16384;
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32) ^ (stream * 0x85EBCA6Bu);
+  for (int sweep = 0; sweep < nsweeps; ++sweep)
+    for (int mu = 0; mu < 4; ++mu)
+      for (int par = 0; par < 2; ++par) {
+        hipLaunchKernelGGL(k_level1_class, dim3((unsigned)grid), dim3(128), 0, st, gv, region, bs, mu, par, beta, k0,
+                           k1, sweep, n_or);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+      }
+  return hipSuccess;
+}
+
 // 16-bit copies for the FP16-storage inner solver: links with scale 1 (their
 // entries are bounded by 1 in magnitude), A^{-1} with one scale per site.
 __global__ void k_quant_links(const double2* __restrict__ U64, h16c* __restrict__ U16, size_t n) {

@@ -95,6 +95,9 @@ hipError_t launch_gather(const double2* canon, const BlockSpec& bs, int p, int n
                          hipStream_t st);
 hipError_t launch_scatter(const double2* eo, const BlockSpec& bs, int p, int nrhs, double scale, double2* canon,
                           hipStream_t st);
+// level-1 updates of the region [gv.r_t0, gv.r_t1) of a gauge version (bs.L the lattice)
+hipError_t launch_level1_sweeps(const GaugeView& gv, double2* region, const BlockSpec& bs, double beta,
+                                uint64_t seed, uint32_t stream, int nsweeps, int n_or, hipStream_t st);
 // out = scale * D_{dGamma} in on canonical [nrhs][V][12] fields, Gamma = [bs.lo, bs.lo + bs.Lb)
 hipError_t launch_boundary(const GaugeView& gv, const BlockSpec& bs, const double2* in, double2* out, int nrhs,
                            double scale, hipStream_t st);

@@ -66,7 +66,7 @@ class ServerStats(ctypes.Structure):
 
 
 EXPORTS = ["ddml_create", "ddml_destroy", "ddml_last_error", "ddml_set_gauge", "ddml_set_gauge_lattice",
-           "ddml_set_gauge_region",
+           "ddml_set_gauge_region", "ddml_level1_update", "ddml_get_gauge",
            "ddml_release_gauge", "ddml_set_domain", "ddml_apply_Dw", "ddml_apply_eo", "ddml_solve_domain",
            "ddml_solve_batch", "ddml_propagator_series", "ddml_propagator_series_batch", "ddml_time_stencil", "ddml_autotune", "ddml_set_launch", "ddml_contract_pp_disconnected", "ddml_contract_nucleon",
            "ddml_apply_boundary", "ddml_factorized_series", "ddml_contract_pion", "ddml_hpe_trace",
@@ -94,6 +94,8 @@ def load():
     lib.ddml_set_gauge.argtypes = [P, P, I, D, D, IP]
     lib.ddml_set_gauge_lattice.argtypes = [P, ctypes.POINTER(Lattice), P, I, D, D, IP]
     lib.ddml_set_gauge_region.argtypes = [P, I, I, I, P, I, IP]
+    lib.ddml_level1_update.argtypes = [P, I, I, I, D, ctypes.c_uint64, ctypes.c_uint32, I, I, IP]
+    lib.ddml_get_gauge.argtypes = [P, I, P, I]
     lib.ddml_release_gauge.argtypes = [P, I]
     lib.ddml_set_domain.argtypes = [P, IP, IP, IP]
     lib.ddml_apply_Dw.argtypes = [P, I, I, P, P, I, I, I, P]
@@ -224,6 +226,19 @@ class Context:
         if base in self.gauge_dims:
             self.gauge_dims[gid.value] = self.gauge_dims[base]
         return gid.value
+
+    def level1_update(self, base, t0, t1, beta, seed, stream, nsweeps=1, n_or=0):
+        gid = ctypes.c_int()
+        self._check(self.lib.ddml_level1_update(self.h, base, t0, t1, float(beta), int(seed) & (2**64 - 1),
+                                                int(stream) & 0xFFFFFFFF, nsweeps, n_or, ctypes.byref(gid)))
+        if base in self.gauge_dims:
+            self.gauge_dims[gid.value] = self.gauge_dims[base]
+        return gid.value
+
+    def get_gauge(self, gid, out):
+        p, dev = _ptr(out)
+        self._check(self.lib.ddml_get_gauge(self.h, gid, p, dev))
+        return out
 
     def release_gauge(self, gid):
         self._check(self.lib.ddml_release_gauge(self.h, gid))
