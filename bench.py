@@ -4,8 +4,9 @@
 Workload (one "step" = one level-1 update round of the two-level scheme):
   32^3 x 64 lattice, quenched beta = 6.0 field, kappa = 0.1340, c_sw = 1.769,
   antiperiodic time; 4 time slabs of 16 slices, each updated independently by
-  one heatbath sweep with its first-slice spatial links frozen (Section 3.1);
-  for every slab update: the new gauge version is uploaded and its clover term
+  one heatbath sweep with its first-slice spatial links frozen (Section 3.1),
+  on the device, each slab's chain starting from its previous update;
+  for every slab update: the new gauge version's clover term is
   built, then the nested Dirichlet domains Gamma0 (4 slices), Gamma1 (8) and
   Gamma2 (the 16-slice slab) are solved for 12 point-source columns to a
   relative residual of 1e-10 (FP32 inner BiCGstab, FP64 defect correction),
@@ -180,18 +181,6 @@ def main():
         ctx.close()
         print(json.dumps({"factorized_pion": out}), flush=True)
         return 0
-    t = time.time()
-    Uw = np.ascontiguousarray(U0.copy())
-    regions = []   # [step][slab] device tensors of the slab's links after the update
-    for j in range(nsteps):
-        row = []
-        for s in range(nslab):
-            inputs.level1_update_inplace(Uw, L, beta, seed, 1000 + j * nslab + s, 16 * s, 16 * s + 16,
-                                         nsweeps=1, n_or=0)
-            reg = np.ascontiguousarray(Uw[16 * s * V3:(16 * s + 16) * V3])
-            row.append(torch.from_numpy(reg).to(dev))
-        regions.append(row)
-    log("level-1 updates: %d x %d slabs (%.1fs)" % (nsteps, nslab, time.time() - t))
     U0_dev = torch.from_numpy(U0).to(dev)
     srcs, terms = [], []
     xs = []
@@ -221,8 +210,21 @@ def main():
     log("autotune fp32 R=%d order=%d grid=%d splits=%d stage=%d (%.3f ms/pair); "
         "fp64 R=%d order=%d grid=%d splits=%d stage=%d (%.3f ms/pair)" % (tune32 + tune64))
 
-    def step(j, prm=params, batched=True):
-        gids = [ctx.set_gauge_region(gid0, 16 * s, 16 * s + 16, regions[j][s]) for s in range(nslab)]
+    def advance(prev, j):
+        """The level-1 update round j: every slab's chain moves on by one sweep
+        (heatbath, first-slice spatial links frozen) on the device."""
+        return [ctx.level1_update(prev[s], 16 * s, 16 * s + 16, beta, seed, 3 + 1000 + j * nslab + s, 1, 0)
+                for s in range(nslab)]
+
+    def release(gids):
+        for g in gids:
+            if g != gid0:
+                ctx.release_gauge(g)
+
+    def step(prev, j, prm=params, batched=True, update=True):
+        gids = advance(prev, j) if update else prev
+        if update:
+            release(prev)   # the previous round's versions and their operator data
         if batched:
             rc, infos = ctx.propagator_series_batch(
                 [(gids[s], doms[s], srcs[s], terms[s], None) for s in range(nslab)], 12, prm)
@@ -239,19 +241,30 @@ def main():
         nuc = [ctx.contract_nucleon(terms[s], 3) for s in range(nslab)]
         pp = [ctx.contract_pp_disconnected(terms[s], terms[(s + 2) % nslab], 3, xs[s], xs[(s + 2) % nslab])
               for s in range(nslab // 2)]
-        for g in gids:
-            ctx.release_gauge(g)
-        return rc, infos, nuc, pp
+        return gids, rc, infos, nuc, pp
+
+    # device level-1 generator on its own: one round of the 4 slab updates
+    chain = [gid0] * nslab
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    trial = advance(chain, 0)
+    torch.cuda.synchronize()
+    l1_ms = 1e3 * (time.perf_counter() - a) / nslab
+    release(trial)
+    nlinks = 16 * V3 * 4 - V3 * 3
+    level1 = {"ms_per_slab_update": l1_ms, "links_per_s": nlinks / (l1_ms * 1e-3),
+              "slab": "16 x %d^3, 1 heatbath sweep, spatial links of the first slice frozen" % L[1]}
+    log("level-1 update: %.2f ms per 16-slice slab (%.3g links/s)" % (l1_ms, level1["links_per_s"]))
 
     # ------------------------------------------------------------ timed
     for j in range(args.warmup):
-        rc, infos, _, _ = step(j)
+        chain, rc, infos, _, _ = step(chain, j)
         log("warmup step %d rc %d" % (j, rc))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters, worst = [], 0.0
     for j in range(args.warmup, nsteps):
-        rc, infos, nuc, pp = step(j)
+        chain, rc, infos, nuc, pp = step(chain, j)
         assert rc == ddml.OK, "solve failed: %s" % ctx.last_error()
         for per_slab in infos:
             for per_level in per_slab:
@@ -270,12 +283,14 @@ def main():
     if not args.no_fp16:
         tune16 = ctx.autotune(gid0, doms[0][2], 12, ddml.MIXED_FP16)
         prm16 = ddml.solver_params(tol=1e-10, prec=ddml.MIXED_FP16)
-        rc, _, _, _ = step(0, prm16)   # warm-up (graph capture)
+        chain16 = [gid0] * nslab   # the same chains again, solved with 16-bit storage
+        for j in range(args.warmup):
+            chain16, rc, _, _, _ = step(chain16, j, prm16)   # warm-up (graph capture)
         torch.cuda.synchronize()
         a = time.perf_counter()
         it16, outer16, worst16 = [], [], 0.0
         for j in range(args.warmup, nsteps):
-            rc, infos, _, _ = step(j, prm16)
+            chain16, rc, infos, _, _ = step(chain16, j, prm16)
             assert rc == ddml.OK, "16-bit solve failed: %s" % ctx.last_error()
             for per_slab in infos:
                 for per_level in per_slab:
@@ -284,6 +299,7 @@ def main():
                     worst16 = max(worst16, max(i.true_rel_residual for i in per_level))
         torch.cuda.synchronize()
         b = time.perf_counter()
+        release(chain16)
         s16 = ctx.time_stencil(gid0, doms[0][2], 12, ddml.MIXED_FP16, args.stencil_iters)
         fp16 = {"solves_per_s": nsolves / (b - a), "ms_per_step": 1e3 * (b - a) / args.steps,
                 "inner_iters_per_solve": it16, "outer_iters_per_solve": outer16,
@@ -310,7 +326,7 @@ def main():
         prm64 = ddml.solver_params(tol=1e-10, prec=ddml.FP64)
         torch.cuda.synchronize()
         a = time.perf_counter()
-        rc, infos, _, _ = step(nsteps - 1, prm64, batched=False)
+        _, rc, infos, _, _ = step(chain, nsteps - 1, prm64, batched=False, update=False)   # the last round's fields
         torch.cuda.synchronize()
         b = time.perf_counter()
         fp64 = {"solves_per_s": 3 * nslab / (b - a), "mode": "FP64 inner and outer, one solve at a time",
@@ -321,7 +337,7 @@ def main():
     # the series buffers of the multi-level workload are not needed any more
     terms.clear()
     srcs.clear()
-    regions.clear()
+    release(chain)
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     fact = None
@@ -378,6 +394,7 @@ def main():
         "projected_pion": proj,
         "inner_iters_per_solve": iters,
         "worst_true_rel_residual": worst,
+        "level1_update": level1,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -258,6 +258,24 @@ int ddml_propagator_series_batch(ddml_ctx ctx, int nseries, const ddml_series_de
 int ddml_contract_pp_disconnected(ddml_ctx ctx, const double* terms_x, const double* terms_y, int nlevels,
                                   const int xsrc[4], const int ysrc[4], double* out, int on_device, void* stream);
 
+/* Two-level estimator (Section 3.1; the bins follow the averaging of the
+ * numerical part of Section 6).  n0 level-0 fields; for each, n1 level-1
+ * updates of region A and, independently, n1 of region B.  a[n0][n1][nc][ma]
+ * are measurements of a factor that depends on A's links only (e.g. the
+ * per-slice traces tr{g5 D_Gamma0^{-1}} of eq. W0), b[n0][n1][nc][mb] of B's
+ * factor.  For each level-0 field i the level-1 means [a]_i, [b]_i are taken
+ * separately and multiplied, contracting c:
+ *   P_i[x][y] = sum_c [a]_i[c][x] [b]_i[c][y],
+ * est_f[ma][mb] = mean over i of P_i, err_f its standard error over the n0
+ * values (0 when n0 = 1).  rest[n0][n1][k] (k >= 0; may be NULL when k = 0):
+ * the other pieces (e.g. the r1, r2 parts), averaged in bins of n1 per
+ * level-0 field; est_r[k], err_r[k] = mean and standard error of the n0 bin
+ * means.  Host memory, caller owned, real values (complex data: real and
+ * imaginary parts as separate c or k entries).  No context needed.
+ * Errors: EINVAL (sizes < 1, NULL pointers). */
+int ddml_two_level_average(int n0, int n1, int nc, int ma, int mb, const double* a, const double* b, int k,
+                           const double* rest, double* est_f, double* err_f, double* est_r, double* err_r);
+
 /* Nucleon two-point function (eq. baryfact, eq. baryN) for each level of a
  * 12-column point-source series: levels_out[i][y0] = sum_{y in slice y0}
  * (W_N1 - W_N2)(y, x) with S = S^(i) (partial sums of terms), and

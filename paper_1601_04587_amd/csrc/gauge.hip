@@ -577,6 +577,7 @@ struct LinkDraws {
 __device__ void wilson_staples(const GaugeView& gv, const int L[4], const int x[4], int mu, double2 A[9]) {
 #pragma unroll
   for (int k = 0; k < 9; ++k) A[k] = make_double2(0, 0);
+#pragma unroll 1
   for (int nu = 0; nu < 4; ++nu) {
     if (nu == mu) continue;
     double2 a[9], b[9], t[9], w[9];
@@ -627,10 +628,18 @@ __device__ void level1_link(double2 U[9], const double2 A[9], double beta, int n
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const int i = k == 2 ? 1 : 0, j = k == 0 ? 1 : 2;
-      double2 W[9];
-      m3(U, false, A, false, W);
-      const double q[4] = {0.5 * (W[3 * i + i].x + W[3 * j + j].x), 0.5 * (W[3 * i + j].y + W[3 * j + i].y),
-                           0.5 * (W[3 * i + j].x - W[3 * j + i].x), 0.5 * (W[3 * i + i].y - W[3 * j + j].y)};
+      // the 2x2 block (rows and columns i, j) of W = U A
+      double2 wii = make_double2(0, 0), wij = wii, wji = wii, wjj = wii;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double2 ui = U[3 * i + c], uj = U[3 * j + c], ai = A[3 * c + i], aj = A[3 * c + j];
+        wii = make_double2(wii.x + ui.x * ai.x - ui.y * ai.y, wii.y + ui.x * ai.y + ui.y * ai.x);
+        wij = make_double2(wij.x + ui.x * aj.x - ui.y * aj.y, wij.y + ui.x * aj.y + ui.y * aj.x);
+        wji = make_double2(wji.x + uj.x * ai.x - uj.y * ai.y, wji.y + uj.x * ai.y + uj.y * ai.x);
+        wjj = make_double2(wjj.x + uj.x * aj.x - uj.y * aj.y, wjj.y + uj.x * aj.y + uj.y * aj.x);
+      }
+      const double q[4] = {0.5 * (wii.x + wjj.x), 0.5 * (wij.y + wji.y), 0.5 * (wij.x - wji.x),
+                           0.5 * (wii.y - wjj.y)};
       const double norm = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
       if (norm < 1e-14) continue;
       const double vd[4] = {q[0] / norm, -q[1] / norm, -q[2] / norm, -q[3] / norm};
@@ -689,28 +698,30 @@ __device__ void level1_link(double2 U[9], const double2 A[9], double beta, int n
   U[8] = cross(0, 4, 1, 3);
 }
 
+// One thread per link of the class: sites of parity `par` in slices
+// [t0, t1) (spatial directions: [t0 + 1, t1)), enumerated as pairs along x3.
 __global__ void __launch_bounds__(128) k_level1_class(GaugeView gv, double2* __restrict__ region, BlockSpec bs,
                                                        int mu, int par, double beta, uint32_t k0, uint32_t k1,
                                                        int sweep, int n_or) {
-  const int t0 = gv.r_t0, t1 = gv.r_t1;
-  const size_t V3 = (size_t)bs.L[1] * bs.L[2] * bs.L[3];
-  const size_t n = (size_t)(t1 - t0) * V3;
+  const int ta = gv.r_t0 + (mu != 0), t1 = gv.r_t1;  // frozen spatial links of the first slice
+  const int h3 = bs.L[3] / 2;
+  const size_t rows = (size_t)(t1 - ta) * bs.L[1] * bs.L[2];
+  const size_t n = rows * h3;
   for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
-    const size_t s = (size_t)t0 * V3 + k;
     int x[4];
-    size_t r = s;
-    x[3] = (int)(r % bs.L[3]); r /= bs.L[3];
+    size_t r = k / h3;
+    const int j = (int)(k - r * h3);
     x[2] = (int)(r % bs.L[2]); r /= bs.L[2];
     x[1] = (int)(r % bs.L[1]);
-    x[0] = (int)(r / bs.L[1]);
-    if (((x[0] + x[1] + x[2] + x[3]) & 1) != par) continue;
-    if (mu != 0 && x[0] == t0) continue;  // frozen spatial links of the first slice
+    x[0] = ta + (int)(r / bs.L[1]);
+    x[3] = 2 * j + ((par + x[0] + x[1] + x[2]) & 1);
+    const size_t s = gidx(bs.L, x);
     double2 A[9], U[9];
     wilson_staples(gv, bs.L, x, mu, A);
     load_link(gv, bs.L, x, mu, U);
     LinkDraws d{k0, k1, (uint32_t)s, (uint32_t)(mu | (sweep << 2)), 0u, 0u, 0u, 0u, 0u, 0};
     level1_link(U, A, beta, n_or, d);
-    double2* dst = region + (k * 4 + mu) * 9;
+    double2* dst = region + ((s - (size_t)gv.r_t0 * bs.L[1] * bs.L[2] * bs.L[3]) * 4 + mu) * 9;
 #pragma unroll
     for (int c = 0; c < 9; ++c) dst[c] = U[c];
   }
@@ -718,7 +729,7 @@ __global__ void __launch_bounds__(128) k_level1_class(GaugeView gv, double2* __r
 
 hipError_t launch_level1_sweeps(const GaugeView& gv, double2* region, const BlockSpec& bs, double beta,
                                 uint64_t seed, uint32_t stream, int nsweeps, int n_or, hipStream_t st) {
-  const size_t n = (size_t)(gv.r_t1 - gv.r_t0) * bs.L[1] * bs.L[2] * bs.L[3];
+  const size_t n = (size_t)(gv.r_t1 - gv.r_t0) * bs.L[1] * bs.L[2] * bs.L[3] / 2;
   size_t grid = (n + 127) / 128;
   if (grid > 16384) grid = 16384;
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32) ^ (stream * 0x85EBCA6Bu);

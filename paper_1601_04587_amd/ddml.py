@@ -70,7 +70,7 @@ EXPORTS = ["ddml_create", "ddml_destroy", "ddml_last_error", "ddml_set_gauge", "
            "ddml_release_gauge", "ddml_set_domain", "ddml_apply_Dw", "ddml_apply_eo", "ddml_solve_domain",
            "ddml_solve_batch", "ddml_propagator_series", "ddml_propagator_series_batch", "ddml_time_stencil", "ddml_autotune", "ddml_set_launch", "ddml_contract_pp_disconnected", "ddml_contract_nucleon",
            "ddml_apply_boundary", "ddml_factorized_series", "ddml_contract_pion", "ddml_hpe_trace",
-           "ddml_inverse_iteration", "ddml_projected_pion",
+           "ddml_inverse_iteration", "ddml_projected_pion", "ddml_two_level_average",
            "ddml_server_start", "ddml_submit", "ddml_poll", "ddml_wait", "ddml_stats", "ddml_server_stop",
            "ddml_now"]
 
@@ -96,6 +96,7 @@ def load():
     lib.ddml_set_gauge_region.argtypes = [P, I, I, I, P, I, IP]
     lib.ddml_level1_update.argtypes = [P, I, I, I, D, ctypes.c_uint64, ctypes.c_uint32, I, I, IP]
     lib.ddml_get_gauge.argtypes = [P, I, P, I]
+    lib.ddml_two_level_average.argtypes = [I, I, I, I, I, P, P, I, P, P, P, P, P]
     lib.ddml_release_gauge.argtypes = [P, I]
     lib.ddml_set_domain.argtypes = [P, IP, IP, IP]
     lib.ddml_apply_Dw.argtypes = [P, I, I, P, P, I, I, I, P]
@@ -143,6 +144,33 @@ def solver_params(tol=1e-10, max_outer=12, max_inner=4000, inner_tol=1e-5, prec=
     """solver 0: BiCGstab restarted at each FP64 correction; 1: BiCGstab with
     reliable updates; 2: GCR(gcr_m) (gcr_m 0 = 8)."""
     return SolverParams(tol, max_outer, max_inner, inner_tol, prec, solver, gcr_m)
+
+
+def two_level_average(a, b, rest=None):
+    """ddml_two_level_average: a [n0, n1, nc, ma], b [n0, n1, nc, mb], rest
+    [n0, n1, k] or None (host float64).  Returns (est_f, err_f) [ma, mb] and,
+    with rest, (est_r, err_r) [k]."""
+    lib = load()
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    if a.ndim != 4 or b.ndim != 4 or a.shape[:3] != b.shape[:3]:
+        raise ValueError("a and b must be [n0, n1, nc, m] with the same n0, n1, nc")
+    n0, n1, nc, ma = a.shape
+    mb = b.shape[3]
+    est, err = np.zeros((ma, mb)), np.zeros((ma, mb))
+    k = 0
+    if rest is not None:
+        rest = np.ascontiguousarray(rest, dtype=np.float64)
+        if rest.ndim != 3 or rest.shape[:2] != (n0, n1):
+            raise ValueError("rest must be [n0, n1, k]")
+        k = rest.shape[2]
+    est_r, err_r = np.zeros(k), np.zeros(k)
+    rc = lib.ddml_two_level_average(n0, n1, nc, ma, mb, a.ctypes.data, b.ctypes.data, k,
+                                    rest.ctypes.data if k else None, est.ctypes.data, err.ctypes.data,
+                                    est_r.ctypes.data, err_r.ctypes.data)
+    if rc != OK:
+        raise DDMLError(rc, "ddml_two_level_average: bad sizes")
+    return (est, err, est_r, err_r) if rest is not None else (est, err)
 
 
 def _ptr(a):
