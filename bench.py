@@ -241,7 +241,8 @@ def main():
         nuc = [ctx.contract_nucleon(terms[s], 3) for s in range(nslab)]
         pp = [ctx.contract_pp_disconnected(terms[s], terms[(s + 2) % nslab], 3, xs[s], xs[(s + 2) % nslab])
               for s in range(nslab // 2)]
-        return gids, rc, infos, nuc, pp
+        tr = [ctx.trace_g5(terms[s], 3, xs[s]) for s in range(nslab)]   # factors of the two-level estimator
+        return gids, rc, infos, nuc, (pp, tr)
 
     # device level-1 generator on its own: one round of the 4 slab updates
     chain = [gid0] * nslab
@@ -263,8 +264,10 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters, worst = [], 0.0
+    meas = []   # per timed round: (pp pieces, traces)
     for j in range(args.warmup, nsteps):
         chain, rc, infos, nuc, pp = step(chain, j)
+        meas.append(pp)
         assert rc == ddml.OK, "solve failed: %s" % ctx.last_error()
         for per_slab in infos:
             for per_level in per_slab:
@@ -277,6 +280,9 @@ def main():
     ms_per_step = 1e3 * (t1 - t0) / args.steps
     log("mixed batched: %d solves in %.2fs -> %.3f solves/s, worst residual %.2e, inner iters %s"
         % (nsolves, t1 - t0, solves_per_s, worst, iters[:6]))
+
+    two_level = two_level_pp(ddml, meas, nslab, L)
+    log("two-level disconnected PP (n0 = 1, n1 = %d): f %s" % (args.steps, two_level["f"]))
 
     # ------------------------------------ 16-bit storage of the inner solve
     fp16 = None
@@ -395,10 +401,36 @@ def main():
         "inner_iters_per_solve": iters,
         "worst_true_rel_residual": worst,
         "level1_update": level1,
+        "two_level_pp": two_level,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     return 0
+
+
+def two_level_pp(ddml, meas, nslab, L):
+    """Two-level estimate (Section 3.1) of the disconnected pseudoscalar pieces
+    for the slab pairs (s, s + 2): the factorized part f = [t_x][t_y] / L^3 from
+    the level-1 means of the two traces, each over its own slab's updates, and
+    r1, r2 binned over the updates.  One level-0 field here (n0 = 1), so no
+    error estimate; the rounds of the timed loop are the level-1 updates."""
+    L3 = float(np.prod(L[1:]))
+    n1 = len(meas)
+    out = {"n0": 1, "n1": n1, "pairs": [], "f": [], "r1": [], "r2": []}
+    for s in range(nslab // 2):
+        y = (s + 2) % nslab
+        tx = np.array([m[1][s] for m in meas])    # [n1, levels] complex
+        ty = np.array([m[1][y] for m in meas])
+        a = np.stack([tx.real, tx.imag], axis=1)[None]            # [1, n1, 2, levels]
+        b = np.stack([ty.real, -ty.imag], axis=1)[None]           # Re(t_x t_y) = sum_c a_c b_c
+        rest = np.array([np.concatenate([m[0][s][:, 1].real, m[0][s][:, 2].real]) for m in meas])[None]
+        est, _, est_r, _ = ddml.two_level_average(a, b, rest)
+        nl = tx.shape[1]
+        out["pairs"].append([s, y])
+        out["f"].append([est[i, i] / L3 for i in range(nl)])
+        out["r1"].append(list(est_r[:nl]))
+        out["r2"].append(list(est_r[nl:]))
+    return out
 
 
 SERVE_MIX = [((16, 8, 8, 8), (4, 12), 1601051), ((16, 16, 16, 16), (4, 12), 1601052),

@@ -258,6 +258,14 @@ int ddml_propagator_series_batch(ddml_ctx ctx, int nseries, const ddml_series_de
 int ddml_contract_pp_disconnected(ddml_ctx ctx, const double* terms_x, const double* terms_y, int nlevels,
                                   const int xsrc[4], const int ysrc[4], double* out, int on_device, void* stream);
 
+/* t[i] = tr{g5 S^(i)(x,x)} (eq. W0, without the 1/L^3) for each level of a
+ * 12-column point-source series around x, S^(i) the partial sum of terms up
+ * to i: the factors whose level-1 means the two-level estimator multiplies.
+ * terms [nlevels][12][V][4][3] complex (as for ddml_contract_pp_disconnected),
+ * out[nlevels] complex on the host.  Errors: EINVAL, EDEVICE. */
+int ddml_trace_g5(ddml_ctx ctx, const double* terms, int nlevels, const int xsrc[4], double* out, int on_device,
+                  void* stream);
+
 /* Two-level estimator (Section 3.1; the bins follow the averaging of the
  * numerical part of Section 6).  n0 level-0 fields; for each, n1 level-1
  * updates of region A and, independently, n1 of region B.  a[n0][n1][nc][ma]

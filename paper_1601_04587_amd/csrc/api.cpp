@@ -678,6 +678,26 @@ int ddml_contract_pp_disconnected(ddml_ctx ctx, const double* terms_x, const dou
   });
 }
 
+int ddml_trace_g5(ddml_ctx ctx, const double* terms, int nlevels, const int xsrc[4], double* out, int on_device,
+                  void* stream) {
+  return guarded(ctx, [&](Ctx* c) {
+    need(terms && xsrc && out && nlevels >= 1 && nlevels <= 64, "bad arguments");
+    const int* L = c->lat.dims;
+    for (int m = 0; m < 4; ++m) need(xsrc[m] >= 0 && xsrc[m] < L[m], "bad site");
+    const size_t bytes = (size_t)nlevels * 12 * c->V * 12 * sizeof(double2);
+    StreamJoin sj(c, stream);
+    Staged st = stage_in(c, terms, bytes, on_device);
+    DBuf o(c->pool.get(), (size_t)nlevels * sizeof(double2));
+    const size_t xs = (((size_t)xsrc[0] * L[1] + xsrc[1]) * L[2] + xsrc[2]) * L[3] + xsrc[3];
+    DDML_HIP(launch_g5_traces(reinterpret_cast<const double2*>(st.cptr), c->V, nlevels, xs, o.as<double2>(),
+                              c->stream));
+    DDML_HIP(hipMemcpyAsync(out, o.p, (size_t)nlevels * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
+    DDML_HIP(hipStreamSynchronize(c->stream));
+    sj.done();
+    return DDML_OK;
+  });
+}
+
 int ddml_contract_nucleon(ddml_ctx ctx, const double* terms, int nlevels, double* levels_out, double* diffs_out,
                           int on_device, void* stream) {
   return guarded(ctx, [&](Ctx* c) {

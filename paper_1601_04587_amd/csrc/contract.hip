@@ -75,6 +75,17 @@ __global__ void k_pp(const double2* __restrict__ tx_terms, const double2* __rest
   out[4 * i + 3] = make_double2(full.x * invL3, full.y * invL3);
 }
 
+__global__ void k_g5_traces(const double2* __restrict__ terms, size_t V, int nlevels, size_t xs,
+                            double2* __restrict__ out) {
+  const int i = threadIdx.x;
+  if (i < nlevels) out[i] = g5_trace(terms, V, i, xs);
+}
+
+hipError_t launch_g5_traces(const double2* terms, size_t V, int nlevels, size_t xs, double2* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_g5_traces, dim3(1), dim3(64), 0, st, terms, V, nlevels, xs, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_pp(const double2* tx, const double2* ty, size_t V, int nlevels, size_t xs, size_t ys, double invL3,
                      double2* out, hipStream_t st) {
   hipLaunchKernelGGL(k_pp, dim3(1), dim3(64), 0, st, tx, ty, V, nlevels, xs, ys, invL3, out);

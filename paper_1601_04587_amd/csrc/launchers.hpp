@@ -104,6 +104,8 @@ hipError_t launch_boundary(const GaugeView& gv, const BlockSpec& bs, const doubl
 
 // contract.hip
 hipError_t launch_series_diff(double2* terms, size_t n, int nlevels, double2* sum, hipStream_t st);
+// out[i] = tr{g5 S^(i)(x,x)}, S^(i) the partial sums of a 12-column series (nlevels <= 64)
+hipError_t launch_g5_traces(const double2* terms, size_t V, int nlevels, size_t xs, double2* out, hipStream_t st);
 hipError_t launch_pp(const double2* tx, const double2* ty, size_t V, int nlevels, size_t xs, size_t ys, double invL3,
                      double2* out, hipStream_t st);
 // connected pion: W scratch [nprops][V]; sums [nprops][T] of tr{S S^dag} per time slice

@@ -70,7 +70,7 @@ EXPORTS = ["ddml_create", "ddml_destroy", "ddml_last_error", "ddml_set_gauge", "
            "ddml_release_gauge", "ddml_set_domain", "ddml_apply_Dw", "ddml_apply_eo", "ddml_solve_domain",
            "ddml_solve_batch", "ddml_propagator_series", "ddml_propagator_series_batch", "ddml_time_stencil", "ddml_autotune", "ddml_set_launch", "ddml_contract_pp_disconnected", "ddml_contract_nucleon",
            "ddml_apply_boundary", "ddml_factorized_series", "ddml_contract_pion", "ddml_hpe_trace",
-           "ddml_inverse_iteration", "ddml_projected_pion", "ddml_two_level_average",
+           "ddml_inverse_iteration", "ddml_projected_pion", "ddml_two_level_average", "ddml_trace_g5",
            "ddml_server_start", "ddml_submit", "ddml_poll", "ddml_wait", "ddml_stats", "ddml_server_stop",
            "ddml_now"]
 
@@ -96,6 +96,7 @@ def load():
     lib.ddml_set_gauge_region.argtypes = [P, I, I, I, P, I, IP]
     lib.ddml_level1_update.argtypes = [P, I, I, I, D, ctypes.c_uint64, ctypes.c_uint32, I, I, IP]
     lib.ddml_get_gauge.argtypes = [P, I, P, I]
+    lib.ddml_trace_g5.argtypes = [P, P, I, IP, P, I, P]
     lib.ddml_two_level_average.argtypes = [I, I, I, I, I, P, P, I, P, P, P, P, P]
     lib.ddml_release_gauge.argtypes = [P, I]
     lib.ddml_set_domain.argtypes = [P, IP, IP, IP]
@@ -445,6 +446,13 @@ class Context:
         self._check(self.lib.ddml_contract_pp_disconnected(self.h, px, py, nlevels, (ctypes.c_int * 4)(*xsrc),
                                                            (ctypes.c_int * 4)(*ysrc), out.ctypes.data, dev,
                                                            _stream(terms_x)))
+        return out
+
+    def trace_g5(self, terms, nlevels, xsrc):
+        out = np.zeros(nlevels, dtype=np.complex128)
+        pt, dev = _ptr(terms)
+        self._check(self.lib.ddml_trace_g5(self.h, pt, nlevels, (ctypes.c_int * 4)(*xsrc), out.ctypes.data, dev,
+                                           _stream(terms)))
         return out
 
     def contract_nucleon(self, terms, nlevels):

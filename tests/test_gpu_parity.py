@@ -206,6 +206,9 @@ def test_series_and_contractions_config1(cfg1):
     pp_gpu = ctx.contract_pp_disconnected(terms, terms, 3, xs, xs)
     pp_ref = oracle.contract_pp_disconnected(terms, terms, s, s, 8 ** 3)
     assert np.abs(pp_gpu - pp_ref).max() <= 1e-12 * np.abs(pp_ref).max()
+    tr_gpu = ctx.trace_g5(terms, 3, xs)
+    tr_ref = np.array([oracle.pp_trace(cum[i], s) for i in range(3)])
+    assert np.abs(tr_gpu - tr_ref).max() <= 1e-12 * np.abs(tr_ref).max()
     lev_gpu, diff_gpu = ctx.contract_nucleon(terms, 3)
     lev_ref, diff_ref = oracle.contract_nucleon(terms, L)
     assert np.abs(lev_gpu - lev_ref).max() <= 1e-12 * np.abs(lev_ref).max()
