@@ -28,6 +28,12 @@ Contents and the passages they follow:
       D_{Gammabar}^{-1} (Section 5.2, eq. approxlong), the bottom-left block of
       eq. Scmpt2 with the exact Schur-complement inverse replaced by the
       propagator of the larger domain Gammabar.
+  * ``factorized_chain``: the multi-slab product of Section 4 (steps 1-3,
+      eqs. stp2, dec1, fctpr): psi_0 = D_{Omega_{m+2}}^{-1} b, then for each
+      thick slab Omega*_i = Lambda_i u Lambda_{i+1} in turn
+      psi_i = -D_{Omega*_i}^{-1} D_{Lambda_{i,i-1}} psi_{i-1}; the last one is
+      S^(f) b on Omega*_l.  D_{Lambda_{i,i-1}} is the block of D itself (the
+      same reading of eq. fact3 as for D_{dGamma}).
   * ``pion_connected``/``contract_pion``: C_Pc(y0) = -(1/L^3) sum tr{S S^dag}
       (eqs. pipi, W0pc) and its expansion in the overlap thickness Delta
       (eqs. decpi, seriespi, with the rest W^(r) = W - W^(f) of eq. W0pc2).
@@ -422,6 +428,23 @@ def factorized_propagator(U, L, kappa, b, bar, star, C=None, antiperiodic=True, 
     bstar = -apply_boundary(U, L, psi, star[0], star[1], antiperiodic)
     sf, _, _ = solve(U, L, kappa, bstar, C=C, antiperiodic=antiperiodic, lo=star[0], hi=star[1], tol=tol)
     return sf, psi
+
+
+def factorized_chain(U, L, kappa, b, doms, C=None, antiperiodic=True, tol=1e-13):
+    """Multi-slab factorized propagator (Section 4, eq. fctpr) applied to b.
+
+    doms = [(lo, hi) of Omega_{m+2}, then of Omega*_{m+1}, ..., Omega*_l]:
+    psi_0 = D_{doms[0]}^{-1} b and psi_k = -D_{doms[k]}^{-1} D_{d doms[k]} psi_{k-1},
+    where D_{d doms[k]} keeps the entries of D from outside doms[k] into it
+    (of which only the hop out of the previous slab's last time slice meets
+    psi_{k-1}).  Returns the list [psi_0, ..., psi_{n-1}]."""
+    psi, _, _ = solve(U, L, kappa, b, C=C, antiperiodic=antiperiodic, lo=doms[0][0], hi=doms[0][1], tol=tol)
+    out = [psi]
+    for lo, hi in doms[1:]:
+        rhs = -apply_boundary(U, L, out[-1], lo, hi, antiperiodic)
+        psi, _, _ = solve(U, L, kappa, rhs, C=C, antiperiodic=antiperiodic, lo=lo, hi=hi, tol=tol)
+        out.append(psi)
+    return out
 
 
 def pion_W(sol):
