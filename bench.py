@@ -544,6 +544,7 @@ def run_factorized(ctx, ddml, torch, dev, U0_dev, L, kappa, csw, args):
     once()    # warm-up
     rc, infos, info_full, (C, diffs, rest), (ts, tf, tc) = once()
     assert rc == ddml.OK, "factorized series failed: %s" % ctx.last_error()
+    chain = run_chain(ctx, ddml, torch, gid, L, b, full, xsrc, prm) if T >= 48 else None
     ctx.release_gauge(gid)
     worst = max(x.true_rel_residual for per in infos for stage in per for x in stage)
     ys = [y for y in (xcut, xcut + 8, xcut + 16, xcut + 24, T - 1) if y < T]
@@ -555,9 +556,41 @@ def run_factorized(ctx, ddml, torch, dev, U0_dev, L, kappa, csw, args):
            "whole_lattice_inner_iters": max(x.inner_iters for x in info_full),
            "worst_true_rel_residual": worst,
            "C_levels": {str(y): [float(C[i, y]) for i in range(len(deltas))] for y in ys},
-           "C_rest": {str(y): float(rest[y]) for y in ys}}
+           "C_rest": {str(y): float(rest[y]) for y in ys},
+           "multi_slab_chain": chain}
     log("factorized pion: %s" % out)
     return out
+
+
+def run_chain(ctx, ddml, torch, gid, L, b, full, xsrc, prm, delta=8):
+    """Section 4 workload (eq. fctpr): the lattice cut in thick slices of
+    Delta = 8, the source in Lambda_0, sinks in Lambda_6 = [48, 56): the chain
+    Omega_2 = [0, 16) (open boundary: no Lambda_{-1}), then Omega*_i =
+    Lambda_i u Lambda_{i+1} for i = 1 .. 6, seven solves one after the other.
+    Reported: the time, and C_Pc on the sink slices against the whole-lattice
+    propagator (eq. errorfact)."""
+    T = L[0]
+    m, l = xsrc[0] // delta, 6
+    blocks = [(max(0, (m - 1) * delta), (m + 2) * delta)] + \
+             [(i * delta, min((i + 2) * delta, T)) for i in range(m + 1, l + 1)]
+    doms = [ctx.set_domain((t0, 0, 0, 0), (t1,) + tuple(L[1:])) for t0, t1 in blocks]
+    out = torch.zeros_like(full)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    rc, infos = ctx.factorized_chain(gid, doms, b, 12, out, None, prm)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - a
+    assert rc == ddml.OK, "chain failed: %s" % ctx.last_error()
+    C, _, rest = ctx.contract_pion(out[None], 1, full)
+    ys = [l * delta, l * delta + delta // 2, (l + 1) * delta - 1]
+    res = {"delta": delta, "domains": [list(x) for x in blocks], "source": list(xsrc), "s": t,
+           "solves_per_s": len(doms) / t,
+           "inner_iters": [max(x.inner_iters for x in inf) for inf in infos],
+           "C_chain": {str(y): float(C[0, y]) for y in ys},
+           "C_exact": {str(y): float(C[0, y] + rest[y]) for y in ys},
+           "rel_error": {str(y): float(abs(rest[y] / (C[0, y] + rest[y]))) for y in ys}}
+    log("multi-slab chain: %s" % res)
+    return res
 
 
 def run_hpe(ctx, ddml, torch, dev, gid, L, args):

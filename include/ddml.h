@@ -325,6 +325,29 @@ int ddml_factorized_series(ddml_ctx ctx, int gauge_id, const int* bar_ids, int n
                            const double* src, int nrhs, const ddml_solver_params* params, double* levels_out,
                            double* bar_out, ddml_rhs_info* info, int on_device, void* stream);
 
+/* Multi-slab factorized propagator (Section 4, steps 1-3, eqs. stp2, dec1,
+ * fctpr): with the lattice cut in thick time slices Lambda_i, a source in
+ * Lambda_m and sinks in Lambda_l (l > m),
+ *   psi_0 = D_{Omega_{m+2}}^{-1} src,          Omega_{m+2} = Lambda_{m-1..m+1},
+ *   psi_k = -D_{Omega*_i}^{-1} D_{Lambda_{i,i-1}} psi_{k-1},
+ *           Omega*_i = Lambda_i u Lambda_{i+1}, i = m+k, k = 1 .. l-m,
+ * and psi_{l-m} = S^(f) src on Omega*_l, a product in which each factor
+ * depends on the links of two or three thick slices only.  dom_ids[0..ndom)
+ * name Omega_{m+2}, Omega*_{m+1}, ..., Omega*_l (any domains: each step
+ * applies the boundary block of dom_ids[k], the entries of D from outside the
+ * domain into it, to psi_{k-1}, as ddml_apply_boundary with scale -1).  The
+ * solves run one after the other (each needs the previous one), each over the
+ * nrhs columns at once (as ddml_solve_domain, same params).
+ *   src       [nrhs][V][4][3]
+ *   out       [nrhs][V][4][3]: psi_{ndom-1}, zero outside dom_ids[ndom-1]
+ *   steps_out [ndom][nrhs][V][4][3] or NULL: every psi_k
+ *   info      [ndom][nrhs]
+ * Errors: EINVAL, ENOMEM, ENOTCONVERGED (info filled; later steps still run),
+ * EDEVICE. */
+int ddml_factorized_chain(ddml_ctx ctx, int gauge_id, const int* dom_ids, int ndom, const double* src, int nrhs,
+                          const ddml_solver_params* params, double* out, double* steps_out, ddml_rhs_info* info,
+                          int on_device, void* stream);
+
 /* Connected pseudoscalar correlator (eqs. pipi, W0pc):
  *   C(y0) = -(1/L^3) sum_{y in slice y0} tr{S(y,x) S(y,x)^dag}
  * for 12-column point-source propagators (the sum over the source position

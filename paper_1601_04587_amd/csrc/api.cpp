@@ -421,6 +421,57 @@ int ddml_factorized_series(ddml_ctx ctx, int gauge_id, const int* bar_ids, int n
   });
 }
 
+int ddml_factorized_chain(ddml_ctx ctx, int gauge_id, const int* dom_ids, int ndom, const double* src, int nrhs,
+                          const ddml_solver_params* params, double* out, double* steps_out, ddml_rhs_info* info,
+                          int on_device, void* stream) {
+  return guarded(ctx, [&](Ctx* c) {
+    need(dom_ids && src && out && info, "NULL argument");
+    need(ndom >= 1 && ndom <= 64, "ndom must be in 1..64");
+    need(nrhs >= 1 && nrhs <= kMaxRhs, "nrhs must be in 1..12");
+    check_params(params);
+    for (int k = 0; k < ndom; ++k) (void)domain_get(c, dom_ids[k]);
+    const size_t per = (size_t)nrhs * gauge_get(c, gauge_id).V * 12;  // complex numbers of one field
+    const size_t bytes = per * sizeof(double2);
+    StreamJoin sj(c, stream);
+    Staged si = stage_in(c, src, bytes, on_device);
+    Staged so = stage_out(c, out, bytes, on_device);
+    Staged ss;
+    if (steps_out) ss = stage_out(c, steps_out, bytes * ndom, on_device);
+    // psi_k goes to steps_out[k] when given, else it alternates between two
+    // buffers (the last step to out)
+    DBuf ping, pong;
+    if (!steps_out && ndom > 1) {
+      ping = DBuf(c->pool.get(), bytes);
+      if (ndom > 2) pong = DBuf(c->pool.get(), bytes);
+    }
+    DBuf rhs(c->pool.get(), ndom > 1 ? bytes : 0);
+    auto dest = [&](int k) -> double* {
+      if (steps_out) return ss.ptr + 2 * per * k;
+      if (k == ndom - 1) return so.ptr;
+      return (k % 2 ? pong : ping).as<double>();
+    };
+    int rc = DDML_OK;
+    for (int k = 0; k < ndom; ++k) {
+      const double* b = si.cptr;
+      if (k > 0) {
+        apply_boundary(c, gauge_id, dom_ids[k], dest(k - 1), rhs.as<double>(), nrhs, -1.0, c->stream);
+        b = rhs.as<double>();
+      }
+      ddml_solve_desc d{gauge_id, dom_ids[k], b, dest(k), nrhs, info + (size_t)k * nrhs};
+      const int r = solve_many(c, 1, &d, params, 1, c->stream);
+      if (rc == DDML_OK) rc = r;
+    }
+    if (steps_out) {
+      DDML_HIP(hipMemcpyAsync(so.ptr, ss.ptr + 2 * per * (ndom - 1), bytes, hipMemcpyDeviceToDevice, c->stream));
+      copy_back(c, steps_out, ss, bytes * ndom, on_device);
+    }
+    copy_back(c, out, so, bytes, on_device);
+    DDML_HIP(hipStreamSynchronize(c->stream));
+    sj.done();
+    return rc;
+  });
+}
+
 int ddml_contract_pion(ddml_ctx ctx, const double* levels, int nlevels, const double* full, double* levels_out,
                        double* diffs_out, double* rest_out, int on_device, void* stream) {
   return guarded(ctx, [&](Ctx* c) {

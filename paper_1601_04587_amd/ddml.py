@@ -69,7 +69,7 @@ EXPORTS = ["ddml_create", "ddml_destroy", "ddml_last_error", "ddml_set_gauge", "
            "ddml_set_gauge_region", "ddml_level1_update", "ddml_get_gauge",
            "ddml_release_gauge", "ddml_set_domain", "ddml_apply_Dw", "ddml_apply_eo", "ddml_solve_domain",
            "ddml_solve_batch", "ddml_propagator_series", "ddml_propagator_series_batch", "ddml_time_stencil", "ddml_autotune", "ddml_set_launch", "ddml_contract_pp_disconnected", "ddml_contract_nucleon",
-           "ddml_apply_boundary", "ddml_factorized_series", "ddml_contract_pion", "ddml_hpe_trace",
+           "ddml_apply_boundary", "ddml_factorized_series", "ddml_factorized_chain", "ddml_contract_pion", "ddml_hpe_trace",
            "ddml_inverse_iteration", "ddml_projected_pion", "ddml_two_level_average", "ddml_trace_g5",
            "ddml_server_start", "ddml_submit", "ddml_poll", "ddml_wait", "ddml_stats", "ddml_server_stop",
            "ddml_now"]
@@ -114,6 +114,7 @@ def load():
     lib.ddml_contract_pp_disconnected.argtypes = [P, P, P, I, IP, IP, P, I, P]
     lib.ddml_contract_nucleon.argtypes = [P, P, I, P, P, I, P]
     lib.ddml_apply_boundary.argtypes = [P, I, I, P, P, I, D, I, P]
+    lib.ddml_factorized_chain.argtypes = [P, I, IP, I, P, I, ctypes.POINTER(SolverParams), P, P, P, I, P]
     lib.ddml_factorized_series.argtypes = [P, I, IP, I, I, P, I, ctypes.POINTER(SolverParams), P, P,
                                            ctypes.POINTER(RhsInfo), I, P]
     lib.ddml_contract_pion.argtypes = [P, P, I, P, P, P, P, I, P]
@@ -375,6 +376,20 @@ class Context:
         self._check(rc, allow=(ENOTCONVERGED, ENUMERIC))
         return rc, [(list(info[(2 * i) * nrhs:(2 * i + 1) * nrhs]), list(info[(2 * i + 1) * nrhs:(2 * i + 2) * nrhs]))
                     for i in range(n)]
+
+    def factorized_chain(self, gid, doms, src, nrhs, out, steps=None, params=None):
+        """psi_0 = D_{doms[0]}^{-1} src, psi_k = -D_{doms[k]}^{-1} D_{d doms[k]} psi_{k-1};
+        out = the last psi.  Returns (rc, infos) with infos[k] the solve infos of step k."""
+        params = params or solver_params()
+        n = len(doms)
+        info = (RhsInfo * (n * nrhs))()
+        ps, dev = _ptr(src)
+        po, _ = _ptr(out)
+        pst = _ptr(steps)[0] if steps is not None else None
+        rc = self.lib.ddml_factorized_chain(self.h, gid, (ctypes.c_int * n)(*doms), n, ps, nrhs,
+                                            ctypes.byref(params), po, pst, info, dev, _stream(src))
+        self._check(rc, allow=(ENOTCONVERGED, ENUMERIC))
+        return rc, [list(info[k * nrhs:(k + 1) * nrhs]) for k in range(n)]
 
     def hpe_trace(self, gid, dom, eta, nsrc, p, params=None, psi_out=None, phi_out=None):
         """Stochastic trace estimates per time slice without and with the hopping

@@ -1,0 +1,164 @@
+"""GPU: multi-slab factorized propagator (Section 4, eqs. stp2, dec1, fctpr)
+against the oracle.
+
+* The 16x8^3 config-2 field cut in Delta = 2 slabs, source in Lambda_1,
+  sinks in Lambda_6 (open and antiperiodic time): every step psi_k against
+  the oracle's chain, and each step's FP64 residual with its right-hand side
+  rebuilt by the oracle from the GPU's previous step.
+* Two domains reproduce the two-domain factorization bit for bit.
+* At 32^3x64 with Delta = 8 (the benchmark's chain): residuals of every step
+  at sampled sites, the right-hand sides on their cut slices.
+Tolerances: each solve stops at relative residual 1e-10; the chain's fields
+then agree with the oracle's to 1e-7 relative (condition numbers below 1e3
+per step, as for the two-domain case).
+"""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+ddml = pytest.importorskip("paper_1601_04587_amd.ddml")
+torch = pytest.importorskip("torch")
+
+TOL = 1e-10
+REL = 1e-7
+KAPPA, CSW = 0.1340, 1.769
+
+
+def _block(L, t0, t1):
+    return ((t0, 0, 0, 0), (t1,) + tuple(L[1:]))
+
+
+def _chain_blocks(L, delta, m, l):
+    doms = [_block(L, (m - 1) * delta, (m + 2) * delta)]
+    doms += [_block(L, i * delta, min((i + 2) * delta, L[0])) for i in range(m + 1, l + 1)]
+    return doms
+
+
+@pytest.mark.parametrize("bc", [ddml.BC_OPEN, ddml.BC_ANTIPERIODIC])
+def test_chain_matches_the_oracle_step_by_step(bc):
+    L = (16, 8, 8, 8)
+    U = inputs.quenched_field(L, 1601002)
+    C = oracle.clover_term(U, L, CSW)
+    ap = oracle.OPEN if bc == ddml.BC_OPEN else True
+    blocks = _chain_blocks(L, 2, 1, 6)
+    x = (3, 2, 5, 1)
+    b = inputs.point_source(L, x)
+    V = int(np.prod(L))
+    ctx = ddml.Context(L, bc)
+    try:
+        gid = ctx.set_gauge(U, KAPPA, CSW)
+        doms = [ctx.set_domain(*d) for d in blocks]
+        out = np.zeros((12, V, 4, 3), complex)
+        steps = np.zeros((len(doms), 12, V, 4, 3), complex)
+        rc, infos = ctx.factorized_chain(gid, doms, b, 12, out, steps, ddml.solver_params(tol=TOL))
+        assert rc == ddml.OK, ctx.last_error()
+        assert np.array_equal(out, steps[-1])
+        # the same chain without the intermediate fields gives the same bits
+        out2 = np.zeros_like(out)
+        ctx.factorized_chain(gid, doms, b, 12, out2, None, ddml.solver_params(tol=TOL))
+        assert np.array_equal(out2, out)
+    finally:
+        ctx.close()
+    ref = oracle.factorized_chain(U, L, KAPPA, b, blocks, C=C, antiperiodic=ap)
+    for k, (lo, hi) in enumerate(blocks):
+        rhs = b if k == 0 else -oracle.apply_boundary(U, L, steps[k - 1], lo, hi, ap)
+        res = oracle.residual(U, L, KAPPA, rhs, steps[k], C=C, antiperiodic=ap, lo=lo, hi=hi)
+        assert res.max() <= TOL * (1 + 1e-3), (k, res.max())
+        assert np.abs(steps[k] - ref[k]).max() <= REL * np.abs(ref[k]).max(), k
+        assert all(i.status == ddml.OK for i in infos[k])
+        mk = oracle.domain_mask(L, lo, hi)
+        assert not steps[k][:, ~mk].any()
+
+
+def test_two_domains_reproduce_the_two_domain_factorization_bitwise():
+    L = (16, 8, 8, 8)
+    U = inputs.quenched_field(L, 1601002)
+    V = int(np.prod(L))
+    b = inputs.point_source(L, (2, 0, 0, 0))
+    ctx = ddml.Context(L, ddml.BC_OPEN)
+    try:
+        gid = ctx.set_gauge(U, KAPPA, CSW)
+        bar, star = ctx.set_domain(*_block(L, 0, 12)), ctx.set_domain(*_block(L, 8, 16))
+        prm = ddml.solver_params(tol=TOL)
+        out = np.zeros((12, V, 4, 3), complex)
+        ctx.factorized_chain(gid, [bar, star], b, 12, out, None, prm)
+        lev = np.zeros((1, 12, V, 4, 3), complex)
+        ctx.factorized_series(gid, [bar], star, b, 12, lev, None, prm)
+        assert np.array_equal(out, lev[0])
+    finally:
+        ctx.close()
+
+
+def test_bad_arguments():
+    L = (8, 4, 4, 4)
+    ctx = ddml.Context(L, ddml.BC_OPEN)
+    try:
+        gid = ctx.set_gauge(inputs.unit_links(L), 0.12, 0.0)
+        b = np.zeros((12, int(np.prod(L)), 4, 3), complex)
+        out = np.zeros_like(b)
+        with pytest.raises(RuntimeError):
+            ctx.factorized_chain(gid, [], b, 12, out)
+        with pytest.raises(RuntimeError):
+            ctx.factorized_chain(gid, [12345], b, 12, out)
+        with pytest.raises(RuntimeError):
+            ctx.factorized_chain(gid, [ctx.set_domain(*_block(L, 0, 4))], b, 13, out)
+    finally:
+        ctx.close()
+
+
+@pytest.mark.slow
+def test_bench_chain_sampled_residuals():
+    """32^3x64, open time boundaries, Delta = 8, source on t = 12 (Lambda_1),
+    sinks in Lambda_6: Omega_3 = [0, 24), Omega*_2 .. Omega*_6 = [16, 32) ..
+    [48, 64).  Each step's residual at 4096 random sites of its domain and
+    at every site of its right-hand side's slice."""
+    L = (64, 32, 32, 32)
+    V = int(np.prod(L))
+    V3 = V // L[0]
+    dev = torch.device("cuda:0")
+    U = inputs.quenched_field(L, 1601004)
+    blocks = _chain_blocks(L, 8, 1, 6)
+    xs = (12, 0, 0, 0)
+    ctx = ddml.Context(L, ddml.BC_OPEN)
+    try:
+        gid = ctx.set_gauge(torch.from_numpy(U).to(dev), KAPPA, CSW)
+        doms = [ctx.set_domain(*d) for d in blocks]
+        b = torch.from_numpy(inputs.point_source(L, xs)).to(dev)
+        steps = torch.zeros((len(doms), 12, V, 4, 3), dtype=torch.complex128, device=dev)
+        out = torch.zeros((12, V, 4, 3), dtype=torch.complex128, device=dev)
+        rc, infos = ctx.factorized_chain(gid, doms, b, 12, out, steps, ddml.solver_params(tol=TOL))
+        torch.cuda.synchronize()
+        assert rc == ddml.OK, ctx.last_error()
+        rng = np.random.default_rng(1601311)
+        sx = inputs.site_index(L, xs)
+        e = np.zeros((12, 4, 3))
+        for k in range(12):
+            e[k, k // 3, k % 3] = 1.0
+        prev = None
+        for k, (lo, hi) in enumerate(blocks):
+            psi = steps[k].cpu().numpy()
+            if k == 0:
+                sites = np.unique(np.concatenate([rng.integers(lo[0] * V3, hi[0] * V3, 4096), [sx]]))
+                r = oracle.apply_D_sites(U, L, KAPPA, psi, sites, csw=CSW, antiperiodic=oracle.OPEN, lo=lo, hi=hi)
+                r[:, sites == sx] -= e[:, None]
+                assert np.abs(r).max() <= TOL * (1 + 1e-3), (k, np.abs(r).max())
+            else:
+                cut = np.arange(lo[0] * V3, (lo[0] + 1) * V3)
+                rhs = -oracle.apply_boundary_sites(U, L, prev, cut, lo, hi, antiperiodic=oracle.OPEN)
+                bn = np.sqrt((np.abs(rhs) ** 2).sum(axis=(1, 2, 3)))
+                sites = np.unique(np.concatenate([cut, rng.integers(lo[0] * V3, hi[0] * V3, 4096)]))
+                r = oracle.apply_D_sites(U, L, KAPPA, psi, sites, csw=CSW, antiperiodic=oracle.OPEN, lo=lo, hi=hi)
+                r[:, :V3] -= rhs          # the first V3 sorted sites are the cut slice
+                per_col = np.abs(r).max(axis=(1, 2, 3)) / bn
+                assert per_col.max() <= TOL * (1 + 1e-3), (k, per_col.max())
+            assert all(i.status == ddml.OK for i in infos[k])
+            prev = psi
+        assert torch.equal(out, steps[-1])
+        print("32^3x64 chain: inner iterations per step",
+              [max(i.inner_iters for i in infos[k]) for k in range(len(doms))])
+    finally:
+        ctx.close()
