@@ -56,6 +56,12 @@ Contents and the passages they follow:
       and eta = D_Gamma*^{-1} D_dGamma* phi, and C(y0, x0) =
       -(1/L^3) Re Tr(Gt(y0) G(x0)).
 
+  * ``colourless_spinors``/``projected_nucleon``: the nucleon with the
+      projector cut (Section 5.2, eq. W0tbary): colourless spinors
+      B[s_i, s_j, s_k; x] of xi_i^T = phi_i^dag D_Gammabar^{-1} and of
+      eta_i = D_Gamma*^{-1} D_dGamma* phi_i, summed per time slice, contracted
+      with g5 P_- for W_N1 and W_N2.
+
   * ``level1_update``: quenched updates of a time slab with the spatial links
       of its first slice fixed (the level-1 updates of Section 3.1): Wilson
       plaquette action, Cabibbo-Marinari heatbath (Kennedy-Pendleton SU(2)
@@ -556,6 +562,44 @@ def projected_pion(U, L, kappa, phi, bar, star, C=None, antiperiodic=True, tol=1
     V3 = int(np.prod(L[1:]))
     Cm = -np.einsum("yij,xji->yx", Gt, G).real / V3
     return Cm, G, Gt
+
+
+def colourless_spinors(s, L):
+    """Slice sums of the colourless spinors of eq. W0tbary for every index triple:
+    out[t, i, j, k, alpha] = sum_{x in slice t} eps^{abc} (s_i^a(x)^T C g5 s_j^b(x)) s_k^c_alpha(x),
+    s[n, V, 4, 3] (the spinor index transposed, not conjugated)."""
+    L = tuple(L)
+    V3 = int(np.prod(L[1:]))
+    s = np.asarray(s).reshape(s.shape[0], L[0], V3, 4, 3)
+    Cg5 = charge_conjugation() @ gamma5()
+    d = np.einsum("itxra,rq,jtxqb->tijxab", s, Cg5, s, optimize=True)         # diquark, colours a, b
+    e = np.einsum("abc,tijxab->tijxc", _eps(), d, optimize=True)
+    return np.einsum("tijxc,ktxgc->tijkg", e, s, optimize=True)
+
+
+def projected_nucleon(U, L, kappa, phi, bar, star, C=None, antiperiodic=True, tol=1e-13):
+    """C_N(y0, x0) = (1/L^3) sum_{x,y} (W_N1 - W_N2) with every propagator replaced by
+    the projected factorized one of eq. approxlong2, S(y,x) = -sum_i eta_i(y) xi_i(x)^T,
+    written with the colourless spinors of eq. W0tbary.  Substituting S into
+    eq. baryfact (three minus signs, and eps^{feg} reordered to eps^{fge}) gives
+      W_N1 = sum_ijk B[xi_j, xi_i, xi_k; x]^T P_- B[eta_i, eta_j, eta_k; y],
+      W_N2 = sum_ijk B[xi_k, xi_i, xi_j; x]^T P_- B[eta_i, eta_j, eta_k; y]
+    (the index orders of eq. W0tbary; its printed prefactor -g5 P_- is read as P_-),
+    xi_i^T = phi_i^dag D_Gammabar^{-1}, i.e. xi_i = conj(g5 D_Gammabar^{-1} g5 phi_i) by
+    gamma5-hermiticity (eq. g5h), and eta_i = D_Gamma*^{-1} D_dGamma* phi_i.
+    Returns (C [T, T] indexed [y0, x0], slice-summed spinors of xi, of eta)."""
+    L = tuple(L)
+    chi, _, _ = solve(U, L, kappa, apply_gamma5(phi), C=C, antiperiodic=antiperiodic, lo=bar[0], hi=bar[1], tol=tol)
+    eta, _, _ = solve(U, L, kappa, apply_boundary(U, L, phi, star[0], star[1], antiperiodic), C=C,
+                      antiperiodic=antiperiodic, lo=star[0], hi=star[1], tol=tol)
+    xi = np.conj(apply_gamma5(chi))
+    Bx = colourless_spinors(xi, L)
+    By = colourless_spinors(eta, L)
+    G = P_minus()
+    V3 = int(np.prod(L[1:]))
+    W1 = np.einsum("xjikr,rq,yijkq->yx", Bx, G, By, optimize=True)
+    W2 = np.einsum("xkijr,rq,yijkq->yx", Bx, G, By, optimize=True)
+    return (W1 - W2) / V3, Bx, By
 
 
 # ------------------------------------------------------- level-1 updates
