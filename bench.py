@@ -636,8 +636,9 @@ def run_projected(ctx, ddml, torch, dev, U0_dev, L, kappa, csw, args):
     Omega* = [x0cut - 8, x0cut + 8) (Gaussian start from a seeded device
     generator), then chi = D_Gammabar^{-1} gamma5 phi, eta = D_Gamma*^{-1} D_d phi,
     the per-slice Gram matrices (rocBLAS ZGEMM, batched over slices) and
-    C(y0, x0) = -(1/L^3) Tr(Gt(y0) G(x0)); x0cut = 24, Gammabar = [0, 32),
-    Gamma* = [24, 64)."""
+    C(y0, x0) = -(1/L^3) Tr(Gt(y0) G(x0)), and from the same solves the
+    nucleon of eq. W0tbary (slice sums of the colourless spinors of xi and
+    eta, one ZGEMM per slice); x0cut = 24, Gammabar = [0, 32), Gamma* = [24, 64)."""
     T = L[0]
     xcut = 24 if T >= 48 else T // 2
     d = 8 if T >= 48 else max(2, T // 8)
@@ -659,8 +660,8 @@ def run_projected(ctx, ddml, torch, dev, U0_dev, L, kappa, csw, args):
     assert rc == ddml.OK, "inverse iteration failed: %s" % ctx.last_error()
     torch.cuda.synchronize()
     b = time.perf_counter()
-    rc, Cm, _, info2 = ctx.projected_pion(gid, bar, star, phi, n, prm)
-    assert rc == ddml.OK, "projected pion failed: %s" % ctx.last_error()
+    rc, CN, Cm, info2 = ctx.projected_nucleon(gid, bar, star, phi, n, prm, pion=True)
+    assert rc == ddml.OK, "projected pion/nucleon failed: %s" % ctx.last_error()
     torch.cuda.synchronize()
     c = time.perf_counter()
     ctx.release_gauge(gid)
@@ -668,12 +669,13 @@ def run_projected(ctx, ddml, torch, dev, U0_dev, L, kappa, csw, args):
     ys = [y for y in (xcut, xcut + 8, xcut + 16, xcut + 24, T - 1) if y < T]
     res = {"lattice": list(L), "bc_time": "open", "vectors": n, "inverse_iterations": args.proj_iters,
            "omega": [xcut - d, xcut + d], "gammabar": [0, xcut + d], "gamma_star": [xcut, T],
-           "s_inverse_iteration": b - a, "s_projected_pion": c - b,
+           "s_inverse_iteration": b - a, "s_projected_pion_and_nucleon": c - b,
            "vector_solves_per_s": (args.proj_iters * n + 2 * n) / (c - a),
            "max_inner_iters": {"inverse_iteration_last": max(x.inner_iters for x in info),
                                "projected": max(x.inner_iters for x in info2)},
-           "C_y0_x0=%d" % x0: {str(y): float(Cm[y, x0]) for y in ys}}
-    log("projected pion: %s" % res)
+           "C_y0_x0=%d" % x0: {str(y): float(Cm[y, x0]) for y in ys},
+           "nucleon_C_y0_x0=%d" % x0: {str(y): [float(CN[y, x0].real), float(CN[y, x0].imag)] for y in ys}}
+    log("projected pion and nucleon: %s" % res)
     return res
 
 

@@ -258,6 +258,33 @@ int ddml_propagator_series_batch(ddml_ctx ctx, int nseries, const ddml_series_de
 int ddml_contract_pp_disconnected(ddml_ctx ctx, const double* terms_x, const double* terms_y, int nlevels,
                                   const int xsrc[4], const int ysrc[4], double* out, int on_device, void* stream);
 
+/* Nucleon with the projector-cut propagator (Section 5.2, eqs. approxlong2,
+ * W0tbary): for orthonormal phi_1..phi_n,
+ *   xi_i^T = phi_i^dag D_Gammabar^{-1}, computed as xi_i = conj(g5 D_Gammabar^{-1} g5 phi_i)
+ *            (gamma5-hermiticity, eq. g5h),
+ *   eta_i  = D_Gamma*^{-1} D_dGamma* phi_i,
+ * the colourless spinors B[s_i, s_j, s_k; x]_alpha = eps^{abc} (s_i^a(x)^T C g5
+ * s_j^b(x)) s_k^c_alpha(x) (C = i g0 g2) summed over each time slice (one
+ * library ZGEMM per slice: diquark colour vectors times spinors), and
+ *   out[y0][x0] = (1/L^3) sum_{ijk} (Bx(j,i,k) - Bx(k,i,j))^T P_- By(i,j,k),
+ * Bx from xi on slice x0 of Gammabar, By from eta on slice y0 of Gamma*: the
+ * nucleon correlator (W_N1 - W_N2 of eq. baryfact, summed over x and y) with
+ * every propagator replaced by -sum_i eta_i(y) xi_i(x)^T.  Written out, that
+ * substitution gives +P_- between the spinors where eq. W0tbary prints
+ * -g5 P_-; the form here is the one equal to eq. baryfact.  With phi spanning
+ * the sites D_dGamma* reads it equals the point-source factorized nucleon
+ * summed over all sources of each slice.
+ *   phi       [nvec][V][4][3]
+ *   out       [T][T] complex, host (zero outside the two time ranges)
+ *   pion_out  [T][T] real, host, or NULL: the projected pion of
+ *             ddml_projected_pion from the same solves
+ *   info      [2][nvec]: the Gammabar solves, then the Gamma* solves
+ * Memory: two [T][nvec^2][4 nvec] complex blocks.  Errors: EINVAL, ENOMEM,
+ * ENOTCONVERGED, EDEVICE. */
+int ddml_projected_nucleon(ddml_ctx ctx, int gauge_id, int bar_id, int star_id, const double* phi, int nvec,
+                           const ddml_solver_params* params, double* out, double* pion_out, ddml_rhs_info* info,
+                           int on_device, void* stream);
+
 /* t[i] = tr{g5 S^(i)(x,x)} (eq. W0, without the 1/L^3) for each level of a
  * 12-column point-source series around x, S^(i) the partial sum of terms up
  * to i: the factors whose level-1 means the two-level estimator multiplies.

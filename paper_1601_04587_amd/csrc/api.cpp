@@ -666,6 +666,66 @@ int ddml_projected_pion(ddml_ctx ctx, int gauge_id, int bar_id, int star_id, con
   });
 }
 
+int ddml_projected_nucleon(ddml_ctx ctx, int gauge_id, int bar_id, int star_id, const double* phi, int nvec,
+                           const ddml_solver_params* params, double* out, double* pion_out, ddml_rhs_info* info,
+                           int on_device, void* stream) {
+  return guarded(ctx, [&](Ctx* c) {
+    need(phi && out && info, "NULL argument");
+    need(nvec >= 1 && nvec <= 1024, "nvec must be in 1..1024");
+    check_params(params);
+    const GaugeRec& g = gauge_get(c, gauge_id);
+    int b0, b1, s0, s1;
+    slab_of(c, g, bar_id, b0, b1);
+    slab_of(c, g, star_id, s0, s1);
+    const int T = g.lat.dims[0];
+    const size_t V = g.V, per = V * 12;
+    const size_t bytes = (size_t)nvec * per * sizeof(double2);
+    const size_t bbytes = (size_t)T * nvec * nvec * 4 * nvec * sizeof(double2);
+    const double invL3 = 1.0 / ((double)g.lat.dims[1] * g.lat.dims[2] * g.lat.dims[3]);
+    StreamJoin sj(c, stream);
+    Staged sp = stage_in(c, phi, bytes, on_device);
+    DBuf src(c->pool.get(), bytes), sol(c->pool.get(), bytes);
+    DBuf Bx(c->pool.get(), bbytes), By(c->pool.get(), bbytes);
+    DBuf o(c->pool.get(), (size_t)T * T * sizeof(double2));
+    DBuf G, Gt, po;
+    if (pion_out) {
+      const size_t gbytes = (size_t)T * nvec * nvec * sizeof(double2);
+      G = DBuf(c->pool.get(), gbytes);
+      Gt = DBuf(c->pool.get(), gbytes);
+      po = DBuf(c->pool.get(), (size_t)T * T * sizeof(double));
+    }
+    // chi = D_Gammabar^{-1} g5 phi; xi = conj(g5 chi)
+    DDML_HIP(launch_gamma5(reinterpret_cast<const double2*>(sp.cptr), src.as<double2>(), (size_t)nvec * V, c->stream));
+    int rc = solve_columns(c, gauge_id, bar_id, src.as<double>(), sol.as<double>(), nvec, per, params, info);
+    bary_slices(c, sol.as<double2>(), nvec, V, T, b0, b1, 1, Bx.as<double2>());
+    if (pion_out) gram_slices(c, sol.as<double2>(), nvec, V, T, b0, b1, G.as<double2>());
+    // eta = D_Gamma*^{-1} D_dGamma* phi
+    for (int first = 0; first < nvec; first += kMaxRhs) {
+      const int cols = std::min(kMaxRhs, nvec - first);
+      apply_boundary(c, gauge_id, star_id, sp.cptr + 2 * per * first, src.as<double>() + 2 * per * first, cols, 1.0,
+                     c->stream);
+    }
+    const int r = solve_columns(c, gauge_id, star_id, src.as<double>(), sol.as<double>(), nvec, per, params,
+                                info + nvec);
+    if (rc == DDML_OK) rc = r;
+    bary_slices(c, sol.as<double2>(), nvec, V, T, s0, s1, 0, By.as<double2>());
+    DDML_HIP(hipMemsetAsync(o.p, 0, o.bytes, c->stream));
+    DDML_HIP(launch_bary_pairs(By.as<double2>(), Bx.as<double2>(), nvec, T, s0, s1, b0, b1, invL3, o.as<double2>(),
+                               c->stream));
+    if (pion_out) {
+      gram_slices(c, sol.as<double2>(), nvec, V, T, s0, s1, Gt.as<double2>());
+      DDML_HIP(hipMemsetAsync(po.p, 0, po.bytes, c->stream));
+      DDML_HIP(launch_trace_pairs(Gt.as<double2>(), G.as<double2>(), nvec, T, s0, s1, b0, b1, -invL3,
+                                  po.as<double>(), c->stream));
+      DDML_HIP(hipMemcpyAsync(pion_out, po.p, po.bytes, hipMemcpyDeviceToHost, c->stream));
+    }
+    DDML_HIP(hipMemcpyAsync(out, o.p, o.bytes, hipMemcpyDeviceToHost, c->stream));
+    DDML_HIP(hipStreamSynchronize(c->stream));
+    sj.done();
+    return rc;
+  });
+}
+
 int ddml_time_stencil(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec, int iters, int R, int order,
                       int grid, int splits, int stage, double out[4]) {
   return guarded(ctx, [&](Ctx* c) {

@@ -234,6 +234,8 @@ void apply_boundary(Ctx* c, int gauge_id, int dom_id, const double* in, double* 
 // columns of X on rows [row0, row0 + nrows) by Cholesky QR (twice)
 void gram_slices(Ctx* c, const double2* X, int n, size_t V, int T, int t0, int t1, double2* G);
 void orthonormalize(Ctx* c, double2* X, int n, size_t V, size_t row0, size_t nrows);
+// slice sums of the colourless spinors of n fields (xi = 1: of conj(g5 X)), B [T][n^2][4n]
+void bary_slices(Ctx* c, const double2* X, int n, size_t V, int T, int t0, int t1, int xi, double2* B);
 void blas_release(Ctx* c);
 // Runs every solve to completion (continuous batching inside).  Device pointers.
 void run_solves(Ctx* c, std::vector<Solve*>& solves);

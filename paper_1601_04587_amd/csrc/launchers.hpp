@@ -122,6 +122,13 @@ hipError_t launch_noise_trace(const double2* eta, const double2* phi, int nsrc, 
 // linalg.hip: G (column-major n x n) -> upper Cholesky factor R, G = R^dag R
 hipError_t launch_cholesky_upper(double2* G, int n, int* bad, hipStream_t st);
 // out[y * T + x] = scale * Re Tr(Gt[y] G[x]) for y in [ya, yb), x in [xa, xb)
+// colourless spinors (eq. W0tbary): diquark colour vectors E [N^2][ns][3] and spinors S [N][4][ns][3]
+// of the sites [site0, site0 + ns) of X [N][V][4][3] (xi = 1: of conj(g5 X)); then
+// out[y T + x] = scale * sum (Bx(j,i,k) - Bx(k,i,j))^T P_- By(i,j,k) for slice pairs
+hipError_t launch_bary_layout(const double2* X, size_t V, int N, size_t site0, int ns, int xi, double2* E,
+                              double2* S, hipStream_t st);
+hipError_t launch_bary_pairs(const double2* By, const double2* Bx, int N, int T, int ya, int yb, int xa, int xb,
+                             double scale, double2* out, hipStream_t st);
 hipError_t launch_trace_pairs(const double2* Gt, const double2* G, int n, int T, int ya, int yb, int xa, int xb,
                               double scale, double* out, hipStream_t st);
 // W: scratch [nlevels][V]; out: [nlevels][T]

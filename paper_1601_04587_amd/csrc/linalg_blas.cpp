@@ -6,6 +6,8 @@
 // eps cond(X)^2).
 #include <rocblas/rocblas.h>
 
+#include <algorithm>
+
 #include "engine.hpp"
 
 namespace ddml {
@@ -67,6 +69,32 @@ void orthonormalize(Ctx* c, double2* X, int n, size_t V, size_t row0, size_t nro
   DDML_HIP(hipMemcpyAsync(&bad, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   DDML_HIP(hipStreamSynchronize(c->stream));
   if (bad) throw Error{DDML_ENUMERIC, "basis vectors are linearly dependent (Cholesky pivot <= 0)"};
+}
+
+// Slice sums of the colourless spinors (eq. W0tbary) of the n fields X for the
+// slices [t0, t1): B[t] (column-major n^2 x 4n, entry (i n + j, 4 k + alpha))
+// = sum_{x in t} E(x)^T S(x), one ZGEMM per chunk of sites (the chunk keeps the
+// diquark matrix E near 1 GiB), accumulated over the chunks of a slice.
+void bary_slices(Ctx* c, const double2* X, int n, size_t V, int T, int t0, int t1, int xi, double2* B) {
+  const size_t blk = (size_t)n * n * 4 * n;
+  DDML_HIP(hipMemsetAsync(B, 0, (size_t)T * blk * sizeof(double2), c->stream));
+  if (t1 <= t0) return;
+  const size_t V3 = V / T;
+  const size_t per_site = (size_t)n * n * 3 * sizeof(double2);
+  size_t ns = ((size_t)1 << 30) / per_site;
+  ns = std::max<size_t>(1, std::min(ns, V3));
+  DBuf E(c->pool.get(), ns * per_site), S(c->pool.get(), (size_t)n * 12 * ns * sizeof(double2));
+  const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
+  for (int t = t0; t < t1; ++t)
+    for (size_t off = 0; off < V3; off += ns) {
+      const int cnt = (int)std::min(ns, V3 - off);
+      DDML_HIP(launch_bary_layout(X, V, n, (size_t)t * V3 + off, cnt, xi, E.as<double2>(), S.as<double2>(),
+                                  c->stream));
+      chk(rocblas_zgemm(blas(c), rocblas_operation_transpose, rocblas_operation_none, n * n, 4 * n, 3 * cnt, &one,
+                        E.as<rocblas_double_complex>(), 3 * cnt, S.as<rocblas_double_complex>(), 3 * cnt,
+                        off ? &one : &zero, reinterpret_cast<rocblas_double_complex*>(B) + (size_t)t * blk, n * n),
+          "zgemm");
+    }
 }
 
 }  // namespace ddml

@@ -70,7 +70,7 @@ EXPORTS = ["ddml_create", "ddml_destroy", "ddml_last_error", "ddml_set_gauge", "
            "ddml_release_gauge", "ddml_set_domain", "ddml_apply_Dw", "ddml_apply_eo", "ddml_solve_domain",
            "ddml_solve_batch", "ddml_propagator_series", "ddml_propagator_series_batch", "ddml_time_stencil", "ddml_autotune", "ddml_set_launch", "ddml_contract_pp_disconnected", "ddml_contract_nucleon",
            "ddml_apply_boundary", "ddml_factorized_series", "ddml_factorized_chain", "ddml_contract_pion", "ddml_hpe_trace",
-           "ddml_inverse_iteration", "ddml_projected_pion", "ddml_two_level_average", "ddml_trace_g5",
+           "ddml_inverse_iteration", "ddml_projected_pion", "ddml_projected_nucleon", "ddml_two_level_average", "ddml_trace_g5",
            "ddml_server_start", "ddml_submit", "ddml_poll", "ddml_wait", "ddml_stats", "ddml_server_stop",
            "ddml_now"]
 
@@ -96,6 +96,7 @@ def load():
     lib.ddml_set_gauge_region.argtypes = [P, I, I, I, P, I, IP]
     lib.ddml_level1_update.argtypes = [P, I, I, I, D, ctypes.c_uint64, ctypes.c_uint32, I, I, IP]
     lib.ddml_get_gauge.argtypes = [P, I, P, I]
+    lib.ddml_projected_nucleon.argtypes = [P, I, I, I, P, I, ctypes.POINTER(SolverParams), P, P, P, I, P]
     lib.ddml_trace_g5.argtypes = [P, P, I, IP, P, I, P]
     lib.ddml_two_level_average.argtypes = [I, I, I, I, I, P, P, I, P, P, P, P, P]
     lib.ddml_release_gauge.argtypes = [P, I]
@@ -435,6 +436,20 @@ class Context:
             gb = np.ascontiguousarray(gb.transpose(0, 2, 1))
             gs = np.ascontiguousarray(gs.transpose(0, 2, 1))
         return rc, out, (gb, gs), list(info)
+
+    def projected_nucleon(self, gid, bar, star, phi, nvec, params=None, pion=False):
+        """Projector-cut nucleon C_N(y0, x0) [T, T] complex; with pion=True also the
+        projected pion [T, T] from the same solves.  Returns (rc, C_N, C_pi or None, infos)."""
+        params = params or solver_params()
+        T = self.gauge_dims.get(gid, self.dims)[0]
+        out = np.zeros((T, T), dtype=np.complex128)
+        pout = np.zeros((T, T)) if pion else None
+        info = (RhsInfo * (2 * nvec))()
+        pp, dev = _ptr(phi)
+        rc = self.lib.ddml_projected_nucleon(self.h, gid, bar, star, pp, nvec, ctypes.byref(params), out.ctypes.data,
+                                             pout.ctypes.data if pion else None, info, dev, _stream(phi))
+        self._check(rc, allow=(ENOTCONVERGED, ENUMERIC))
+        return rc, out, pout, list(info)
 
     def time_stencil(self, gid, dom, nrhs, prec=MIXED_FP32, iters=20, R=0, order=-1, grid=0, splits=0, stage=-1):
         """(ms_odd_half, ms_even_half, bytes_odd_half, bytes_even_half) per launch."""

@@ -7,6 +7,10 @@ fullfactpi, Bpions) and its inverse-iteration basis.
   same basis vectors: a complete projector on a 8x2^3 lattice (equal to the
   factorized correlator summed over all sources, pinned in the oracle tests)
   and the GPU's own inverse-iteration basis on the 16x8^3 field.
+* The nucleon with the same projector (eq. W0tbary): against the oracle's
+  colourless-spinor contraction (pinned to the Wick contraction) for a
+  complete and a random projector and on the GPU's basis; the pion from the
+  same solves equals the projected-pion entry point's bit for bit.
 * At 32^3x64 with open time boundaries: orthonormality of the basis, Gram
   matrices Hermitian and positive semi-definite, zero outside their domains,
   and the correlator equal to the trace of the returned Gram matrices.
@@ -123,6 +127,67 @@ def test_projected_pion_on_the_inverse_iteration_basis(cfg2, basis):
     assert np.abs(G - Gr).max() <= REL * np.abs(Gr).max()
     assert np.abs(Gt - Gtr).max() <= REL * np.abs(Gtr).max()
     assert np.all(Cg[8:, :12] < 0) and not Cg[:8].any() and not Cg[:, 12:].any()
+
+
+@pytest.mark.parametrize("bc,n", [(ddml.BC_OPEN, 0), (ddml.BC_ANTIPERIODIC, 5)])
+def test_projected_nucleon_matches_the_oracle(bc, n):
+    """n = 0: the complete projector on the slice below the cut (96 unit
+    vectors); n > 0: n random orthonormal vectors on the slices D_dGamma* reads."""
+    L = (8, 2, 2, 2)
+    V = int(np.prod(L))
+    V3 = V // L[0]
+    kappa = 0.13
+    U = inputs.random_links(L, 1601702, 0.4)
+    C = oracle.clover_term(U, L, 1.2)
+    xcut, delta = 4, 2
+    bar = ((0, 0, 0, 0), (xcut + delta, 2, 2, 2))
+    star = ((xcut, 0, 0, 0), L)
+    ap = oracle.OPEN if bc == ddml.BC_OPEN else True
+    slices = [xcut - 1] if bc == ddml.BC_OPEN else [0, xcut - 1]
+    if n == 0:
+        phi = _unit_vectors(L, slices)
+    else:
+        rng = np.random.default_rng(1601703)
+        raw = np.zeros((n, V, 4, 3), complex)
+        for t in slices:
+            raw[:, t * V3:(t + 1) * V3] = rng.normal(size=(n, V3, 4, 3)) + 1j * rng.normal(size=(n, V3, 4, 3))
+        q, _ = np.linalg.qr(raw.reshape(n, -1).T)
+        phi = np.ascontiguousarray(q.T.reshape(n, V, 4, 3))
+    nv = phi.shape[0]
+    ctx = ddml.Context(L, bc)
+    try:
+        gid = ctx.set_gauge(U, kappa, 1.2)
+        rc, CN, Cpi, info = ctx.projected_nucleon(gid, ctx.set_domain(*bar), ctx.set_domain(*star), phi, nv,
+                                                  ddml.solver_params(tol=TOL), pion=True)
+        assert rc == ddml.OK, ctx.last_error()
+    finally:
+        ctx.close()
+    ref, _, _ = oracle.projected_nucleon(U, L, kappa, phi, bar, star, C=C, antiperiodic=ap)
+    ys, xs = slice(xcut, L[0]), slice(0, xcut + delta)
+    assert np.abs(CN - ref).max() <= 1e-6 * np.abs(ref[ys, xs]).max()
+    assert not CN[:xcut].any() and not CN[:, xcut + delta:].any()
+    pref, _, _ = oracle.projected_pion(U, L, kappa, phi, bar, star, C=C, antiperiodic=ap)
+    assert np.abs(Cpi - pref).max() <= REL * np.abs(pref).max()
+
+
+def test_projected_nucleon_on_the_inverse_iteration_basis(cfg2, basis):
+    """16x8^3 field, the GPU's own basis; the pion from the same solves equals
+    the projected-pion entry point's."""
+    L, U, C, ctx, gid = cfg2
+    start, om, out = basis
+    phi = out[3]
+    n = phi.shape[0]
+    bar = ((0, 0, 0, 0), (12, 8, 8, 8))
+    star = ((8, 0, 0, 0), L)
+    db, ds = ctx.set_domain(*bar), ctx.set_domain(*star)
+    prm = ddml.solver_params(tol=TOL)
+    rc, CN, Cpi, info = ctx.projected_nucleon(gid, db, ds, phi, n, prm, pion=True)
+    assert rc == ddml.OK and len(info) == 2 * n
+    ref, _, _ = oracle.projected_nucleon(U, L, 0.1340, phi, bar, star, C=C)
+    assert np.abs(CN - ref).max() <= 1e-6 * np.abs(ref).max()
+    _, Cp2, _, _ = ctx.projected_pion(gid, db, ds, phi, n, prm)
+    assert np.array_equal(Cpi, Cp2)
+    print("projected nucleon C_N(y0, x0=2):", CN[8:, 2])
 
 
 def test_projected_error_paths(cfg2):
