@@ -77,6 +77,8 @@ def parse():
     ap.add_argument("--hpe-sources", type=int, default=24, help="Gaussian sources per domain (stochastic traces)")
     ap.add_argument("--factorized-only", action="store_true",
                     help="only the factorized pion leg (profiling runs)")
+    ap.add_argument("--projected-only", action="store_true",
+                    help="only the projector-cut pion and nucleon leg (profiling runs)")
     ap.add_argument("--serve-requests", type=int, default=64, help="requests per serving stream")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="configured Poisson rate, req/s")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -171,15 +173,18 @@ def main():
     t = time.time()
     U0 = inputs.quenched_field(L, seed, beta=beta)
     log("base field %s plaquette %.4f (%.1fs)" % (L, inputs.plaquette(U0, L), time.time() - t))
-    if args.factorized_only:
+    if args.factorized_only or args.projected_only:
         ctx = ddml.Context(L, ddml.BC_ANTIPERIODIC, device=0)
         U0_dev = torch.from_numpy(U0).to(dev)
         g = ctx.set_gauge(U0_dev, kappa, csw)
         tune = ctx.autotune(g, ctx.set_domain((0, 0, 0, 0), (16,) + L[1:]), 12, ddml.MIXED_FP32)
         log("autotune fp32 R=%d order=%d grid=%d splits=%d stage=%d (%.3f ms/pair)" % tune)
-        out = run_factorized(ctx, ddml, torch, dev, U0_dev, L, kappa, csw, args)
+        if args.factorized_only:
+            out = {"factorized_pion": run_factorized(ctx, ddml, torch, dev, U0_dev, L, kappa, csw, args)}
+        else:
+            out = {"projected_pion": run_projected(ctx, ddml, torch, dev, U0_dev, L, kappa, csw, args)}
         ctx.close()
-        print(json.dumps({"factorized_pion": out}), flush=True)
+        print(json.dumps(out), flush=True)
         return 0
     U0_dev = torch.from_numpy(U0).to(dev)
     srcs, terms = [], []
