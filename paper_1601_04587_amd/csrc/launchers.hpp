@@ -122,6 +122,9 @@ hipError_t launch_noise_trace(const double2* eta, const double2* phi, int nsrc, 
 // linalg.hip: G (column-major n x n) -> upper Cholesky factor R, G = R^dag R
 hipError_t launch_cholesky_upper(double2* G, int n, int* bad, hipStream_t st);
 // out[y * T + x] = scale * Re Tr(Gt[y] G[x]) for y in [ya, yb), x in [xa, xb)
+// C[s] = (accumulate ? C[s] : 0) + sum_q P[s Q + q]: reduction of a GEMM split along its inner dimension
+hipError_t launch_sum_chunks(const double2* P, int Q, int m, int n, int nslices, double2* C, int ldc, size_t sC,
+                             int accumulate, hipStream_t st);
 // colourless spinors (eq. W0tbary): diquark colour vectors E [N^2][ns][3] and spinors S [N][4][ns][3]
 // of the sites [site0, site0 + ns) of X [N][V][4][3] (xi = 1: of conj(g5 X)); then
 // out[y T + x] = scale * sum (Bx(j,i,k) - Bx(k,i,j))^T P_- By(i,j,k) for slice pairs

@@ -86,6 +86,39 @@ hipError_t launch_trace_pairs(const double2* Gt, const double2* G, int n, int T,
   return hipGetLastError();
 }
 
+// C[s] (m x n, column-major, leading dimension ldc, slices sC apart) = (or +=)
+// sum_{q < Q} P[s Q + q] (m x n each, packed): the reduction of a GEMM whose
+// long inner dimension was split into Q chunks, in a fixed order.
+__global__ void k_sum_chunks(const double2* __restrict__ P, int Q, int m, int n, int nslices,
+                             double2* __restrict__ C, int ldc, size_t sC, int accumulate) {
+  const size_t mn = (size_t)m * n, total = mn * nslices;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+    const size_t s = t / mn, e = t % mn;
+    const int i = (int)(e % m), j = (int)(e / m);
+    double re = 0, im = 0;
+    for (int q = 0; q < Q; ++q) {
+      const double2 v = P[(s * Q + q) * mn + e];
+      re += v.x;
+      im += v.y;
+    }
+    double2* d = C + s * sC + i + (size_t)j * ldc;
+    if (accumulate) {
+      re += d->x;
+      im += d->y;
+    }
+    *d = make_double2(re, im);
+  }
+}
+
+hipError_t launch_sum_chunks(const double2* P, int Q, int m, int n, int nslices, double2* C, int ldc, size_t sC,
+                             int accumulate, hipStream_t st) {
+  size_t g = ((size_t)m * n * nslices + 255) / 256;
+  if (g > 16384) g = 16384;
+  hipLaunchKernelGGL(k_sum_chunks, dim3((unsigned)(g ? g : 1)), dim3(256), 0, st, P, Q, m, n, nslices, C, ldc, sC,
+                     accumulate);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------- colourless spinors
 // Eq. W0tbary: B[s_i, s_j, s_k; x]_alpha = eps^{abc} (s_i^a(x)^T C g5 s_j^b(x)) s_k^c_alpha(x)
 // = sum_c e_ij^c(x) s_k^c_alpha(x), with the colour vector of the diquark
