@@ -93,6 +93,26 @@ def test_two_domains_reproduce_the_two_domain_factorization_bitwise():
         ctx.close()
 
 
+def test_one_domain_is_a_plain_domain_solve_bitwise():
+    L = (16, 8, 8, 8)
+    U = inputs.quenched_field(L, 1601002)
+    V = int(np.prod(L))
+    b = inputs.point_source(L, (5, 1, 2, 3))
+    ctx = ddml.Context(L, ddml.BC_OPEN)
+    try:
+        gid = ctx.set_gauge(U, KAPPA, CSW)
+        dom = ctx.set_domain(*_block(L, 2, 10))
+        prm = ddml.solver_params(tol=TOL)
+        out = np.zeros((12, V, 4, 3), complex)
+        rc, infos = ctx.factorized_chain(gid, [dom], b, 12, out, None, prm)
+        assert rc == ddml.OK and len(infos) == 1
+        ref = np.zeros_like(out)
+        ctx.solve_domain(gid, dom, b, ref, 12, prm)
+        assert np.array_equal(out, ref)
+    finally:
+        ctx.close()
+
+
 def test_bad_arguments():
     L = (8, 4, 4, 4)
     ctx = ddml.Context(L, ddml.BC_OPEN)

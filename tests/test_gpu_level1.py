@@ -142,6 +142,17 @@ def test_operator_of_an_updated_version(cfg2, rng):
     assert np.abs(out - ref).max() < 1e-9 * np.abs(ref).max()
 
 
+def test_one_slice_slab_updates_only_its_time_links(cfg2):
+    """A slab of one slice: its spatial links are the frozen ones, so only the
+    time links move."""
+    L, U, ctx, gid = cfg2
+    g = ctx.level1_update(gid, 7, 8, BETA, SEED, 3 + 11, 2, 1)
+    got = _gpu_field(ctx, g, L)
+    ctx.release_gauge(g)
+    ref = oracle.level1_update(U, L, BETA, SEED, 11, 7, 8, 2, 1)
+    _compare(L, U, got, ref, 7, 8)
+
+
 def test_zero_sweeps_copy_and_argument_errors(cfg2):
     L, U, ctx, gid = cfg2
     g = ctx.level1_update(gid, 2, 6, BETA, SEED, 3, 0, 0)

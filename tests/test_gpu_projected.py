@@ -129,7 +129,7 @@ def test_projected_pion_on_the_inverse_iteration_basis(cfg2, basis):
     assert np.all(Cg[8:, :12] < 0) and not Cg[:8].any() and not Cg[:, 12:].any()
 
 
-@pytest.mark.parametrize("bc,n", [(ddml.BC_OPEN, 0), (ddml.BC_ANTIPERIODIC, 5)])
+@pytest.mark.parametrize("bc,n", [(ddml.BC_OPEN, 0), (ddml.BC_ANTIPERIODIC, 5), (ddml.BC_OPEN, 1)])
 def test_projected_nucleon_matches_the_oracle(bc, n):
     """n = 0: the complete projector on the slice below the cut (96 unit
     vectors); n > 0: n random orthonormal vectors on the slices D_dGamma* reads."""
