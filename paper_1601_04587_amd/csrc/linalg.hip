@@ -227,7 +227,8 @@ __global__ void __launch_bounds__(256) k_bary_pairs(const double2* __restrict__ 
       const double2 pm = make_double2(0.5 * (p0.x + p1.x), 0.5 * (p0.y + p1.y));
       const double2 u0 = A[a1 + NN * r], u1 = A[a1 + NN * (r + 2)];
       const double2 v0 = A[a2 + NN * r], v1 = A[a2 + NN * (r + 2)];
-      const double2 w = make_double2(u0.x + u1.x - v0.x - v1.x, u0.y + u1.y - v0.y - v1.y);
+      // (W_N1 term) - (W_N2 term): equal index triples cancel exactly
+      const double2 w = make_double2((u0.x + u1.x) - (v0.x + v1.x), (u0.y + u1.y) - (v0.y + v1.y));
       re += w.x * pm.x - w.y * pm.y;
       im += w.x * pm.y + w.y * pm.x;
     }
