@@ -370,6 +370,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(U0, L, kappa, csw, args.cpu_seconds)
+        level1["cpu_oracle"] = cpu_level1(U0, L, beta, seed)
 
     ctx.close()
     out = {
@@ -682,6 +683,20 @@ def run_projected(ctx, ddml, torch, dev, U0_dev, L, kappa, csw, args):
            "nucleon_C_y0_x0=%d" % x0: {str(y): [float(CN[y, x0].real), float(CN[y, x0].imag)] for y in ys}}
     log("projected pion and nucleon: %s" % res)
     return res
+
+
+def cpu_level1(U0, L, beta, seed):
+    """The FP64 CPU oracle's level-1 sweep of one 16-slice slab (the same update
+    the device makes first), timed on the host cores."""
+    import oracle
+
+    V3 = int(np.prod(L[1:]))
+    t = time.time()
+    oracle.level1_update(U0, L, beta, seed, 1000, 0, 16, 1, 0)
+    dt = time.time() - t
+    nlinks = 16 * V3 * 4 - V3 * 3
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count()))
+    return {"s_per_slab_update": dt, "links_per_s": nlinks / dt, "cores": cores, "kind": "oracle"}
 
 
 def cpu_baseline(U0, L, kappa, csw, seconds):
