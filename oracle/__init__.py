@@ -74,6 +74,11 @@ Contents and the passages they follow:
       pieces grouped in bins of n1 and treated as n0 independent measurements
       (the averaging of the numerical part of Section 6).
 
+Parity unpinned: the clover term's convention against the paper, which
+mentions the O(a) improvement without writing the term; it is pinned to the
+Sheikholeslami-Wohlert definition stated in oracle.c (single-link closed form,
+hermiticity, gauge covariance), not to a formula of the paper.
+
 Time boundary conditions: ``antiperiodic`` is True (antiperiodic), False
 (periodic) or ``OPEN`` (hops across the time boundary dropped, the set-up
 Sections 2 and 5.2 assume).

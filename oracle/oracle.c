@@ -16,7 +16,8 @@
  *                               + (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu) ].
  *    m0 = 1/(2 kappa) - 4 so that 2 kappa D = 1 - kappa D_hop (Section 6).
  *  - O(a) improvement (mentioned in the footnotes of Sections 4 and 6, not
- *    defined by the paper): the Sheikholeslami-Wohlert term
+ *    defined by the paper, so parity unpinned against the paper: the tests
+ *    pin it to the definition below): the Sheikholeslami-Wohlert term
  *      c_sw (i/4) sum_{mu,nu} sigma_{mu nu} Fhat_{mu nu}(x),
  *    sigma_{mu nu} = (i/2)[gamma_mu, gamma_nu], Fhat = (Q_{mu nu} - Q_{nu mu})/8,
  *    Q_{mu nu}(x) the sum of the four plaquettes of the (mu,nu) plane at x.
