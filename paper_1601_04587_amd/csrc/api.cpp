@@ -337,8 +337,22 @@ static int series_many(Ctx* c, int ns, const ddml_series_desc* sd, int nrhs, con
   int rc = solve_many(c, (int)d.size(), d.data(), params, 1, c->stream);
   for (int k = 0; k < ns; ++k) {
     const size_t bytes = per[k] * sizeof(double2);
-    DDML_HIP(launch_series_diff(reinterpret_cast<double2*>(st[k].ptr), per[k], sd[k].nlevels,
-                                sd[k].sum ? reinterpret_cast<double2*>(ss[k].ptr) : nullptr, c->stream));
+    // the solutions vanish outside their domains: difference only the time
+    // slices the union of the series' domains covers (whole column ranges)
+    const GaugeRec& g = gauge_get(c, sd[k].gauge_id);
+    int t0 = g.lat.dims[0], t1 = 0;
+    for (int i = 0; i < sd[k].nlevels; ++i) {
+      const DomainRec& dr = sd[k].dom_ids[i] == -1 ? DomainRec{{0, 0, 0, 0}, {g.lat.dims[0], 0, 0, 0}}
+                                                  : domain_get(c, sd[k].dom_ids[i]);
+      t0 = std::min(t0, dr.lo[0]);
+      t1 = std::max(t1, std::min(dr.hi[0], g.lat.dims[0]));
+    }
+    const size_t row = g.V / g.lat.dims[0] * 12;   // complex numbers of one time slice of one column
+    double2* sum = sd[k].sum ? reinterpret_cast<double2*>(ss[k].ptr) : nullptr;
+    if (sum && (t0 > 0 || t1 < g.lat.dims[0])) DDML_HIP(hipMemsetAsync(sum, 0, bytes, c->stream));
+    if (t1 > t0)
+      DDML_HIP(launch_series_diff(reinterpret_cast<double2*>(st[k].ptr), per[k], sd[k].nlevels, sum, c->stream,
+                                  nrhs, g.V * 12, (size_t)t0 * row, (size_t)(t1 - t0) * row));
     copy_back(c, sd[k].terms, st[k], bytes * sd[k].nlevels, on_device);
     if (sd[k].sum) copy_back(c, sd[k].sum, ss[k], bytes, on_device);
   }

@@ -23,8 +23,14 @@
 
 namespace ddml {
 
-__global__ void k_series_diff(double2* __restrict__ terms, size_t n, int nlevels, double2* __restrict__ sum) {
-  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+// terms[l] <- terms[l] - terms[l-1] (l >= 1) and sum <- terms[last] on the
+// elements [lo, lo + len) of each of ncol columns (column stride cstride) of
+// fields n apart; the elements outside hold zeros in every level.
+__global__ void k_series_diff(double2* __restrict__ terms, size_t n, int nlevels, double2* __restrict__ sum,
+                              int ncol, size_t cstride, size_t lo, size_t len) {
+  const size_t total = (size_t)ncol * len;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+    const size_t k = (t / len) * cstride + lo + t % len;
     double2 prev = terms[k];
     for (int l = 1; l < nlevels; ++l) {
       const double2 cur = terms[(size_t)l * n + k];
@@ -35,10 +41,18 @@ __global__ void k_series_diff(double2* __restrict__ terms, size_t n, int nlevels
   }
 }
 
-hipError_t launch_series_diff(double2* terms, size_t n, int nlevels, double2* sum, hipStream_t st) {
-  size_t g = (n + 255) / 256;
+hipError_t launch_series_diff(double2* terms, size_t n, int nlevels, double2* sum, hipStream_t st, int ncol,
+                              size_t cstride, size_t lo, size_t len) {
+  if (ncol <= 0) {   // the whole field
+    ncol = 1;
+    cstride = n;
+    lo = 0;
+    len = n;
+  }
+  size_t g = ((size_t)ncol * len + 255) / 256;
   if (g > 16384) g = 16384;
-  hipLaunchKernelGGL(k_series_diff, dim3((int)g), dim3(256), 0, st, terms, n, nlevels, sum);
+  if (g == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_series_diff, dim3((int)g), dim3(256), 0, st, terms, n, nlevels, sum, ncol, cstride, lo, len);
   return hipGetLastError();
 }
 

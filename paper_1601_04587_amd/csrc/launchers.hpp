@@ -103,7 +103,8 @@ hipError_t launch_boundary(const GaugeView& gv, const BlockSpec& bs, const doubl
                            double scale, hipStream_t st);
 
 // contract.hip
-hipError_t launch_series_diff(double2* terms, size_t n, int nlevels, double2* sum, hipStream_t st);
+hipError_t launch_series_diff(double2* terms, size_t n, int nlevels, double2* sum, hipStream_t st, int ncol = 0,
+                              size_t cstride = 0, size_t lo = 0, size_t len = 0);
 // out[i] = tr{g5 S^(i)(x,x)}, S^(i) the partial sums of a 12-column series (nlevels <= 64)
 hipError_t launch_g5_traces(const double2* terms, size_t V, int nlevels, size_t xs, double2* out, hipStream_t st);
 hipError_t launch_pp(const double2* tx, const double2* ty, size_t V, int nlevels, size_t xs, size_t ys, double invL3,
