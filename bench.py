@@ -150,7 +150,7 @@ def main():
     if args.stencil_only:
         return stencil_only(args)
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs every domain solve on a single "
+        print("bench.py measures one GPU only: the library runs every domain solve on a single "
               "MI355X (no collectives); --gpus %d is not supported." % args.gpus, file=sys.stderr)
         return 2
     import torch
