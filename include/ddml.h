@@ -512,6 +512,11 @@ typedef struct {
  * batching); params applies to every request.  max_queue bounds pending
  * requests (submit returns EAGAIN beyond it). */
 int ddml_server_start(ddml_ctx ctx, const ddml_solver_params* params, int max_queue);
+/* Queue one request.  src and sol must be device memory on the context's
+ * device: host pointers return EINVAL here, before anything is queued; a
+ * request whose buffers do not hold nrhs canonical fields of its gauge field's
+ * lattice inside one device allocation finishes with status EINVAL at
+ * admission, before any kernel touches them. */
 int ddml_submit(ddml_ctx ctx, const ddml_request* req, uint64_t* ticket);
 /* EAGAIN while pending; DDML_OK and *res once finished (the result is kept). */
 int ddml_poll(ddml_ctx ctx, uint64_t ticket, ddml_result* res);

@@ -862,6 +862,11 @@ int ddml_server_start(ddml_ctx ctx, const ddml_solver_params* params, int max_qu
 int ddml_submit(ddml_ctx ctx, const ddml_request* req, uint64_t* ticket) {
   if (!ctx || !req || !ticket || !ctx->c.server) return DDML_EINVAL;
   if (req->nrhs < 1 || req->nrhs > kMaxRhs || !req->src || !req->sol) return DDML_EINVAL;
+  // the request loop hands these to kernels: refuse host memory here, before
+  // anything is queued (their extent is checked at admission, when the
+  // field's volume is known)
+  if (!device_span_ok(req->src, 0, ctx->c.device) || !device_span_ok(req->sol, 0, ctx->c.device))
+    return DDML_EINVAL;
   return ctx->c.server->submit(*req, ticket);
 }
 

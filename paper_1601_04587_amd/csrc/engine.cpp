@@ -472,6 +472,25 @@ int gcr_len(const ddml_solver_params& prm) {
   return prm.gcr_m > 0 ? prm.gcr_m : kGcrMax;
 }
 
+bool device_span_ok(const void* p, size_t bytes, int device) {
+  hipPointerAttribute_t a{};
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();   // plain host memory: not an error of the stream
+    return false;
+  }
+  if (a.type != hipMemoryTypeDevice || a.device != device) return false;
+  if (bytes == 0) return true;
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  const char* b = static_cast<const char*>(base);
+  const char* q = static_cast<const char*>(p);
+  return q >= b && (size_t)(q - b) + bytes <= size;
+}
+
 size_t solve_footprint(Ctx* c, int gauge_id, int dom_id, int nrhs, const ddml_solver_params& prm) {
   const int prec = prm.prec, m = gcr_len(prm);
   const DomainRec d = domain_on(c, gauge_get(c, gauge_id), dom_id);

@@ -222,6 +222,9 @@ int domain_new(Ctx* c, const int lo[4], const int hi[4]);
 const DomainRec& domain_get(Ctx* c, int dom_id);  // dom_id -1 = full lattice
 std::shared_ptr<OpBlock> opblock(Ctx* c, int gauge_id, int dom_id);
 size_t solve_footprint(Ctx* c, int gauge_id, int dom_id, int nrhs, const ddml_solver_params& prm);
+// True if [p, p + bytes) lies inside one device allocation on `device`
+// (bytes 0: only that p is device memory there).  Host memory gives false.
+bool device_span_ok(const void* p, size_t bytes, int device);
 // GCR restart length of a parameter set (0 for BiCGstab)
 int gcr_len(const ddml_solver_params& prm);
 void apply_D(Ctx* c, int gauge_id, int dom_id, const double* in, double* out, int nrhs, hipStream_t st);

@@ -135,6 +135,9 @@ void Server::loop() {
         size_t fp = 0;
         try {
           fp = solve_footprint(ctx, s->gauge_id, s->dom_id, s->nrhs, s->prm);
+          const size_t bytes = (size_t)s->nrhs * gauge_get(ctx, s->gauge_id).V * 12 * sizeof(double2);
+          if (!device_span_ok(s->src, bytes, ctx->device) || !device_span_ok(s->sol, bytes, ctx->device))
+            throw Error{DDML_EINVAL, "request buffers do not hold nrhs canonical fields in device memory"};
         } catch (const Error& e) {
           q->res.status = e.code;
           waiting.pop_front();

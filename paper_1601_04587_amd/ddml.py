@@ -214,6 +214,7 @@ class Context:
         if rc != OK:
             raise DDMLError(rc, "ddml_create failed")
         self.h = h
+        self.device = int(device)
 
     def close(self):
         if self.h:
@@ -514,6 +515,13 @@ class Context:
         self._check(self.lib.ddml_server_start(self.h, ctypes.byref(params), max_queue))
 
     def submit(self, gid, dom, src, sol, nrhs, arrival_time=None):
+        """Queue one request; src and sol must be contiguous device tensors on
+        the context's device (the request loop reads and writes them later)."""
+        for name, a in (("src", src), ("sol", sol)):
+            if not (hasattr(a, "is_cuda") and a.is_cuda and a.is_contiguous()):
+                raise ValueError("%s must be a contiguous device tensor" % name)
+            if a.device.index != self.device:
+                raise ValueError("%s is on device %s, the context on %d" % (name, a.device, self.device))
         ps, _ = _ptr(src)
         pd, _ = _ptr(sol)
         t = now() if arrival_time is None else arrival_time

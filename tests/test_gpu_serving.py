@@ -65,6 +65,42 @@ def test_serving_alone_equals_mixed_bitwise(setup):
     assert res.max() <= 1e-10 * (1 + 1e-3)
 
 
+def test_submit_rejects_host_and_short_buffers(setup):
+    """Host memory is refused by the binding and by ddml_submit itself before
+    anything is queued; a device buffer too small for nrhs canonical fields
+    finishes with EINVAL at admission, before any kernel reads it."""
+    import ctypes
+    L, U, ctx, gid, doms, ids = setup
+    dev = torch.device("cuda:0")
+    V = int(np.prod(L))
+    src = torch.from_numpy(inputs.point_source(L, (7, 0, 0, 0))).to(dev)
+    out = torch.zeros((12, V, 4, 3), dtype=torch.complex128, device=dev)
+    host = np.zeros((12, V, 4, 3), dtype=np.complex128)
+    torch.cuda.synchronize()
+    ctx.server_start(ddml.solver_params(tol=1e-10))
+    try:
+        with pytest.raises(ValueError):
+            ctx.submit(gid, ids["G0"], src, host, 12)
+        with pytest.raises(ValueError):
+            ctx.submit(gid, ids["G0"], src.cpu(), out, 12)
+        # the C entry point on its own (no binding check in front of it)
+        ticket = ctypes.c_uint64()
+        for ps, pd in ((host.ctypes.data, out.data_ptr()), (src.data_ptr(), host.ctypes.data)):
+            req = ddml.Request(gid, ids["G0"], ps, pd, 12, ddml.now())
+            assert ctx.lib.ddml_submit(ctx.h, ctypes.byref(req), ctypes.byref(ticket)) == ddml.EINVAL
+        # one element in a small-block segment cannot hold 12 fields of 16 x 8^3 sites
+        tiny = torch.zeros(1, dtype=torch.complex128, device=dev)
+        torch.cuda.synchronize()
+        r = ctx.wait(ctx.submit(gid, ids["G0"], src, tiny, 12), 60.0)
+        assert r is not None and r.status == ddml.EINVAL
+        assert tiny.item() == 0
+        # the loop keeps serving good requests
+        r = ctx.wait(ctx.submit(gid, ids["G0"], src, out, 12), 120.0)
+        assert r is not None and r.status == ddml.OK
+    finally:
+        ctx.server_stop()
+
+
 def test_series_batch_matches_single_series(setup):
     L, U, ctx, gid, doms, ids = setup
     V = int(np.prod(L))
