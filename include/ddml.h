@@ -319,6 +319,25 @@ int ddml_two_level_average(int n0, int n1, int nc, int ma, int mb, const double*
 int ddml_contract_nucleon(ddml_ctx ctx, const double* terms, int nlevels, double* levels_out, double* diffs_out,
                           int on_device, void* stream);
 
+/* Allocation-free variant of ddml_contract_nucleon, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  It computes the same two arrays (the sum
+ * over each sink slice is taken per workgroup of 8 sites first, so results
+ * agree with ddml_contract_nucleon to rounding, not bit for bit) and calls no
+ * hipMalloc, hipFree or allocating library routine: its scratch, the
+ * per-workgroup partial sums of nlevels x V/8 complex numbers, lives in a
+ * static device array of 16 MiB per device, held until the process ends.
+ * terms [nlevels][12][V][4][3] complex, levels_out and diffs_out (diffs_out
+ * may be NULL) [nlevels][T] complex: all device memory on the context's
+ * device, owned by the caller.  Work is queued on `stream` (NULL: the null
+ * stream) and not waited for.  Every call on one device shares the scratch
+ * array and overwrites it, so calls that overlap on one device (several
+ * streams, several contexts or threads) race; order them on one stream.
+ * Errors: EINVAL (host pointers, buffers too small, nlevels outside 1..64,
+ * nlevels x V / 8 x 16 bytes beyond 16 MiB), EDEVICE. */
+int ddml_contract_nucleon_noalloc(ddml_ctx ctx, const double* terms, int nlevels, double* levels_out,
+                                  double* diffs_out, void* stream);
+
 /* Boundary block of D (Section 2, eq. blkdec; the off-diagonal block of eq.
  * Scmpt2): out = scale * D_{dGamma} in, where D_{dGamma} holds the entries of
  * D that couple a site y outside the domain Gamma to a site x inside it,

@@ -849,6 +849,29 @@ int ddml_contract_nucleon(ddml_ctx ctx, const double* terms, int nlevels, double
   });
 }
 
+int ddml_contract_nucleon_noalloc(ddml_ctx ctx, const double* terms, int nlevels, double* levels_out,
+                                  double* diffs_out, void* stream) {
+  return guarded(ctx, [&](Ctx* c) {
+    need(terms && levels_out && nlevels >= 1 && nlevels <= 64, "bad arguments");
+    const int T = c->lat.dims[0];
+    const size_t need_scratch = (size_t)nlevels * (c->V / 8) * sizeof(double2);
+    if (need_scratch > kNucScratchBytes)
+      throw Error{DDML_EINVAL, "nlevels x volume too large for the allocation-free nucleon contraction (" +
+                                   std::to_string(need_scratch) + " > " + std::to_string(kNucScratchBytes) +
+                                   " bytes of scratch)"};
+    const size_t bytes = (size_t)nlevels * 12 * c->V * 12 * sizeof(double2);
+    const size_t obytes = (size_t)nlevels * T * sizeof(double2);
+    need(device_span_ok(terms, bytes, c->device), "terms must be device memory holding nlevels series terms");
+    need(device_span_ok(levels_out, obytes, c->device), "levels_out must be device memory of nlevels x T complex");
+    need(!diffs_out || device_span_ok(diffs_out, obytes, c->device),
+         "diffs_out must be device memory of nlevels x T complex");
+    DDML_HIP(launch_nucleon_noalloc(reinterpret_cast<const double2*>(terms), c->V, T, nlevels,
+                                    reinterpret_cast<double2*>(levels_out), reinterpret_cast<double2*>(diffs_out),
+                                    c->device, static_cast<hipStream_t>(stream)));
+    return DDML_OK;
+  });
+}
+
 int ddml_server_start(ddml_ctx ctx, const ddml_solver_params* params, int max_queue) {
   return guarded(ctx, [&](Ctx* c) {
     check_params(params);

@@ -18,6 +18,8 @@
 //    site (sources, then components, in order) before the slice sums.
 // In the chiral basis C = diag(s_2, -s_2), so C g5 = diag(s_2, s_2), and
 // P_- = [[1,1],[1,1]]/2 in 2x2 spin blocks; both are applied in closed form below.
+#include <mutex>
+
 #include "ddml_common.hpp"
 #include "launchers.hpp"
 
@@ -178,10 +180,16 @@ __device__ double2 nucleon_pair(const double2* S, int pair) {
   return make_double2(sgn * (w1.x - w2.x), sgn * (w1.y - w2.y));
 }
 
+// PART = false: W[level][site] per sink site.  PART = true: W[level][block],
+// the sum over the workgroup's kNucSites sites in site order (the sites of a
+// workgroup lie in one time slice: every extent is even, so L^3 is a multiple
+// of 8).
+template <bool PART>
 __global__ void __launch_bounds__(64) k_nucleon_site(const double2* __restrict__ terms, size_t V, int nlevels,
                                                      double2* __restrict__ W) {
   __shared__ double2 S[kNucSites][144];
   __shared__ double2 part[64];
+  __shared__ double2 sites[kNucSites];
   __shared__ int nz[kNucSites];
   const size_t y0 = (size_t)blockIdx.x * kNucSites;
   const int nsite = (int)(V - y0 < (size_t)kNucSites ? V - y0 : kNucSites);
@@ -213,7 +221,16 @@ __global__ void __launch_bounds__(64) k_nucleon_site(const double2* __restrict__
     if (q == 0 && ls < nsite) {
       double2 s = part[tid];                    // fixed order over the site's threads
       for (int k = 1; k < kNucThreads; ++k) s = cadd2(s, part[tid + k]);
-      W[(size_t)level * V + y0 + ls] = s;
+      if (PART) sites[ls] = s;
+      else W[(size_t)level * V + y0 + ls] = s;
+    }
+    if (PART) {
+      __syncthreads();
+      if (tid == 0) {
+        double2 s = sites[0];                   // fixed order over the workgroup's sites
+        for (int k = 1; k < nsite; ++k) s = cadd2(s, sites[k]);
+        W[(size_t)level * (V / kNucSites) + blockIdx.x] = s;
+      }
     }
     __syncthreads();
   }
@@ -335,8 +352,66 @@ hipError_t launch_noise_trace(const double2* eta, const double2* phi, int nsrc, 
 hipError_t launch_nucleon(const double2* terms, size_t V, int T, int nlevels, double2* W, double2* out,
                           hipStream_t st) {
   const unsigned blocks = (unsigned)((V + kNucSites - 1) / kNucSites);
-  hipLaunchKernelGGL(k_nucleon_site, dim3(blocks), dim3(64), 0, st, terms, V, nlevels, W);
+  hipLaunchKernelGGL(k_nucleon_site<false>, dim3(blocks), dim3(64), 0, st, terms, V, nlevels, W);
   hipLaunchKernelGGL(k_slice_sum, dim3(T, nlevels), dim3(256), 0, st, W, V, T, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------- nucleon without allocations
+// Scratch of the allocation-free nucleon contraction: the per-workgroup
+// partial sums [nlevels][V / 8] complex.  One copy per device, resolved once
+// per device with hipGetSymbolAddress and used through that address only (in
+// host code the array's name is not a device address).  Every call on a
+// device shares it; calls that overlap on one device race.
+static __device__ __align__(256) double2 scratch[kNucScratchBytes / sizeof(double2)];
+
+namespace {
+std::mutex g_scratch_mu;
+double2* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t nucleon_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != device) return hipErrorInvalidDevice;   // the caller makes `device` current
+  void* p = nullptr;
+  e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = static_cast<double2*>(p);
+  return hipSuccess;
+}
+
+// diffs[0] = levels[0], diffs[i] = levels[i] - levels[i-1] (eq. seriesN)
+__global__ void k_level_diffs(const double2* __restrict__ levels, int nlevels, int T, double2* __restrict__ diffs) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < T; t += gridDim.x * blockDim.x) {
+    double2 prev = make_double2(0, 0);
+    for (int i = 0; i < nlevels; ++i) {
+      const double2 c = levels[(size_t)i * T + t];
+      diffs[(size_t)i * T + t] = make_double2(c.x - prev.x, c.y - prev.y);
+      prev = c;
+    }
+  }
+}
+
+hipError_t launch_nucleon_noalloc(const double2* terms, size_t V, int T, int nlevels, double2* levels,
+                                  double2* diffs, int device, hipStream_t st) {
+  if (device < 0 || device >= kMaxDevices || nlevels < 1 || T < 1 || V % ((size_t)T * kNucSites))
+    return hipErrorInvalidValue;
+  double2* P;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    P = g_scratch_ptr[device];
+  }
+  if (!P) return hipErrorNotInitialized;
+  if ((size_t)nlevels * (V / kNucSites) * sizeof(double2) > kNucScratchBytes) return hipErrorInvalidValue;
+  const unsigned blocks = (unsigned)(V / kNucSites);
+  hipLaunchKernelGGL(k_nucleon_site<true>, dim3(blocks), dim3(64), 0, st, terms, V, nlevels, P);
+  hipLaunchKernelGGL(k_slice_sum, dim3(T, nlevels), dim3(256), 0, st, P, V / kNucSites, T, levels);
+  if (diffs) hipLaunchKernelGGL(k_level_diffs, dim3((T + 63) / 64), dim3(64), 0, st, levels, nlevels, T, diffs);
   return hipGetLastError();
 }
 

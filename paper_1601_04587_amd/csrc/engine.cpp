@@ -125,6 +125,8 @@ void ctx_init(Ctx* c, const ddml_lattice* lat, int device, size_t budget) {
   DDML_HIP(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) throw Error{DDML_EINVAL, "no such device"};
   DDML_HIP(hipSetDevice(device));
+  // the allocation-free entry points' scratch: its address on this device
+  DDML_HIP(nucleon_scratch_init(device));
   c->lat = *lat;
   c->device = device;
   c->V = (size_t)lat->dims[0] * lat->dims[1] * lat->dims[2] * lat->dims[3];

@@ -138,5 +138,15 @@ hipError_t launch_trace_pairs(const double2* Gt, const double2* G, int n, int T,
 // W: scratch [nlevels][V]; out: [nlevels][T]
 hipError_t launch_nucleon(const double2* terms, size_t V, int T, int nlevels, double2* W, double2* out,
                           hipStream_t st);
+// Allocation-free nucleon contraction (the scratch is a static device array
+// of kNucScratchBytes per device): levels [nlevels][T] and, if not null,
+// diffs [nlevels][T], device pointers, stream-ordered on st.
+// nucleon_scratch_init resolves the array's address on `device`, which must
+// be current; once per device, before the first launch there.
+constexpr size_t kNucScratchBytes = (size_t)16 << 20;
+constexpr int kMaxDevices = 64;
+hipError_t nucleon_scratch_init(int device);
+hipError_t launch_nucleon_noalloc(const double2* terms, size_t V, int T, int nlevels, double2* levels,
+                                  double2* diffs, int device, hipStream_t st);
 
 }  // namespace ddml

@@ -69,6 +69,7 @@ EXPORTS = ["ddml_create", "ddml_destroy", "ddml_last_error", "ddml_set_gauge", "
            "ddml_set_gauge_region", "ddml_level1_update", "ddml_get_gauge",
            "ddml_release_gauge", "ddml_set_domain", "ddml_apply_Dw", "ddml_apply_eo", "ddml_solve_domain",
            "ddml_solve_batch", "ddml_propagator_series", "ddml_propagator_series_batch", "ddml_time_stencil", "ddml_autotune", "ddml_set_launch", "ddml_contract_pp_disconnected", "ddml_contract_nucleon",
+           "ddml_contract_nucleon_noalloc",
            "ddml_apply_boundary", "ddml_factorized_series", "ddml_factorized_chain", "ddml_contract_pion", "ddml_hpe_trace",
            "ddml_inverse_iteration", "ddml_projected_pion", "ddml_projected_nucleon", "ddml_two_level_average", "ddml_trace_g5",
            "ddml_server_start", "ddml_submit", "ddml_poll", "ddml_wait", "ddml_stats", "ddml_server_stop",
@@ -114,6 +115,7 @@ def load():
     lib.ddml_set_launch.argtypes = [P, I, I, I, I, I, I]
     lib.ddml_contract_pp_disconnected.argtypes = [P, P, P, I, IP, IP, P, I, P]
     lib.ddml_contract_nucleon.argtypes = [P, P, I, P, P, I, P]
+    lib.ddml_contract_nucleon_noalloc.argtypes = [P, P, I, P, P, P]
     lib.ddml_apply_boundary.argtypes = [P, I, I, P, P, I, D, I, P]
     lib.ddml_factorized_chain.argtypes = [P, I, IP, I, P, I, ctypes.POINTER(SolverParams), P, P, P, I, P]
     lib.ddml_factorized_series.argtypes = [P, I, IP, I, I, P, I, ctypes.POINTER(SolverParams), P, P,
@@ -494,6 +496,17 @@ class Context:
         self._check(self.lib.ddml_contract_nucleon(self.h, pt, nlevels, levels.ctypes.data, diffs.ctypes.data, dev,
                                                    _stream(terms)))
         return levels, diffs
+
+    def contract_nucleon_noalloc(self, terms, nlevels, levels_out, diffs_out=None):
+        """ddml_contract_nucleon_noalloc: terms, levels_out [nlevels, T] and diffs_out
+        (or None) complex128 device tensors; queued on terms' current stream."""
+        for a in (terms, levels_out) + ((diffs_out,) if diffs_out is not None else ()):
+            if not (hasattr(a, "is_cuda") and a.is_cuda):
+                raise ValueError("contract_nucleon_noalloc takes device tensors")
+        pt, _ = _ptr(terms)
+        pl, _ = _ptr(levels_out)
+        pd = _ptr(diffs_out)[0] if diffs_out is not None else None
+        self._check(self.lib.ddml_contract_nucleon_noalloc(self.h, pt, nlevels, pl, pd, _stream(terms)))
 
     def contract_pion(self, levels, nlevels, full=None):
         """Connected pion correlator per level, its series differences and (with the full
