@@ -33,6 +33,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM = 8.0e12  # MI355X HBM3E, bytes/s
+# reals per domain site of the links of both stencil halves and the clover
+# inverse in one M-hat application: 4 links per site and half, stored as their
+# first two rows (12 reals; the stencil rebuilds the third), 72 for A^-1
+LINK_REALS = 168
 
 
 def log(*a):
@@ -79,11 +83,15 @@ def parse():
                     help="only the factorized pion leg (profiling runs)")
     ap.add_argument("--projected-only", action="store_true",
                     help="only the projector-cut pion and nucleon leg (profiling runs)")
-    ap.add_argument("--serve-requests", type=int, default=64, help="requests per serving stream")
+    ap.add_argument("--serve-requests", type=int, default=256,
+                    help="requests per serving stream (at least a few hundred, so that p99 is not the maximum)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="configured Poisson rate, req/s")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--stencil-iters", type=int, default=20)
     ap.add_argument("--sweep-iters", type=int, default=2, help="timed pairs per launch variant (--stencil-only)")
+    ap.add_argument("--decorrelate", type=int, default=4,
+                    help="full-volume sweeps (1 heatbath + 4 over-relaxation) of the base field after replicating "
+                         "a thermalised 16x8^3 field")
     ap.add_argument("--stencil-only", action="store_true",
                     help="only time the stencil kernels on the 32^3x16 slab domain (profiling runs); "
                          "also runs one plain 1 GiB device copy as the reference for HBM counters")
@@ -94,7 +102,7 @@ def launch_variants(nrhs=12):
     """Every stencil launch the autotuner considers, in its order:
     (R, tile_order, grid, splits, stage)."""
     out = []
-    for stage in (0, 1):
+    for stage in (1,):   # FP32 fields are read through the LDS staging (two-row links)
         for R in (1, 2, 3):
             for splits in (1, 2, 3):
                 if splits > (nrhs + R - 1) // R:
@@ -171,8 +179,9 @@ def main():
 
     # ------------------------------------------------------------ inputs
     t = time.time()
-    U0 = inputs.quenched_field(L, seed, beta=beta)
-    log("base field %s plaquette %.4f (%.1fs)" % (L, inputs.plaquette(U0, L), time.time() - t))
+    U0 = inputs.quenched_field(L, seed, beta=beta, decorrelate=args.decorrelate)
+    plaq0 = inputs.plaquette(U0, L)
+    log("base field %s plaquette %.5f after %d full sweeps (%.1fs)" % (L, plaq0, args.decorrelate, time.time() - t))
     if args.factorized_only or args.projected_only:
         ctx = ddml.Context(L, ddml.BC_ANTIPERIODIC, device=0)
         U0_dev = torch.from_numpy(U0).to(dev)
@@ -323,13 +332,22 @@ def main():
                                                  s16[3] / s16[1] * 1e-6))
 
     # --------------------------------------------------- stencil roofline
+    # One application of the Schur operator M-hat (odd half, then even half) on
+    # the 16-slice slab domain, 12 columns: (60 nrhs + LINK_REALS) reals per
+    # site of the domain (input, intermediate and output spinors; links of
+    # both halves and the clover inverse), HIP events around each launch.
     sten32 = ctx.time_stencil(gid0, doms[0][2], 12, ddml.MIXED_FP32, args.stencil_iters)
     sten64 = ctx.time_stencil(gid0, doms[0][2], 12, ddml.FP64, max(4, args.stencil_iters // 2))
-    ach = sten32[3] / (sten32[1] * 1e-3)
-    ach_odd = sten32[2] / (sten32[0] * 1e-3)
-    ach64 = sten64[3] / (sten64[1] * 1e-3)
-    log("stencil fp32: even half %.3f ms %.0f GB/s, odd half %.3f ms %.0f GB/s; fp64 even half %.0f GB/s"
-        % (sten32[1], ach / 1e9, sten32[0], ach_odd / 1e9, ach64 / 1e9))
+    VG = 16 * V3
+    bytes_pair = VG * (60 * 12 + LINK_REALS) * 4
+    ms_pair = sten32[0] + sten32[1]
+    ach = bytes_pair / (ms_pair * 1e-3)
+    ach64 = VG * (60 * 12 + 216) * 8 / ((sten64[0] + sten64[1]) * 1e-3)
+    t_odd = counter_traffic("odd,R=%d,order=%d,grid=%d,splits=%d,stage=%d" % tune32[:5])
+    t_even = counter_traffic("even,R=%d,order=%d,grid=%d,splits=%d,stage=%d" % tune32[:5])
+    traffic = (t_odd + t_even) if (t_odd is not None and t_even is not None) else None
+    log("stencil fp32 M-hat: odd %.3f ms + even %.3f ms -> %.0f GB/s (%.3f of peak); fp64 M-hat %.0f GB/s"
+        % (sten32[0], sten32[1], ach / 1e9, ach / PEAK_HBM, ach64 / 1e9))
 
     # ------------------------------------------------ plain FP64 baseline
     fp64 = None
@@ -369,7 +387,8 @@ def main():
     # ------------------------------------------------------- CPU baseline
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(U0, L, kappa, csw, args.cpu_seconds)
+        lev_iters = [float(np.mean(iters[k::3])) for k in range(3)]
+        cpu = cpu_baseline(U0, L, kappa, csw, args.cpu_seconds, lev_iters)
         level1["cpu_oracle"] = cpu_level1(U0, L, beta, seed)
 
     ctx.close()
@@ -386,15 +405,19 @@ def main():
         "vs_baseline": None,
         "dtype": "fp32 inner / fp64 outer",
         "data": "synthetic: seeded beta=6.0 quenched heatbath fields and level-1 slab updates",
+        "base_field": {"plaquette": plaq0, "full_volume_sweeps": args.decorrelate},
         "config": {"workload": "batched multi-level, %s lattice, %d slabs x 1 update per step, "
                                "Gamma0/1/2 = 4/8/16 slices x 12 rhs, tol 1e-10" % ("x".join(map(str, L)), nslab),
                    "lattice": list(L), "kappa": kappa, "csw": csw, "solves_per_step": 3 * nslab, "nrhs": 12},
         "roofline": {"bound": "hbm", "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                     "frac": ach / PEAK_HBM, "traffic": counter_traffic("even,R=%d,order=%d,grid=%d,splits=%d,stage=%d" % tune32[:5]),
-                     "kernel": "k_hop_batch<float2> even half-stencil (Schur + fused dot), 32^3x16 domain, 12 rhs",
-                     "ms_per_launch": sten32[1], "bytes_per_launch": sten32[3],
-                     "odd_half": {"ms": sten32[0], "GB/s": ach_odd / 1e9},
-                     "fp64_even_half_GBps": ach64 / 1e9},
+                     "frac": ach / PEAK_HBM, "traffic": traffic,
+                     "kernel": "k_hop_batch<float2> M-hat pair (odd half A^-1 H, then even half Schur + fused "
+                               "shadow dot), 32^3x16 domain, 12 rhs",
+                     "ms_per_launch": ms_pair, "bytes_per_launch": bytes_pair,
+                     "bytes_per_site": (60 * 12 + LINK_REALS) * 4,
+                     "odd_half": {"ms": sten32[0], "bytes": sten32[2], "GB/s": sten32[2] / sten32[0] * 1e-6},
+                     "even_half": {"ms": sten32[1], "bytes": sten32[3], "GB/s": sten32[3] / sten32[1] * 1e-6},
+                     "fp64_mhat_GBps": ach64 / 1e9},
         "autotune": {"fp32": dict(zip(("R", "tile_order", "grid", "splits", "stage", "ms_pair"), tune32)),
                      "fp64": dict(zip(("R", "tile_order", "grid", "splits", "stage", "ms_pair"), tune64))},
         "fp64_one_at_a_time": fp64,
@@ -699,8 +722,15 @@ def cpu_level1(U0, L, beta, seed):
     return {"s_per_slab_update": dt, "links_per_s": nlinks / dt, "cores": cores, "kind": "oracle"}
 
 
-def cpu_baseline(U0, L, kappa, csw, seconds):
-    """FP64 CPU oracle on a bounded sample: one column of a Gamma0 (4 x 32^3) solve."""
+def cpu_baseline(U0, L, kappa, csw, seconds, lev_iters):
+    """FP64 CPU oracle on a bounded sample: one column of a Gamma0 (4 x 32^3)
+    solve to 1e-10, scaled to the step's mix of Gamma0/1/2 solves (volumes
+    1:2:4) with the GPU's measured inner iterations per level as the ratio of
+    iteration counts (the oracle's unpreconditioned BiCGstab needs more
+    iterations than the even-odd solve, by about the same factor on every
+    level).  Also the single-thread rate from a few iterations on one thread."""
+    import ctypes
+
     import inputs
     import oracle
 
@@ -712,7 +742,7 @@ def cpu_baseline(U0, L, kappa, csw, seconds):
     b = inputs.point_source(Ls, (7, 0, 0, 0))[:1]
     # calibrate the iteration time, then run a bounded solve
     t = time.time()
-    _, it0, _ = oracle.solve(Us, Ls, kappa, b, C=C, lo=lo, hi=hi, tol=1e-30, maxiter=3)
+    oracle.solve(Us, Ls, kappa, b, C=C, lo=lo, hi=hi, tol=1e-30, maxiter=3)
     per_it = (time.time() - t) / 3
     maxit = max(5, int(seconds / per_it))
     t = time.time()
@@ -725,13 +755,30 @@ def cpu_baseline(U0, L, kappa, csw, seconds):
     else:  # linear in log residual
         need = int(np.ceil(it * np.log(1e-10) / np.log(max(r, 1e-300))))
     t_col = el / max(it, 1) * need
-    # a domain solve has 12 columns; the step mixes Gamma0/1/2 with volumes 1:2:4
-    solves_per_s = 3.0 / (12 * t_col * (1 + 2 + 4))
+    vol = (1.0, 2.0, 4.0)
+    ratio = [lev_iters[k] / lev_iters[0] for k in range(3)]
+    t_step_cols = 12 * t_col * sum(vol[k] * ratio[k] for k in range(3))   # one Gamma0/1/2 triple
+    solves_per_s = 3.0 / t_step_cols
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count()))
+    # one thread: a few iterations of the same column
+    single = None
+    try:
+        omp = ctypes.CDLL("libgomp.so.1")
+        omp.omp_set_num_threads(1)
+        t = time.time()
+        oracle.solve(Us, Ls, kappa, b, C=C, lo=lo, hi=hi, tol=1e-30, maxiter=3)
+        per_it1 = (time.time() - t) / 3
+        omp.omp_set_num_threads(cores)
+        single = solves_per_s * per_it / per_it1
+    except OSError:
+        pass
     out = {"value": solves_per_s, "unit": "domain solves/s", "cores": cores, "kind": "oracle",
+           "single_thread_value": single,
            "sample": "1 of 12 columns of a Gamma0 (4x32^3) solve, %d BiCGstab iterations in %.1fs, residual %.1e%s; "
-                     "scaled to 12 columns and the 1:2:4 volume mix of Gamma0/1/2 assuming equal iteration counts"
-                     % (it, el, r, "" if r <= 1e-10 else " (iterations to 1e-10 extrapolated: %d)" % need)}
+                     "scaled to 12 columns and to the step's Gamma0/1/2 mix by volume (1:2:4) times the GPU's "
+                     "measured inner-iteration ratio per level (%.2f : %.2f : %.2f)"
+                     % (it, el, r, "" if r <= 1e-10 else " (iterations to 1e-10 extrapolated: %d)" % need,
+                        ratio[0], ratio[1], ratio[2])}
     log("cpu baseline: %s" % out)
     return out
 

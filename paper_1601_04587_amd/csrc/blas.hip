@@ -1,11 +1,19 @@
 // Krylov vector kernels and FP64 reductions for the batched BiCGstab.
 //
 // BiCGstab (van der Vorst 1992) on the even-odd Schur operator, one
-// independent recursion per right-hand side.  Reliable updates: when the
-// FP64 defect-correction loop replaces the recursive residual r by the true
-// one, the Krylov state (r0, p, v, alpha, omega) is kept and only rho and beta
-// are rescaled to the new r (VEC_RELUP + FIN_RELUP); a column whose recursion
-// broke down starts afresh instead.  Every kernel walks a slot table
+// independent recursion per right-hand side, with a hashed shadow vector h
+// (shadow_bits) in place of the stored r0.  One iteration:
+//   v = M p, alpha = rho / (h, v);  s = r - alpha v;  t = M s,
+//   omega = (t, s) / (t, t);  x += alpha p + omega s;  r = s - omega t;
+//   p = r + beta (p - omega v),  beta = (rho'/rho)(alpha/omega),
+// where rho' = (h, r) of the new residual equals (h, s) - omega (h, t): both
+// dot products come from the kernels that write s and t, so beta is known
+// before r is formed and the direction update shares the x/r pass (VEC_XRP).
+// Reliable updates: when the FP64 defect-correction loop replaces the
+// recursive residual by the true one r', the Krylov space is kept and only p
+// and rho are rescaled, p = r' + (rho'/rho)(p - r_old) (VEC_RELUP, FIN_RELUP,
+// VEC_PFIX); a column whose recursion broke down starts afresh instead.
+// Every kernel walks a slot table
 // (one entry per domain solve in flight) with a grid-stride loop over virtual
 // 64-site tiles; a workgroup is 64 sites x nrhs columns, one wavefront per
 // column, so every reduction is a wavefront reduction written to a fixed
@@ -34,6 +42,11 @@ __device__ __forceinline__ int find_slot_v(const int* __restrict__ start, int n,
   return lo;
 }
 
+// Partial-sum slot k of column col, tile `tile`
+__device__ __forceinline__ double2* part_at(double2* partial, int nrhs, int ntiles, int k, int col, int tile) {
+  return partial + ((size_t)k * nrhs + col) * ntiles + tile;
+}
+
 template <typename T2, int OP>
 __global__ void __launch_bounds__(768) k_vec(const SlotDesc<T2>* __restrict__ slots, const int* __restrict__ tile_start,
                                              const int* __restrict__ nslots_p) {
@@ -52,100 +65,91 @@ __global__ void __launch_bounds__(768) k_vec(const SlotDesc<T2>* __restrict__ sl
     const bool valid = i < d.g.Vh;
     const size_t base = fidx(d.ntiles, col, 0, i);
     const BiState& st = d.st[col];
+    const unsigned hb = shadow_bits(col, i);
     double2 s0 = make_double2(0, 0), s1 = make_double2(0, 0);
-    if (OP == VEC_P) {
-      if (valid) {
-        const T2 be = mk<T2>((T)st.beta.x, (T)st.beta.y), om = mk<T2>((T)st.omega.x, (T)st.omega.y);
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-          const size_t o = base + 128 * k;
-          T2 p0, p1, r0, r1, v0, v1;
-          ld2(d.f[F_P] + o, p0, p1);
-          ld2(d.f[F_R] + o, r0, r1);
-          ld2(d.f[F_V] + o, v0, v1);
-          st2(d.f[F_P] + o, cadd(r0, cmul(be, csub(p0, cmul(om, v0)))), cadd(r1, cmul(be, csub(p1, cmul(om, v1)))));
-        }
-      }
-    } else if (OP == VEC_S) {
+    if (OP == VEC_S) {
       const T2 al = mk<T2>((T)st.alpha.x, (T)st.alpha.y);
+      T2 o[12];
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
-        const size_t o = base + 128 * k;
+        const size_t q = base + 128 * k;
         T2 r0 = mk<T2>(0, 0), r1 = r0, v0 = r0, v1 = r0;
         if (valid) {
-          ld2(d.f[F_R] + o, r0, r1);
-          ld2(d.f[F_V] + o, v0, v1);
+          ld2(d.f[F_R] + q, r0, r1);
+          ld2(d.f[F_V] + q, v0, v1);
         }
-        st2(d.f[F_S] + o, csub(r0, cmul(al, v0)), csub(r1, cmul(al, v1)));
+        o[2 * k] = csub(r0, cmul(al, v0));
+        o[2 * k + 1] = csub(r1, cmul(al, v1));
+        st2(d.f[F_S] + q, o[2 * k], o[2 * k + 1]);
       }
-    } else if (OP == VEC_XR) {
+      shadow_dot(hb, o, s0);
+    } else if (OP == VEC_XRP) {
       if (valid) {
         const T2 al = mk<T2>((T)st.alpha.x, (T)st.alpha.y), om = mk<T2>((T)st.omega.x, (T)st.omega.y);
+        const T2 be = mk<T2>((T)st.beta.x, (T)st.beta.y);
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-          const size_t o = base + 128 * k;
-          T2 x0, x1, p0, p1, s0v, s1v, t0, t1, h0, h1;
-          ld2(d.f[F_X] + o, x0, x1);
-          ld2(d.f[F_P] + o, p0, p1);
-          ld2(d.f[F_S] + o, s0v, s1v);
-          ld2(d.f[F_T] + o, t0, t1);
-          ld2(d.f[F_RH] + o, h0, h1);
-          st2(d.f[F_X] + o, cadd(x0, cadd(cmul(al, p0), cmul(om, s0v))), cadd(x1, cadd(cmul(al, p1), cmul(om, s1v))));
-          const T2 n0 = csub(s0v, cmul(om, t0)), n1 = csub(s1v, cmul(om, t1));
-          st2(d.f[F_R] + o, n0, n1);
-          s0.x += (double)h0.x * n0.x + (double)h0.y * n0.y + (double)h1.x * n1.x + (double)h1.y * n1.y;
-          s0.y += (double)h0.x * n0.y - (double)h0.y * n0.x + (double)h1.x * n1.y - (double)h1.y * n1.x;
+          const size_t q = base + 128 * k;
+          T2 x0, x1, p0, p1, sv0, sv1, t0, t1, v0, v1;
+          ld2(d.f[F_X] + q, x0, x1);
+          ld2(d.f[F_P] + q, p0, p1);
+          ld2(d.f[F_S] + q, sv0, sv1);
+          ld2(d.f[F_T] + q, t0, t1);
+          ld2(d.f[F_V] + q, v0, v1);
+          st2(d.f[F_X] + q, cadd(x0, cadd(cmul(al, p0), cmul(om, sv0))), cadd(x1, cadd(cmul(al, p1), cmul(om, sv1))));
+          const T2 n0 = csub(sv0, cmul(om, t0)), n1 = csub(sv1, cmul(om, t1));
+          st2(d.f[F_R] + q, n0, n1);
+          st2(d.f[F_P] + q, cadd(n0, cmul(be, csub(p0, cmul(om, v0)))), cadd(n1, cmul(be, csub(p1, cmul(om, v1)))));
           s1.x += (double)n0.x * n0.x + (double)n0.y * n0.y + (double)n1.x * n1.x + (double)n1.y * n1.y;
         }
       }
-    } else if (OP == VEC_RELUP) {
-      // r = (T) src64 and x = 0; a column that restarts also gets rh = r, p = v = 0
-      const bool fresh = st.status != 0;
+    } else if (OP == VEC_PFIX) {
+      if (valid) {
+        const T2 be = mk<T2>((T)st.beta.x, (T)st.beta.y);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          const size_t q = base + 128 * k;
+          T2 p0, p1, r0, r1;
+          ld2(d.f[F_P] + q, p0, p1);
+          ld2(d.f[F_R] + q, r0, r1);
+          st2(d.f[F_P] + q, cadd(r0, cmul(be, p0)), cadd(r1, cmul(be, p1)));
+        }
+      }
+    } else {  // VEC_INIT / VEC_RELUP: r = (T) src64, x = 0 (padding sites: all zero)
+      // a fresh column gets p = r; a column that keeps its Krylov space gets
+      // p - r_old, which VEC_PFIX turns into r + (rho'/rho)(p - r_old)
+      const bool fresh = OP == VEC_INIT || st.status != 0;
       const T2 z = mk<T2>(0, 0);
+      T2 o[12];
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
-        const size_t o = base + 128 * k;
+        const size_t q = base + 128 * k;
         double2 b0 = make_double2(0, 0), b1 = b0;
-        if (valid) ld2(d.src64 + o, b0, b1);
+        if (valid) ld2(d.src64 + q, b0, b1);
         const T2 t0 = mk<T2>((T)b0.x, (T)b0.y), t1 = mk<T2>((T)b1.x, (T)b1.y);
-        st2(d.f[F_R] + o, t0, t1);
-        st2(d.f[F_X] + o, z, z);
-        T2 h0 = t0, h1 = t1;
         if (fresh) {
-          st2(d.f[F_RH] + o, t0, t1);
-          st2(d.f[F_P] + o, z, z);
-          st2(d.f[F_V] + o, z, z);
+          st2(d.f[F_P] + q, t0, t1);
         } else if (valid) {
-          ld2(d.f[F_RH] + o, h0, h1);
+          T2 p0, p1, r0, r1;
+          ld2(d.f[F_P] + q, p0, p1);
+          ld2(d.f[F_R] + q, r0, r1);
+          st2(d.f[F_P] + q, csub(p0, r0), csub(p1, r1));
         }
-        s0.x += (double)h0.x * t0.x + (double)h0.y * t0.y + (double)h1.x * t1.x + (double)h1.y * t1.y;
-        s0.y += (double)h0.x * t0.y - (double)h0.y * t0.x + (double)h1.x * t1.y - (double)h1.y * t1.x;
+        st2(d.f[F_R] + q, t0, t1);
+        st2(d.f[F_X] + q, z, z);
+        o[2 * k] = t0;
+        o[2 * k + 1] = t1;
         s1.x += (double)t0.x * t0.x + (double)t0.y * t0.y + (double)t1.x * t1.x + (double)t1.y * t1.y;
       }
-    } else {  // VEC_INIT: r = rh = (T) src64, x = p = v = 0 (padding sites: all zero)
-      const T2 z = mk<T2>(0, 0);
-#pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        const size_t o = base + 128 * k;
-        double2 b0 = make_double2(0, 0), b1 = b0;
-        if (valid) ld2(d.src64 + o, b0, b1);
-        const T2 t0 = mk<T2>((T)b0.x, (T)b0.y), t1 = mk<T2>((T)b1.x, (T)b1.y);
-        st2(d.f[F_R] + o, t0, t1);
-        st2(d.f[F_RH] + o, t0, t1);
-        st2(d.f[F_X] + o, z, z);
-        st2(d.f[F_P] + o, z, z);
-        st2(d.f[F_V] + o, z, z);
-        const double n2 = (double)t0.x * t0.x + (double)t0.y * t0.y + (double)t1.x * t1.x + (double)t1.y * t1.y;
-        s0.x += n2;
-        s1.x += n2;
-      }
+      shadow_dot(hb, o, s0);
     }
-    if (OP == VEC_XR || OP == VEC_INIT || OP == VEC_RELUP) {
-      s0 = wsum(s0);
-      s1 = wsum(s1);
+    if (OP != VEC_PFIX) {
+      if (OP != VEC_XRP) s0 = wsum(s0);
+      if (OP != VEC_S) s1 = wsum(s1);
       if (lane == 0) {
-        d.partial[(size_t)col * d.ntiles + tile] = s0;
-        d.partial[((size_t)d.nrhs + col) * d.ntiles + tile] = s1;
+        if (OP == VEC_S) *part_at(d.partial, d.nrhs, d.ntiles, 3, col, tile) = s0;
+        if (OP == VEC_INIT || OP == VEC_RELUP) *part_at(d.partial, d.nrhs, d.ntiles, 0, col, tile) = s0;
+        if (OP != VEC_S) *part_at(d.partial, d.nrhs, d.ntiles, 1, col, tile) = s1;
       }
     }
   }
@@ -176,6 +180,7 @@ __global__ void __launch_bounds__(768) k_vec16(const SlotDesc<h16c>* __restrict_
     const size_t base = fidx(nt, col, 0, i);
     const size_t sx = (size_t)col * nt * kTile + i;
     const BiState& st = d.st[col];
+    const unsigned hb = shadow_bits(col, i);
     auto ld = [&](int f, float2 v[12]) { spinor_load_q(d.f[f] + base, d.nrm[f][sx], v, true); };
     auto stq = [&](int f, const float2 v[12], float2 dq[12]) {
       spinor_store_q(d.f[f] + base, d.nrm[f] + sx, v, dq, true);
@@ -184,19 +189,7 @@ __global__ void __launch_bounds__(768) k_vec16(const SlotDesc<h16c>* __restrict_
     float2 z[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) z[c] = make_float2(0, 0);
-    if (OP == VEC_P) {
-      if (valid) {
-        const float2 be = make_float2((float)st.beta.x, (float)st.beta.y);
-        const float2 om = make_float2((float)st.omega.x, (float)st.omega.y);
-        float2 p[12], r[12], v[12], o[12], dq[12];
-        ld(F_P, p);
-        ld(F_R, r);
-        ld(F_V, v);
-#pragma unroll
-        for (int c = 0; c < 12; ++c) o[c] = cadd(r[c], cm32(be, csub(p[c], cm32(om, v[c]))));
-        stq(F_P, o, dq);
-      }
-    } else if (OP == VEC_S) {
+    if (OP == VEC_S) {
       const float2 al = make_float2((float)st.alpha.x, (float)st.alpha.y);
       float2 r[12], v[12], o[12], dq[12];
       if (valid) {
@@ -209,15 +202,17 @@ __global__ void __launch_bounds__(768) k_vec16(const SlotDesc<h16c>* __restrict_
         for (int c = 0; c < 12; ++c) o[c] = z[c];
       }
       stq(F_S, o, dq);
-    } else if (OP == VEC_XR) {
+      shadow_dot(hb, dq, s0);
+    } else if (OP == VEC_XRP) {
       if (valid) {
         const float2 al = make_float2((float)st.alpha.x, (float)st.alpha.y);
         const float2 om = make_float2((float)st.omega.x, (float)st.omega.y);
-        float2 p[12], sv[12], t[12], h[12], o[12], dq[12];
+        const float2 be = make_float2((float)st.beta.x, (float)st.beta.y);
+        float2 p[12], sv[12], t[12], v[12], o[12], dq[12], np[12], dp[12];
         ld(F_P, p);
         ld(F_S, sv);
         ld(F_T, t);
-        ld(F_RH, h);
+        ld(F_V, v);
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
           float2 x0, x1;
@@ -229,15 +224,26 @@ __global__ void __launch_bounds__(768) k_vec16(const SlotDesc<h16c>* __restrict_
 #pragma unroll
         for (int c = 0; c < 12; ++c) o[c] = csub(sv[c], cm32(om, t[c]));
         stq(F_R, o, dq);
+        // the new direction from the stored (quantised) residual
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-          s0.x += (double)h[c].x * dq[c].x + (double)h[c].y * dq[c].y;
-          s0.y += (double)h[c].x * dq[c].y - (double)h[c].y * dq[c].x;
-          s1.x += (double)dq[c].x * dq[c].x + (double)dq[c].y * dq[c].y;
-        }
+        for (int c = 0; c < 12; ++c) np[c] = cadd(dq[c], cm32(be, csub(p[c], cm32(om, v[c]))));
+        stq(F_P, np, dp);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) s1.x += (double)dq[c].x * dq[c].x + (double)dq[c].y * dq[c].y;
       }
-    } else {  // VEC_INIT / VEC_RELUP: r = (16-bit) src64, x = 0; a fresh column also gets rh = r, p = v = 0
-      float2 b[12], dq[12], h[12];
+    } else if (OP == VEC_PFIX) {
+      if (valid) {
+        const float2 be = make_float2((float)st.beta.x, (float)st.beta.y);
+        float2 p[12], r[12], o[12], dq[12];
+        ld(F_P, p);
+        ld(F_R, r);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) o[c] = cadd(r[c], cm32(be, p[c]));
+        stq(F_P, o, dq);
+      }
+    } else {  // VEC_INIT / VEC_RELUP: r = (16-bit) src64, x = 0; p as in k_vec
+      const bool fresh = OP == VEC_INIT || st.status != 0;
+      float2 b[12], dq[12];
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
         double2 b0 = make_double2(0, 0), b1 = b0;
@@ -246,32 +252,30 @@ __global__ void __launch_bounds__(768) k_vec16(const SlotDesc<h16c>* __restrict_
         b[2 * k + 1] = make_float2((float)b1.x, (float)b1.y);
         st2(d.x32 + base + 128 * k, z[2 * k], z[2 * k + 1]);
       }
+      if (!fresh && valid) {
+        float2 p[12], r[12], o[12], dp[12];
+        ld(F_P, p);
+        ld(F_R, r);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) o[c] = csub(p[c], r[c]);
+        stq(F_P, o, dp);
+      }
       stq(F_R, b, dq);
-      const bool fresh = OP == VEC_INIT || st.status != 0;
       if (fresh) {
-        float2 dz[12];
-        stq(F_RH, b, h);
-        stq(F_P, z, dz);
-        stq(F_V, z, dz);
-      } else if (valid) {
-        ld(F_RH, h);
-      } else {
-#pragma unroll
-        for (int c = 0; c < 12; ++c) h[c] = z[c];
+        float2 dp[12];
+        stq(F_P, dq, dp);
       }
+      shadow_dot(hb, dq, s0);
 #pragma unroll
-      for (int c = 0; c < 12; ++c) {
-        s0.x += (double)h[c].x * dq[c].x + (double)h[c].y * dq[c].y;
-        s0.y += (double)h[c].x * dq[c].y - (double)h[c].y * dq[c].x;
-        s1.x += (double)dq[c].x * dq[c].x + (double)dq[c].y * dq[c].y;
-      }
+      for (int c = 0; c < 12; ++c) s1.x += (double)dq[c].x * dq[c].x + (double)dq[c].y * dq[c].y;
     }
-    if (OP == VEC_XR || OP == VEC_INIT || OP == VEC_RELUP) {
-      s0 = wsum(s0);
-      s1 = wsum(s1);
+    if (OP != VEC_PFIX) {
+      if (OP != VEC_XRP) s0 = wsum(s0);
+      if (OP != VEC_S) s1 = wsum(s1);
       if (lane == 0) {
-        d.partial[(size_t)col * d.ntiles + tile] = s0;
-        d.partial[((size_t)d.nrhs + col) * d.ntiles + tile] = s1;
+        if (OP == VEC_S) *part_at(d.partial, d.nrhs, nt, 3, col, tile) = s0;
+        if (OP == VEC_INIT || OP == VEC_RELUP) *part_at(d.partial, d.nrhs, nt, 0, col, tile) = s0;
+        if (OP != VEC_S) *part_at(d.partial, d.nrhs, nt, 1, col, tile) = s1;
       }
     }
   }
@@ -285,6 +289,20 @@ __device__ __forceinline__ double2 cmuld(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 __device__ __forceinline__ bool finite2(double2 a) { return isfinite(a.x) && isfinite(a.y); }
+__device__ __forceinline__ bool zero2(double2 a) { return a.x == 0 && a.y == 0; }
+
+// Sum of partial slot k of a column over its tiles in a fixed order (lane
+// strides, then the wavefront tree).
+__device__ __forceinline__ double2 slot_sum(const double2* partial, int nrhs, int ntiles, int k, int col, int lane) {
+  double2 a = make_double2(0, 0);
+  const double2* p = partial + ((size_t)k * nrhs + col) * ntiles;
+  for (int t = lane; t < ntiles; t += 64) {
+    const double2 u = p[t];
+    a.x += u.x;
+    a.y += u.y;
+  }
+  return wsum(a);
+}
 
 // One workgroup per slot, one wavefront per column: sum the tile partials in a
 // fixed order, then update that column's BiCGstab scalars.
@@ -298,75 +316,80 @@ __global__ void __launch_bounds__(768) k_fin(const SlotDesc<T2>* __restrict__ sl
   if (col >= d.nrhs) return;
   BiState& st = d.st[col];
   if (OP != FIN_INIT && OP != FIN_RELUP && !d.active[col]) return;
-  double2 a = make_double2(0, 0), b = make_double2(0, 0);
-  const double2* p0 = d.partial + (size_t)col * d.ntiles;
-  const double2* p1 = d.partial + ((size_t)d.nrhs + col) * d.ntiles;
-  for (int t = lane; t < d.ntiles; t += 64) {
-    const double2 u = p0[t];
-    a.x += u.x; a.y += u.y;
-    if (OP != FIN_ALPHA) {
-      const double2 w = p1[t];
-      b.x += w.x; b.y += w.y;
-    }
-  }
-  a = wsum(a);
-  b = wsum(b);
+  const int nr = d.nrhs, nt = d.ntiles;
+  const double2 z = make_double2(0, 0);
+  const double2 a = (OP == FIN_CHECK) ? z : slot_sum(d.partial, nr, nt, 0, col, lane);
+  const double2 b = (OP == FIN_ALPHA) ? z : slot_sum(d.partial, nr, nt, 1, col, lane);
+  const double2 c2 = (OP == FIN_OMEGA) ? slot_sum(d.partial, nr, nt, 2, col, lane) : z;
+  const double2 c3 = (OP == FIN_OMEGA) ? slot_sum(d.partial, nr, nt, 3, col, lane) : z;
   if (lane != 0) return;
   if (OP == FIN_RELUP && st.status == 0) {
-    // a = (rh, r'), b = |r'|^2 for the replaced residual r'; keep the Krylov
-    // state and rescale: beta' = beta rho'/rho, rho' = (rh, r')
+    // a = (h, r'), b = |r'|^2 for the replaced residual r'; the Krylov space is
+    // kept: VEC_PFIX makes p = r' + (rho'/rho) (p - r_old)
     const int want = d.active[col];
-    if (finite2(a) && isfinite(b.x) && (st.rho.x != 0 || st.rho.y != 0)) {
-      st.beta = cmuld(st.beta, cdiv(a, st.rho));
+    if (finite2(a) && isfinite(b.x) && !zero2(st.rho)) {
+      st.beta = cdiv(a, st.rho);
+      st.rho = a;
+    } else {
+      st.beta = z;   // p = r' + 0: a fresh direction
       st.rho = a;
     }
     st.rr = b.x;
     st.rr0 = b.x;
     st.iters = 0;
-    const int on = want && b.x > 0 && isfinite(b.x);
+    const int on = want && b.x > 0 && isfinite(b.x) && !zero2(a);
     if (want && !isfinite(b.x)) st.status = 3;
     d.active[col] = on;
     st.active = on;
   } else if (OP == FIN_INIT || OP == FIN_RELUP) {
-    // a = (rh, r) = |r|^2, b = |r|^2 ; st.active holds the request flag
+    // a = (h, r), b = |r|^2 ; d.active holds the request flag; p = r already
     const int want = d.active[col];
     st.rr = b.x;
     st.rr0 = b.x;
-    st.rho = make_double2(b.x, 0);
+    st.rho = a;
     st.alpha = make_double2(1, 0);
     st.omega = make_double2(1, 0);
-    st.beta = st.rho;  // (rho/1)(1/1): p = r on the first iteration
+    st.beta = z;
     st.iters = 0;
     st.status = 0;
-    const int on = want && b.x > 0 && isfinite(b.x);
+    const int on = want && b.x > 0 && isfinite(b.x) && finite2(a) && !zero2(a);
     if (want && !isfinite(b.x)) st.status = 3;
     d.active[col] = on;
     st.active = on;
   } else if (OP == FIN_ALPHA) {
-    if (!finite2(a) || (a.x == 0 && a.y == 0)) {
+    // a = (h, v)
+    if (!finite2(a) || zero2(a)) {
       st.status = 1;
       st.active = 0;
       d.active[col] = 0;
-      st.alpha = make_double2(0, 0);
+      st.alpha = z;
       return;
     }
     st.alpha = cdiv(st.rho, a);
   } else if (OP == FIN_OMEGA) {
+    // a = (t, s), b.x = |t|^2, c2 = (h, t), c3 = (h, s); the residual after
+    // this iteration is r' = s - omega t, so rho' = (h, r') = c3 - omega c2
+    // and the next direction's beta is known before r' is formed
     if (b.x > 0 && isfinite(b.x) && finite2(a)) st.omega = make_double2(a.x / b.x, a.y / b.x);
-    else st.omega = make_double2(0, 0);
-  } else {  // FIN_RHO: a = (rh, r), b = |r|^2
+    else st.omega = z;
+    const double2 rho1 = make_double2(c3.x - (st.omega.x * c2.x - st.omega.y * c2.y),
+                                      c3.y - (st.omega.x * c2.y + st.omega.y * c2.x));
+    if (zero2(st.omega) || !finite2(rho1) || zero2(rho1) || zero2(st.rho)) {
+      st.beta = z;     // x and r are still updated; FIN_CHECK ends the column
+      st.status = 1;
+    } else {
+      st.beta = cmuld(cdiv(rho1, st.rho), cdiv(st.alpha, st.omega));
+    }
+    st.rho = rho1;
+  } else {  // FIN_CHECK: b = |r|^2
     st.iters += 1;
     st.rr = b.x;
     const bool conv = b.x <= st.tol2 * st.rr0;
     int on = 1;
-    if (!isfinite(b.x) || !finite2(a)) { st.status = 3; on = 0; }
+    if (!isfinite(b.x)) { st.status = 3; on = 0; }
     else if (conv) { st.status = 0; on = 0; }
+    else if (st.status == 1) { on = 0; }
     else if (st.iters >= st.max_iters) { st.status = 2; on = 0; }
-    else if ((a.x == 0 && a.y == 0) || (st.omega.x == 0 && st.omega.y == 0)) { st.status = 1; on = 0; }
-    if (on) {
-      st.beta = cmuld(cdiv(a, st.rho), cdiv(st.alpha, st.omega));
-      st.rho = a;
-    }
     st.active = on;
     d.active[col] = on;
   }
@@ -610,9 +633,9 @@ static hipError_t vec_impl(const SlotDesc<T2>* slots, const int* tile_start, con
                            int grid, hipStream_t st) {
   dim3 b(64 * nrhs);
   switch (op) {
-    case VEC_P: hipLaunchKernelGGL((k_vec<T2, VEC_P>), dim3(grid), b, 0, st, slots, tile_start, nslots_p); break;
     case VEC_S: hipLaunchKernelGGL((k_vec<T2, VEC_S>), dim3(grid), b, 0, st, slots, tile_start, nslots_p); break;
-    case VEC_XR: hipLaunchKernelGGL((k_vec<T2, VEC_XR>), dim3(grid), b, 0, st, slots, tile_start, nslots_p); break;
+    case VEC_XRP: hipLaunchKernelGGL((k_vec<T2, VEC_XRP>), dim3(grid), b, 0, st, slots, tile_start, nslots_p); break;
+    case VEC_PFIX: hipLaunchKernelGGL((k_vec<T2, VEC_PFIX>), dim3(grid), b, 0, st, slots, tile_start, nslots_p); break;
     case VEC_INIT: hipLaunchKernelGGL((k_vec<T2, VEC_INIT>), dim3(grid), b, 0, st, slots, tile_start, nslots_p); break;
     case VEC_RELUP: hipLaunchKernelGGL((k_vec<T2, VEC_RELUP>), dim3(grid), b, 0, st, slots, tile_start, nslots_p); break;
     default: return hipErrorInvalidValue;
@@ -631,9 +654,9 @@ hipError_t launch_vec(const SlotDesc<h16c>* slots, const int* tile_start, const 
                       int grid, hipStream_t st) {
   dim3 b(64 * nrhs);
   switch (op) {
-    case VEC_P: hipLaunchKernelGGL(k_vec16<VEC_P>, dim3(grid), b, 0, st, slots, tile_start, nslots_p); break;
     case VEC_S: hipLaunchKernelGGL(k_vec16<VEC_S>, dim3(grid), b, 0, st, slots, tile_start, nslots_p); break;
-    case VEC_XR: hipLaunchKernelGGL(k_vec16<VEC_XR>, dim3(grid), b, 0, st, slots, tile_start, nslots_p); break;
+    case VEC_XRP: hipLaunchKernelGGL(k_vec16<VEC_XRP>, dim3(grid), b, 0, st, slots, tile_start, nslots_p); break;
+    case VEC_PFIX: hipLaunchKernelGGL(k_vec16<VEC_PFIX>, dim3(grid), b, 0, st, slots, tile_start, nslots_p); break;
     case VEC_INIT: hipLaunchKernelGGL(k_vec16<VEC_INIT>, dim3(grid), b, 0, st, slots, tile_start, nslots_p); break;
     case VEC_RELUP: hipLaunchKernelGGL(k_vec16<VEC_RELUP>, dim3(grid), b, 0, st, slots, tile_start, nslots_p); break;
     default: return hipErrorInvalidValue;
@@ -648,7 +671,7 @@ static hipError_t fin_impl(const SlotDesc<T2>* slots, const int* nslots_p, int m
     case FIN_INIT: hipLaunchKernelGGL((k_fin<T2, FIN_INIT>), dim3(max_slots), b, 0, st, slots, nslots_p); break;
     case FIN_ALPHA: hipLaunchKernelGGL((k_fin<T2, FIN_ALPHA>), dim3(max_slots), b, 0, st, slots, nslots_p); break;
     case FIN_OMEGA: hipLaunchKernelGGL((k_fin<T2, FIN_OMEGA>), dim3(max_slots), b, 0, st, slots, nslots_p); break;
-    case FIN_RHO: hipLaunchKernelGGL((k_fin<T2, FIN_RHO>), dim3(max_slots), b, 0, st, slots, nslots_p); break;
+    case FIN_CHECK: hipLaunchKernelGGL((k_fin<T2, FIN_CHECK>), dim3(max_slots), b, 0, st, slots, nslots_p); break;
     case FIN_RELUP: hipLaunchKernelGGL((k_fin<T2, FIN_RELUP>), dim3(max_slots), b, 0, st, slots, nslots_p); break;
     default: return hipErrorInvalidValue;
   }

@@ -16,7 +16,9 @@
 // 1 KiB burst; the data of a tile sits in a few KiB instead of planes
 // megabytes apart (which alias in the L2 sets).
 //   spinor field of one parity : [nrhs][ntiles][6 pairs][64][2]  (component = spin*3 + colour)
-//   links                      : [2][ntiles][4 mu][5 pairs][64][2] (9 entries + 1 zero pad)
+//   links, FP64                : [2][ntiles][4 mu][5 pairs][64][2] (9 entries + 1 zero pad)
+//   links, FP32 and 16-bit     : [2][ntiles][4 mu][3 pairs][64][2] (the first two rows; the
+//                                stencil rebuilds the third, see stage_tile)
 //   clover A or A^{-1}         : [2][ntiles][18 pairs][64][2]   (two Hermitian 6x6 chiral blocks,
 //                                                              18 slots each: 3 packed diagonal
 //                                                              pairs, then the 15 upper elements)
@@ -98,6 +100,8 @@ struct BoxGeom {
   int Vh;       // sites per parity
   int half3;    // L[3]/2
   int ntiles;   // ceil(Vh / 64)
+  int twrap;    // 1 if the time links of the box's last slice carry the antiperiodic sign
+                // (the box spans the whole antiperiodic time extent), else 0
 };
 
 // tile-blocked, pair-packed offsets (in complex numbers)
@@ -109,6 +113,11 @@ __host__ __device__ __forceinline__ size_t fidx(int ntiles, int col, int c, int 
 }
 __host__ __device__ __forceinline__ size_t lidx(int ntiles, int par, int mu, int k, int i) {
   return ((size_t)(par * ntiles + (i >> 6)) * 20 + mu * 5 + (k >> 1)) * 128 + (i & 63) * 2 + (k & 1);
+}
+// the two-row link layout of the FP32 and 16-bit copies (entries k = 0..5)
+constexpr int kLinkSlots2 = 24;   // complex per site of the 4 links (two rows each)
+__host__ __device__ __forceinline__ size_t lidx2(int ntiles, int par, int mu, int k, int i) {
+  return ((size_t)(par * ntiles + (i >> 6)) * 12 + mu * 3 + (k >> 1)) * 128 + (i & 63) * 2 + (k & 1);
 }
 __host__ __device__ __forceinline__ size_t cidx(int ntiles, int par, int k, int i) {
   return ((size_t)(par * ntiles + (i >> 6)) * 18 + (k >> 1)) * 128 + (i & 63) * 2 + (k & 1);
@@ -287,12 +296,46 @@ template <typename T2> struct HopItem {
 //   MODE_PREP      out = C (aux + c1 acc)            (C = A^{-1}_pp: EO prepare/reconstruct)
 //   MODE_RES       out = red_a - (C aux - c1 acc)    (residual b - M x)
 enum { MODE_CINV_HOP = 0, MODE_SCHUR = 1, MODE_M = 2, MODE_PREP = 3, MODE_RES = 4 };
-// Fused reductions (FP64 partial sums per 64-site tile and column):
-//   RED_DOT  (red_a, out);  RED_TS  (out, aux) and |out|^2;  RED_NORM |out|^2
+// Fused reductions (FP64 partial sums per 64-site tile and column, written to
+// partial slot k at [k][nrhs][ntiles]):
+//   RED_DOT  slot 0: (h, out), h the shadow vector below
+//   RED_TS   slot 0: (out, aux), slot 1: |out|^2, slot 2: (h, out)
+//   RED_NORM slot 0: |out|^2
 enum { RED_NONE = 0, RED_DOT = 1, RED_TS = 2, RED_NORM = 3 };
 
-// Krylov vector slots of one inner solve (even parity unless noted)
-enum { F_R = 0, F_RH = 1, F_P = 2, F_V = 3, F_S = 4, F_T = 5, F_X = 6, F_TMP = 7 /* odd */, F_NUM = 8 };
+// Shadow residual h of the inner BiCGstab: a fixed vector whose entries are
+// (+-1 +- i), the signs taken from an integer hash of (column, site) (the
+// "lowbias32" finaliser of C. Wellons' hash-prospector), so it is computed
+// where a dot product needs it and never stored or read.  BiCGstab admits any
+// fixed shadow vector not orthogonal to the residual; a dense random one also
+// avoids the poor choice h = r0 for a point source (a vector with a single
+// non-zero site).  Bits 2c and 2c + 1 are the signs of Re and Im of component c.
+__host__ __device__ __forceinline__ unsigned shadow_bits(int col, int site) {
+  unsigned x = (unsigned)site * 0x9E3779B1u ^ ((unsigned)col * 0x85EBCA77u + 0x27D4EB2Fu);
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+// acc += conj(h_c) v_c for the 12 components of one site (exact sign flips)
+template <typename T2>
+__device__ __forceinline__ void shadow_dot(unsigned bits, const T2 v[12], double2& acc) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const double vr = v[c].x, vi = v[c].y;
+    const double sr = ((bits >> (2 * c)) & 1u) ? -1.0 : 1.0, si = ((bits >> (2 * c + 1)) & 1u) ? -1.0 : 1.0;
+    acc.x += sr * vr + si * vi;
+    acc.y += sr * vi - si * vr;
+  }
+}
+
+// Krylov vector slots of one inner solve (even parity unless noted); slot 1
+// is unused by BiCGstab (its shadow vector is hashed, see shadow_bits)
+enum { F_R = 0, F_UNUSED = 1, F_P = 2, F_V = 3, F_S = 4, F_T = 5, F_X = 6, F_TMP = 7 /* odd */, F_NUM = 8 };
+// Partial-sum slots of BiCGstab ([kBiPartials][nrhs][ntiles] per solve)
+constexpr int kBiPartials = 4;
 // GCR(m) (solver 2) keeps m search directions p_j and their images q_j = M p_j
 // in the field slots after the BiCGstab ones (F_R, F_X and F_TMP are shared).
 constexpr int kGcrMax = 8;

@@ -184,12 +184,32 @@ __device__ __forceinline__ void herm6_apply(const T2 m[18], const T2 x[6], T2 y[
 // 8 hops of every site ([hop = 2 mu + backward][5 pairs]) and the 18 clover
 // pairs, as [58 pairs][64 lanes][2] complex (the pair stride of the global
 // layout).  The workgroup reads them from HBM/L2 once instead of once per
-// wavefront (12 wavefronts share a tile at R = 1).
+// wavefront (12 wavefronts share a tile at R = 1).  FP64 links are read whole;
+// the FP32 and 16-bit copies hold the first two rows of each link (3 pairs)
+// and the third is rebuilt here, as conj(row 0 x row 1) for an SU(3) matrix,
+// times -1 for the time links of the last slice of a box that spans the
+// whole antiperiodic time extent (the sign folded into the stored rows
+// cancels in the cross product); a zeroed face link rebuilds to zero.  One
+// wavefront stages all of a link, so one barrier closes the staging.
 constexpr int kStageLinkPairs = 8 * 5;
 constexpr int kStagePairs = kStageLinkPairs + 18;
 
 template <typename E>
 constexpr bool kIs16 = std::is_same<E, h16c>::value;
+template <typename E>
+constexpr bool kTwoRow = !std::is_same<E, double2>::value;
+
+// one pair of a staged field (16-bit: dequantised with scale sc)
+template <typename E, typename C>
+__device__ __forceinline__ void stage_load(const E* src, float sc, C& a, C& b) {
+  if constexpr (kIs16<E>) {
+    ld2q_nt(src, a, b);
+    a = make_float2(a.x * sc, a.y * sc);
+    b = make_float2(b.x * sc, b.y * sc);
+  } else {
+    ld2nt(src, a, b);
+  }
+}
 
 // E: element type of the fields (float2, double2 or 16-bit h16c); C: compute type.
 template <typename E, typename C = typename CompOf<E>::type>
@@ -203,35 +223,53 @@ __device__ __forceinline__ void stage_tile(const BoxGeom& g, const E* __restrict
   const int q = 1 - p;
   int y[4] = {0, 0, 0, 0};
   if (valid) eo_coords(g, p, i, y);
-  for (int j = w; j < kStagePairs; j += W) {
-    C a = mk<C>(0, 0), b = mk<C>(0, 0);
-    const E* src = nullptr;
-    float sc = 1.0f / kQ;
-    if (j < kStageLinkPairs) {
-      const int h = j / 5, k = j - 5 * h, mu = h >> 1;
-      if (valid) {
-        if ((h & 1) == 0) {
-          src = U + lidx(nt, p, mu, 2 * k, i);
-        } else {
-          int z[4] = {y[0], y[1], y[2], y[3]};
-          z[mu] = (y[mu] == 0) ? g.L[mu] - 1 : y[mu] - 1;
-          src = U + lidx(nt, q, mu, 2 * k, eo_index(g, z));
-        }
+  const C z = mk<C>(0, 0);
+  // links: hop h = 2 mu + backward, forward from this site, backward from y - mu
+  for (int h = w; h < 8; h += W) {
+    const int mu = h >> 1;
+    const bool bwd = h & 1;
+    int par = p, site = i;
+    if (valid && bwd) {
+      int zz[4] = {y[0], y[1], y[2], y[3]};
+      zz[mu] = (y[mu] == 0) ? g.L[mu] - 1 : y[mu] - 1;
+      par = q;
+      site = eo_index(g, zz);
+    }
+    C e[10];
+    if constexpr (kTwoRow<E>) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        e[2 * k] = z;
+        e[2 * k + 1] = z;
+        if (valid) stage_load<E, C>(U + lidx2(nt, par, mu, 2 * k, site), 1.0f / kQ, e[2 * k], e[2 * k + 1]);
       }
+      // the time link of the box's last slice, if it carries the antiperiodic sign
+      const bool flip = g.twrap && mu == 0 && valid && (bwd ? y[0] == 0 : y[0] == g.L[0] - 1);
+#pragma unroll
+      for (int c3 = 0; c3 < 3; ++c3) {
+        const int a = (c3 + 1) % 3, b = (c3 + 2) % 3;
+        C v = csub(cmul(e[a], e[3 + b]), cmul(e[b], e[3 + a]));
+        e[6 + c3] = flip ? mk<C>(-v.x, v.y) : mk<C>(v.x, -v.y);
+      }
+      e[9] = z;
     } else {
-      src = clov + cidx(nt, p, 2 * (j - kStageLinkPairs), i);  // padding sites hold zeros
-      if constexpr (kIs16<E>) sc = clov_n[(size_t)p * nt * kTile + i] / kQ;
-    }
-    if (src) {
-      if constexpr (kIs16<E>) {
-        ld2q_nt(src, a, b);
-        a = make_float2(a.x * sc, a.y * sc);
-        b = make_float2(b.x * sc, b.y * sc);
-      } else {
-        ld2nt(src, a, b);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        e[2 * k] = z;
+        e[2 * k + 1] = z;
+        if (valid) ld2nt(U + lidx(nt, par, mu, 2 * k, site), e[2 * k], e[2 * k + 1]);
       }
     }
-    sts2(sm + j * 128 + lane * 2, a, b);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) sts2(sm + (h * 5 + k) * 128 + lane * 2, e[2 * k], e[2 * k + 1]);
+  }
+  // clover data of the output parity (padding sites hold zeros)
+  for (int j = w; j < 18; j += W) {
+    C a = z, b = z;
+    float sc = 1.0f / kQ;
+    if constexpr (kIs16<E>) sc = clov_n[(size_t)p * nt * kTile + i] / kQ;
+    stage_load<E, C>(clov + cidx(nt, p, 2 * j, i), sc, a, b);
+    sts2(sm + (kStageLinkPairs + j) * 128 + lane * 2, a, b);
   }
   __syncthreads();
 }
@@ -265,7 +303,7 @@ __device__ __forceinline__ void hop_sum(const BoxGeom& g, int p, int i, const E*
 #pragma unroll
         for (int k = 0; k < 5; ++k) lds2(ul + 128 * k, u[2 * k], u[2 * k + 1]);
       } else {
-        static_assert(!kIs16<E>, "16-bit fields are read through the LDS staging only");
+        static_assert(!kTwoRow<E>, "two-row links (FP32, 16-bit) are read through the LDS staging only");
         const E* __restrict__ ul = fwd ? U + lidx(nt, p, mu, 0, i) : U + lidx(nt, q, mu, 0, n);
 #pragma unroll
         for (int k = 0; k < 5; ++k) ld2nt(ul + 128 * k, u[2 * k], u[2 * k + 1]);
@@ -378,30 +416,25 @@ __device__ __forceinline__ void hop_tile(const BoxGeom g, const TileArgs<E>& a, 
     if (r >= nr) break;
     const int col = r0 + r;
     if (!((on >> r) & 1u)) continue;  // uniform across the wave
-    double2 s0 = make_double2(0, 0), s1 = make_double2(0, 0);
+    double2 s0 = make_double2(0, 0), s1 = make_double2(0, 0), s2 = make_double2(0, 0);
     const size_t base = fidx(nt, col, 0, i);
     const size_t ns = (size_t)col * nt * kTile + i;  // scale index of 16-bit fields
     if (valid) {
       C av[12], ra[12], o[12];
       if constexpr (kIs16<E>) {
         if (MODE != MODE_CINV_HOP) spinor_load_q(a.aux + base, a.aux_n[ns], av, true);
-        if (MODE == MODE_RES || RED == RED_DOT) spinor_load_q(a.red_a + base, a.red_n[ns], ra, true);
+        if (MODE == MODE_RES) spinor_load_q(a.red_a + base, a.red_n[ns], ra, true);
         C w[12];
         epilogue<C, MODE, ST>(cl, acc[r], av, ra, c1, c2, w);
         spinor_store_q(a.out + base, a.out_n + ns, w, o, true);
       } else {
         if (MODE != MODE_CINV_HOP) spinor_load_nt(a.aux + base, av);
-        if (MODE == MODE_RES || RED == RED_DOT) spinor_load_nt(a.red_a + base, ra);
+        if (MODE == MODE_RES) spinor_load_nt(a.red_a + base, ra);
         epilogue<C, MODE, ST>(cl, acc[r], av, ra, c1, c2, o);
         spinor_store_nt(a.out + base, o);
       }
       if (RED == RED_DOT) {
-#pragma unroll
-        for (int c = 0; c < 12; ++c) {
-          const double rx = ra[c].x, ry = ra[c].y, ox = o[c].x, oy = o[c].y;
-          s0.x = fmadd(rx, ox, fmadd(ry, oy, s0.x));
-          s0.y = fmadd(rx, oy, fmadd(-ry, ox, s0.y));
-        }
+        shadow_dot(shadow_bits(col, i), o, s0);
       } else if (RED == RED_TS) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
@@ -410,6 +443,7 @@ __device__ __forceinline__ void hop_tile(const BoxGeom g, const TileArgs<E>& a, 
           s0.y = fmadd(ox, ay, fmadd(-oy, ax, s0.y));
           s1.x = fmadd(ox, ox, fmadd(oy, oy, s1.x));
         }
+        shadow_dot(shadow_bits(col, i), o, s2);
       } else if (RED == RED_NORM) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
@@ -427,10 +461,16 @@ __device__ __forceinline__ void hop_tile(const BoxGeom g, const TileArgs<E>& a, 
     }
     if (RED != RED_NONE) {
       s0 = wave_sum(s0);
-      if (RED == RED_TS) s1 = wave_sum(s1);
+      if (RED == RED_TS) {
+        s1 = wave_sum(s1);
+        s2 = wave_sum(s2);
+      }
       if (lane == 0) {
         partial[(size_t)col * nt + tile] = s0;
-        if (RED == RED_TS) partial[((size_t)nrhs + col) * nt + tile] = s1;
+        if (RED == RED_TS) {
+          partial[((size_t)nrhs + col) * nt + tile] = s1;
+          partial[((size_t)2 * nrhs + col) * nt + tile] = s2;
+        }
       }
     }
   }
@@ -585,9 +625,6 @@ static hipError_t hop_item_impl(const HopItem<T2>& it, int mode, int red, int R,
 hipError_t launch_hop_item(const HopItem<double2>& it, int mode, int red, int R, int order, hipStream_t st) {
   return hop_item_impl(it, mode, red, R, order, st);
 }
-hipError_t launch_hop_item(const HopItem<float2>& it, int mode, int red, int R, int order, hipStream_t st) {
-  return hop_item_impl(it, mode, red, R, order, st);
-}
 
 #define DDML_HOPB_DISPATCH1(T2, Rv, MODEv, REDv, STv)                                                    \
   if (R == Rv && mode == MODEv && red == REDv) {                                                         \
@@ -621,11 +658,11 @@ static hipError_t hop_batch_impl(const SlotDesc<T2>* slots, const int* tile_star
   if (stage) {
     DDML_HOPB_DISPATCH_ST(T2, true)
   } else {
-    if constexpr (!kIs16<T2>) {
+    if constexpr (!kTwoRow<T2>) {
       DDML_HOPB_DISPATCH_ST(T2, false)
     }
   }
-  return hipErrorInvalidValue;  // unknown variant; 16-bit fields need stage = 1
+  return hipErrorInvalidValue;  // unknown variant; FP32 and 16-bit fields need stage = 1
 }
 
 hipError_t launch_hop_batch(const SlotDesc<float2>* slots, const int* tile_start, const int* xstart, int xstride,

@@ -139,7 +139,8 @@ void ctx_init(Ctx* c, const ddml_lattice* lat, int device, size_t budget) {
   }
   c->pool.reset(new DevPool(budget));
   c->flag = DBuf(c->pool.get(), sizeof(int));
-  c->tune16.stage = 1;  // 16-bit fields are always read through the LDS staging
+  c->tune16.stage = 1;  // FP32 and 16-bit fields (two-row links) are always read through the LDS staging
+  c->tune32.stage = 1;
   for (int m = 0; m < 4; ++m) {
     c->full.lo[m] = 0;
     c->full.hi[m] = lat->dims[m];
@@ -329,10 +330,11 @@ static void fill_spec(Ctx* c, const GaugeRec& g, const DomainRec& d, BlockSpec& 
   geo.Vh = bs.Lb[0] * bs.Lb[1] * bs.Lb[2] * bs.Lb[3] / 2;
   geo.half3 = bs.Lb[3] / 2;
   geo.ntiles = (geo.Vh + kTile - 1) / kTile;
+  geo.twrap = (bs.Lb[0] == bs.L[0] && bs.tbc == DDML_BC_ANTIPERIODIC) ? 1 : 0;
 }
 
 static size_t opblock_bytes(size_t nsites) {  // nsites = 2 * ntiles * 64
-  return DevPool::round(kLinkSlots * nsites * sizeof(double2)) + DevPool::round(kLinkSlots * nsites * sizeof(float2)) +
+  return DevPool::round(kLinkSlots * nsites * sizeof(double2)) + DevPool::round(kLinkSlots2 * nsites * sizeof(float2)) +
          2 * DevPool::round(kCloverSlots * nsites * sizeof(double2)) +
          DevPool::round(kCloverSlots * nsites * sizeof(float2)) + 2 * DevPool::round(sizeof(int) * nsites / 128);
 }
@@ -420,7 +422,7 @@ std::shared_ptr<OpBlock> opblock(Ctx* c, int gauge_id, int dom_id) {
   ob->bytes = opblock_bytes(ns);
   if (!c->pool->fits(ob->bytes)) evict_blocks(c);
   ob->U64 = DBuf(c->pool.get(), kLinkSlots * ns * sizeof(double2));
-  ob->U32 = DBuf(c->pool.get(), kLinkSlots * ns * sizeof(float2));
+  ob->U32 = DBuf(c->pool.get(), kLinkSlots2 * ns * sizeof(float2));
   ob->A64 = DBuf(c->pool.get(), kCloverSlots * ns * sizeof(double2));
   ob->Ainv64 = DBuf(c->pool.get(), kCloverSlots * ns * sizeof(double2));
   ob->Ainv32 = DBuf(c->pool.get(), kCloverSlots * ns * sizeof(float2));
@@ -439,13 +441,14 @@ std::shared_ptr<OpBlock> opblock(Ctx* c, int gauge_id, int dom_id) {
   gv.r_t0 = git->second.r_t0;
   gv.r_t1 = git->second.r_t1;
   DDML_HIP(hipMemsetAsync(c->flag.p, 0, sizeof(int), c->stream));
-  DDML_HIP(launch_build_links(gv, ob->bs, ob->U64.as<double2>(), ob->U32.as<float2>(), c->stream));
+  DDML_HIP(launch_build_links(gv, ob->bs, ob->U64.as<double2>(), ob->U32.as<float2>(), c->flag.as<int>(), c->stream));
   DDML_HIP(launch_build_clover(gv, ob->bs, ob->A64.as<double2>(), ob->Ainv64.as<double2>(), ob->Ainv32.as<float2>(),
                                c->flag.as<int>(), c->stream));
   int* hf = (int*)pinned_area(c, sizeof(int));
   DDML_HIP(hipMemcpyAsync(hf, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   DDML_HIP(hipStreamSynchronize(c->stream));
-  if (*hf) throw Error{DDML_ENUMERIC, "clover block not positive definite (cannot invert A)"};
+  if (*hf & 1) throw Error{DDML_ENUMERIC, "clover block not positive definite (cannot invert A)"};
+  ob->su3 = !(*hf & 2);
   c->blocks[key] = ob;
   return ob;
 }
@@ -454,10 +457,10 @@ std::shared_ptr<OpBlock> opblock(Ctx* c, int gauge_id, int dom_id) {
 static void ensure16(Ctx* c, OpBlock& ob) {
   if (ob.U16.p) return;
   const size_t ns = (size_t)2 * ob.ntiles * kTile;
-  ob.U16 = DBuf(c->pool.get(), kLinkSlots * ns * sizeof(h16c));
+  ob.U16 = DBuf(c->pool.get(), kLinkSlots2 * ns * sizeof(h16c));
   ob.Ainv16 = DBuf(c->pool.get(), kCloverSlots * ns * sizeof(h16c));
   ob.Ainv16n = DBuf(c->pool.get(), ns * sizeof(float));
-  DDML_HIP(launch_quant_links(ob.U64.as<double2>(), ob.U16.as<h16c>(), kLinkSlots * ns, c->stream));
+  DDML_HIP(launch_quant_links(ob.U32.as<float2>(), ob.U16.as<h16c>(), kLinkSlots2 * ns, c->stream));
   DDML_HIP(launch_quant_clover(ob.Ainv64.as<double2>(), ob.Ainv16.as<h16c>(), ob.Ainv16n.as<float>(), ob.ntiles,
                                c->stream));
   ob.bytes += ob.U16.bytes + ob.Ainv16.bytes + ob.Ainv16n.bytes;
@@ -502,8 +505,8 @@ size_t solve_footprint(Ctx* c, int gauge_id, int dom_id, int nrhs, const ddml_so
   const size_t ntiles = (Vh + kTile - 1) / kTile;
   const size_t n = (size_t)nrhs * 12 * ntiles * kTile;
   const size_t fx = prec == DDML_MIXED_FP16 ? n * sizeof(float2) : inner_field_bytes(prec, n, nrhs, ntiles);
-  const size_t nfield = m > 0 ? 2 + 2 * (size_t)m : F_NUM - 1;  // besides F_X
-  const size_t npart = m > 0 ? std::max(2, m) : 2;
+  const size_t nfield = m > 0 ? 2 + 2 * (size_t)m : F_NUM - 2;  // besides F_X (and BiCGstab's unused slot)
+  const size_t npart = m > 0 ? std::max(2, m) : kBiPartials;
   return 8 * DevPool::round(n * sizeof(double2)) + nfield * DevPool::round(inner_field_bytes(prec, n, nrhs, ntiles)) +
          DevPool::round(fx) + DevPool::round(npart * nrhs * ntiles * sizeof(double2)) +
          DevPool::round(2 * nrhs * ntiles * sizeof(double2)) + 6 * DevPool::round(64);
@@ -592,38 +595,46 @@ static void schur_apply(Ctx* c, const OpBlock& ob, const T2* U, const T2* Ainv, 
   DDML_HIP(launch_hop_item(it, MODE_SCHUR, RED_NONE, tn.R, tn.order, st));
 }
 
-// The Schur operator in 16-bit storage (input quantised, both half-stencils
-// through the batched kernels on a one-slot table, output read back to FP64).
-static void schur_apply16(Ctx* c, OpBlock& ob, const double2* xe, double2* oe, int nrhs, hipStream_t st) {
-  ensure16(c, ob);
-  const TuneChoice& tn = c->tune16;
+// The Schur operator in FP32 or 16-bit storage (input rounded or quantised,
+// both half-stencils through the batched kernels on a one-slot table, output
+// read back to FP64).
+template <typename T2>
+static void schur_apply_staged(Ctx* c, OpBlock& ob, const double2* xe, double2* oe, int nrhs, hipStream_t st) {
+  constexpr bool h16 = std::is_same<T2, h16c>::value;
+  const int prec = h16 ? DDML_MIXED_FP16 : DDML_MIXED_FP32;
+  if (h16) ensure16(c, ob);
+  const TuneChoice& tn = c->tune(prec);
   const size_t n = (size_t)nrhs * ob.field, nt = ob.ntiles;
-  const size_t fb = inner_field_bytes(DDML_MIXED_FP16, n, nrhs, nt);
+  const size_t fb = inner_field_bytes(prec, n, nrhs, nt);
   DevPool* P = c->pool.get();
   DBuf fx(P, fb), ft(P, fb), fo(P, fb);
   DBuf part(P, 2 * nrhs * nt * sizeof(double2)), act(P, kMaxRhs * sizeof(int));
-  DBuf tab(P, sizeof(SlotDesc<h16c>)), ts(P, 2 * sizeof(int)), ns(P, sizeof(int)), xs(P, kXcd * 2 * sizeof(int));
+  DBuf tab(P, sizeof(SlotDesc<T2>)), ts(P, 2 * sizeof(int)), ns(P, sizeof(int)), xs(P, kXcd * 2 * sizeof(int));
   auto scales = [&](DBuf& b) { return reinterpret_cast<float*>(b.as<h16c>() + n); };
-  DDML_HIP(launch_quant16(xe, fx.as<h16c>(), scales(fx), nrhs, (int)nt, st));
-  std::vector<int> ones(kMaxRhs, 1);
-  DDML_HIP(hipMemcpyAsync(act.p, ones.data(), kMaxRhs * sizeof(int), hipMemcpyHostToDevice, st));
-  SlotDesc<h16c> d{};
+  SlotDesc<T2> d{};
   d.g = ob.g;
   d.nrhs = nrhs;
   d.ntiles = ob.ntiles;
   d.tps = ob.tps;
   d.kappa = ob.bs.kappa;
-  d.U = ob.U16.as<h16c>();
-  d.Ainv = ob.Ainv16.as<h16c>();
-  d.Ainv_nrm = ob.Ainv16n.as<float>();
-  d.f[F_P] = fx.as<h16c>();
-  d.nrm[F_P] = scales(fx);
-  d.f[F_RH] = fx.as<h16c>();
-  d.nrm[F_RH] = scales(fx);
-  d.f[F_TMP] = ft.as<h16c>();
-  d.nrm[F_TMP] = scales(ft);
-  d.f[F_V] = fo.as<h16c>();
-  d.nrm[F_V] = scales(fo);
+  d.f[F_P] = fx.as<T2>();
+  d.f[F_TMP] = ft.as<T2>();
+  d.f[F_V] = fo.as<T2>();
+  if constexpr (h16) {
+    DDML_HIP(launch_quant16(xe, fx.as<h16c>(), scales(fx), nrhs, (int)nt, st));
+    d.U = ob.U16.as<h16c>();
+    d.Ainv = ob.Ainv16.as<h16c>();
+    d.Ainv_nrm = ob.Ainv16n.as<float>();
+    d.nrm[F_P] = scales(fx);
+    d.nrm[F_TMP] = scales(ft);
+    d.nrm[F_V] = scales(fo);
+  } else {
+    DDML_HIP(launch_cast_to_f(xe, fx.as<float2>(), n, st));
+    d.U = ob.U32.as<float2>();
+    d.Ainv = ob.Ainv32.as<float2>();
+  }
+  std::vector<int> ones(kMaxRhs, 1);
+  DDML_HIP(hipMemcpyAsync(act.p, ones.data(), kMaxRhs * sizeof(int), hipMemcpyHostToDevice, st));
   d.partial = part.as<double2>();
   d.active = act.as<int>();
   attach_walk(d, ob, tn.order);
@@ -638,12 +649,14 @@ static void schur_apply16(Ctx* c, OpBlock& ob, const double2* xe, double2* oe, i
   DDML_HIP(hipMemcpyAsync(xs.p, h_xs, sizeof(h_xs), hipMemcpyHostToDevice, st));
   const int grid = ((tn.grid + kXcd - 1) / kXcd) * kXcd;
   const int splits = std::min(tn.splits, (nrhs + tn.R - 1) / tn.R);
-  auto* tb = tab.as<SlotDesc<h16c>>();
+  auto* tb = tab.as<SlotDesc<T2>>();
   DDML_HIP(launch_hop_batch(tb, ts.as<int>(), xs.as<int>(), 2, ns.as<int>(), nrhs, tn.R, MODE_CINV_HOP, RED_NONE, F_P,
                             -1, F_TMP, -1, 1, grid, tn.order, splits, 1, st));
+  // (with the fused shadow dot, the variant every element type has; its partial sums are not used here)
   DDML_HIP(launch_hop_batch(tb, ts.as<int>(), xs.as<int>(), 2, ns.as<int>(), nrhs, tn.R, MODE_SCHUR, RED_DOT, F_TMP,
-                            F_P, F_V, F_RH, 0, grid, tn.order, splits, 1, st));
-  DDML_HIP(launch_dequant16(fo.as<h16c>(), scales(fo), oe, nrhs, (int)nt, st));
+                            F_P, F_V, -1, 0, grid, tn.order, splits, 1, st));
+  if constexpr (h16) DDML_HIP(launch_dequant16(fo.as<h16c>(), scales(fo), oe, nrhs, (int)nt, st));
+  else DDML_HIP(launch_cast_to_d(fo.as<float2>(), oe, n, st));
   DDML_HIP(hipStreamSynchronize(st));  // temporaries go back to the pool
 }
 
@@ -660,18 +673,11 @@ void apply_eo(Ctx* c, int gauge_id, int dom_id, const double* in, double* out, i
     DDML_HIP(hipMemsetAsync(out, 0, (size_t)nrhs * gauge_get(c, gauge_id).V * 12 * sizeof(double2), st));
     DDML_HIP(launch_scatter(oe.as<double2>(), ob->bs, 0, nrhs, 1.0, reinterpret_cast<double2*>(out), st));
     DDML_HIP(hipStreamSynchronize(st));
-  } else if (prec == DDML_MIXED_FP16) {
-    schur_apply16(c, *ob, xe.as<double2>(), oe.as<double2>(), nrhs, st);
-    DDML_HIP(hipMemsetAsync(out, 0, (size_t)nrhs * gauge_get(c, gauge_id).V * 12 * sizeof(double2), st));
-    DDML_HIP(launch_scatter(oe.as<double2>(), ob->bs, 0, nrhs, 1.0, reinterpret_cast<double2*>(out), st));
-    DDML_HIP(hipStreamSynchronize(st));
   } else {
-    DBuf xf(c->pool.get(), n * sizeof(float2)), tf(c->pool.get(), n * sizeof(float2)),
-        of(c->pool.get(), n * sizeof(float2));
-    DDML_HIP(launch_cast_to_f(xe.as<double2>(), xf.as<float2>(), n, st));
-    schur_apply<float2>(c, *ob, ob->U32.as<float2>(), ob->Ainv32.as<float2>(), xf.as<float2>(), tf.as<float2>(),
-                        of.as<float2>(), nrhs, st);
-    DDML_HIP(launch_cast_to_d(of.as<float2>(), oe.as<double2>(), n, st));
+    if (!ob->su3)
+      throw Error{DDML_EINVAL, "the FP32 and 16-bit operator copies keep two rows per link and need SU(3) links"};
+    if (prec == DDML_MIXED_FP16) schur_apply_staged<h16c>(c, *ob, xe.as<double2>(), oe.as<double2>(), nrhs, st);
+    else schur_apply_staged<float2>(c, *ob, xe.as<double2>(), oe.as<double2>(), nrhs, st);
     DDML_HIP(hipMemsetAsync(out, 0, (size_t)nrhs * gauge_get(c, gauge_id).V * 12 * sizeof(double2), st));
     DDML_HIP(launch_scatter(oe.as<double2>(), ob->bs, 0, nrhs, 1.0, reinterpret_cast<double2*>(out), st));
     DDML_HIP(hipStreamSynchronize(st));
@@ -748,11 +754,12 @@ void BatchRunner<T2>::capture() {
       chk(launch_gcr_fin(tb, ns, max_slots, GFIN_CHECK, k, s));
     }
   }
+  // BiCGstab iterations (the direction p of the next iteration is formed by
+  // VEC_XRP of this one, and by the (re)initialisation for the first)
   for (int k = 0; k < (gcr_m > 0 ? 0 : K); ++k) {
-    chk(launch_vec(tb, ts, ns, nrhs, VEC_P, grid, s));
     chk(launch_hop_batch(tb, ts, xs, xw, ns, nrhs, R, MODE_CINV_HOP, RED_NONE, F_P, -1, F_TMP, -1, 1, grid, order,
                          splits, stage, s));
-    chk(launch_hop_batch(tb, ts, xs, xw, ns, nrhs, R, MODE_SCHUR, RED_DOT, F_TMP, F_P, F_V, F_RH, 0, grid, order,
+    chk(launch_hop_batch(tb, ts, xs, xw, ns, nrhs, R, MODE_SCHUR, RED_DOT, F_TMP, F_P, F_V, -1, 0, grid, order,
                          splits, stage, s));
     chk(launch_fin(tb, ns, max_slots, FIN_ALPHA, s));
     chk(launch_vec(tb, ts, ns, nrhs, VEC_S, grid, s));
@@ -761,8 +768,8 @@ void BatchRunner<T2>::capture() {
     chk(launch_hop_batch(tb, ts, xs, xw, ns, nrhs, R, MODE_SCHUR, RED_TS, F_TMP, F_S, F_T, -1, 0, grid, order,
                          splits, stage, s));
     chk(launch_fin(tb, ns, max_slots, FIN_OMEGA, s));
-    chk(launch_vec(tb, ts, ns, nrhs, VEC_XR, grid, s));
-    chk(launch_fin(tb, ns, max_slots, FIN_RHO, s));
+    chk(launch_vec(tb, ts, ns, nrhs, VEC_XRP, grid, s));
+    chk(launch_fin(tb, ns, max_slots, FIN_CHECK, s));
   }
   hipError_t e = hipStreamEndCapture(s, &graph);
   if (e != hipSuccess) throw Error{DDML_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(e)};
@@ -839,7 +846,7 @@ SlotDesc<h16c> make_desc<h16c>(const Solve* s, BiState* st, int* act, int order)
   d.Ainv = ob.Ainv16.as<h16c>();
   d.Ainv_nrm = ob.Ainv16n.as<float>();
   for (int k = 0; k < F_NUM; ++k) {
-    if (k == F_X) continue;
+    if (k == F_X || k == F_UNUSED) continue;
     d.f[k] = s->f[k].as<h16c>();
     d.nrm[k] = reinterpret_cast<float*>(d.f[k] + n);
   }
@@ -975,6 +982,8 @@ BatchRunner<h16c>& runner<h16c>(Ctx* c, int nrhs, int m) {
 void solve_prepare(Ctx* c, Solve* s) {
   if (s->nrhs < 1 || s->nrhs > kMaxRhs) throw Error{DDML_EINVAL, "nrhs must be in 1..12"};
   s->ob = opblock(c, s->gauge_id, s->dom_id);
+  if (s->prec != DDML_FP64 && !s->ob->su3)
+    throw Error{DDML_EINVAL, "the FP32 and 16-bit operator copies keep two rows per link and need SU(3) links"};
   const size_t Vh = s->ob->g.Vh, n = (size_t)s->nrhs * s->ob->field;
   const size_t nt = s->ob->ntiles;
   DevPool* P = c->pool.get();
@@ -993,11 +1002,11 @@ void solve_prepare(Ctx* c, Solve* s) {
   for (int k = 0; k < F_ALL; ++k) {
     const bool used = m > 0 ? (k == F_R || k == F_X || k == F_TMP || (k >= F_GP0 && k < F_GP0 + m) ||
                                (k >= F_GQ0 && k < F_GQ0 + m))
-                            : k < F_NUM;
+                            : (k < F_NUM && k != F_UNUSED);
     if (used) s->f[k] = DBuf(P, (k == F_X && s->prec == DDML_MIXED_FP16) ? n * sizeof(float2) : fb);
   }
   if (s->prec == DDML_MIXED_FP16) ensure16(c, *s->ob);
-  s->partial = DBuf(P, (size_t)std::max(2, m) * s->nrhs * nt * sizeof(double2));
+  s->partial = DBuf(P, (size_t)(m > 0 ? std::max(2, m) : kBiPartials) * s->nrhs * nt * sizeof(double2));
   s->table1 = DBuf(P, std::max({sizeof(SlotDesc<double2>), sizeof(SlotDesc<float2>), sizeof(SlotDesc<h16c>)}));
   s->tstart1 = DBuf(P, 2 * sizeof(int));
   s->n1 = DBuf(P, sizeof(int));
@@ -1126,6 +1135,9 @@ static bool try_join(Ctx* c, Solve* s) {
     DDML_HIP(launch_vec(s->table1.as<SlotDesc<T2>>(), s->tstart1.as<int>(), s->n1.as<int>(), s->nrhs,
                         relup ? VEC_RELUP : VEC_INIT, grid, c->stream));
     DDML_HIP(launch_fin(s->table1.as<SlotDesc<T2>>(), s->n1.as<int>(), 1, relup ? FIN_RELUP : FIN_INIT, c->stream));
+    if (relup)
+      DDML_HIP(launch_vec(s->table1.as<SlotDesc<T2>>(), s->tstart1.as<int>(), s->n1.as<int>(), s->nrhs, VEC_PFIX,
+                          grid, c->stream));
   }
   s->state = 2;
   return true;
@@ -1254,16 +1266,14 @@ static void time_stencil_t(Ctx* c, const OpBlock& ob, const T2* U, const T2* Ain
   const int prec = h16 ? DDML_MIXED_FP16 : (sizeof(T2) == sizeof(double2) ? DDML_FP64 : DDML_MIXED_FP32);
   const size_t fb = inner_field_bytes(prec, n, nrhs, ob.ntiles), nn = (size_t)nrhs * ob.ntiles * kTile;
   DevPool* P = c->pool.get();
-  DBuf fP(P, fb), fT(P, fb), fV(P, fb), fR(P, fb);
+  DBuf fP(P, fb), fT(P, fb), fV(P, fb);
   DBuf part(P, 2 * nrhs * ob.ntiles * sizeof(double2)), act(P, kMaxRhs * sizeof(int));
   DBuf tab(P, sizeof(SlotDesc<T2>)), ts(P, 2 * sizeof(int)), ns(P, sizeof(int)), xs(P, kXcd * 2 * sizeof(int));
   auto scales = [&](DBuf& b) { return reinterpret_cast<float*>(b.as<h16c>() + n); };
   if constexpr (h16) {
     DDML_HIP(launch_fill16(fP.as<h16c>(), n, scales(fP), nn, 1.0, st));
-    DDML_HIP(launch_fill16(fR.as<h16c>(), n, scales(fR), nn, 0.5, st));
   } else {
     DDML_HIP(launch_fill(fP.as<T2>(), n, 1.0, st));
-    DDML_HIP(launch_fill(fR.as<T2>(), n, 0.5, st));
   }
   std::vector<int> ones(kMaxRhs, 1);
   DDML_HIP(hipMemcpyAsync(act.p, ones.data(), kMaxRhs * sizeof(int), hipMemcpyHostToDevice, st));
@@ -1278,12 +1288,10 @@ static void time_stencil_t(Ctx* c, const OpBlock& ob, const T2* U, const T2* Ain
   d.f[F_P] = fP.as<T2>();
   d.f[F_TMP] = fT.as<T2>();
   d.f[F_V] = fV.as<T2>();
-  d.f[F_RH] = fR.as<T2>();
   if constexpr (h16) {
     d.nrm[F_P] = scales(fP);
     d.nrm[F_TMP] = scales(fT);
     d.nrm[F_V] = scales(fV);
-    d.nrm[F_RH] = scales(fR);
     d.Ainv_nrm = ob.Ainv16n.as<float>();
   }
   d.partial = part.as<double2>();
@@ -1306,7 +1314,7 @@ static void time_stencil_t(Ctx* c, const OpBlock& ob, const T2* U, const T2* Ain
                                 F_P, -1, F_TMP, -1, 1, grid, order, splits, stage, st));
     else
       DDML_HIP(launch_hop_batch(tb, ts.as<int>(), xs.as<int>(), 2, ns.as<int>(), nrhs, R, MODE_SCHUR, RED_DOT, F_TMP,
-                                F_P, F_V, F_RH, 0, grid, order, splits, stage, st));
+                                F_P, F_V, -1, 0, grid, order, splits, stage, st));
   };
   for (int w = 0; w < 3; ++w) { launch(0); launch(1); }
   std::vector<hipEvent_t> ev(2 * iters + 1);
@@ -1330,15 +1338,17 @@ static void time_stencil_t(Ctx* c, const OpBlock& ob, const T2* U, const T2* Ain
   for (auto& e : ev) DDML_HIP(hipEventDestroy(e));
   const double s = h16 ? 2.0 : sizeof(T2) / 2;  // bytes per real
   // CINV_HOP: read the input spinor, all links of the box (4 per site), A^{-1} of
-  // the output parity; write the output.  SCHUR (+dot): read input, aux and the
-  // dot operand, links, A^{-1}; write the output.
+  // the output parity; write the output.  SCHUR (+ the hashed-shadow dot): read
+  // input and aux, links, A^{-1}; write the output.
   out[0] = t0 / iters;
   out[1] = t1 / iters;
   // 16-bit: plus one 4-byte scale per site and column of every spinor touched
-  // and per site of A^{-1}
+  // and per site of A^{-1}.  Links: 8 per output site, 12 reals each in the
+  // two-row FP32 and 16-bit copies, 18 in FP64.
   const double sc = h16 ? 4.0 : 0.0;
-  out[2] = (double)Vh * ((48.0 * nrhs + 144.0 + 72.0) * s + sc * (2 * nrhs + 1));
-  out[3] = (double)Vh * ((96.0 * nrhs + 144.0 + 72.0) * s + sc * (4 * nrhs + 1));
+  const double lr = std::is_same<T2, double2>::value ? 144.0 : 96.0;
+  out[2] = (double)Vh * ((48.0 * nrhs + lr + 72.0) * s + sc * (2 * nrhs + 1));
+  out[3] = (double)Vh * ((72.0 * nrhs + lr + 72.0) * s + sc * (3 * nrhs + 1));
 }
 
 void time_stencil(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, int iters, const TuneChoice& want,
@@ -1364,15 +1374,16 @@ void time_stencil(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, int iter
     time_stencil_t<h16c>(c, *ob, ob->U16.as<h16c>(), ob->Ainv16.as<h16c>(), nrhs, iters, R, order, grid, splits,
                          stage, out);
   } else {
+    if (stage != 1) throw Error{DDML_EINVAL, "FP32 fields need stage 1"};
     time_stencil_t<float2>(c, *ob, ob->U32.as<float2>(), ob->Ainv32.as<float2>(), nrhs, iters, R, order, grid,
                            splits, stage, out);
   }
 }
 
 void set_launch(Ctx* c, int prec, const TuneChoice& want) {
-  const bool h16 = prec == DDML_MIXED_FP16;
+  const bool staged = prec != DDML_FP64;   // two-row links are rebuilt in the LDS staging
   if (want.R < 1 || want.R > 3 || want.order < 0 || want.order >= TILE_ORDER_NUM || want.grid < kXcd ||
-      want.splits < 1 || want.splits > 12 || want.stage < 0 || want.stage > 1 || (h16 && want.stage != 1))
+      want.splits < 1 || want.splits > 12 || want.stage < 0 || want.stage > 1 || (staged && want.stage != 1))
     throw Error{DDML_EINVAL, "invalid launch choice"};
   TuneChoice& t = c->tune(prec);
   const int K = t.K;
@@ -1386,7 +1397,7 @@ void set_launch(Ctx* c, int prec, const TuneChoice& want) {
 void autotune(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, double best[6]) {
   double bt = 1e300;
   TuneChoice b = c->tune(prec);
-  for (int stage = prec == DDML_MIXED_FP16 ? 1 : 0; stage <= 1; ++stage)
+  for (int stage = prec == DDML_FP64 ? 0 : 1; stage <= 1; ++stage)
     for (int R = 1; R <= 3; ++R)
       for (int splits = 1; splits <= 3; ++splits) {
         if (splits > (nrhs + R - 1) / R) continue;

@@ -106,6 +106,7 @@ struct OpBlock {
   DBuf walk[2];            // tile walks of TILE_ORDER_SUB2 / TILE_ORDER_SUB4
   int xoff[2][kXcd + 1] = {};
   size_t bytes = 0;
+  bool su3 = true;         // links are SU(3) to 1e-5 (the FP32 and 16-bit copies keep two rows)
 };
 
 struct Ctx;

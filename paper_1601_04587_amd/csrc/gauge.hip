@@ -50,7 +50,13 @@ __host__ __device__ __forceinline__ int ntiles_of(const BlockSpec& bs) {
   return (Vh + kTile - 1) / kTile;
 }
 
-__global__ void k_build_links(GaugeView gv, BlockSpec bs, double2* __restrict__ U64, float2* __restrict__ U32) {
+// FP64 links in the 5-pair layout; the FP32 copy keeps the first two rows
+// (two-row layout, lidx2) and the stencil rebuilds the third as the complex
+// conjugate of the cross product of the first two, times the face factor
+// (+-1; 0 zeroes all rows).  That holds for SU(3) matrices only: a link whose
+// third row differs from the rebuilt one by more than 1e-5 sets bit 2 of *bad.
+__global__ void k_build_links(GaugeView gv, BlockSpec bs, double2* __restrict__ U64, float2* __restrict__ U32,
+                              int* __restrict__ bad) {
   const int Vb = bs.Lb[0] * bs.Lb[1] * bs.Lb[2] * bs.Lb[3];
   const int nt = ntiles_of(bs);
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < Vb; s += gridDim.x * blockDim.x) {
@@ -71,10 +77,20 @@ __global__ void k_build_links(GaugeView gv, BlockSpec bs, double2* __restrict__ 
 #pragma unroll
       for (int k = 0; k < 10; ++k) {  // entry 9 is the zero pad of the last pair
         const double2 v = k < 9 ? make_double2(f * u[k].x, f * u[k].y) : make_double2(0, 0);
-        const size_t o = lidx(nt, p, mu, k, i);
-        if (U64) U64[o] = v;
-        if (U32) U32[o] = make_float2((float)v.x, (float)v.y);
+        if (U64) U64[lidx(nt, p, mu, k, i)] = v;
+        if (U32 && k < 6) U32[lidx2(nt, p, mu, k, i)] = make_float2((float)v.x, (float)v.y);
       }
+      // third row against conj(row 0 x row 1)
+      double dev = 0;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const int a = (q + 1) % 3, b = (q + 2) % 3;
+        const double2 x1 = u[a], y1 = u[3 + b], x2 = u[b], y2 = u[3 + a];
+        const double cr = (x1.x * y1.x - x1.y * y1.y) - (x2.x * y2.x - x2.y * y2.y);
+        const double ci = (x1.x * y1.y + x1.y * y1.x) - (x2.x * y2.y + x2.y * y2.x);
+        dev = fmax(dev, fabs(u[6 + q].x - cr) + fabs(u[6 + q].y + ci));
+      }
+      if (!(dev <= 1e-5)) atomicOr(bad, 2);
     }
   }
 }
@@ -360,11 +376,12 @@ __global__ void __launch_bounds__(128) k_invert_clover(const double2* __restrict
   }
 }
 
-hipError_t launch_build_links(const GaugeView& gv, const BlockSpec& bs, double2* U64, float2* U32, hipStream_t st) {
+hipError_t launch_build_links(const GaugeView& gv, const BlockSpec& bs, double2* U64, float2* U32, int* bad,
+                              hipStream_t st) {
   const int Vb = bs.Lb[0] * bs.Lb[1] * bs.Lb[2] * bs.Lb[3];
   int grid = (Vb + 255) / 256;
   if (grid > 16384) grid = 16384;
-  hipLaunchKernelGGL(k_build_links, dim3(grid), dim3(256), 0, st, gv, bs, U64, U32);
+  hipLaunchKernelGGL(k_build_links, dim3(grid), dim3(256), 0, st, gv, bs, U64, U32, bad);
   return hipGetLastError();
 }
 hipError_t launch_build_clover(const GaugeView& gv, const BlockSpec& bs, double2* A64, double2* Ainv64,
@@ -746,10 +763,10 @@ hipError_t launch_level1_sweeps(const GaugeView& gv, double2* region, const Bloc
 
 // 16-bit copies for the FP16-storage inner solver: links with scale 1 (their
 // entries are bounded by 1 in magnitude), A^{-1} with one scale per site.
-__global__ void k_quant_links(const double2* __restrict__ U64, h16c* __restrict__ U16, size_t n) {
+__global__ void k_quant_links(const float2* __restrict__ U32, h16c* __restrict__ U16, size_t n) {
   for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
-    const double2 u = U64[k];
-    U16[k] = h16c{q16((float)u.x * kQ), q16((float)u.y * kQ)};
+    const float2 u = U32[k];
+    U16[k] = h16c{q16(u.x * kQ), q16(u.y * kQ)};
   }
 }
 __global__ void k_quant_clover(const double2* __restrict__ A, h16c* __restrict__ A16, float* __restrict__ nrm,
@@ -771,9 +788,9 @@ __global__ void k_quant_clover(const double2* __restrict__ A, h16c* __restrict__
     nrm[t] = mf;
   }
 }
-hipError_t launch_quant_links(const double2* U64, h16c* U16, size_t n, hipStream_t st) {
+hipError_t launch_quant_links(const float2* U32, h16c* U16, size_t n, hipStream_t st) {
   size_t g = (n + 255) / 256;
-  hipLaunchKernelGGL(k_quant_links, dim3((int)(g > 16384 ? 16384 : (g ? g : 1))), dim3(256), 0, st, U64, U16, n);
+  hipLaunchKernelGGL(k_quant_links, dim3((int)(g > 16384 ? 16384 : (g ? g : 1))), dim3(256), 0, st, U32, U16, n);
   return hipGetLastError();
 }
 hipError_t launch_quant_clover(const double2* Ainv64, h16c* Ainv16, float* nrm, int ntiles, hipStream_t st) {

@@ -6,7 +6,6 @@ namespace ddml {
 
 // dirac.hip
 hipError_t launch_hop_item(const HopItem<double2>& it, int mode, int red, int R, int order, hipStream_t st);
-hipError_t launch_hop_item(const HopItem<float2>& it, int mode, int red, int R, int order, hipStream_t st);
 // xstart: [kXcd][xstride] per-XCD prefix of tile counts (all orders but linear);
 // splits: the waves covering the columns of a tile are spread over this many
 // workgroups (1 = one workgroup per tile); stage: 1 = stage each tile's links
@@ -30,8 +29,18 @@ hipError_t launch_clover_apply(const BoxGeom& g, const double2* clov, int p, con
                                int nrhs, hipStream_t st);
 
 // blas.hip: inner BiCGstab steps over a slot table
-enum { VEC_P = 0, VEC_S = 1, VEC_XR = 2, VEC_INIT = 3, VEC_RELUP = 4 };
-enum { FIN_INIT = 0, FIN_ALPHA = 1, FIN_OMEGA = 2, FIN_RHO = 3, FIN_RELUP = 4 };
+// BiCGstab vector steps (k_vec) and scalar steps (k_fin), h the hashed shadow vector:
+//   VEC_S     s = r - alpha v;                                     slot 3: (h, s)
+//   VEC_XRP   x += alpha p + omega s; r = s - omega t;
+//             p = r + beta (p - omega v);                          slot 1: |r|^2
+//   VEC_INIT  r = p = b, x = 0;                                    slot 0: (h, r), slot 1: |r|^2
+//   VEC_RELUP r = b, x = 0; p = r (fresh column) or p - r_old;     slot 0: (h, r), slot 1: |r|^2
+//   VEC_PFIX  p = r + beta p
+//   FIN_ALPHA alpha = rho / (h, v)
+//   FIN_OMEGA omega = (t, s) / |t|^2; rho' = (h, s) - omega (h, t); beta = (rho'/rho)(alpha/omega)
+//   FIN_CHECK stopping test on |r|^2
+enum { VEC_S = 1, VEC_XRP = 2, VEC_INIT = 3, VEC_RELUP = 4, VEC_PFIX = 5 };
+enum { FIN_INIT = 0, FIN_ALPHA = 1, FIN_OMEGA = 2, FIN_CHECK = 3, FIN_RELUP = 4 };
 hipError_t launch_vec(const SlotDesc<float2>* slots, const int* tile_start, const int* nslots_p, int nrhs, int op,
                       int grid, hipStream_t st);
 hipError_t launch_vec(const SlotDesc<double2>* slots, const int* tile_start, const int* nslots_p, int nrhs, int op,
@@ -84,11 +93,14 @@ struct BlockSpec {
   int tbc;        // time boundary of the lattice: 0 periodic, 1 antiperiodic, 2 open
   double kappa, csw;
 };
-hipError_t launch_build_links(const GaugeView& gv, const BlockSpec& bs, double2* U64, float2* U32, hipStream_t st);
+// FP64 links (5-pair layout) and the two-row FP32 copy; bit 2 of *bad if a link is not SU(3)
+hipError_t launch_build_links(const GaugeView& gv, const BlockSpec& bs, double2* U64, float2* U32, int* bad,
+                              hipStream_t st);
 hipError_t launch_build_clover(const GaugeView& gv, const BlockSpec& bs, double2* A64, double2* Ainv64,
                                float2* Ainv32, int* bad, hipStream_t st);
-// 16-bit copies of an operator block's links and A^{-1} (n = 2 * ntiles * 64 sites)
-hipError_t launch_quant_links(const double2* U64, h16c* U16, size_t n, hipStream_t st);
+// 16-bit copies of an operator block's links (from the two-row FP32 copy, n complex
+// numbers) and A^{-1} (2 * ntiles * 64 sites)
+hipError_t launch_quant_links(const float2* U32, h16c* U16, size_t n, hipStream_t st);
 hipError_t launch_quant_clover(const double2* Ainv64, h16c* Ainv16, float* nrm, int ntiles, hipStream_t st);
 // canonical [nrhs][V][12] complex128 <-> domain EO field [nrhs][ntiles][12][64] of parity p, scaled
 hipError_t launch_gather(const double2* canon, const BlockSpec& bs, int p, int nrhs, double scale, double2* eo,

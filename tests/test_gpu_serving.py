@@ -152,7 +152,8 @@ def test_autotune_and_stencil_timing(setup):
     assert stage in (0, 1)
     ms_odd, ms_even, b_odd, b_even = ctx.time_stencil(gid, ids["G2"], 12, ddml.MIXED_FP32, 5)
     Vh = int(np.prod(L)) // 2
-    assert b_odd == Vh * (48 * 12 + 216) * 4 and b_even == Vh * (96 * 12 + 216) * 4
+    # two-row links in FP32: 8 links x 12 reals + 72 of A^-1 per output site
+    assert b_odd == Vh * (48 * 12 + 96 + 72) * 4 and b_even == Vh * (72 * 12 + 96 + 72) * 4
     assert ms_odd > 0 and ms_even > 0
     # a solve after retuning still matches the oracle
     lo, hi = doms["G0"]
@@ -186,7 +187,7 @@ def test_fp16_storage_solve_and_iterations(setup):
 
 def test_every_launch_variant_computes_the_same_bits():
     """The stencil launch (columns per thread, tile order, grid, column splits,
-    LDS staging) changes only the schedule: every site and column is computed
+    LDS staging, which FP32 and 16-bit need for their two-row links) changes only the schedule: every site and column is computed
     and reduced the same way, so solves agree bit for bit.  A 16^4 box gives
     planar tile walks (sub-banded orders); a 6^4 box has time slices that are
     not whole tiles (banded fallback walks, a padded last tile)."""
@@ -201,8 +202,8 @@ def test_every_launch_variant_computes_the_same_bits():
         dom2 = ctx.set_domain((2, 2, 2, 2), (8, 8, 8, 8))
         b2 = inputs.point_source(L, (4, 4, 4, 4))
         variants = {
-            ddml.MIXED_FP32: [(1, 1, 1024, 1, 0), (1, 3, 512, 1, 1), (1, 2, 1024, 2, 1), (2, 0, 512, 2, 0),
-                              (3, 1, 2048, 1, 1), (1, 0, 1024, 3, 0)],
+            ddml.MIXED_FP32: [(1, 1, 1024, 1, 1), (1, 3, 512, 1, 1), (1, 2, 1024, 2, 1), (2, 0, 512, 2, 1),
+                              (3, 1, 2048, 1, 1), (1, 0, 1024, 3, 1)],
             ddml.FP64: [(1, 1, 1024, 1, 0), (1, 3, 1024, 1, 1), (3, 2, 512, 2, 1)],
             ddml.MIXED_FP16: [(1, 1, 1024, 1, 1), (1, 3, 512, 2, 1), (2, 2, 1024, 1, 1)],
         }
@@ -222,6 +223,8 @@ def test_every_launch_variant_computes_the_same_bits():
                     assert all(np.array_equal(x, r) for x, r in zip(xs, ref)), (prec, v)
         with pytest.raises(ddml.DDMLError):
             ctx.set_launch(ddml.MIXED_FP16, 1, 1, 1024, 1, 0)      # 16-bit needs the LDS staging
+        with pytest.raises(ddml.DDMLError):
+            ctx.set_launch(ddml.MIXED_FP32, 1, 1, 1024, 1, 0)      # so does FP32 (two-row links)
         with pytest.raises(ddml.DDMLError):
             ctx.set_launch(ddml.MIXED_FP32, 1, 1, 1024, 1, 2)      # no such stage
     finally:
