@@ -470,7 +470,8 @@ int ddml_projected_pion(ddml_ctx ctx, int gauge_id, int bar_id, int star_id, con
  * library stream with HIP events, after 3 untimed warm-up pairs.  out[0],
  * out[1]: average milliseconds per launch of the odd half (out_o = A_oo^{-1}
  * H_oe in_e) and of the even half (out_e = in_e - kappa^2 A_ee^{-1} H_eo t_o
- * with the dot product (r0, out_e)); out[2], out[3]: algorithmic bytes of one
+ * with the dot product (h, out_e), h the solver's hashed shadow vector);
+ * out[2], out[3]: algorithmic bytes of one
  * launch of each (every array the kernel must touch, counted once).
  * prec: DDML_FP64, DDML_MIXED_FP32 or DDML_MIXED_FP16 (16-bit storage, stage 1
  * only; bytes then count 2 per real plus the scales).  R (columns per thread,
@@ -478,18 +479,21 @@ int ddml_projected_pion(ddml_ctx ctx, int gauge_id, int bar_id, int star_id, con
  * <= 0 (order, stage: < 0) take the context's current choice.  Tile orders: 0 linear;
  * 1 each of the 8 XCDs owns a band of every time slice and walks the slices in
  * turn; 2 and 3: each XCD owns an x1 range of the domain, split by x2 into 2
- * (order 2) or 4 (order 3) sub-bands, each walked slice by slice.  splits: the
+ * (order 2) or 4 (order 3) sub-bands, each walked slice by slice; 4: the
+ * sub-bands of order 3 walked in blocks of 4 slices, the slices of a block
+ * innermost.  splits: the
  * ceil(nrhs / R) wavefronts that cover the columns of a 64-site tile are spread
  * over this many workgroups (1 = one workgroup per tile; clamped to the number
  * of wavefronts).  stage: 1 = each workgroup first copies the links and
  * clover data of its tile to LDS, so they are read once per tile instead of
- * once per wavefront; 0 = every wavefront reads them itself.
+ * once per wavefront; 0 = every wavefront reads them itself (FP64 only: the
+ * FP32 and 16-bit copies keep two rows per link, rebuilt in the staging).
  * Errors: EINVAL, ENOMEM. */
 int ddml_time_stencil(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec, int iters, int R, int order,
                       int grid, int splits, int stage, double out[4]);
 
-/* Autotuner: times the stencil launch variants (stage 0/1, R in 1..3, splits
- * in 1..3, tile orders 0..3, grid in {512, 1024, 2048}) on (gauge_id, dom_id,
+/* Autotuner: times the stencil launch variants (stage 0/1 in FP64, 1 otherwise;
+ * R in 1..3, splits in 1..3, tile orders 0..4, grid in {512, 1024, 2048}) on (gauge_id, dom_id,
  * nrhs, prec) and makes the fastest the context's choice for every later solve
  * (the captured solver graphs are rebuilt).  best[0..5] = R, order, grid,
  * splits, stage, ms per odd+even pair.

@@ -291,38 +291,50 @@ __device__ __forceinline__ double2 cmuld(double2 a, double2 b) {
 __device__ __forceinline__ bool finite2(double2 a) { return isfinite(a.x) && isfinite(a.y); }
 __device__ __forceinline__ bool zero2(double2 a) { return a.x == 0 && a.y == 0; }
 
-// Sum of partial slot k of a column over its tiles in a fixed order (lane
-// strides, then the wavefront tree).
-__device__ __forceinline__ double2 slot_sum(const double2* partial, int nrhs, int ntiles, int k, int col, int lane) {
+// Sum of partial slot k of a column over its tiles in a fixed order: thread
+// t of the workgroup adds tiles t, t + 256, ... in turn, then a fixed tree in
+// LDS (the same for every batch the solve is in).  Every thread calls it.
+constexpr int kFinThreads = 256;
+__device__ __forceinline__ double2 slot_sum(const double2* partial, int nrhs, int ntiles, int k, int col,
+                                            double2* red) {
+  const int tid = threadIdx.x;
   double2 a = make_double2(0, 0);
   const double2* p = partial + ((size_t)k * nrhs + col) * ntiles;
-  for (int t = lane; t < ntiles; t += 64) {
+  for (int t = tid; t < ntiles; t += kFinThreads) {
     const double2 u = p[t];
     a.x += u.x;
     a.y += u.y;
   }
-  return wsum(a);
+  red[tid] = a;
+  __syncthreads();
+  for (int off = kFinThreads / 2; off > 0; off >>= 1) {
+    if (tid < off) red[tid] = make_double2(red[tid].x + red[tid + off].x, red[tid].y + red[tid + off].y);
+    __syncthreads();
+  }
+  const double2 r = red[0];
+  __syncthreads();
+  return r;
 }
 
-// One workgroup per slot, one wavefront per column: sum the tile partials in a
-// fixed order, then update that column's BiCGstab scalars.
+// One workgroup per (slot, column): sum the tile partials in a fixed order,
+// then update that column's BiCGstab scalars.
 template <typename T2, int OP>
-__global__ void __launch_bounds__(768) k_fin(const SlotDesc<T2>* __restrict__ slots, const int* __restrict__ nslots_p) {
-  const int s = blockIdx.x;
+__global__ void __launch_bounds__(kFinThreads) k_fin(const SlotDesc<T2>* __restrict__ slots,
+                                                     const int* __restrict__ nslots_p) {
+  __shared__ double2 red[kFinThreads];
+  const int s = blockIdx.x, col = blockIdx.y;
   if (s >= *nslots_p) return;
   const SlotDesc<T2>& d = slots[s];
-  const int lane = threadIdx.x & 63;
-  const int col = threadIdx.x >> 6;
   if (col >= d.nrhs) return;
   BiState& st = d.st[col];
-  if (OP != FIN_INIT && OP != FIN_RELUP && !d.active[col]) return;
+  if (OP != FIN_INIT && OP != FIN_RELUP && !d.active[col]) return;   // uniform over the workgroup
   const int nr = d.nrhs, nt = d.ntiles;
   const double2 z = make_double2(0, 0);
-  const double2 a = (OP == FIN_CHECK) ? z : slot_sum(d.partial, nr, nt, 0, col, lane);
-  const double2 b = (OP == FIN_ALPHA) ? z : slot_sum(d.partial, nr, nt, 1, col, lane);
-  const double2 c2 = (OP == FIN_OMEGA) ? slot_sum(d.partial, nr, nt, 2, col, lane) : z;
-  const double2 c3 = (OP == FIN_OMEGA) ? slot_sum(d.partial, nr, nt, 3, col, lane) : z;
-  if (lane != 0) return;
+  const double2 a = (OP == FIN_CHECK) ? z : slot_sum(d.partial, nr, nt, 0, col, red);
+  const double2 b = (OP == FIN_ALPHA) ? z : slot_sum(d.partial, nr, nt, 1, col, red);
+  const double2 c2 = (OP == FIN_OMEGA) ? slot_sum(d.partial, nr, nt, 2, col, red) : z;
+  const double2 c3 = (OP == FIN_OMEGA) ? slot_sum(d.partial, nr, nt, 3, col, red) : z;
+  if (threadIdx.x != 0) return;
   if (OP == FIN_RELUP && st.status == 0) {
     // a = (h, r'), b = |r'|^2 for the replaced residual r'; the Krylov space is
     // kept: VEC_PFIX makes p = r' + (rho'/rho) (p - r_old)
@@ -666,13 +678,13 @@ hipError_t launch_vec(const SlotDesc<h16c>* slots, const int* tile_start, const 
 
 template <typename T2>
 static hipError_t fin_impl(const SlotDesc<T2>* slots, const int* nslots_p, int max_slots, int op, hipStream_t st) {
-  dim3 b(64 * kMaxRhs);
+  const dim3 b(kFinThreads), grid(max_slots, kMaxRhs);
   switch (op) {
-    case FIN_INIT: hipLaunchKernelGGL((k_fin<T2, FIN_INIT>), dim3(max_slots), b, 0, st, slots, nslots_p); break;
-    case FIN_ALPHA: hipLaunchKernelGGL((k_fin<T2, FIN_ALPHA>), dim3(max_slots), b, 0, st, slots, nslots_p); break;
-    case FIN_OMEGA: hipLaunchKernelGGL((k_fin<T2, FIN_OMEGA>), dim3(max_slots), b, 0, st, slots, nslots_p); break;
-    case FIN_CHECK: hipLaunchKernelGGL((k_fin<T2, FIN_CHECK>), dim3(max_slots), b, 0, st, slots, nslots_p); break;
-    case FIN_RELUP: hipLaunchKernelGGL((k_fin<T2, FIN_RELUP>), dim3(max_slots), b, 0, st, slots, nslots_p); break;
+    case FIN_INIT: hipLaunchKernelGGL((k_fin<T2, FIN_INIT>), grid, b, 0, st, slots, nslots_p); break;
+    case FIN_ALPHA: hipLaunchKernelGGL((k_fin<T2, FIN_ALPHA>), grid, b, 0, st, slots, nslots_p); break;
+    case FIN_OMEGA: hipLaunchKernelGGL((k_fin<T2, FIN_OMEGA>), grid, b, 0, st, slots, nslots_p); break;
+    case FIN_CHECK: hipLaunchKernelGGL((k_fin<T2, FIN_CHECK>), grid, b, 0, st, slots, nslots_p); break;
+    case FIN_RELUP: hipLaunchKernelGGL((k_fin<T2, FIN_RELUP>), grid, b, 0, st, slots, nslots_p); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -260,12 +260,17 @@ __device__ __forceinline__ int eo_index(const BoxGeom& g, const int y[4]) {
 //                      slices in order;
 //   TILE_ORDER_SUB2/4  the XCD owns an x1 range of the box, split by the x2
 //                      position of the tiles into 2 or 4 sub-bands, and walks
-//                      each sub-band slice by slice (walk table of the box).
+//                      each sub-band slice by slice (walk table of the box);
+//   TILE_ORDER_SUB4T   the sub-bands of SUB4 walked in blocks of 4 slices,
+//                      the slices of a block innermost, so a tile's time
+//                      neighbours are its neighbours in the walk.
 // Either way the neighbours of a tile (same slice, adjacent slices) are read
 // through the same L2 shortly after they were first fetched; the sub-bands
 // shorten the distance to the next time slice so it stays in the L2.
 constexpr int kXcd = 8;
-enum { TILE_ORDER_LINEAR = 0, TILE_ORDER_BANDED = 1, TILE_ORDER_SUB2 = 2, TILE_ORDER_SUB4 = 3, TILE_ORDER_NUM = 4 };
+enum { TILE_ORDER_LINEAR = 0, TILE_ORDER_BANDED = 1, TILE_ORDER_SUB2 = 2, TILE_ORDER_SUB4 = 3, TILE_ORDER_SUB4T = 4,
+       TILE_ORDER_NUM = 5 };
+constexpr int kWalks = TILE_ORDER_NUM - TILE_ORDER_SUB2;   // orders with a walk table
 
 // ---------------------------------------------------------- kernel argument
 // Work item of the batched launches: one domain solve (or one operator
@@ -319,16 +324,22 @@ __host__ __device__ __forceinline__ unsigned shadow_bits(int col, int site) {
   x ^= x >> 16;
   return x;
 }
-// acc += conj(h_c) v_c for the 12 components of one site (exact sign flips)
-template <typename T2>
-__device__ __forceinline__ void shadow_dot(unsigned bits, const T2 v[12], double2& acc) {
+// acc += conj(h_c) v_c for the components c0 .. c0 + N - 1 of one site, v
+// holding those N components (exact sign flips)
+template <typename T2, int N>
+__device__ __forceinline__ void shadow_dot_part(unsigned bits, int c0, const T2 v[N], double2& acc) {
 #pragma unroll
-  for (int c = 0; c < 12; ++c) {
-    const double vr = v[c].x, vi = v[c].y;
+  for (int k = 0; k < N; ++k) {
+    const int c = c0 + k;
+    const double vr = v[k].x, vi = v[k].y;
     const double sr = ((bits >> (2 * c)) & 1u) ? -1.0 : 1.0, si = ((bits >> (2 * c + 1)) & 1u) ? -1.0 : 1.0;
     acc.x += sr * vr + si * vi;
     acc.y += sr * vi - si * vr;
   }
+}
+template <typename T2>
+__device__ __forceinline__ void shadow_dot(unsigned bits, const T2 v[12], double2& acc) {
+  shadow_dot_part<T2, 12>(bits, 0, v, acc);
 }
 
 // Krylov vector slots of one inner solve (even parity unless noted); slot 1

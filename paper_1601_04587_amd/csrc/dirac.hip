@@ -103,6 +103,14 @@ __device__ __forceinline__ void su3_mul(const T2 u[9], bool dag, const T2 h[6], 
     }
 }
 
+// g = W h per spin of the half spinor, W a link staged in LDS as 5 pairs of
+// its 9 row-major entries (pair k at ul + 128 k): each row is read when it is
+// needed, so at most a row and a half of W is live.  Every g is the same
+// sequence of fused multiply-adds as su3_mul (with W = U^dag for a backward
+// hop, conj(u) * h in cmacc is the product w * h in cmac).
+template <typename T2>
+__device__ __forceinline__ void su3_rows(const T2* ul, const T2 h[6], T2 g[6]);
+
 // Loads of one pair from the LDS staging area of a tile (same pair stride as
 // the global layout: pair k of lane l at base + 128 k, base = area + 2 l).
 __device__ __forceinline__ void lds2(const float2* p, float2& a, float2& b) {
@@ -127,6 +135,30 @@ __device__ __forceinline__ void sts2(double2* p, double2 a, double2 b) {
   u.x = a.x; u.y = a.y; v.x = b.x; v.y = b.y;
   q[0] = u;
   q[1] = v;
+}
+
+template <typename T2>
+__device__ __forceinline__ void su3_row(const T2 w0, const T2 w1, const T2 w2, const T2 h[6], int a, T2 g[6]) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    T2 acc = mk<T2>(0, 0);
+    acc = cmac(acc, w0, h[3 * s]);
+    acc = cmac(acc, w1, h[3 * s + 1]);
+    acc = cmac(acc, w2, h[3 * s + 2]);
+    g[3 * s + a] = acc;
+  }
+}
+template <typename T2>
+__device__ __forceinline__ void su3_rows(const T2* ul, const T2 h[6], T2 g[6]) {
+  T2 w0, w1, w2, w3, w4, w5, w6, w7, w8, wp;
+  lds2(ul, w0, w1);
+  lds2(ul + 128, w2, w3);
+  su3_row(w0, w1, w2, h, 0, g);
+  lds2(ul + 256, w4, w5);
+  su3_row(w3, w4, w5, h, 1, g);
+  lds2(ul + 384, w6, w7);
+  lds2(ul + 512, w8, wp);
+  su3_row(w6, w7, w8, h, 2, g);
 }
 
 // 18 slots of one Hermitian 6x6 block (9 pairs, pair k at base + 128 k)
@@ -179,6 +211,42 @@ __device__ __forceinline__ void herm6_apply(const T2 m[18], const T2 x[6], T2 y[
     }
 }
 
+// y = M x for one Hermitian 6x6 block staged in LDS (18 slots in 9 pairs:
+// the diagonal packed in slots 0..2, then the 15 upper entries, row by row),
+// reading each pair when it is needed: the same operations in the same order
+// as herm6_apply on the whole block.
+template <typename T2>
+__device__ __forceinline__ void herm6_apply_lds(const T2* base, const T2 x[6], T2 y[6]) {
+  T2 m0, m1;
+  lds2(base, m0, m1);
+  y[0] = cscale(x[0], m0.x);
+  y[1] = cscale(x[1], m0.y);
+  y[2] = cscale(x[2], m1.x);
+  y[3] = cscale(x[3], m1.y);
+  lds2(base + 128, m0, m1);
+  y[4] = cscale(x[4], m0.x);
+  y[5] = cscale(x[5], m0.y);
+  // slot k (k >= 3) holds entry (i, j) of the upper triangle, row by row
+  T2 h = m1;   // slot 3
+  int k = 3;
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = i + 1; j < 6; ++j) {
+      if (k > 3) {
+        if (k & 1) {
+          h = m1;
+        } else {
+          lds2(base + 128 * (k >> 1), m0, m1);
+          h = m0;
+        }
+      }
+      y[i] = cmac(y[i], h, x[j]);
+      y[j] = cmacc(y[j], h, x[i]);
+      ++k;
+    }
+}
+
 // ------------------------------------------------------------ the stencil core
 // LDS staging of the operator data of one tile (ST = true): the links of the
 // 8 hops of every site ([hop = 2 mu + backward][5 pairs]) and the 18 clover
@@ -190,7 +258,9 @@ __device__ __forceinline__ void herm6_apply(const T2 m[18], const T2 x[6], T2 y[
 // times -1 for the time links of the last slice of a box that spans the
 // whole antiperiodic time extent (the sign folded into the stored rows
 // cancels in the cross product); a zeroed face link rebuilds to zero.  One
-// wavefront stages all of a link, so one barrier closes the staging.
+// wavefront stages all of a link, so one barrier closes the staging.  A
+// backward hop's link is staged as U^dag (conjugated transpose), so every hop
+// multiplies by the rows of its staged matrix (su3_rows).
 constexpr int kStageLinkPairs = 8 * 5;
 constexpr int kStagePairs = kStageLinkPairs + 18;
 
@@ -260,6 +330,15 @@ __device__ __forceinline__ void stage_tile(const BoxGeom& g, const E* __restrict
         if (valid) ld2nt(U + lidx(nt, par, mu, 2 * k, site), e[2 * k], e[2 * k + 1]);
       }
     }
+    if (bwd) {   // the hop multiplies by U^dag: stage it as such (rows of U^dag = conj columns of U)
+      C t[9];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) t[3 * a + b] = mk<C>(e[3 * b + a].x, -e[3 * b + a].y);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) e[k] = t[k];
+    }
 #pragma unroll
     for (int k = 0; k < 5; ++k) sts2(sm + (h * 5 + k) * 128 + lane * 2, e[2 * k], e[2 * k + 1]);
   }
@@ -298,15 +377,14 @@ __device__ __forceinline__ void hop_sum(const BoxGeom& g, int p, int i, const E*
       else z[mu] = (y[mu] == 0) ? g.L[mu] - 1 : y[mu] - 1;
       const int n = eo_index(g, z);
       C u[10];
+      const C* ul = nullptr;
       if constexpr (ST) {
-        const C* ul = sm + (2 * mu + dir) * 5 * 128 + (i & 63) * 2;
-#pragma unroll
-        for (int k = 0; k < 5; ++k) lds2(ul + 128 * k, u[2 * k], u[2 * k + 1]);
+        ul = sm + (2 * mu + dir) * 5 * 128 + (i & 63) * 2;
       } else {
         static_assert(!kTwoRow<E>, "two-row links (FP32, 16-bit) are read through the LDS staging only");
-        const E* __restrict__ ul = fwd ? U + lidx(nt, p, mu, 0, i) : U + lidx(nt, q, mu, 0, n);
+        const E* __restrict__ ug = fwd ? U + lidx(nt, p, mu, 0, i) : U + lidx(nt, q, mu, 0, n);
 #pragma unroll
-        for (int k = 0; k < 5; ++k) ld2nt(ul + 128 * k, u[2 * k], u[2 * k + 1]);
+        for (int k = 0; k < 5; ++k) ld2nt(ug + 128 * k, u[2 * k], u[2 * k + 1]);
       }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -317,7 +395,8 @@ __device__ __forceinline__ void hop_sum(const BoxGeom& g, int p, int i, const E*
           else
             spinor_load(in + fidx(nt, r0 + r, 0, n), psi);
           project(mu, fwd, psi, h);
-          su3_mul(u, !fwd, h, gg);
+          if constexpr (ST) su3_rows(ul, h, gg);
+          else su3_mul(u, !fwd, h, gg);
           reconstruct(mu, fwd, gg, acc[r]);
         }
       }
@@ -336,35 +415,71 @@ __device__ __forceinline__ double2 wave_sum(double2 v) {
 
 // Epilogue on one column.  acc = (H in)(x); cl points at slot 0 of this site.
 template <typename T2, int MODE, bool ST>
-__device__ __forceinline__ void epilogue(const T2* cl, const T2 acc[12], const T2 aux[12],
-                                         const T2 ra[12], double c1, double c2, T2 out[12]) {
+__device__ __forceinline__ void epilogue_block(const T2* cl, int b, const T2 acc[6], const T2 aux[6], const T2 ra[6],
+                                               double c1, double c2, T2 out[6]) {
   using T = decltype(T2::x);
   const T k1 = (T)c1, k2 = (T)c2;
+  T2 m[18];
+  const T2* cb = cl + 128 * 9 * b;
+  if (!ST) herm6_load(cb, m);
+  auto apply = [&](const T2 x[6], T2 y[6]) {
+    if (ST) herm6_apply_lds(cb, x, y);
+    else herm6_apply(m, x, y);
+  };
+  if (MODE == MODE_CINV_HOP) {
+    apply(acc, out);
+  } else if (MODE == MODE_SCHUR) {
+    T2 y[6];
+    apply(acc, y);
 #pragma unroll
-  for (int b = 0; b < 2; ++b) {
-    T2 m[18];
-    if (ST) herm6_load_lds(cl + 128 * 9 * b, m);
-    else herm6_load(cl + 128 * 9 * b, m);
-    if (MODE == MODE_CINV_HOP) {
-      herm6_apply(m, acc + 6 * b, out + 6 * b);
-    } else if (MODE == MODE_SCHUR) {
-      T2 y[6];
-      herm6_apply(m, acc + 6 * b, y);
+    for (int c = 0; c < 6; ++c) out[c] = cmas(aux[c], y[c], -k1);
+  } else if (MODE == MODE_M || MODE == MODE_RES) {
+    T2 y[6];
+    apply(aux, y);
 #pragma unroll
-      for (int c = 0; c < 6; ++c) out[6 * b + c] = cmas(aux[6 * b + c], y[c], -k1);
-    } else if (MODE == MODE_M || MODE == MODE_RES) {
-      T2 y[6];
-      herm6_apply(m, aux + 6 * b, y);
+    for (int c = 0; c < 6; ++c) {
+      T2 v = cmas(y[c], acc[c], -k1);
+      out[c] = (MODE == MODE_M) ? cscale(v, k2) : csub(ra[c], v);
+    }
+  } else {  // MODE_PREP: out = C (aux + c1 acc)
+    T2 v[6];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        T2 v = cmas(y[c], acc[6 * b + c], -k1);
-        out[6 * b + c] = (MODE == MODE_M) ? cscale(v, k2) : csub(ra[6 * b + c], v);
-      }
-    } else {  // MODE_PREP: out = C (aux + c1 acc)
-      T2 v[6];
+    for (int c = 0; c < 6; ++c) v[c] = cmas(aux[c], acc[c], k1);
+    apply(v, out);
+  }
+}
+
+// The epilogue on the two chiral blocks of one column (acc = (H in)(x); cl
+// points at slot 0 of this site's clover data).
+template <typename T2, int MODE, bool ST>
+__device__ __forceinline__ void epilogue(const T2* cl, const T2 acc[12], const T2 aux[12],
+                                         const T2 ra[12], double c1, double c2, T2 out[12]) {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) v[c] = cmas(aux[6 * b + c], acc[6 * b + c], k1);
-      herm6_apply(m, v, out + 6 * b);
+  for (int b = 0; b < 2; ++b)
+    epilogue_block<T2, MODE, ST>(cl, b, acc + 6 * b, aux + 6 * b, ra + 6 * b, c1, c2, out + 6 * b);
+}
+
+// The fused reductions of one output column over its components [c0, c0 + N)
+// (o the output, av the aux field), each accumulated in component order.
+template <int RED, int N, typename C>
+__device__ __forceinline__ void fused_reductions(unsigned hb, int c0, const C o[N], const C av[N], double2& s0,
+                                                 double2& s1, double2& s2) {
+  if (RED == RED_DOT) {
+    shadow_dot_part<C, N>(hb, c0, o, s0);
+  } else if (RED == RED_TS) {
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      const double ox = o[c].x, oy = o[c].y, ax = av[c].x, ay = av[c].y;
+      s0.x = fmadd(ox, ax, fmadd(oy, ay, s0.x));
+      s0.y = fmadd(ox, ay, fmadd(-oy, ax, s0.y));
+      s1.x = fmadd(ox, ox, fmadd(oy, oy, s1.x));
+    }
+    shadow_dot_part<C, N>(hb, c0, o, s2);
+  } else if (RED == RED_NORM) {
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      const double ox = o[c].x, oy = o[c].y;
+      s0.x = fmadd(ox, ox, fmadd(oy, oy, s0.x));
     }
   }
 }
@@ -408,6 +523,9 @@ __device__ __forceinline__ void hop_tile(const BoxGeom g, const TileArgs<E>& a, 
   if (on == 0) return;  // uniform across the wave
   C acc[R][12];
   if (valid) hop_sum<E, R, ST>(g, p, i, a.U, sm, a.in, a.in_n, r0, nr, on, acc);
+  // keep the epilogue's loads after the hop sum: hoisted above it they would
+  // stay live through the hop loop and cost occupancy
+  __builtin_amdgcn_sched_barrier(0);
   const C* cl;
   if constexpr (ST) cl = sm + kStageLinkPairs * 128 + lane * 2;
   else cl = a.clov + cidx(nt, p, 0, i);
@@ -420,35 +538,28 @@ __device__ __forceinline__ void hop_tile(const BoxGeom g, const TileArgs<E>& a, 
     const size_t base = fidx(nt, col, 0, i);
     const size_t ns = (size_t)col * nt * kTile + i;  // scale index of 16-bit fields
     if (valid) {
-      C av[12], ra[12], o[12];
+      const unsigned hb = shadow_bits(col, i);
       if constexpr (kIs16<E>) {
+        C av[12], ra[12], o[12], w[12];
         if (MODE != MODE_CINV_HOP) spinor_load_q(a.aux + base, a.aux_n[ns], av, true);
         if (MODE == MODE_RES) spinor_load_q(a.red_a + base, a.red_n[ns], ra, true);
-        C w[12];
         epilogue<C, MODE, ST>(cl, acc[r], av, ra, c1, c2, w);
-        spinor_store_q(a.out + base, a.out_n + ns, w, o, true);
+        spinor_store_q(a.out + base, a.out_n + ns, w, o, true);   // one scale over all 12 components
+        fused_reductions<RED, 12>(hb, 0, o, av, s0, s1, s2);
       } else {
-        if (MODE != MODE_CINV_HOP) spinor_load_nt(a.aux + base, av);
-        if (MODE == MODE_RES) spinor_load_nt(a.red_a + base, ra);
-        epilogue<C, MODE, ST>(cl, acc[r], av, ra, c1, c2, o);
-        spinor_store_nt(a.out + base, o);
-      }
-      if (RED == RED_DOT) {
-        shadow_dot(shadow_bits(col, i), o, s0);
-      } else if (RED == RED_TS) {
+        // chiral block by block: aux in, 6x6 clover block, out, reductions
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-          const double ox = o[c].x, oy = o[c].y, ax = av[c].x, ay = av[c].y;
-          s0.x = fmadd(ox, ax, fmadd(oy, ay, s0.x));
-          s0.y = fmadd(ox, ay, fmadd(-oy, ax, s0.y));
-          s1.x = fmadd(ox, ox, fmadd(oy, oy, s1.x));
-        }
-        shadow_dot(shadow_bits(col, i), o, s2);
-      } else if (RED == RED_NORM) {
+        for (int b = 0; b < 2; ++b) {
+          C av[6], ra[6], o[6];
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-          const double ox = o[c].x, oy = o[c].y;
-          s0.x = fmadd(ox, ox, fmadd(oy, oy, s0.x));
+          for (int k = 0; k < 3; ++k) {
+            if (MODE != MODE_CINV_HOP) ld2nt(a.aux + base + 128 * (3 * b + k), av[2 * k], av[2 * k + 1]);
+            if (MODE == MODE_RES) ld2nt(a.red_a + base + 128 * (3 * b + k), ra[2 * k], ra[2 * k + 1]);
+          }
+          epilogue_block<C, MODE, ST>(cl, b, acc[r] + 6 * b, av, ra, c1, c2, o);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) st2nt(a.out + base + 128 * (3 * b + k), o[2 * k], o[2 * k + 1]);
+          fused_reductions<RED, 6>(hb, 6 * b, o, av, s0, s1, s2);
         }
       }
     } else {
@@ -529,9 +640,15 @@ __device__ __forceinline__ int find_slot(const int* __restrict__ start, int n, i
 // workgroup stages each tile's links and clover data in LDS first (the trip
 // count of the tile loop is uniform over the workgroup, so every wavefront
 // reaches both barriers).
+// The FP32 and 16-bit odd half (A^-1 H) at R = 1 is held to 6 waves per
+// SIMD (80 VGPRs, no spills), so that two 12-wave workgroups (one tile each)
+// share a CU; the even half would spill at that limit and is left free.
+template <typename T2, int R, int MODE>
+constexpr int kHopWaves = (!std::is_same<T2, double2>::value && R == 1 && MODE == MODE_CINV_HOP) ? 6 : 1;
+
 template <typename T2, int R, int MODE, int RED, bool ST>
 __global__ void __launch_bounds__(64 * ((kMaxRhs + R - 1) / R))
-    k_hop_batch(const SlotDesc<T2>* __restrict__ slots, const int* __restrict__ tile_start,
+    __attribute__((amdgpu_waves_per_eu(kHopWaves<T2, R, MODE>))) k_hop_batch(const SlotDesc<T2>* __restrict__ slots, const int* __restrict__ tile_start,
                 const int* __restrict__ xstart, int xstride, const int* __restrict__ nslots_p, int fin, int faux,
                 int fout, int fred, int par_out, int order, int ng) {
   using C = typename CompOf<T2>::type;

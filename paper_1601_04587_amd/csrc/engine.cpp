@@ -349,10 +349,12 @@ static void evict_blocks(Ctx* c) {
 // Tile walk of the sub-banded orders: XCD x takes the x1 range
 // [x L1 / 8, (x+1) L1 / 8) of the box, splits its tiles by their x2 position
 // inside the (t, x1) plane into nsub sub-bands and walks each sub-band slice by
-// slice (t outermost, then x1, then the tiles of the plane).  A box whose
-// (x2, x3) planes are not a whole number of tiles, or with L1 < 8, gets the
-// banded walk instead.  The walk is checked to be a permutation of the tiles.
-static void build_walk(const BoxGeom& g, int tps, int nsub, std::vector<int>& walk, int xoff[kXcd + 1]) {
+// slice (t outermost, then x1, then the tiles of the plane); with tblock > 1
+// the slices go in blocks of tblock, the slices of a block innermost.  A box
+// whose (x2, x3) planes are not a whole number of tiles, or with L1 < 8, gets
+// the banded walk instead.  The walk is checked to be a permutation of the tiles.
+static void build_walk(const BoxGeom& g, int tps, int nsub, int tblock, std::vector<int>& walk,
+                       int xoff[kXcd + 1]) {
   walk.clear();
   const int nt = g.ntiles;
   const long plane = (long)g.L[2] * g.L[3] / 2;
@@ -364,9 +366,10 @@ static void build_walk(const BoxGeom& g, int tps, int nsub, std::vector<int>& wa
       const int a = x * g.L[1] / kXcd, b = (x + 1) * g.L[1] / kXcd;
       for (int sb = 0; sb < nsub; ++sb) {
         const int glo = sb * tpp / nsub, ghi = (sb + 1) * tpp / nsub;
-        for (int t = 0; t < nslice; ++t)
+        for (int t0 = 0; t0 < nslice; t0 += tblock)
           for (int x1 = a; x1 < b; ++x1)
-            for (int gg = glo; gg < ghi; ++gg) walk.push_back(t * tps + x1 * tpp + gg);
+            for (int gg = glo; gg < ghi; ++gg)
+              for (int t = t0; t < std::min(t0 + tblock, nslice); ++t) walk.push_back(t * tps + x1 * tpp + gg);
       }
     }
   } else {
@@ -428,9 +431,9 @@ std::shared_ptr<OpBlock> opblock(Ctx* c, int gauge_id, int dom_id) {
   ob->Ainv32 = DBuf(c->pool.get(), kCloverSlots * ns * sizeof(float2));
   for (DBuf* b : {&ob->U64, &ob->U32, &ob->A64, &ob->Ainv64, &ob->Ainv32})
     DDML_HIP(hipMemsetAsync(b->p, 0, b->bytes, c->stream));
-  std::vector<int> walks[2];
-  for (int w = 0; w < 2; ++w) {
-    build_walk(ob->g, ob->tps, w == 0 ? 2 : 4, walks[w], ob->xoff[w]);
+  std::vector<int> walks[kWalks];
+  for (int w = 0; w < kWalks; ++w) {
+    build_walk(ob->g, ob->tps, w == 0 ? 2 : 4, w == 2 ? 4 : 1, walks[w], ob->xoff[w]);
     ob->walk[w] = DBuf(c->pool.get(), sizeof(int) * walks[w].size());
     DDML_HIP(hipMemcpyAsync(ob->walk[w].p, walks[w].data(), sizeof(int) * walks[w].size(), hipMemcpyHostToDevice,
                             c->stream));

@@ -148,7 +148,7 @@ def test_mixed_solver_iterations_close_to_fp64(setup, solver):
 def test_autotune_and_stencil_timing(setup):
     L, U, ctx, gid, doms, ids = setup
     R, order, grid, splits, stage, ms = ctx.autotune(gid, ids["G2"], 12, ddml.MIXED_FP32)
-    assert 1 <= R <= 3 and order in (0, 1, 2, 3) and grid in (512, 1024, 2048) and 1 <= splits <= 3 and ms > 0
+    assert 1 <= R <= 3 and order in (0, 1, 2, 3, 4) and grid in (512, 1024, 2048) and 1 <= splits <= 3 and ms > 0
     assert stage in (0, 1)
     ms_odd, ms_even, b_odd, b_even = ctx.time_stencil(gid, ids["G2"], 12, ddml.MIXED_FP32, 5)
     Vh = int(np.prod(L)) // 2
@@ -203,9 +203,9 @@ def test_every_launch_variant_computes_the_same_bits():
         b2 = inputs.point_source(L, (4, 4, 4, 4))
         variants = {
             ddml.MIXED_FP32: [(1, 1, 1024, 1, 1), (1, 3, 512, 1, 1), (1, 2, 1024, 2, 1), (2, 0, 512, 2, 1),
-                              (3, 1, 2048, 1, 1), (1, 0, 1024, 3, 1)],
+                              (3, 1, 2048, 1, 1), (1, 0, 1024, 3, 1), (1, 4, 1024, 1, 1)],
             ddml.FP64: [(1, 1, 1024, 1, 0), (1, 3, 1024, 1, 1), (3, 2, 512, 2, 1)],
-            ddml.MIXED_FP16: [(1, 1, 1024, 1, 1), (1, 3, 512, 2, 1), (2, 2, 1024, 1, 1)],
+            ddml.MIXED_FP16: [(1, 1, 1024, 1, 1), (1, 3, 512, 2, 1), (2, 2, 1024, 1, 1), (1, 4, 2048, 1, 1)],
         }
         for prec, vs in variants.items():
             ref = None
