@@ -60,6 +60,7 @@ __global__ void __launch_bounds__(768) k_vec(const SlotDesc<T2>* __restrict__ sl
     const SlotDesc<T2>& d = slots[s];
     if (col >= d.nrhs) continue;
     if (OP != VEC_INIT && OP != VEC_RELUP && !d.active[col]) continue;  // uniform per wave
+    if ((OP == VEC_INIT || OP == VEC_RELUP || OP == VEC_PFIX) && !init_here(d, OP == VEC_INIT ? 0 : 1)) continue;
     const int tile = vt - tile_start[s];
     const int i = tile * kTile + lane;
     const bool valid = i < d.g.Vh;
@@ -173,6 +174,7 @@ __global__ void __launch_bounds__(768) k_vec16(const SlotDesc<h16c>* __restrict_
     const SlotDesc<h16c>& d = slots[s];
     if (col >= d.nrhs) continue;
     if (OP != VEC_INIT && OP != VEC_RELUP && !d.active[col]) continue;  // uniform per wave
+    if ((OP == VEC_INIT || OP == VEC_RELUP || OP == VEC_PFIX) && !init_here(d, OP == VEC_INIT ? 0 : 1)) continue;
     const int tile = vt - tile_start[s];
     const int nt = d.ntiles;
     const int i = tile * kTile + lane;
@@ -328,6 +330,7 @@ __global__ void __launch_bounds__(kFinThreads) k_fin(const SlotDesc<T2>* __restr
   if (col >= d.nrhs) return;
   BiState& st = d.st[col];
   if (OP != FIN_INIT && OP != FIN_RELUP && !d.active[col]) return;   // uniform over the workgroup
+  if ((OP == FIN_INIT || OP == FIN_RELUP) && !init_here(d, OP == FIN_INIT ? 0 : 1)) return;
   const int nr = d.nrhs, nt = d.ntiles;
   const double2 z = make_double2(0, 0);
   const double2 a = (OP == FIN_CHECK) ? z : slot_sum(d.partial, nr, nt, 0, col, red);

@@ -347,6 +347,9 @@ __device__ __forceinline__ void shadow_dot(unsigned bits, const T2 v[12], double
 enum { F_R = 0, F_UNUSED = 1, F_P = 2, F_V = 3, F_S = 4, F_T = 5, F_X = 6, F_TMP = 7 /* odd */, F_NUM = 8 };
 // Partial-sum slots of BiCGstab ([kBiPartials][nrhs][ntiles] per solve)
 constexpr int kBiPartials = 4;
+// Smallest relative reduction asked of a 16-bit inner solve: below it the
+// recursive residual drifts away from the true one by the storage rounding.
+constexpr double kInnerFloor16 = 1e-3;
 // GCR(m) (solver 2) keeps m search directions p_j and their images q_j = M p_j
 // in the field slots after the BiCGstab ones (F_R, F_X and F_TMP are shared).
 constexpr int kGcrMax = 8;
@@ -363,6 +366,30 @@ struct BiState {
   int max_iters;
   int status;       // 0 ok/converged, 1 breakdown, 2 max iterations
 };
+
+// Device-side outer loop of a batched solve (defect correction in FP64 run
+// by kernels captured with the inner iterations).  A slot goes
+//   PH_NEW (x = 0) -> residual -> decide -> PH_PREP -> inner init -> PH_INNER
+//   -> (every column's inner solve stopped) PH_EXPORT -> x += e -> residual
+//   -> decide -> PH_PREP again, or PH_DONE when every column has converged,
+//   failed or used its corrections.
+enum { PH_IDLE = 0, PH_NEW = 1, PH_INNER = 2, PH_EXPORT = 3, PH_PREP = 4, PH_DONE = 5 };
+// per slot: phase, number of inner cycles started
+struct SlotState {
+  int phase;
+  int cycles;
+};
+// per column of a slot
+struct OuterState {
+  double bn2;       // |b'|^2
+  double rel;       // last true relative residual |b' - M x| / |b'|
+  int inner_total;  // inner iterations over all cycles
+  int done;         // 1: converged, failed or out of corrections
+  int status;       // 0, or DDML_ENUMERIC
+  int pad;
+};
+// Outer-step column flags ([3][nrhs] per slot): export, residual, prepare.
+enum { OF_EXPORT = 0, OF_RESID = 1, OF_PREP = 2 };
 
 // One inner-solver slot as seen by the batched kernels.
 template <typename T2> struct SlotDesc {
@@ -386,6 +413,30 @@ template <typename T2> struct SlotDesc {
   float* nrm[F_ALL];
   const float* Ainv_nrm;
   float2* x32;
+  // device-side outer loop (null phase: the host drives it)
+  const T2* A;             // clover A, for the FP64 residual views (MODE_RES)
+  SlotState* sst;
+  OuterState* ost;         // [nrhs]
+  int* oflag;              // [3][nrhs]
+  double2* o64[8];         // FP64 outer fields: b'_e, b'_o, x_e, x_o, r_e, r_o, t_e, t_o
+  const double2* Ainv64;   // FP64 A^{-1} (A_oo^{-1} r_o of the preparation)
+  double2* partial64;      // [2][nrhs][ntiles]: |r_e|^2, |r_o|^2 partial sums
+  double tol, inner_tol;
+  int max_outer, max_inner, prec, solver;
 };
+enum { O_BE = 0, O_BO = 1, O_XE = 2, O_XO = 3, O_RE = 4, O_RO = 5, O_TE = 6, O_TO = 7 };
+
+// Whether the inner (re)initialisation of kind `kind` (0: fresh start, 1:
+// reliable update keeping the Krylov space) runs on slot d.  A host-driven
+// slot runs the one the host launched; a device-driven slot runs only in
+// PH_PREP, with the reliable update from its second cycle on when asked for.
+template <typename T2>
+__device__ __forceinline__ bool init_here(const SlotDesc<T2>& d, int kind) {
+  if (!d.sst) return true;
+  const SlotState st = *d.sst;
+  if (st.phase != PH_PREP) return false;
+  const int relup = d.solver == 1 && st.cycles > 1;
+  return relup == kind;
+}
 
 }  // namespace ddml

@@ -673,15 +673,25 @@ __global__ void __launch_bounds__(64 * ((kMaxRhs + R - 1) / R))
     } else if (order != TILE_ORDER_LINEAR) {
       tile = ldg(d.walk + d.xoff[x] + tile);
     }
+    // a workgroup whose columns are all inactive skips the tile (uniform: every
+    // thread reads the same flags), before the staging
+    {
+      const int c0 = grp * W * R, c1 = min(d.nrhs, c0 + W * R);
+      bool any = false;
+      for (int c = c0; c < c1; ++c) any = any || ldg(d.active + c);
+      if (!any) continue;
+    }
     const bool h16 = kIs16<T2>;
-    const TileArgs<T2> ta{d.U, d.Ainv, h16 ? d.Ainv_nrm : nullptr,
+    const T2* clov = MODE == MODE_RES ? d.A : d.Ainv;   // M = A - kappa H needs A itself
+    const TileArgs<T2> ta{d.U, clov, h16 ? d.Ainv_nrm : nullptr,
                           d.f[fin], h16 ? d.nrm[fin] : nullptr,
                           faux >= 0 ? d.f[faux] : nullptr, h16 && faux >= 0 ? d.nrm[faux] : nullptr,
                           fred >= 0 ? d.f[fred] : nullptr, h16 && fred >= 0 ? d.nrm[fred] : nullptr,
                           d.f[fout], h16 ? d.nrm[fout] : nullptr};
-    if constexpr (ST) stage_tile<T2>(d.g, d.U, d.Ainv, ta.clov_n, par_out, tile, sm);
-    hop_tile<T2, R, MODE, RED, ST>(d.g, ta, d.partial, d.active, par_out, d.nrhs, d.kappa * d.kappa, 0.0, tile,
-                                   grp * W, sm);
+    if constexpr (ST) stage_tile<T2>(d.g, d.U, clov, ta.clov_n, par_out, tile, sm);
+    // c1: kappa^2 in the Schur operator, kappa in the FP64 residual and preparation
+    const double c1 = (MODE == MODE_PREP || MODE == MODE_RES) ? d.kappa : d.kappa * d.kappa;
+    hop_tile<T2, R, MODE, RED, ST>(d.g, ta, d.partial, d.active, par_out, d.nrhs, c1, 0.0, tile, grp * W, sm);
     if constexpr (ST) __syncthreads();
   }
 }
@@ -755,6 +765,10 @@ hipError_t launch_hop_item(const HopItem<double2>& it, int mode, int red, int R,
   DDML_HOPB_DISPATCH1(T2, Rv, MODE_SCHUR, RED_TS, STv)           \
   if constexpr (!kIs16<T2>) {                                    \
     DDML_HOPB_DISPATCH1(T2, Rv, MODE_SCHUR, RED_NONE, STv)       \
+  }                                                              \
+  if constexpr (std::is_same<T2, double2>::value && Rv == 1) {   \
+    DDML_HOPB_DISPATCH1(T2, Rv, MODE_PREP, RED_NONE, STv)        \
+    DDML_HOPB_DISPATCH1(T2, Rv, MODE_RES, RED_NORM, STv)         \
   }
 #define DDML_HOPB_DISPATCH_ST(T2, STv) \
   DDML_HOPB_DISPATCH_R(T2, 1, STv)     \

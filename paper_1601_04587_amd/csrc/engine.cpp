@@ -691,6 +691,27 @@ void apply_eo(Ctx* c, int gauge_id, int dom_id, const double* in, double* out, i
 template <typename T2>
 BatchRunner<T2>::~BatchRunner() {
   if (exec) (void)hipGraphExecDestroy(exec);
+  for (int k = 0; k < 2; ++k) {
+    if (ev[k]) {
+      (void)hipEventSynchronize(ev[k]);
+      (void)hipEventDestroy(ev[k]);
+    }
+    if (pin_up[k]) (void)hipHostFree(pin_up[k]);
+    if (pin_rb[k]) (void)hipHostFree(pin_rb[k]);
+  }
+}
+
+// Byte layout of a device-loop table upload: slot table, the four FP64 view
+// tables, tile starts, XCD tile starts, slot count.
+template <typename T2>
+static size_t up_layout(int max_slots, size_t off[5]) {
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  off[0] = 0;
+  off[1] = off[0] + al(sizeof(SlotDesc<T2>) * max_slots);
+  off[2] = off[1] + al(sizeof(SlotDesc<double2>) * 4 * max_slots);
+  off[3] = off[2] + al(sizeof(int) * (max_slots + 1));
+  off[4] = off[3] + al(sizeof(int) * kXcd * (max_slots + 1));
+  return off[4] + al(sizeof(int));
 }
 
 template <typename T2>
@@ -712,10 +733,30 @@ void BatchRunner<T2>::init(Ctx* c, int nrhs_, const TuneChoice& tn, int max_slot
   st_all = DBuf(c->pool.get(), sizeof(BiState) * max_slots * kMaxRhs);
   act_all = DBuf(c->pool.get(), sizeof(int) * max_slots * kMaxRhs);
   if (gcr_m > 0) gc_all = DBuf(c->pool.get(), sizeof(double2) * max_slots * kMaxRhs * 2 * kGcrMax);
+  device = gcr_m == 0;
+  if (device) {
+    sst_all = DBuf(c->pool.get(), sizeof(SlotState) * max_slots);
+    ost_all = DBuf(c->pool.get(), sizeof(OuterState) * max_slots * kMaxRhs);
+    oflag_all = DBuf(c->pool.get(), sizeof(int) * max_slots * 3 * kMaxRhs);
+    views = DBuf(c->pool.get(), sizeof(SlotDesc<double2>) * 4 * max_slots);
+    h_views.assign((size_t)4 * max_slots, SlotDesc<double2>{});
+    size_t off[5];
+    up_bytes = up_layout<T2>(max_slots, off);
+    rb_bytes = sizeof(SlotState) * max_slots + sizeof(OuterState) * max_slots * kMaxRhs;
+    for (int k = 0; k < 2; ++k) {
+      DDML_HIP(hipHostMalloc(&pin_up[k], up_bytes, hipHostMallocDefault));
+      DDML_HIP(hipHostMalloc(&pin_rb[k], rb_bytes, hipHostMallocDefault));
+      DDML_HIP(hipEventCreateWithFlags(&ev[k], hipEventDisableTiming));
+      snap[k].assign(max_slots, 0);
+    }
+    DDML_HIP(launch_outer_reset(sst_all.as<SlotState>(), ost_all.as<OuterState>(), act_all.as<int>(),
+                                oflag_all.as<int>(), max_slots, PH_IDLE, c->stream));
+  }
   SlotDesc<T2> empty{};
   h_table.assign(max_slots, empty);
   h_tstart.assign(max_slots + 1, 0);
   slot_of.assign(max_slots, nullptr);
+  gen_of.assign(max_slots, 0);
   h_st.assign((size_t)max_slots * kMaxRhs, BiState{});
   DDML_HIP(hipMemsetAsync(act_all.p, 0, sizeof(int) * max_slots * kMaxRhs, c->stream));
   nused = 0;
@@ -739,6 +780,38 @@ void BatchRunner<T2>::capture() {
   // the stream: keep the first one and fail after the capture is closed
   hipError_t first = hipSuccess;
   auto chk = [&](hipError_t r) { if (first == hipSuccess && r != hipSuccess) first = r; };
+  if (device) {
+    // the FP64 outer step of every slot that needs one (flags set by the gate)
+    const auto* vw = views.as<SlotDesc<double2>>();
+    const SlotDesc<double2>* vexp = vw;
+    const SlotDesc<double2>* vres0 = vw + max_slots;
+    const SlotDesc<double2>* vres1 = vw + 2 * max_slots;
+    const SlotDesc<double2>* vprep = vw + 3 * max_slots;
+    auto outer = [&](int step) { chk(launch_outer(tb, ts, ns, max_slots, nrhs, step, grid, s)); };
+    outer(OUTER_GATE);
+    // export: t_e = x, t_o = A_oo^{-1}(r_o + kappa H_oe t_e), x += t
+    outer(OUTER_CAST);
+    chk(launch_hop_batch(vexp, ts, xs, xw, ns, nrhs, 1, MODE_PREP, RED_NONE, O_TE, O_RO, O_TO, -1, 1, grid, order, 1,
+                         1, s));
+    outer(OUTER_AXPY);
+    // r = b' - M x on both parities with |r|^2 partials
+    chk(launch_hop_batch(vres0, ts, xs, xw, ns, nrhs, 1, MODE_RES, RED_NORM, O_XO, O_XE, O_RE, O_BE, 0, grid, order,
+                         1, 1, s));
+    chk(launch_hop_batch(vres1, ts, xs, xw, ns, nrhs, 1, MODE_RES, RED_NORM, O_XE, O_XO, O_RO, O_BO, 1, grid, order,
+                         1, 1, s));
+    outer(OUTER_DECIDE);
+    outer(OUTER_PHASE);
+    // rhat_e = A_ee^{-1}(r_e + kappa H_eo A_oo^{-1} r_o), then the inner initialisation
+    outer(OUTER_CLOVER);
+    chk(launch_hop_batch(vprep, ts, xs, xw, ns, nrhs, 1, MODE_PREP, RED_NONE, O_TO, O_RE, O_TE, -1, 0, grid, order, 1,
+                         1, s));
+    chk(launch_vec(tb, ts, ns, nrhs, VEC_INIT, grid, s));
+    chk(launch_fin(tb, ns, max_slots, FIN_INIT, s));
+    chk(launch_vec(tb, ts, ns, nrhs, VEC_RELUP, grid, s));
+    chk(launch_fin(tb, ns, max_slots, FIN_RELUP, s));
+    chk(launch_vec(tb, ts, ns, nrhs, VEC_PFIX, grid, s));
+    outer(OUTER_COMMIT);
+  }
   if constexpr (!std::is_same<T2, h16c>::value) {
     // one GCR(m) cycle: step k applies M to p_k, orthogonalises against the
     // cycle's earlier directions and updates x, r and the next direction
@@ -862,6 +935,35 @@ SlotDesc<h16c> make_desc<h16c>(const Solve* s, BiState* st, int* act, int order)
   return d;
 }
 
+// FP64 view of a solve's outer fields for the batched stencil: f[O_*] are
+// b'_e, b'_o, x_e, x_o, r_e, r_o, t_e, t_o; clov is the clover data the
+// epilogue applies (A for the residual, A^{-1} otherwise).
+static SlotDesc<double2> view64(const Solve* s, int order, int* act, const double2* clov, double2* partial) {
+  const OpBlock& ob = *s->ob;
+  SlotDesc<double2> d{};
+  d.g = ob.g;
+  d.nrhs = s->nrhs;
+  d.ntiles = ob.ntiles;
+  d.tps = ob.tps;
+  d.kappa = ob.bs.kappa;
+  d.U = ob.U64.as<double2>();
+  d.Ainv = clov;
+  d.A = clov;
+  const DBuf* o[8] = {&s->be, &s->bo, &s->xe, &s->xo, &s->re, &s->ro, &s->te, &s->to};
+  for (int k = 0; k < 8; ++k) d.f[k] = o[k]->as<double2>();
+  d.partial = partial;
+  d.active = act;
+  attach_walk(d, ob, order);
+  return d;
+}
+
+template <typename T2>
+bool BatchRunner<T2>::has_free() const {
+  for (int i = 0; i < max_slots; ++i)
+    if (!slot_of[i]) return true;
+  return false;
+}
+
 template <typename T2>
 int BatchRunner<T2>::join(Solve* s) {
   int slot = -1;
@@ -870,9 +972,39 @@ int BatchRunner<T2>::join(Solve* s) {
   if (slot < 0) return -1;
   BiState* st = st_all.as<BiState>() + (size_t)slot * kMaxRhs;
   int* act = act_all.as<int>() + (size_t)slot * kMaxRhs;
-  h_table[slot] = make_desc<T2>(s, st, act, order);
-  if (gcr_m > 0) h_table[slot].gcoef = gc_all.template as<double2>() + (size_t)slot * kMaxRhs * 2 * kGcrMax;
+  SlotDesc<T2> d = make_desc<T2>(s, st, act, order);
+  if (gcr_m > 0) d.gcoef = gc_all.template as<double2>() + (size_t)slot * kMaxRhs * 2 * kGcrMax;
+  if (device) {
+    const OpBlock& ob = *s->ob;
+    SlotState* sst = sst_all.as<SlotState>() + slot;
+    OuterState* ost = ost_all.as<OuterState>() + (size_t)slot * kMaxRhs;
+    int* ofl = oflag_all.as<int>() + (size_t)slot * 3 * kMaxRhs;
+    d.sst = sst;
+    d.ost = ost;
+    d.oflag = ofl;
+    const DBuf* o[8] = {&s->be, &s->bo, &s->xe, &s->xo, &s->re, &s->ro, &s->te, &s->to};
+    for (int k = 0; k < 8; ++k) d.o64[k] = o[k]->as<double2>();
+    d.Ainv64 = ob.Ainv64.as<double2>();
+    d.partial64 = s->partial64.as<double2>();
+    d.tol = s->prm.tol;
+    d.inner_tol = s->prm.inner_tol;
+    d.max_outer = s->prm.max_outer;
+    d.max_inner = s->prm.max_inner;
+    d.prec = s->prec;
+    d.solver = s->prm.solver;
+    const size_t half = (size_t)s->nrhs * ob.ntiles;
+    double2* p64 = s->partial64.as<double2>();
+    h_views[slot] = view64(s, order, ofl + OF_EXPORT * s->nrhs, ob.Ainv64.as<double2>(), nullptr);
+    h_views[max_slots + slot] = view64(s, order, ofl + OF_RESID * s->nrhs, ob.A64.as<double2>(), p64);
+    h_views[2 * max_slots + slot] = view64(s, order, ofl + OF_RESID * s->nrhs, ob.A64.as<double2>(), p64 + half);
+    h_views[3 * max_slots + slot] = view64(s, order, ofl + OF_PREP * s->nrhs, ob.Ainv64.as<double2>(), nullptr);
+    // the slot starts at PH_NEW with cleared outer state and flags
+    DDML_HIP(launch_outer_reset(sst, ost, act, ofl, 1, PH_NEW, ctx->stream));
+    s->dev = true;
+  }
+  h_table[slot] = d;
   slot_of[slot] = s;
+  gen_of[slot] = ++joins;
   s->slot = slot;
   dirty = true;
   return slot;
@@ -882,7 +1014,10 @@ template <typename T2>
 void BatchRunner<T2>::leave(Solve* s) {
   if (s->slot < 0) return;
   h_table[s->slot] = SlotDesc<T2>{};
+  if (device)
+    for (int v = 0; v < 4; ++v) h_views[(size_t)v * max_slots + s->slot] = SlotDesc<double2>{};
   slot_of[s->slot] = nullptr;
+  gen_of[s->slot] = 0;
   s->slot = -1;
   dirty = true;
 }
@@ -899,6 +1034,28 @@ void BatchRunner<T2>::upload() {
     int* P = h_xstart.data() + (size_t)x * (max_slots + 1);
     for (int i = 0; i < max_slots; ++i)
       P[i + 1] = P[i] + (slot_of[i] && order != TILE_ORDER_LINEAR ? xcd_share(h_table[i], order, x) : 0);
+  }
+  if (device) {
+    // through pinned staging, so that the copies stay asynchronous; the
+    // buffer of this ring position was last read by the replay before the
+    // previous one, which the host has already waited for
+    size_t off[5];
+    up_layout<T2>(max_slots, off);
+    char* h = static_cast<char*>(pin_up[ring]);
+    std::memcpy(h + off[0], h_table.data(), sizeof(SlotDesc<T2>) * max_slots);
+    std::memcpy(h + off[1], h_views.data(), sizeof(SlotDesc<double2>) * 4 * max_slots);
+    std::memcpy(h + off[2], h_tstart.data(), sizeof(int) * (max_slots + 1));
+    std::memcpy(h + off[3], h_xstart.data(), sizeof(int) * h_xstart.size());
+    std::memcpy(h + off[4], &nused, sizeof(int));
+    hipStream_t st = ctx->stream;
+    DDML_HIP(hipMemcpyAsync(table.p, h + off[0], sizeof(SlotDesc<T2>) * max_slots, hipMemcpyHostToDevice, st));
+    DDML_HIP(hipMemcpyAsync(views.p, h + off[1], sizeof(SlotDesc<double2>) * 4 * max_slots, hipMemcpyHostToDevice,
+                            st));
+    DDML_HIP(hipMemcpyAsync(tstart.p, h + off[2], sizeof(int) * (max_slots + 1), hipMemcpyHostToDevice, st));
+    DDML_HIP(hipMemcpyAsync(xstart.p, h + off[3], sizeof(int) * h_xstart.size(), hipMemcpyHostToDevice, st));
+    DDML_HIP(hipMemcpyAsync(nslots.p, h + off[4], sizeof(int), hipMemcpyHostToDevice, st));
+    dirty = false;
+    return;
   }
   DDML_HIP(hipMemcpyAsync(table.p, h_table.data(), sizeof(SlotDesc<T2>) * max_slots, hipMemcpyHostToDevice,
                           ctx->stream));
@@ -919,6 +1076,49 @@ void BatchRunner<T2>::replay() {
   DDML_HIP(hipMemcpyAsync(hs, st_all.p, nb, hipMemcpyDeviceToHost, ctx->stream));
   DDML_HIP(hipStreamSynchronize(ctx->stream));
   std::memcpy(h_st.data(), hs, nb);
+}
+
+template <typename T2>
+void BatchRunner<T2>::launch_dev() {
+  hipStream_t st = ctx->stream;
+  if (dirty) upload();
+  DDML_HIP(hipGraphLaunch(exec, st));
+  const int n = std::max(nused, 1);
+  char* h = static_cast<char*>(pin_rb[ring]);
+  DDML_HIP(hipMemcpyAsync(h, sst_all.p, sizeof(SlotState) * n, hipMemcpyDeviceToHost, st));
+  DDML_HIP(hipMemcpyAsync(h + sizeof(SlotState) * max_slots, ost_all.p, sizeof(OuterState) * n * kMaxRhs,
+                          hipMemcpyDeviceToHost, st));
+  DDML_HIP(hipEventRecord(ev[ring], st));
+  snap[ring] = gen_of;
+  rb_used[ring] = nused;
+  pending[ring] = true;
+  ring ^= 1;
+}
+
+template <typename T2>
+void BatchRunner<T2>::collect_dev() {
+  const int k = ring;   // the replay before the latest one
+  if (!pending[k]) return;
+  DDML_HIP(hipEventSynchronize(ev[k]));
+  pending[k] = false;
+  const char* h = static_cast<const char*>(pin_rb[k]);
+  const SlotState* ss = reinterpret_cast<const SlotState*>(h);
+  const OuterState* os = reinterpret_cast<const OuterState*>(h + sizeof(SlotState) * max_slots);
+  for (int slot = 0; slot < rb_used[k]; ++slot) {
+    // a slot retired since (and maybe taken by another solve) is skipped
+    if (snap[k][slot] == 0 || gen_of[slot] != snap[k][slot] || ss[slot].phase != PH_DONE) continue;
+    Solve* s = slot_of[slot];
+    s->outer = ss[slot].cycles;
+    for (int col = 0; col < s->nrhs; ++col) {
+      const OuterState& o = os[(size_t)slot * kMaxRhs + col];
+      s->inner_iters[col] = o.inner_total;
+      s->rel[col] = o.rel;
+      s->status[col] = o.status;
+      s->done[col] = 1;
+    }
+    leave(s);
+    s->state = 3;
+  }
 }
 
 template struct BatchRunner<float2>;
@@ -1090,9 +1290,6 @@ static void launch_export(Ctx* c, Solve* s) {
   DDML_HIP(launch_axpy_d(s->xo.as<double2>(), s->to.as<double2>(), 1.0, n, c->stream));
 }
 
-// Smallest relative reduction asked of a 16-bit inner solve: below it the
-// recursive residual drifts away from the true one by the storage rounding.
-constexpr double kInnerFloor16 = 1e-3;
 
 template <typename T2>
 static bool try_join(Ctx* c, Solve* s) {
@@ -1148,9 +1345,62 @@ static bool try_join(Ctx* c, Solve* s) {
 
 static void finish_state(Solve* s) { s->state = 3; }
 
-// One scheduling round over the live solves.
+// One scheduling round of the device loop: prepared solves join a free slot
+// of their runner, every runner with members replays its graph once (the
+// outer step and K inner iterations of every slot), and the slots that the
+// previous replay left at PH_DONE retire (state 3).  The host waits only for
+// the replay before the latest one, so one replay is always queued.
+bool solve_join(Ctx* c, Solve* s) {
+  if (gcr_len(s->prm) > 0) return true;   // the host loop joins between cycles
+  if (s->slot >= 0) return true;
+  int slot = -1;
+  if (s->prec == DDML_FP64) slot = runner<double2>(c, s->nrhs, 0).join(s);
+  else if (s->prec == DDML_MIXED_FP16) slot = runner<h16c>(c, s->nrhs, 0).join(s);
+  else slot = runner<float2>(c, s->nrhs, 0).join(s);
+  if (slot < 0) return false;
+  s->state = 2;
+  return true;
+}
+
+static void dev_progress(Ctx* c, std::vector<Solve*>& live) {
+  for (Solve* s : live)
+    if (s->state == 1 && s->slot < 0) solve_join(c, s);
+  auto round = [&](auto& runs) {
+    for (auto& kv : runs) {
+      auto& run = *kv.second;
+      if (!run.device) continue;
+      if (run.members() > 0) run.launch_dev();
+      run.collect_dev();
+    }
+  };
+  round(c->run32);
+  round(c->run64);
+  round(c->run16);
+}
+
+// True if a prepared solve with these parameters would find a free slot.
+bool solve_slot_free(Ctx* c, int prec, int nrhs, const ddml_solver_params& prm) {
+  const int m = gcr_len(prm);
+  if (m > 0) return true;   // the host loop queues solves for its runner itself
+  if (prec == DDML_FP64) return runner<double2>(c, nrhs, 0).has_free();
+  if (prec == DDML_MIXED_FP16) return runner<h16c>(c, nrhs, 0).has_free();
+  return runner<float2>(c, nrhs, 0).has_free();
+}
+
+static void host_progress(Ctx* c, std::vector<Solve*>& live);
+
+// One scheduling round over the live solves: BiCGstab solves run the device
+// loop, GCR(m) solves the host loop.
 void solve_progress(Ctx* c, std::vector<Solve*>& live, bool block) {
   (void)block;
+  std::vector<Solve*> host, dev;
+  for (Solve* s : live) (gcr_len(s->prm) > 0 ? host : dev).push_back(s);
+  if (!dev.empty()) dev_progress(c, dev);
+  if (!host.empty()) host_progress(c, host);
+}
+
+// One scheduling round of the host loop (GCR(m) solves).
+static void host_progress(Ctx* c, std::vector<Solve*>& live) {
   hipStream_t st = c->stream;
   // 1. residuals of every solve that needs one, one synchronisation
   std::vector<Solve*> need;
@@ -1204,7 +1454,7 @@ void solve_progress(Ctx* c, std::vector<Solve*>& live, bool block) {
     using T2 = decltype(tag);
     for (auto& kv : runs) {
       auto& run = *kv.second;
-      if (run.members() == 0) continue;
+      if (run.device || run.members() == 0) continue;
       run.replay();
       for (int slot = 0; slot < run.max_slots; ++slot) {
         Solve* s = run.slot_of[slot];
@@ -1439,6 +1689,7 @@ void run_solves(Ctx* c, std::vector<Solve*>& solves) {
   while (!queue.empty() || !live.empty()) {
     while (!queue.empty()) {
       Solve* s = queue.front();
+      if (!solve_slot_free(c, s->prec, s->nrhs, s->prm)) break;   // retry once a slot has retired
       const size_t fp = solve_footprint(c, s->gauge_id, s->dom_id, s->nrhs, s->prm);
       if (!live.empty() && !c->pool->fits_device(fp)) break;
       try {
@@ -1448,6 +1699,7 @@ void run_solves(Ctx* c, std::vector<Solve*>& solves) {
         if (e.code == DDML_ENOMEM && !live.empty()) break;  // retry once solves in flight have finished
         throw;
       }
+      solve_join(c, s);
       queue.pop_front();
       live.push_back(s);
     }

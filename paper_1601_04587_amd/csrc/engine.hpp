@@ -126,6 +126,7 @@ struct Solve {
   DBuf partial;     // [2][nrhs][ntiles]
   DBuf table1, tstart1, n1;  // one-entry slot table
   int slot = -1;    // position in the batch table
+  bool dev = false; // the outer loop runs on the device
   // host bookkeeping
   std::vector<double> bn2, rel;
   std::vector<int> done, inner_iters, status;
@@ -150,15 +151,39 @@ struct TuneChoice {
   int stage = 0;
 };
 
-// Batched inner solver for one precision, nrhs and Krylov method: a slot table
-// in device memory and a captured graph of K BiCGstab iterations (or of one
-// GCR(m) cycle) over it.
+// Batched solver for one precision, nrhs and Krylov method: a slot table in
+// device memory and a captured graph over it.
+//   BiCGstab (device loop): the FP64 outer step of every slot (export of the
+//   inner solution, true residual, decision, preparation of the next inner
+//   right-hand side and the inner initialisation), then K inner iterations.
+//   The host only admits solves into free slots and retires the slots that
+//   the device has marked PH_DONE, reading the slot phases asynchronously one
+//   replay behind.
+//   GCR(m) (host loop): one GCR(m) cycle; the host runs the FP64 outer steps
+//   between cycles.
 template <typename T2>
 struct BatchRunner {
   Ctx* ctx = nullptr;
   int nrhs = 0, R = 3, K = 8, grid = 1024, max_slots = 64, splits = 1, stage = 0;
   int gcr_m = 0;                  // 0: BiCGstab; m > 0: GCR(m)
+  bool device = false;            // the outer loop runs on the device (BiCGstab)
   DBuf table, tstart, xstart, nslots, st_all, act_all, gc_all;
+  // device loop: per-slot phase, per-column outer state, step flags [3][kMaxRhs]
+  // per slot, and the FP64 view tables [4][max_slots] (export, residual even,
+  // residual odd, preparation)
+  DBuf sst_all, ost_all, oflag_all, views;
+  std::vector<SlotDesc<double2>> h_views;
+  void* pin_up[2] = {nullptr, nullptr};   // pinned table uploads (two in flight at most)
+  void* pin_rb[2] = {nullptr, nullptr};   // pinned phase / outer-state readbacks
+  size_t up_bytes = 0, rb_bytes = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  bool pending[2] = {false, false};
+  int rb_used[2] = {0, 0};
+  // join number of each slot's occupant (never reused, unlike Solve addresses),
+  // now and at the time of each readback
+  uint64_t joins = 0;
+  std::vector<uint64_t> gen_of, snap[2];
+  int ring = 0;
   int order = TILE_ORDER_BANDED;
   std::vector<SlotDesc<T2>> h_table;
   std::vector<int> h_tstart, h_xstart;
@@ -175,6 +200,11 @@ struct BatchRunner {
   void upload();
   void replay();
   int members() const;
+  bool has_free() const;
+  // device loop: enqueue one replay and its phase readback; then retire the
+  // slots the previous readback found finished (their solves get state 3)
+  void launch_dev();
+  void collect_dev();
 };
 
 
@@ -246,6 +276,10 @@ void run_solves(Ctx* c, std::vector<Solve*>& solves);
 // Pieces used by the serving loop
 void solve_prepare(Ctx* c, Solve* s);                // allocate + set up (state -> 1)
 void solve_progress(Ctx* c, std::vector<Solve*>& live, bool block);  // one scheduling round
+// Device loop: whether a solve of this kind would find a free slot now, and
+// joining a prepared solve to its slot (false: no slot free yet)
+bool solve_slot_free(Ctx* c, int prec, int nrhs, const ddml_solver_params& prm);
+bool solve_join(Ctx* c, Solve* s);
 void solve_finish(Ctx* c, Solve* s);                 // scatter, info, free
 void solve_release(Solve* s);                        // free device state (after a failed prepare)
 void check_params(const ddml_solver_params* p);

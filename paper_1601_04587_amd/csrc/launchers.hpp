@@ -61,6 +61,19 @@ hipError_t launch_gcr_fin(const SlotDesc<float2>* slots, const int* nslots_p, in
 hipError_t launch_gcr_fin(const SlotDesc<double2>* slots, const int* nslots_p, int max_slots, int op, int k,
                           hipStream_t st);
 hipError_t launch_fin(const SlotDesc<h16c>* slots, const int* nslots_p, int max_slots, int op, hipStream_t st);
+// Steps of the device-side outer loop (outer.hip), over the whole slot table.
+enum { OUTER_GATE = 0, OUTER_CAST = 1, OUTER_AXPY = 2, OUTER_CLOVER = 3, OUTER_DECIDE = 4, OUTER_PHASE = 5,
+       OUTER_COMMIT = 6 };
+hipError_t launch_outer(const SlotDesc<float2>* slots, const int* tile_start, const int* nslots_p, int max_slots,
+                        int nrhs, int step, int grid, hipStream_t st);
+hipError_t launch_outer(const SlotDesc<double2>* slots, const int* tile_start, const int* nslots_p, int max_slots,
+                        int nrhs, int step, int grid, hipStream_t st);
+// Clears n consecutive slots of the device loop (phase, outer state, column
+// and step flags; each slot holds kMaxRhs columns and 3 kMaxRhs flags).
+hipError_t launch_outer_reset(SlotState* sst, OuterState* ost, int* act, int* oflag, int n, int phase,
+                              hipStream_t st);
+hipError_t launch_outer(const SlotDesc<h16c>* slots, const int* tile_start, const int* nslots_p, int max_slots,
+                        int nrhs, int step, int grid, hipStream_t st);
 
 // elementwise helpers on raw FP64 / mixed arrays (n complex numbers)
 hipError_t launch_cast_to_d(const float2* in, double2* out, size_t n, hipStream_t st);

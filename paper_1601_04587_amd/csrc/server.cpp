@@ -1,15 +1,18 @@
 // Serving loop: continuous batching of domain-solve requests.
 //
 // A host thread owns the engine while requests are in flight.  Each round it
-// (1) admits queued requests whose device footprint fits the HBM budget
-// (gauge fields and operator blocks stay resident and are shared), (2) runs
-// one scheduling round of the batched solver (FP64 residual checks for solves
-// between cycles, one graph replay of the inner iterations of every solve in
-// the batch), and (3) retires finished requests.  A request that arrives
-// while others are on the GPU joins the batch at the next round, so its work
-// overlaps theirs.  Per-request arithmetic does not depend on the batch: the
-// kernels reduce in a fixed order per solve and a solve's iterations are
-// independent of its neighbours in the slot table.
+// (1) admits queued requests whose device footprint fits the HBM budget and
+// whose runner has a free slot (gauge fields and operator blocks stay
+// resident and are shared), (2) runs one scheduling round of the batched
+// solver (one graph replay per runner, holding the FP64 outer step and K
+// inner iterations of every slot; the host reads the slot phases one replay
+// behind), and (3) retires the solves the device has finished: their
+// solutions are scattered on the stream and the requests complete when an
+// event after the scatter has passed, without draining the stream.  A
+// request that arrives while others are on the GPU joins the batch at the
+// next round, so its work overlaps theirs.  Per-request arithmetic does not
+// depend on the batch: the kernels reduce in a fixed order per solve and a
+// solve's iterations are independent of its neighbours in the slot table.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -102,10 +105,13 @@ void Server::loop() {
   std::deque<Req*> waiting;
   std::vector<Solve*> live;
   std::map<Solve*, Req*> owner;
+  // retired requests whose solution scatter is still on the stream
+  std::deque<std::pair<hipEvent_t, std::vector<Req*>>> landing;
+  std::vector<hipEvent_t> spare;
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(m);
-      if (live.empty() && waiting.empty() && incoming.empty()) {
+      if (live.empty() && waiting.empty() && incoming.empty() && landing.empty()) {
         if (stop) break;
         cv.wait_for(lk, std::chrono::milliseconds(2));
       }
@@ -114,9 +120,9 @@ void Server::loop() {
         incoming.pop_front();
       }
       waiting_count = waiting.size();
-      if (stop && live.empty() && waiting.empty()) break;
+      if (stop && live.empty() && waiting.empty() && landing.empty()) break;
     }
-    if (live.empty() && waiting.empty()) continue;
+    if (live.empty() && waiting.empty() && landing.empty()) continue;
     std::vector<Req*> finished;
     {
       std::lock_guard<std::recursive_mutex> g(ctx->mu);
@@ -145,9 +151,11 @@ void Server::loop() {
           continue;
         }
         if (!live.empty() && !ctx->pool->fits_device(fp)) break;
+        if (!solve_slot_free(ctx, s->prec, s->nrhs, s->prm)) break;
         waiting.pop_front();
         try {
           solve_prepare(ctx, s);
+          solve_join(ctx, s);
           q->res.admit_time = now_s();
           live.push_back(s);
           owner[s] = q;
@@ -164,18 +172,39 @@ void Server::loop() {
       }
       try {
         if (!live.empty()) solve_progress(ctx, live, false);
+        std::vector<Req*> retired;
         for (auto it = live.begin(); it != live.end();) {
           Solve* s = *it;
           if (s->state == 3) {
             solve_finish(ctx, s);
-            finished.push_back(owner[s]);
+            retired.push_back(owner[s]);
             owner.erase(s);
             it = live.erase(it);
           } else {
             ++it;
           }
         }
-        if (!finished.empty()) DDML_HIP(hipStreamSynchronize(ctx->stream));
+        if (!retired.empty()) {
+          hipEvent_t e = nullptr;
+          if (!spare.empty()) {
+            e = spare.back();
+            spare.pop_back();
+          } else {
+            DDML_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+          }
+          DDML_HIP(hipEventRecord(e, ctx->stream));
+          landing.emplace_back(e, std::move(retired));
+        }
+        // requests whose scatter has landed (all of them once nothing is left on the GPU)
+        while (!landing.empty()) {
+          hipEvent_t e = landing.front().first;
+          const hipError_t q = live.empty() ? hipEventSynchronize(e) : hipEventQuery(e);
+          if (q == hipErrorNotReady) break;
+          DDML_HIP(q);
+          for (Req* r : landing.front().second) finished.push_back(r);
+          spare.push_back(e);
+          landing.pop_front();
+        }
       } catch (const Error& e) {
         // a device error ends every request in flight
         for (Solve* s : live) {
@@ -185,6 +214,14 @@ void Server::loop() {
         }
         live.clear();
         owner.clear();
+        for (auto& l : landing) {
+          spare.push_back(l.first);
+          for (Req* r : l.second) {
+            r->res.status = e.code;
+            finished.push_back(r);
+          }
+        }
+        landing.clear();
       }
     }
     const double t = now_s();
@@ -218,6 +255,7 @@ void Server::loop() {
     }
     if (!finished.empty()) cv_done.notify_all();
   }
+  for (hipEvent_t e : spare) (void)hipEventDestroy(e);
 }
 
 }  // namespace ddml

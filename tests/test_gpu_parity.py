@@ -306,6 +306,77 @@ def test_batch_equals_individual_solves_bitwise(cfg1, prec):
     assert np.array_equal(outs[0], outs[3])
 
 
+@pytest.mark.parametrize("prec,solver", [(0, 0), (1, 1), (2, 1)])
+def test_device_loop_batch_equals_solo_fp64_and_reliable_updates(cfg1, prec, solver):
+    """The device-side outer loop (FP64 inner solves, and BiCGstab with reliable
+    updates carrying the Krylov space across corrections) gives the same bits in
+    a batch as alone, and reaches the tolerance against the oracle's operator."""
+    L, U, C, ctx, gid, doms, ids = cfg1
+    V = int(np.prod(L))
+    b = inputs.point_source(L, (9, 3, 2, 1))
+    prm = ddml.solver_params(tol=1e-10, prec=prec, solver=solver)
+    items = []
+    for k in ("G2", "G0", "G1"):
+        items.append((gid, ids[k], b, np.zeros((12, V, 4, 3), dtype=np.complex128), 12))
+    rc, infos = ctx.solve_batch(items, prm)
+    assert rc == ddml.OK
+    bn = b.reshape(12, V, 4, 3)
+    for (g, d, src, xb, n), info, k in zip(items, infos, ("G2", "G0", "G1")):
+        x1 = np.zeros_like(xb)
+        rc1, info1 = ctx.solve_domain(g, d, src, x1, 12, prm)
+        assert rc1 == ddml.OK
+        assert np.array_equal(x1, xb), k
+        assert [i.inner_iters for i in info1] == [i.inner_iters for i in info]
+        assert [i.outer_iters for i in info1] == [i.outer_iters for i in info]
+        lo, hi = doms[k]
+        res = oracle.residual(U, L, 0.1340, bn, xb, C=C, lo=lo, hi=hi)
+        assert res.max() <= 1e-10 * (1 + 1e-3), (k, res.max())
+        assert all(i.true_rel_residual <= 1e-10 for i in info)
+
+
+def test_device_loop_more_solves_than_slots(cfg0):
+    """70 solves through one runner of 64 slots: slots retire and are taken
+    again inside one call; every solve equals its solo solve bit for bit."""
+    L, U, ctx, gid = cfg0
+    V = int(np.prod(L))
+    rng = np.random.default_rng(70)
+    prm = ddml.solver_params(tol=1e-10, prec=ddml.MIXED_FP32)
+    items = []
+    for k in range(70):
+        src = _rand(rng, L, 2)
+        items.append((gid, -1, src, np.zeros((2, V, 4, 3), dtype=np.complex128), 2))
+    rc, infos = ctx.solve_batch(items, prm)
+    assert rc == ddml.OK
+    for k in (0, 33, 63, 64, 69):
+        g, d, src, xb, n = items[k]
+        x1 = np.zeros_like(xb)
+        ctx.solve_domain(g, d, src, x1, 2, prm)
+        assert np.array_equal(x1, xb), k
+    for (g, d, src, xb, n), info in zip(items, infos):
+        res = oracle.residual(U, L, 0.12, src, xb)
+        assert res.max() <= 1e-10 * (1 + 1e-3)
+
+
+def test_device_loop_out_of_corrections(cfg1):
+    """With one FP64 correction allowed and a tolerance that one FP32 inner
+    solve cannot reach, every column reports ENOTCONVERGED after exactly one
+    outer iteration, with the true residual it reached."""
+    L, U, C, ctx, gid, doms, ids = cfg1
+    V = int(np.prod(L))
+    b = inputs.point_source(L, (7, 1, 2, 3))
+    x = np.zeros((12, V, 4, 3), dtype=np.complex128)
+    prm = ddml.solver_params(tol=1e-12, max_outer=1, inner_tol=1e-5, prec=ddml.MIXED_FP32)
+    rc, info = ctx.solve_domain(gid, ids["G1"], b, x, 12, prm)
+    assert rc == ddml.ENOTCONVERGED
+    lo, hi = doms["G1"]
+    res = oracle.residual(U, L, 0.1340, b.reshape(12, V, 4, 3), x, C=C, lo=lo, hi=hi)
+    for col, i in enumerate(info):
+        assert i.outer_iters == 1
+        assert i.status == ddml.ENOTCONVERGED
+        assert 1e-12 < i.true_rel_residual < 1e-3
+        assert abs(i.true_rel_residual - res[col]) <= 1e-6 * res[col]
+
+
 def test_error_paths(cfg0):
     L, U, ctx, gid = cfg0
     with pytest.raises(ddml.DDMLError) as e:
