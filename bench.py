@@ -9,9 +9,14 @@ Workload (one "step" = one level-1 update round of the two-level scheme):
   for every slab update: the new gauge version's clover term is
   built, then the nested Dirichlet domains Gamma0 (4 slices), Gamma1 (8) and
   Gamma2 (the 16-slice slab) are solved for 12 point-source columns to a
-  relative residual of 1e-10 (FP32 inner BiCGstab, FP64 defect correction),
-  all 12 solves of the round in one batch; the telescoping series and the
-  nucleon and disconnected pseudoscalar contractions follow.
+  relative residual of 1e-10 (FP32 inner BiCGstab, FP64 defect correction
+  on the device); the telescoping series and the nucleon and disconnected
+  pseudoscalar contractions follow.  The default 16 steps are the n1 = 16
+  updates of every slab, run as one continuous queue: each update's series
+  (three solves) enters the library's request loop as soon as its gauge
+  version exists, so the next round's solves join the slot table while the
+  previous round's largest domains still run; a round is contracted when its
+  output buffers are needed again (two rounds in flight).
 Reported: domain solves/s (a solve = one domain x 12 columns to 1e-10), the
 stencil roofline (HIP events inside the library), the plain FP64 solver one
 solve at a time, serving latency percentiles, and the FP64 CPU oracle on a
@@ -66,7 +71,7 @@ def counter_traffic(mode_key):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=16, help="level-1 update rounds (16 = n1 updates of every slab)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--dims", default="64,32,32,32", help="T,L1,L2,L3 (T a multiple of 16)")
     ap.add_argument("--no-fp64", action="store_true")
@@ -206,7 +211,8 @@ def main():
         for r in range(12):
             b[r, idx, r // 3, r % 3] = 1.0
         srcs.append(b)
-        terms.append(torch.zeros((3, 12, V, 4, 3), dtype=torch.complex128, device=dev))
+        # two rounds in flight: ring of two series outputs per slab
+        terms.append([torch.zeros((3, 12, V, 4, 3), dtype=torch.complex128, device=dev) for _ in range(2)])
     torch.cuda.synchronize()
 
     ctx = ddml.Context(L, ddml.BC_ANTIPERIODIC, device=0)
@@ -239,24 +245,78 @@ def main():
         gids = advance(prev, j) if update else prev
         if update:
             release(prev)   # the previous round's versions and their operator data
+        buf = [terms[s][0] for s in range(nslab)]
         if batched:
             rc, infos = ctx.propagator_series_batch(
-                [(gids[s], doms[s], srcs[s], terms[s], None) for s in range(nslab)], 12, prm)
+                [(gids[s], doms[s], srcs[s], buf[s], None) for s in range(nslab)], 12, prm)
         else:
             infos = []
             rc = ddml.OK
             for s in range(nslab):
                 per = []
                 for lev in range(3):
-                    r, inf = ctx.solve_domain(gids[s], doms[s][lev], srcs[s], terms[s][lev], 12, prm)
+                    r, inf = ctx.solve_domain(gids[s], doms[s][lev], srcs[s], buf[s][lev], 12, prm)
                     rc = rc or r
                     per.append(inf)
                 infos.append(per)
-        nuc = [ctx.contract_nucleon(terms[s], 3) for s in range(nslab)]
-        pp = [ctx.contract_pp_disconnected(terms[s], terms[(s + 2) % nslab], 3, xs[s], xs[(s + 2) % nslab])
+        nuc, pp = contract(buf)
+        return gids, rc, infos, nuc, pp
+
+    def contract(buf):
+        nuc = [ctx.contract_nucleon(buf[s], 3) for s in range(nslab)]
+        pp = [ctx.contract_pp_disconnected(buf[s], buf[(s + 2) % nslab], 3, xs[s], xs[(s + 2) % nslab])
               for s in range(nslab // 2)]
-        tr = [ctx.trace_g5(terms[s], 3, xs[s]) for s in range(nslab)]   # factors of the two-level estimator
-        return gids, rc, infos, nuc, (pp, tr)
+        tr = [ctx.trace_g5(buf[s], 3, xs[s]) for s in range(nslab)]   # factors of the two-level estimator
+        return nuc, (pp, tr)
+
+    def queue_rounds(chain, j0, n, prm):
+        """Rounds j0 .. j0+n-1 as one continuous queue through the request loop.
+        Round j draws the 4 slab updates on the device and submits their 4
+        series (12 solves) into ring position j % 2; before that, round j - 2
+        (the previous user of the position) is waited for, contracted and its
+        gauge versions released.  Returns the last round's gauge versions, the
+        per-round [slab][level][column] solve details and the contractions."""
+        live = {}
+        infos, meas, nucs = [], [], []
+
+        def finish(r):
+            gids, tks, inf = live.pop(r)
+            for t in tks:
+                res = ctx.wait(t, 1200.0)
+                assert res is not None and res.status == ddml.OK, "series failed: %s" % (
+                    None if res is None else ddml.STATUS_NAMES.get(res.status, res.status))
+            nuc, pp = contract([terms[s][r % 2] for s in range(nslab)])
+            nucs.append(nuc)
+            meas.append(pp)
+            infos.append([[list(inf[s][12 * lev:12 * (lev + 1)]) for lev in range(3)] for s in range(nslab)])
+            return gids
+
+        ctx.server_start(prm, max_queue=1000)
+        try:
+            older = []
+            for j in range(j0, j0 + n):
+                if j - 2 in live:
+                    older.append(finish(j - 2))
+                gids = advance(chain, j)
+                tks, inf = [], []
+                for s in range(nslab):
+                    ia = (ddml.RhsInfo * 36)()
+                    tks.append(ctx.submit_series(gids[s], doms[s], srcs[s], terms[s][j % 2], 12, info=ia))
+                    inf.append(ia)
+                live[j] = (gids, tks, inf)
+                if j == j0:
+                    older.append(chain)   # the chain heads this call started from
+                chain = gids
+                for g in older:
+                    release(g)   # versions of finished rounds that no chain continues from
+                older = []
+            for r in sorted(live):
+                g = finish(r)
+                if g is not chain:
+                    release(g)
+        finally:
+            ctx.server_stop()
+        return chain, infos, nucs, meas
 
     # device level-1 generator on its own: one round of the 4 slab updates
     chain = [gid0] * nslab
@@ -272,23 +332,21 @@ def main():
     log("level-1 update: %.2f ms per 16-slice slab (%.3g links/s)" % (l1_ms, level1["links_per_s"]))
 
     # ------------------------------------------------------------ timed
-    for j in range(args.warmup):
-        chain, rc, infos, _, _ = step(chain, j)
-        log("warmup step %d rc %d" % (j, rc))
+    if args.warmup:
+        chain, _, _, _ = queue_rounds(chain, 0, args.warmup, params)   # graph capture, allocator warm-up
+        log("warmup: %d rounds" % args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    iters, worst = [], 0.0
-    meas = []   # per timed round: (pp pieces, traces)
-    for j in range(args.warmup, nsteps):
-        chain, rc, infos, nuc, pp = step(chain, j)
-        meas.append(pp)
-        assert rc == ddml.OK, "solve failed: %s" % ctx.last_error()
-        for per_slab in infos:
-            for per_level in per_slab:
-                iters.append(max(i.inner_iters for i in per_level))
-                worst = max(worst, max(i.true_rel_residual for i in per_level))
+    chain, rinfos, _, meas = queue_rounds(chain, args.warmup, args.steps, params)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    iters, outers, worst = [], [], 0.0
+    for per_round in rinfos:
+        for per_slab in per_round:
+            for per_level in per_slab:
+                iters.append(max(i.inner_iters for i in per_level))
+                outers.append(max(i.outer_iters for i in per_level))
+                worst = max(worst, max(i.true_rel_residual for i in per_level))
     nsolves = 3 * nslab * args.steps
     solves_per_s = nsolves / (t1 - t0)
     ms_per_step = 1e3 * (t1 - t0) / args.steps
@@ -304,21 +362,20 @@ def main():
         tune16 = ctx.autotune(gid0, doms[0][2], 12, ddml.MIXED_FP16)
         prm16 = ddml.solver_params(tol=1e-10, prec=ddml.MIXED_FP16)
         chain16 = [gid0] * nslab   # the same chains again, solved with 16-bit storage
-        for j in range(args.warmup):
-            chain16, rc, _, _, _ = step(chain16, j, prm16)   # warm-up (graph capture)
+        if args.warmup:
+            chain16, _, _, _ = queue_rounds(chain16, 0, args.warmup, prm16)   # warm-up (graph capture)
         torch.cuda.synchronize()
         a = time.perf_counter()
+        chain16, rinf16, _, _ = queue_rounds(chain16, args.warmup, args.steps, prm16)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
         it16, outer16, worst16 = [], [], 0.0
-        for j in range(args.warmup, nsteps):
-            chain16, rc, infos, _, _ = step(chain16, j, prm16)
-            assert rc == ddml.OK, "16-bit solve failed: %s" % ctx.last_error()
-            for per_slab in infos:
+        for per_round in rinf16:
+            for per_slab in per_round:
                 for per_level in per_slab:
                     it16.append(max(i.inner_iters for i in per_level))
                     outer16.append(max(i.outer_iters for i in per_level))
                     worst16 = max(worst16, max(i.true_rel_residual for i in per_level))
-        torch.cuda.synchronize()
-        b = time.perf_counter()
         release(chain16)
         s16 = ctx.time_stencil(gid0, doms[0][2], 12, ddml.MIXED_FP16, args.stencil_iters)
         fp16 = {"solves_per_s": nsolves / (b - a), "ms_per_step": 1e3 * (b - a) / args.steps,
@@ -406,9 +463,11 @@ def main():
         "dtype": "fp32 inner / fp64 outer",
         "data": "synthetic: seeded beta=6.0 quenched heatbath fields and level-1 slab updates",
         "base_field": {"plaquette": plaq0, "full_volume_sweeps": args.decorrelate},
-        "config": {"workload": "batched multi-level, %s lattice, %d slabs x 1 update per step, "
-                               "Gamma0/1/2 = 4/8/16 slices x 12 rhs, tol 1e-10" % ("x".join(map(str, L)), nslab),
-                   "lattice": list(L), "kappa": kappa, "csw": csw, "solves_per_step": 3 * nslab, "nrhs": 12},
+        "config": {"workload": "batched multi-level, %s lattice, %d slabs x %d updates as one continuous queue "
+                               "(device-side outer loop), Gamma0/1/2 = 4/8/16 slices x 12 rhs, tol 1e-10"
+                               % ("x".join(map(str, L)), nslab, args.steps),
+                   "lattice": list(L), "kappa": kappa, "csw": csw, "solves_per_step": 3 * nslab, "nrhs": 12,
+                   "solves": nsolves},
         "roofline": {"bound": "hbm", "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                      "frac": ach / PEAK_HBM, "traffic": traffic,
                      "kernel": "k_hop_batch<float2> M-hat pair (odd half A^-1 H, then even half Schur + fused "
@@ -428,6 +487,7 @@ def main():
         "stochastic_traces": hpe,
         "projected_pion": proj,
         "inner_iters_per_solve": iters,
+        "outer_iters_per_solve": outers,
         "worst_true_rel_residual": worst,
         "level1_update": level1,
         "two_level_pp": two_level,

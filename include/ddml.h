@@ -497,13 +497,13 @@ int ddml_time_stencil(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec
  * nrhs, prec) and makes the fastest the context's choice for every later solve
  * (the captured solver graphs are rebuilt).  best[0..5] = R, order, grid,
  * splits, stage, ms per odd+even pair.
- * Errors: EINVAL, ENOMEM, EDEVICE. */
+ * Errors: EINVAL (also while the request loop runs), ENOMEM, EDEVICE. */
 int ddml_autotune(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec, double best[6]);
 
 /* Sets the stencil launch of precision prec by hand (same meaning as the
  * arguments of ddml_time_stencil; grid >= 8; 16-bit storage needs stage 1).
  * Every launch choice computes the same bits.
- * Errors: EINVAL. */
+ * Errors: EINVAL (also while the request loop runs). */
 int ddml_set_launch(ddml_ctx ctx, int prec, int R, int order, int grid, int splits, int stage);
 
 /* ------------------------------------------------------------- serving */
@@ -541,6 +541,28 @@ int ddml_server_start(ddml_ctx ctx, const ddml_solver_params* params, int max_qu
  * lattice inside one device allocation finishes with status EINVAL at
  * admission, before any kernel touches them. */
 int ddml_submit(ddml_ctx ctx, const ddml_request* req, uint64_t* ticket);
+/* A propagator series as one request (eq. Dseries, as ddml_propagator_series):
+ * one domain solve per nested domain, admitted level by level as they fit;
+ * when the last one has finished, terms[0] = S^(0), terms[i] = S^(i) -
+ * S^(i-1) and sum = S^(nlevels-1).  The result aggregates every level and
+ * column; info, if not NULL, receives the per-level, per-column details
+ * before the request completes. */
+typedef struct {
+  int gauge_id;
+  const int* dom_ids;   /* [nlevels], nested; copied at submit */
+  int nlevels;          /* 1..64 */
+  const double* src;    /* device [nrhs][V][4][3], valid until completion */
+  double* terms;        /* device [nlevels][nrhs][V][4][3], written on completion */
+  double* sum;          /* device [nrhs][V][4][3] or NULL */
+  int nrhs;
+  double arrival_time;  /* caller's clock (seconds), used for latency */
+  ddml_rhs_info* info;  /* host [nlevels][nrhs] or NULL */
+} ddml_series_request;
+
+/* Queue one series request.  Pointers as ddml_submit (host memory: EINVAL
+ * here; extents and domains are checked at admission, where a failure ends
+ * the request with EINVAL before any kernel touches its buffers). */
+int ddml_submit_series(ddml_ctx ctx, const ddml_series_request* req, uint64_t* ticket);
 /* EAGAIN while pending; DDML_OK and *res once finished (the result is kept). */
 int ddml_poll(ddml_ctx ctx, uint64_t ticket, ddml_result* res);
 int ddml_wait(ddml_ctx ctx, uint64_t ticket, ddml_result* res, double timeout_s);

@@ -39,7 +39,11 @@ struct StreamJoin {
 template <typename F>
 int guarded(ddml_ctx ctx, F&& f) {
   if (!ctx) return DDML_EINVAL;
-  std::lock_guard<std::recursive_mutex> lk(ctx->c.mu);
+  // announce the call, so that the request loop lets it take the context
+  // lock between its rounds (std::mutex promises no fairness)
+  ctx->c.api_waiting.fetch_add(1);
+  std::unique_lock<std::recursive_mutex> lk(ctx->c.mu);
+  ctx->c.api_waiting.fetch_sub(1);
   try {
     DDML_HIP(hipSetDevice(ctx->c.device));
     int rc = f(&ctx->c);
@@ -337,22 +341,7 @@ static int series_many(Ctx* c, int ns, const ddml_series_desc* sd, int nrhs, con
   int rc = solve_many(c, (int)d.size(), d.data(), params, 1, c->stream);
   for (int k = 0; k < ns; ++k) {
     const size_t bytes = per[k] * sizeof(double2);
-    // the solutions vanish outside their domains: difference only the time
-    // slices the union of the series' domains covers (whole column ranges)
-    const GaugeRec& g = gauge_get(c, sd[k].gauge_id);
-    int t0 = g.lat.dims[0], t1 = 0;
-    for (int i = 0; i < sd[k].nlevels; ++i) {
-      const DomainRec& dr = sd[k].dom_ids[i] == -1 ? DomainRec{{0, 0, 0, 0}, {g.lat.dims[0], 0, 0, 0}}
-                                                  : domain_get(c, sd[k].dom_ids[i]);
-      t0 = std::min(t0, dr.lo[0]);
-      t1 = std::max(t1, std::min(dr.hi[0], g.lat.dims[0]));
-    }
-    const size_t row = g.V / g.lat.dims[0] * 12;   // complex numbers of one time slice of one column
-    double2* sum = sd[k].sum ? reinterpret_cast<double2*>(ss[k].ptr) : nullptr;
-    if (sum && (t0 > 0 || t1 < g.lat.dims[0])) DDML_HIP(hipMemsetAsync(sum, 0, bytes, c->stream));
-    if (t1 > t0)
-      DDML_HIP(launch_series_diff(reinterpret_cast<double2*>(st[k].ptr), per[k], sd[k].nlevels, sum, c->stream,
-                                  nrhs, g.V * 12, (size_t)t0 * row, (size_t)(t1 - t0) * row));
+    series_terms(c, sd[k].gauge_id, sd[k].dom_ids, sd[k].nlevels, st[k].ptr, sd[k].sum ? ss[k].ptr : nullptr, nrhs);
     copy_back(c, sd[k].terms, st[k], bytes * sd[k].nlevels, on_device);
     if (sd[k].sum) copy_back(c, sd[k].sum, ss[k], bytes, on_device);
   }
@@ -745,6 +734,7 @@ int ddml_time_stencil(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec
   return guarded(ctx, [&](Ctx* c) {
     need(out != nullptr, "out is NULL");
     need(prec == DDML_FP64 || prec == DDML_MIXED_FP32 || prec == DDML_MIXED_FP16, "unknown precision");
+    need(!c->server, "the solver graphs are rebuilt: stop the request loop first");
     TuneChoice w;
     w.R = R;
     w.order = order;
@@ -774,6 +764,7 @@ int ddml_autotune(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec, do
   return guarded(ctx, [&](Ctx* c) {
     need(best != nullptr, "best is NULL");
     need(prec == DDML_FP64 || prec == DDML_MIXED_FP32 || prec == DDML_MIXED_FP16, "unknown precision");
+    need(!c->server, "the solver graphs are rebuilt: stop the request loop first");
     autotune(c, gauge_id, dom_id, nrhs, prec, best);
     return DDML_OK;
   });
@@ -891,6 +882,16 @@ int ddml_submit(ddml_ctx ctx, const ddml_request* req, uint64_t* ticket) {
   if (!device_span_ok(req->src, 0, ctx->c.device) || !device_span_ok(req->sol, 0, ctx->c.device))
     return DDML_EINVAL;
   return ctx->c.server->submit(*req, ticket);
+}
+
+int ddml_submit_series(ddml_ctx ctx, const ddml_series_request* req, uint64_t* ticket) {
+  if (!ctx || !req || !ticket || !ctx->c.server) return DDML_EINVAL;
+  if (req->nrhs < 1 || req->nrhs > kMaxRhs || !req->src || !req->terms || !req->dom_ids) return DDML_EINVAL;
+  if (req->nlevels < 1 || req->nlevels > 64) return DDML_EINVAL;
+  if (!device_span_ok(req->src, 0, ctx->c.device) || !device_span_ok(req->terms, 0, ctx->c.device) ||
+      (req->sum && !device_span_ok(req->sum, 0, ctx->c.device)))
+    return DDML_EINVAL;
+  return ctx->c.server->submit_series(*req, ticket);
 }
 
 int ddml_poll(ddml_ctx ctx, uint64_t ticket, ddml_result* res) {

@@ -1081,6 +1081,9 @@ void BatchRunner<T2>::replay() {
 template <typename T2>
 void BatchRunner<T2>::launch_dev() {
   hipStream_t st = ctx->stream;
+  // this ring position's pinned buffers are reused below: its readback must
+  // have been taken (two launches in a row, e.g. from two callers)
+  if (pending[ring]) collect_dev();   // collects position `ring`
   if (dirty) upload();
   DDML_HIP(hipGraphLaunch(exec, st));
   const int n = std::max(nused, 1);
@@ -1477,6 +1480,26 @@ static void host_progress(Ctx* c, std::vector<Solve*>& live) {
   step(c->run32, float2{});
   step(c->run64, double2{});
   step(c->run16, h16c{});
+}
+
+void series_terms(Ctx* c, int gauge_id, const int* dom_ids, int nlevels, double* terms, double* sum, int nrhs) {
+  const GaugeRec& g = gauge_get(c, gauge_id);
+  const size_t per = (size_t)nrhs * g.V * 12;   // complex numbers of one level
+  // the solutions vanish outside their domains: difference only the time
+  // slices the union of the series' domains covers (whole column ranges)
+  int t0 = g.lat.dims[0], t1 = 0;
+  for (int i = 0; i < nlevels; ++i) {
+    const DomainRec& dr = dom_ids[i] == -1 ? DomainRec{{0, 0, 0, 0}, {g.lat.dims[0], 0, 0, 0}}
+                                           : domain_get(c, dom_ids[i]);
+    t0 = std::min(t0, dr.lo[0]);
+    t1 = std::max(t1, std::min(dr.hi[0], g.lat.dims[0]));
+  }
+  const size_t row = g.V / g.lat.dims[0] * 12;   // complex numbers of one time slice of one column
+  double2* s2 = reinterpret_cast<double2*>(sum);
+  if (s2 && (t0 > 0 || t1 < g.lat.dims[0])) DDML_HIP(hipMemsetAsync(s2, 0, per * sizeof(double2), c->stream));
+  if (t1 > t0)
+    DDML_HIP(launch_series_diff(reinterpret_cast<double2*>(terms), per, nlevels, s2, c->stream, nrhs, g.V * 12,
+                                (size_t)t0 * row, (size_t)(t1 - t0) * row));
 }
 
 void solve_finish(Ctx* c, Solve* s) {

@@ -217,6 +217,7 @@ struct Ctx {
   hipStream_t stream = nullptr;
   std::unique_ptr<DevPool> pool;
   std::recursive_mutex mu;
+  std::atomic<int> api_waiting{0};   // API calls waiting for mu (the request loop yields to them)
   std::string last_error;
   int next_gauge = 1, next_dom = 1;
   std::map<int, GaugeRec> gauges;
@@ -282,6 +283,10 @@ bool solve_slot_free(Ctx* c, int prec, int nrhs, const ddml_solver_params& prm);
 bool solve_join(Ctx* c, Solve* s);
 void solve_finish(Ctx* c, Solve* s);                 // scatter, info, free
 void solve_release(Solve* s);                        // free device state (after a failed prepare)
+// eq. Dseries in place: terms[0..nlevels) hold S^(0..nlevels-1) (canonical
+// device fields, nrhs columns each) and become S^(0), S^(1) - S^(0), ...;
+// sum (device, or null) receives S^(nlevels-1).  On the context's stream.
+void series_terms(Ctx* c, int gauge_id, const int* dom_ids, int nlevels, double* terms, double* sum, int nrhs);
 void check_params(const ddml_solver_params* p);
 // Times the two stencil kernels of the inner solver (k_hop_batch, CINV_HOP and
 // SCHUR with its fused dot product) on one slot; out = {ms_cinv, ms_schur,

@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <set>
 
 #include "engine.hpp"
 #include "server.hpp"
@@ -40,21 +41,43 @@ Server::~Server() {
   if (th.joinable()) th.join();
 }
 
-int Server::submit(const ddml_request& r, uint64_t* ticket) {
+int Server::enqueue(std::unique_ptr<Req> q, uint64_t* ticket) {
   std::lock_guard<std::mutex> lk(m);
   if ((int)(incoming.size() + waiting_count) >= max_queue) return DDML_EAGAIN;
-  auto q = std::make_unique<Req>();
-  q->r = r;
   q->ticket = next_ticket++;
   q->res.status = DDML_EAGAIN;
-  q->res.arrival_time = r.arrival_time;
+  q->res.arrival_time = q->r.arrival_time;
+  q->left = q->levels();
+  q->solves.resize(q->levels());
+  q->info.assign((size_t)q->levels() * q->r.nrhs, ddml_rhs_info{});
   *ticket = q->ticket;
   incoming.push_back(q.get());
+  first_arrival = std::min(first_arrival, q->r.arrival_time);
   reqs[q->ticket] = std::move(q);
   submitted++;
-  first_arrival = std::min(first_arrival, r.arrival_time);
   cv.notify_all();
   return DDML_OK;
+}
+
+int Server::submit(const ddml_request& r, uint64_t* ticket) {
+  auto q = std::make_unique<Req>();
+  q->r = r;
+  return enqueue(std::move(q), ticket);
+}
+
+int Server::submit_series(const ddml_series_request& r, uint64_t* ticket) {
+  auto q = std::make_unique<Req>();
+  q->r.gauge_id = r.gauge_id;
+  q->r.dom_id = r.dom_ids[0];
+  q->r.src = r.src;
+  q->r.sol = nullptr;
+  q->r.nrhs = r.nrhs;
+  q->r.arrival_time = r.arrival_time;
+  q->doms.assign(r.dom_ids, r.dom_ids + r.nlevels);
+  q->terms = r.terms;
+  q->sum = r.sum;
+  q->user_info = r.info;
+  return enqueue(std::move(q), ticket);
 }
 
 int Server::poll(uint64_t t, ddml_result* res) {
@@ -101,11 +124,31 @@ void Server::stats(ddml_server_stats* s) {
   s->hbm_budget = ctx->pool->budget();
 }
 
+// Checks a request's buffers (and, for a series, its domains) once the gauge
+// field's volume is known; throws Error{EINVAL}.
+static void check_request(Ctx* ctx, const Req* q) {
+  const size_t bytes = (size_t)q->r.nrhs * gauge_get(ctx, q->r.gauge_id).V * 12 * sizeof(double2);
+  bool ok = device_span_ok(q->r.src, bytes, ctx->device);
+  if (q->series()) {
+    for (int d : q->doms)
+      if (d != -1) (void)domain_get(ctx, d);
+    ok = ok && device_span_ok(q->terms, bytes * q->doms.size(), ctx->device);
+    if (q->sum) ok = ok && device_span_ok(q->sum, bytes, ctx->device);
+  } else {
+    ok = ok && device_span_ok(q->r.sol, bytes, ctx->device);
+  }
+  if (!ok) throw Error{DDML_EINVAL, "request buffers do not hold its canonical fields in device memory"};
+}
+
 void Server::loop() {
-  std::deque<Req*> waiting;
+  struct Unit {
+    Req* q;
+    int lev;
+  };
+  std::deque<Unit> waiting;
   std::vector<Solve*> live;
   std::map<Solve*, Req*> owner;
-  // retired requests whose solution scatter is still on the stream
+  // requests whose last solve (and series difference) is still on the stream
   std::deque<std::pair<hipEvent_t, std::vector<Req*>>> landing;
   std::vector<hipEvent_t> spare;
   for (;;) {
@@ -116,38 +159,53 @@ void Server::loop() {
         cv.wait_for(lk, std::chrono::milliseconds(2));
       }
       while (!incoming.empty()) {
-        waiting.push_back(incoming.front());
+        Req* q = incoming.front();
+        for (int l = 0; l < q->levels(); ++l) waiting.push_back(Unit{q, l});
         incoming.pop_front();
       }
       waiting_count = waiting.size();
       if (stop && live.empty() && waiting.empty() && landing.empty()) break;
     }
     if (live.empty() && waiting.empty() && landing.empty()) continue;
-    std::vector<Req*> finished;
+    std::vector<Req*> finished;   // requests that never reached the GPU
+    std::vector<Req*> retired;    // requests whose last solve finished this round
     {
+      // API calls of other threads (e.g. the sampler's gauge updates and
+      // contractions) go first; the queued replays keep the GPU busy meanwhile
+      while (ctx->api_waiting.load() > 0) std::this_thread::sleep_for(std::chrono::microseconds(20));
       std::lock_guard<std::recursive_mutex> g(ctx->mu);
-      // admission by device footprint
+      // a level that will not run: the request fails, and completes once its
+      // levels in flight have finished
+      auto drop = [&](Req* q, int code) {
+        if (q->res.status == DDML_EAGAIN) q->res.status = code;
+        if (--q->left == 0) finished.push_back(q);
+      };
+      // admission by device footprint and free slots
       while (!waiting.empty()) {
-        Req* q = waiting.front();
-        Solve* s = &q->solve;
+        const Unit u = waiting.front();
+        Req* q = u.q;
+        if (q->res.status != DDML_EAGAIN) {   // an earlier level failed
+          waiting.pop_front();
+          drop(q, q->res.status);
+          continue;
+        }
+        Solve* s = &q->solves[u.lev];
         s->gauge_id = q->r.gauge_id;
-        s->dom_id = q->r.dom_id;
+        s->dom_id = q->series() ? q->doms[u.lev] : q->r.dom_id;
         s->nrhs = q->r.nrhs;
         s->prec = prm.prec;
         s->prm = prm;
         s->src = q->r.src;
-        s->sol = q->r.sol;
-        s->info = q->info;
+        s->info = q->info.data() + (size_t)u.lev * q->r.nrhs;
         size_t fp = 0;
         try {
+          if (u.lev == 0) check_request(ctx, q);
+          const size_t per = (size_t)q->r.nrhs * gauge_get(ctx, q->r.gauge_id).V * 12 * 2;   // doubles
+          s->sol = q->series() ? q->terms + per * u.lev : q->r.sol;
           fp = solve_footprint(ctx, s->gauge_id, s->dom_id, s->nrhs, s->prm);
-          const size_t bytes = (size_t)s->nrhs * gauge_get(ctx, s->gauge_id).V * 12 * sizeof(double2);
-          if (!device_span_ok(s->src, bytes, ctx->device) || !device_span_ok(s->sol, bytes, ctx->device))
-            throw Error{DDML_EINVAL, "request buffers do not hold nrhs canonical fields in device memory"};
         } catch (const Error& e) {
-          q->res.status = e.code;
           waiting.pop_front();
-          finished.push_back(q);
+          drop(q, e.code);
           continue;
         }
         if (!live.empty() && !ctx->pool->fits_device(fp)) break;
@@ -156,30 +214,34 @@ void Server::loop() {
         try {
           solve_prepare(ctx, s);
           solve_join(ctx, s);
-          q->res.admit_time = now_s();
+          if (u.lev == 0) q->res.admit_time = now_s();
           live.push_back(s);
           owner[s] = q;
         } catch (const Error& e) {
           solve_release(s);
           if (e.code == DDML_ENOMEM && !live.empty()) {
             // memory frees up as the solves in flight finish: wait for them
-            waiting.push_front(q);
+            waiting.push_front(u);
             break;
           }
-          q->res.status = e.code;
-          finished.push_back(q);
+          drop(q, e.code);
         }
       }
       try {
         if (!live.empty()) solve_progress(ctx, live, false);
-        std::vector<Req*> retired;
         for (auto it = live.begin(); it != live.end();) {
           Solve* s = *it;
           if (s->state == 3) {
+            Req* q = owner[s];
             solve_finish(ctx, s);
-            retired.push_back(owner[s]);
             owner.erase(s);
             it = live.erase(it);
+            if (--q->left == 0) {
+              if (q->series() && q->res.status == DDML_EAGAIN)
+                series_terms(ctx, q->r.gauge_id, q->doms.data(), (int)q->doms.size(), q->terms, q->sum,
+                             q->r.nrhs);
+              retired.push_back(q);
+            }
           } else {
             ++it;
           }
@@ -194,34 +256,36 @@ void Server::loop() {
           }
           DDML_HIP(hipEventRecord(e, ctx->stream));
           landing.emplace_back(e, std::move(retired));
+          retired.clear();
         }
-        // requests whose scatter has landed (all of them once nothing is left on the GPU)
+        // requests whose results have landed (all of them once nothing is left on the GPU)
         while (!landing.empty()) {
           hipEvent_t e = landing.front().first;
-          const hipError_t q = live.empty() ? hipEventSynchronize(e) : hipEventQuery(e);
-          if (q == hipErrorNotReady) break;
-          DDML_HIP(q);
+          const hipError_t st = live.empty() ? hipEventSynchronize(e) : hipEventQuery(e);
+          if (st == hipErrorNotReady) break;
+          DDML_HIP(st);
           for (Req* r : landing.front().second) finished.push_back(r);
           spare.push_back(e);
           landing.pop_front();
         }
       } catch (const Error& e) {
         // a device error ends every request in flight
-        for (Solve* s : live) {
-          Req* q = owner[s];
-          q->res.status = e.code;
-          finished.push_back(q);
+        std::set<Req*> hit;
+        for (Solve* s : live) hit.insert(owner[s]);
+        for (Req* r : retired) hit.insert(r);
+        for (auto& l : landing) {
+          spare.push_back(l.first);
+          for (Req* r : l.second) hit.insert(r);
         }
         live.clear();
         owner.clear();
-        for (auto& l : landing) {
-          spare.push_back(l.first);
-          for (Req* r : l.second) {
-            r->res.status = e.code;
-            finished.push_back(r);
-          }
-        }
         landing.clear();
+        for (Req* r : hit) {
+          r->res.status = e.code;
+          r->left = 0;
+          finished.push_back(r);
+        }
+        // levels of those requests still waiting are dropped when reached
       }
     }
     const double t = now_s();
@@ -234,8 +298,7 @@ void Server::loop() {
         if (r.status == DDML_EAGAIN) {
           int st = DDML_OK, mo = 0, mi = 0;
           double worst = 0;
-          for (int col = 0; col < q->r.nrhs; ++col) {
-            const ddml_rhs_info& in = q->info[col];
+          for (const ddml_rhs_info& in : q->info) {
             if (in.status != DDML_OK && st == DDML_OK) st = in.status;
             mo = std::max(mo, in.outer_iters);
             mi = std::max(mi, in.inner_iters);
@@ -246,6 +309,7 @@ void Server::loop() {
           r.max_inner_iters = mi;
           r.worst_rel_residual = worst;
         }
+        if (q->user_info) std::copy(q->info.begin(), q->info.end(), q->user_info);
         r.finish_time = t;
         q->done = true;
         completed++;

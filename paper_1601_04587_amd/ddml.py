@@ -52,6 +52,12 @@ class Request(ctypes.Structure):
                 ("sol", ctypes.c_void_p), ("nrhs", ctypes.c_int), ("arrival_time", ctypes.c_double)]
 
 
+class SeriesRequest(ctypes.Structure):
+    _fields_ = [("gauge_id", ctypes.c_int), ("dom_ids", ctypes.POINTER(ctypes.c_int)), ("nlevels", ctypes.c_int),
+                ("src", ctypes.c_void_p), ("terms", ctypes.c_void_p), ("sum", ctypes.c_void_p),
+                ("nrhs", ctypes.c_int), ("arrival_time", ctypes.c_double), ("info", ctypes.POINTER(RhsInfo))]
+
+
 class Result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("max_outer", ctypes.c_int), ("max_inner_iters", ctypes.c_int),
                 ("worst_rel_residual", ctypes.c_double), ("arrival_time", ctypes.c_double),
@@ -72,7 +78,7 @@ EXPORTS = ["ddml_create", "ddml_destroy", "ddml_last_error", "ddml_set_gauge", "
            "ddml_contract_nucleon_noalloc",
            "ddml_apply_boundary", "ddml_factorized_series", "ddml_factorized_chain", "ddml_contract_pion", "ddml_hpe_trace",
            "ddml_inverse_iteration", "ddml_projected_pion", "ddml_projected_nucleon", "ddml_two_level_average", "ddml_trace_g5",
-           "ddml_server_start", "ddml_submit", "ddml_poll", "ddml_wait", "ddml_stats", "ddml_server_stop",
+           "ddml_server_start", "ddml_submit", "ddml_submit_series", "ddml_poll", "ddml_wait", "ddml_stats", "ddml_server_stop",
            "ddml_now"]
 
 _lib = None
@@ -129,6 +135,7 @@ def load():
                                    ctypes.POINTER(RhsInfo), I, P]
     lib.ddml_server_start.argtypes = [P, ctypes.POINTER(SolverParams), I]
     lib.ddml_submit.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+    lib.ddml_submit_series.argtypes = [P, ctypes.POINTER(SeriesRequest), ctypes.POINTER(ctypes.c_uint64)]
     lib.ddml_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Result)]
     lib.ddml_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(Result), D]
     lib.ddml_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
@@ -541,6 +548,30 @@ class Context:
         req = Request(gid, dom, ps, pd, nrhs, t)
         ticket = ctypes.c_uint64()
         rc = self.lib.ddml_submit(self.h, ctypes.byref(req), ctypes.byref(ticket))
+        self._check(rc)
+        return ticket.value
+
+    def submit_series(self, gid, doms, src, terms, nrhs, sum=None, info=None, arrival_time=None):
+        """Queue a propagator series over the nested domains `doms` (eq. Dseries);
+        src, terms ([levels][nrhs][V][4][3]) and sum are contiguous device tensors
+        on the context's device, info an optional (RhsInfo * levels*nrhs) array
+        filled before completion."""
+        for name, a in (("src", src), ("terms", terms), ("sum", sum)):
+            if a is None and name == "sum":
+                continue
+            if not (hasattr(a, "is_cuda") and a.is_cuda and a.is_contiguous()):
+                raise ValueError("%s must be a contiguous device tensor" % name)
+            if a.device.index != self.device:
+                raise ValueError("%s is on device %s, the context on %d" % (name, a.device, self.device))
+        ids = (ctypes.c_int * len(doms))(*doms)
+        ps, _ = _ptr(src)
+        pt, _ = _ptr(terms)
+        pm = _ptr(sum)[0] if sum is not None else None
+        t = now() if arrival_time is None else arrival_time
+        inf = ctypes.cast(info, ctypes.POINTER(RhsInfo)) if info is not None else None
+        req = SeriesRequest(gid, ids, len(doms), ps, pt, pm, nrhs, t, inf)
+        ticket = ctypes.c_uint64()
+        rc = self.lib.ddml_submit_series(self.h, ctypes.byref(req), ctypes.byref(ticket))
         self._check(rc)
         return ticket.value
 

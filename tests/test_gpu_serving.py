@@ -122,6 +122,51 @@ def test_series_batch_matches_single_series(setup):
         assert oracle.residual(U, L, 0.1340, b2, cum[i], C=C, lo=lo, hi=hi).max() <= 1e-10 * (1 + 1e-3)
 
 
+def test_series_requests_match_series_call_bitwise(setup):
+    """Propagator series submitted to the request loop (one solve per nested
+    domain, differences on completion) give the bits of ddml_propagator_series,
+    also when several series and single solves overlap on the device; a series
+    naming an unknown domain finishes with EINVAL and leaves its buffers alone."""
+    L, U, ctx, gid, doms, ids = setup
+    dev = torch.device("cuda:0")
+    V = int(np.prod(L))
+    order = [ids["G0"], ids["G1"], ids["G2"]]
+    b = [inputs.point_source(L, (7, k, 1, 0)) for k in range(3)]
+    ref = []
+    for k in range(3):
+        t = np.zeros((3, 12, V, 4, 3), dtype=np.complex128)
+        sm = np.zeros((12, V, 4, 3), dtype=np.complex128)
+        rc, _ = ctx.propagator_series(gid, order, b[k], 12, t, sm)
+        assert rc == ddml.OK
+        ref.append((t, sm))
+    srcs = [torch.from_numpy(x).to(dev) for x in b]
+    terms = [torch.zeros((3, 12, V, 4, 3), dtype=torch.complex128, device=dev) for _ in range(3)]
+    sums = [torch.zeros((12, V, 4, 3), dtype=torch.complex128, device=dev) for _ in range(3)]
+    single = torch.zeros((12, V, 4, 3), dtype=torch.complex128, device=dev)
+    bad = torch.full((3, 12, V, 4, 3), 7.0, dtype=torch.complex128, device=dev)
+    infos = [(ddml.RhsInfo * 36)() for _ in range(3)]
+    torch.cuda.synchronize()
+    ctx.server_start(ddml.solver_params(tol=1e-10))
+    try:
+        tk = [ctx.submit_series(gid, order, srcs[0], terms[0], 12, sum=sums[0], info=infos[0]),
+              ctx.submit(gid, ids["G2"], srcs[2], single, 12),
+              ctx.submit_series(gid, order, srcs[1], terms[1], 12, sum=sums[1], info=infos[1]),
+              ctx.submit_series(gid, [ids["G0"], 999], srcs[1], bad, 12),
+              ctx.submit_series(gid, order, srcs[2], terms[2], 12, sum=sums[2], info=infos[2])]
+        res = [ctx.wait(x, 300.0) for x in tk]
+    finally:
+        ctx.server_stop()
+    torch.cuda.synchronize()
+    assert [r is not None for r in res] == [True] * 5
+    assert [r.status for r in res] == [ddml.OK, ddml.OK, ddml.OK, ddml.EINVAL, ddml.OK]
+    for k, j in ((0, 0), (1, 2), (2, 4)):
+        assert np.array_equal(terms[k].cpu().numpy(), ref[k][0]), k
+        assert np.array_equal(sums[k].cpu().numpy(), ref[k][1]), k
+        assert res[j].max_outer == max(i.outer_iters for i in infos[k]) >= 1
+        assert res[j].worst_rel_residual == max(i.true_rel_residual for i in infos[k]) <= 1e-10
+    assert bool(torch.all(bad == 7.0))
+
+
 @pytest.mark.parametrize("solver", [0, 1])
 def test_mixed_solver_iterations_close_to_fp64(setup, solver):
     """Mixed precision (restarted or with reliable updates) converges in about
