@@ -94,7 +94,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--stencil-iters", type=int, default=20)
     ap.add_argument("--sweep-iters", type=int, default=2, help="timed pairs per launch variant (--stencil-only)")
-    ap.add_argument("--decorrelate", type=int, default=4,
+    ap.add_argument("--decorrelate", type=int, default=50,
                     help="full-volume sweeps (1 heatbath + 4 over-relaxation) of the base field after replicating "
                          "a thermalised 16x8^3 field")
     ap.add_argument("--stencil-only", action="store_true",

@@ -734,7 +734,6 @@ int ddml_time_stencil(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec
   return guarded(ctx, [&](Ctx* c) {
     need(out != nullptr, "out is NULL");
     need(prec == DDML_FP64 || prec == DDML_MIXED_FP32 || prec == DDML_MIXED_FP16, "unknown precision");
-    need(!c->server, "the solver graphs are rebuilt: stop the request loop first");
     TuneChoice w;
     w.R = R;
     w.order = order;
@@ -749,6 +748,7 @@ int ddml_time_stencil(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec
 int ddml_set_launch(ddml_ctx ctx, int prec, int R, int order, int grid, int splits, int stage) {
   return guarded(ctx, [&](Ctx* c) {
     need(prec == DDML_FP64 || prec == DDML_MIXED_FP32 || prec == DDML_MIXED_FP16, "unknown precision");
+    need(!c->server, "the solver graphs are rebuilt: stop the request loop first");
     TuneChoice w;
     w.R = R;
     w.order = order;

@@ -241,3 +241,62 @@ def test_bench_size_projected_properties():
         assert np.abs(Gm - np.conj(Gm.transpose(0, 2, 1))).max() <= 1e-12 * np.abs(Gm).max()
         assert min(np.linalg.eigvalsh(g).min() for g in Gm[a:b]) > -1e-10 * np.abs(Gm).max()
     print("32^3x64 projected pion C(y0, x0=4) at y0 = 32, 40, 48:", Cg[[32, 40, 48], 4])
+
+
+@pytest.mark.slow
+def test_bench_size_projector_at_120_vectors():
+    """The paper's projector size: 32^3x64 with open time boundaries, N = 120
+    basis vectors (2 inverse iterations on Omega* = [16, 32) keep the test
+    short; the bench leg runs 10).  Properties that hold at any size: the basis
+    is orthonormal; the pion from the nucleon's solves equals the projected-pion
+    entry point's bit for bit, and equals -Tr(Gt(y0) G(x0)) / L^3 from its
+    per-slice Gram matrices, which are Hermitian, positive semi-definite and
+    vanish outside their domains; the nucleon vanishes outside
+    y0 in Gamma*, x0 in Gammabar and is finite.  The two [T][N^2][4N] blocks
+    (7.1 GB each) are allocated and contracted at full size."""
+    L = (64, 32, 32, 32)
+    V = int(np.prod(L))
+    U = inputs.quenched_field(L, 1601004)
+    dev = torch.device("cuda:0")
+    n = 120
+    # the library's budget is taken from the free memory when the context is
+    # created: before the 2 x 48 GB of vectors the caller holds here
+    ctx = ddml.Context(L, ddml.BC_OPEN)
+    try:
+        gid = ctx.set_gauge(torch.from_numpy(U).to(dev), 0.1340, 1.769)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(1601803)
+        start = torch.complex(torch.randn((n, V, 4, 3), generator=gen, device=dev, dtype=torch.float64),
+                              torch.randn((n, V, 4, 3), generator=gen, device=dev, dtype=torch.float64))
+        q = torch.zeros_like(start)
+        torch.cuda.synchronize()
+        rc, _ = ctx.inverse_iteration(gid, ctx.set_domain((16, 0, 0, 0), (32,) + L[1:]), start, n, 2, q,
+                                      ddml.solver_params(tol=TOL))
+        assert rc == ddml.OK
+        del start
+        M = q.reshape(n, -1)
+        gram = (torch.conj(M) @ M.T).cpu().numpy()
+        assert np.abs(gram - np.eye(n)).max() < 1e-12
+        del M
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        bar = ctx.set_domain((0, 0, 0, 0), (32,) + L[1:])
+        star = ctx.set_domain((24, 0, 0, 0), L)
+        rc, CN, Cpi, info = ctx.projected_nucleon(gid, bar, star, q, n, ddml.solver_params(tol=TOL), pion=True)
+        assert rc == ddml.OK and len(info) == 2 * n
+        rc, Cg, (G, Gt), _ = ctx.projected_pion(gid, bar, star, q, n, ddml.solver_params(tol=TOL), grams=True)
+        assert rc == ddml.OK
+    finally:
+        ctx.close()
+    assert np.array_equal(Cpi, Cg)
+    V3 = V // L[0]
+    ref = -np.einsum("yij,xji->yx", Gt, G).real / V3
+    assert np.abs(Cg - ref).max() <= 1e-12 * np.abs(ref).max()
+    for Gm, (a, b) in ((G, (0, 32)), (Gt, (24, 64))):
+        assert not np.delete(Gm, np.arange(a, b), axis=0).any()
+        assert np.abs(Gm - np.conj(Gm.transpose(0, 2, 1))).max() <= 1e-12 * np.abs(Gm).max()
+        assert min(np.linalg.eigvalsh(g).min() for g in Gm[a:b]) > -1e-10 * np.abs(Gm).max()
+    assert np.all(np.isfinite(CN)) and np.abs(CN[24:, :32]).max() > 0
+    assert not CN[:24].any() and not CN[:, 32:].any()
+    print("N=120 projected pion C(y0, x0=4) at y0 = 32, 40, 48:", Cg[[32, 40, 48], 4])
+    print("N=120 projected nucleon C_N(y0, x0=4) at y0 = 32, 40, 48:", CN[[32, 40, 48], 4])

@@ -153,6 +153,11 @@ def test_series_requests_match_series_call_bitwise(setup):
               ctx.submit_series(gid, order, srcs[1], terms[1], 12, sum=sums[1], info=infos[1]),
               ctx.submit_series(gid, [ids["G0"], 999], srcs[1], bad, 12),
               ctx.submit_series(gid, order, srcs[2], terms[2], 12, sum=sums[2], info=infos[2])]
+        # the solver graphs hold the loop's slots: no relaunch while it runs
+        with pytest.raises(ddml.DDMLError):
+            ctx.set_launch(ddml.MIXED_FP32, 1, 0, 1024, 1, 1)
+        with pytest.raises(ddml.DDMLError):
+            ctx.autotune(gid, ids["G0"], 12)
         res = [ctx.wait(x, 300.0) for x in tk]
     finally:
         ctx.server_stop()
