@@ -183,9 +183,10 @@ __global__ void __launch_bounds__(768) k_vec16(const SlotDesc<h16c>* __restrict_
     const size_t sx = (size_t)col * nt * kTile + i;
     const BiState& st = d.st[col];
     const unsigned hb = shadow_bits(col, i);
-    auto ld = [&](int f, float2 v[12]) { spinor_load_q(d.f[f] + base, d.nrm[f][sx], v, true); };
+    const size_t qb = qidx(nt, col, i);   // 16-bit fields (quad-packed)
+    auto ld = [&](int f, float2 v[12]) { spinor_load_q(d.f[f] + qb, d.nrm[f][sx], v, true); };
     auto stq = [&](int f, const float2 v[12], float2 dq[12]) {
-      spinor_store_q(d.f[f] + base, d.nrm[f] + sx, v, dq, true);
+      spinor_store_q(d.f[f] + qb, d.nrm[f] + sx, v, dq, true);
     };
     double2 s0 = make_double2(0, 0), s1 = make_double2(0, 0);
     float2 z[12];
@@ -776,7 +777,7 @@ __global__ void k_quant16(const double2* __restrict__ in, h16c* __restrict__ out
       v[2 * k] = make_float2((float)a.x, (float)a.y);
       v[2 * k + 1] = make_float2((float)b.x, (float)b.y);
     }
-    spinor_store_q(out + base, nrm + t, v, dq, false);
+    spinor_store_q(out + qidx(ntiles, col, i), nrm + t, v, dq, false);
   }
 }
 __global__ void k_dequant16(const h16c* __restrict__ in, const float* __restrict__ nrm, double2* __restrict__ out,
@@ -786,7 +787,7 @@ __global__ void k_dequant16(const h16c* __restrict__ in, const float* __restrict
     const int col = (int)(t / per), i = (int)(t % per);
     const size_t base = fidx(ntiles, col, 0, i);
     float2 v[12];
-    spinor_load_q(in + base, nrm[t], v, false);
+    spinor_load_q(in + qidx(ntiles, col, i), nrm[t], v, false);
 #pragma unroll
     for (int k = 0; k < 6; ++k)
       st2(out + base + 128 * k, make_double2(v[2 * k].x, v[2 * k].y), make_double2(v[2 * k + 1].x, v[2 * k + 1].y));

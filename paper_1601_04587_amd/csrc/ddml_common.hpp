@@ -178,7 +178,8 @@ __device__ __forceinline__ void st2(double2* p, double2 a, double2 b) {
   q[1] = v;
 }
 
-// 16-bit pairs: two complex numbers as 4 x int16 (8 bytes per lane).  ld2q
+// 16-bit pairs (links and clover data): two complex numbers as 4 x int16 (8
+// bytes per lane).  ld2q
 // returns the raw integers as floats; the caller applies the scale.
 typedef short s16x4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ void ld2q(const h16c* p, float2& a, float2& b) {
@@ -192,14 +193,20 @@ __device__ __forceinline__ void ld2q_nt(const h16c* p, float2& a, float2& b) {
   b = make_float2((float)v.z, (float)v.w);
 }
 __device__ __forceinline__ short q16(float v) { return (short)__float2int_rn(fminf(fmaxf(v, -kQ), kQ)); }
-// a, b already multiplied by kQ / scale
-__device__ __forceinline__ void st2q(h16c* p, float2 a, float2 b, bool nt) {
-  s16x4 v;
-  v.x = q16(a.x); v.y = q16(a.y); v.z = q16(b.x); v.w = q16(b.y);
-  if (nt) __builtin_nontemporal_store(v, (DDML_GLOBAL s16x4*)p);
-  else *(DDML_GLOBAL s16x4*)p = v;
+// 16-bit spinor fields are quad-packed: per (column, tile) three blocks of
+// 256 complex numbers, block k holding components 4k .. 4k+3 of the tile's 64
+// sites, 16 bytes per lane (half the load instructions of the pair layout).
+__host__ __device__ __forceinline__ size_t qidx(int ntiles, int col, int i) {
+  return (size_t)(col * ntiles + (i >> 6)) * 768 + (i & 63) * 4;
 }
-// One site-column (12 complex, pair k at base + 128 k) in 16-bit storage.
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ void ld4q(const h16c* p, float2 r[4], bool nt) {
+  const s16x8 w = nt ? __builtin_nontemporal_load((const DDML_GLOBAL s16x8*)p) : *(const DDML_GLOBAL s16x8*)p;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) r[j] = make_float2((float)w[2 * j], (float)w[2 * j + 1]);
+}
+// One site-column (12 complex, quad k at base + 256 k, base = field + qidx)
+// in 16-bit storage.
 // a product that is rounded on its own (never fused into a following add), so
 // that a dequantised value is the same number wherever it is used
 __device__ __forceinline__ float mul_rounded(float a, float b) {
@@ -209,12 +216,11 @@ __device__ __forceinline__ float mul_rounded(float a, float b) {
 __device__ __forceinline__ void spinor_load_q(const h16c* base, float nrm, float2 v[12], bool nt) {
   const float sc = nrm / kQ;
 #pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    float2 a, b;
-    if (nt) ld2q_nt(base + 128 * k, a, b);
-    else ld2q(base + 128 * k, a, b);
-    v[2 * k] = make_float2(mul_rounded(a.x, sc), mul_rounded(a.y, sc));
-    v[2 * k + 1] = make_float2(mul_rounded(b.x, sc), mul_rounded(b.y, sc));
+  for (int k = 0; k < 3; ++k) {
+    float2 r[4];
+    ld4q(base + 256 * k, r, nt);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[4 * k + j] = make_float2(mul_rounded(r[j].x, sc), mul_rounded(r[j].y, sc));
   }
 }
 // Stores v with scale max|v| (NaN if any component is not finite) and returns
@@ -230,12 +236,17 @@ __device__ __forceinline__ void spinor_store_q(h16c* base, float* nrm, const flo
   const float inv = (m > 0.f && isfinite(m)) ? kQ / m : 0.f;
   const float sc = m / kQ;
 #pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    const float2 a = make_float2(v[2 * k].x * inv, v[2 * k].y * inv);
-    const float2 b = make_float2(v[2 * k + 1].x * inv, v[2 * k + 1].y * inv);
-    st2q(base + 128 * k, a, b, nt);
-    dq[2 * k] = make_float2((float)q16(a.x) * sc, (float)q16(a.y) * sc);
-    dq[2 * k + 1] = make_float2((float)q16(b.x) * sc, (float)q16(b.y) * sc);
+  for (int k = 0; k < 3; ++k) {
+    s16x8 w;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float2 a = make_float2(v[4 * k + j].x * inv, v[4 * k + j].y * inv);
+      w[2 * j] = q16(a.x);
+      w[2 * j + 1] = q16(a.y);
+      dq[4 * k + j] = make_float2((float)w[2 * j] * sc, (float)w[2 * j + 1] * sc);
+    }
+    if (nt) __builtin_nontemporal_store(w, (DDML_GLOBAL s16x8*)(base + 256 * k));
+    else *(DDML_GLOBAL s16x8*)(base + 256 * k) = w;
   }
   *nrm = m;
 }

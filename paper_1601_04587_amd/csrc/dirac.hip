@@ -391,7 +391,7 @@ __device__ __forceinline__ void hop_sum(const BoxGeom& g, int p, int i, const E*
         if (r < nr && ((on >> r) & 1u)) {
           C psi[12], h[6], gg[6];
           if constexpr (kIs16<E>)
-            spinor_load_q(in + fidx(nt, r0 + r, 0, n), in_n[(size_t)(r0 + r) * nt * kTile + n], psi, false);
+            spinor_load_q(in + qidx(nt, r0 + r, n), in_n[(size_t)(r0 + r) * nt * kTile + n], psi, false);
           else
             spinor_load(in + fidx(nt, r0 + r, 0, n), psi);
           project(mu, fwd, psi, h);
@@ -541,10 +541,11 @@ __device__ __forceinline__ void hop_tile(const BoxGeom g, const TileArgs<E>& a, 
       const unsigned hb = shadow_bits(col, i);
       if constexpr (kIs16<E>) {
         C av[12], ra[12], o[12], w[12];
-        if (MODE != MODE_CINV_HOP) spinor_load_q(a.aux + base, a.aux_n[ns], av, true);
-        if (MODE == MODE_RES) spinor_load_q(a.red_a + base, a.red_n[ns], ra, true);
+        const size_t qb = qidx(nt, col, i);
+        if (MODE != MODE_CINV_HOP) spinor_load_q(a.aux + qb, a.aux_n[ns], av, true);
+        if (MODE == MODE_RES) spinor_load_q(a.red_a + qb, a.red_n[ns], ra, true);
         epilogue<C, MODE, ST>(cl, acc[r], av, ra, c1, c2, w);
-        spinor_store_q(a.out + base, a.out_n + ns, w, o, true);   // one scale over all 12 components
+        spinor_store_q(a.out + qb, a.out_n + ns, w, o, true);   // one scale over all 12 components
         fused_reductions<RED, 12>(hb, 0, o, av, s0, s1, s2);
       } else {
         // chiral block by block: aux in, 6x6 clover block, out, reductions
@@ -567,7 +568,7 @@ __device__ __forceinline__ void hop_tile(const BoxGeom g, const TileArgs<E>& a, 
       C z[12], zq[12];
 #pragma unroll
       for (int c = 0; c < 12; ++c) z[c] = mk<C>(0, 0);
-      if constexpr (kIs16<E>) spinor_store_q(a.out + base, a.out_n + ns, z, zq, false);
+      if constexpr (kIs16<E>) spinor_store_q(a.out + qidx(nt, col, i), a.out_n + ns, z, zq, false);
       else spinor_store(a.out + base, z);
     }
     if (RED != RED_NONE) {
