@@ -259,8 +259,13 @@ def test_bench_size_projector_at_120_vectors():
     U = inputs.quenched_field(L, 1601004)
     dev = torch.device("cuda:0")
     n = 120
-    # the library's budget is taken from the free memory when the context is
-    # created: before the 2 x 48 GB of vectors the caller holds here
+    # this test needs most of the device: give back what earlier tests left in
+    # torch's cache; the library's budget is taken from the free memory when
+    # the context is created, before the 2 x 48 GB of vectors held here
+    import gc
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     ctx = ddml.Context(L, ddml.BC_OPEN)
     try:
         gid = ctx.set_gauge(torch.from_numpy(U).to(dev), 0.1340, 1.769)
