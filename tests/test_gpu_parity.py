@@ -377,6 +377,36 @@ def test_device_loop_out_of_corrections(cfg1):
         assert abs(i.true_rel_residual - res[col]) <= 1e-6 * res[col]
 
 
+def test_device_loop_failing_column_leaves_the_batch_alone(cfg1):
+    """A non-finite right-hand side column fails (ENUMERIC) in its slot while
+    its other columns and the other solves of the batch converge, with the bits
+    they have alone."""
+    L, U, C, ctx, gid, doms, ids = cfg1
+    V = int(np.prod(L))
+    b = inputs.point_source(L, (7, 2, 2, 2))
+    bad = b.copy()
+    bad[5, inputs.site_index(L, (7, 2, 2, 2)), 1, 2] = np.inf
+    prm = ddml.solver_params(tol=1e-10)
+    items = [(gid, ids["G1"], b, np.zeros((12, V, 4, 3), dtype=np.complex128), 12),
+             (gid, ids["G1"], bad, np.zeros((12, V, 4, 3), dtype=np.complex128), 12),
+             (gid, ids["G0"], b, np.zeros((12, V, 4, 3), dtype=np.complex128), 12)]
+    rc, infos = ctx.solve_batch(items, prm)
+    assert rc == ddml.ENUMERIC
+    assert infos[1][5].status == ddml.ENUMERIC
+    assert all(infos[1][c].status == ddml.OK for c in range(12) if c != 5)
+    assert all(i.status == ddml.OK for k in (0, 2) for i in infos[k])
+    for k in (0, 2):
+        g, d, src, xb, n = items[k]
+        x1 = np.zeros_like(xb)
+        ctx.solve_domain(g, d, src, x1, 12, prm)
+        assert np.array_equal(x1, xb), k
+    # the good columns of the failing solve equal the same columns solved alone
+    x1 = np.zeros_like(items[1][3])
+    ctx.solve_domain(gid, ids["G1"], b, x1, 12, prm)
+    good = [c for c in range(12) if c != 5]
+    assert np.array_equal(x1[good], items[1][3][good])
+
+
 def test_error_paths(cfg0):
     L, U, ctx, gid = cfg0
     with pytest.raises(ddml.DDMLError) as e:
