@@ -1524,6 +1524,26 @@ void solve_finish(Ctx* c, Solve* s) {
   s->state = 3;
 }
 
+// Takes a solve out of its runner's slot table (if it holds a slot) without
+// creating a runner; the next replay uploads a table without it.
+template <typename T2>
+static void leave_slot(std::map<int, std::unique_ptr<BatchRunner<T2>>>& runs, Solve* s) {
+  if (s->slot < 0) return;
+  auto it = runs.find(s->nrhs + 64 * gcr_len(s->prm));
+  if (it != runs.end() && it->second->slot_of[s->slot] == s) it->second->leave(s);
+  s->slot = -1;
+}
+
+void solve_abandon(Ctx* c, Solve* s) {
+  if (s->prec == DDML_FP64) leave_slot(c->run64, s);
+  else if (s->prec == DDML_MIXED_FP16) leave_slot(c->run16, s);
+  else leave_slot(c->run32, s);
+  // buffers go back to the pool, which keeps them allocated: a replay already
+  // queued on the stream that still names them touches valid memory
+  solve_release(s);
+  s->state = 3;
+}
+
 void solve_release(Solve* s) {
   s->be.reset(); s->bo.reset(); s->xe.reset(); s->xo.reset();
   s->re.reset(); s->ro.reset(); s->te.reset(); s->to.reset();
@@ -1709,6 +1729,7 @@ void autotune(Ctx* c, int gauge_id, int dom_id, int nrhs, int prec, double best[
 void run_solves(Ctx* c, std::vector<Solve*>& solves) {
   std::deque<Solve*> queue(solves.begin(), solves.end());
   std::vector<Solve*> live;
+  try {
   while (!queue.empty() || !live.empty()) {
     while (!queue.empty()) {
       Solve* s = queue.front();
@@ -1735,6 +1756,11 @@ void run_solves(Ctx* c, std::vector<Solve*>& solves) {
         ++it;
       }
     }
+  }
+  } catch (...) {
+    // the caller's solves are about to go away: no slot may keep naming them
+    for (Solve* s : live) solve_abandon(c, s);
+    throw;
   }
   DDML_HIP(hipStreamSynchronize(c->stream));
 }

@@ -283,6 +283,9 @@ bool solve_slot_free(Ctx* c, int prec, int nrhs, const ddml_solver_params& prm);
 bool solve_join(Ctx* c, Solve* s);
 void solve_finish(Ctx* c, Solve* s);                 // scatter, info, free
 void solve_release(Solve* s);                        // free device state (after a failed prepare)
+// a solve in flight given up after an error: its slot is freed, its device
+// state released, state -> 3 (no results)
+void solve_abandon(Ctx* c, Solve* s);
 // eq. Dseries in place: terms[0..nlevels) hold S^(0..nlevels-1) (canonical
 // device fields, nrhs columns each) and become S^(0), S^(1) - S^(0), ...;
 // sum (device, or null) receives S^(nlevels-1).  On the context's stream.

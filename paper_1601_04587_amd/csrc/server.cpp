@@ -271,7 +271,10 @@ void Server::loop() {
       } catch (const Error& e) {
         // a device error ends every request in flight
         std::set<Req*> hit;
-        for (Solve* s : live) hit.insert(owner[s]);
+        for (Solve* s : live) {
+          hit.insert(owner[s]);
+          solve_abandon(ctx, s);
+        }
         for (Req* r : retired) hit.insert(r);
         for (auto& l : landing) {
           spare.push_back(l.first);

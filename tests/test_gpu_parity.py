@@ -461,6 +461,19 @@ def test_links_outside_su3_are_refused_by_the_two_row_copies():
         with pytest.raises(ddml.DDMLError) as e:
             ctx.apply_eo(gid, -1, b, out, 12, 1)
         assert e.value.code == ddml.EINVAL
+        # refused in the middle of a batch: the solve already in a slot is given
+        # up with the call, and the context keeps solving with the same bits
+        good = ctx.set_gauge(inputs.random_links(L, 1601096), 0.12, 0.0)
+        prm = ddml.solver_params(tol=1e-10)
+        xa, xb = np.zeros_like(b), np.zeros_like(b)
+        with pytest.raises(ddml.DDMLError) as e:
+            ctx.solve_batch([(good, -1, b, xa, 12), (gid, -1, b, xb, 12)], prm)
+        assert e.value.code == ddml.EINVAL
+        x1, x2 = np.zeros_like(b), np.zeros_like(b)
+        rc, _ = ctx.solve_domain(good, -1, b, x1, 12, prm)
+        assert rc == ddml.OK
+        rc, _ = ctx.solve_batch([(good, -1, b, x2, 12), (good, -1, b, np.zeros_like(b), 12)], prm)
+        assert rc == ddml.OK and np.array_equal(x1, x2)
     finally:
         ctx.close()
 
