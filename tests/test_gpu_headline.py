@@ -6,14 +6,17 @@ sampled outputs.
 antiperiodic time; the stencil launch picked by the autotuner; each of the 4
 slabs of 16 slices updated by one level-1 sweep on the device; the nested
 domains Gamma0/1/2 = 4/8/16 slices around the source (slab start + 7) solved
-for 12 point-source columns to 1e-10 in one batch of 12 solves.  Checked:
+for 12 point-source columns to 1e-10, submitted as the benchmark does: one
+series request per slab to the library's request loop.  Checked:
 * the slab links of one update against the oracle's level-1 sweep;
 * for two slabs, every level's residual on the updated field at 4096 random
   sites of its domain and at the source (|r(x)| <= 1e-10 ||b|| per column
   must hold at every site);
 * the telescoping sum of the terms equals the returned total to rounding;
 * the nucleon contraction on three sampled sink slices and the disconnected
-  pieces of a slab pair against the oracle's, from the GPU terms (1e-11).
+  pieces of a slab pair against the oracle's, from the GPU terms (1e-11);
+* the series of two slabs through the request loop equal the same series
+  solved by ddml_propagator_series_batch, bit for bit.
 """
 import numpy as np
 import pytest
@@ -52,11 +55,19 @@ def test_one_headline_step_on_sampled_sites():
         ctx.autotune(gid0, doms[0][2], 12, ddml.MIXED_FP32)
         gids = [ctx.level1_update(gid0, 16 * s, 16 * s + 16, BETA, SEED, 3 + 1000 + s, 1, 0) for s in range(nslab)]
         totals = [torch.zeros((12, V, 4, 3), dtype=torch.complex128, device=dev) for _ in range(nslab)]
-        rc, infos = ctx.propagator_series_batch(
-            [(gids[s], doms[s], srcs[s], terms[s], totals[s]) for s in range(nslab)], 12,
-            ddml.solver_params(tol=TOL))
         torch.cuda.synchronize()
-        assert rc == ddml.OK, ctx.last_error()
+        prm = ddml.solver_params(tol=TOL)
+        arrays = [(ddml.RhsInfo * 36)() for _ in range(nslab)]
+        ctx.server_start(prm)
+        try:
+            tickets = [ctx.submit_series(gids[s], doms[s], srcs[s], terms[s], 12, sum=totals[s], info=arrays[s])
+                       for s in range(nslab)]
+            res = [ctx.wait(t, 600.0) for t in tickets]
+        finally:
+            ctx.server_stop()
+        torch.cuda.synchronize()
+        assert all(r is not None and r.status == ddml.OK for r in res), ctx.last_error()
+        infos = [[list(a[12 * lev:12 * (lev + 1)]) for lev in range(3)] for a in arrays]
         nuc = [ctx.contract_nucleon(terms[s], 3) for s in (0, 2)]
         pp = ctx.contract_pp_disconnected(terms[0], terms[2], 3, xs[0], xs[2])
         Ug = np.zeros((V, 4, 3, 3), complex)
@@ -89,6 +100,14 @@ def test_one_headline_step_on_sampled_sites():
                     ref = oracle.nucleon(psi[:, t * V3:(t + 1) * V3], (1,) + L[1:])[0]
                     assert abs(lv[lev, t] - ref) <= 1e-11 * abs(ref), (s, lev, t)
                 del psi
+        # the same two series through the batch call
+        again = [torch.zeros_like(terms[0]) for _ in range(2)]
+        rc, _ = ctx.propagator_series_batch([(gids[s], doms[s], srcs[s], again[k], None)
+                                             for k, s in enumerate((0, 2))], 12, prm)
+        torch.cuda.synchronize()
+        assert rc == ddml.OK
+        assert torch.equal(again[0], terms[0]) and torch.equal(again[1], terms[2])
+        del again
         # disconnected pieces from the terms at the two source points
         tx = terms[0][:, :, inputs.site_index(L, xs[0])].cpu().numpy()[:, :, None]
         ty = terms[2][:, :, inputs.site_index(L, xs[2])].cpu().numpy()[:, :, None]
