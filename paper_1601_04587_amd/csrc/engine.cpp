@@ -1235,7 +1235,6 @@ void solve_prepare(Ctx* c, Solve* s) {
   s->inner_iters.assign(s->nrhs, 0);
   s->status.assign(s->nrhs, DDML_OK);
   s->outer = 0;
-  s->saved.clear();
   s->state = 1;
 }
 
@@ -1294,16 +1293,16 @@ static void launch_export(Ctx* c, Solve* s) {
 }
 
 
+// Host loop (GCR(m)): joins a solve to its runner for one cycle, with the
+// per-column request flags and limits of the cycle, and initialises the cycle.
 template <typename T2>
 static bool try_join(Ctx* c, Solve* s) {
   const int m = gcr_len(s->prm);
   BatchRunner<T2>& run = runner<T2>(c, s->nrhs, m);
   const int slot = run.join(s);
   if (slot < 0) return false;
-  // per-column request flags and limits for this cycle
-  const bool relup = !s->saved.empty() && s->prm.solver == 1;
   std::vector<int> want(kMaxRhs, 0);
-  std::vector<BiState> st = relup ? s->saved : std::vector<BiState>(kMaxRhs, BiState{});
+  std::vector<BiState> st(kMaxRhs, BiState{});
   const double tol = s->prm.tol;
   for (int col = 0; col < s->nrhs; ++col) {
     want[col] = !s->done[col];
@@ -1328,19 +1327,10 @@ static bool try_join(Ctx* c, Solve* s) {
   DDML_HIP(hipMemcpyAsync(s->tstart1.p, ts, sizeof(ts), hipMemcpyHostToDevice, c->stream));
   DDML_HIP(hipMemcpyAsync(s->n1.p, &one, sizeof(int), hipMemcpyHostToDevice, c->stream));
   const int grid = std::min(d.ntiles, 4096);
-  if (m > 0) {
-    if constexpr (!std::is_same<T2, h16c>::value) {
-      DDML_HIP(launch_gcr(s->table1.as<SlotDesc<T2>>(), s->tstart1.as<int>(), s->n1.as<int>(), s->nrhs, GCR_INIT, 0,
-                          m, grid, c->stream));
-      DDML_HIP(launch_gcr_fin(s->table1.as<SlotDesc<T2>>(), s->n1.as<int>(), 1, GFIN_INIT, 0, c->stream));
-    }
-  } else {
-    DDML_HIP(launch_vec(s->table1.as<SlotDesc<T2>>(), s->tstart1.as<int>(), s->n1.as<int>(), s->nrhs,
-                        relup ? VEC_RELUP : VEC_INIT, grid, c->stream));
-    DDML_HIP(launch_fin(s->table1.as<SlotDesc<T2>>(), s->n1.as<int>(), 1, relup ? FIN_RELUP : FIN_INIT, c->stream));
-    if (relup)
-      DDML_HIP(launch_vec(s->table1.as<SlotDesc<T2>>(), s->tstart1.as<int>(), s->n1.as<int>(), s->nrhs, VEC_PFIX,
-                          grid, c->stream));
+  if constexpr (!std::is_same<T2, h16c>::value) {   // GCR(m) runs with FP32 or FP64 vectors
+    DDML_HIP(launch_gcr(s->table1.as<SlotDesc<T2>>(), s->tstart1.as<int>(), s->n1.as<int>(), s->nrhs, GCR_INIT, 0,
+                        m, grid, c->stream));
+    DDML_HIP(launch_gcr_fin(s->table1.as<SlotDesc<T2>>(), s->n1.as<int>(), 1, GFIN_INIT, 0, c->stream));
   }
   s->state = 2;
   return true;
@@ -1469,8 +1459,6 @@ static void host_progress(Ctx* c, std::vector<Solve*>& live) {
           const BiState& b = run.h_st[(size_t)slot * kMaxRhs + col];
           if (!s->done[col]) s->inner_iters[col] += b.iters;
         }
-        // keep the Krylov scalars for the reliable update of the next cycle
-        s->saved.assign(run.h_st.begin() + (size_t)slot * kMaxRhs, run.h_st.begin() + (size_t)(slot + 1) * kMaxRhs);
         run.leave(s);
         launch_export<T2>(c, s);
         s->state = 1;

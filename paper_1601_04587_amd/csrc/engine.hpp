@@ -131,8 +131,8 @@ struct Solve {
   std::vector<double> bn2, rel;
   std::vector<int> done, inner_iters, status;
   int outer = 0;
-  int state = 0;    // 0 new, 1 needs residual, 4 ready to join, 2 inner, 3 finished
-  std::vector<BiState> saved;  // Krylov scalars kept across reliable updates (empty: fresh start)
+  int state = 0;    // 0 new, 1 prepared (host loop: needs a residual), 4 ready to join (host loop),
+                    // 2 in a slot, 3 finished
   const double* src = nullptr;   // canonical device pointer
   double* sol = nullptr;         // canonical device pointer
   ddml_rhs_info* info = nullptr; // host
