@@ -56,7 +56,7 @@ def test_one_headline_step_on_sampled_sites():
         gids = [ctx.level1_update(gid0, 16 * s, 16 * s + 16, BETA, SEED, 3 + 1000 + s, 1, 0) for s in range(nslab)]
         totals = [torch.zeros((12, V, 4, 3), dtype=torch.complex128, device=dev) for _ in range(nslab)]
         torch.cuda.synchronize()
-        prm = ddml.solver_params(tol=TOL)
+        prm = ddml.solver_params(tol=TOL, solver=1)   # the benchmark's solver
         arrays = [(ddml.RhsInfo * 36)() for _ in range(nslab)]
         ctx.server_start(prm)
         try:
