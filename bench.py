@@ -579,7 +579,13 @@ def run_serving(ctx, ddml, torch, dev, gid0, L, args):
             k = kinds[int(pick[j])]
             tickets.append(ctx.submit(k["gid"], k["dom"], k["src"], k["sols"][j % 4], 12,
                                       arrival_time=t0 + arrivals[j]))
-        res = [ctx.wait(tk, 600.0) for tk in tickets]
+            if (j + 1) % 250 == 0:
+                log("serving stream at %.3g req/s: %d of %d submitted" % (rate, j + 1, n))
+        res = []
+        for j, tk in enumerate(tickets):
+            res.append(ctx.wait(tk, 600.0))
+            if (j + 1) % 250 == 0:
+                log("serving stream at %.3g req/s: %d of %d finished" % (rate, j + 1, n))
         st = ctx.stats()
         ctx.server_stop()
         ok = sum(1 for r in res if r is not None and r.status == ddml.OK)
