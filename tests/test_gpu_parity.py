@@ -1,6 +1,6 @@
 """GPU parity: libddml (HIP, gfx950) against the FP64 oracle on the same seeded inputs.
 
-Tolerances (from the arithmetic, see DESIGN.md):
+Tolerances (from the arithmetic):
   * FP64 operator applications: max |gpu - oracle| <= 1e-13 max |oracle|
     (same operator, different summation order only);
   * FP32 Schur operator: ||gpu - oracle|| <= 2e-6 ||oracle|| (single rounding of
