@@ -87,7 +87,7 @@ typedef enum {
                            fixed point (one FP32 scale per site and column for
                            spinors, per site for A^{-1}), FP32 arithmetic and FP32
                            solution vector, FP64 defect correction.  Inner solves
-                           stop at no less than 1e-3 relative reduction. */
+                           stop at no less than 3e-4 relative reduction. */
 } ddml_prec;
 
 typedef struct {

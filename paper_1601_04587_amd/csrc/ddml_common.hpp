@@ -359,8 +359,10 @@ enum { F_R = 0, F_UNUSED = 1, F_P = 2, F_V = 3, F_S = 4, F_T = 5, F_X = 6, F_TMP
 // Partial-sum slots of BiCGstab ([kBiPartials][nrhs][ntiles] per solve)
 constexpr int kBiPartials = 4;
 // Smallest relative reduction asked of a 16-bit inner solve: below it the
-// recursive residual drifts away from the true one by the storage rounding.
-constexpr double kInnerFloor16 = 1e-3;
+// recursive residual drifts away from the true one by the storage rounding
+// (at 3e-4 three FP64 corrections reach 1e-10; at 1e-3 four were needed, at
+// 1e-4 the inner solves take more iterations than they save).
+constexpr double kInnerFloor16 = 3e-4;
 // GCR(m) (solver 2) keeps m search directions p_j and their images q_j = M p_j
 // in the field slots after the BiCGstab ones (F_R, F_X and F_TMP are shared).
 constexpr int kGcrMax = 8;

@@ -231,7 +231,7 @@ def test_fp16_storage_solve_and_iterations(setup):
     it16 = max(i.inner_iters for i in info16)
     it32 = max(i.inner_iters for i in info32)
     assert it16 <= 2 * it32 + 10, (it16, it32)
-    # 16-bit runs take more FP64 corrections (each inner solve stops at 1e-3)
+    # 16-bit runs take at least as many FP64 corrections (each inner solve stops at 3e-4)
     assert max(i.outer_iters for i in info16) >= max(i.outer_iters for i in info32)
 
 
