@@ -540,13 +540,24 @@ __device__ __forceinline__ void hop_tile(const BoxGeom g, const TileArgs<E>& a, 
     if (valid) {
       const unsigned hb = shadow_bits(col, i);
       if constexpr (kIs16<E>) {
-        C av[12], ra[12], o[12], w[12];
+        // one scale over the 12 output components, so the epilogue runs on all
+        // of them before the store.  To stay within the register budget it
+        // works in place: the aux components become the output, the store
+        // returns the stored values in the same registers, and the (t, s)
+        // sums read aux again (the first load leaves it in cache for that)
+        C w[12], ra[12];
         const size_t qb = qidx(nt, col, i);
-        if (MODE != MODE_CINV_HOP) spinor_load_q(a.aux + qb, a.aux_n[ns], av, true);
+        if (MODE != MODE_CINV_HOP) spinor_load_q(a.aux + qb, a.aux_n[ns], w, RED != RED_TS);
         if (MODE == MODE_RES) spinor_load_q(a.red_a + qb, a.red_n[ns], ra, true);
-        epilogue<C, MODE, ST>(cl, acc[r], av, ra, c1, c2, w);
-        spinor_store_q(a.out + qb, a.out_n + ns, w, o, true);   // one scale over all 12 components
-        fused_reductions<RED, 12>(hb, 0, o, av, s0, s1, s2);
+        epilogue<C, MODE, ST>(cl, acc[r], w, ra, c1, c2, w);
+        spinor_store_q(a.out + qb, a.out_n + ns, w, w, true);
+        if constexpr (RED == RED_TS) {
+          C av[12];
+          spinor_load_q(a.aux + qb, a.aux_n[ns], av, true);
+          fused_reductions<RED, 12>(hb, 0, w, av, s0, s1, s2);
+        } else {
+          fused_reductions<RED, 12>(hb, 0, w, w, s0, s1, s2);
+        }
       } else {
         // chiral block by block: aux in, 6x6 clover block, out, reductions
 #pragma unroll
