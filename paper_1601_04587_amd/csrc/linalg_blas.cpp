@@ -71,7 +71,7 @@ void gram_slices(Ctx* c, const double2* X, int n, size_t V, int T, int t0, int t
 // orthonormal: X <- X R^{-1}, G = X^dag X = R^dag R, twice.
 void orthonormalize(Ctx* c, double2* X, int n, size_t V, size_t row0, size_t nrows) {
   DBuf G(c->pool.get(), (size_t)n * n * sizeof(double2));
-  const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
+  const rocblas_double_complex one = {1.0, 0.0};
   auto* A = reinterpret_cast<rocblas_double_complex*>(X) + row0;
   auto* R = G.as<rocblas_double_complex>();
   const rocblas_int lda = (rocblas_int)(12 * V);
@@ -103,7 +103,6 @@ void bary_slices(Ctx* c, const double2* X, int n, size_t V, int T, int t0, int t
   size_t ns = ((size_t)1 << 30) / per_site;
   ns = std::max<size_t>(1, std::min(ns, V3));
   DBuf E(c->pool.get(), ns * per_site), S(c->pool.get(), (size_t)n * 12 * ns * sizeof(double2));
-  const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
   for (int t = t0; t < t1; ++t)
     for (size_t off = 0; off < V3; off += ns) {
       const int cnt = (int)std::min(ns, V3 - off);
