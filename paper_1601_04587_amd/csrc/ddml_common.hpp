@@ -140,6 +140,13 @@ __device__ __forceinline__ void ld2(const double2* p, double2& a, double2& b) {
   b = make_double2(v.x, v.y);
 }
 __device__ __forceinline__ int ldg(const int* p) { return *(const DDML_GLOBAL int*)p; }
+__device__ __forceinline__ float ldgf(const float* p) { return *(const DDML_GLOBAL float*)p; }
+__device__ __forceinline__ void stgf(float* p, float v) { *(DDML_GLOBAL float*)p = v; }
+__device__ __forceinline__ void stg2(double2* p, double2 v) {
+  f64x2 u;
+  u.x = v.x; u.y = v.y;
+  *(DDML_GLOBAL f64x2*)p = u;
+}
 // Streaming variants (non-temporal hint): data read or written once per
 // kernel, so that it does not push the reused neighbour spinors out of L2.
 __device__ __forceinline__ void ld2nt(const float2* p, float2& a, float2& b) {
@@ -248,7 +255,7 @@ __device__ __forceinline__ void spinor_store_q(h16c* base, float* nrm, const flo
     if (nt) __builtin_nontemporal_store(w, (DDML_GLOBAL s16x8*)(base + 256 * k));
     else *(DDML_GLOBAL s16x8*)(base + 256 * k) = w;
   }
-  *nrm = m;
+  stgf(nrm, m);
 }
 
 // local coordinates of EO index i of parity p

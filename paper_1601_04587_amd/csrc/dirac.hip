@@ -85,6 +85,38 @@ __device__ __forceinline__ void reconstruct(int mu, bool fwd, const T2 g[6], T2 
   }
 }
 
+// reconstruct with a scale s folded in (acc += s times the rebuilt spinor):
+// every add is a fused multiply-add by s, so a 16-bit input spinor's per-site
+// scale is applied here once instead of to each of its loaded components
+template <typename T2>
+__device__ __forceinline__ void reconstruct_s(int mu, bool fwd, const T2 g[6], decltype(T2::x) s, T2 acc[12]) {
+  const decltype(T2::x) m = -s;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const T2 g0 = g[c], g1 = g[3 + c];
+    acc[c] = cmas(acc[c], g0, s);
+    acc[3 + c] = cmas(acc[3 + c], g1, s);
+    switch (mu) {
+      case 0:
+        acc[6 + c] = cmas(acc[6 + c], g0, fwd ? s : m);
+        acc[9 + c] = cmas(acc[9 + c], g1, fwd ? s : m);
+        break;
+      case 1:
+        acc[6 + c] = cmas(acc[6 + c], fwd ? cmi(g1) : ci(g1), s);
+        acc[9 + c] = cmas(acc[9 + c], fwd ? cmi(g0) : ci(g0), s);
+        break;
+      case 2:
+        acc[6 + c] = cmas(acc[6 + c], g1, fwd ? m : s);
+        acc[9 + c] = cmas(acc[9 + c], g0, fwd ? s : m);
+        break;
+      default:
+        acc[6 + c] = cmas(acc[6 + c], fwd ? cmi(g0) : ci(g0), s);
+        acc[9 + c] = cmas(acc[9 + c], fwd ? ci(g1) : cmi(g1), s);
+        break;
+    }
+  }
+}
+
 // g = U h (dag=false) or U^dag h (dag=true), per spin of the half spinor;
 // every complex multiply-add is four fused multiply-adds
 template <typename T2>
@@ -346,7 +378,7 @@ __device__ __forceinline__ void stage_tile(const BoxGeom& g, const E* __restrict
   for (int j = w; j < 18; j += W) {
     C a = z, b = z;
     float sc = 1.0f / kQ;
-    if constexpr (kIs16<E>) sc = clov_n[(size_t)p * nt * kTile + i] / kQ;
+    if constexpr (kIs16<E>) sc = ldgf(clov_n + (size_t)p * nt * kTile + i) / kQ;
     stage_load<E, C>(clov + cidx(nt, p, 2 * j, i), sc, a, b);
     sts2(sm + (kStageLinkPairs + j) * 128 + lane * 2, a, b);
   }
@@ -390,14 +422,30 @@ __device__ __forceinline__ void hop_sum(const BoxGeom& g, int p, int i, const E*
       for (int r = 0; r < R; ++r) {
         if (r < nr && ((on >> r) & 1u)) {
           C psi[12], h[6], gg[6];
-          if constexpr (kIs16<E>)
-            spinor_load_q(in + qidx(nt, r0 + r, n), in_n[(size_t)(r0 + r) * nt * kTile + n], psi, false);
-          else
+          if constexpr (kIs16<E>) {
+            // the stored integers are projected and multiplied as they are
+            // (the projection is exact on them) and the spinor's scale enters
+            // once, in the fused rebuild
+            const h16c* b = in + qidx(nt, r0 + r, n);
+            const float sc = ldgf(in_n + (size_t)(r0 + r) * nt * kTile + n) * (1.0f / kQ);
+            s16x8 w[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) w[k] = *(const DDML_GLOBAL s16x8*)(b + 256 * k);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+              for (int j = 0; j < 4; ++j) psi[4 * k + j] = make_float2((float)w[k][2 * j], (float)w[k][2 * j + 1]);
+            project(mu, fwd, psi, h);
+            su3_rows(ul, h, gg);
+            reconstruct_s(mu, fwd, gg, sc, acc[r]);
+          } else {
             spinor_load(in + fidx(nt, r0 + r, 0, n), psi);
-          project(mu, fwd, psi, h);
-          if constexpr (ST) su3_rows(ul, h, gg);
-          else su3_mul(u, !fwd, h, gg);
-          reconstruct(mu, fwd, gg, acc[r]);
+            project(mu, fwd, psi, h);
+            if constexpr (ST) su3_rows(ul, h, gg);
+            else su3_mul(u, !fwd, h, gg);
+            reconstruct(mu, fwd, gg, acc[r]);
+          }
         }
       }
     }
@@ -547,13 +595,13 @@ __device__ __forceinline__ void hop_tile(const BoxGeom g, const TileArgs<E>& a, 
         // sums read aux again (the first load leaves it in cache for that)
         C w[12], ra[12];
         const size_t qb = qidx(nt, col, i);
-        if (MODE != MODE_CINV_HOP) spinor_load_q(a.aux + qb, a.aux_n[ns], w, RED != RED_TS);
-        if (MODE == MODE_RES) spinor_load_q(a.red_a + qb, a.red_n[ns], ra, true);
+        if (MODE != MODE_CINV_HOP) spinor_load_q(a.aux + qb, ldgf(a.aux_n + ns), w, RED != RED_TS);
+        if (MODE == MODE_RES) spinor_load_q(a.red_a + qb, ldgf(a.red_n + ns), ra, true);
         epilogue<C, MODE, ST>(cl, acc[r], w, ra, c1, c2, w);
         spinor_store_q(a.out + qb, a.out_n + ns, w, w, true);
         if constexpr (RED == RED_TS) {
           C av[12];
-          spinor_load_q(a.aux + qb, a.aux_n[ns], av, true);
+          spinor_load_q(a.aux + qb, ldgf(a.aux_n + ns), av, true);
           fused_reductions<RED, 12>(hb, 0, w, av, s0, s1, s2);
         } else {
           fused_reductions<RED, 12>(hb, 0, w, w, s0, s1, s2);
@@ -589,10 +637,10 @@ __device__ __forceinline__ void hop_tile(const BoxGeom g, const TileArgs<E>& a, 
         s2 = wave_sum(s2);
       }
       if (lane == 0) {
-        partial[(size_t)col * nt + tile] = s0;
+        stg2(partial + (size_t)col * nt + tile, s0);
         if (RED == RED_TS) {
-          partial[((size_t)nrhs + col) * nt + tile] = s1;
-          partial[((size_t)2 * nrhs + col) * nt + tile] = s2;
+          stg2(partial + ((size_t)nrhs + col) * nt + tile, s1);
+          stg2(partial + ((size_t)2 * nrhs + col) * nt + tile, s2);
         }
       }
     }
