@@ -100,6 +100,10 @@ def parse():
     ap.add_argument("--stencil-only", action="store_true",
                     help="only time the stencil kernels on the 32^3x16 slab domain (profiling runs); "
                          "also runs one plain 1 GiB device copy as the reference for HBM counters")
+    ap.add_argument("--stencil-prec", choices=("fp32", "fp16"), default="fp32",
+                    help="storage of the --stencil-only kernels: FP32 or 16-bit fixed point")
+    ap.add_argument("--stencil-launch", default=None,
+                    help="R,order,grid,splits,stage: time this launch only (--stencil-only, no sweep)")
     return ap.parse_args()
 
 
@@ -121,7 +125,8 @@ def launch_variants(nrhs=12):
 def stencil_only(args):
     """Stencil kernels alone on the Gamma2 slab domain, for rocprofv3 runs: every
     launch variant (3 untimed + `--sweep-iters` timed pairs each, in the order
-    printed), then the fastest one for `--stencil-iters` pairs."""
+    printed), then the fastest one for `--stencil-iters` pairs; with
+    `--stencil-launch` only that launch (3 untimed + `--stencil-iters` pairs)."""
     import torch
 
     import inputs
@@ -132,16 +137,22 @@ def stencil_only(args):
     ctx = ddml.Context(L, ddml.BC_ANTIPERIODIC, device=0)
     gid = ctx.set_gauge(U, 0.1340, 1.769)
     dom = ctx.set_domain((0, 0, 0, 0), (16,) + L[1:])
+    prec, name = (ddml.MIXED_FP32, "fp32") if args.stencil_prec == "fp32" else (ddml.MIXED_FP16, "fp16")
     sweep = []
-    for v in launch_variants():
-        o = ctx.time_stencil(gid, dom, 12, ddml.MIXED_FP32, args.sweep_iters, *v)
-        sweep.append(list(v) + [o[0], o[1]])
-    best = min(sweep, key=lambda r: r[5] + r[6])
-    tune = tuple(best[:5])
-    log("fastest fp32 launch: R=%d order=%d grid=%d splits=%d stage=%d" % tune)
-    s32 = ctx.time_stencil(gid, dom, 12, ddml.MIXED_FP32, args.stencil_iters, *tune)
-    log("stencil-only fp32: odd %.4f ms (%.3e B), even %.4f ms (%.3e B) -> even %.0f GB/s, odd %.0f GB/s"
-        % (s32[0], s32[2], s32[1], s32[3], s32[3] / s32[1] * 1e-6, s32[2] / s32[0] * 1e-6))
+    if args.stencil_launch:
+        tune = tuple(int(v) for v in args.stencil_launch.split(","))
+        if len(tune) != 5:
+            raise SystemExit("--stencil-launch takes R,order,grid,splits,stage")
+    else:
+        for v in launch_variants():
+            o = ctx.time_stencil(gid, dom, 12, prec, args.sweep_iters, *v)
+            sweep.append(list(v) + [o[0], o[1]])
+        best = min(sweep, key=lambda r: r[5] + r[6])
+        tune = tuple(best[:5])
+        log("fastest %s launch: R=%d order=%d grid=%d splits=%d stage=%d" % ((name,) + tune))
+    s32 = ctx.time_stencil(gid, dom, 12, prec, args.stencil_iters, *tune)
+    log("stencil-only %s: odd %.4f ms (%.3e B), even %.4f ms (%.3e B) -> even %.0f GB/s, odd %.0f GB/s"
+        % (name, s32[0], s32[2], s32[1], s32[3], s32[3] / s32[1] * 1e-6, s32[2] / s32[0] * 1e-6))
     # plain copy of known size: the reference reading of the HBM byte counters
     a = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0")   # 1 GiB
     b = torch.empty_like(a)
@@ -150,7 +161,7 @@ def stencil_only(args):
     b.copy_(a)
     torch.cuda.synchronize()
     ctx.close()
-    print(json.dumps({"stencil_fp32": {"ms_odd": s32[0], "ms_even": s32[1], "bytes_odd": s32[2],
+    print(json.dumps({"stencil_" + name: {"ms_odd": s32[0], "ms_even": s32[1], "bytes_odd": s32[2],
                                        "bytes_even": s32[3], "R": tune[0], "tile_order": tune[1], "grid": tune[2],
                                        "splits": tune[3], "stage": tune[4]},
                       "sweep_iters": args.sweep_iters, "stencil_iters": args.stencil_iters,
