@@ -116,7 +116,7 @@ def launch_variants(nrhs=12):
             for splits in (1, 2, 3):
                 if splits > (nrhs + R - 1) // R:
                     continue
-                for order in (0, 1, 2, 3, 4):
+                for order in (0, 1, 2, 3, 4, 5):
                     for grid in (512, 1024, 2048):
                         out.append((R, order, grid, splits, stage))
     return out

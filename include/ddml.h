@@ -481,7 +481,9 @@ int ddml_projected_pion(ddml_ctx ctx, int gauge_id, int bar_id, int star_id, con
  * turn; 2 and 3: each XCD owns an x1 range of the domain, split by x2 into 2
  * (order 2) or 4 (order 3) sub-bands, each walked slice by slice; 4: the
  * sub-bands of order 3 walked in blocks of 4 slices, the slices of a block
- * innermost.  splits: the
+ * innermost; 5: each XCD owns half of the x1 rows and a quarter of the tiles
+ * of each (x2, x3) plane, cut along x1 into 4 sub-bands walked as in order 4
+ * (orders 2..5 fall back to order 1 on boxes that do not split so).  splits: the
  * ceil(nrhs / R) wavefronts that cover the columns of a 64-site tile are spread
  * over this many workgroups (1 = one workgroup per tile; clamped to the number
  * of wavefronts).  stage: 1 = each workgroup first copies the links and
@@ -493,7 +495,7 @@ int ddml_time_stencil(ddml_ctx ctx, int gauge_id, int dom_id, int nrhs, int prec
                       int grid, int splits, int stage, double out[4]);
 
 /* Autotuner: times the stencil launch variants (stage 0/1 in FP64, 1 otherwise;
- * R in 1..3, splits in 1..3, tile orders 0..4, grid in {512, 1024, 2048}) on (gauge_id, dom_id,
+ * R in 1..3, splits in 1..3, tile orders 0..5, grid in {512, 1024, 2048}) on (gauge_id, dom_id,
  * nrhs, prec) and makes the fastest the context's choice for every later solve
  * (the captured solver graphs are rebuilt).  best[0..5] = R, order, grid,
  * splits, stage, ms per odd+even pair.

@@ -281,13 +281,17 @@ __device__ __forceinline__ int eo_index(const BoxGeom& g, const int y[4]) {
 //                      each sub-band slice by slice (walk table of the box);
 //   TILE_ORDER_SUB4T   the sub-bands of SUB4 walked in blocks of 4 slices,
 //                      the slices of a block innermost, so a tile's time
-//                      neighbours are its neighbours in the walk.
+//                      neighbours are its neighbours in the walk;
+//   TILE_ORDER_QUAD    the XCD owns half of the x1 rows and a quarter of the
+//                      tiles of each (x2, x3) plane (fewer tiles on the
+//                      region's border than an x1 range of every plane),
+//                      cut along x1 into 4 sub-bands walked as in SUB4T.
 // Either way the neighbours of a tile (same slice, adjacent slices) are read
 // through the same L2 shortly after they were first fetched; the sub-bands
 // shorten the distance to the next time slice so it stays in the L2.
 constexpr int kXcd = 8;
 enum { TILE_ORDER_LINEAR = 0, TILE_ORDER_BANDED = 1, TILE_ORDER_SUB2 = 2, TILE_ORDER_SUB4 = 3, TILE_ORDER_SUB4T = 4,
-       TILE_ORDER_NUM = 5 };
+       TILE_ORDER_QUAD = 5, TILE_ORDER_NUM = 6 };
 constexpr int kWalks = TILE_ORDER_NUM - TILE_ORDER_SUB2;   // orders with a walk table
 
 // ---------------------------------------------------------- kernel argument

@@ -346,28 +346,40 @@ static void evict_blocks(Ctx* c) {
   }
 }
 
-// Tile walk of the sub-banded orders: XCD x takes the x1 range
-// [x L1 / 8, (x+1) L1 / 8) of the box, splits its tiles by their x2 position
-// inside the (t, x1) plane into nsub sub-bands and walks each sub-band slice by
-// slice (t outermost, then x1, then the tiles of the plane); with tblock > 1
-// the slices go in blocks of tblock, the slices of a block innermost.  A box
-// whose (x2, x3) planes are not a whole number of tiles, or with L1 < 8, gets
-// the banded walk instead.  The walk is checked to be a permutation of the tiles.
-static void build_walk(const BoxGeom& g, int tps, int nsub, int tblock, std::vector<int>& walk,
-                       int xoff[kXcd + 1]) {
+// Tile walk of the sub-banded orders.  XCD x owns a region of the box's
+// (x1, tile-row) cross-section over all slices: with nrg = 1 the x1 range
+// [x L1 / 8, (x+1) L1 / 8) and every tile of its (x2, x3) planes; with nrg = 4
+// the x1 half x % 2 and the quarter x / 2 of the tiles of each plane.  The
+// region is cut into nsub sub-bands (along the tiles of a plane, or along x1
+// with split_x1) and each sub-band is walked slice by slice (t outermost, then
+// x1, then the tiles of the plane); with tblock > 1 the slices go in blocks of
+// tblock, the slices of a block innermost.  A box whose (x2, x3) planes are
+// not a whole number of tiles, or that does not split into the regions and
+// sub-bands, gets the banded walk instead.  The walk is checked to be a
+// permutation of the tiles.
+static void build_walk(const BoxGeom& g, int tps, int nrg, int nsub, bool split_x1, int tblock,
+                       std::vector<int>& walk, int xoff[kXcd + 1]) {
   walk.clear();
   const int nt = g.ntiles;
   const long plane = (long)g.L[2] * g.L[3] / 2;
-  if (tps > 0 && plane % kTile == 0 && g.L[1] >= kXcd) {
-    const int tpp = (int)(plane / kTile);
+  const int nrx = kXcd / nrg;   // regions along x1
+  const int tpp = plane % kTile == 0 ? (int)(plane / kTile) : 0;
+  const bool fits = tps > 0 && tpp > 0 && g.L[1] >= kXcd &&
+                    (nrg == 1 || (g.L[1] % nrx == 0 && tpp % nrg == 0 && (g.L[1] / nrx) % nsub == 0));
+  if (fits) {
     const int nslice = nt / tps;
     for (int x = 0; x < kXcd; ++x) {
       xoff[x] = (int)walk.size();
-      const int a = x * g.L[1] / kXcd, b = (x + 1) * g.L[1] / kXcd;
+      const int ax = x % nrx, ag = x / nrx;
+      const int a = nrg == 1 ? x * g.L[1] / kXcd : ax * (g.L[1] / nrx);
+      const int b = nrg == 1 ? (x + 1) * g.L[1] / kXcd : (ax + 1) * (g.L[1] / nrx);
+      const int g0 = ag * (tpp / nrg), g1 = (ag + 1) * (tpp / nrg);
       for (int sb = 0; sb < nsub; ++sb) {
-        const int glo = sb * tpp / nsub, ghi = (sb + 1) * tpp / nsub;
+        const int xlo = split_x1 ? a + sb * (b - a) / nsub : a, xhi = split_x1 ? a + (sb + 1) * (b - a) / nsub : b;
+        const int glo = split_x1 ? g0 : g0 + sb * (g1 - g0) / nsub;
+        const int ghi = split_x1 ? g1 : g0 + (sb + 1) * (g1 - g0) / nsub;
         for (int t0 = 0; t0 < nslice; t0 += tblock)
-          for (int x1 = a; x1 < b; ++x1)
+          for (int x1 = xlo; x1 < xhi; ++x1)
             for (int gg = glo; gg < ghi; ++gg)
               for (int t = t0; t < std::min(t0 + tblock, nslice); ++t) walk.push_back(t * tps + x1 * tpp + gg);
       }
@@ -433,7 +445,11 @@ std::shared_ptr<OpBlock> opblock(Ctx* c, int gauge_id, int dom_id) {
     DDML_HIP(hipMemsetAsync(b->p, 0, b->bytes, c->stream));
   std::vector<int> walks[kWalks];
   for (int w = 0; w < kWalks; ++w) {
-    build_walk(ob->g, ob->tps, w == 0 ? 2 : 4, w == 2 ? 4 : 1, walks[w], ob->xoff[w]);
+    // orders 2, 3, 4: x1 ranges split into 2 / 4 / 4 sub-bands along x2 (order 4
+    // in blocks of 4 slices); order 5: regions of half the x1 rows and a quarter
+    // of the tiles of a plane, 4 sub-bands along x1, blocks of 4 slices
+    if (w < 3) build_walk(ob->g, ob->tps, 1, w == 0 ? 2 : 4, false, w == 2 ? 4 : 1, walks[w], ob->xoff[w]);
+    else build_walk(ob->g, ob->tps, 4, 4, true, 4, walks[w], ob->xoff[w]);
     ob->walk[w] = DBuf(c->pool.get(), sizeof(int) * walks[w].size());
     DDML_HIP(hipMemcpyAsync(ob->walk[w].p, walks[w].data(), sizeof(int) * walks[w].size(), hipMemcpyHostToDevice,
                             c->stream));

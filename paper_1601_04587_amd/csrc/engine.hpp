@@ -103,7 +103,7 @@ struct OpBlock {
   DBuf U64, A64, Ainv64;   // FP64 operator data
   DBuf U32, Ainv32;        // FP32 copies for the inner solve
   DBuf U16, Ainv16, Ainv16n;  // 16-bit copies (built on first use by a DDML_MIXED_FP16 solve)
-  DBuf walk[kWalks];       // tile walks of TILE_ORDER_SUB2, SUB4, SUB4T
+  DBuf walk[kWalks];       // tile walks of TILE_ORDER_SUB2, SUB4, SUB4T, QUAD
   int xoff[kWalks][kXcd + 1] = {};
   size_t bytes = 0;
   bool su3 = true;         // links are SU(3) to 1e-5 (the FP32 and 16-bit copies keep two rows)

@@ -198,7 +198,7 @@ def test_mixed_solver_iterations_close_to_fp64(setup, solver):
 def test_autotune_and_stencil_timing(setup):
     L, U, ctx, gid, doms, ids = setup
     R, order, grid, splits, stage, ms = ctx.autotune(gid, ids["G2"], 12, ddml.MIXED_FP32)
-    assert 1 <= R <= 3 and order in (0, 1, 2, 3, 4) and grid in (512, 1024, 2048) and 1 <= splits <= 3 and ms > 0
+    assert 1 <= R <= 3 and order in (0, 1, 2, 3, 4, 5) and grid in (512, 1024, 2048) and 1 <= splits <= 3 and ms > 0
     assert stage in (0, 1)
     ms_odd, ms_even, b_odd, b_even = ctx.time_stencil(gid, ids["G2"], 12, ddml.MIXED_FP32, 5)
     Vh = int(np.prod(L)) // 2
@@ -277,5 +277,42 @@ def test_every_launch_variant_computes_the_same_bits():
             ctx.set_launch(ddml.MIXED_FP32, 1, 1, 1024, 1, 0)      # so does FP32 (two-row links)
         with pytest.raises(ddml.DDMLError):
             ctx.set_launch(ddml.MIXED_FP32, 1, 1, 1024, 1, 2)      # no such stage
+    finally:
+        ctx.close()
+
+
+def test_quadrant_walk_computes_the_same_bits():
+    """Tile order 5 (each XCD owns half of the x1 rows and a quarter of the
+    tiles of a plane, 4 sub-bands along x1) needs a box whose x1 extent splits
+    into 2 x 4 rows and whose (x2, x3) planes hold a multiple of 4 tiles: on
+    8^3 x 32 boxes of an 8 x 8 x 16 x 32 lattice (a 4-slice slab and the
+    whole antiperiodic lattice) it walks its own table, and solves agree bit
+    for bit with the banded order in all three precisions."""
+    L = (8, 8, 16, 32)
+    U = inputs.random_links(L, 1601078, 0.3)
+    ctx = ddml.Context(L, ddml.BC_ANTIPERIODIC)
+    try:
+        gid = ctx.set_gauge(U, 0.1200, 1.0)
+        doms = [(ctx.set_domain((2, 0, 0, 0), (6,) + L[1:]), inputs.point_source(L, (3, 1, 5, 7))),
+                (ctx.set_domain((0, 0, 0, 0), L), inputs.point_source(L, (7, 6, 2, 30)))]
+        variants = {
+            ddml.MIXED_FP32: [(1, 1, 1024, 1, 1), (1, 5, 512, 1, 1), (1, 5, 1024, 1, 1), (2, 5, 512, 2, 1)],
+            ddml.FP64: [(1, 1, 1024, 1, 0), (1, 5, 1024, 1, 1), (1, 5, 512, 1, 0)],
+            ddml.MIXED_FP16: [(1, 1, 1024, 1, 1), (1, 5, 2048, 1, 1)],
+        }
+        for prec, vs in variants.items():
+            ref = None
+            for v in vs:
+                ctx.set_launch(prec, *v)
+                xs = []
+                for d, src in doms:
+                    x = np.zeros_like(src)
+                    rc, info = ctx.solve_domain(gid, d, src, x, 12, ddml.solver_params(tol=1e-10, prec=prec))
+                    assert rc == ddml.OK, (prec, v)
+                    xs.append(x)
+                if ref is None:
+                    ref = xs
+                else:
+                    assert all(np.array_equal(x, r) for x, r in zip(xs, ref)), (prec, v)
     finally:
         ctx.close()
