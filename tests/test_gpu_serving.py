@@ -287,7 +287,8 @@ def test_quadrant_walk_computes_the_same_bits():
     into 2 x 4 rows and whose (x2, x3) planes hold a multiple of 4 tiles: on
     8^3 x 32 boxes of an 8 x 8 x 16 x 32 lattice (a 4-slice slab and the
     whole antiperiodic lattice) it walks its own table, and solves agree bit
-    for bit with the banded order in all three precisions."""
+    for bit with the banded order in all three precisions, alone and as two
+    series in one batch (slots of both boxes in every launch)."""
     L = (8, 8, 16, 32)
     U = inputs.random_links(L, 1601078, 0.3)
     ctx = ddml.Context(L, ddml.BC_ANTIPERIODIC)
@@ -314,5 +315,21 @@ def test_quadrant_walk_computes_the_same_bits():
                     ref = xs
                 else:
                     assert all(np.array_equal(x, r) for x, r in zip(xs, ref)), (prec, v)
+        # two series in one batch: slots of both boxes share every launch
+        ids = [d for d, _ in doms]
+        srcs = [doms[0][1], inputs.point_source(L, (4, 6, 2, 30))]   # both inside the inner level
+        for prec, vs in ((ddml.MIXED_FP32, [(1, 1, 1024, 1, 1), (1, 4, 1024, 1, 1), (1, 5, 512, 1, 1)]),
+                         (ddml.MIXED_FP16, [(1, 1, 1024, 1, 1), (1, 5, 1024, 1, 1)])):
+            ref = None
+            for v in vs:
+                ctx.set_launch(prec, *v)
+                terms = [np.zeros((2,) + b.shape, complex) for b in srcs]
+                rc, _ = ctx.propagator_series_batch([(gid, ids, b, t, None) for b, t in zip(srcs, terms)], 12,
+                                                    ddml.solver_params(tol=1e-10, prec=prec, solver=1))
+                assert rc == ddml.OK, (prec, v)
+                if ref is None:
+                    ref = terms
+                else:
+                    assert all(np.array_equal(t, r) for t, r in zip(terms, ref)), (prec, v)
     finally:
         ctx.close()
