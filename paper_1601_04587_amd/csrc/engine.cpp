@@ -15,6 +15,7 @@
 
 #include <type_traits>
 #include "server.hpp"
+#include "tile_walk.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -346,60 +347,12 @@ static void evict_blocks(Ctx* c) {
   }
 }
 
-// Tile walk of the sub-banded orders.  XCD x owns a region of the box's
-// (x1, tile-row) cross-section over all slices: with nrg = 1 the x1 range
-// [x L1 / 8, (x+1) L1 / 8) and every tile of its (x2, x3) planes; with nrg = 4
-// the x1 half x % 2 and the quarter x / 2 of the tiles of each plane.  The
-// region is cut into nsub sub-bands (along the tiles of a plane, or along x1
-// with split_x1) and each sub-band is walked slice by slice (t outermost, then
-// x1, then the tiles of the plane); with tblock > 1 the slices go in blocks of
-// tblock, the slices of a block innermost.  A box whose (x2, x3) planes are
-// not a whole number of tiles, or that does not split into the regions and
-// sub-bands, gets the banded walk instead.  The walk is checked to be a
-// permutation of the tiles.
+// Tile walk of one box for the sub-banded and quadrant orders (tile_walk.hpp),
+// checked to be a permutation of the tiles.
 static void build_walk(const BoxGeom& g, int tps, int nrg, int nsub, bool split_x1, int tblock,
                        std::vector<int>& walk, int xoff[kXcd + 1]) {
-  walk.clear();
-  const int nt = g.ntiles;
-  const long plane = (long)g.L[2] * g.L[3] / 2;
-  const int nrx = kXcd / nrg;   // regions along x1
-  const int tpp = plane % kTile == 0 ? (int)(plane / kTile) : 0;
-  const bool fits = tps > 0 && tpp > 0 && g.L[1] >= kXcd &&
-                    (nrg == 1 || (g.L[1] % nrx == 0 && tpp % nrg == 0 && (g.L[1] / nrx) % nsub == 0));
-  if (fits) {
-    const int nslice = nt / tps;
-    for (int x = 0; x < kXcd; ++x) {
-      xoff[x] = (int)walk.size();
-      const int ax = x % nrx, ag = x / nrx;
-      const int a = nrg == 1 ? x * g.L[1] / kXcd : ax * (g.L[1] / nrx);
-      const int b = nrg == 1 ? (x + 1) * g.L[1] / kXcd : (ax + 1) * (g.L[1] / nrx);
-      const int g0 = ag * (tpp / nrg), g1 = (ag + 1) * (tpp / nrg);
-      for (int sb = 0; sb < nsub; ++sb) {
-        const int xlo = split_x1 ? a + sb * (b - a) / nsub : a, xhi = split_x1 ? a + (sb + 1) * (b - a) / nsub : b;
-        const int glo = split_x1 ? g0 : g0 + sb * (g1 - g0) / nsub;
-        const int ghi = split_x1 ? g1 : g0 + (sb + 1) * (g1 - g0) / nsub;
-        for (int t0 = 0; t0 < nslice; t0 += tblock)
-          for (int x1 = xlo; x1 < xhi; ++x1)
-            for (int gg = glo; gg < ghi; ++gg)
-              for (int t = t0; t < std::min(t0 + tblock, nslice); ++t) walk.push_back(t * tps + x1 * tpp + gg);
-      }
-    }
-  } else {
-    const int S = tps > 0 ? tps : nt;
-    for (int x = 0; x < kXcd; ++x) {
-      xoff[x] = (int)walk.size();
-      const int lo = (int)((long)x * S / kXcd), bs = (int)((long)(x + 1) * S / kXcd) - lo;
-      for (int v = 0; v < bs * (nt / S); ++v) walk.push_back((v / bs) * S + lo + v % bs);
-    }
-  }
-  xoff[kXcd] = (int)walk.size();
-  std::vector<char> seen(nt, 0);
-  bool ok = (int)walk.size() == nt;
-  for (int t : walk) {
-    if (t < 0 || t >= nt || seen[t]) { ok = false; break; }
-    seen[t] = 1;
-  }
-  if (!ok) throw Error{DDML_EDEVICE, "internal: tile walk is not a permutation"};
+  if (!tile_walk(g.L, g.ntiles, tps, kTile, kXcd, nrg, nsub, split_x1, tblock, walk, xoff))
+    throw Error{DDML_EDEVICE, "internal: tile walk is not a permutation"};
 }
 
 // Attaches the walk of `order` (if it uses one) to a kernel argument.
